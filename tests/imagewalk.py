@@ -1,0 +1,312 @@
+"""Test-side reader of canonical wavelet images, with query walkers.
+
+This module is part of the test suite only.  It decodes an image (the byte
+layout the oracle and the GPU library both emit), and answers access / rank /
+select by walking the levels the way the queries on these structures are
+defined (the pointerless traversals that Sec. 2 says replace the topology
+pointers).  Tests compare these walks with brute force on S, which pins the
+*meaning* of an image independently of how it was built.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+MAGIC = 0x54564157
+KIND_WT, KIND_WM, KIND_SHAPED, KIND_MULTI = 1, 2, 3, 4
+LEAF = 0x80000000
+NO_CHILD = 0xFFFFFFFF
+
+
+def _u64(buf, off, count=1):
+    return np.frombuffer(buf[off:off + 8 * count].tobytes(), dtype=np.uint64)
+
+
+class Image:
+    def __init__(self, buf: np.ndarray):
+        self.buf = np.asarray(buf, dtype=np.uint8)
+        b = self.buf
+        h32 = np.frombuffer(b[:40].tobytes(), dtype=np.uint32)
+        self.magic, self.version, self.kind, self.arity_log2 = (int(v) for v in h32[:4])
+        self.n = int(_u64(b, 16)[0])
+        self.sigma = int(h32[6])
+        self.nlevels = int(h32[7])
+        self.key_bits = int(h32[8])
+        self.status = int(h32[9])
+        self.image_bytes = int(_u64(b, 40)[0])
+        self.levels_off = int(_u64(b, 48)[0])
+        self.nodes_off = int(_u64(b, 56)[0])
+        self.nnodes = int(_u64(b, 64)[0])
+        self.codes_off = int(_u64(b, 72)[0])
+        self.ncoded = int(_u64(b, 80)[0])
+        self.levels = []
+        for l in range(self.nlevels):
+            e = _u64(b, self.levels_off + 64 * l, 8)
+            self.levels.append(dict(n=int(e[0]), zeros=int(e[1]), ones=int(e[2]),
+                                    bits_off=int(e[3]), rank_off=int(e[4]),
+                                    sel0_off=int(e[5]), sel1_off=int(e[6]), nsel=int(e[7])))
+        self._bits = {}
+        self._zpre = {}
+
+    # ---- binary levels ---------------------------------------------------
+    def words(self, l: int) -> np.ndarray:
+        lv = self.levels[l]
+        nw = (lv["n"] + 63) // 64
+        return _u64(self.buf, lv["bits_off"], nw)
+
+    def bits(self, l: int) -> np.ndarray:
+        if l not in self._bits:
+            lv = self.levels[l]
+            raw = self.buf[lv["bits_off"]:lv["bits_off"] + (lv["n"] + 7) // 8]
+            self._bits[l] = np.unpackbits(raw, bitorder="little")[:lv["n"]]
+        return self._bits[l]
+
+    def _zeros_prefix(self, l: int) -> np.ndarray:
+        if l not in self._zpre:
+            z = np.zeros(self.levels[l]["n"] + 1, dtype=np.int64)
+            z[1:] = np.cumsum(self.bits(l) == 0)
+            self._zpre[l] = z
+        return self._zpre[l]
+
+    def rank_dir(self, l: int) -> np.ndarray:
+        lv = self.levels[l]
+        ns = (lv["n"] + 511) // 512
+        return _u64(self.buf, lv["rank_off"], 2 * (ns + 1)).reshape(ns + 1, 2)
+
+    def sel(self, l: int, which: int) -> np.ndarray:
+        lv = self.levels[l]
+        off = lv["sel1_off"] if which else lv["sel0_off"]
+        return _u64(self.buf, off, lv["nsel"])
+
+    def rank0_via_directory(self, l: int, i: int) -> int:
+        """zeros in [0, i) using only the directory and one word."""
+        d = self.rank_dir(l)
+        k, q = divmod(i, 512)
+        r = int(d[k, 0])
+        if q >= 64:
+            r += (int(d[k, 1]) >> (9 * (q // 64 - 1))) & 511
+        t = q % 64
+        if t:
+            w = int(self.words(l)[i // 64])
+            r += t - bin(w & ((1 << t) - 1)).count("1")
+        return r
+
+    def rank(self, l: int, b: int, i: int) -> int:
+        """number of b-bits in [0, i) on binary level l"""
+        z = int(self._zeros_prefix(l)[i])
+        return z if b == 0 else i - z
+
+    def select(self, l: int, b: int, j: int) -> int:
+        """position of the b-bit with 0-based ordinal j on level l"""
+        pos = np.flatnonzero(self.bits(l) == b)
+        return int(pos[j])
+
+    # ---- multiary levels ---------------------------------------------------
+    def digits(self, l: int) -> np.ndarray:
+        D = self.arity_log2
+        p = 64 // D
+        lv = self.levels[l]
+        nw = (lv["n"] + p - 1) // p
+        w = _u64(self.buf, lv["bits_off"], nw)
+        t = np.arange(lv["n"], dtype=np.uint64)
+        return ((w[t // p] >> (np.uint64(D) * (t % p))) & np.uint64((1 << D) - 1)).astype(np.int64)
+
+    def digit_counters(self, l: int):
+        D = self.arity_log2
+        p, d = 64 // D, 1 << D
+        m = self.levels[l]["n"]
+        sbd, bd = 64 * p, 8 * p
+        nsb, nb = -(-m // sbd), -(-m // bd)
+        off = self.levels[l]["rank_off"]
+        sb = _u64(self.buf, off, (nsb + 1) * d).reshape(nsb + 1, d)
+        o2 = off + (nsb + 1) * d * 8
+        blk = np.frombuffer(self.buf[o2:o2 + nb * d * 2].tobytes(), dtype=np.uint16).reshape(nb, d)
+        return sb, blk
+
+    def mrank(self, l: int, c: int, i: int) -> int:
+        return int(np.count_nonzero(self.digits(l)[:i] == c))
+
+    # ---- shaped trees ------------------------------------------------------
+    def nodes(self):
+        if getattr(self, "_nodes", None) is not None:
+            return self._nodes
+        out = []
+        for t in range(self.nnodes):
+            o = self.nodes_off + 32 * t
+            st, cnt = (int(v) for v in _u64(self.buf, o, 2))
+            c0, c1, lev, pre = (int(v) for v in np.frombuffer(self.buf[o + 16:o + 32].tobytes(), dtype=np.uint32))
+            out.append(dict(start=st, count=cnt, child=(c0, c1), level=lev, prefix=pre))
+        self._nodes = out
+        return out
+
+    def codes(self):
+        if getattr(self, "_codes", None) is not None:
+            return self._codes
+        c = np.zeros(self.sigma, dtype=np.uint64)
+        ln = np.zeros(self.sigma, dtype=np.uint32)
+        for s in range(self.sigma):
+            o = self.codes_off + 16 * s
+            c[s] = _u64(self.buf, o)[0]
+            ln[s] = np.frombuffer(self.buf[o + 8:o + 12].tobytes(), dtype=np.uint32)[0]
+        self._codes = (c, ln)
+        return self._codes
+
+    # ---- queries -----------------------------------------------------------
+    def access(self, i: int) -> int:
+        if self.kind == KIND_WM:
+            x = 0
+            for l in range(self.nlevels):
+                b = int(self.bits(l)[i])
+                x = (x << 1) | b
+                i = self.rank(l, b, i) + (self.levels[l]["zeros"] if b else 0)
+            return x
+        if self.kind == KIND_WT:
+            s, e, x = 0, self.n, 0
+            for l in range(self.nlevels):
+                b = int(self.bits(l)[i])
+                x = (x << 1) | b
+                zs, zi, ze = self.rank(l, 0, s), self.rank(l, 0, i), self.rank(l, 0, e)
+                if b == 0:
+                    i, e = s + (zi - zs), s + (ze - zs)
+                else:
+                    i = s + (ze - zs) + (i - s) - (zi - zs)
+                    s = s + (ze - zs)
+            return x
+        if self.kind == KIND_MULTI:
+            d = 1 << self.arity_log2
+            s, e, x = 0, self.n, 0
+            for l in range(self.nlevels):
+                g = int(self.digits(l)[i])
+                x = (x << self.arity_log2) | g
+                below = sum(self.mrank(l, c, e) - self.mrank(l, c, s) for c in range(g))
+                ns = s + below
+                i, e = ns + self.mrank(l, g, i) - self.mrank(l, g, s), ns + self.mrank(l, g, e) - self.mrank(l, g, s)
+                s = ns
+                assert d > g
+            return x
+        if self.kind == KIND_SHAPED:
+            nodes = self.nodes()
+            v, rel = 0, i
+            while True:
+                nd = nodes[v]
+                l, st = nd["level"], nd["start"]
+                b = int(self.bits(l)[st + rel])
+                rel = self.rank(l, b, st + rel) - self.rank(l, b, st)
+                ch = nd["child"][b]
+                if ch & LEAF:
+                    return ch & ~LEAF
+                v = ch
+        raise ValueError("kind")
+
+    def rank_sym(self, c: int, i: int) -> int:
+        """occurrences of c in positions 0..i (inclusive)"""
+        if self.kind in (KIND_WM, KIND_WT):
+            L = self.nlevels
+            if c >= (1 << L):
+                return 0
+            if self.kind == KIND_WM:
+                s, e = 0, i + 1
+                for l in range(L):
+                    b = (c >> (L - 1 - l)) & 1
+                    z = self.levels[l]["zeros"] if b else 0
+                    s, e = self.rank(l, b, s) + z, self.rank(l, b, e) + z
+                return e - s
+            s, p, e = 0, i + 1, self.n
+            for l in range(L):
+                b = (c >> (L - 1 - l)) & 1
+                zs, zp, ze = self.rank(l, 0, s), self.rank(l, 0, p), self.rank(l, 0, e)
+                if b == 0:
+                    p, e = s + (zp - zs), s + (ze - zs)
+                else:
+                    p = s + (ze - zs) + (p - s) - (zp - zs)
+                    s = s + (ze - zs)
+            return p - s
+        if self.kind == KIND_MULTI:
+            D, M = self.arity_log2, self.nlevels
+            s, p, e = 0, i + 1, self.n
+            for l in range(M):
+                g = (c >> (D * (M - 1 - l))) & ((1 << D) - 1)
+                below = sum(self.mrank(l, cc, e) - self.mrank(l, cc, s) for cc in range(g))
+                ns = s + below
+                p = ns + self.mrank(l, g, p) - self.mrank(l, g, s)
+                e = ns + self.mrank(l, g, e) - self.mrank(l, g, s)
+                s = ns
+            return p - s
+        if self.kind == KIND_SHAPED:
+            codes, lens = self.codes()
+            if lens[c] == 0:
+                return 0
+            nodes = self.nodes()
+            v, rel = 0, i + 1
+            for t in range(int(lens[c])):
+                nd = nodes[v]
+                l, st = nd["level"], nd["start"]
+                b = int((int(codes[c]) >> (int(lens[c]) - 1 - t)) & 1)
+                rel = self.rank(l, b, st + rel) - self.rank(l, b, st)
+                v = nd["child"][b]
+            return rel
+        raise ValueError("kind")
+
+    def select_sym(self, c: int, k: int):
+        """position of the k-th occurrence of c (k >= 1), None if absent"""
+        if k < 1:
+            return None
+        total = self.rank_sym(c, self.n - 1) if self.n else 0
+        if k > total:
+            return None
+        if self.kind == KIND_WM:
+            L = self.nlevels
+            s = 0
+            for l in range(L):
+                b = (c >> (L - 1 - l)) & 1
+                s = self.rank(l, b, s) + (self.levels[l]["zeros"] if b else 0)
+            p = s + k - 1
+            for l in range(L - 1, -1, -1):
+                b = (c >> (L - 1 - l)) & 1
+                p = self.select(l, b, p - (self.levels[l]["zeros"] if b else 0))
+            return p
+        if self.kind == KIND_WT:
+            L = self.nlevels
+            starts = []
+            s, e = 0, self.n
+            for l in range(L):
+                starts.append(s)
+                b = (c >> (L - 1 - l)) & 1
+                zs, ze = self.rank(l, 0, s), self.rank(l, 0, e)
+                if b == 0:
+                    e = s + (ze - zs)
+                else:
+                    s = s + (ze - zs)
+            p = s + k - 1
+            child_start = s
+            for l in range(L - 1, -1, -1):
+                b = (c >> (L - 1 - l)) & 1
+                st = starts[l]
+                p = self.select(l, b, self.rank(l, b, st) + (p - child_start))
+                child_start = st
+            return p
+        if self.kind == KIND_SHAPED:
+            codes, lens = self.codes()
+            nodes = self.nodes()
+            path = []
+            v = 0
+            for t in range(int(lens[c])):
+                path.append(v)
+                b = int((int(codes[c]) >> (int(lens[c]) - 1 - t)) & 1)
+                v = nodes[v]["child"][b]
+            rel = k - 1
+            for t in range(int(lens[c]) - 1, -1, -1):
+                nd = nodes[path[t]]
+                l, st = nd["level"], nd["start"]
+                b = int((int(codes[c]) >> (int(lens[c]) - 1 - t)) & 1)
+                rel = self.select(l, b, self.rank(l, b, st) + rel) - st
+            return rel
+        if self.kind == KIND_MULTI:
+            lo, hi = 0, self.n - 1
+            while lo < hi:
+                mid = (lo + hi) // 2
+                if self.rank_sym(c, mid) >= k:
+                    hi = mid
+                else:
+                    lo = mid + 1
+            return lo
+        raise ValueError("kind")

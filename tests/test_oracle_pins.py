@@ -1,0 +1,443 @@
+"""Pins of the CPU oracle against things other than itself (no GPU needed).
+
+* the worked example on the sequence of Fig. 1 (values derived by hand);
+* brute-force access/rank/select walked through the image, exhaustively on
+  tiny inputs (a wrong bit, index or sign anywhere breaks a walk);
+* closed forms: every level is a stable argsort of S by a key derived from
+  the symbol (library sort, not the oracle's partition loop);
+* directories against cumulative sums and ``flatnonzero``;
+* Huffman codes: Kraft sum, optimal cost from an independent heap merge,
+  canonical order.
+"""
+import heapq
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from imagewalk import Image, KIND_MULTI, KIND_SHAPED, KIND_WM, KIND_WT, LEAF
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def key_bits(sigma):
+    return max(1, (sigma - 1).bit_length())
+
+
+def bitrev(v, nbits):
+    out = np.zeros_like(v)
+    for t in range(nbits):
+        out |= ((v >> t) & 1) << (nbits - 1 - t)
+    return out
+
+
+def wm_closed_form(S, sigma):
+    """level l = bit l of S stably sorted by the bit-reversed top-l prefix"""
+    L = key_bits(sigma)
+    x = S.astype(np.int64)
+    out = []
+    for l in range(L):
+        pre = (x >> (L - l)) if l else np.zeros_like(x)
+        order = np.argsort(bitrev(pre, l), kind="stable")
+        out.append(((x[order] >> (L - 1 - l)) & 1).astype(np.uint8))
+    return out
+
+
+def wt_closed_form(S, sigma):
+    """level l = bit l of S stably sorted by the top-l prefix"""
+    L = key_bits(sigma)
+    x = S.astype(np.int64)
+    out = []
+    for l in range(L):
+        pre = (x >> (L - l)) if l else np.zeros_like(x)
+        order = np.argsort(pre, kind="stable")
+        out.append(((x[order] >> (L - 1 - l)) & 1).astype(np.uint8))
+    return out
+
+
+def multi_closed_form(S, sigma, D):
+    L = key_bits(sigma)
+    M = -(-L // D)
+    Lb = D * M
+    x = S.astype(np.int64)
+    out = []
+    for be in range(M):
+        pre = (x >> (Lb - D * be)) if be else np.zeros_like(x)
+        order = np.argsort(pre, kind="stable")
+        out.append((x[order] >> (Lb - D * (be + 1))) & ((1 << D) - 1))
+    return out
+
+
+def brute_rank(S, c, i):
+    return int(np.count_nonzero(S[:i + 1] == c))
+
+
+def brute_select(S, c, k):
+    pos = np.flatnonzero(S == c)
+    return int(pos[k - 1]) if 1 <= k <= pos.size else None
+
+
+def build(kind, S, sigma, D=1):
+    if kind == KIND_SHAPED:
+        codes, lens = oracle.huffman(oracle.symbol_counts(S, sigma))
+        return oracle.build_image(kind, S, sigma, codes=codes, lens=lens)
+    return oracle.build_image(kind, S, sigma, D)
+
+
+def check_queries(img: Image, S: np.ndarray, sigma: int, all_symbols=True):
+    n = S.size
+    for i in range(n):
+        assert img.access(i) == int(S[i]), ("access", i)
+    syms = range(sigma) if all_symbols else np.unique(S)
+    for c in syms:
+        c = int(c)
+        for i in range(n):
+            assert img.rank_sym(c, i) == brute_rank(S, c, i), ("rank", c, i)
+        cnt = int(np.count_nonzero(S == c))
+        for k in range(1, cnt + 2):
+            assert img.select_sym(c, k) == brute_select(S, c, k), ("select", c, k)
+
+
+# ---------------------------------------------------------------------------
+# worked example (Fig. 1 caption sequence)
+# ---------------------------------------------------------------------------
+
+def test_fig1_worked_example():
+    with open(os.path.join(GOLDEN, "fig1_example.json")) as f:
+        g = json.load(f)
+    S = np.array(g["S"], dtype=np.uint8)
+    sigma = g["sigma"]
+    for kind, key in ((KIND_WT, "wt"), (KIND_WM, "wm")):
+        img = Image(oracle.build_image(kind, S, sigma))
+        assert img.magic == 0x54564157 and img.kind == kind and img.nlevels == g["L"]
+        for l in range(g["L"]):
+            bits = "".join(str(int(b)) for b in img.bits(l))
+            assert bits == g[f"{key}_levels"][l]
+            assert img.levels[l]["zeros"] == g[f"{key}_zeros"][l]
+            assert int(img.words(l)[0]) == int(g[f"{key}_words_hex"][l], 16)
+        for i, x in g["queries"]["access"]:
+            assert img.access(i) == x
+        for c, i, r in g["queries"]["rank"]:
+            assert img.rank_sym(c, i) == r
+        for c, k, p in g["queries"]["select"]:
+            assert img.select_sym(c, k) == p
+    # the node bitstrings of level 2 of the tree, concatenated left to right
+    img = Image(oracle.build_image(KIND_WT, S, sigma))
+    assert "".join(str(int(b)) for b in img.bits(2)) == "".join(g["wt_level2_nodes"])
+    # final wavelet-matrix order = stable sort by the bit-reversed symbol
+    order = np.argsort(bitrev(S.astype(np.int64), 3), kind="stable")
+    assert S[order].tolist() == g["wm_final_order"]
+    img4 = Image(oracle.build_image(KIND_MULTI, S, sigma, 2))
+    assert img4.nlevels == 2
+    for l in range(2):
+        assert img4.digits(l).tolist() == g["multiary4_levels"][l]
+    for i, x in g["queries"]["access"]:
+        assert img4.access(i) == x
+
+
+# ---------------------------------------------------------------------------
+# brute force on every tiny input
+# ---------------------------------------------------------------------------
+
+def tiny_cases():
+    for sigma, nmax in ((1, 4), (2, 6), (3, 5), (4, 4), (5, 3)):
+        for n in range(0, nmax + 1):
+            for t in itertools.product(range(sigma), repeat=n):
+                yield sigma, np.array(t, dtype=np.uint8)
+
+
+@pytest.mark.parametrize("kind,D", [(KIND_WT, 1), (KIND_WM, 1), (KIND_MULTI, 1),
+                                    (KIND_MULTI, 2), (KIND_MULTI, 3), (KIND_SHAPED, 1)])
+def test_exhaustive_tiny_queries(kind, D):
+    for sigma, S in tiny_cases():
+        if kind == KIND_SHAPED and S.size == 0:
+            continue
+        img = Image(build(kind, S, sigma, D))
+        assert img.n == S.size and img.status == 0
+        check_queries(img, S, sigma)
+
+
+# ---------------------------------------------------------------------------
+# closed forms on random inputs
+# ---------------------------------------------------------------------------
+
+SIZES = [0, 1, 2, 63, 64, 65, 300, 511, 512, 513]
+SIGMAS = [1, 2, 3, 4, 5, 7, 8, 9, 255, 256, 257, 4096, 65536]
+
+
+@pytest.mark.parametrize("sigma", SIGMAS)
+def test_closed_forms_wt_wm(sigma):
+    rng = np.random.default_rng(sigma)
+    dt = np.uint8 if sigma <= 256 else (np.uint16 if sigma <= 65536 else np.uint32)
+    for n in SIZES:
+        S = rng.integers(0, sigma, n).astype(dt)
+        for kind, cf in ((KIND_WT, wt_closed_form), (KIND_WM, wm_closed_form)):
+            img = Image(oracle.build_image(kind, S, sigma))
+            assert img.nlevels == img.key_bits == key_bits(sigma)
+            for l, want in enumerate(cf(S, sigma)):
+                assert np.array_equal(img.bits(l), want), (kind, n, l)
+                assert img.levels[l]["n"] == n
+                assert img.levels[l]["zeros"] == int(np.count_nonzero(want == 0))
+                assert img.levels[l]["ones"] == int(np.count_nonzero(want))
+        # both kinds share levels 0 and 1 (one node or two halves)
+        a = Image(oracle.build_image(KIND_WT, S, sigma))
+        b = Image(oracle.build_image(KIND_WM, S, sigma))
+        for l in range(min(2, a.nlevels)):
+            assert np.array_equal(a.bits(l), b.bits(l))
+
+
+@pytest.mark.parametrize("D", [1, 2, 3, 4])
+@pytest.mark.parametrize("sigma", [2, 5, 16, 17, 255, 4096])
+def test_closed_forms_multiary(D, sigma):
+    rng = np.random.default_rng(100 + D * sigma)
+    for n in SIZES + [5000]:
+        S = rng.integers(0, sigma, n).astype(np.uint16)
+        img = Image(oracle.build_image(KIND_MULTI, S, sigma, D))
+        want = multi_closed_form(S, sigma, D)
+        assert img.nlevels == len(want) and img.arity_log2 == D
+        for l, w in enumerate(want):
+            got = img.digits(l)
+            assert np.array_equal(got, w), (n, l)
+            # counters against cumulative counts
+            sb, blk = img.digit_counters(l)
+            p = 64 // D
+            d = 1 << D
+            cum = np.zeros((n + 1, d), dtype=np.int64)
+            for c in range(d):
+                cum[1:, c] = np.cumsum(w == c)
+            for k in range(sb.shape[0]):
+                assert np.array_equal(sb[k].astype(np.int64), cum[min(k * 64 * p, n)])
+            for bi in range(blk.shape[0]):
+                t = bi * 8 * p
+                base = cum[(t // (64 * p)) * 64 * p]
+                assert np.array_equal(blk[bi].astype(np.int64), cum[t] - base)
+
+
+def test_multiary_top_bit_matches_binary_level():
+    # with L divisible by D, digit level beta's top bit is binary level beta*D
+    rng = np.random.default_rng(7)
+    S = rng.integers(0, 256, 3000).astype(np.uint8)
+    wt = Image(oracle.build_image(KIND_WT, S, 256))
+    for D in (1, 2, 4):
+        mt = Image(oracle.build_image(KIND_MULTI, S, 256, D))
+        for be in range(mt.nlevels):
+            top = (mt.digits(be) >> (D - 1)) & 1
+            assert np.array_equal(top.astype(np.uint8), wt.bits(be * D))
+
+
+# ---------------------------------------------------------------------------
+# directories
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [0, 1, 511, 512, 513, 4095, 4096, 4097, 20000, 70001])
+def test_rank_select_directory(n):
+    rng = np.random.default_rng(n)
+    sigma = 2
+    for p1 in (0.0, 0.03, 0.5, 1.0):
+        S = (rng.random(n) < p1).astype(np.uint8)
+        img = Image(oracle.build_image(KIND_WM, S, sigma))
+        bits = img.bits(0)
+        assert np.array_equal(bits, S)
+        zp = np.concatenate([[0], np.cumsum(bits == 0)])
+        d = img.rank_dir(0)
+        ns = -(-n // 512)
+        assert d.shape[0] == ns + 1
+        for k in range(ns + 1):
+            s = min(512 * k, n)
+            assert int(d[k, 0]) == zp[s]
+            want = 0
+            if 512 * k < n:
+                for j in range(1, 8):
+                    want |= int(zp[min(512 * k + 64 * j, n)] - zp[512 * k]) << (9 * (j - 1))
+            assert int(d[k, 1]) == want
+        for i in list(range(0, n + 1, 97)) + [n]:
+            assert img.rank0_via_directory(0, i) == zp[i]
+        nsel = -(-n // 4096) + 1
+        for which in (0, 1):
+            s = img.sel(0, which)
+            pos = np.flatnonzero(bits == which)[::4096]
+            want = np.full(nsel, n, dtype=np.uint64)
+            want[:pos.size] = pos
+            assert np.array_equal(s, want)
+        # padding bits past n are zero
+        w = img.words(0)
+        if n % 64:
+            assert int(w[-1]) >> (n % 64) == 0
+
+
+# ---------------------------------------------------------------------------
+# Huffman codes and shaped trees
+# ---------------------------------------------------------------------------
+
+def heap_cost(counts):
+    h = [int(c) for c in counts if c > 0]
+    if len(h) <= 1:
+        return sum(h)
+    heapq.heapify(h)
+    cost = 0
+    while len(h) > 1:
+        a, b = heapq.heappop(h), heapq.heappop(h)
+        cost += a + b
+        heapq.heappush(h, a + b)
+    return cost
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_huffman_codes(seed):
+    rng = np.random.default_rng(seed)
+    sigma = int(rng.integers(1, 300))
+    counts = rng.integers(0, 50, sigma).astype(np.uint64)
+    if seed % 3 == 0:
+        counts = (rng.geometric(0.2, sigma) - 1).astype(np.uint64)
+    codes, lens = oracle.huffman(counts)
+    used = counts > 0
+    assert np.all((lens > 0) == used)
+    k = int(used.sum())
+    if k == 0:
+        return
+    if k == 1:
+        assert lens[used].tolist() == [1]
+        return
+    assert sum(2.0 ** -int(l) for l in lens[used]) == pytest.approx(1.0)
+    assert int((counts * lens.astype(np.uint64)).sum()) == heap_cost(counts)
+    # canonical: ordered by (len, symbol) the codes increase, prefix-free
+    syms = sorted(np.flatnonzero(used), key=lambda s: (int(lens[s]), int(s)))
+    prev_left = -1
+    for s in syms:
+        left = int(codes[s]) << (64 - int(lens[s]))
+        assert left > prev_left
+        prev_left = left
+    assert int(codes[syms[0]]) == 0
+
+
+def test_huffman_tie_rule_small():
+    # counts (5,1,1,2,0,7): merges {1,1}->2, then leaf 2 before node 2 -> 4,
+    # then 4+5 -> 9, then 7+9: lengths 2,4,4,3,-,1 ; canonical codes
+    codes, lens = oracle.huffman(np.array([5, 1, 1, 2, 0, 7], dtype=np.uint64))
+    assert lens.tolist() == [2, 4, 4, 3, 0, 1]
+    assert codes.tolist() == [0b10, 0b1110, 0b1111, 0b110, 0, 0b0]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_shaped_closed_form_and_nodes(seed):
+    rng = np.random.default_rng(50 + seed)
+    sigma = [3, 17, 100, 4096, 2, 64][seed]
+    n = [1, 200, 2000, 5000, 64, 777][seed]
+    S = np.minimum(rng.geometric(0.05, n) - 1, sigma - 1).astype(np.uint16)
+    codes, lens = oracle.huffman(oracle.symbol_counts(S, sigma))
+    img = Image(oracle.build_image(KIND_SHAPED, S, sigma, codes=codes, lens=lens))
+    h = int(lens.max())
+    assert img.nlevels == h == img.key_bits
+    cs = codes.astype(np.int64)[S]          # codeword of every position
+    ls = lens.astype(np.int64)[S]
+    for l in range(h):
+        sel = np.flatnonzero(ls > l)
+        pre = (cs[sel] >> (ls[sel] - l)) if l else np.zeros(sel.size, dtype=np.int64)
+        order = sel[np.argsort(pre, kind="stable")]
+        want = ((cs[order] >> (ls[order] - 1 - l)) & 1).astype(np.uint8)
+        assert np.array_equal(img.bits(l), want)
+        assert img.levels[l]["n"] == sel.size
+    gc, gl = img.codes()
+    assert np.array_equal(gc[lens > 0], codes[lens > 0]) and np.array_equal(gl, lens)
+    # node table: every proper prefix once, ordered by (level, prefix)
+    nodes = img.nodes()
+    c64 = codes.astype(np.int64)
+    l64 = lens.astype(np.int64)
+    keys = sorted({(l, int(c64[s] >> (l64[s] - l)) if l else 0)
+                   for s in np.flatnonzero(lens) for l in range(int(l64[s]))})
+    assert [(nd["level"], nd["prefix"]) for nd in nodes] == keys
+    keyset = set(keys)
+    leaves = {(int(l64[s]), int(c64[s])): int(s) for s in np.flatnonzero(lens)}
+    for nd in nodes:
+        l, p = nd["level"], nd["prefix"]
+        sel = ls > l
+        pre = (cs >> np.maximum(ls - l, 0)) if l else np.zeros_like(cs)
+        members = sel & (pre == p)
+        assert nd["count"] == int(members.sum())
+        assert nd["start"] == int((sel & (pre < p)).sum())
+        for b in (0, 1):
+            ch = nd["child"][b]
+            q = 2 * p + b
+            if (l + 1, q) in leaves:
+                assert ch == (LEAF | leaves[(l + 1, q)])
+            elif (l + 1, q) in keyset:
+                assert nodes[ch]["level"] == l + 1 and nodes[ch]["prefix"] == q
+            else:
+                assert ch == 0xFFFFFFFF
+    # queries walked through the image on a prefix of S (brute force is O(n))
+    m = min(n, 300)
+    sub = S[:m]
+    img2 = Image(oracle.build_image(KIND_SHAPED, sub, sigma, codes=codes, lens=lens))
+    check_queries(img2, sub, sigma, all_symbols=False)
+
+
+def test_shaped_incomplete_code():
+    # a prefix code that is not full: 0 -> "0", 1 -> "10", 2 -> "110"
+    codes = np.array([0b0, 0b10, 0b110], dtype=np.uint64)
+    lens = np.array([1, 2, 3], dtype=np.uint32)
+    S = np.array([2, 0, 1, 1, 2, 0, 0], dtype=np.uint8)
+    img = Image(oracle.build_image(KIND_SHAPED, S, 3, codes=codes, lens=lens))
+    nodes = img.nodes()
+    assert [(nd["level"], nd["prefix"]) for nd in nodes] == [(0, 0), (1, 1), (2, 3)]
+    assert nodes[2]["child"] == (LEAF | 2, 0xFFFFFFFF)
+    check_queries(img, S, 3)
+
+
+# ---------------------------------------------------------------------------
+# errors and layout
+# ---------------------------------------------------------------------------
+
+def test_errors():
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.build_image(KIND_WM, np.array([0, 5, 1], dtype=np.uint8), 5)
+    assert e.value.code == oracle.ERANGE
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.build_image(KIND_WT, np.array([0], dtype=np.uint8), 0)
+    assert e.value.code == oracle.EINVAL
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.build_image(KIND_MULTI, np.array([0], dtype=np.uint8), 4, 5)
+    assert e.value.code == oracle.EINVAL
+    codes = np.array([0, 1, 0], dtype=np.uint64)
+    lens = np.array([1, 1, 0], dtype=np.uint32)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.build_image(KIND_SHAPED, np.array([0, 2], dtype=np.uint8), 3, codes=codes, lens=lens)
+    assert e.value.code == oracle.ERANGE
+
+
+@pytest.mark.parametrize("kind,D", [(KIND_WT, 1), (KIND_WM, 1), (KIND_MULTI, 2), (KIND_SHAPED, 1)])
+def test_layout(kind, D):
+    rng = np.random.default_rng(kind)
+    S = rng.integers(0, 37, 1000).astype(np.uint8)
+    buf = build(kind, S, 37, D)
+    img = Image(buf)
+    assert img.image_bytes == buf.size and buf.size % 256 == 0
+    spans = [(0, 256 + 64 * img.nlevels)]
+    for l, lv in enumerate(img.levels):
+        for key in ("bits_off", "rank_off", "sel0_off", "sel1_off"):
+            if lv[key]:
+                assert lv[key] % 256 == 0
+        m = lv["n"]
+        if kind == KIND_MULTI:
+            p = 64 // D
+            d = 1 << D
+            spans.append((lv["bits_off"], lv["bits_off"] + 8 * (-(-m // p))))
+            nsb, nb = -(-m // (64 * p)), -(-m // (8 * p))
+            spans.append((lv["rank_off"], lv["rank_off"] + (nsb + 1) * d * 8 + nb * d * 2))
+        else:
+            spans.append((lv["bits_off"], lv["bits_off"] + 8 * (-(-m // 64))))
+            spans.append((lv["rank_off"], lv["rank_off"] + 16 * (-(-m // 512) + 1)))
+            spans.append((lv["sel0_off"], lv["sel0_off"] + 8 * lv["nsel"]))
+            spans.append((lv["sel1_off"], lv["sel1_off"] + 8 * lv["nsel"]))
+    if kind == KIND_SHAPED:
+        spans.append((img.nodes_off, img.nodes_off + 32 * img.nnodes))
+        spans.append((img.codes_off, img.codes_off + 16 * img.sigma))
+    spans.sort()
+    for (a0, a1), (b0, b1) in zip(spans, spans[1:]):
+        assert a1 <= b0
+    covered = np.zeros(buf.size, dtype=bool)
+    for a, b in spans:
+        covered[a:b] = True
+    assert not buf[~covered].any(), "bytes outside every array must be zero"
