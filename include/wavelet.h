@@ -1,0 +1,217 @@
+/*
+ * wavelet.h -- C-ABI of the MI355X wavelet tree / wavelet matrix builder.
+ *
+ * Builds, on one AMD Instinct MI355X (gfx950), the structures of Shun,
+ * "Improved Parallel Construction of Wavelet Trees and Rank/Select
+ * Structures", over an integer sequence S of n symbols drawn from the
+ * alphabet [0, sigma-1] (Sec. 2, problem statement):
+ *
+ *   kind WT_KIND_WT        balanced binary wavelet tree, levelwise and
+ *                          pointerless (Sec. 2, recursive definition)
+ *   kind WT_KIND_WM        wavelet matrix (Sec. 4.3, "Wavelet matrix")
+ *   kind WT_KIND_SHAPED    binary tree shaped by given codewords, e.g.
+ *                          Huffman-shaped (Sec. 4.3, "Arbitrarily-shaped")
+ *   kind WT_KIND_MULTIARY  balanced multiary tree of degree d = 2^D,
+ *                          D in 1..4 (Sec. 4.3, "Multiary wavelet trees")
+ *
+ * Every binary level carries a rank-of-0 directory (Sec. 5.1, "Rank": 512-bit
+ * ranges, 64-bit sub-ranges) and sampled select on ones and zeros (Sec. 5.1,
+ * "Select", sampling every 4096th one/zero); multiary levels carry per-digit
+ * rank counters (Sec. 5.2, "Rank").
+ *
+ * Output: one flat, position-independent byte image per structure (layout
+ * below).  The image only holds offsets, so it can be copied, saved and
+ * reloaded as is.
+ *
+ * Conventions shared by every call:
+ *   - "dev" pointers are device memory (hipMalloc'ed or torch CUDA tensors);
+ *     "host" pointers are ordinary host memory.  All buffers are owned by the
+ *     caller; the library never allocates device memory on the build path.
+ *   - `stream` is a hipStream_t passed as void*; NULL is the default stream.
+ *     Build and query calls are asynchronous on `stream` unless stated.
+ *   - Return value: WT_OK or a negative WT_E* code.  Argument errors are
+ *     reported before anything is launched.  A symbol >= sigma is found on
+ *     the device: the build then marks the image header and wt_check()
+ *     returns WT_ERANGE (the rest of the image is unspecified).
+ *   - Limits: n < 2^32, sigma >= 1, sym_bytes in {1, 2, 4}, at most 32
+ *     levels, codeword length <= 32.
+ */
+#ifndef WAVELET_H
+#define WAVELET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define WT_OK       0
+#define WT_EINVAL  (-1)   /* bad n / sigma / width / shape / pointer       */
+#define WT_ERANGE  (-2)   /* a symbol >= sigma (or without codeword) seen  */
+#define WT_ENOSPC  (-3)   /* output or workspace buffer too small          */
+#define WT_EHIP    (-4)   /* a HIP runtime call failed                     */
+#define WT_EUNSUP  (-5)   /* outside the supported limits                  */
+
+/* ---- kinds -------------------------------------------------------------- */
+#define WT_KIND_WT        1
+#define WT_KIND_WM        2
+#define WT_KIND_SHAPED    3
+#define WT_KIND_MULTIARY  4
+
+/* ---- image layout (little endian) ----------------------------------------
+ * Header, 256 bytes at offset 0:
+ *   u32 magic 0x54564157 ("WAVT"), u32 version 1, u32 kind, u32 arity_log2,
+ *   u64 n, u32 sigma, u32 nlevels, u32 key_bits, u32 status (0 ok, 1 = a
+ *   symbol >= sigma was seen), u64 image_bytes, u64 levels_off (= 256),
+ *   u64 nodes_off, u64 nnodes, u64 codes_off, u64 ncoded; rest zero.
+ * Level descriptors, 64 bytes each, at levels_off + 64*l:
+ *   u64 n_l, u64 zeros, u64 ones, u64 bits_off, u64 rank_off, u64 sel0_off,
+ *   u64 sel1_off, u64 nsel.   (multiary: zeros = ones = sel* = nsel = 0)
+ * Arrays, each starting on a 256-byte boundary, level after level:
+ *   binary level  bits: ceil(n_l/64) u64 words, bit i at bit (i%64) of word
+ *                 i/64 (LSB first), padding bits 0;
+ *                 rank: ceil(n_l/512)+1 pairs {u64 sb0, u64 blk}: sb0[k] =
+ *                 zeros in [0, min(512k, n_l)); blk[k] = sum over j = 1..7 of
+ *                 (zeros in [512k, min(512k+64j, n_l))) << 9(j-1), 0 when
+ *                 512k >= n_l;
+ *                 sel0 / sel1: nsel = ceil(n_l/4096)+1 u64: position of the
+ *                 zero / one whose 0-based ordinal is 4096k, then n_l.
+ *   multiary level (D-bit digits, P = floor(64/D) per word, digit t at bits
+ *                 [tD, tD+D) of word t/P): ceil(n_l/P) words; then counters:
+ *                 (ceil(n_l/64P)+1) x d u64 = count of each digit before
+ *                 every 64-word range (last entry = totals), followed by
+ *                 ceil(n_l/8P) x d u16 = count of each digit from the start
+ *                 of its range to the start of every 8-word sub-range.
+ *   shaped trees  node table (32 B per internal node, ordered by (level,
+ *                 prefix)): u64 start in its level, u64 count, u32 child[2]
+ *                 (node index, or 0x80000000|symbol for a leaf, 0xFFFFFFFF
+ *                 if absent), u32 level, u32 prefix; then the code table
+ *                 (16 B per symbol): u64 codeword, u32 length (0 = none), u32 0.
+ * Bytes outside every array are zero.  Balanced trees (Sec. 2): level l is
+ * the concatenation of the node bitstrings of depth l, left to right, every
+ * level has n bits.  Wavelet matrix: level l is bit l from the top of the
+ * symbols in the order of level l, zeros counted in `zeros` (Sec. 4.3).
+ * ------------------------------------------------------------------------ */
+
+typedef struct wt_shape {
+    uint32_t arity_log2;       /* multiary: D in 1..4; binary kinds: 0 or 1 */
+    uint32_t reserved;
+    const uint64_t* codes;     /* shaped: host [sigma], codeword value, its
+                                  i-th most significant of code_len bits is 0
+                                  when the root-to-leaf path turns left
+                                  (Sec. 4.3, "Arbitrarily-shaped")          */
+    const uint32_t* code_len;  /* shaped: host [sigma], 0 = no codeword    */
+    const uint64_t* counts;    /* shaped: host [sigma], occurrences of every
+                                  symbol in S (fixes the level sizes)       */
+} wt_shape;
+
+typedef struct wt_tuning {
+    uint32_t tau;      /* key bits per partition pass, 1..8 (0 = automatic) */
+    uint32_t tile;     /* elements per tile (0 = automatic)                 */
+    uint32_t blocks;   /* workgroups per pass (0 = automatic)               */
+    uint32_t flags;    /* WT_FLAG_*                                         */
+} wt_tuning;
+
+/* force the level-by-level path (one level per pass) for any kind */
+#define WT_FLAG_LEVELWISE 1u
+
+typedef struct wt_plan_info {
+    uint32_t kind, nlevels, key_bits, arity_log2;
+    uint64_t n;
+    uint32_t sigma, tau;
+    uint64_t out_bytes;        /* size of the canonical image              */
+    uint64_t workspace_bytes;  /* device scratch the build needs           */
+    uint64_t level_n[32];      /* bits / digits per level                  */
+} wt_plan_info;
+
+/* Size a build (Sec. 2 problem statement; host only, no device work).
+ * shape: NULL for WT/WM; codes+code_len+counts for SHAPED; arity for
+ * MULTIARY.  tune may be NULL.  Fills *info. */
+int wt_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes,
+            const wt_shape* shape, const wt_tuning* tune, wt_plan_info* info);
+
+/* Build a balanced binary wavelet tree (Sec. 2), or, when shape->codes is
+ * set, the tree shaped by those codewords (Sec. 4.3, Thm. 4.4).
+ * S: dev, n symbols of sym_bytes each.  out: dev, out_bytes >= plan
+ * out_bytes, receives the image.  ws: dev scratch of ws_bytes >= plan
+ * workspace_bytes.  Shaped builds synchronize `stream` once (symbol counts
+ * are checked against shape->counts; a mismatch returns WT_EINVAL). */
+int wt_build(const void* S, uint64_t n, uint32_t sigma, uint32_t sym_bytes,
+             const wt_shape* shape, const wt_tuning* tune,
+             void* out, size_t out_bytes, void* ws, size_t ws_bytes, void* stream);
+
+/* Build a wavelet matrix (Sec. 4.3, Thm. 4.6).  Same arguments as wt_build;
+ * shape must be NULL. Fully asynchronous. */
+int wm_build(const void* S, uint64_t n, uint32_t sigma, uint32_t sym_bytes,
+             const wt_shape* shape, const wt_tuning* tune,
+             void* out, size_t out_bytes, void* ws, size_t ws_bytes, void* stream);
+
+/* Build a balanced multiary wavelet tree of degree 2^shape->arity_log2
+ * (Sec. 4.3, Thm. 4.5) with per-digit rank counters (Sec. 5.2).  Same
+ * arguments as wt_build.  Synchronizes `stream` once (node table). */
+int multiary_build(const void* S, uint64_t n, uint32_t sigma, uint32_t sym_bytes,
+                   const wt_shape* shape, const wt_tuning* tune,
+                   void* out, size_t out_bytes, void* ws, size_t ws_bytes, void* stream);
+
+/* Synchronize `stream` and read the status word of a built image (dev).
+ * Returns WT_OK, or WT_ERANGE if a symbol >= sigma was seen. */
+int wt_check(const void* image, void* stream);
+
+/* Batched queries on a built image (dev), m queries, all arrays dev.
+ * access (Sec. 2): res[q] = S[pos[q]], UINT32_MAX if pos[q] >= n.
+ * rank   (Sec. 2): res[q] = occurrences of c[q] in S[0..i[q]] (inclusive);
+ *                  0 if c[q] >= sigma or has no codeword; UINT64_MAX if
+ *                  i[q] >= n.
+ * select (Sec. 2): res[q] = position of the k[q]-th occurrence of c[q]
+ *                  (k 1-based); UINT64_MAX if k = 0, k > count or c invalid. */
+int wt_access(const void* image, const uint64_t* pos, uint32_t* res, uint64_t m, void* stream);
+int wt_rank(const void* image, const uint32_t* c, const uint64_t* i, uint64_t* res,
+            uint64_t m, void* stream);
+int wt_select(const void* image, const uint32_t* c, const uint64_t* k, uint64_t* res,
+              uint64_t m, void* stream);
+
+/* Occurrences of every symbol of S (dev) into counts (dev, sigma u64), e.g.
+ * to build Huffman codewords; symbols >= sigma are not counted. */
+int wt_symbol_counts(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma,
+                     uint64_t* counts, void* stream);
+
+/* Canonical Huffman codewords from counts (all host arrays of sigma).
+ * Two-queue merge with leaves ordered by (count, symbol), the leaf taken on
+ * equal weight; codes assigned in (length, symbol) order; a single coded
+ * symbol gets length 1; count 0 gets length 0.  WT_EUNSUP if a length
+ * exceeds 32. */
+int wt_huffman_codes(const uint64_t* counts, uint32_t sigma, uint64_t* codes, uint32_t* code_len);
+
+/* One sequence of a batched build.  S, out: dev pointers. */
+typedef struct wt_seq_desc {
+    const void* S;
+    uint64_t n;
+    uint32_t sigma;
+    uint32_t sym_bytes;
+    void* out;
+    uint64_t out_bytes;
+} wt_seq_desc;
+
+/* Size of the workspace a batched build of `count` sequences needs. */
+int wt_batch_plan(int kind, const wt_seq_desc* seqs, uint32_t count, const wt_tuning* tune,
+                  uint64_t* workspace_bytes);
+
+/* Build wavelet matrices (kind WT_KIND_WM) of many sequences with a few
+ * persistent launches; each image equals the one wm_build writes for that
+ * sequence alone.  seqs: host array of count descriptors. */
+int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count,
+                   void* ws, size_t ws_bytes, const wt_tuning* tune, void* stream);
+
+/* Bytes of a built image (reads the header; dev image, synchronizes). */
+int wt_image_bytes(const void* image, uint64_t* bytes, void* stream);
+
+/* Human-readable text of a status code. */
+const char* wt_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WAVELET_H */

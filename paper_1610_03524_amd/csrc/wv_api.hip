@@ -1,0 +1,559 @@
+// wv_api.hip -- C-ABI entry points of libwavelet (declared in wavelet.h).
+//
+// Planning (image layout and workspace), the host-side pieces of the tree
+// builds (node tables from symbol counts, canonical Huffman codewords) and
+// the dispatch to the device passes.
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <utility>
+#include <vector>
+
+#include "wv_internal.h"
+#include "wv_levelwise.h"
+#include "wv_wm_passes.h"
+
+namespace {
+
+struct Plan {
+    int kind = 0;
+    uint32_t sigma = 0, sym_bytes = 0, D = 1, key_bits = 0, nlevels = 0, tau = 0;
+    uint64_t n = 0, nnodes_image = 0, ncoded = 0;
+    bool levelwise = false;
+    wv_layout_in lin{};
+    wv_layout_out lay{};
+    // workspace regions (byte offsets)
+    uint64_t ws_scalars = 0, ws_keys_a = 0, ws_keys_b = 0, ws_nodes_a = 0, ws_nodes_b = 0;
+    uint64_t ws_sb_ones = 0, ws_sb_pre = 0, ws_partial = 0, ws_counts = 0;
+    uint64_t ws_nt_start = 0, ws_nt_cstart = 0, ws_nt_child = 0, node_bound = 0;
+    uint64_t ws_codes = 0, ws_lens = 0, ws_wm = 0;
+    uint64_t ws_bytes = 0;
+    wv_wm_plan wm{};
+};
+
+bool is_tree(int kind) { return kind == WT_KIND_WT || kind == WT_KIND_SHAPED || kind == WT_KIND_MULTIARY; }
+
+uint64_t bump(uint64_t& off, uint64_t bytes)
+{
+    uint64_t at = off;
+    off = wv_round256(off + bytes);
+    return at;
+}
+
+int make_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt_shape* shape,
+              const wt_tuning* tune, Plan& p)
+{
+    if (kind < WT_KIND_WT || kind > WT_KIND_MULTIARY) return WT_EINVAL;
+    if (sigma == 0) return WT_EINVAL;
+    if (sym_bytes != 1 && sym_bytes != 2 && sym_bytes != 4) return WT_EINVAL;
+    if (n >= (1ull << 32)) return WT_EUNSUP;
+    p.kind = kind;
+    p.n = n;
+    p.sigma = sigma;
+    p.sym_bytes = sym_bytes;
+    const uint32_t L = wv_key_bits(sigma);
+    p.levelwise = tune && ((tune->flags & WT_FLAG_LEVELWISE) || tune->tau == 1);
+    if (kind == WT_KIND_WM && shape && shape->codes) return WT_EINVAL;
+
+    std::vector<uint64_t> level_n;
+    if (kind == WT_KIND_WT || kind == WT_KIND_WM) {
+        p.D = 1;
+        p.key_bits = L;
+        p.nlevels = L;
+        level_n.assign(L, n);
+    } else if (kind == WT_KIND_MULTIARY) {
+        if (!shape || shape->arity_log2 < 1 || shape->arity_log2 > 4) return WT_EINVAL;
+        p.D = shape->arity_log2;
+        p.nlevels = (L + p.D - 1) / p.D;
+        p.key_bits = p.D * p.nlevels;
+        level_n.assign(p.nlevels, n);
+    } else {
+        if (!shape || !shape->codes || !shape->code_len || !shape->counts) return WT_EINVAL;
+        uint32_t h = 0;
+        uint64_t total = 0;
+        for (uint32_t s = 0; s < sigma; s++) {
+            const uint32_t len = shape->code_len[s];
+            if (len > 32) return WT_EUNSUP;
+            if (len && len < 64 && (shape->codes[s] >> len)) return WT_EINVAL;
+            if (len) p.ncoded++;
+            h = std::max(h, len);
+            total += shape->counts[s];
+            if (shape->counts[s] && !len) return WT_ERANGE;
+        }
+        if (h == 0 || total != n) return WT_EINVAL;
+        p.D = 1;
+        p.key_bits = h;
+        p.nlevels = h;
+        level_n.assign(h, 0);
+        for (uint32_t s = 0; s < sigma; s++)
+            for (uint32_t l = 0; l < shape->code_len[s]; l++) level_n[l] += shape->counts[s];
+    }
+    if (p.nlevels > WV_MAX_LEVELS) return WT_EUNSUP;
+
+    // image layout
+    p.lin = wv_layout_in{};
+    p.lin.kind = (uint32_t)kind;
+    p.lin.arity_log2 = kind == WT_KIND_MULTIARY ? p.D : 1u;
+    p.lin.nlevels = p.nlevels;
+    p.lin.key_bits = p.key_bits;
+    p.lin.sigma = sigma;
+    p.lin.n = n;
+    p.lin.ncoded = p.ncoded;
+    for (uint32_t l = 0; l < p.nlevels; l++) p.lin.level_n[l] = level_n[l];
+    if (kind == WT_KIND_SHAPED) {
+        // internal nodes: distinct proper prefixes of the codewords
+        std::vector<std::pair<uint32_t, uint64_t>> keys;
+        for (uint32_t s = 0; s < sigma; s++)
+            for (uint32_t l = 0; l < shape->code_len[s]; l++)
+                keys.emplace_back(l, l ? shape->codes[s] >> (shape->code_len[s] - l) : 0ull);
+        std::sort(keys.begin(), keys.end());
+        keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+        p.nnodes_image = keys.size();
+        p.lin.nnodes = p.nnodes_image;
+    }
+    wv_layout(p.lin, p.lay);
+
+    // node-table bound for the tree builds
+    if (kind == WT_KIND_SHAPED) {
+        p.node_bound = std::max<uint64_t>(p.nnodes_image, 1);
+    } else if (is_tree(kind)) {
+        uint64_t b = 0;
+        for (uint32_t be = 0; be < p.nlevels; be++) {
+            const uint32_t sh = p.key_bits - p.D * be;
+            uint64_t a = sh >= 64 ? 1 : (((uint64_t)(sigma - 1) >> sh) + 1);
+            uint64_t full = (p.D * be >= 40) ? ~0ull : (1ull << (p.D * be));
+            b += std::min(std::min(a, full), std::max<uint64_t>(n, 1));
+        }
+        p.node_bound = b;
+    }
+
+    // workspace
+    const uint32_t d = 1u << p.D;
+    const uint64_t ns = wv_cdiv(n, WV_SB_BITS);
+    const uint64_t nr = kind == WT_KIND_MULTIARY ? wv_mranges(n, p.D) : 0;
+    const uint64_t dir_items = std::max<uint64_t>(std::max(ns, nr * d), 1);
+    uint64_t off = 0;
+    p.ws_scalars = bump(off, 256);
+    p.ws_sb_ones = bump(off, dir_items * 4);
+    p.ws_sb_pre = bump(off, dir_items * 8);
+    p.ws_partial = bump(off, 8 * std::max(wv_scan_partials(ns, 1), wv_scan_partials(nr, d)));
+    if (kind == WT_KIND_WM && !p.levelwise) {
+        int rc = wv_wm_make_plan(n, sigma, sym_bytes, tune, p.wm);
+        if (rc) return rc;
+        p.levelwise = !p.wm.enabled;
+    }
+    if (kind == WT_KIND_WM && !p.levelwise) {
+        p.tau = p.wm.tau;
+        p.ws_wm = bump(off, p.wm.ws_bytes);
+    } else {
+        p.tau = 1;
+        p.ws_keys_a = bump(off, std::max<uint64_t>(n, 1) * 4);
+        p.ws_keys_b = bump(off, std::max<uint64_t>(n, 1) * 4);
+    }
+    if (is_tree(kind)) {
+        p.ws_nodes_a = bump(off, std::max<uint64_t>(n, 1) * 4);
+        p.ws_nodes_b = bump(off, std::max<uint64_t>(n, 1) * 4);
+        p.ws_counts = bump(off, (uint64_t)sigma * 8);
+        p.ws_nt_start = bump(off, p.node_bound * 4);
+        p.ws_nt_cstart = bump(off, p.node_bound * d * 4);
+        p.ws_nt_child = bump(off, p.node_bound * d * 4);
+    }
+    if (kind == WT_KIND_SHAPED) {
+        p.ws_codes = bump(off, (uint64_t)sigma * 4);
+        p.ws_lens = bump(off, (uint64_t)sigma * 4);
+    }
+    p.ws_bytes = off;
+    return WT_OK;
+}
+
+// ---- host node tables ----------------------------------------------------------
+
+struct HostNodes {
+    std::vector<uint32_t> start, child_start, child;
+};
+
+// Balanced trees (binary D = 1, or multiary): node = nonempty prefix of the
+// top D*beta key bits; every level keeps all n symbols, so a node's start is
+// the number of symbols with a smaller prefix.
+int balanced_nodes(const std::vector<uint64_t>& counts, uint32_t sigma, uint32_t Lb, uint32_t D, uint32_t M,
+                   HostNodes& H)
+{
+    const uint32_t d = 1u << D;
+    std::vector<std::vector<uint64_t>> pc(M), st(M);
+    std::vector<std::vector<uint32_t>> id(M);
+    uint32_t next = 0;
+    for (uint32_t be = 0; be < M; be++) {
+        const uint32_t sh = Lb - D * be;
+        const uint64_t size = sh >= 64 ? 1 : (((uint64_t)(sigma - 1) >> sh) + 1);
+        pc[be].assign(size, 0);
+        for (uint32_t x = 0; x < sigma; x++) pc[be][sh >= 64 ? 0 : ((uint64_t)x >> sh)] += counts[x];
+        st[be].assign(size, 0);
+        id[be].assign(size, WV_NONE);
+        uint64_t run = 0;
+        for (uint64_t q = 0; q < size; q++) {
+            st[be][q] = run;
+            run += pc[be][q];
+            if (pc[be][q] || (be == 0)) id[be][q] = next++;
+        }
+    }
+    H.start.assign(next, 0);
+    H.child_start.assign((uint64_t)next * d, 0);
+    H.child.assign((uint64_t)next * d, WV_NONE);
+    for (uint32_t be = 0; be < M; be++) {
+        for (uint64_t q = 0; q < pc[be].size(); q++) {
+            const uint32_t k = id[be][q];
+            if (k == WV_NONE) continue;
+            H.start[k] = (uint32_t)st[be][q];
+            for (uint32_t g = 0; g < d; g++) {
+                uint32_t c = WV_LEAF;
+                uint64_t cs = 0;
+                if (be + 1 < M) {
+                    const uint64_t q2 = q * d + g;
+                    c = WV_NONE;
+                    if (q2 < pc[be + 1].size() && pc[be + 1][q2]) {
+                        c = id[be + 1][q2];
+                        cs = st[be + 1][q2];
+                    }
+                }
+                H.child[(uint64_t)k * d + g] = c;
+                H.child_start[(uint64_t)k * d + g] = (uint32_t)cs;
+            }
+        }
+    }
+    return WT_OK;
+}
+
+// Shaped tree (Sec. 4.3): internal nodes are the proper codeword prefixes,
+// ordered by (level, prefix); the start of a node on its level is the number
+// of symbols of that level under smaller prefixes.  Also fills the image's
+// node-table records.
+int shaped_nodes(const wt_shape& sh, uint32_t sigma, HostNodes& H, std::vector<uint8_t>& rec)
+{
+    std::vector<std::pair<uint32_t, uint64_t>> keys;
+    for (uint32_t s = 0; s < sigma; s++)
+        for (uint32_t l = 0; l < sh.code_len[s]; l++)
+            keys.emplace_back(l, l ? sh.codes[s] >> (sh.code_len[s] - l) : 0ull);
+    std::sort(keys.begin(), keys.end());
+    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+    const uint64_t N = keys.size();
+    auto find = [&](uint32_t l, uint64_t p) -> int64_t {
+        auto it = std::lower_bound(keys.begin(), keys.end(), std::make_pair(l, p));
+        if (it == keys.end() || it->first != l || it->second != p) return -1;
+        return it - keys.begin();
+    };
+    std::map<std::pair<uint32_t, uint64_t>, uint32_t> leaf;   // (len, code) -> symbol
+    for (uint32_t s = 0; s < sigma; s++) {
+        if (!sh.code_len[s]) continue;
+        auto k = std::make_pair(sh.code_len[s], sh.codes[s]);
+        if (leaf.count(k) || find(k.first, k.second) >= 0) return WT_EINVAL;   // not prefix-free
+        leaf[k] = s;
+    }
+    std::vector<uint64_t> cnt(N, 0), start(N, 0);
+    for (uint32_t s = 0; s < sigma; s++)
+        for (uint32_t l = 0; l < sh.code_len[s]; l++)
+            cnt[find(l, l ? sh.codes[s] >> (sh.code_len[s] - l) : 0ull)] += sh.counts[s];
+    uint64_t run = 0;
+    for (uint64_t t = 0; t < N; t++) {
+        if (t == 0 || keys[t].first != keys[t - 1].first) run = 0;
+        start[t] = run;
+        run += cnt[t];
+    }
+    H.start.assign(N, 0);
+    H.child_start.assign(2 * N, 0);
+    H.child.assign(2 * N, WV_NONE);
+    rec.assign(N * WV_NODE_BYTES, 0);
+    for (uint64_t t = 0; t < N; t++) {
+        H.start[t] = (uint32_t)start[t];
+        uint32_t ch[2];
+        for (uint32_t b = 0; b < 2; b++) {
+            const uint32_t l1 = keys[t].first + 1;
+            const uint64_t q = keys[t].second * 2 + b;
+            uint32_t c = WV_NONE;
+            uint64_t cs = 0;
+            auto lf = leaf.find(std::make_pair(l1, q));
+            if (lf != leaf.end()) {
+                c = WV_LEAF | lf->second;
+            } else {
+                const int64_t k = find(l1, q);
+                if (k >= 0) { c = (uint32_t)k; cs = start[k]; }
+            }
+            ch[b] = c;
+            H.child[2 * t + b] = c;
+            H.child_start[2 * t + b] = (uint32_t)cs;
+        }
+        uint8_t* e = rec.data() + t * WV_NODE_BYTES;
+        const uint32_t lev = keys[t].first, pre = (uint32_t)keys[t].second;
+        std::memcpy(e + 0, &start[t], 8);
+        std::memcpy(e + 8, &cnt[t], 8);
+        std::memcpy(e + 16, &ch[0], 4);
+        std::memcpy(e + 20, &ch[1], 4);
+        std::memcpy(e + 24, &lev, 4);
+        std::memcpy(e + 28, &pre, 4);
+    }
+    return WT_OK;
+}
+
+template <typename T>
+T* at(void* base, uint64_t off) { return (T*)((uint8_t*)base + off); }
+
+wv_lw_args lw_args(const Plan& p, const void* S, void* out, void* ws)
+{
+    wv_lw_args a{};
+    a.kind = p.kind;
+    a.arity_log2 = p.D;
+    a.key_bits = p.key_bits;
+    a.nlevels = p.nlevels;
+    a.S = S;
+    a.image = (uint8_t*)out;
+    a.lay = &p.lay;
+    a.keys_a = at<uint32_t>(ws, p.ws_keys_a);
+    a.keys_b = at<uint32_t>(ws, p.ws_keys_b);
+    a.nodes_a = at<uint32_t>(ws, p.ws_nodes_a);
+    a.nodes_b = at<uint32_t>(ws, p.ws_nodes_b);
+    a.dir.sb_ones = at<uint32_t>(ws, p.ws_sb_ones);
+    a.dir.sb_pre = at<uint64_t>(ws, p.ws_sb_pre);
+    a.dir.partial = at<uint64_t>(ws, p.ws_partial);
+    a.dir.total = at<uint64_t>(ws, p.ws_scalars + 8);
+    a.mdir.rng_cnt = a.dir.sb_ones;
+    a.mdir.rng_pre = a.dir.sb_pre;
+    a.mdir.partial = a.dir.partial;
+    a.mdir.totals = at<uint64_t>(ws, p.ws_scalars + 16);
+    a.zl = at<uint64_t>(ws, p.ws_scalars);
+    a.nt.start = at<uint32_t>(ws, p.ws_nt_start);
+    a.nt.child_start = at<uint32_t>(ws, p.ws_nt_cstart);
+    a.nt.child = at<uint32_t>(ws, p.ws_nt_child);
+    a.codes = at<uint32_t>(ws, p.ws_codes);
+    a.lens = at<uint32_t>(ws, p.ws_lens);
+    return a;
+}
+
+int check_buffers(const Plan& p, const void* S, void* out, size_t out_bytes, void* ws, size_t ws_bytes)
+{
+    if ((!S && p.n) || !out || (!ws && p.ws_bytes)) return WT_EINVAL;
+    if (out_bytes < p.lay.image_bytes || ws_bytes < p.ws_bytes) return WT_ENOSPC;
+    return WT_OK;
+}
+
+int build_any(int kind, const void* S, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt_shape* shape,
+              const wt_tuning* tune, void* out, size_t out_bytes, void* ws, size_t ws_bytes, hipStream_t s)
+{
+    Plan p;
+    int rc = make_plan(kind, n, sigma, sym_bytes, shape, tune, p);
+    if (rc) return rc;
+    rc = check_buffers(p, S, out, out_bytes, ws, ws_bytes);
+    if (rc) return rc;
+    uint8_t* img = (uint8_t*)out;
+    WV_CHECK(wv_write_header(img, p.lin, s));
+
+    if (kind == WT_KIND_WM && !p.levelwise) {
+        WV_CHECK(wv_validate(S, n, sym_bytes, sigma, img, nullptr, s));
+        wv_dir_scratch dir{at<uint32_t>(ws, p.ws_sb_ones), at<uint64_t>(ws, p.ws_sb_pre),
+                           at<uint64_t>(ws, p.ws_partial), at<uint64_t>(ws, p.ws_scalars + 8)};
+        WV_CHECK(wv_wm_run(p.wm, S, img, p.lay, at<uint8_t>(ws, p.ws_wm), dir, s));
+        return WT_OK;
+    }
+
+    wv_lw_args a = lw_args(p, S, out, ws);
+    if (is_tree(kind)) {
+        uint64_t* dcounts = at<uint64_t>(ws, p.ws_counts);
+        WV_CHECK(wv_validate(S, n, sym_bytes, sigma, img, dcounts, s));
+        std::vector<uint64_t> counts(sigma);
+        uint32_t status = 0;
+        WV_CHECK(hipMemcpyAsync(counts.data(), dcounts, (uint64_t)sigma * 8, hipMemcpyDeviceToHost, s));
+        WV_CHECK(hipMemcpyAsync(&status, img + 36, 4, hipMemcpyDeviceToHost, s));
+        WV_CHECK(hipStreamSynchronize(s));
+        if (status) return WT_ERANGE;
+        HostNodes H;
+        std::vector<uint8_t> rec;
+        std::vector<uint8_t> code_rec;
+        std::vector<uint32_t> c32, l32;
+        if (kind == WT_KIND_SHAPED) {
+            for (uint32_t x = 0; x < sigma; x++)
+                if (counts[x] != shape->counts[x]) return WT_EINVAL;
+            rc = shaped_nodes(*shape, sigma, H, rec);
+            if (rc) return rc;
+            code_rec.assign((uint64_t)sigma * WV_CODE_BYTES, 0);
+            c32.resize(sigma);
+            l32.resize(sigma);
+            for (uint32_t x = 0; x < sigma; x++) {
+                const uint64_t c = shape->code_len[x] ? shape->codes[x] : 0;
+                const uint32_t len = shape->code_len[x];
+                std::memcpy(code_rec.data() + (uint64_t)x * WV_CODE_BYTES, &c, 8);
+                std::memcpy(code_rec.data() + (uint64_t)x * WV_CODE_BYTES + 8, &len, 4);
+                c32[x] = (uint32_t)c;
+                l32[x] = len;
+            }
+        } else {
+            rc = balanced_nodes(counts, sigma, p.key_bits, p.D, p.nlevels, H);
+            if (rc) return rc;
+        }
+        if (H.start.size() > p.node_bound) return WT_EUNSUP;
+        WV_CHECK(hipMemcpyAsync((void*)a.nt.start, H.start.data(), H.start.size() * 4, hipMemcpyHostToDevice, s));
+        WV_CHECK(hipMemcpyAsync((void*)a.nt.child_start, H.child_start.data(), H.child_start.size() * 4,
+                                hipMemcpyHostToDevice, s));
+        WV_CHECK(hipMemcpyAsync((void*)a.nt.child, H.child.data(), H.child.size() * 4, hipMemcpyHostToDevice, s));
+        if (kind == WT_KIND_SHAPED) {
+            WV_CHECK(hipMemcpyAsync((void*)a.codes, c32.data(), (uint64_t)sigma * 4, hipMemcpyHostToDevice, s));
+            WV_CHECK(hipMemcpyAsync((void*)a.lens, l32.data(), (uint64_t)sigma * 4, hipMemcpyHostToDevice, s));
+            if (!rec.empty())
+                WV_CHECK(hipMemcpyAsync(img + p.lay.nodes_off, rec.data(), rec.size(), hipMemcpyHostToDevice, s));
+            WV_CHECK(hipMemcpyAsync(img + p.lay.codes_off, code_rec.data(), code_rec.size(), hipMemcpyHostToDevice,
+                                    s));
+        }
+        // the host vectors above go out of scope: finish the copies first
+        WV_CHECK(hipStreamSynchronize(s));
+    } else {
+        WV_CHECK(wv_validate(S, n, sym_bytes, sigma, img, nullptr, s));
+    }
+    WV_CHECK(wv_run_levelwise(a, sym_bytes, s));
+    return WT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* wt_strerror(int code)
+{
+    switch (code) {
+    case WT_OK: return "ok";
+    case WT_EINVAL: return "invalid argument";
+    case WT_ERANGE: return "symbol out of range (>= sigma or without codeword)";
+    case WT_ENOSPC: return "output or workspace buffer too small";
+    case WT_EHIP: return "HIP runtime error";
+    case WT_EUNSUP: return "outside the supported limits";
+    default: return "unknown status";
+    }
+}
+
+int wt_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt_shape* shape,
+            const wt_tuning* tune, wt_plan_info* info)
+{
+    if (!info) return WT_EINVAL;
+    Plan p;
+    int rc = make_plan(kind, n, sigma, sym_bytes, shape, tune, p);
+    if (rc) return rc;
+    std::memset(info, 0, sizeof(*info));
+    info->kind = (uint32_t)kind;
+    info->nlevels = p.nlevels;
+    info->key_bits = p.key_bits;
+    info->arity_log2 = p.lin.arity_log2;
+    info->n = n;
+    info->sigma = sigma;
+    info->tau = p.tau;
+    info->out_bytes = p.lay.image_bytes;
+    info->workspace_bytes = p.ws_bytes;
+    for (uint32_t l = 0; l < p.nlevels; l++) info->level_n[l] = p.lay.lv[l].n;
+    return WT_OK;
+}
+
+int wt_build(const void* S, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt_shape* shape,
+             const wt_tuning* tune, void* out, size_t out_bytes, void* ws, size_t ws_bytes, void* stream)
+{
+    const int kind = (shape && shape->codes) ? WT_KIND_SHAPED : WT_KIND_WT;
+    return build_any(kind, S, n, sigma, sym_bytes, shape, tune, out, out_bytes, ws, ws_bytes, (hipStream_t)stream);
+}
+
+int wm_build(const void* S, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt_shape* shape,
+             const wt_tuning* tune, void* out, size_t out_bytes, void* ws, size_t ws_bytes, void* stream)
+{
+    if (shape && (shape->codes || shape->arity_log2 > 1)) return WT_EINVAL;
+    return build_any(WT_KIND_WM, S, n, sigma, sym_bytes, nullptr, tune, out, out_bytes, ws, ws_bytes,
+                     (hipStream_t)stream);
+}
+
+int multiary_build(const void* S, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt_shape* shape,
+                   const wt_tuning* tune, void* out, size_t out_bytes, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!shape || shape->codes) return WT_EINVAL;
+    return build_any(WT_KIND_MULTIARY, S, n, sigma, sym_bytes, shape, tune, out, out_bytes, ws, ws_bytes,
+                     (hipStream_t)stream);
+}
+
+int wt_check(const void* image, void* stream)
+{
+    if (!image) return WT_EINVAL;
+    uint32_t status = 0;
+    WV_CHECK(hipStreamSynchronize((hipStream_t)stream));
+    WV_CHECK(hipMemcpy(&status, (const uint8_t*)image + 36, 4, hipMemcpyDeviceToHost));
+    return status ? WT_ERANGE : WT_OK;
+}
+
+int wt_image_bytes(const void* image, uint64_t* bytes, void* stream)
+{
+    if (!image || !bytes) return WT_EINVAL;
+    uint32_t magic = 0;
+    WV_CHECK(hipStreamSynchronize((hipStream_t)stream));
+    WV_CHECK(hipMemcpy(&magic, image, 4, hipMemcpyDeviceToHost));
+    if (magic != WV_MAGIC) return WT_EINVAL;
+    WV_CHECK(hipMemcpy(bytes, (const uint8_t*)image + 40, 8, hipMemcpyDeviceToHost));
+    return WT_OK;
+}
+
+int wt_symbol_counts(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma, uint64_t* counts, void* stream)
+{
+    if ((!S && n) || !counts || sigma == 0) return WT_EINVAL;
+    if (sym_bytes != 1 && sym_bytes != 2 && sym_bytes != 4) return WT_EINVAL;
+    WV_CHECK(wv_validate(S, n, sym_bytes, sigma, nullptr, counts, (hipStream_t)stream));
+    return WT_OK;
+}
+
+// Canonical Huffman codewords.  Leaves are queued by (count, symbol); merged
+// nodes are queued in creation order (their weights never decrease); each
+// merge takes the two lightest heads, the leaf first on equal weight.
+int wt_huffman_codes(const uint64_t* counts, uint32_t sigma, uint64_t* codes, uint32_t* code_len)
+{
+    if (!counts || !codes || !code_len) return WT_EINVAL;
+    std::vector<std::pair<uint64_t, uint32_t>> leaves;
+    for (uint32_t s = 0; s < sigma; s++) {
+        codes[s] = 0;
+        code_len[s] = 0;
+        if (counts[s]) leaves.emplace_back(counts[s], s);
+    }
+    const size_t k = leaves.size();
+    if (k == 0) return WT_OK;
+    if (k == 1) {
+        code_len[leaves[0].second] = 1;
+        return WT_OK;
+    }
+    std::sort(leaves.begin(), leaves.end());
+    // tree nodes: 0..k-1 leaves (sorted order), k.. merged nodes
+    std::vector<uint64_t> merged_w;
+    std::vector<size_t> up(2 * k - 1, 0);
+    size_t lf = 0, mf = 0;
+    while (merged_w.size() < k - 1) {
+        size_t pick[2];
+        uint64_t w = 0;
+        for (int t = 0; t < 2; t++) {
+            const bool leaf_ok = lf < k;
+            const bool merged_ok = mf < merged_w.size();
+            if (leaf_ok && (!merged_ok || leaves[lf].first <= merged_w[mf])) {
+                w += leaves[lf].first;
+                pick[t] = lf++;
+            } else {
+                w += merged_w[mf];
+                pick[t] = k + mf++;
+            }
+        }
+        const size_t id = k + merged_w.size();
+        up[pick[0]] = up[pick[1]] = id;
+        merged_w.push_back(w);
+    }
+    std::vector<uint32_t> depth(2 * k - 1, 0);
+    for (size_t v = 2 * k - 2; v-- > 0;) depth[v] = depth[up[v]] + 1;
+    std::vector<std::pair<uint32_t, uint32_t>> order;   // (length, symbol)
+    for (size_t t = 0; t < k; t++) {
+        if (depth[t] > 32) return WT_EUNSUP;
+        code_len[leaves[t].second] = depth[t];
+        order.emplace_back(depth[t], leaves[t].second);
+    }
+    std::sort(order.begin(), order.end());
+    uint64_t c = 0;
+    for (size_t t = 0; t < order.size(); t++) {
+        if (t) c = (c + 1) << (order[t].first - order[t - 1].first);
+        codes[order[t].second] = c;
+    }
+    return WT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,185 @@
+// wv_common.h -- internal definitions shared by the HIP sources of libwavelet.
+//
+// The canonical image layout (documented in include/wavelet.h) is computed by
+// wv_layout(), callable on the host (planning) and on the device (header
+// writer), so the offsets every kernel uses come from one rule.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "wavelet.h"
+
+#define WV_MAGIC        0x54564157u
+#define WV_VERSION      1u
+#define WV_HEADER_BYTES 256u
+#define WV_LEVEL_BYTES  64u
+#define WV_NODE_BYTES   32u
+#define WV_CODE_BYTES   16u
+#define WV_SB_BITS      512u    // rank range (superblock), Sec. 5.1
+#define WV_SEL_STRIDE   4096u   // select sampling stride, Sec. 5.1
+#define WV_MAX_LEVELS   32u
+#define WV_LEAF         0x80000000u
+#define WV_NONE         0xFFFFFFFFu
+
+#define WV_CHECK(call)                                        \
+    do {                                                      \
+        hipError_t e_ = (call);                               \
+        if (e_ != hipSuccess) return WT_EHIP;                 \
+    } while (0)
+
+__host__ __device__ inline uint64_t wv_round256(uint64_t x) { return (x + 255u) & ~(uint64_t)255u; }
+__host__ __device__ inline uint64_t wv_cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+// L = max(1, ceil(log2 sigma)): the root range is [0, 2^L - 1] (Sec. 2).
+__host__ __device__ inline uint32_t wv_key_bits(uint32_t sigma)
+{
+    uint32_t L = 1;
+    while (L < 32 && ((uint64_t)1 << L) < sigma) L++;
+    return L;
+}
+
+// Sizes of the arrays of one level.
+__host__ __device__ inline uint64_t wv_bits_bytes(uint64_t m) { return wv_cdiv(m, 64) * 8; }
+__host__ __device__ inline uint64_t wv_rank_bytes(uint64_t m) { return (wv_cdiv(m, WV_SB_BITS) + 1) * 16; }
+__host__ __device__ inline uint64_t wv_nsel(uint64_t m) { return wv_cdiv(m, WV_SEL_STRIDE) + 1; }
+__host__ __device__ inline uint32_t wv_digits_per_word(uint32_t D) { return 64u / D; }
+__host__ __device__ inline uint64_t wv_mbits_bytes(uint64_t m, uint32_t D)
+{
+    return wv_cdiv(m, wv_digits_per_word(D)) * 8;
+}
+// multiary counters: range = 64 words, sub-range = 8 words
+__host__ __device__ inline uint64_t wv_mranges(uint64_t m, uint32_t D) { return wv_cdiv(m, 64ull * wv_digits_per_word(D)); }
+__host__ __device__ inline uint64_t wv_msubs(uint64_t m, uint32_t D) { return wv_cdiv(m, 8ull * wv_digits_per_word(D)); }
+__host__ __device__ inline uint64_t wv_mrank_bytes(uint64_t m, uint32_t D)
+{
+    uint64_t d = 1ull << D;
+    return (wv_mranges(m, D) + 1) * d * 8 + wv_msubs(m, D) * d * 2;
+}
+
+struct wv_level {
+    uint64_t n, bits_off, rank_off, sel0_off, sel1_off, nsel;
+};
+
+// Everything needed to place the arrays of an image.
+struct wv_layout_in {
+    uint32_t kind, arity_log2, nlevels, key_bits;
+    uint32_t sigma, pad;
+    uint64_t n, nnodes, ncoded;
+    uint64_t level_n[WV_MAX_LEVELS];
+};
+
+struct wv_layout_out {
+    wv_level lv[WV_MAX_LEVELS];
+    uint64_t nodes_off, codes_off, image_bytes;
+};
+
+__host__ __device__ inline void wv_layout(const wv_layout_in& in, wv_layout_out& out)
+{
+    const bool multi = in.kind == WT_KIND_MULTIARY;
+    const uint32_t D = in.arity_log2;
+    uint64_t off = WV_HEADER_BYTES + wv_round256((uint64_t)WV_LEVEL_BYTES * in.nlevels);
+    for (uint32_t l = 0; l < in.nlevels; l++) {
+        const uint64_t m = in.level_n[l];
+        wv_level& L = out.lv[l];
+        L.n = m;
+        L.bits_off = off;
+        off = wv_round256(off + (multi ? wv_mbits_bytes(m, D) : wv_bits_bytes(m)));
+        L.rank_off = off;
+        off = wv_round256(off + (multi ? wv_mrank_bytes(m, D) : wv_rank_bytes(m)));
+        if (!multi) {
+            L.nsel = wv_nsel(m);
+            L.sel0_off = off;
+            off = wv_round256(off + L.nsel * 8);
+            L.sel1_off = off;
+            off = wv_round256(off + L.nsel * 8);
+        } else {
+            L.nsel = L.sel0_off = L.sel1_off = 0;
+        }
+    }
+    out.nodes_off = out.codes_off = 0;
+    if (in.kind == WT_KIND_SHAPED) {
+        out.nodes_off = off;
+        off = wv_round256(off + in.nnodes * WV_NODE_BYTES);
+        out.codes_off = off;
+        off = wv_round256(off + (uint64_t)in.sigma * WV_CODE_BYTES);
+    }
+    out.image_bytes = off;
+}
+
+// ---- device helpers ---------------------------------------------------------
+
+template <typename T>
+__device__ inline uint32_t wv_load_sym(const void* S, uint64_t i)
+{
+    return (uint32_t)((const T*)S)[i];
+}
+
+// position of the set bit with 0-based ordinal r in w (r < popcount(w))
+__device__ inline uint32_t wv_select_in_word(uint64_t w, uint32_t r)
+{
+    uint32_t base = 0;
+    uint32_t c = __popc((uint32_t)w);
+    if (r >= c) { r -= c; w >>= 32; base = 32; }
+    uint32_t x = (uint32_t)w;
+    for (uint32_t step = 16; step >= 1; step >>= 1) {
+        uint32_t lo = x & ((1u << step) - 1u);
+        uint32_t cl = __popc(lo);
+        if (r >= cl) { r -= cl; x >>= step; base += step; } else { x = lo; }
+    }
+    return base;
+}
+
+// zeros in [0, i) of a binary level, from its rank directory and bit words
+__device__ inline uint64_t wv_rank0(const uint64_t* __restrict__ words,
+                                    const uint64_t* __restrict__ dir, uint64_t i)
+{
+    const uint64_t k = i >> 9;
+    const uint32_t q = (uint32_t)(i & 511);
+    uint64_t r = dir[2 * k];
+    const uint32_t j = q >> 6;
+    if (j) r += (dir[2 * k + 1] >> (9 * (j - 1))) & 511u;
+    const uint32_t t = q & 63;
+    if (t) {
+        const uint64_t w = words[i >> 6];
+        r += t - __popcll(w & ((1ull << t) - 1ull));
+    }
+    return r;
+}
+
+// number of digits equal to g among the first t (< P) digits of word w
+__device__ inline uint32_t wv_count_digit(uint64_t w, uint32_t D, uint32_t g, uint32_t t)
+{
+    if (t == 0) return 0;
+    // low-bit-of-every-digit mask
+    uint64_t lowm = 0;
+    for (uint32_t s = 0; s < 64 / D; s++) lowm |= 1ull << (s * D);
+    uint64_t pat = lowm * (uint64_t)g;
+    uint64_t x = w ^ pat;               // digit == g  <=>  digit of x == 0
+    uint64_t any = x;
+    for (uint32_t b = 1; b < D; b++) any |= x >> b;
+    uint64_t eq = ~any & lowm;
+    uint64_t keep = (t * D >= 64) ? ~0ull : ((1ull << (t * D)) - 1ull);
+    return (uint32_t)__popcll(eq & keep);
+}
+
+// digit g count in [0, i) of a multiary level from its counters and words
+__device__ inline uint64_t wv_mrank(const uint64_t* __restrict__ words, const uint8_t* __restrict__ cnt,
+                                    uint64_t m, uint32_t D, uint32_t g, uint64_t i)
+{
+    const uint32_t P = 64u / D;
+    const uint64_t d = 1ull << D;
+    const uint64_t nr = wv_mranges(m, D);
+    const uint64_t* rng = (const uint64_t*)cnt;
+    const uint16_t* sub = (const uint16_t*)(cnt + (nr + 1) * d * 8);
+    const uint64_t rk = i / (64ull * P);
+    uint64_t r = rng[rk * d + g];
+    const uint64_t sk = i / (8ull * P);
+    if (sk < wv_msubs(m, D) && (sk * 8ull * P) < m) r += sub[sk * d + g];
+    const uint64_t wk = i / P;
+    // whole words between the sub-range start and the word holding i
+    for (uint64_t w = sk * 8; w < wk; w++) r += wv_count_digit(words[w], D, g, P);
+    const uint32_t t = (uint32_t)(i - wk * P);
+    if (t) r += wv_count_digit(words[wk], D, g, t);
+    return r;
+}

@@ -1,0 +1,359 @@
+// wv_directory.hip -- rank/select directories, multiary counters, image
+// header and input validation.
+//
+// Binary levels (Sec. 5.1, "Rank"): the ones of every 512-bit superblock are
+// counted, an exclusive prefix sum gives the rank at every superblock
+// boundary (the paper's prefix sum over per-word counts, read every 8th
+// word), and each superblock then writes {zeros before it, seven 9-bit zero
+// counts relative to its start}.  Sampled select (Sec. 5.1, "Select"): the
+// superblock holding the one (zero) of ordinal 4096k finds it inside its
+// word and writes its position.  Multiary levels (Sec. 5.2, "Rank"): the same
+// with one counter per digit value.
+#include "wv_internal.h"
+
+namespace {
+
+constexpr int DIR_THREADS = 256;
+
+__device__ inline uint64_t valid_mask(int64_t vb)
+{
+    if (vb <= 0) return 0ull;
+    if (vb >= 64) return ~0ull;
+    return (1ull << vb) - 1ull;
+}
+
+__global__ void __launch_bounds__(DIR_THREADS)
+count_superblocks_k(const uint64_t* __restrict__ words, uint64_t n, uint32_t* __restrict__ sb_ones)
+{
+    const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t ns = wv_cdiv(n, WV_SB_BITS), nw = wv_cdiv(n, 64);
+    if (k >= ns) return;
+    uint32_t c = 0;
+    for (uint64_t j = 0; j < 8; j++) {
+        uint64_t w = 8 * k + j;
+        if (w < nw) c += __popcll(words[w]);
+    }
+    sb_ones[k] = c;
+}
+
+__global__ void __launch_bounds__(DIR_THREADS)
+dir_write_k(uint8_t* __restrict__ image, wv_level L, const uint64_t* __restrict__ sb_pre)
+{
+    const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t n = L.n;
+    const uint64_t ns = wv_cdiv(n, WV_SB_BITS), nw = wv_cdiv(n, 64);
+    if (k >= ns) return;
+    const uint64_t* words = (const uint64_t*)(image + L.bits_off);
+    uint64_t* dir = (uint64_t*)(image + L.rank_off);
+    uint64_t* sel0 = (uint64_t*)(image + L.sel0_off);
+    uint64_t* sel1 = (uint64_t*)(image + L.sel1_off);
+    const uint64_t base = k * WV_SB_BITS;
+    const uint64_t ones_before = sb_pre[k];
+    const uint64_t zeros_before = base - ones_before;
+
+    uint64_t w[8];
+    uint32_t o[8], z[8];
+    uint64_t blk = 0;
+    uint32_t zacc = 0, oacc = 0;
+    for (int j = 0; j < 8; j++) {
+        const uint64_t wi = 8 * k + j;
+        w[j] = wi < nw ? words[wi] : 0ull;
+        const int64_t vb = (int64_t)n - (int64_t)(base + 64u * j);
+        const uint32_t v = vb <= 0 ? 0u : (vb >= 64 ? 64u : (uint32_t)vb);
+        o[j] = __popcll(w[j]);
+        z[j] = v - o[j];
+        if (j >= 1) blk |= (uint64_t)zacc << (9 * (j - 1));
+        zacc += z[j];
+        oacc += o[j];
+    }
+    dir[2 * k] = zeros_before;
+    dir[2 * k + 1] = blk;
+
+    // the one of ordinal t (a multiple of 4096) inside this superblock
+    uint64_t t = wv_cdiv(ones_before, WV_SEL_STRIDE) * WV_SEL_STRIDE;
+    if (t < ones_before + oacc) {
+        uint32_t r = (uint32_t)(t - ones_before);
+        for (int j = 0; j < 8; j++) {
+            if (r < o[j]) { sel1[t / WV_SEL_STRIDE] = base + 64u * j + wv_select_in_word(w[j], r); break; }
+            r -= o[j];
+        }
+    }
+    t = wv_cdiv(zeros_before, WV_SEL_STRIDE) * WV_SEL_STRIDE;
+    if (t < zeros_before + zacc) {
+        uint32_t r = (uint32_t)(t - zeros_before);
+        for (int j = 0; j < 8; j++) {
+            if (r < z[j]) {
+                const int64_t vb = (int64_t)n - (int64_t)(base + 64u * j);
+                sel0[t / WV_SEL_STRIDE] = base + 64u * j + wv_select_in_word(~w[j] & valid_mask(vb), r);
+                break;
+            }
+            r -= z[j];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(DIR_THREADS)
+dir_finish_k(uint8_t* __restrict__ image, uint32_t level, wv_level L,
+             const uint64_t* __restrict__ total_ones, uint64_t* __restrict__ zl_dev)
+{
+    const uint64_t n = L.n;
+    const uint64_t ones = *total_ones, zeros = n - ones;
+    const uint64_t ns = wv_cdiv(n, WV_SB_BITS);
+    uint64_t* dir = (uint64_t*)(image + L.rank_off);
+    uint64_t* sel0 = (uint64_t*)(image + L.sel0_off);
+    uint64_t* sel1 = (uint64_t*)(image + L.sel1_off);
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    if (tid == 0) {
+        dir[2 * ns] = zeros;
+        dir[2 * ns + 1] = 0;
+        uint64_t* desc = (uint64_t*)(image + WV_HEADER_BYTES + (uint64_t)WV_LEVEL_BYTES * level);
+        desc[1] = zeros;
+        desc[2] = ones;
+        if (zl_dev) *zl_dev = zeros;
+    }
+    for (uint64_t k = wv_cdiv(ones, WV_SEL_STRIDE) + tid; k < L.nsel; k += stride) sel1[k] = n;
+    for (uint64_t k = wv_cdiv(zeros, WV_SEL_STRIDE) + tid; k < L.nsel; k += stride) sel0[k] = n;
+}
+
+// ---- multiary counters -------------------------------------------------------
+
+__global__ void __launch_bounds__(DIR_THREADS)
+mcount_k(const uint64_t* __restrict__ words, uint64_t m, uint32_t D, uint32_t* __restrict__ rng_cnt)
+{
+    const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t P = 64u / D, d = 1u << D;
+    const uint64_t nr = wv_mranges(m, D), nw = wv_cdiv(m, P);
+    if (r >= nr) return;
+    uint32_t c[16];
+    for (uint32_t g = 0; g < 16; g++) c[g] = 0;
+    for (uint64_t wi = 64 * r; wi < 64 * r + 64 && wi < nw; wi++) {
+        const uint64_t w = words[wi];
+        const uint64_t left = m - wi * P;
+        const uint32_t valid = left >= P ? P : (uint32_t)left;
+        for (uint32_t g = 0; g < d; g++) c[g] += wv_count_digit(w, D, g, valid);
+    }
+    for (uint32_t g = 0; g < d; g++) rng_cnt[r * d + g] = c[g];
+}
+
+__global__ void __launch_bounds__(DIR_THREADS)
+mwrite_k(uint8_t* __restrict__ image, wv_level L, uint32_t D, const uint64_t* __restrict__ rng_pre)
+{
+    const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t m = L.n;
+    const uint32_t P = 64u / D, d = 1u << D;
+    const uint64_t nr = wv_mranges(m, D), nsub = wv_msubs(m, D), nw = wv_cdiv(m, P);
+    if (r >= nr) return;
+    const uint64_t* words = (const uint64_t*)(image + L.bits_off);
+    uint64_t* rng = (uint64_t*)(image + L.rank_off);
+    uint16_t* sub = (uint16_t*)(image + L.rank_off + (nr + 1) * d * 8);
+    for (uint32_t g = 0; g < d; g++) rng[r * d + g] = rng_pre[r * d + g];
+    uint32_t c[16];
+    for (uint32_t g = 0; g < 16; g++) c[g] = 0;
+    for (uint32_t s = 0; s < 8; s++) {
+        const uint64_t sk = 8 * r + s;
+        if (sk >= nsub) break;
+        for (uint32_t g = 0; g < d; g++) sub[sk * d + g] = (uint16_t)c[g];
+        for (uint64_t wi = sk * 8; wi < sk * 8 + 8 && wi < nw; wi++) {
+            const uint64_t w = words[wi];
+            const uint64_t left = m - wi * P;
+            const uint32_t valid = left >= P ? P : (uint32_t)left;
+            for (uint32_t g = 0; g < d; g++) c[g] += wv_count_digit(w, D, g, valid);
+        }
+    }
+}
+
+__global__ void mfinish_k(uint8_t* __restrict__ image, wv_level L, uint32_t D, const uint64_t* __restrict__ totals)
+{
+    const uint32_t d = 1u << D;
+    const uint64_t nr = wv_mranges(L.n, D);
+    uint64_t* rng = (uint64_t*)(image + L.rank_off);
+    if (threadIdx.x < d) rng[nr * d + threadIdx.x] = totals[threadIdx.x];
+}
+
+// ---- header ------------------------------------------------------------------
+
+__global__ void __launch_bounds__(DIR_THREADS)
+header_k(uint8_t* __restrict__ img, wv_layout_in in)
+{
+    __shared__ wv_layout_out lay;
+    __shared__ uint64_t span_lo[4 * WV_MAX_LEVELS + 4], span_hi[4 * WV_MAX_LEVELS + 4];
+    __shared__ int nspan;
+    if (threadIdx.x == 0) {
+        wv_layout(in, lay);
+        const bool multi = in.kind == WT_KIND_MULTIARY;
+        int s = 0;
+        span_lo[s] = 0;
+        span_hi[s++] = WV_HEADER_BYTES + (uint64_t)WV_LEVEL_BYTES * in.nlevels;
+        for (uint32_t l = 0; l < in.nlevels; l++) {
+            const wv_level& L = lay.lv[l];
+            span_lo[s] = L.bits_off;
+            span_hi[s++] = L.bits_off + (multi ? wv_mbits_bytes(L.n, in.arity_log2) : wv_bits_bytes(L.n));
+            span_lo[s] = L.rank_off;
+            span_hi[s++] = L.rank_off + (multi ? wv_mrank_bytes(L.n, in.arity_log2) : wv_rank_bytes(L.n));
+            if (!multi) {
+                span_lo[s] = L.sel0_off;
+                span_hi[s++] = L.sel0_off + 8 * L.nsel;
+                span_lo[s] = L.sel1_off;
+                span_hi[s++] = L.sel1_off + 8 * L.nsel;
+            }
+        }
+        if (in.kind == WT_KIND_SHAPED) {
+            span_lo[s] = lay.nodes_off;
+            span_hi[s++] = lay.nodes_off + in.nnodes * WV_NODE_BYTES;
+            span_lo[s] = lay.codes_off;
+            span_hi[s++] = lay.codes_off + (uint64_t)in.sigma * WV_CODE_BYTES;
+        }
+        span_lo[s] = lay.image_bytes;   // sentinel
+        span_hi[s] = lay.image_bytes;
+        nspan = s;
+
+        uint32_t* h32 = (uint32_t*)img;
+        uint64_t* h64 = (uint64_t*)img;
+        h32[0] = WV_MAGIC;
+        h32[1] = WV_VERSION;
+        h32[2] = in.kind;
+        h32[3] = in.arity_log2;
+        h64[2] = in.n;
+        h32[6] = in.sigma;
+        h32[7] = in.nlevels;
+        h32[8] = in.key_bits;
+        h32[9] = 0;
+        h64[5] = lay.image_bytes;
+        h64[6] = WV_HEADER_BYTES;
+        h64[7] = lay.nodes_off;
+        h64[8] = in.nnodes;
+        h64[9] = lay.codes_off;
+        h64[10] = in.ncoded;
+    }
+    __syncthreads();
+    for (uint32_t b = 88 + threadIdx.x; b < WV_HEADER_BYTES; b += blockDim.x) img[b] = 0;
+    if (threadIdx.x < in.nlevels) {
+        const wv_level& L = lay.lv[threadIdx.x];
+        uint64_t* e = (uint64_t*)(img + WV_HEADER_BYTES + (uint64_t)WV_LEVEL_BYTES * threadIdx.x);
+        e[0] = L.n;
+        e[1] = 0;
+        e[2] = 0;
+        e[3] = L.bits_off;
+        e[4] = L.rank_off;
+        e[5] = L.sel0_off;
+        e[6] = L.sel1_off;
+        e[7] = L.nsel;
+    }
+    // zero every gap between consecutive arrays
+    for (int s = 0; s < nspan; s++) {
+        const uint64_t lo = span_hi[s], hi = span_lo[s + 1];
+        for (uint64_t b = lo + threadIdx.x; b < hi; b += blockDim.x) img[b] = 0;
+    }
+}
+
+// ---- validation / symbol counts ------------------------------------------------
+
+constexpr uint32_t LDS_HIST_MAX = 8192;
+
+template <typename T>
+__global__ void __launch_bounds__(DIR_THREADS)
+validate_k(const void* __restrict__ S, uint64_t n, uint32_t sigma, uint32_t* __restrict__ status,
+           unsigned long long* __restrict__ counts)
+{
+    __shared__ uint32_t h[LDS_HIST_MAX];
+    const bool lds = counts && sigma <= LDS_HIST_MAX;
+    if (lds) {
+        for (uint32_t b = threadIdx.x; b < sigma; b += blockDim.x) h[b] = 0;
+        __syncthreads();
+    }
+    bool bad = false;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t x = wv_load_sym<T>(S, i);
+        if (x >= sigma) { bad = true; continue; }
+        if (counts) {
+            if (lds) atomicAdd(&h[x], 1u);
+            else atomicAdd(&counts[x], 1ull);
+        }
+    }
+    if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0 && status) atomicOr(status, 1u);
+    if (lds) {
+        __syncthreads();
+        for (uint32_t b = threadIdx.x; b < sigma; b += blockDim.x)
+            if (h[b]) atomicAdd(&counts[b], (unsigned long long)h[b]);
+    }
+}
+
+__global__ void fill_u64_k(uint64_t* p, uint64_t count, uint64_t value)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = value;
+}
+
+inline uint32_t grid_for(uint64_t items, uint32_t threads, uint32_t cap = 65535u)
+{
+    uint64_t g = wv_cdiv(items ? items : 1, threads);
+    return (uint32_t)(g < cap ? g : cap);
+}
+
+}  // namespace
+
+hipError_t wv_fill_u64(uint64_t* p, uint64_t count, uint64_t value, hipStream_t s)
+{
+    if (!count) return hipSuccess;
+    fill_u64_k<<<grid_for(count, 256, 4096), 256, 0, s>>>(p, count, value);
+    return hipGetLastError();
+}
+
+hipError_t wv_count_superblocks(const uint8_t* image, const wv_level& L, uint32_t* sb_ones, hipStream_t s)
+{
+    const uint64_t ns = wv_cdiv(L.n, WV_SB_BITS);
+    if (!ns) return hipSuccess;
+    count_superblocks_k<<<(uint32_t)wv_cdiv(ns, DIR_THREADS), DIR_THREADS, 0, s>>>(
+        (const uint64_t*)(image + L.bits_off), L.n, sb_ones);
+    return hipGetLastError();
+}
+
+hipError_t wv_binary_directory(uint8_t* image, uint32_t level, const wv_level& L,
+                               const wv_dir_scratch& sc, uint64_t* zl_dev, hipStream_t s)
+{
+    const uint64_t ns = wv_cdiv(L.n, WV_SB_BITS);
+    hipError_t e = wv_scan_u32(sc.sb_ones, sc.sb_pre, ns, 1, sc.partial, sc.total, s);
+    if (e != hipSuccess) return e;
+    if (ns) dir_write_k<<<(uint32_t)wv_cdiv(ns, DIR_THREADS), DIR_THREADS, 0, s>>>(image, L, sc.sb_pre);
+    dir_finish_k<<<grid_for(L.nsel, DIR_THREADS, 64), DIR_THREADS, 0, s>>>(image, level, L, sc.total, zl_dev);
+    return hipGetLastError();
+}
+
+hipError_t wv_multiary_counters(uint8_t* image, const wv_level& L, uint32_t D,
+                                const wv_mdir_scratch& sc, hipStream_t s)
+{
+    const uint64_t nr = wv_mranges(L.n, D);
+    const uint32_t d = 1u << D;
+    if (nr) mcount_k<<<(uint32_t)wv_cdiv(nr, DIR_THREADS), DIR_THREADS, 0, s>>>(
+        (const uint64_t*)(image + L.bits_off), L.n, D, sc.rng_cnt);
+    hipError_t e = wv_scan_u32(sc.rng_cnt, sc.rng_pre, nr, d, sc.partial, sc.totals, s);
+    if (e != hipSuccess) return e;
+    if (nr) mwrite_k<<<(uint32_t)wv_cdiv(nr, DIR_THREADS), DIR_THREADS, 0, s>>>(image, L, D, sc.rng_pre);
+    mfinish_k<<<1, 64, 0, s>>>(image, L, D, sc.totals);
+    return hipGetLastError();
+}
+
+hipError_t wv_write_header(uint8_t* image, const wv_layout_in& in, hipStream_t s)
+{
+    header_k<<<1, DIR_THREADS, 0, s>>>(image, in);
+    return hipGetLastError();
+}
+
+hipError_t wv_validate(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma,
+                       uint8_t* image, uint64_t* counts, hipStream_t s)
+{
+    uint32_t* status = image ? (uint32_t*)(image + 36) : nullptr;
+    unsigned long long* c = (unsigned long long*)counts;
+    if (counts) {
+        hipError_t e = wv_fill_u64(counts, sigma, 0, s);
+        if (e != hipSuccess) return e;
+    }
+    if (!n) return hipSuccess;
+    const uint32_t grid = grid_for(n, DIR_THREADS * 16, 2048);
+    if (sym_bytes == 1) validate_k<uint8_t><<<grid, DIR_THREADS, 0, s>>>(S, n, sigma, status, c);
+    else if (sym_bytes == 2) validate_k<uint16_t><<<grid, DIR_THREADS, 0, s>>>(S, n, sigma, status, c);
+    else validate_k<uint32_t><<<grid, DIR_THREADS, 0, s>>>(S, n, sigma, status, c);
+    return hipGetLastError();
+}

@@ -1,0 +1,47 @@
+// wv_internal.h -- declarations shared by the HIP translation units of
+// libwavelet (not part of the C-ABI).
+#pragma once
+
+#include "wv_common.h"
+
+// ---- prefix sum (wv_scan.hip) ----------------------------------------------
+// scratch entries (uint64) the scan of `count` items in `ncols` columns needs
+uint64_t wv_scan_partials(uint64_t count, uint32_t ncols);
+// exclusive prefix of in[i*ncols+c] into out[i*ncols+c]; totals[c] = sum
+hipError_t wv_scan_u32(const uint32_t* in, uint64_t* out, uint64_t count, uint32_t ncols,
+                       uint64_t* partial, uint64_t* totals, hipStream_t s);
+
+// ---- directories (wv_directory.hip) ----------------------------------------
+// Rank directory + sampled select of one binary level whose words are already
+// written and whose per-superblock ones counts are in sb_ones.  Writes the
+// level's zeros/ones into its descriptor and the zero count to *zl_dev.
+struct wv_dir_scratch {
+    uint32_t* sb_ones;   // ceil(n/512) counts (filled by the level writer)
+    uint64_t* sb_pre;    // ceil(n/512)
+    uint64_t* partial;   // wv_scan_partials(ceil(n/512), 1)
+    uint64_t* total;     // 1 entry: ones on the level
+};
+hipError_t wv_binary_directory(uint8_t* image, uint32_t level, const wv_level& L,
+                               const wv_dir_scratch& sc, uint64_t* zl_dev, hipStream_t s);
+// ones per superblock of an already written binary level (when the level
+// writer did not produce them)
+hipError_t wv_count_superblocks(const uint8_t* image, const wv_level& L, uint32_t* sb_ones,
+                                hipStream_t s);
+
+// per-digit counters of one multiary level
+struct wv_mdir_scratch {
+    uint32_t* rng_cnt;   // ranges * d
+    uint64_t* rng_pre;   // ranges * d
+    uint64_t* partial;   // wv_scan_partials(ranges, d)
+    uint64_t* totals;    // d
+};
+hipError_t wv_multiary_counters(uint8_t* image, const wv_level& L, uint32_t D,
+                                const wv_mdir_scratch& sc, hipStream_t s);
+
+// ---- header (wv_directory.hip) ---------------------------------------------
+// header, level descriptors (zeros/ones left 0) and zeroed gaps between arrays
+hipError_t wv_write_header(uint8_t* image, const wv_layout_in& in, hipStream_t s);
+// status word: set when a symbol >= sigma is found
+hipError_t wv_validate(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma,
+                       uint8_t* image, uint64_t* counts /*nullable*/, hipStream_t s);
+hipError_t wv_fill_u64(uint64_t* p, uint64_t count, uint64_t value, hipStream_t s);

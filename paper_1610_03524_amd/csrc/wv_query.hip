@@ -1,0 +1,394 @@
+// wv_query.hip -- batched access / rank / select on built images.
+//
+// The queries are those of the problem statement (Sec. 2): access(i) = S[i],
+// rank_c(i) = occurrences of c in S[0..i], select_c(k) = position of the k-th
+// c.  They walk the levels without topology pointers (Sec. 2 notes the
+// pointers can be dropped by changing the queries):
+//   wavelet matrix: position i on level l maps to rank0(i) (bit 0) or
+//     Z_l + rank1(i) (bit 1) on level l+1;
+//   balanced trees: the node range [s, e) is refined by rank0 at s, i, e;
+//   shaped trees: the node table gives every node's start and children;
+//   multiary trees: per-digit counters replace rank0.
+// select walks down to the symbol's range, then back up with select0/1,
+// which uses the sampled positions plus a binary search over the rank
+// superblocks (Sec. 5.1).  One thread answers one query.
+#include "wv_internal.h"
+
+namespace {
+
+constexpr int Q_THREADS = 256;
+constexpr uint64_t U64MAX = ~0ull;
+
+struct QLevel {
+    uint64_t n, zeros, bits_off, rank_off, sel0_off, sel1_off, nsel;
+};
+
+struct QImg {
+    const uint8_t* img;
+    uint32_t kind, D, nlevels, sigma;
+    uint64_t n, nodes_off, codes_off;
+    QLevel lv[WV_MAX_LEVELS];
+};
+
+__device__ inline void load_image(const uint8_t* img, QImg& q)
+{
+    const uint32_t* h32 = (const uint32_t*)img;
+    const uint64_t* h64 = (const uint64_t*)img;
+    q.img = img;
+    q.kind = h32[2];
+    q.D = h32[3];
+    q.n = h64[2];
+    q.sigma = h32[6];
+    q.nlevels = h32[7] > WV_MAX_LEVELS ? WV_MAX_LEVELS : h32[7];
+    q.nodes_off = h64[7];
+    q.codes_off = h64[9];
+    for (uint32_t l = 0; l < q.nlevels; l++) {
+        const uint64_t* e = (const uint64_t*)(img + WV_HEADER_BYTES + (uint64_t)WV_LEVEL_BYTES * l);
+        q.lv[l] = QLevel{e[0], e[1], e[3], e[4], e[5], e[6], e[7]};
+    }
+}
+
+__device__ inline const uint64_t* words_of(const QImg& q, uint32_t l) { return (const uint64_t*)(q.img + q.lv[l].bits_off); }
+__device__ inline const uint64_t* dir_of(const QImg& q, uint32_t l) { return (const uint64_t*)(q.img + q.lv[l].rank_off); }
+
+__device__ inline uint32_t bit_at(const QImg& q, uint32_t l, uint64_t i)
+{
+    return (uint32_t)((words_of(q, l)[i >> 6] >> (i & 63)) & 1ull);
+}
+
+__device__ inline uint64_t rank0(const QImg& q, uint32_t l, uint64_t i) { return wv_rank0(words_of(q, l), dir_of(q, l), i); }
+__device__ inline uint64_t rankb(const QImg& q, uint32_t l, uint32_t b, uint64_t i)
+{
+    const uint64_t z = rank0(q, l, i);
+    return b ? i - z : z;
+}
+
+// position of the b-bit of 0-based ordinal j on level l (j < count of b-bits)
+__device__ uint64_t selectb(const QImg& q, uint32_t l, uint32_t b, uint64_t j)
+{
+    const QLevel& L = q.lv[l];
+    const uint64_t* sel = (const uint64_t*)(q.img + (b ? L.sel1_off : L.sel0_off));
+    const uint64_t* dir = dir_of(q, l);
+    const uint64_t* words = words_of(q, l);
+    const uint64_t ns = wv_cdiv(L.n, WV_SB_BITS), nw = wv_cdiv(L.n, 64);
+    const uint64_t s = j / WV_SEL_STRIDE;
+    const uint64_t p0 = sel[s], p1 = sel[s + 1];
+    uint64_t lo = p0 >> 9, hi = (p1 >> 9) < ns ? (p1 >> 9) : ns - 1;
+    auto before = [&](uint64_t k) -> uint64_t { return b ? (k * WV_SB_BITS - dir[2 * k]) : dir[2 * k]; };
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi + 1) / 2;
+        if (before(mid) <= j) lo = mid; else hi = mid - 1;
+    }
+    const uint64_t k = lo;
+    const uint64_t r = j - before(k);
+    const uint64_t blk = dir[2 * k + 1];
+    uint32_t qw = 0;
+    uint64_t cq = 0;
+    for (uint32_t t = 1; t < 8; t++) {
+        if (8 * k + t >= nw) break;
+        const uint64_t f = (blk >> (9 * (t - 1))) & 511u;
+        const uint64_t c = b ? (64u * t - f) : f;
+        if (c <= r) { qw = t; cq = c; } else break;
+    }
+    uint64_t w = words[8 * k + qw];
+    if (!b) w = ~w;
+    return k * WV_SB_BITS + 64u * qw + wv_select_in_word(w, (uint32_t)(r - cq));
+}
+
+__device__ inline uint32_t digit_at(const QImg& q, uint32_t l, uint64_t i)
+{
+    const uint32_t P = 64u / q.D;
+    return (uint32_t)((words_of(q, l)[i / P] >> (q.D * (i % P))) & ((1ull << q.D) - 1ull));
+}
+
+__device__ inline uint64_t mrank(const QImg& q, uint32_t l, uint32_t g, uint64_t i)
+{
+    return wv_mrank(words_of(q, l), q.img + q.lv[l].rank_off, q.lv[l].n, q.D, g, i);
+}
+
+struct QNode {
+    uint64_t start, count;
+    uint32_t child[2], level;
+};
+
+__device__ inline QNode node_at(const QImg& q, uint32_t k)
+{
+    const uint8_t* e = q.img + q.nodes_off + (uint64_t)k * WV_NODE_BYTES;
+    QNode nd;
+    nd.start = ((const uint64_t*)e)[0];
+    nd.count = ((const uint64_t*)e)[1];
+    nd.child[0] = ((const uint32_t*)e)[4];
+    nd.child[1] = ((const uint32_t*)e)[5];
+    nd.level = ((const uint32_t*)e)[6];
+    return nd;
+}
+
+// ---- access ------------------------------------------------------------------
+
+__device__ uint32_t q_access(const QImg& q, uint64_t i)
+{
+    if (i >= q.n) return 0xFFFFFFFFu;
+    uint32_t x = 0;
+    if (q.kind == WT_KIND_WM) {
+        for (uint32_t l = 0; l < q.nlevels; l++) {
+            const uint32_t b = bit_at(q, l, i);
+            const uint64_t z = rank0(q, l, i);
+            i = b ? q.lv[l].zeros + (i - z) : z;
+            x = (x << 1) | b;
+        }
+        return x;
+    }
+    if (q.kind == WT_KIND_WT) {
+        uint64_t s = 0, e = q.n;
+        for (uint32_t l = 0; l < q.nlevels; l++) {
+            const uint32_t b = bit_at(q, l, i);
+            const uint64_t zs = rank0(q, l, s), zi = rank0(q, l, i), ze = rank0(q, l, e);
+            if (!b) {
+                i = s + (zi - zs);
+                e = s + (ze - zs);
+            } else {
+                i = s + (ze - zs) + (i - s) - (zi - zs);
+                s = s + (ze - zs);
+            }
+            x = (x << 1) | b;
+        }
+        return x;
+    }
+    if (q.kind == WT_KIND_MULTIARY) {
+        uint64_t s = 0, e = q.n;
+        const uint32_t d = 1u << q.D;
+        for (uint32_t l = 0; l < q.nlevels; l++) {
+            const uint32_t g = digit_at(q, l, i);
+            uint64_t below = 0;
+            for (uint32_t c = 0; c < g; c++) below += mrank(q, l, c, e) - mrank(q, l, c, s);
+            const uint64_t gs = mrank(q, l, g, s);
+            const uint64_t cs = s + below;
+            const uint64_t ni = cs + mrank(q, l, g, i) - gs;
+            e = cs + mrank(q, l, g, e) - gs;
+            s = cs;
+            i = ni;
+            x = (x << q.D) | g;
+            (void)d;
+        }
+        return x;
+    }
+    // shaped: follow the node table
+    uint32_t k = 0;
+    uint64_t rel = i;
+    for (uint32_t step = 0; step <= WV_MAX_LEVELS; step++) {
+        const QNode nd = node_at(q, k);
+        const uint64_t pos = nd.start + rel;
+        const uint32_t b = bit_at(q, nd.level, pos);
+        rel = rankb(q, nd.level, b, pos) - rankb(q, nd.level, b, nd.start);
+        const uint32_t c = nd.child[b];
+        if (c & WV_LEAF) return c == WV_NONE ? 0xFFFFFFFFu : (c & ~WV_LEAF);
+        k = c;
+    }
+    return 0xFFFFFFFFu;
+}
+
+// ---- rank / select ---------------------------------------------------------------
+
+__device__ inline bool shaped_code(const QImg& q, uint32_t c, uint64_t& code, uint32_t& len)
+{
+    if (c >= q.sigma) return false;
+    const uint8_t* e = q.img + q.codes_off + (uint64_t)c * WV_CODE_BYTES;
+    code = ((const uint64_t*)e)[0];
+    len = ((const uint32_t*)e)[2];
+    return len != 0;
+}
+
+// occurrences of c among the first p symbols (positions 0..p-1)
+__device__ uint64_t q_count_prefix(const QImg& q, uint32_t c, uint64_t p)
+{
+    const uint32_t L = q.nlevels;
+    if (q.kind == WT_KIND_WM) {
+        uint64_t s = 0, e = p;
+        for (uint32_t l = 0; l < L; l++) {
+            const uint32_t b = (c >> (L - 1 - l)) & 1u;
+            const uint64_t zs = rank0(q, l, s), ze = rank0(q, l, e);
+            if (b) { s = q.lv[l].zeros + s - zs; e = q.lv[l].zeros + e - ze; }
+            else { s = zs; e = ze; }
+        }
+        return e - s;
+    }
+    if (q.kind == WT_KIND_WT) {
+        uint64_t s = 0, e = q.n;
+        for (uint32_t l = 0; l < L; l++) {
+            const uint32_t b = (c >> (L - 1 - l)) & 1u;
+            const uint64_t zs = rank0(q, l, s), zp = rank0(q, l, p), ze = rank0(q, l, e);
+            if (!b) {
+                p = s + (zp - zs);
+                e = s + (ze - zs);
+            } else {
+                p = s + (ze - zs) + (p - s) - (zp - zs);
+                s = s + (ze - zs);
+            }
+        }
+        return p - s;
+    }
+    if (q.kind == WT_KIND_MULTIARY) {
+        uint64_t s = 0, e = q.n;
+        for (uint32_t l = 0; l < L; l++) {
+            const uint32_t g = (c >> (q.D * (L - 1 - l))) & ((1u << q.D) - 1u);
+            uint64_t below = 0;
+            for (uint32_t cc = 0; cc < g; cc++) below += mrank(q, l, cc, e) - mrank(q, l, cc, s);
+            const uint64_t gs = mrank(q, l, g, s);
+            const uint64_t cs = s + below;
+            p = cs + mrank(q, l, g, p) - gs;
+            e = cs + mrank(q, l, g, e) - gs;
+            s = cs;
+        }
+        return p - s;
+    }
+    uint64_t code;
+    uint32_t len;
+    if (!shaped_code(q, c, code, len)) return 0;
+    uint32_t k = 0;
+    uint64_t rel = p;
+    for (uint32_t t = 0; t < len; t++) {
+        const QNode nd = node_at(q, k);
+        const uint32_t b = (uint32_t)((code >> (len - 1 - t)) & 1ull);
+        const uint64_t pos = nd.start + rel;
+        rel = rankb(q, nd.level, b, pos) - rankb(q, nd.level, b, nd.start);
+        k = nd.child[b];
+    }
+    return rel;
+}
+
+__device__ uint64_t q_rank(const QImg& q, uint32_t c, uint64_t i)
+{
+    if (i >= q.n) return U64MAX;
+    if (c >= q.sigma) return 0;
+    return q_count_prefix(q, c, i + 1);
+}
+
+__device__ uint64_t q_select(const QImg& q, uint32_t c, uint64_t k)
+{
+    if (k == 0 || c >= q.sigma || q.n == 0) return U64MAX;
+    const uint64_t total = q_count_prefix(q, c, q.n);
+    if (k > total) return U64MAX;
+    const uint32_t L = q.nlevels;
+    if (q.kind == WT_KIND_WM) {
+        uint64_t s = 0;
+        for (uint32_t l = 0; l < L; l++) {
+            const uint32_t b = (c >> (L - 1 - l)) & 1u;
+            const uint64_t zs = rank0(q, l, s);
+            s = b ? q.lv[l].zeros + s - zs : zs;
+        }
+        uint64_t p = s + k - 1;
+        for (uint32_t l = L; l-- > 0;) {
+            const uint32_t b = (c >> (L - 1 - l)) & 1u;
+            p = selectb(q, l, b, b ? p - q.lv[l].zeros : p);
+        }
+        return p;
+    }
+    if (q.kind == WT_KIND_WT) {
+        uint64_t starts[WV_MAX_LEVELS];
+        uint64_t s = 0, e = q.n;
+        for (uint32_t l = 0; l < L; l++) {
+            starts[l] = s;
+            const uint32_t b = (c >> (L - 1 - l)) & 1u;
+            const uint64_t zs = rank0(q, l, s), ze = rank0(q, l, e);
+            if (!b) e = s + (ze - zs); else s = s + (ze - zs);
+        }
+        uint64_t p = s + k - 1, child = s;
+        for (uint32_t l = L; l-- > 0;) {
+            const uint32_t b = (c >> (L - 1 - l)) & 1u;
+            const uint64_t st = starts[l];
+            p = selectb(q, l, b, rankb(q, l, b, st) + (p - child));
+            child = st;
+        }
+        return p;
+    }
+    if (q.kind == WT_KIND_SHAPED) {
+        uint64_t code;
+        uint32_t len;
+        shaped_code(q, c, code, len);
+        uint32_t path[WV_MAX_LEVELS];
+        uint32_t kk = 0;
+        for (uint32_t t = 0; t < len; t++) {
+            path[t] = kk;
+            kk = node_at(q, kk).child[(code >> (len - 1 - t)) & 1ull];
+        }
+        uint64_t rel = k - 1;
+        for (uint32_t t = len; t-- > 0;) {
+            const QNode nd = node_at(q, path[t]);
+            const uint32_t b = (uint32_t)((code >> (len - 1 - t)) & 1ull);
+            rel = selectb(q, nd.level, b, rankb(q, nd.level, b, nd.start) + rel) - nd.start;
+        }
+        return rel;
+    }
+    // multiary: smallest p with count(c in [0, p]) >= k
+    uint64_t lo = 0, hi = q.n - 1;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) / 2;
+        if (q_count_prefix(q, c, mid + 1) >= k) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(Q_THREADS)
+access_k(const uint8_t* __restrict__ img, const uint64_t* __restrict__ pos, uint32_t* __restrict__ res, uint64_t m)
+{
+    __shared__ QImg q;
+    if (threadIdx.x == 0) load_image(img, q);
+    __syncthreads();
+    const uint64_t t = (uint64_t)blockIdx.x * Q_THREADS + threadIdx.x;
+    if (t < m) res[t] = q_access(q, pos[t]);
+}
+
+__global__ void __launch_bounds__(Q_THREADS)
+rank_k(const uint8_t* __restrict__ img, const uint32_t* __restrict__ c, const uint64_t* __restrict__ i,
+       uint64_t* __restrict__ res, uint64_t m)
+{
+    __shared__ QImg q;
+    if (threadIdx.x == 0) load_image(img, q);
+    __syncthreads();
+    const uint64_t t = (uint64_t)blockIdx.x * Q_THREADS + threadIdx.x;
+    if (t < m) res[t] = q_rank(q, c[t], i[t]);
+}
+
+__global__ void __launch_bounds__(Q_THREADS)
+select_k(const uint8_t* __restrict__ img, const uint32_t* __restrict__ c, const uint64_t* __restrict__ k,
+         uint64_t* __restrict__ res, uint64_t m)
+{
+    __shared__ QImg q;
+    if (threadIdx.x == 0) load_image(img, q);
+    __syncthreads();
+    const uint64_t t = (uint64_t)blockIdx.x * Q_THREADS + threadIdx.x;
+    if (t < m) res[t] = q_select(q, c[t], k[t]);
+}
+
+}  // namespace
+
+extern "C" {
+
+int wt_access(const void* image, const uint64_t* pos, uint32_t* res, uint64_t m, void* stream)
+{
+    if (!image || (m && (!pos || !res))) return WT_EINVAL;
+    if (!m) return WT_OK;
+    access_k<<<(uint32_t)wv_cdiv(m, Q_THREADS), Q_THREADS, 0, (hipStream_t)stream>>>(
+        (const uint8_t*)image, pos, res, m);
+    return hipGetLastError() == hipSuccess ? WT_OK : WT_EHIP;
+}
+
+int wt_rank(const void* image, const uint32_t* c, const uint64_t* i, uint64_t* res, uint64_t m, void* stream)
+{
+    if (!image || (m && (!c || !i || !res))) return WT_EINVAL;
+    if (!m) return WT_OK;
+    rank_k<<<(uint32_t)wv_cdiv(m, Q_THREADS), Q_THREADS, 0, (hipStream_t)stream>>>(
+        (const uint8_t*)image, c, i, res, m);
+    return hipGetLastError() == hipSuccess ? WT_OK : WT_EHIP;
+}
+
+int wt_select(const void* image, const uint32_t* c, const uint64_t* k, uint64_t* res, uint64_t m, void* stream)
+{
+    if (!image || (m && (!c || !k || !res))) return WT_EINVAL;
+    if (!m) return WT_OK;
+    select_k<<<(uint32_t)wv_cdiv(m, Q_THREADS), Q_THREADS, 0, (hipStream_t)stream>>>(
+        (const uint8_t*)image, c, k, res, m);
+    return hipGetLastError() == hipSuccess ? WT_OK : WT_EHIP;
+}
+
+}  // extern "C"

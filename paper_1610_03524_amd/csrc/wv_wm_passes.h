@@ -1,0 +1,17 @@
+// wv_wm_passes.h -- multi-level partition passes for the wavelet matrix.
+#pragma once
+
+#include "wv_internal.h"
+
+struct wv_wm_plan {
+    bool enabled;          // false: the one-level-per-pass builder is used
+    uint32_t tau;          // key bits handled per pass
+    uint64_t ws_bytes;     // workspace the passes need
+};
+
+// Decide whether (and how) the multi-level passes build this matrix.
+int wv_wm_make_plan(uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt_tuning* tune, wv_wm_plan& p);
+
+// Build every level, directory and select sample of the matrix into `image`.
+hipError_t wv_wm_run(const wv_wm_plan& p, const void* S, uint8_t* image, const wv_layout_out& lay,
+                     uint8_t* ws, const wv_dir_scratch& dir, hipStream_t s);

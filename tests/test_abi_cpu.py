@@ -1,0 +1,89 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry
+point the header declares, and its host-only calls (planning, Huffman
+codewords) agree with the oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1610_03524_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "wavelet.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.lib()
+    names = header_functions()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(B.exported_symbols())
+
+
+@pytest.mark.parametrize("kind,sigma,D", [(B.KIND_WT, 256, 0), (B.KIND_WM, 65536, 0), (B.KIND_MULTIARY, 4096, 2),
+                                          (B.KIND_MULTIARY, 5, 3), (B.KIND_MULTIARY, 70000, 4), (B.KIND_WM, 1, 0),
+                                          (B.KIND_WT, 3, 0), (B.KIND_WM, 2 ** 20, 0)])
+@pytest.mark.parametrize("n", [0, 1, 64, 513, 4097, 100000])
+def test_plan_matches_oracle_layout(kind, sigma, D, n):
+    dt = np.uint8 if sigma <= 256 else (np.uint16 if sigma <= 65536 else np.uint32)
+    S = np.zeros(n, dtype=dt)
+    info = B.plan(kind, n, sigma, S.itemsize, B.make_shape(D) if D else None)
+    img = oracle.build_image(kind, S, sigma, max(D, 1))
+    assert info.out_bytes == img.size
+    L = max(1, (sigma - 1).bit_length())
+    assert info.nlevels == (L if kind != B.KIND_MULTIARY else -(-L // D))
+    assert info.workspace_bytes > 0
+
+
+def test_plan_shaped_matches_oracle():
+    rng = np.random.default_rng(3)
+    S = np.minimum(rng.geometric(0.05, 5000) - 1, 299).astype(np.uint16)
+    counts = oracle.symbol_counts(S, 300)
+    codes, lens = oracle.huffman(counts)
+    info = B.plan(B.KIND_SHAPED, S.size, 300, 2, B.make_shape(0, codes, lens, counts))
+    img = oracle.build_image(oracle.KIND_SHAPED, S, 300, codes=codes, lens=lens)
+    assert info.out_bytes == img.size and info.nlevels == int(lens.max())
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_huffman_codes_equal_oracle(seed):
+    rng = np.random.default_rng(seed)
+    sigma = int(rng.integers(1, 5000))
+    if seed % 4 == 0:
+        counts = rng.integers(0, 3, sigma)
+    elif seed % 4 == 1:
+        counts = rng.geometric(0.01, sigma)
+    else:
+        counts = rng.integers(0, 10 ** int(rng.integers(1, 9)), sigma)
+    codes, lens = B.huffman_codes(counts)
+    ocodes, olens = oracle.huffman(counts)
+    assert np.array_equal(lens, olens) and np.array_equal(codes, ocodes)
+
+
+def test_plan_errors():
+    with pytest.raises(B.WaveletError) as e:
+        B.plan(B.KIND_WM, 10, 0, 1)
+    assert e.value.code == B.WT_EINVAL
+    with pytest.raises(B.WaveletError) as e:
+        B.plan(B.KIND_WM, 10, 5, 3)
+    assert e.value.code == B.WT_EINVAL
+    with pytest.raises(B.WaveletError) as e:
+        B.plan(B.KIND_MULTIARY, 10, 5, 1, B.make_shape(5))
+    assert e.value.code == B.WT_EINVAL
+    with pytest.raises(B.WaveletError) as e:
+        B.plan(B.KIND_WM, 1 << 32, 5, 1)
+    assert e.value.code == B.WT_EUNSUP
+    # a symbol that occurs but has no codeword
+    with pytest.raises(B.WaveletError) as e:
+        B.plan(B.KIND_SHAPED, 3, 3, 1, B.make_shape(0, np.array([0, 1, 0]), np.array([1, 1, 0]),
+                                                      np.array([1, 1, 1])))
+    assert e.value.code == B.WT_ERANGE
+    assert "out of range" in B.strerror(B.WT_ERANGE)

@@ -1,0 +1,107 @@
+"""GPU parity: every image the HIP library builds equals the oracle's image
+byte for byte (integer work, tolerance 0), over sizes that span many tiles
+and ragged tails, edge alphabets and degenerate sequences."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import assert_same, gpu_image, oracle_image, to_device
+from paper_1610_03524_amd import binding as B
+
+pytestmark = pytest.mark.gpu
+
+EDGE_N = [0, 1, 63, 64, 65, 511, 512, 513, 4095, 4096, 4097, 70001]
+SIGMAS = [1, 2, 3, 4, 5, 8, 255, 256, 257, 4096, 65536, 65537, 1 << 20]
+
+
+def dtype_for(sigma):
+    return np.uint8 if sigma <= 256 else (np.uint16 if sigma <= 65536 else np.uint32)
+
+
+def patterns(n, sigma, rng):
+    dt = dtype_for(sigma)
+    yield "uniform", rng.integers(0, sigma, n).astype(dt)
+    if n > 1:
+        yield "equal", np.full(n, sigma - 1, dtype=dt)
+        yield "sorted", np.sort(rng.integers(0, sigma, n)).astype(dt)
+        yield "reverse", np.sort(rng.integers(0, sigma, n))[::-1].astype(dt).copy()
+        yield "alternating", (np.arange(n) % min(sigma, 2) * (sigma - 1)).astype(dt)
+        rare = np.zeros(n, dtype=dt)
+        rare[n // 2] = sigma - 1
+        yield "one_rare", rare
+
+
+def shaped_inputs(S, sigma):
+    """codewords for the GPU build from the library (device counts + host
+    Huffman), and for the oracle from the oracle's own counts and Huffman."""
+    counts = B.symbol_counts(to_device(S), sigma).cpu().numpy().astype(np.uint64)
+    gcodes, glens = B.huffman_codes(counts)
+    ocodes, olens = oracle.huffman(oracle.symbol_counts(S, sigma))
+    return (gcodes, glens), (ocodes, olens)
+
+
+@pytest.mark.parametrize("kind", [B.KIND_WM, B.KIND_WT])
+@pytest.mark.parametrize("sigma", SIGMAS)
+def test_binary_parity(kind, sigma):
+    rng = np.random.default_rng(sigma * 7 + kind)
+    for n in EDGE_N:
+        for name, S in patterns(n, sigma, rng):
+            g = gpu_image(kind, S, sigma)
+            o = oracle_image(kind, S, sigma)
+            assert_same(g, o, f"kind={kind} sigma={sigma} n={n} {name}")
+
+
+@pytest.mark.parametrize("D", [1, 2, 3, 4])
+@pytest.mark.parametrize("sigma", [2, 5, 16, 17, 256, 4096, 65536])
+def test_multiary_parity(D, sigma):
+    rng = np.random.default_rng(1000 + D * sigma)
+    for n in [0, 1, 31, 32, 33, 2047, 2048, 2049, 70001]:
+        for name, S in patterns(n, sigma, rng):
+            g = gpu_image(B.KIND_MULTIARY, S, sigma, D)
+            o = oracle_image(B.KIND_MULTIARY, S, sigma, D)
+            assert_same(g, o, f"D={D} sigma={sigma} n={n} {name}")
+
+
+@pytest.mark.parametrize("sigma", [2, 3, 100, 4096])
+def test_shaped_parity(sigma):
+    rng = np.random.default_rng(77 + sigma)
+    for n in [1, 2, 64, 513, 4097, 70001]:
+        for p in (0.5, 0.05, 0.005):
+            S = np.minimum(rng.geometric(p, n) - 1, sigma - 1).astype(dtype_for(sigma))
+            (gc, gl), (oc, ol) = shaped_inputs(S, sigma)
+            g = gpu_image(B.KIND_SHAPED, S, sigma, codes=gc, lens=gl)
+            o = oracle_image(B.KIND_SHAPED, S, sigma, codes=oc, lens=ol)
+            assert_same(g, o, f"shaped sigma={sigma} n={n} p={p}")
+
+
+@pytest.mark.parametrize("kind", [B.KIND_WM, B.KIND_WT])
+def test_levelwise_equals_default(kind):
+    rng = np.random.default_rng(5)
+    S = rng.integers(0, 1000, 200003).astype(np.uint16)
+    a = gpu_image(kind, S, 1000)
+    b = gpu_image(kind, S, 1000, tune=B.make_tuning(flags=B.FLAG_LEVELWISE))
+    assert_same(a, b, "levelwise vs default")
+
+
+def test_symbol_out_of_range_sets_status():
+    import torch
+    S = to_device(np.array([0, 1, 7, 2], dtype=np.uint8))
+    for kind in (B.KIND_WM,):
+        img, _ = B.build(kind, S, 5)
+        assert B.check(img) == B.WT_ERANGE
+    with pytest.raises(B.WaveletError) as e:
+        B.build(B.KIND_WT, S, 5)
+    assert e.value.code == B.WT_ERANGE
+    torch.cuda.synchronize()
+
+
+def test_buffer_too_small():
+    import torch
+    S = to_device(np.arange(100, dtype=np.uint8))
+    info = B.plan(B.KIND_WM, 100, 100, 1)
+    out = torch.empty(info.out_bytes - 1, dtype=torch.uint8, device="cuda")
+    ws = torch.empty(info.workspace_bytes, dtype=torch.uint8, device="cuda")
+    assert B.build_into(B.KIND_WM, S, 100, out, ws) == B.WT_ENOSPC
+    out = torch.empty(info.out_bytes, dtype=torch.uint8, device="cuda")
+    ws = torch.empty(info.workspace_bytes - 1, dtype=torch.uint8, device="cuda")
+    assert B.build_into(B.KIND_WM, S, 100, out, ws) == B.WT_ENOSPC

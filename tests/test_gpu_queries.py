@@ -1,0 +1,80 @@
+"""GPU batched queries (access / rank / select) against brute force on S."""
+import numpy as np
+import pytest
+
+from gpu_util import to_device
+from paper_1610_03524_amd import binding as B
+from test_gpu_parity import dtype_for, shaped_inputs
+
+pytestmark = pytest.mark.gpu
+
+U32MAX = 0xFFFFFFFF
+U64MAX = 0xFFFFFFFFFFFFFFFF
+
+
+def brute(S, sigma, pos, c, i, k):
+    n = S.size
+    vals = S[np.minimum(pos, max(n - 1, 0))].astype(np.uint64) if n else np.zeros(len(pos), np.uint64)
+    acc = np.where(pos < n, vals, np.uint64(U32MAX))
+    where = {}
+    rk = np.zeros(len(c), dtype=np.uint64)
+    sl = np.zeros(len(c), dtype=np.uint64)
+    for q in range(len(c)):
+        cc = int(c[q])
+        if cc not in where:
+            where[cc] = np.flatnonzero(S == cc)
+        p = where[cc]
+        rk[q] = U64MAX if i[q] >= n else (0 if cc >= sigma else np.searchsorted(p, i[q], side="right"))
+        kk = int(k[q])
+        sl[q] = p[kk - 1] if (cc < sigma and 1 <= kk <= p.size) else U64MAX
+    return acc, rk, sl
+
+
+def run_queries(img, S, sigma, rng, m=3000):
+    import torch
+    n = S.size
+    pos = rng.integers(0, n + 3, m).astype(np.uint64)
+    c = np.where(rng.random(m) < 0.9, S[rng.integers(0, max(n, 1), m)] if n else 0,
+                 rng.integers(0, sigma + 3, m)).astype(np.uint32)
+    i = rng.integers(0, n + 3, m).astype(np.uint64)
+    cnt = np.bincount(S.astype(np.int64), minlength=sigma + 3)
+    k = np.array([rng.integers(0, cnt[cc] + 3) for cc in c], dtype=np.uint64)
+    tp = torch.from_numpy(pos.view(np.int64)).cuda()
+    tc = torch.from_numpy(c.view(np.int32)).cuda()
+    ti = torch.from_numpy(i.view(np.int64)).cuda()
+    tk = torch.from_numpy(k.view(np.int64)).cuda()
+    ga = B.access(img, tp).cpu().numpy().view(np.uint32).astype(np.uint64)
+    gr = B.rank(img, tc, ti).cpu().numpy().view(np.uint64)
+    gs = B.select(img, tc, tk).cpu().numpy().view(np.uint64)
+    ba, br, bs = brute(S, sigma, pos, c, i, k)
+    assert np.array_equal(ga, ba), "access"
+    assert np.array_equal(gr, br), "rank"
+    assert np.array_equal(gs, bs), "select"
+
+
+@pytest.mark.parametrize("kind,D", [(B.KIND_WM, 0), (B.KIND_WT, 0), (B.KIND_MULTIARY, 2), (B.KIND_MULTIARY, 3),
+                                    (B.KIND_SHAPED, 0)])
+@pytest.mark.parametrize("sigma", [1, 2, 7, 256, 4096, 65536])
+def test_queries_match_brute_force(kind, D, sigma):
+    rng = np.random.default_rng(sigma + 10 * kind + D)
+    for n in [1, 100, 5000, 300001]:
+        if kind == B.KIND_SHAPED:
+            S = np.minimum(rng.geometric(0.02, n) - 1, sigma - 1).astype(dtype_for(sigma))
+            (gc, gl), _ = shaped_inputs(S, sigma)
+            counts = B.symbol_counts(to_device(S), sigma).cpu().numpy()
+            img, _ = B.build(kind, to_device(S), sigma, codes=gc, code_len=gl, counts=counts)
+        else:
+            S = rng.integers(0, sigma, n).astype(dtype_for(sigma))
+            img, _ = B.build(kind, to_device(S), sigma, arity_log2=D)
+        run_queries(img, S, sigma, rng)
+
+
+def test_select_sparse_and_dense_levels():
+    # long zero runs force the select binary search across many superblocks
+    rng = np.random.default_rng(9)
+    n = 1 << 20
+    S = np.zeros(n, dtype=np.uint8)
+    S[rng.choice(n, 37, replace=False)] = 1
+    for kind in (B.KIND_WM, B.KIND_WT):
+        img, _ = B.build(kind, to_device(S), 2)
+        run_queries(img, S, 2, rng)
