@@ -1,0 +1,140 @@
+#!/usr/bin/env python3
+"""Benchmark: wavelet-matrix construction on one MI355X.
+
+Default workload: n = 2^28 uint32 symbols, sigma = 2^16, Zipf(s=1.1) over a
+seed-permuted alphabet (16 levels, rank directory and sampled select on every
+level).  One step = one complete wm_build (every level bitvector, every rank
+directory, every select sample, the image header) from the input already in
+HBM.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3h|c3m|c4]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "build GB/s of input (symbol-levels/sec) and % HBM roofline; batched vs plain"
+
+
+def algorithmic_bytes(info, n, sym_bytes):
+    """compulsory bytes of one build: read S once, write every output array
+    once (level bits, rank directory, select samples, header)"""
+    return n * sym_bytes + info.out_bytes
+
+
+def symbol_levels(info):
+    return sum(int(info.level_n[l]) for l in range(info.nlevels))
+
+
+def time_builds(build_once, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        build_once()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(steps):
+        build_once()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps   # ms per step
+
+
+def cpu_baseline_wm(S_dev, sigma, target_s=15.0):
+    """the oracle (single-threaded C, -O2) on a prefix of the same input"""
+    import oracle
+    n_total = S_dev.numel()
+    n_s = min(n_total, 1 << 22)
+    S = S_dev[:n_s].cpu().numpy().view(np.uint32)
+    t = time.perf_counter()
+    oracle.build_image(oracle.KIND_WM, S, sigma)
+    dt = time.perf_counter() - t
+    # grow the sample towards ~target_s seconds of oracle work
+    if dt < target_s / 4 and n_s < n_total:
+        n_s = int(min(n_total, n_s * max(1.0, target_s / max(dt, 1e-3))))
+        n_s = max(1 << 22, n_s & ~0xFFFF)
+        S = S_dev[:n_s].cpu().numpy().view(np.uint32)
+        t = time.perf_counter()
+        oracle.build_image(oracle.KIND_WM, S, sigma)
+        dt = time.perf_counter() - t
+    return {"value": round(n_s * 4 / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n_s} symbols of the same input, full wavelet matrix with directories, "
+                      f"{dt:.1f} s single-threaded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU form of this "
+              "build is a design, not an implementation", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1610_03524_amd import binding as B
+    from paper_1610_03524_amd import inputs
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    sigma = 1 << 16
+    n = 1 << 28
+    S = inputs.c2_zipf(n=n, sigma=sigma, seed=2, device=dev)
+    torch.cuda.synchronize()
+    info = B.plan(B.KIND_WM, n, sigma, 4)
+    out = torch.empty(info.out_bytes, dtype=torch.uint8, device=dev)
+    ws = torch.empty(info.workspace_bytes, dtype=torch.uint8, device=dev)
+
+    def build_once():
+        rc = B.build_into(B.KIND_WM, S, sigma, out, ws, stream=stream)
+        if rc != 0:
+            raise RuntimeError(f"wm_build failed: {B.strerror(rc)}")
+
+    ms = time_builds(build_once, args.steps, args.warmup, stream)
+    assert B.check(out, stream) == B.WT_OK
+    t = ms / 1e3
+    balg = algorithmic_bytes(info, n, 4)
+    achieved = balg / t / 1e9
+    line = {
+        "metric": METRIC,
+        "value": round(n * 4 / t / 1e9, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "C2 wavelet matrix: n=2^28 uint32, sigma=2^16, Zipf(s=1.1) over a permuted "
+                               "alphabet, 16 levels + rank directory + select samples",
+                   "n": n, "sigma": sigma, "levels": info.nlevels, "tau": info.tau},
+        "symbol_levels_per_s": round(symbol_levels(info) / t, 1),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "kernel": "whole build", "alg_bytes": balg},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_wm(S, sigma)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

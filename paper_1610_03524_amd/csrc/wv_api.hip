@@ -346,7 +346,7 @@ int build_any(int kind, const void* S, uint64_t n, uint32_t sigma, uint32_t sym_
     WV_CHECK(wv_write_header(img, p.lin, s));
 
     if (kind == WT_KIND_WM && !p.levelwise) {
-        WV_CHECK(wv_validate(S, n, sym_bytes, sigma, img, nullptr, s));
+        // the first pass validates S while counting its digits
         wv_dir_scratch dir{at<uint32_t>(ws, p.ws_sb_ones), at<uint64_t>(ws, p.ws_sb_pre),
                            at<uint64_t>(ws, p.ws_partial), at<uint64_t>(ws, p.ws_scalars + 8)};
         WV_CHECK(wv_wm_run(p.wm, S, img, p.lay, at<uint8_t>(ws, p.ws_wm), dir, s));

@@ -9,6 +9,8 @@
 // superblock holding the one (zero) of ordinal 4096k finds it inside its
 // word and writes its position.  Multiary levels (Sec. 5.2, "Rank"): the same
 // with one counter per digit value.
+#include <algorithm>
+
 #include "wv_internal.h"
 
 namespace {
@@ -355,5 +357,169 @@ hipError_t wv_validate(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t s
     if (sym_bytes == 1) validate_k<uint8_t><<<grid, DIR_THREADS, 0, s>>>(S, n, sigma, status, c);
     else if (sym_bytes == 2) validate_k<uint16_t><<<grid, DIR_THREADS, 0, s>>>(S, n, sigma, status, c);
     else validate_k<uint32_t><<<grid, DIR_THREADS, 0, s>>>(S, n, sigma, status, c);
+    return hipGetLastError();
+}
+
+// ---- directories of several levels in one launch per step ----------------------
+
+namespace {
+
+constexpr uint32_t SD_T = 256;                 // threads, two words each
+constexpr uint32_t SD_W = 2 * SD_T;            // words per chunk (64 superblocks)
+
+struct SpanLevels {
+    uint64_t bits_off[WV_MAX_LEVELS], rank_off[WV_MAX_LEVELS], sel0_off[WV_MAX_LEVELS], sel1_off[WV_MAX_LEVELS];
+    uint64_t n, nsel;
+    uint32_t l0, nl;
+};
+
+__global__ void __launch_bounds__(SD_T)
+span_count_k(const uint8_t* __restrict__ image, SpanLevels a, uint32_t* __restrict__ cnt)
+{
+    __shared__ uint32_t part[SD_T / 64];
+    const uint32_t c = blockIdx.x, l = blockIdx.y;
+    const uint64_t nw = wv_cdiv(a.n, 64);
+    const uint64_t* words = (const uint64_t*)(image + a.bits_off[l]);
+    const uint64_t w0 = (uint64_t)c * SD_W + 2 * threadIdx.x;
+    uint32_t o = 0;
+    if (w0 < nw) o += __popcll(words[w0]);
+    if (w0 + 1 < nw) o += __popcll(words[w0 + 1]);
+    for (int d = 32; d >= 1; d >>= 1) o += __shfl_xor(o, d, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = o;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t s = 0;
+        for (uint32_t k = 0; k < SD_T / 64; k++) s += part[k];
+        cnt[(uint64_t)c * a.nl + l] = s;
+    }
+}
+
+__global__ void __launch_bounds__(SD_T)
+span_write_k(uint8_t* __restrict__ image, SpanLevels a, const uint64_t* __restrict__ pre)
+{
+    __shared__ uint32_t wpart[SD_T / 64];
+    __shared__ uint64_t zex[SD_W];   // zeros in [0, min(64w, n)) per word of the chunk
+    const uint32_t c = blockIdx.x, l = blockIdx.y;
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t n = a.n, nw = wv_cdiv(n, 64), ns = wv_cdiv(n, WV_SB_BITS);
+    const uint64_t* words = (const uint64_t*)(image + a.bits_off[l]);
+    uint64_t* dir = (uint64_t*)(image + a.rank_off[l]);
+    uint64_t* sel0 = (uint64_t*)(image + a.sel0_off[l]);
+    uint64_t* sel1 = (uint64_t*)(image + a.sel1_off[l]);
+    const uint64_t cw = (uint64_t)c * SD_W;
+    const uint64_t w0 = cw + 2 * threadIdx.x;
+    const uint64_t x0 = w0 < nw ? words[w0] : 0ull, x1 = w0 + 1 < nw ? words[w0 + 1] : 0ull;
+    const uint32_t o0 = __popcll(x0), o1 = __popcll(x1);
+    // exclusive prefix of ones over the words of the chunk
+    uint32_t inc = o0 + o1;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = __shfl_up(inc, d, 64);
+        if (lane >= (uint32_t)d) inc += t;
+    }
+    if (lane == 63) wpart[wave] = inc;
+    __syncthreads();
+    uint32_t off = 0;
+    for (uint32_t k = 0; k < wave; k++) off += wpart[k];
+    const uint64_t ob0 = pre[(uint64_t)c * a.nl + l] + off + inc - (o0 + o1);   // ones before word w0
+    const uint64_t ob1 = ob0 + o0;
+    const uint64_t z0 = min(64 * w0, n) - ob0, z1 = min(64 * (w0 + 1), n) - ob1;
+    zex[2 * threadIdx.x] = z0;
+    zex[2 * threadIdx.x + 1] = z1;
+    // sampled select: the one / zero of ordinal 4096k inside one of my words
+    const uint64_t xs[2] = {x0, x1};
+    const uint32_t os[2] = {o0, o1};
+    const uint64_t obs[2] = {ob0, ob1}, zbs[2] = {z0, z1};
+    for (int q = 0; q < 2; q++) {
+        const uint64_t w = w0 + q;
+        if (w >= nw) break;
+        const uint64_t t1 = wv_cdiv(obs[q], WV_SEL_STRIDE) * WV_SEL_STRIDE;
+        if (t1 < obs[q] + os[q])
+            sel1[t1 / WV_SEL_STRIDE] = 64 * w + wv_select_in_word(xs[q], (uint32_t)(t1 - obs[q]));
+        const uint64_t valid = min((uint64_t)64, n - 64 * w);
+        const uint64_t vm = valid >= 64 ? ~0ull : ((1ull << valid) - 1ull);
+        const uint32_t zc = (uint32_t)valid - os[q];
+        const uint64_t t0 = wv_cdiv(zbs[q], WV_SEL_STRIDE) * WV_SEL_STRIDE;
+        if (t0 < zbs[q] + zc)
+            sel0[t0 / WV_SEL_STRIDE] = 64 * w + wv_select_in_word(~xs[q] & vm, (uint32_t)(t0 - zbs[q]));
+    }
+    __syncthreads();
+    // one thread per superblock of the chunk
+    if (threadIdx.x < SD_W / 8) {
+        const uint64_t k = cw / 8 + threadIdx.x;
+        if (k < ns) {
+            const uint64_t zb = zex[8 * threadIdx.x];
+            uint64_t blk = 0;
+            for (uint32_t q = 1; q < 8; q++) blk |= (zex[8 * threadIdx.x + q] - zb) << (9 * (q - 1));
+            dir[2 * k] = zb;
+            dir[2 * k + 1] = blk;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(SD_T)
+span_finish_k(uint8_t* __restrict__ image, SpanLevels a, const uint64_t* __restrict__ totals)
+{
+    const uint32_t l = blockIdx.x;
+    const uint64_t n = a.n, ns = wv_cdiv(n, WV_SB_BITS);
+    const uint64_t ones = totals[l], zeros = n - ones;
+    uint64_t* dir = (uint64_t*)(image + a.rank_off[l]);
+    uint64_t* sel0 = (uint64_t*)(image + a.sel0_off[l]);
+    uint64_t* sel1 = (uint64_t*)(image + a.sel1_off[l]);
+    if (threadIdx.x == 0) {
+        dir[2 * ns] = zeros;
+        dir[2 * ns + 1] = 0;
+        uint64_t* desc = (uint64_t*)(image + WV_HEADER_BYTES + (uint64_t)WV_LEVEL_BYTES * (a.l0 + l));
+        desc[1] = zeros;
+        desc[2] = ones;
+    }
+    for (uint64_t k = wv_cdiv(ones, WV_SEL_STRIDE) + threadIdx.x; k < a.nsel; k += SD_T) sel1[k] = n;
+    for (uint64_t k = wv_cdiv(zeros, WV_SEL_STRIDE) + threadIdx.x; k < a.nsel; k += SD_T) sel0[k] = n;
+}
+
+}  // namespace
+
+wv_span_dir wv_span_dir_sizes(uint64_t n, uint32_t nl)
+{
+    wv_span_dir z{};
+    z.nl = nl;
+    z.nchunks = wv_cdiv(wv_cdiv(n, 64), SD_W);
+    const uint64_t items = std::max<uint64_t>(z.nchunks * nl, 1);
+    uint64_t off = 0;
+    z.off_cnt = off;
+    off = wv_round256(off + items * 4);
+    z.off_pre = off;
+    off = wv_round256(off + items * 8);
+    z.off_part = off;
+    off = wv_round256(off + 8 * wv_scan_partials(z.nchunks, nl));
+    z.off_tot = off;
+    off = wv_round256(off + 8 * (uint64_t)std::max<uint32_t>(nl, 1));
+    z.bytes = off;
+    return z;
+}
+
+hipError_t wv_span_directory(uint8_t* image, const wv_layout_out& lay, uint32_t l0, uint32_t nl,
+                             uint8_t* scratch, const wv_span_dir& sz, hipStream_t s)
+{
+    if (!nl) return hipSuccess;
+    SpanLevels a{};
+    a.n = lay.lv[l0].n;
+    a.nsel = lay.lv[l0].nsel;
+    a.l0 = l0;
+    a.nl = nl;
+    for (uint32_t l = 0; l < nl; l++) {
+        a.bits_off[l] = lay.lv[l0 + l].bits_off;
+        a.rank_off[l] = lay.lv[l0 + l].rank_off;
+        a.sel0_off[l] = lay.lv[l0 + l].sel0_off;
+        a.sel1_off[l] = lay.lv[l0 + l].sel1_off;
+    }
+    uint32_t* cnt = (uint32_t*)(scratch + sz.off_cnt);
+    uint64_t* pre = (uint64_t*)(scratch + sz.off_pre);
+    uint64_t* tot = (uint64_t*)(scratch + sz.off_tot);
+    const dim3 grid((uint32_t)sz.nchunks, nl);
+    if (sz.nchunks) span_count_k<<<grid, SD_T, 0, s>>>(image, a, cnt);
+    hipError_t e = wv_scan_u32(cnt, pre, sz.nchunks, nl, (uint64_t*)(scratch + sz.off_part), tot, s);
+    if (e != hipSuccess) return e;
+    if (sz.nchunks) span_write_k<<<grid, SD_T, 0, s>>>(image, a, pre);
+    span_finish_k<<<nl, SD_T, 0, s>>>(image, a, tot);
     return hipGetLastError();
 }

@@ -28,6 +28,17 @@ hipError_t wv_binary_directory(uint8_t* image, uint32_t level, const wv_level& L
 hipError_t wv_count_superblocks(const uint8_t* image, const wv_level& L, uint32_t* sb_ones,
                                 hipStream_t s);
 
+// Directories of several binary levels of n bits each (levels l0..l0+nl-1)
+// with one launch per step: per-chunk ones counts, a column-wise prefix sum,
+// then every chunk writes its superblocks and select samples.
+struct wv_span_dir {
+    uint64_t nchunks, nl;
+    uint64_t off_cnt, off_pre, off_part, off_tot, bytes;
+};
+wv_span_dir wv_span_dir_sizes(uint64_t n, uint32_t nl);
+hipError_t wv_span_directory(uint8_t* image, const wv_layout_out& lay, uint32_t l0, uint32_t nl,
+                             uint8_t* scratch, const wv_span_dir& sz, hipStream_t s);
+
 // per-digit counters of one multiary level
 struct wv_mdir_scratch {
     uint32_t* rng_cnt;   // ranges * d

@@ -5,11 +5,16 @@
 
 struct wv_wm_plan {
     bool enabled;          // false: the one-level-per-pass builder is used
-    uint32_t tau;          // key bits handled per pass
+    uint32_t tau;          // key bits (levels) handled per pass
+    uint32_t L, sym_bytes, K, C, sigma;
+    uint64_t n;
+    // workspace offsets
+    uint64_t off_H, off_tot, off_G0, off_pay[2], off_dir;
+    wv_span_dir dir;
     uint64_t ws_bytes;     // workspace the passes need
 };
 
-// Decide whether (and how) the multi-level passes build this matrix.
+// Decide how the multi-level passes build this matrix.
 int wv_wm_make_plan(uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt_tuning* tune, wv_wm_plan& p);
 
 // Build every level, directory and select sample of the matrix into `image`.

@@ -1,16 +1,540 @@
-// wv_wm_passes.hip -- multi-level partition passes for the wavelet matrix.
+// wv_wm_passes.hip -- the wavelet matrix built tau levels per pass.
+//
+// Sec. 4.3 ("Wavelet matrix") builds every tau-th level by an integer sort of
+// the current sequence on the reversed tau bits below the levels already
+// done, and the levels in between from the short tau-bit keys.  Here one pass
+// handles tau consecutive levels l = a*tau + j (j = 0..tau-1):
+//
+//   * The sequence of the pass (S for the first pass, then the compacted
+//     remaining key bits written by the previous pass) is cut into K
+//     contiguous chunks, one workgroup each; a chunk is a sub-problem of the
+//     domain decomposition of Sec. 4.2, processed tile after tile.
+//   * Level a*tau + j holds bit j of the tau-bit digit in the order of a
+//     stable sort by the first j digit bits, the most recent bit most
+//     significant (the wavelet-matrix order).  Inside a tile that order is
+//     produced by j stable 1-bit partitions in LDS; the tile's bits then form
+//     2^j runs, one per key, each going to a contiguous range of the level at
+//     an offset from the prefix sums of the per-chunk digit histograms
+//     (the prefix-sum offsets of Sec. 4.1 / Sec. 4.2).
+//   * Runs are written as 64-bit words.  A chunk carries the partial last
+//     word of each run from tile to tile, so only the first and last word of
+//     a chunk's run can be shared with another chunk; those "boundary" words
+//     (Sec. 4.2) are zeroed beforehand and OR-ed atomically, every other word
+//     is a plain store.
+//   * After the last sub-level the remaining key bits are scattered to the
+//     order of level (a+1)*tau (the next pass's input, the big-node sequence
+//     of Sec. 3/4.1), compacted to the narrowest integer type.
+//
+// Kernels per pass: a histogram of the pass digit per chunk (the first pass
+// also validates S), two small scans giving every chunk's run offsets and
+// zeroing the boundary words, and the pass itself.  The rank directories and
+// select samples of all levels follow (wv_directory.hip).
+#include <algorithm>
+
 #include "wv_wm_passes.h"
 
-int wv_wm_make_plan(uint64_t, uint32_t, uint32_t, const wt_tuning*, wv_wm_plan& p)
+namespace {
+
+constexpr int NT = 512;             // threads of a pass workgroup
+constexpr int NWAVE = NT / 64;
+constexpr int E = 8;                // elements per thread per tile
+constexpr int T = NT * E;           // tile
+constexpr int TW = T / 64;          // bit words per tile level
+constexpr int MAXG = 511;           // run groups of sub-levels j = 0..8
+constexpr int HT = 256;             // histogram / scan threads
+constexpr uint32_t KMAX = 768;      // chunks (all resident: 3 per CU)
+
+__device__ __host__ inline uint32_t gidx(uint32_t j, uint32_t u) { return (1u << j) - 1u + u; }
+
+__device__ inline uint32_t brev(uint32_t v, uint32_t nbits) { return nbits ? (__brev(v) >> (32 - nbits)) : 0u; }
+
+struct PassArgs {
+    const void* in;
+    void* pay_out;
+    uint64_t* words[8];     // bit arrays of levels a*tau + j
+    const uint32_t* G0;     // [K][MAXG] first run offset of every chunk
+    uint32_t n, C, K;       // elements, chunk length (multiple of T), chunks
+    uint32_t R, tau;        // key bits still to do, digit bits of this pass
+    uint32_t keymask;       // applied to the loaded keys
+};
+
+template <typename T_>
+__device__ inline uint32_t ld(const void* p, uint64_t i) { return (uint32_t)((const T_*)p)[i]; }
+
+// 64 bits of the tile bit string starting at bit `src`, keeping `nb` (1..64)
+__device__ inline uint64_t extract(const uint64_t* lb, uint32_t src, uint32_t nb)
 {
-    p.enabled = false;
-    p.tau = 1;
-    p.ws_bytes = 0;
+    const uint32_t w = src >> 6, o = src & 63;
+    uint64_t v = lb[w] >> o;
+    if (o && o + nb > 64) v |= lb[w + 1] << (64 - o);
+    return nb >= 64 ? v : (v & ((1ull << nb) - 1ull));
+}
+
+__device__ inline uint64_t lanemask_lt()
+{
+    const uint32_t lane = threadIdx.x & 63;
+    return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+// exclusive scan of up to 64 values held by one wave (lane l holds v)
+__device__ inline uint32_t wave_excl_scan(uint32_t v, uint32_t* total)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    uint32_t inc = v;
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(inc, d, 64);
+        if (lane >= (uint32_t)d) inc += t;
+    }
+    *total = __shfl(inc, 63, 64);
+    return inc - v;
+}
+
+template <typename IT, typename OT>
+__global__ void __launch_bounds__(NT)
+wm_pass_k(PassArgs a)
+{
+    __shared__ uint32_t buf[2][T];
+    __shared__ uint64_t lb[TW + 1];
+    __shared__ uint32_t zw[TW];
+    __shared__ uint32_t hist[256];
+    __shared__ uint32_t cnt[MAXG], ls[MAXG], g[MAXG], fw[MAXG];
+    __shared__ uint64_t carry[255];
+    __shared__ uint32_t sp[129];
+    __shared__ uint32_t ztot_s;
+
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t b = blockIdx.x;
+    const uint32_t tau = a.tau, R = a.R;
+    const uint32_t ngroups = (2u << tau) - 1u;         // j = 0..tau
+    const uint32_t cstart = b * a.C;
+    const uint32_t cend = min(a.n, cstart + a.C);
+    const uint32_t dshift = R - tau;
+    const uint32_t dmask = (1u << tau) - 1u;
+    const uint32_t pmask = dshift >= 32 ? ~0u : ((1u << dshift) - 1u);
+
+    for (uint32_t i = tid; i < ngroups; i += NT) {
+        const uint32_t g0 = a.G0[(uint64_t)b * MAXG + i];
+        g[i] = g0;
+        fw[i] = (g0 & 63u) ? (g0 >> 6) : 0xFFFFFFFFu;
+        if (i < 255) carry[i] = 0;
+    }
+    if (tid == 0) lb[TW] = 0;
+
+    for (uint32_t ts = cstart; ts < cend; ts += T) {
+        const uint32_t tc = min((uint32_t)T, cend - ts);
+        if (tid < 256) hist[tid] = 0;
+        __syncthreads();
+        // load the tile, count its digits
+        for (int e = 0; e < E; e++) {
+            const uint32_t p = tid + NT * e;
+            if (p < tc) {
+                const uint32_t x = ld<IT>(a.in, (uint64_t)ts + p) & a.keymask;
+                buf[0][p] = x;
+                atomicAdd(&hist[(x >> dshift) & dmask], 1u);
+            }
+        }
+        __syncthreads();
+        // run sizes of every key at every sub-level, from the digit counts
+        for (uint32_t i = tid; i < ngroups; i += NT) {
+            uint32_t j = 31 - __clz(i + 1);
+            uint32_t u = i + 1 - (1u << j);
+            uint32_t span = 1u << (tau - j);
+            uint32_t s = 0;
+            for (uint32_t d = u * span; d < (u + 1) * span; d++) s += hist[d];
+            cnt[i] = s;
+        }
+        __syncthreads();
+        // local start of every run: keys ordered by their bit-reversed value
+        for (uint32_t j = wave; j <= tau; j += NWAVE) {
+            const uint32_t nk = 1u << j;
+            uint32_t run = 0;
+            for (uint32_t r0 = 0; r0 < nk; r0 += 64) {
+                const uint32_t r = r0 + lane;
+                const uint32_t u = r < nk ? brev(r, j) : 0;
+                const uint32_t v = r < nk ? cnt[gidx(j, u)] : 0;
+                uint32_t tot;
+                const uint32_t ex = wave_excl_scan(v, &tot);
+                if (r < nk) ls[gidx(j, u)] = run + ex;
+                run += tot;
+            }
+        }
+        __syncthreads();
+
+        uint32_t cur = 0;
+        for (uint32_t j = 0; j < tau; j++) {
+            // bit j of every element, in the order of sub-level j
+            uint32_t xs[E];
+            uint64_t balls[E];
+            for (int e = 0; e < E; e++) {
+                const uint32_t p = tid + NT * e;
+                const bool valid = p < tc;
+                xs[e] = valid ? buf[cur][p] : 0u;
+                const uint32_t bit = valid ? ((xs[e] >> (R - 1 - j)) & 1u) : 0u;
+                balls[e] = __ballot(bit);
+                if (lane == 0) {
+                    const uint32_t wi = e * NWAVE + wave;
+                    lb[wi] = balls[e];
+                    const uint32_t base = wi * 64;
+                    const uint32_t nvalid = base >= tc ? 0u : min(64u, tc - base);
+                    zw[wi] = nvalid - __popcll(balls[e]);
+                }
+            }
+            __syncthreads();
+            if (wave == 0) {
+                // one wave: every lane reads its count before any lane writes
+                uint32_t tot;
+                const uint32_t v = lane < TW ? zw[lane] : 0u;
+                const uint32_t ex = wave_excl_scan(v, &tot);
+                if (lane < TW) zw[lane] = ex;
+                if (lane == 0) ztot_s = tot;
+            }
+            // run slots of this sub-level
+            const uint32_t nk = 1u << j;
+            const uint32_t gb = gidx(j, 0);
+            if (wave == 1) {
+                uint32_t v = 0;
+                if (lane < nk && lane < 64) {
+                    const uint32_t gg = g[gb + lane];
+                    v = ((gg + cnt[gb + lane]) >> 6) - (gg >> 6);
+                }
+                uint32_t tot;
+                uint32_t ex = wave_excl_scan(v, &tot);
+                if (lane < 64) sp[lane] = ex;
+                uint32_t run = tot;
+                if (nk > 64) {
+                    const uint32_t u = 64 + lane;
+                    uint32_t v2 = 0;
+                    if (u < nk) {
+                        const uint32_t gg = g[gb + u];
+                        v2 = ((gg + cnt[gb + u]) >> 6) - (gg >> 6);
+                    }
+                    uint32_t tot2;
+                    const uint32_t ex2 = wave_excl_scan(v2, &tot2);
+                    if (u < nk) sp[u] = run + ex2;
+                    run += tot2;
+                }
+                if (lane == 0) sp[nk] = run;
+            }
+            __syncthreads();
+            // stable partition by bit j: zeros first (the next sub-level order)
+            const uint32_t ztot = ztot_s;
+            for (int e = 0; e < E; e++) {
+                const uint32_t p = tid + NT * e;
+                if (p < tc) {
+                    const uint32_t wi = e * NWAVE + wave;
+                    const uint32_t zb = zw[wi] + (lane - __popcll(balls[e] & lanemask_lt()));
+                    const uint32_t bit = (uint32_t)((balls[e] >> lane) & 1ull);
+                    buf[cur ^ 1][bit ? ztot + (p - zb) : zb] = xs[e];
+                }
+            }
+            // emit the complete words of every run of sub-level j
+            uint64_t* words = a.words[j];
+            const uint32_t total = sp[nk];
+            for (uint32_t s = tid; s < total; s += NT) {
+                uint32_t lo = 0, hi = nk - 1;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi + 1) >> 1;
+                    if (sp[mid] <= s) lo = mid; else hi = mid - 1;
+                }
+                const uint32_t u = lo, gi = gb + u;
+                const uint32_t i = s - sp[u];
+                const uint32_t gg = g[gi];
+                const uint32_t W = (gg >> 6) + i;
+                const uint32_t wlo = max(W * 64u, gg);
+                const uint32_t nb = W * 64u + 64u - wlo;
+                uint64_t v = extract(lb, ls[gi] + (wlo - gg), nb) << (wlo - W * 64u);
+                if (i == 0) v |= carry[gi];
+                if (W == fw[gi]) atomicOr((unsigned long long*)&words[W], (unsigned long long)v);
+                else words[W] = v;
+            }
+            __syncthreads();
+            // carry the partial last word of every run to the next tile
+            for (uint32_t u = tid; u < nk; u += NT) {
+                const uint32_t gi = gb + u;
+                const uint32_t gg = g[gi], e = gg + cnt[gi];
+                uint64_t v = 0;
+                if (e & 63u) {
+                    const uint32_t We = e >> 6;
+                    const uint32_t wlo = max(We * 64u, gg);
+                    const uint32_t nb = e - wlo;
+                    if (nb) v = extract(lb, ls[gi] + (wlo - gg), nb) << (wlo - We * 64u);
+                    if (We == (gg >> 6)) v |= carry[gi];
+                }
+                carry[gi] = v;
+            }
+            cur ^= 1;
+            __syncthreads();
+        }
+        // remaining key bits to the order of the next pass
+        if (a.pay_out) {
+            for (int e = 0; e < E; e++) {
+                const uint32_t p = tid + NT * e;
+                if (p < tc) {
+                    const uint32_t x = buf[cur][p];
+                    const uint32_t gi = gidx(tau, (x >> dshift) & dmask);
+                    ((OT*)a.pay_out)[g[gi] + (p - ls[gi])] = (OT)(x & pmask);
+                }
+            }
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < ngroups; i += NT) g[i] += cnt[i];
+        __syncthreads();
+    }
+    // flush the partial words left at the end of the chunk
+    for (uint32_t i = tid; i < (1u << tau) - 1u; i += NT) {
+        const uint32_t j = 31 - __clz(i + 1);
+        if ((g[i] & 63u) && carry[i])
+            atomicOr((unsigned long long*)&a.words[j][g[i] >> 6], (unsigned long long)carry[i]);
+    }
+}
+
+// per-chunk histogram of the pass digit (first pass: also validates S)
+template <typename IT>
+__global__ void __launch_bounds__(HT)
+wm_hist_k(const void* __restrict__ in, uint32_t n, uint32_t C, uint32_t K, uint32_t R, uint32_t tau,
+          uint32_t keymask, uint32_t* __restrict__ H, uint32_t* __restrict__ status, uint32_t sigma)
+{
+    __shared__ uint32_t h[256];
+    const uint32_t b = blockIdx.x;
+    const uint32_t s = b * C, e = min(n, s + C);
+    const uint32_t dshift = R - tau, dmask = (1u << tau) - 1u;
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    bool bad = false;
+    constexpr uint32_t V = 16 / sizeof(IT);
+    // chunk starts are multiples of the tile, so 16-byte aligned
+    const uint32_t vs = s / V, ve = e / V;
+    const uint4* in4 = (const uint4*)in;
+    for (uint32_t v = vs + threadIdx.x; v < ve; v += HT) {
+        const uint4 q = in4[v];
+        const uint32_t wds[4] = {q.x, q.y, q.z, q.w};
+        for (uint32_t k = 0; k < V; k++) {
+            const uint32_t x = (sizeof(IT) == 4) ? wds[k]
+                             : (sizeof(IT) == 2) ? ((wds[k / 2] >> (16 * (k & 1))) & 0xFFFFu)
+                                                 : ((wds[k / 4] >> (8 * (k & 3))) & 0xFFu);
+            if (status && x >= sigma) bad = true;
+            atomicAdd(&h[((x & keymask) >> dshift) & dmask], 1u);
+        }
+    }
+    for (uint32_t i = max(s, ve * V) + threadIdx.x; i < e; i += HT) {
+        const uint32_t x = ld<IT>(in, i);
+        if (status && x >= sigma) bad = true;
+        atomicAdd(&h[((x & keymask) >> dshift) & dmask], 1u);
+    }
+    if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(status, 1u);
+    __syncthreads();
+    if (threadIdx.x <= dmask) H[(uint64_t)threadIdx.x * K + b] = h[threadIdx.x];
+}
+
+// exclusive prefix of every digit's counts over the chunks (in place)
+__global__ void __launch_bounds__(HT)
+wm_scan_chunks_k(uint32_t* __restrict__ H, uint32_t K, uint32_t* __restrict__ totals)
+{
+    __shared__ uint32_t ws[HT / 64];
+    const uint32_t d = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t* h = H + (uint64_t)d * K;
+    uint32_t run = 0;
+    for (uint32_t base = 0; base < K; base += HT) {
+        const uint32_t i = base + threadIdx.x;
+        const uint32_t v = i < K ? h[i] : 0u;
+        uint32_t wt;
+        const uint32_t ex = wave_excl_scan(v, &wt);
+        if (lane == 0) ws[wave] = wt;
+        __syncthreads();
+        uint32_t off = 0, tot = 0;
+        for (uint32_t w = 0; w < HT / 64; w++) {
+            if (w < wave) off += ws[w];
+            tot += ws[w];
+        }
+        if (i < K) h[i] = run + off + ex;
+        run += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) totals[d] = run;
+}
+
+// every chunk's first offset of every run, and zero the boundary words
+struct OffArgs {
+    const uint32_t* PH;
+    const uint32_t* totals;
+    uint32_t* G0;
+    uint64_t* words[8];
+    uint32_t K, tau, n;
+};
+
+__global__ void __launch_bounds__(HT)
+wm_offsets_k(OffArgs a)
+{
+    __shared__ uint32_t ph[256], tot[256];
+    __shared__ uint32_t cj[MAXG], tj[MAXG], bs[MAXG];
+    const uint32_t b = blockIdx.x, tau = a.tau;
+    const uint32_t nd = 1u << tau, ngroups = (2u << tau) - 1u;
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x < nd) {
+        ph[threadIdx.x] = a.PH[(uint64_t)threadIdx.x * a.K + b];
+        tot[threadIdx.x] = a.totals[threadIdx.x];
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < ngroups; i += HT) {
+        const uint32_t j = 31 - __clz(i + 1);
+        const uint32_t u = i + 1 - (1u << j);
+        const uint32_t span = 1u << (tau - j);
+        uint32_t s1 = 0, s2 = 0;
+        for (uint32_t d = u * span; d < (u + 1) * span; d++) { s1 += ph[d]; s2 += tot[d]; }
+        cj[i] = s1;
+        tj[i] = s2;
+    }
+    __syncthreads();
+    // start of every key's run on its level: keys in bit-reversed order
+    for (uint32_t j = wave; j <= tau; j += HT / 64) {
+        const uint32_t nk = 1u << j;
+        uint32_t run = 0;
+        for (uint32_t r0 = 0; r0 < nk; r0 += 64) {
+            const uint32_t r = r0 + lane;
+            const uint32_t u = r < nk ? brev(r, j) : 0;
+            const uint32_t v = r < nk ? tj[gidx(j, u)] : 0;
+            uint32_t t;
+            const uint32_t ex = wave_excl_scan(v, &t);
+            if (r < nk) bs[gidx(j, u)] = run + ex;
+            run += t;
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < ngroups; i += HT) {
+        const uint32_t g0 = bs[i] + cj[i];
+        a.G0[(uint64_t)b * MAXG + i] = g0;
+        const uint32_t j = 31 - __clz(i + 1);
+        if (j < tau && (g0 & 63u) && g0 < a.n) a.words[j][g0 >> 6] = 0;
+    }
+    if (b == 0 && threadIdx.x < tau && (a.n & 63u)) a.words[threadIdx.x][(a.n - 1) >> 6] = 0;
+}
+
+inline uint32_t width_bytes(uint32_t bits) { return bits <= 8 ? 1u : (bits <= 16 ? 2u : 4u); }
+
+struct Geometry {
+    uint32_t K, C;
+};
+
+Geometry geometry(uint64_t n, uint32_t blocks)
+{
+    const uint64_t tiles = wv_cdiv(n ? n : 1, T);
+    uint64_t K = blocks ? blocks : KMAX;
+    K = std::min<uint64_t>(K, tiles);
+    const uint64_t C = wv_cdiv(wv_cdiv(n ? n : 1, K), T) * T;
+    return Geometry{(uint32_t)wv_cdiv(n ? n : 1, C), (uint32_t)C};
+}
+
+template <typename IT, typename OT>
+void launch_pass(const PassArgs& a, hipStream_t s)
+{
+    wm_pass_k<IT, OT><<<a.K, NT, 0, s>>>(a);
+}
+
+template <typename IT>
+void launch_pass_out(const PassArgs& a, uint32_t out_bytes, hipStream_t s)
+{
+    if (!a.pay_out) launch_pass<IT, uint8_t>(a, s);
+    else if (out_bytes == 1) launch_pass<IT, uint8_t>(a, s);
+    else if (out_bytes == 2) launch_pass<IT, uint16_t>(a, s);
+    else launch_pass<IT, uint32_t>(a, s);
+}
+
+void launch_hist(uint32_t in_bytes, const void* in, uint32_t n, const Geometry& geo, uint32_t R, uint32_t tau,
+                 uint32_t keymask, uint32_t* H, uint32_t* status, uint32_t sigma, hipStream_t s)
+{
+    if (in_bytes == 1) wm_hist_k<uint8_t><<<geo.K, HT, 0, s>>>(in, n, geo.C, geo.K, R, tau, keymask, H, status, sigma);
+    else if (in_bytes == 2) wm_hist_k<uint16_t><<<geo.K, HT, 0, s>>>(in, n, geo.C, geo.K, R, tau, keymask, H, status, sigma);
+    else wm_hist_k<uint32_t><<<geo.K, HT, 0, s>>>(in, n, geo.C, geo.K, R, tau, keymask, H, status, sigma);
+}
+
+}  // namespace
+
+int wv_wm_make_plan(uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt_tuning* tune, wv_wm_plan& p)
+{
+    const uint32_t L = wv_key_bits(sigma);
+    uint32_t tau = tune && tune->tau ? tune->tau : 0;
+    if (tau > 8) return WT_EINVAL;
+    if (!tau) {
+        const uint32_t passes = (L + 7) / 8;
+        tau = (L + passes - 1) / passes;
+    }
+    tau = std::min(tau, L);
+    const Geometry geo = geometry(n, tune ? tune->blocks : 0);
+    p.enabled = true;
+    p.tau = tau;
+    p.L = L;
+    p.sym_bytes = sym_bytes;
+    p.K = geo.K;
+    p.C = geo.C;
+    p.n = n;
+    p.sigma = sigma;
+    // payload buffers: widest remaining key after the first pass
+    const uint32_t rem = L > tau ? L - tau : 0;
+    const uint64_t pay = rem ? (uint64_t)std::max<uint64_t>(n, 1) * width_bytes(rem) : 0;
+    uint64_t off = 0;
+    auto bump = [&](uint64_t bytes) { uint64_t at = off; off = wv_round256(off + bytes); return at; };
+    p.off_H = bump((uint64_t)256 * geo.K * 4);
+    p.off_tot = bump(256 * 4);
+    p.off_G0 = bump((uint64_t)geo.K * MAXG * 4);
+    p.off_pay[0] = bump(pay);
+    p.off_pay[1] = bump(L > 2 * tau ? pay : 0);
+    // directory scratch for all levels at once
+    p.dir = wv_span_dir_sizes(n, L);
+    p.off_dir = bump(p.dir.bytes);
+    p.ws_bytes = off;
     return WT_OK;
 }
 
-hipError_t wv_wm_run(const wv_wm_plan&, const void*, uint8_t*, const wv_layout_out&, uint8_t*,
-                     const wv_dir_scratch&, hipStream_t)
+hipError_t wv_wm_run(const wv_wm_plan& p, const void* S, uint8_t* image, const wv_layout_out& lay, uint8_t* ws,
+                     const wv_dir_scratch&, hipStream_t s)
 {
-    return hipErrorNotSupported;
+    const uint32_t L = p.L, n = (uint32_t)p.n;
+    uint32_t* H = (uint32_t*)(ws + p.off_H);
+    uint32_t* tot = (uint32_t*)(ws + p.off_tot);
+    uint32_t* G0 = (uint32_t*)(ws + p.off_G0);
+    uint32_t* status = (uint32_t*)(image + 36);
+    const Geometry geo{p.K, p.C};
+    const void* in = S;
+    uint32_t in_bytes = p.sym_bytes;
+    uint32_t keymask = L >= 32 ? ~0u : ((1u << L) - 1u);
+    int side = 0;
+    if (n) {
+        for (uint32_t l0 = 0; l0 < L; l0 += p.tau) {
+            const uint32_t tau = std::min(p.tau, L - l0);
+            const uint32_t R = L - l0;
+            const uint32_t rem = R - tau;
+            launch_hist(in_bytes, in, n, geo, R, tau, keymask, H, l0 == 0 ? status : nullptr, p.sigma, s);
+            wm_scan_chunks_k<<<1u << tau, HT, 0, s>>>(H, geo.K, tot);
+            OffArgs oa{};
+            oa.PH = H;
+            oa.totals = tot;
+            oa.G0 = G0;
+            for (uint32_t j = 0; j < tau; j++) oa.words[j] = (uint64_t*)(image + lay.lv[l0 + j].bits_off);
+            oa.K = geo.K;
+            oa.tau = tau;
+            oa.n = n;
+            wm_offsets_k<<<geo.K, HT, 0, s>>>(oa);
+            PassArgs pa{};
+            pa.in = in;
+            pa.pay_out = rem ? (void*)(ws + p.off_pay[side]) : nullptr;
+            for (uint32_t j = 0; j < tau; j++) pa.words[j] = oa.words[j];
+            pa.G0 = G0;
+            pa.n = n;
+            pa.C = geo.C;
+            pa.K = geo.K;
+            pa.R = R;
+            pa.tau = tau;
+            pa.keymask = keymask;
+            if (in_bytes == 1) launch_pass_out<uint8_t>(pa, width_bytes(rem), s);
+            else if (in_bytes == 2) launch_pass_out<uint16_t>(pa, width_bytes(rem), s);
+            else launch_pass_out<uint32_t>(pa, width_bytes(rem), s);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            in = pa.pay_out;
+            in_bytes = width_bytes(rem);
+            keymask = ~0u;
+            side ^= 1;
+        }
+    }
+    return wv_span_directory(image, lay, 0, L, ws + p.off_dir, p.dir, s);
 }

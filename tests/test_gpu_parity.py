@@ -105,3 +105,25 @@ def test_buffer_too_small():
     out = torch.empty(info.out_bytes, dtype=torch.uint8, device="cuda")
     ws = torch.empty(info.workspace_bytes - 1, dtype=torch.uint8, device="cuda")
     assert B.build_into(B.KIND_WM, S, 100, out, ws) == B.WT_ENOSPC
+
+
+@pytest.mark.parametrize("tau", [0, 1, 2, 3, 5, 7, 8])
+@pytest.mark.parametrize("blocks", [0, 1, 3, 7])
+def test_wm_passes_any_tau_and_chunking(tau, blocks):
+    """the matrix does not depend on the pass width or on how the sequence is
+    cut into chunks and tiles (many tiles per chunk, ragged last tile)"""
+    from paper_1610_03524_amd import inputs
+    S = inputs.c2_zipf(n=(1 << 18) + 4097, sigma=1 << 16, seed=11)
+    o = oracle_image(B.KIND_WM, S, 1 << 16)
+    g = gpu_image(B.KIND_WM, S, 1 << 16, tune=B.make_tuning(tau=tau, blocks=blocks))
+    assert_same(g, o, f"tau={tau} blocks={blocks}")
+
+
+@pytest.mark.parametrize("sigma,dt", [(256, np.uint8), (5, np.uint8), (1 << 20, np.uint32), (3000, np.uint16)])
+def test_wm_passes_widths(sigma, dt):
+    rng = np.random.default_rng(sigma)
+    S = rng.integers(0, sigma, 300001).astype(dt)
+    o = oracle_image(B.KIND_WM, S, sigma)
+    for blocks in (0, 2):
+        g = gpu_image(B.KIND_WM, S, sigma, tune=B.make_tuning(blocks=blocks))
+        assert_same(g, o, f"sigma={sigma} blocks={blocks}")
