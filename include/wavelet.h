@@ -116,6 +116,8 @@ typedef struct wt_tuning {
 
 /* force the level-by-level path (one level per pass) for any kind */
 #define WT_FLAG_LEVELWISE 1u
+/* time every kernel of the build with HIP events (read by wt_profile_read) */
+#define WT_FLAG_PROFILE   2u
 
 typedef struct wt_plan_info {
     uint32_t kind, nlevels, key_bits, arity_log2;
@@ -206,6 +208,17 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count,
 
 /* Bytes of a built image (reads the header; dev image, synchronizes). */
 int wt_image_bytes(const void* image, uint64_t* bytes, void* stream);
+
+/* Per-kernel timing of builds run with WT_FLAG_PROFILE: synchronizes the
+ * recorded events and returns, per kernel name, the number of launches and
+ * their summed duration (ms) since the last call; resets the totals.
+ * out: host array of cap entries; *count = number of names (may exceed cap). */
+typedef struct wt_profile_entry {
+    char name[48];
+    uint64_t launches;
+    double ms;
+} wt_profile_entry;
+int wt_profile_read(wt_profile_entry* out, uint32_t cap, uint32_t* count);
 
 /* Human-readable text of a status code. */
 const char* wt_strerror(int code);

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libwavelet.so")
 WT_OK, WT_EINVAL, WT_ERANGE, WT_ENOSPC, WT_EHIP, WT_EUNSUP = 0, -1, -2, -3, -4, -5
 KIND_WT, KIND_WM, KIND_SHAPED, KIND_MULTIARY = 1, 2, 3, 4
 FLAG_LEVELWISE = 1
+FLAG_PROFILE = 2
 U32_MAX = 0xFFFFFFFF
 U64_MAX = 0xFFFFFFFFFFFFFFFF
 
@@ -42,6 +43,10 @@ class wt_plan_info(ctypes.Structure):
 class wt_seq_desc(ctypes.Structure):
     _fields_ = [("S", c_vp), ("n", c_u64), ("sigma", c_u32), ("sym_bytes", c_u32),
                 ("out", c_vp), ("out_bytes", c_u64)]
+
+
+class wt_profile_entry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", c_u64), ("ms", ctypes.c_double)]
 
 
 class WaveletError(RuntimeError):
@@ -69,6 +74,7 @@ _SIGS = {
     "wt_batch_plan": (c_int, [c_int, c_vp, c_u32, c_vp, c_vp]),
     "wt_batch_build": (c_int, [c_int, c_vp, c_u32, c_vp, ctypes.c_size_t, c_vp, c_vp]),
     "wt_image_bytes": (c_int, [c_vp, c_vp, c_vp]),
+    "wt_profile_read": (c_int, [c_vp, c_u32, c_vp]),
     "wt_strerror": (ctypes.c_char_p, [c_int]),
 }
 
@@ -224,6 +230,14 @@ def image_bytes(image, stream=None) -> int:
     b = ctypes.c_uint64(0)
     _check(lib().wt_image_bytes(_ptr(image), ctypes.byref(b), _stream(stream)), "wt_image_bytes")
     return b.value
+
+
+def profile_read(cap: int = 64) -> dict:
+    """{kernel name: (launches, total ms)} of profiled builds since the last read"""
+    arr = (wt_profile_entry * cap)()
+    cnt = ctypes.c_uint32(0)
+    _check(lib().wt_profile_read(arr, cap, ctypes.byref(cnt)), "wt_profile_read")
+    return {arr[i].name.decode(): (arr[i].launches, arr[i].ms) for i in range(min(cap, cnt.value))}
 
 
 def batch_plan(kind: int, descs, tune=None) -> int:

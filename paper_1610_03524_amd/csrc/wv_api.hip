@@ -343,7 +343,8 @@ int build_any(int kind, const void* S, uint64_t n, uint32_t sigma, uint32_t sym_
     rc = check_buffers(p, S, out, out_bytes, ws, ws_bytes);
     if (rc) return rc;
     uint8_t* img = (uint8_t*)out;
-    WV_CHECK(wv_write_header(img, p.lin, s));
+    const bool prof = tune && (tune->flags & WT_FLAG_PROFILE);
+    WV_TIMED(prof, s, "header", WV_CHECK(wv_write_header(img, p.lin, s)));
 
     if (kind == WT_KIND_WM && !p.levelwise) {
         // the first pass validates S while counting its digits

@@ -498,7 +498,7 @@ wv_span_dir wv_span_dir_sizes(uint64_t n, uint32_t nl)
 }
 
 hipError_t wv_span_directory(uint8_t* image, const wv_layout_out& lay, uint32_t l0, uint32_t nl,
-                             uint8_t* scratch, const wv_span_dir& sz, hipStream_t s)
+                             uint8_t* scratch, const wv_span_dir& sz, hipStream_t s, bool prof)
 {
     if (!nl) return hipSuccess;
     SpanLevels a{};
@@ -516,10 +516,12 @@ hipError_t wv_span_directory(uint8_t* image, const wv_layout_out& lay, uint32_t 
     uint64_t* pre = (uint64_t*)(scratch + sz.off_pre);
     uint64_t* tot = (uint64_t*)(scratch + sz.off_tot);
     const dim3 grid((uint32_t)sz.nchunks, nl);
-    if (sz.nchunks) span_count_k<<<grid, SD_T, 0, s>>>(image, a, cnt);
-    hipError_t e = wv_scan_u32(cnt, pre, sz.nchunks, nl, (uint64_t*)(scratch + sz.off_part), tot, s);
+    if (sz.nchunks) WV_TIMED(prof, s, "dir_count", (span_count_k<<<grid, SD_T, 0, s>>>(image, a, cnt)));
+    hipError_t e = hipSuccess;
+    WV_TIMED(prof, s, "dir_scan",
+             e = wv_scan_u32(cnt, pre, sz.nchunks, nl, (uint64_t*)(scratch + sz.off_part), tot, s));
     if (e != hipSuccess) return e;
-    if (sz.nchunks) span_write_k<<<grid, SD_T, 0, s>>>(image, a, pre);
-    span_finish_k<<<nl, SD_T, 0, s>>>(image, a, tot);
+    if (sz.nchunks) WV_TIMED(prof, s, "dir_write", (span_write_k<<<grid, SD_T, 0, s>>>(image, a, pre)));
+    WV_TIMED(prof, s, "dir_finish", (span_finish_k<<<nl, SD_T, 0, s>>>(image, a, tot)));
     return hipGetLastError();
 }

@@ -4,6 +4,18 @@
 
 #include "wv_common.h"
 
+// ---- optional per-kernel timing (wv_profile.hip) ----------------------------
+int wv_prof_before(hipStream_t s);
+void wv_prof_after(int slot, hipStream_t s, const char* name);
+// run `launch` (one or more kernel launches on stream s), bracketed by events
+// named `name` when `on`
+#define WV_TIMED(on, s, name, launch)                  \
+    do {                                               \
+        const int slot_ = (on) ? wv_prof_before(s) : -1; \
+        launch;                                        \
+        if (slot_ >= 0) wv_prof_after(slot_, s, name); \
+    } while (0)
+
 // ---- prefix sum (wv_scan.hip) ----------------------------------------------
 // scratch entries (uint64) the scan of `count` items in `ncols` columns needs
 uint64_t wv_scan_partials(uint64_t count, uint32_t ncols);
@@ -37,7 +49,7 @@ struct wv_span_dir {
 };
 wv_span_dir wv_span_dir_sizes(uint64_t n, uint32_t nl);
 hipError_t wv_span_directory(uint8_t* image, const wv_layout_out& lay, uint32_t l0, uint32_t nl,
-                             uint8_t* scratch, const wv_span_dir& sz, hipStream_t s);
+                             uint8_t* scratch, const wv_span_dir& sz, hipStream_t s, bool prof = false);
 
 // per-digit counters of one multiary level
 struct wv_mdir_scratch {

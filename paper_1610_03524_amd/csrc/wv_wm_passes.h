@@ -12,6 +12,7 @@ struct wv_wm_plan {
     uint64_t off_H, off_tot, off_G0, off_pay[2], off_dir;
     wv_span_dir dir;
     uint64_t ws_bytes;     // workspace the passes need
+    bool profile;          // bracket the launches with timing events
 };
 
 // Decide how the multi-level passes build this matrix.

@@ -37,12 +37,13 @@ namespace {
 
 constexpr int NT = 512;             // threads of a pass workgroup
 constexpr int NWAVE = NT / 64;
-constexpr int E = 8;                // elements per thread per tile
+constexpr int E = 32;               // elements per thread per tile
 constexpr int T = NT * E;           // tile
 constexpr int TW = T / 64;          // bit words per tile level
 constexpr int MAXG = 511;           // run groups of sub-levels j = 0..8
 constexpr int HT = 256;             // histogram / scan threads
-constexpr uint32_t KMAX = 768;      // chunks (all resident: 3 per CU)
+constexpr uint32_t KMAX = 512;      // chunks (all resident: 2 per CU)
+
 
 __device__ __host__ inline uint32_t gidx(uint32_t j, uint32_t u) { return (1u << j) - 1u + u; }
 
@@ -89,18 +90,46 @@ __device__ inline uint32_t wave_excl_scan(uint32_t v, uint32_t* total)
     return inc - v;
 }
 
-template <typename IT, typename OT>
+template <typename IT, typename KT_>
+__device__ inline void load_tile(const void* in, uint32_t ts, uint32_t tc, uint32_t keymask, KT_* buf)
+{
+    // 16-byte loads; tile starts are multiples of the tile, so aligned
+    constexpr uint32_t V = 16 / sizeof(IT);
+    const uint32_t nv = tc / V;
+    const uint4* src = (const uint4*)((const IT*)in + ts);
+    for (uint32_t v = threadIdx.x; v < nv; v += NT) {
+        const uint4 q = src[v];
+        const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
+        for (uint32_t k = 0; k < V; k++) {
+            const uint32_t x = (sizeof(IT) == 4) ? wd[k]
+                             : (sizeof(IT) == 2) ? ((wd[k / 2] >> (16 * (k & 1))) & 0xFFFFu)
+                                                 : ((wd[k / 4] >> (8 * (k & 3))) & 0xFFu);
+            buf[v * V + k] = (KT_)(x & keymask);
+        }
+    }
+    for (uint32_t p = nv * V + threadIdx.x; p < tc; p += NT) buf[p] = (KT_)(ld<IT>(in, (uint64_t)ts + p) & keymask);
+}
+
+// zeros among the first s bits of the tile bit string (s <= tile length)
+__device__ inline uint32_t local_rank0(const uint64_t* lb, const uint32_t* zw, uint32_t s)
+{
+    const uint32_t w = s >> 6, o = s & 63;
+    uint32_t z = zw[w];
+    if (o) z += o - __popcll(lb[w] & ((1ull << o) - 1ull));
+    return z;
+}
+
+// KT_: type of the keys held in LDS (16 bits when at most 16 key bits remain)
+template <typename IT, typename OT, typename KT_>
 __global__ void __launch_bounds__(NT)
 wm_pass_k(PassArgs a)
 {
-    __shared__ uint32_t buf[2][T];
+    __shared__ KT_ buf[T];
     __shared__ uint64_t lb[TW + 1];
-    __shared__ uint32_t zw[TW];
-    __shared__ uint32_t hist[256];
+    __shared__ uint32_t zw[TW + 1];
     __shared__ uint32_t cnt[MAXG], ls[MAXG], g[MAXG], fw[MAXG];
-    __shared__ uint64_t carry[255];
+    __shared__ uint64_t carry[2][255];
     __shared__ uint32_t sp[129];
-    __shared__ uint32_t ztot_s;
 
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t b = blockIdx.x;
@@ -116,119 +145,112 @@ wm_pass_k(PassArgs a)
         const uint32_t g0 = a.G0[(uint64_t)b * MAXG + i];
         g[i] = g0;
         fw[i] = (g0 & 63u) ? (g0 >> 6) : 0xFFFFFFFFu;
-        if (i < 255) carry[i] = 0;
+        if (i < 255) carry[0][i] = 0;
     }
     if (tid == 0) lb[TW] = 0;
+    uint32_t cpar = 0;   // carry buffer read this tile
 
     for (uint32_t ts = cstart; ts < cend; ts += T) {
         const uint32_t tc = min((uint32_t)T, cend - ts);
-        if (tid < 256) hist[tid] = 0;
-        __syncthreads();
-        // load the tile, count its digits
-        for (int e = 0; e < E; e++) {
-            const uint32_t p = tid + NT * e;
-            if (p < tc) {
-                const uint32_t x = ld<IT>(a.in, (uint64_t)ts + p) & a.keymask;
-                buf[0][p] = x;
-                atomicAdd(&hist[(x >> dshift) & dmask], 1u);
-            }
-        }
-        __syncthreads();
-        // run sizes of every key at every sub-level, from the digit counts
-        for (uint32_t i = tid; i < ngroups; i += NT) {
-            uint32_t j = 31 - __clz(i + 1);
-            uint32_t u = i + 1 - (1u << j);
-            uint32_t span = 1u << (tau - j);
-            uint32_t s = 0;
-            for (uint32_t d = u * span; d < (u + 1) * span; d++) s += hist[d];
-            cnt[i] = s;
-        }
-        __syncthreads();
-        // local start of every run: keys ordered by their bit-reversed value
-        for (uint32_t j = wave; j <= tau; j += NWAVE) {
-            const uint32_t nk = 1u << j;
-            uint32_t run = 0;
-            for (uint32_t r0 = 0; r0 < nk; r0 += 64) {
-                const uint32_t r = r0 + lane;
-                const uint32_t u = r < nk ? brev(r, j) : 0;
-                const uint32_t v = r < nk ? cnt[gidx(j, u)] : 0;
-                uint32_t tot;
-                const uint32_t ex = wave_excl_scan(v, &tot);
-                if (r < nk) ls[gidx(j, u)] = run + ex;
-                run += tot;
-            }
-        }
+        load_tile<IT, KT_>(a.in, ts, tc, a.keymask, buf);
+        if (tid == 0) { cnt[0] = tc; ls[0] = 0; }
         __syncthreads();
 
-        uint32_t cur = 0;
         for (uint32_t j = 0; j < tau; j++) {
-            // bit j of every element, in the order of sub-level j
+            // phase 1: bit j of every element, in the order of sub-level j
             uint32_t xs[E];
-            uint64_t balls[E];
+            const uint32_t sh = R - 1 - j;
             for (int e = 0; e < E; e++) {
                 const uint32_t p = tid + NT * e;
-                const bool valid = p < tc;
-                xs[e] = valid ? buf[cur][p] : 0u;
-                const uint32_t bit = valid ? ((xs[e] >> (R - 1 - j)) & 1u) : 0u;
-                balls[e] = __ballot(bit);
+                xs[e] = p < tc ? (uint32_t)buf[p] : 0u;
+            }
+            for (int e = 0; e < E; e++) {
+                const uint32_t p = tid + NT * e;
+                const uint64_t ball = __ballot(p < tc && ((xs[e] >> sh) & 1u));
                 if (lane == 0) {
                     const uint32_t wi = e * NWAVE + wave;
-                    lb[wi] = balls[e];
+                    lb[wi] = ball;
                     const uint32_t base = wi * 64;
-                    const uint32_t nvalid = base >= tc ? 0u : min(64u, tc - base);
-                    zw[wi] = nvalid - __popcll(balls[e]);
+                    zw[wi] = (base >= tc ? 0u : min(64u, tc - base)) - __popcll(ball);
                 }
             }
-            __syncthreads();
-            if (wave == 0) {
-                // one wave: every lane reads its count before any lane writes
-                uint32_t tot;
-                const uint32_t v = lane < TW ? zw[lane] : 0u;
-                const uint32_t ex = wave_excl_scan(v, &tot);
-                if (lane < TW) zw[lane] = ex;
-                if (lane == 0) ztot_s = tot;
-            }
-            // run slots of this sub-level
             const uint32_t nk = 1u << j;
             const uint32_t gb = gidx(j, 0);
-            if (wave == 1) {
-                uint32_t v = 0;
-                if (lane < nk && lane < 64) {
-                    const uint32_t gg = g[gb + lane];
-                    v = ((gg + cnt[gb + lane]) >> 6) - (gg >> 6);
+            __syncthreads();
+            // phase 2: zero prefix over the words (wave 0), run slots (wave 1)
+            if (wave == 0) {
+                uint32_t v[TW / 64];
+                for (uint32_t k = 0; k < TW / 64; k++) v[k] = zw[64 * k + lane];
+                uint32_t run = 0;
+                for (uint32_t k = 0; k < TW / 64; k++) {
+                    uint32_t tot;
+                    const uint32_t ex = wave_excl_scan(v[k], &tot);
+                    zw[64 * k + lane] = run + ex;
+                    run += tot;
                 }
-                uint32_t tot;
-                uint32_t ex = wave_excl_scan(v, &tot);
-                if (lane < 64) sp[lane] = ex;
-                uint32_t run = tot;
-                if (nk > 64) {
-                    const uint32_t u = 64 + lane;
-                    uint32_t v2 = 0;
+                if (lane == 0) zw[TW] = run;
+            } else if (wave == 1) {
+                uint32_t run = 0;
+                for (uint32_t u0 = 0; u0 < nk; u0 += 64) {
+                    const uint32_t u = u0 + lane;
+                    uint32_t v = 0;
                     if (u < nk) {
                         const uint32_t gg = g[gb + u];
-                        v2 = ((gg + cnt[gb + u]) >> 6) - (gg >> 6);
+                        v = ((gg + cnt[gb + u]) >> 6) - (gg >> 6);
                     }
-                    uint32_t tot2;
-                    const uint32_t ex2 = wave_excl_scan(v2, &tot2);
-                    if (u < nk) sp[u] = run + ex2;
-                    run += tot2;
+                    uint32_t tot;
+                    const uint32_t ex = wave_excl_scan(v, &tot);
+                    if (u < nk) sp[u] = run + ex;
+                    run += tot;
                 }
                 if (lane == 0) sp[nk] = run;
             }
             __syncthreads();
-            // stable partition by bit j: zeros first (the next sub-level order)
-            const uint32_t ztot = ztot_s;
-            for (int e = 0; e < E; e++) {
-                const uint32_t p = tid + NT * e;
-                if (p < tc) {
-                    const uint32_t wi = e * NWAVE + wave;
-                    const uint32_t zb = zw[wi] + (lane - __popcll(balls[e] & lanemask_lt()));
-                    const uint32_t bit = (uint32_t)((balls[e] >> lane) & 1ull);
-                    buf[cur ^ 1][bit ? ztot + (p - zb) : zb] = xs[e];
+            // phase 3: partition, child runs, emit words
+            const uint32_t ztot = zw[TW];
+            const uint64_t ltm = lanemask_lt();
+            for (int e0 = 0; e0 < E; e0 += 8) {
+                // eight words' ballots and zero prefixes first, then the moves
+                uint64_t balls[8];
+                uint32_t zws[8];
+                for (int k = 0; k < 8; k++) {
+                    const uint32_t wi = (e0 + k) * NWAVE + wave;
+                    balls[k] = lb[wi];
+                    zws[k] = zw[wi];
+                }
+                for (int k = 0; k < 8; k++) {
+                    const uint32_t p = tid + NT * (e0 + k);
+                    if (p < tc) {
+                        const uint32_t zb = zws[k] + (lane - __popcll(balls[k] & ltm));
+                        const uint32_t bit = (uint32_t)((balls[k] >> lane) & 1ull);
+                        buf[bit ? ztot + (p - zb) : zb] = (KT_)xs[e0 + k];
+                    }
                 }
             }
-            // emit the complete words of every run of sub-level j
+            // runs of sub-level j+1 split the runs of j by bit j; a child's
+            // elements keep their order, zeros of the tile first
+            const uint32_t gc = gidx(j + 1, 0);
             uint64_t* words = a.words[j];
+            for (uint32_t u = tid; u < nk; u += NT) {
+                const uint32_t s0 = ls[gb + u], c = cnt[gb + u];
+                const uint32_t zs = local_rank0(lb, zw, s0), ze = local_rank0(lb, zw, s0 + c);
+                cnt[gc + 2 * u] = ze - zs;
+                cnt[gc + 2 * u + 1] = c - (ze - zs);
+                ls[gc + 2 * u] = zs;
+                ls[gc + 2 * u + 1] = ztot + (s0 - zs);
+                // the partial last word of the run, carried to the next tile
+                const uint32_t gi = gb + u;
+                const uint32_t gg = g[gi], en = gg + c;
+                uint64_t v = 0;
+                if (en & 63u) {
+                    const uint32_t We = en >> 6;
+                    const uint32_t wlo = max(We * 64u, gg);
+                    const uint32_t nb = en - wlo;
+                    if (nb) v = extract(lb, s0 + (wlo - gg), nb) << (wlo - We * 64u);
+                    if (We == (gg >> 6)) v |= carry[cpar][gi];
+                }
+                carry[cpar ^ 1][gi] = v;
+            }
             const uint32_t total = sp[nk];
             for (uint32_t s = tid; s < total; s += NT) {
                 uint32_t lo = 0, hi = nk - 1;
@@ -236,33 +258,17 @@ wm_pass_k(PassArgs a)
                     const uint32_t mid = (lo + hi + 1) >> 1;
                     if (sp[mid] <= s) lo = mid; else hi = mid - 1;
                 }
-                const uint32_t u = lo, gi = gb + u;
-                const uint32_t i = s - sp[u];
+                const uint32_t gi = gb + lo;
+                const uint32_t i = s - sp[lo];
                 const uint32_t gg = g[gi];
                 const uint32_t W = (gg >> 6) + i;
                 const uint32_t wlo = max(W * 64u, gg);
                 const uint32_t nb = W * 64u + 64u - wlo;
                 uint64_t v = extract(lb, ls[gi] + (wlo - gg), nb) << (wlo - W * 64u);
-                if (i == 0) v |= carry[gi];
+                if (i == 0) v |= carry[cpar][gi];
                 if (W == fw[gi]) atomicOr((unsigned long long*)&words[W], (unsigned long long)v);
                 else words[W] = v;
             }
-            __syncthreads();
-            // carry the partial last word of every run to the next tile
-            for (uint32_t u = tid; u < nk; u += NT) {
-                const uint32_t gi = gb + u;
-                const uint32_t gg = g[gi], e = gg + cnt[gi];
-                uint64_t v = 0;
-                if (e & 63u) {
-                    const uint32_t We = e >> 6;
-                    const uint32_t wlo = max(We * 64u, gg);
-                    const uint32_t nb = e - wlo;
-                    if (nb) v = extract(lb, ls[gi] + (wlo - gg), nb) << (wlo - We * 64u);
-                    if (We == (gg >> 6)) v |= carry[gi];
-                }
-                carry[gi] = v;
-            }
-            cur ^= 1;
             __syncthreads();
         }
         // remaining key bits to the order of the next pass
@@ -270,7 +276,7 @@ wm_pass_k(PassArgs a)
             for (int e = 0; e < E; e++) {
                 const uint32_t p = tid + NT * e;
                 if (p < tc) {
-                    const uint32_t x = buf[cur][p];
+                    const uint32_t x = buf[p];
                     const uint32_t gi = gidx(tau, (x >> dshift) & dmask);
                     ((OT*)a.pay_out)[g[gi] + (p - ls[gi])] = (OT)(x & pmask);
                 }
@@ -278,52 +284,89 @@ wm_pass_k(PassArgs a)
         }
         __syncthreads();
         for (uint32_t i = tid; i < ngroups; i += NT) g[i] += cnt[i];
+        cpar ^= 1;
         __syncthreads();
     }
     // flush the partial words left at the end of the chunk
     for (uint32_t i = tid; i < (1u << tau) - 1u; i += NT) {
         const uint32_t j = 31 - __clz(i + 1);
-        if ((g[i] & 63u) && carry[i])
-            atomicOr((unsigned long long*)&a.words[j][g[i] >> 6], (unsigned long long)carry[i]);
+        if ((g[i] & 63u) && carry[cpar][i])
+            atomicOr((unsigned long long*)&a.words[j][g[i] >> 6], (unsigned long long)carry[cpar][i]);
     }
 }
 
-// per-chunk histogram of the pass digit (first pass: also validates S)
+constexpr uint32_t HSPLIT = 8;       // histogram workgroups per chunk
+constexpr uint32_t HUNROLL = 4;      // 16-byte loads in flight per thread
+
+__device__ inline uint32_t sym_of(const uint32_t* wds, uint32_t k, uint32_t size)
+{
+    return size == 4 ? wds[k] : (size == 2 ? ((wds[k / 2] >> (16 * (k & 1))) & 0xFFFFu)
+                                           : ((wds[k / 4] >> (8 * (k & 3))) & 0xFFu));
+}
+
+// per-chunk histogram of the pass digit (first pass: also validates S);
+// HSPLIT workgroups share a chunk and add their counts into H
 template <typename IT>
 __global__ void __launch_bounds__(HT)
 wm_hist_k(const void* __restrict__ in, uint32_t n, uint32_t C, uint32_t K, uint32_t R, uint32_t tau,
           uint32_t keymask, uint32_t* __restrict__ H, uint32_t* __restrict__ status, uint32_t sigma)
 {
-    __shared__ uint32_t h[256];
-    const uint32_t b = blockIdx.x;
-    const uint32_t s = b * C, e = min(n, s + C);
+    __shared__ uint32_t h[HT / 64][256];
+    const uint32_t b = blockIdx.x / HSPLIT, part = blockIdx.x % HSPLIT;
+    const uint32_t wave = threadIdx.x >> 6;
+    const uint32_t cs = b * C, ce = min(n, cs + C);
     const uint32_t dshift = R - tau, dmask = (1u << tau) - 1u;
-    h[threadIdx.x] = 0;
+    for (uint32_t i = threadIdx.x; i < (HT / 64) * 256; i += HT) (&h[0][0])[i] = 0;
     __syncthreads();
     bool bad = false;
     constexpr uint32_t V = 16 / sizeof(IT);
-    // chunk starts are multiples of the tile, so 16-byte aligned
-    const uint32_t vs = s / V, ve = e / V;
+    // the chunk's 16-byte vectors (chunk starts are tile multiples, so
+    // aligned), split evenly over the HSPLIT workgroups
+    const uint32_t nvec = (ce - cs) / V;
+    const uint32_t per = (nvec + HSPLIT - 1) / HSPLIT;
+    const uint32_t vs = cs / V + part * per;
+    const uint32_t ve = cs / V + min(nvec, (part + 1) * per);
     const uint4* in4 = (const uint4*)in;
-    for (uint32_t v = vs + threadIdx.x; v < ve; v += HT) {
-        const uint4 q = in4[v];
-        const uint32_t wds[4] = {q.x, q.y, q.z, q.w};
-        for (uint32_t k = 0; k < V; k++) {
-            const uint32_t x = (sizeof(IT) == 4) ? wds[k]
-                             : (sizeof(IT) == 2) ? ((wds[k / 2] >> (16 * (k & 1))) & 0xFFFFu)
-                                                 : ((wds[k / 4] >> (8 * (k & 3))) & 0xFFu);
-            if (status && x >= sigma) bad = true;
-            atomicAdd(&h[((x & keymask) >> dshift) & dmask], 1u);
+    for (uint32_t v0 = vs + threadIdx.x; v0 < ve; v0 += HT * HUNROLL) {
+        uint4 q[HUNROLL];
+        for (uint32_t u = 0; u < HUNROLL; u++) {
+            const uint32_t v = v0 + u * HT;
+            q[u] = v < ve ? in4[v] : make_uint4(0, 0, 0, 0);
+        }
+        for (uint32_t u = 0; u < HUNROLL; u++) {
+            if (v0 + u * HT >= ve) break;
+            const uint32_t wds[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
+            // runs of equal digits (common once the sequence is grouped by
+            // its leading bits) are added at once
+            uint32_t cur = ((sym_of(wds, 0, sizeof(IT)) & keymask) >> dshift) & dmask, run = 0;
+            for (uint32_t k = 0; k < V; k++) {
+                const uint32_t x = sym_of(wds, k, sizeof(IT));
+                bad |= x >= sigma;
+                const uint32_t d = ((x & keymask) >> dshift) & dmask;
+                if (d != cur) {
+                    atomicAdd(&h[wave][cur], run);
+                    cur = d;
+                    run = 0;
+                }
+                run++;
+            }
+            atomicAdd(&h[wave][cur], run);
         }
     }
-    for (uint32_t i = max(s, ve * V) + threadIdx.x; i < e; i += HT) {
-        const uint32_t x = ld<IT>(in, i);
-        if (status && x >= sigma) bad = true;
-        atomicAdd(&h[((x & keymask) >> dshift) & dmask], 1u);
+    if (part == HSPLIT - 1) {
+        for (uint32_t i = cs + nvec * V + threadIdx.x; i < ce; i += HT) {
+            const uint32_t x = ld<IT>(in, i);
+            bad |= x >= sigma;
+            atomicAdd(&h[wave][((x & keymask) >> dshift) & dmask], 1u);
+        }
     }
-    if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(status, 1u);
+    if (status && __ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(status, 1u);
     __syncthreads();
-    if (threadIdx.x <= dmask) H[(uint64_t)threadIdx.x * K + b] = h[threadIdx.x];
+    if (threadIdx.x <= dmask) {
+        uint32_t c = 0;
+        for (uint32_t w = 0; w < HT / 64; w++) c += h[w][threadIdx.x];
+        if (c) atomicAdd(&H[(uint64_t)threadIdx.x * K + b], c);
+    }
 }
 
 // exclusive prefix of every digit's counts over the chunks (in place)
@@ -427,7 +470,8 @@ Geometry geometry(uint64_t n, uint32_t blocks)
 template <typename IT, typename OT>
 void launch_pass(const PassArgs& a, hipStream_t s)
 {
-    wm_pass_k<IT, OT><<<a.K, NT, 0, s>>>(a);
+    if (a.R <= 16) wm_pass_k<IT, OT, uint16_t><<<a.K, NT, 0, s>>>(a);
+    else wm_pass_k<IT, OT, uint32_t><<<a.K, NT, 0, s>>>(a);
 }
 
 template <typename IT>
@@ -439,12 +483,20 @@ void launch_pass_out(const PassArgs& a, uint32_t out_bytes, hipStream_t s)
     else launch_pass<IT, uint32_t>(a, s);
 }
 
+__global__ void zero_u32_k(uint32_t* p, uint32_t count)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
 void launch_hist(uint32_t in_bytes, const void* in, uint32_t n, const Geometry& geo, uint32_t R, uint32_t tau,
                  uint32_t keymask, uint32_t* H, uint32_t* status, uint32_t sigma, hipStream_t s)
 {
-    if (in_bytes == 1) wm_hist_k<uint8_t><<<geo.K, HT, 0, s>>>(in, n, geo.C, geo.K, R, tau, keymask, H, status, sigma);
-    else if (in_bytes == 2) wm_hist_k<uint16_t><<<geo.K, HT, 0, s>>>(in, n, geo.C, geo.K, R, tau, keymask, H, status, sigma);
-    else wm_hist_k<uint32_t><<<geo.K, HT, 0, s>>>(in, n, geo.C, geo.K, R, tau, keymask, H, status, sigma);
+    const uint32_t cells = (1u << tau) * geo.K;
+    zero_u32_k<<<(cells + 255) / 256, 256, 0, s>>>(H, cells);
+    const uint32_t grid = geo.K * HSPLIT;
+    if (in_bytes == 1) wm_hist_k<uint8_t><<<grid, HT, 0, s>>>(in, n, geo.C, geo.K, R, tau, keymask, H, status, sigma);
+    else if (in_bytes == 2) wm_hist_k<uint16_t><<<grid, HT, 0, s>>>(in, n, geo.C, geo.K, R, tau, keymask, H, status, sigma);
+    else wm_hist_k<uint32_t><<<grid, HT, 0, s>>>(in, n, geo.C, geo.K, R, tau, keymask, H, status, sigma);
 }
 
 }  // namespace
@@ -461,6 +513,7 @@ int wv_wm_make_plan(uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt_tun
     tau = std::min(tau, L);
     const Geometry geo = geometry(n, tune ? tune->blocks : 0);
     p.enabled = true;
+    p.profile = tune && (tune->flags & WT_FLAG_PROFILE);
     p.tau = tau;
     p.L = L;
     p.sym_bytes = sym_bytes;
@@ -503,8 +556,10 @@ hipError_t wv_wm_run(const wv_wm_plan& p, const void* S, uint8_t* image, const w
             const uint32_t tau = std::min(p.tau, L - l0);
             const uint32_t R = L - l0;
             const uint32_t rem = R - tau;
-            launch_hist(in_bytes, in, n, geo, R, tau, keymask, H, l0 == 0 ? status : nullptr, p.sigma, s);
-            wm_scan_chunks_k<<<1u << tau, HT, 0, s>>>(H, geo.K, tot);
+            const bool pr = p.profile;
+            WV_TIMED(pr, s, "wm_hist",
+                     launch_hist(in_bytes, in, n, geo, R, tau, keymask, H, l0 == 0 ? status : nullptr, p.sigma, s));
+            WV_TIMED(pr, s, "wm_scan", (wm_scan_chunks_k<<<1u << tau, HT, 0, s>>>(H, geo.K, tot)));
             OffArgs oa{};
             oa.PH = H;
             oa.totals = tot;
@@ -513,7 +568,7 @@ hipError_t wv_wm_run(const wv_wm_plan& p, const void* S, uint8_t* image, const w
             oa.K = geo.K;
             oa.tau = tau;
             oa.n = n;
-            wm_offsets_k<<<geo.K, HT, 0, s>>>(oa);
+            WV_TIMED(pr, s, "wm_offsets", (wm_offsets_k<<<geo.K, HT, 0, s>>>(oa)));
             PassArgs pa{};
             pa.in = in;
             pa.pay_out = rem ? (void*)(ws + p.off_pay[side]) : nullptr;
@@ -525,9 +580,10 @@ hipError_t wv_wm_run(const wv_wm_plan& p, const void* S, uint8_t* image, const w
             pa.R = R;
             pa.tau = tau;
             pa.keymask = keymask;
-            if (in_bytes == 1) launch_pass_out<uint8_t>(pa, width_bytes(rem), s);
-            else if (in_bytes == 2) launch_pass_out<uint16_t>(pa, width_bytes(rem), s);
-            else launch_pass_out<uint32_t>(pa, width_bytes(rem), s);
+            WV_TIMED(pr, s, "wm_pass",
+                     if (in_bytes == 1) launch_pass_out<uint8_t>(pa, width_bytes(rem), s);
+                     else if (in_bytes == 2) launch_pass_out<uint16_t>(pa, width_bytes(rem), s);
+                     else launch_pass_out<uint32_t>(pa, width_bytes(rem), s));
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
             in = pa.pay_out;
@@ -536,5 +592,5 @@ hipError_t wv_wm_run(const wv_wm_plan& p, const void* S, uint8_t* image, const w
             side ^= 1;
         }
     }
-    return wv_span_directory(image, lay, 0, L, ws + p.off_dir, p.dir, s);
+    return wv_span_directory(image, lay, 0, L, ws + p.off_dir, p.dir, s, p.profile);
 }
