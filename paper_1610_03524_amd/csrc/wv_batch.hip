@@ -1,5 +1,411 @@
-// wv_batch.hip -- batched wavelet-matrix builds over many sequences.
-#include "wv_internal.h"
+// wv_batch.hip -- wavelet matrices of many sequences with a few persistent
+// launches.
+//
+// Every sequence is built exactly as wm_build builds it alone (same passes,
+// same chunking rule, same image), but each step runs for all sequences in
+// one launch: the chunk histograms of every sequence, then one workgroup per
+// sequence turning its histograms into run offsets, then a persistent pass
+// kernel whose workgroups pull chunks of any sequence from a device-side
+// queue (largest sequences first), and finally the directories of every
+// level of every sequence.  Sequences with more levels take more rounds of
+// passes; a round only holds the sequences that still have levels to build.
+// The host writes the per-round descriptor arrays into the workspace and the
+// call returns when the batch is complete.
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "wv_wm_core.h"
+#include "wv_wm_passes.h"
+
+namespace {
+
+struct SeqRound {
+    PassArgs pa;            // the pass of this round (G0 points to the sequence's table)
+    uint32_t* H;            // [2^tau][K] digit counts of the chunks
+    uint32_t* status;       // image status word (first round) or null
+    uint32_t in_bytes, out_bytes, sigma, chunk0;   // chunk0: first global chunk index
+};
+
+struct SpanDesc {
+    uint8_t* image;
+    uint64_t n, bits_off, rank_off, sel0_off, sel1_off, nsel;
+    uint32_t* cnt;          // ones per directory chunk
+    uint64_t* pre;          // exclusive prefix of cnt
+    uint32_t level, chunk0; // level index, first global directory chunk
+};
+
+constexpr uint32_t SDW = 512;   // words per directory chunk
+
+// global item -> owner, over an exclusive prefix array of `count` owners
+__device__ inline uint32_t owner_of(const uint32_t* first, uint32_t count, uint32_t item)
+{
+    uint32_t lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= item) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(HT)
+b_hist_k(const SeqRound* __restrict__ seqs, const uint32_t* __restrict__ chunk0, uint32_t nseq)
+{
+    __shared__ uint32_t h[HT / 64][256];
+    const uint32_t item = blockIdx.x / HSPLIT, part = blockIdx.x % HSPLIT;
+    const uint32_t s = owner_of(chunk0, nseq, item);
+    const SeqRound& q = seqs[s];
+    const uint32_t b = item - q.chunk0;
+    const PassArgs& a = q.pa;
+    if (q.in_bytes == 1)
+        wm_hist_part<uint8_t>(a.in, a.n, a.C, a.K, a.R, a.tau, a.keymask, q.H, q.status, q.sigma, b, part, h);
+    else if (q.in_bytes == 2)
+        wm_hist_part<uint16_t>(a.in, a.n, a.C, a.K, a.R, a.tau, a.keymask, q.H, q.status, q.sigma, b, part, h);
+    else
+        wm_hist_part<uint32_t>(a.in, a.n, a.C, a.K, a.R, a.tau, a.keymask, q.H, q.status, q.sigma, b, part, h);
+}
+
+// one workgroup per sequence: prefix of every digit over the sequence's
+// chunks, then every chunk's run offsets (and zeroed boundary words)
+__global__ void __launch_bounds__(HT)
+b_offsets_k(const SeqRound* __restrict__ seqs)
+{
+    __shared__ uint32_t ph[256], tot[256];
+    __shared__ uint32_t cj[MAXG], tj[MAXG], bs[MAXG];
+    const SeqRound& q = seqs[blockIdx.x];
+    const PassArgs& a = q.pa;
+    const uint32_t tau = a.tau, K = a.K;
+    const uint32_t nd = 1u << tau, ngroups = (2u << tau) - 1u;
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // totals per digit, then per key of every sub-level its start on the level
+    if (threadIdx.x < nd) {
+        uint32_t t = 0;
+        for (uint32_t b = 0; b < K; b++) t += q.H[(uint64_t)threadIdx.x * K + b];
+        tot[threadIdx.x] = t;
+        ph[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < ngroups; i += HT) {
+        const uint32_t j = 31 - __clz(i + 1), u = i + 1 - (1u << j), span = 1u << (tau - j);
+        uint32_t s2 = 0;
+        for (uint32_t d = u * span; d < (u + 1) * span; d++) s2 += tot[d];
+        tj[i] = s2;
+    }
+    __syncthreads();
+    for (uint32_t j = wave; j <= tau; j += HT / 64) {
+        const uint32_t nk = 1u << j;
+        uint32_t run = 0;
+        for (uint32_t r0 = 0; r0 < nk; r0 += 64) {
+            const uint32_t r = r0 + lane;
+            const uint32_t u = r < nk ? brev(r, j) : 0;
+            const uint32_t v = r < nk ? tj[gidx(j, u)] : 0;
+            uint32_t t;
+            const uint32_t ex = wave_excl_scan(v, &t);
+            if (r < nk) bs[gidx(j, u)] = run + ex;
+            run += t;
+        }
+    }
+    __syncthreads();
+    for (uint32_t b = 0; b < K; b++) {
+        for (uint32_t i = threadIdx.x; i < ngroups; i += HT) {
+            const uint32_t j = 31 - __clz(i + 1), u = i + 1 - (1u << j), span = 1u << (tau - j);
+            uint32_t s1 = 0;
+            for (uint32_t d = u * span; d < (u + 1) * span; d++) s1 += ph[d];
+            cj[i] = s1;
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < ngroups; i += HT) {
+            const uint32_t g0 = bs[i] + cj[i];
+            ((uint32_t*)a.G0)[(uint64_t)b * MAXG + i] = g0;
+            const uint32_t j = 31 - __clz(i + 1);
+            if (j < tau && (g0 & 63u) && g0 < a.n) a.words[j][g0 >> 6] = 0;
+        }
+        __syncthreads();
+        if (threadIdx.x < nd) ph[threadIdx.x] += q.H[(uint64_t)threadIdx.x * K + b];
+        __syncthreads();
+    }
+    if (threadIdx.x < tau && (a.n & 63u)) a.words[threadIdx.x][(a.n - 1) >> 6] = 0;
+}
+
+// persistent pass: workgroups take chunks from the queue until it is empty
+template <typename KT_>
+__global__ void __launch_bounds__(NT)
+b_pass_k(const SeqRound* __restrict__ seqs, const uint32_t* __restrict__ chunk0, uint32_t nseq,
+         uint32_t nchunks, uint32_t* __restrict__ queue)
+{
+    __shared__ PassShared<KT_> sh;
+    __shared__ uint32_t item_s;
+    for (;;) {
+        if (threadIdx.x == 0) item_s = atomicAdd(queue, 1u);
+        __syncthreads();
+        const uint32_t item = item_s;
+        __syncthreads();
+        if (item >= nchunks) break;
+        const uint32_t s = owner_of(chunk0, nseq, item);
+        const SeqRound& q = seqs[s];
+        const uint32_t b = item - q.chunk0;
+        const uint32_t ib = q.in_bytes, ob = q.out_bytes;
+        if (ib == 1) {
+            wm_pass_chunk<uint8_t, uint8_t, KT_>(q.pa, b, sh);
+        } else if (ib == 2) {
+            if (ob == 2) wm_pass_chunk<uint16_t, uint16_t, KT_>(q.pa, b, sh);
+            else wm_pass_chunk<uint16_t, uint8_t, KT_>(q.pa, b, sh);
+        } else {
+            if (ob == 4) wm_pass_chunk<uint32_t, uint32_t, KT_>(q.pa, b, sh);
+            else if (ob == 2) wm_pass_chunk<uint32_t, uint16_t, KT_>(q.pa, b, sh);
+            else wm_pass_chunk<uint32_t, uint8_t, KT_>(q.pa, b, sh);
+        }
+        __syncthreads();
+    }
+}
+
+// ---- directories of every (sequence, level) ------------------------------------
+
+__global__ void __launch_bounds__(256)
+b_dir_count_k(const SpanDesc* __restrict__ spans, const uint32_t* __restrict__ chunk0, uint32_t nspan)
+{
+    __shared__ uint32_t part[4];
+    const uint32_t s = owner_of(chunk0, nspan, blockIdx.x);
+    const SpanDesc& d = spans[s];
+    const uint32_t c = blockIdx.x - d.chunk0;
+    const uint64_t nw = wv_cdiv(d.n, 64);
+    const uint64_t* words = (const uint64_t*)(d.image + d.bits_off);
+    const uint64_t w0 = (uint64_t)c * SDW + 2 * threadIdx.x;
+    uint32_t o = 0;
+    if (w0 < nw) o += __popcll(words[w0]);
+    if (w0 + 1 < nw) o += __popcll(words[w0 + 1]);
+    for (int k = 32; k >= 1; k >>= 1) o += __shfl_xor(o, k, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = o;
+    __syncthreads();
+    if (threadIdx.x == 0) d.cnt[c] = part[0] + part[1] + part[2] + part[3];
+}
+
+// one workgroup per span: prefix of its chunk counts, sentinels, descriptor
+__global__ void __launch_bounds__(256)
+b_dir_scan_k(const SpanDesc* __restrict__ spans)
+{
+    __shared__ uint32_t ws[4];
+    __shared__ uint64_t total_s;
+    const SpanDesc& d = spans[blockIdx.x];
+    const uint64_t nch = wv_cdiv(wv_cdiv(d.n, 64), SDW);
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint64_t run = 0;
+    for (uint64_t base = 0; base < nch; base += 256) {
+        const uint64_t i = base + threadIdx.x;
+        const uint32_t v = i < nch ? d.cnt[i] : 0u;
+        uint32_t wt;
+        const uint32_t ex = wave_excl_scan(v, &wt);
+        if (lane == 0) ws[wave] = wt;
+        __syncthreads();
+        uint32_t off = 0, tot = 0;
+        for (uint32_t k = 0; k < 4; k++) {
+            if (k < wave) off += ws[k];
+            tot += ws[k];
+        }
+        if (i < nch) d.pre[i] = run + off + ex;
+        run += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) total_s = run;
+    __syncthreads();
+    const uint64_t ones = total_s, zeros = d.n - ones, ns = wv_cdiv(d.n, WV_SB_BITS);
+    uint64_t* dir = (uint64_t*)(d.image + d.rank_off);
+    uint64_t* sel0 = (uint64_t*)(d.image + d.sel0_off);
+    uint64_t* sel1 = (uint64_t*)(d.image + d.sel1_off);
+    if (threadIdx.x == 0) {
+        dir[2 * ns] = zeros;
+        dir[2 * ns + 1] = 0;
+        uint64_t* desc = (uint64_t*)(d.image + WV_HEADER_BYTES + (uint64_t)WV_LEVEL_BYTES * d.level);
+        desc[1] = zeros;
+        desc[2] = ones;
+    }
+    for (uint64_t k = wv_cdiv(ones, WV_SEL_STRIDE) + threadIdx.x; k < d.nsel; k += 256) sel1[k] = d.n;
+    for (uint64_t k = wv_cdiv(zeros, WV_SEL_STRIDE) + threadIdx.x; k < d.nsel; k += 256) sel0[k] = d.n;
+}
+
+__global__ void __launch_bounds__(256)
+b_dir_write_k(const SpanDesc* __restrict__ spans, const uint32_t* __restrict__ chunk0, uint32_t nspan)
+{
+    __shared__ uint32_t wpart[4];
+    __shared__ uint64_t zex[SDW];
+    const uint32_t s = owner_of(chunk0, nspan, blockIdx.x);
+    const SpanDesc& d = spans[s];
+    const uint32_t c = blockIdx.x - d.chunk0;
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t n = d.n, nw = wv_cdiv(n, 64), ns = wv_cdiv(n, WV_SB_BITS);
+    const uint64_t* words = (const uint64_t*)(d.image + d.bits_off);
+    uint64_t* dir = (uint64_t*)(d.image + d.rank_off);
+    uint64_t* sel0 = (uint64_t*)(d.image + d.sel0_off);
+    uint64_t* sel1 = (uint64_t*)(d.image + d.sel1_off);
+    const uint64_t cw = (uint64_t)c * SDW, w0 = cw + 2 * threadIdx.x;
+    const uint64_t x0 = w0 < nw ? words[w0] : 0ull, x1 = w0 + 1 < nw ? words[w0 + 1] : 0ull;
+    const uint32_t o0 = __popcll(x0), o1 = __popcll(x1);
+    uint32_t tot;
+    const uint32_t ex = wave_excl_scan(o0 + o1, &tot);
+    if (lane == 0) wpart[wave] = tot;
+    __syncthreads();
+    uint32_t off = 0;
+    for (uint32_t k = 0; k < wave; k++) off += wpart[k];
+    const uint64_t ob0 = d.pre[c] + off + ex, ob1 = ob0 + o0;
+    const uint64_t z0 = min(64 * w0, n) - ob0, z1 = min(64 * (w0 + 1), n) - ob1;
+    zex[2 * threadIdx.x] = z0;
+    zex[2 * threadIdx.x + 1] = z1;
+    const uint64_t xs[2] = {x0, x1}, obs[2] = {ob0, ob1}, zbs[2] = {z0, z1};
+    const uint32_t os[2] = {o0, o1};
+    for (int qd = 0; qd < 2; qd++) {
+        const uint64_t w = w0 + qd;
+        if (w >= nw) break;
+        const uint64_t t1 = wv_cdiv(obs[qd], WV_SEL_STRIDE) * WV_SEL_STRIDE;
+        if (t1 < obs[qd] + os[qd]) sel1[t1 / WV_SEL_STRIDE] = 64 * w + wv_select_in_word(xs[qd], (uint32_t)(t1 - obs[qd]));
+        const uint64_t valid = min((uint64_t)64, n - 64 * w);
+        const uint64_t vm = valid >= 64 ? ~0ull : ((1ull << valid) - 1ull);
+        const uint32_t zc = (uint32_t)valid - os[qd];
+        const uint64_t t0 = wv_cdiv(zbs[qd], WV_SEL_STRIDE) * WV_SEL_STRIDE;
+        if (t0 < zbs[qd] + zc)
+            sel0[t0 / WV_SEL_STRIDE] = 64 * w + wv_select_in_word(~xs[qd] & vm, (uint32_t)(t0 - zbs[qd]));
+    }
+    __syncthreads();
+    if (threadIdx.x < SDW / 8) {
+        const uint64_t k = cw / 8 + threadIdx.x;
+        if (k < ns) {
+            const uint64_t zb = zex[8 * threadIdx.x];
+            uint64_t blk = 0;
+            for (uint32_t qd = 1; qd < 8; qd++) blk |= (zex[8 * threadIdx.x + qd] - zb) << (9 * (qd - 1));
+            dir[2 * k] = zb;
+            dir[2 * k + 1] = blk;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256)
+b_header_k(uint8_t* const* __restrict__ images, const wv_layout_in* __restrict__ lins)
+{
+    // same header writer as a single build, one workgroup per image
+    __shared__ wv_layout_out lay;
+    __shared__ uint64_t span_lo[4 * WV_MAX_LEVELS + 4], span_hi[4 * WV_MAX_LEVELS + 4];
+    __shared__ int nspan;
+    uint8_t* img = images[blockIdx.x];
+    const wv_layout_in& in = lins[blockIdx.x];
+    if (threadIdx.x == 0) {
+        wv_layout(in, lay);
+        int s = 0;
+        span_lo[s] = 0;
+        span_hi[s++] = WV_HEADER_BYTES + (uint64_t)WV_LEVEL_BYTES * in.nlevels;
+        for (uint32_t l = 0; l < in.nlevels; l++) {
+            const wv_level& L = lay.lv[l];
+            span_lo[s] = L.bits_off;  span_hi[s++] = L.bits_off + wv_bits_bytes(L.n);
+            span_lo[s] = L.rank_off;  span_hi[s++] = L.rank_off + wv_rank_bytes(L.n);
+            span_lo[s] = L.sel0_off;  span_hi[s++] = L.sel0_off + 8 * L.nsel;
+            span_lo[s] = L.sel1_off;  span_hi[s++] = L.sel1_off + 8 * L.nsel;
+        }
+        span_lo[s] = lay.image_bytes;
+        span_hi[s] = lay.image_bytes;
+        nspan = s;
+        uint32_t* h32 = (uint32_t*)img;
+        uint64_t* h64 = (uint64_t*)img;
+        h32[0] = WV_MAGIC; h32[1] = WV_VERSION; h32[2] = in.kind; h32[3] = in.arity_log2;
+        h64[2] = in.n; h32[6] = in.sigma; h32[7] = in.nlevels; h32[8] = in.key_bits; h32[9] = 0;
+        h64[5] = lay.image_bytes; h64[6] = WV_HEADER_BYTES; h64[7] = 0; h64[8] = 0; h64[9] = 0; h64[10] = 0;
+    }
+    __syncthreads();
+    for (uint32_t b = 88 + threadIdx.x; b < WV_HEADER_BYTES; b += blockDim.x) img[b] = 0;
+    if (threadIdx.x < in.nlevels) {
+        const wv_level& L = lay.lv[threadIdx.x];
+        uint64_t* e = (uint64_t*)(img + WV_HEADER_BYTES + (uint64_t)WV_LEVEL_BYTES * threadIdx.x);
+        e[0] = L.n; e[1] = 0; e[2] = 0; e[3] = L.bits_off; e[4] = L.rank_off; e[5] = L.sel0_off;
+        e[6] = L.sel1_off; e[7] = L.nsel;
+    }
+    for (int s = 0; s < nspan; s++)
+        for (uint64_t b = span_hi[s] + threadIdx.x; b < span_lo[s + 1]; b += blockDim.x) img[b] = 0;
+}
+
+__global__ void b_zero_k(uint32_t* p, uint64_t count)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+inline uint32_t width_of(uint32_t bits) { return bits <= 8 ? 1u : (bits <= 16 ? 2u : 4u); }
+
+// ---- host planning -----------------------------------------------------------------
+
+struct SeqPlan {
+    uint32_t L, tau, passes, K, C, sym_bytes, sigma;
+    uint64_t n;
+    uint64_t off_H, off_G0, off_pay[2], off_dcnt, off_dpre;
+    wv_layout_out lay;
+    wv_layout_in lin;
+};
+
+struct BatchPlan {
+    std::vector<SeqPlan> seq;
+    std::vector<uint32_t> order;     // sequences by decreasing n
+    uint64_t off_desc = 0, desc_bytes = 0, off_queue = 0, ws_bytes = 0;
+    uint64_t zero_lo = 0, zero_hi = 0;   // H region zeroed every round
+    uint32_t max_passes = 0;
+};
+
+int make_batch_plan(const wt_seq_desc* seqs, uint32_t count, const wt_tuning* tune, BatchPlan& bp)
+{
+    bp.seq.resize(count);
+    uint64_t off = 0;
+    auto bump = [&](uint64_t bytes) { uint64_t at = off; off = wv_round256(off + bytes); return at; };
+    bp.off_queue = bump(256);
+    uint64_t total_chunks = 0, total_spans = 0, total_dch = 0;
+    // H of every sequence first (zeroed by one fill every round)
+    for (uint32_t i = 0; i < count; i++) {
+        const wt_seq_desc& d = seqs[i];
+        wv_wm_plan wp;
+        int rc = wv_wm_make_plan(d.n, d.sigma, d.sym_bytes, tune, wp);
+        if (rc) return rc;
+        wt_plan_info info;
+        rc = wt_plan(WT_KIND_WM, d.n, d.sigma, d.sym_bytes, nullptr, tune, &info);
+        if (rc) return rc;
+        if (!d.S && d.n) return WT_EINVAL;
+        if (!d.out || d.out_bytes < info.out_bytes) return WT_ENOSPC;
+        SeqPlan& s = bp.seq[i];
+        s.L = wp.L; s.tau = wp.tau; s.K = wp.K; s.C = wp.C; s.n = d.n; s.sym_bytes = d.sym_bytes; s.sigma = d.sigma;
+        s.passes = d.n ? (s.L + s.tau - 1) / s.tau : 0;
+        bp.max_passes = std::max(bp.max_passes, s.passes);
+        s.off_H = bump((uint64_t)256 * s.K * 4);
+        total_chunks += s.K;
+    }
+    bp.zero_lo = bp.seq.empty() ? off : bp.seq[0].off_H;
+    bp.zero_hi = off;
+    for (uint32_t i = 0; i < count; i++) {
+        SeqPlan& s = bp.seq[i];
+        s.off_G0 = bump((uint64_t)s.K * MAXG * 4);
+        const uint32_t rem = s.L > s.tau ? s.L - s.tau : 0;
+        const uint64_t pay = rem ? std::max<uint64_t>(s.n, 1) * width_of(rem) : 0;
+        s.off_pay[0] = bump(pay);
+        s.off_pay[1] = bump(s.L > 2 * s.tau ? pay : 0);
+        const uint64_t dch = wv_cdiv(wv_cdiv(s.n, 64), SDW);
+        s.off_dcnt = bump(std::max<uint64_t>(dch, 1) * s.L * 4);
+        s.off_dpre = bump(std::max<uint64_t>(dch, 1) * s.L * 8);
+        total_spans += s.L;
+        total_dch += dch * s.L;
+        s.lin = wv_layout_in{};
+        s.lin.kind = WT_KIND_WM; s.lin.arity_log2 = 1; s.lin.nlevels = s.L; s.lin.key_bits = s.L;
+        s.lin.sigma = s.sigma; s.lin.n = s.n;
+        for (uint32_t l = 0; l < s.L; l++) s.lin.level_n[l] = s.n;
+        wv_layout(s.lin, s.lay);
+    }
+    // descriptor area: the largest of (round arrays, span arrays, headers)
+    const uint64_t round_bytes = count * (sizeof(SeqRound) + 4) + 256;
+    const uint64_t span_bytes = total_spans * (sizeof(SpanDesc) + 4) + 256;
+    const uint64_t head_bytes = count * (sizeof(wv_layout_in) + sizeof(uint8_t*)) + 256;
+    bp.desc_bytes = std::max(round_bytes, std::max(span_bytes, head_bytes));
+    bp.off_desc = bump(bp.desc_bytes);
+    bp.ws_bytes = off;
+    bp.order.resize(count);
+    std::iota(bp.order.begin(), bp.order.end(), 0u);
+    std::stable_sort(bp.order.begin(), bp.order.end(), [&](uint32_t a, uint32_t b) { return bp.seq[a].n > bp.seq[b].n; });
+    (void)total_chunks;
+    (void)total_dch;
+    return WT_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -7,29 +413,141 @@ int wt_batch_plan(int kind, const wt_seq_desc* seqs, uint32_t count, const wt_tu
                   uint64_t* workspace_bytes)
 {
     if (kind != WT_KIND_WM || (!seqs && count) || !workspace_bytes) return WT_EINVAL;
-    uint64_t ws = 0;
-    for (uint32_t i = 0; i < count; i++) {
-        wt_plan_info info;
-        int rc = wt_plan(WT_KIND_WM, seqs[i].n, seqs[i].sigma, seqs[i].sym_bytes, nullptr, tune, &info);
-        if (rc) return rc;
-        if (seqs[i].out_bytes < info.out_bytes) return WT_ENOSPC;
-        ws = info.workspace_bytes > ws ? info.workspace_bytes : ws;
-    }
-    *workspace_bytes = ws;
+    BatchPlan bp;
+    int rc = make_batch_plan(seqs, count, tune, bp);
+    if (rc) return rc;
+    *workspace_bytes = bp.ws_bytes;
     return WT_OK;
 }
 
-int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws, size_t ws_bytes,
+int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_, size_t ws_bytes,
                    const wt_tuning* tune, void* stream)
 {
-    uint64_t need = 0;
-    int rc = wt_batch_plan(kind, seqs, count, tune, &need);
+    if (kind != WT_KIND_WM || (!seqs && count)) return WT_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    BatchPlan bp;
+    int rc = make_batch_plan(seqs, count, tune, bp);
     if (rc) return rc;
-    if (ws_bytes < need) return WT_ENOSPC;
-    for (uint32_t i = 0; i < count; i++) {
-        rc = wm_build(seqs[i].S, seqs[i].n, seqs[i].sigma, seqs[i].sym_bytes, nullptr, tune, seqs[i].out,
-                      seqs[i].out_bytes, ws, ws_bytes, stream);
-        if (rc) return rc;
+    if (!count) return WT_OK;
+    if (!ws_ || ws_bytes < bp.ws_bytes) return WT_ENOSPC;
+    uint8_t* ws = (uint8_t*)ws_;
+    uint8_t* desc = ws + bp.off_desc;
+    uint32_t* queue = (uint32_t*)(ws + bp.off_queue);
+
+    // headers of every image
+    {
+        std::vector<uint8_t> host(bp.desc_bytes, 0);
+        uint8_t** imgs = (uint8_t**)host.data();
+        wv_layout_in* lins = (wv_layout_in*)(host.data() + wv_round256(count * sizeof(uint8_t*)));
+        for (uint32_t i = 0; i < count; i++) {
+            imgs[i] = (uint8_t*)seqs[i].out;
+            lins[i] = bp.seq[i].lin;
+        }
+        WV_CHECK(hipMemcpyAsync(desc, host.data(), bp.desc_bytes, hipMemcpyHostToDevice, s));
+        b_header_k<<<count, 256, 0, s>>>((uint8_t* const*)desc,
+                                         (const wv_layout_in*)(desc + wv_round256(count * sizeof(uint8_t*))));
+        WV_CHECK(hipGetLastError());
+        WV_CHECK(hipStreamSynchronize(s));
+    }
+
+    std::vector<const void*> cur_in(count);
+    std::vector<uint32_t> cur_bytes(count);
+    for (uint32_t i = 0; i < count; i++) { cur_in[i] = seqs[i].S; cur_bytes[i] = seqs[i].sym_bytes; }
+
+    for (uint32_t r = 0; r < bp.max_passes; r++) {
+        // two groups: keys up to 16 bits (16-bit LDS keys) and wider ones
+        for (int wide = 0; wide < 2; wide++) {
+            std::vector<uint8_t> host(bp.desc_bytes, 0);
+            std::vector<uint32_t> members;
+            for (uint32_t i : bp.order) {
+                const SeqPlan& sp = bp.seq[i];
+                if (r >= sp.passes) continue;
+                const uint32_t R = sp.L - r * sp.tau;
+                if ((R > 16) != (wide == 1)) continue;
+                members.push_back(i);
+            }
+            if (members.empty()) continue;
+            const uint32_t m = (uint32_t)members.size();
+            SeqRound* q = (SeqRound*)host.data();
+            uint32_t* first = (uint32_t*)(host.data() + wv_round256((uint64_t)m * sizeof(SeqRound)));
+            uint32_t chunks = 0;
+            for (uint32_t k = 0; k < m; k++) {
+                const uint32_t i = members[k];
+                const SeqPlan& sp = bp.seq[i];
+                const uint32_t l0 = r * sp.tau, tau = std::min(sp.tau, sp.L - l0), R = sp.L - l0, rem = R - tau;
+                SeqRound& e = q[k];
+                e.pa.in = cur_in[i];
+                e.pa.pay_out = rem ? (void*)(ws + sp.off_pay[r & 1]) : nullptr;
+                for (uint32_t j = 0; j < tau; j++) e.pa.words[j] = (uint64_t*)((uint8_t*)seqs[i].out + sp.lay.lv[l0 + j].bits_off);
+                e.pa.G0 = (const uint32_t*)(ws + sp.off_G0);
+                e.pa.n = (uint32_t)sp.n; e.pa.C = sp.C; e.pa.K = sp.K; e.pa.R = R; e.pa.tau = tau;
+                e.pa.keymask = r == 0 ? (sp.L >= 32 ? ~0u : ((1u << sp.L) - 1u)) : ~0u;
+                e.H = (uint32_t*)(ws + sp.off_H);
+                e.status = r == 0 ? (uint32_t*)((uint8_t*)seqs[i].out + 36) : nullptr;
+                e.in_bytes = cur_bytes[i];
+                e.out_bytes = rem ? width_of(rem) : 1;
+                e.sigma = sp.sigma;
+                e.chunk0 = chunks;
+                first[k] = chunks;
+                chunks += sp.K;
+            }
+            WV_CHECK(hipMemcpyAsync(desc, host.data(), bp.desc_bytes, hipMemcpyHostToDevice, s));
+            const SeqRound* dq = (const SeqRound*)desc;
+            const uint32_t* dfirst = (const uint32_t*)(desc + wv_round256((uint64_t)m * sizeof(SeqRound)));
+            const uint64_t hz = (bp.zero_hi - bp.zero_lo) / 4;
+            b_zero_k<<<(uint32_t)std::min<uint64_t>(wv_cdiv(hz, 256), 4096), 256, 0, s>>>((uint32_t*)(ws + bp.zero_lo), hz);
+            b_zero_k<<<1, 64, 0, s>>>(queue, 1);
+            b_hist_k<<<chunks * HSPLIT, HT, 0, s>>>(dq, dfirst, m);
+            b_offsets_k<<<m, HT, 0, s>>>(dq);
+            const uint32_t workers = std::min<uint32_t>(chunks, 512);
+            if (wide) b_pass_k<uint32_t><<<workers, NT, 0, s>>>(dq, dfirst, m, chunks, queue);
+            else b_pass_k<uint16_t><<<workers, NT, 0, s>>>(dq, dfirst, m, chunks, queue);
+            WV_CHECK(hipGetLastError());
+            // the descriptor area is rewritten next: wait for this group
+            WV_CHECK(hipStreamSynchronize(s));
+            for (uint32_t k = 0; k < m; k++) {
+                const uint32_t i = members[k];
+                if (q[k].pa.pay_out) { cur_in[i] = q[k].pa.pay_out; cur_bytes[i] = q[k].out_bytes; }
+            }
+        }
+    }
+
+    // directories of every level of every sequence
+    {
+        std::vector<uint8_t> host(bp.desc_bytes, 0);
+        uint32_t nspan = 0;
+        for (uint32_t i = 0; i < count; i++) nspan += bp.seq[i].L;
+        SpanDesc* sd = (SpanDesc*)host.data();
+        uint32_t* first = (uint32_t*)(host.data() + wv_round256((uint64_t)nspan * sizeof(SpanDesc)));
+        uint32_t k = 0, chunks = 0;
+        for (uint32_t i = 0; i < count; i++) {
+            const SeqPlan& sp = bp.seq[i];
+            const uint64_t dch = wv_cdiv(wv_cdiv(sp.n, 64), SDW);
+            for (uint32_t l = 0; l < sp.L; l++, k++) {
+                SpanDesc& d = sd[k];
+                d.image = (uint8_t*)seqs[i].out;
+                d.n = sp.n;
+                d.bits_off = sp.lay.lv[l].bits_off;
+                d.rank_off = sp.lay.lv[l].rank_off;
+                d.sel0_off = sp.lay.lv[l].sel0_off;
+                d.sel1_off = sp.lay.lv[l].sel1_off;
+                d.nsel = sp.lay.lv[l].nsel;
+                d.cnt = (uint32_t*)(ws + sp.off_dcnt) + l * std::max<uint64_t>(dch, 1);
+                d.pre = (uint64_t*)(ws + sp.off_dpre) + l * std::max<uint64_t>(dch, 1);
+                d.level = l;
+                d.chunk0 = chunks;
+                first[k] = chunks;
+                chunks += (uint32_t)dch;
+            }
+        }
+        WV_CHECK(hipMemcpyAsync(desc, host.data(), bp.desc_bytes, hipMemcpyHostToDevice, s));
+        const SpanDesc* dsd = (const SpanDesc*)desc;
+        const uint32_t* dfirst = (const uint32_t*)(desc + wv_round256((uint64_t)nspan * sizeof(SpanDesc)));
+        if (chunks) b_dir_count_k<<<chunks, 256, 0, s>>>(dsd, dfirst, nspan);
+        b_dir_scan_k<<<nspan, 256, 0, s>>>(dsd);
+        if (chunks) b_dir_write_k<<<chunks, 256, 0, s>>>(dsd, dfirst, nspan);
+        WV_CHECK(hipGetLastError());
+        WV_CHECK(hipStreamSynchronize(s));
     }
     return WT_OK;
 }

@@ -1,0 +1,437 @@
+// wv_wm_core.h -- device code of the wavelet-matrix partition passes, shared
+// by the single build (wv_wm_passes.hip) and the batched build
+// (wv_batch.hip).  See wv_wm_passes.hip for the method.
+#pragma once
+
+#include "wv_internal.h"
+
+namespace {
+
+constexpr int NT = 512;             // threads of a pass workgroup
+constexpr int NWAVE = NT / 64;
+constexpr int E = 32;               // elements per thread per tile
+constexpr int T = NT * E;           // tile
+constexpr int TW = T / 64;          // bit words per tile level
+constexpr int MAXG = 511;           // run groups of sub-levels j = 0..8
+constexpr int HT = 256;             // histogram / scan threads
+constexpr uint32_t KMAX = 512;      // chunks (all resident: 2 per CU)
+
+
+__device__ __host__ inline uint32_t gidx(uint32_t j, uint32_t u) { return (1u << j) - 1u + u; }
+
+__device__ inline uint32_t brev(uint32_t v, uint32_t nbits) { return nbits ? (__brev(v) >> (32 - nbits)) : 0u; }
+
+struct PassArgs {
+    const void* in;
+    void* pay_out;
+    uint64_t* words[8];     // bit arrays of levels a*tau + j
+    const uint32_t* G0;     // [K][MAXG] first run offset of every chunk
+    uint32_t n, C, K;       // elements, chunk length (multiple of T), chunks
+    uint32_t R, tau;        // key bits still to do, digit bits of this pass
+    uint32_t keymask;       // applied to the loaded keys
+};
+
+template <typename T_>
+__device__ inline uint32_t ld(const void* p, uint64_t i) { return (uint32_t)((const T_*)p)[i]; }
+
+// 64 bits of the tile bit string starting at bit `src`, keeping `nb` (1..64)
+__device__ inline uint64_t extract(const uint64_t* lb, uint32_t src, uint32_t nb)
+{
+    const uint32_t w = src >> 6, o = src & 63;
+    uint64_t v = lb[w] >> o;
+    if (o && o + nb > 64) v |= lb[w + 1] << (64 - o);
+    return nb >= 64 ? v : (v & ((1ull << nb) - 1ull));
+}
+
+__device__ inline uint64_t lanemask_lt()
+{
+    const uint32_t lane = threadIdx.x & 63;
+    return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+// exclusive scan of up to 64 values held by one wave (lane l holds v)
+__device__ inline uint32_t wave_excl_scan(uint32_t v, uint32_t* total)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    uint32_t inc = v;
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(inc, d, 64);
+        if (lane >= (uint32_t)d) inc += t;
+    }
+    *total = __shfl(inc, 63, 64);
+    return inc - v;
+}
+
+template <typename IT, typename KT_>
+__device__ inline void load_tile(const void* in, uint32_t ts, uint32_t tc, uint32_t keymask, KT_* buf)
+{
+    // 16-byte loads; tile starts are multiples of the tile, so aligned
+    constexpr uint32_t V = 16 / sizeof(IT);
+    const uint32_t nv = tc / V;
+    const uint4* src = (const uint4*)((const IT*)in + ts);
+    for (uint32_t v = threadIdx.x; v < nv; v += NT) {
+        const uint4 q = src[v];
+        const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
+        for (uint32_t k = 0; k < V; k++) {
+            const uint32_t x = (sizeof(IT) == 4) ? wd[k]
+                             : (sizeof(IT) == 2) ? ((wd[k / 2] >> (16 * (k & 1))) & 0xFFFFu)
+                                                 : ((wd[k / 4] >> (8 * (k & 3))) & 0xFFu);
+            buf[v * V + k] = (KT_)(x & keymask);
+        }
+    }
+    for (uint32_t p = nv * V + threadIdx.x; p < tc; p += NT) buf[p] = (KT_)(ld<IT>(in, (uint64_t)ts + p) & keymask);
+}
+
+// zeros among the first s bits of the tile bit string (s <= tile length)
+__device__ inline uint32_t local_rank0(const uint64_t* lb, const uint32_t* zw, uint32_t s)
+{
+    const uint32_t w = s >> 6, o = s & 63;
+    uint32_t z = zw[w];
+    if (o) z += o - __popcll(lb[w] & ((1ull << o) - 1ull));
+    return z;
+}
+
+// LDS of one pass workgroup; KT_ holds the keys (16 bits when at most 16
+// key bits remain)
+template <typename KT_>
+struct PassShared {
+    KT_ buf[T];
+    uint64_t lb[TW + 1];
+    uint32_t zw[TW + 1];
+    uint32_t cnt[MAXG], ls[MAXG], g[MAXG], fw[MAXG];
+    uint64_t carry[2][255];
+    uint32_t sp[129];
+};
+
+// One chunk b of one pass (see the file comment of wv_wm_passes.hip).
+template <typename IT, typename OT, typename KT_>
+__device__ void wm_pass_chunk(const PassArgs& a, uint32_t b, PassShared<KT_>& S)
+{
+    KT_* buf = S.buf;
+    uint64_t* lb = S.lb;
+    uint32_t* zw = S.zw;
+    uint32_t *cnt = S.cnt, *ls = S.ls, *g = S.g, *fw = S.fw;
+    uint64_t (*carry)[255] = S.carry;
+    uint32_t* sp = S.sp;
+
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t tau = a.tau, R = a.R;
+    const uint32_t ngroups = (2u << tau) - 1u;         // j = 0..tau
+    const uint32_t cstart = b * a.C;
+    const uint32_t cend = min(a.n, cstart + a.C);
+    const uint32_t dshift = R - tau;
+    const uint32_t dmask = (1u << tau) - 1u;
+    const uint32_t pmask = dshift >= 32 ? ~0u : ((1u << dshift) - 1u);
+
+    for (uint32_t i = tid; i < ngroups; i += NT) {
+        const uint32_t g0 = a.G0[(uint64_t)b * MAXG + i];
+        g[i] = g0;
+        fw[i] = (g0 & 63u) ? (g0 >> 6) : 0xFFFFFFFFu;
+        if (i < 255) carry[0][i] = 0;
+    }
+    if (tid == 0) lb[TW] = 0;
+    uint32_t cpar = 0;   // carry buffer read this tile
+
+    for (uint32_t ts = cstart; ts < cend; ts += T) {
+        const uint32_t tc = min((uint32_t)T, cend - ts);
+        load_tile<IT, KT_>(a.in, ts, tc, a.keymask, buf);
+        if (tid == 0) { cnt[0] = tc; ls[0] = 0; }
+        __syncthreads();
+
+        for (uint32_t j = 0; j < tau; j++) {
+            // phase 1: bit j of every element, in the order of sub-level j
+            uint32_t xs[E];
+            const uint32_t sh = R - 1 - j;
+            for (int e = 0; e < E; e++) {
+                const uint32_t p = tid + NT * e;
+                xs[e] = p < tc ? (uint32_t)buf[p] : 0u;
+            }
+            for (int e = 0; e < E; e++) {
+                const uint32_t p = tid + NT * e;
+                const uint64_t ball = __ballot(p < tc && ((xs[e] >> sh) & 1u));
+                if (lane == 0) {
+                    const uint32_t wi = e * NWAVE + wave;
+                    lb[wi] = ball;
+                    const uint32_t base = wi * 64;
+                    zw[wi] = (base >= tc ? 0u : min(64u, tc - base)) - __popcll(ball);
+                }
+            }
+            const uint32_t nk = 1u << j;
+            const uint32_t gb = gidx(j, 0);
+            __syncthreads();
+            // phase 2: zero prefix over the words (wave 0), run slots (wave 1)
+            if (wave == 0) {
+                uint32_t v[TW / 64];
+                for (uint32_t k = 0; k < TW / 64; k++) v[k] = zw[64 * k + lane];
+                uint32_t run = 0;
+                for (uint32_t k = 0; k < TW / 64; k++) {
+                    uint32_t tot;
+                    const uint32_t ex = wave_excl_scan(v[k], &tot);
+                    zw[64 * k + lane] = run + ex;
+                    run += tot;
+                }
+                if (lane == 0) zw[TW] = run;
+            } else if (wave == 1) {
+                uint32_t run = 0;
+                for (uint32_t u0 = 0; u0 < nk; u0 += 64) {
+                    const uint32_t u = u0 + lane;
+                    uint32_t v = 0;
+                    if (u < nk) {
+                        const uint32_t gg = g[gb + u];
+                        v = ((gg + cnt[gb + u]) >> 6) - (gg >> 6);
+                    }
+                    uint32_t tot;
+                    const uint32_t ex = wave_excl_scan(v, &tot);
+                    if (u < nk) sp[u] = run + ex;
+                    run += tot;
+                }
+                if (lane == 0) sp[nk] = run;
+            }
+            __syncthreads();
+            // phase 3: partition, child runs, emit words
+            const uint32_t ztot = zw[TW];
+            const uint64_t ltm = lanemask_lt();
+            for (int e0 = 0; e0 < E; e0 += 8) {
+                // eight words' ballots and zero prefixes first, then the moves
+                uint64_t balls[8];
+                uint32_t zws[8];
+                for (int k = 0; k < 8; k++) {
+                    const uint32_t wi = (e0 + k) * NWAVE + wave;
+                    balls[k] = lb[wi];
+                    zws[k] = zw[wi];
+                }
+                for (int k = 0; k < 8; k++) {
+                    const uint32_t p = tid + NT * (e0 + k);
+                    if (p < tc) {
+                        const uint32_t zb = zws[k] + (lane - __popcll(balls[k] & ltm));
+                        const uint32_t bit = (uint32_t)((balls[k] >> lane) & 1ull);
+                        buf[bit ? ztot + (p - zb) : zb] = (KT_)xs[e0 + k];
+                    }
+                }
+            }
+            // runs of sub-level j+1 split the runs of j by bit j; a child's
+            // elements keep their order, zeros of the tile first
+            const uint32_t gc = gidx(j + 1, 0);
+            uint64_t* words = a.words[j];
+            for (uint32_t u = tid; u < nk; u += NT) {
+                const uint32_t s0 = ls[gb + u], c = cnt[gb + u];
+                const uint32_t zs = local_rank0(lb, zw, s0), ze = local_rank0(lb, zw, s0 + c);
+                cnt[gc + 2 * u] = ze - zs;
+                cnt[gc + 2 * u + 1] = c - (ze - zs);
+                ls[gc + 2 * u] = zs;
+                ls[gc + 2 * u + 1] = ztot + (s0 - zs);
+                // the partial last word of the run, carried to the next tile
+                const uint32_t gi = gb + u;
+                const uint32_t gg = g[gi], en = gg + c;
+                uint64_t v = 0;
+                if (en & 63u) {
+                    const uint32_t We = en >> 6;
+                    const uint32_t wlo = max(We * 64u, gg);
+                    const uint32_t nb = en - wlo;
+                    if (nb) v = extract(lb, s0 + (wlo - gg), nb) << (wlo - We * 64u);
+                    if (We == (gg >> 6)) v |= carry[cpar][gi];
+                }
+                carry[cpar ^ 1][gi] = v;
+            }
+            const uint32_t total = sp[nk];
+            for (uint32_t s = tid; s < total; s += NT) {
+                uint32_t lo = 0, hi = nk - 1;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi + 1) >> 1;
+                    if (sp[mid] <= s) lo = mid; else hi = mid - 1;
+                }
+                const uint32_t gi = gb + lo;
+                const uint32_t i = s - sp[lo];
+                const uint32_t gg = g[gi];
+                const uint32_t W = (gg >> 6) + i;
+                const uint32_t wlo = max(W * 64u, gg);
+                const uint32_t nb = W * 64u + 64u - wlo;
+                uint64_t v = extract(lb, ls[gi] + (wlo - gg), nb) << (wlo - W * 64u);
+                if (i == 0) v |= carry[cpar][gi];
+                if (W == fw[gi]) atomicOr((unsigned long long*)&words[W], (unsigned long long)v);
+                else words[W] = v;
+            }
+            __syncthreads();
+        }
+        // remaining key bits to the order of the next pass
+        if (a.pay_out) {
+            for (int e = 0; e < E; e++) {
+                const uint32_t p = tid + NT * e;
+                if (p < tc) {
+                    const uint32_t x = buf[p];
+                    const uint32_t gi = gidx(tau, (x >> dshift) & dmask);
+                    ((OT*)a.pay_out)[g[gi] + (p - ls[gi])] = (OT)(x & pmask);
+                }
+            }
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < ngroups; i += NT) g[i] += cnt[i];
+        cpar ^= 1;
+        __syncthreads();
+    }
+    // flush the partial words left at the end of the chunk
+    for (uint32_t i = tid; i < (1u << tau) - 1u; i += NT) {
+        const uint32_t j = 31 - __clz(i + 1);
+        if ((g[i] & 63u) && carry[cpar][i])
+            atomicOr((unsigned long long*)&a.words[j][g[i] >> 6], (unsigned long long)carry[cpar][i]);
+    }
+}
+
+constexpr uint32_t HSPLIT = 8;       // histogram workgroups per chunk
+constexpr uint32_t HUNROLL = 4;      // 16-byte loads in flight per thread
+
+__device__ inline uint32_t sym_of(const uint32_t* wds, uint32_t k, uint32_t size)
+{
+    return size == 4 ? wds[k] : (size == 2 ? ((wds[k / 2] >> (16 * (k & 1))) & 0xFFFFu)
+                                           : ((wds[k / 4] >> (8 * (k & 3))) & 0xFFu));
+}
+
+// per-chunk histogram of the pass digit (first pass: also validates S);
+// HSPLIT workgroups share a chunk and add their counts into H
+template <typename IT>
+__device__ void wm_hist_part(const void* __restrict__ in, uint32_t n, uint32_t C, uint32_t K, uint32_t R,
+                             uint32_t tau, uint32_t keymask, uint32_t* __restrict__ H,
+                             uint32_t* __restrict__ status, uint32_t sigma, uint32_t b, uint32_t part,
+                             uint32_t (*h)[256])
+{
+    const uint32_t wave = threadIdx.x >> 6;
+    const uint32_t cs = b * C, ce = min(n, cs + C);
+    const uint32_t dshift = R - tau, dmask = (1u << tau) - 1u;
+    for (uint32_t i = threadIdx.x; i < (HT / 64) * 256; i += HT) (&h[0][0])[i] = 0;
+    __syncthreads();
+    bool bad = false;
+    constexpr uint32_t V = 16 / sizeof(IT);
+    // the chunk's 16-byte vectors (chunk starts are tile multiples, so
+    // aligned), split evenly over the HSPLIT workgroups
+    const uint32_t nvec = (ce - cs) / V;
+    const uint32_t per = (nvec + HSPLIT - 1) / HSPLIT;
+    const uint32_t vs = cs / V + part * per;
+    const uint32_t ve = cs / V + min(nvec, (part + 1) * per);
+    const uint4* in4 = (const uint4*)in;
+    for (uint32_t v0 = vs + threadIdx.x; v0 < ve; v0 += HT * HUNROLL) {
+        uint4 q[HUNROLL];
+        for (uint32_t u = 0; u < HUNROLL; u++) {
+            const uint32_t v = v0 + u * HT;
+            q[u] = v < ve ? in4[v] : make_uint4(0, 0, 0, 0);
+        }
+        for (uint32_t u = 0; u < HUNROLL; u++) {
+            if (v0 + u * HT >= ve) break;
+            const uint32_t wds[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
+            // runs of equal digits (common once the sequence is grouped by
+            // its leading bits) are added at once
+            uint32_t cur = ((sym_of(wds, 0, sizeof(IT)) & keymask) >> dshift) & dmask, run = 0;
+            for (uint32_t k = 0; k < V; k++) {
+                const uint32_t x = sym_of(wds, k, sizeof(IT));
+                bad |= x >= sigma;
+                const uint32_t d = ((x & keymask) >> dshift) & dmask;
+                if (d != cur) {
+                    atomicAdd(&h[wave][cur], run);
+                    cur = d;
+                    run = 0;
+                }
+                run++;
+            }
+            atomicAdd(&h[wave][cur], run);
+        }
+    }
+    if (part == HSPLIT - 1) {
+        for (uint32_t i = cs + nvec * V + threadIdx.x; i < ce; i += HT) {
+            const uint32_t x = ld<IT>(in, i);
+            bad |= x >= sigma;
+            atomicAdd(&h[wave][((x & keymask) >> dshift) & dmask], 1u);
+        }
+    }
+    if (status && __ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(status, 1u);
+    __syncthreads();
+    if (threadIdx.x <= dmask) {
+        uint32_t c = 0;
+        for (uint32_t w = 0; w < HT / 64; w++) c += h[w][threadIdx.x];
+        if (c) atomicAdd(&H[(uint64_t)threadIdx.x * K + b], c);
+    }
+}
+
+// exclusive prefix of every digit's counts over the chunks (in place)
+__global__ void __launch_bounds__(HT)
+wm_scan_chunks_k(uint32_t* __restrict__ H, uint32_t K, uint32_t* __restrict__ totals)
+{
+    __shared__ uint32_t ws[HT / 64];
+    const uint32_t d = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t* h = H + (uint64_t)d * K;
+    uint32_t run = 0;
+    for (uint32_t base = 0; base < K; base += HT) {
+        const uint32_t i = base + threadIdx.x;
+        const uint32_t v = i < K ? h[i] : 0u;
+        uint32_t wt;
+        const uint32_t ex = wave_excl_scan(v, &wt);
+        if (lane == 0) ws[wave] = wt;
+        __syncthreads();
+        uint32_t off = 0, tot = 0;
+        for (uint32_t w = 0; w < HT / 64; w++) {
+            if (w < wave) off += ws[w];
+            tot += ws[w];
+        }
+        if (i < K) h[i] = run + off + ex;
+        run += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) totals[d] = run;
+}
+
+// every chunk's first offset of every run, and zero the boundary words
+struct OffArgs {
+    const uint32_t* PH;
+    const uint32_t* totals;
+    uint32_t* G0;
+    uint64_t* words[8];
+    uint32_t K, tau, n;
+};
+
+__global__ void __launch_bounds__(HT)
+wm_offsets_k(OffArgs a)
+{
+    __shared__ uint32_t ph[256], tot[256];
+    __shared__ uint32_t cj[MAXG], tj[MAXG], bs[MAXG];
+    const uint32_t b = blockIdx.x, tau = a.tau;
+    const uint32_t nd = 1u << tau, ngroups = (2u << tau) - 1u;
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x < nd) {
+        ph[threadIdx.x] = a.PH[(uint64_t)threadIdx.x * a.K + b];
+        tot[threadIdx.x] = a.totals[threadIdx.x];
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < ngroups; i += HT) {
+        const uint32_t j = 31 - __clz(i + 1);
+        const uint32_t u = i + 1 - (1u << j);
+        const uint32_t span = 1u << (tau - j);
+        uint32_t s1 = 0, s2 = 0;
+        for (uint32_t d = u * span; d < (u + 1) * span; d++) { s1 += ph[d]; s2 += tot[d]; }
+        cj[i] = s1;
+        tj[i] = s2;
+    }
+    __syncthreads();
+    // start of every key's run on its level: keys in bit-reversed order
+    for (uint32_t j = wave; j <= tau; j += HT / 64) {
+        const uint32_t nk = 1u << j;
+        uint32_t run = 0;
+        for (uint32_t r0 = 0; r0 < nk; r0 += 64) {
+            const uint32_t r = r0 + lane;
+            const uint32_t u = r < nk ? brev(r, j) : 0;
+            const uint32_t v = r < nk ? tj[gidx(j, u)] : 0;
+            uint32_t t;
+            const uint32_t ex = wave_excl_scan(v, &t);
+            if (r < nk) bs[gidx(j, u)] = run + ex;
+            run += t;
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < ngroups; i += HT) {
+        const uint32_t g0 = bs[i] + cj[i];
+        a.G0[(uint64_t)b * MAXG + i] = g0;
+        const uint32_t j = 31 - __clz(i + 1);
+        if (j < tau && (g0 & 63u) && g0 < a.n) a.words[j][g0 >> 6] = 0;
+    }
+    if (b == 0 && threadIdx.x < tau && (a.n & 63u)) a.words[threadIdx.x][(a.n - 1) >> 6] = 0;
+}
+
+
+}  // namespace

@@ -1,0 +1,71 @@
+"""Batched builds: every image equals the oracle's (small varied mix) and
+the image wm_build writes for that sequence alone (the configuration's own
+size mix)."""
+import numpy as np
+import pytest
+
+from gpu_util import assert_same, oracle_image, to_device
+from paper_1610_03524_amd import binding as B
+from paper_1610_03524_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def run_batch(seqs, tune=None):
+    """seqs: list of (numpy S, sigma); returns list of images (numpy)"""
+    import torch
+    dev = [to_device(S) for S, _ in seqs]
+    outs, descs = [], []
+    for (S, sigma), St in zip(seqs, dev):
+        info = B.plan(B.KIND_WM, S.size, sigma, S.itemsize, tune=tune)
+        out = torch.empty(info.out_bytes, dtype=torch.uint8, device="cuda")
+        d = B.wt_seq_desc()
+        d.S, d.n, d.sigma, d.sym_bytes = St.data_ptr(), S.size, sigma, S.itemsize
+        d.out, d.out_bytes = out.data_ptr(), info.out_bytes
+        outs.append(out)
+        descs.append(d)
+    need = B.batch_plan(B.KIND_WM, descs, tune)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device="cuda")
+    rc = B.batch_build(B.KIND_WM, descs, ws, tune)
+    assert rc == B.WT_OK, B.strerror(rc)
+    torch.cuda.synchronize()
+    for o in outs:
+        assert B.check(o) == B.WT_OK
+    return [o.cpu().numpy() for o in outs]
+
+
+def test_batch_matches_oracle_on_mixed_sizes():
+    rng = np.random.default_rng(44)
+    seqs = []
+    for k in range(80):
+        n = int(2 ** rng.uniform(0, 16)) if k > 2 else [0, 1, 64][k]
+        sigma = max(1, int(2 ** rng.uniform(0, 20)))
+        dt = np.uint8 if sigma <= 256 else (np.uint16 if sigma <= 65536 else np.uint32)
+        if k % 7 == 3:   # wider storage than needed
+            dt = np.uint32
+        seqs.append((rng.integers(0, sigma, n).astype(dt), sigma))
+    imgs = run_batch(seqs)
+    for k, ((S, sigma), g) in enumerate(zip(seqs, imgs)):
+        assert_same(g, oracle_image(B.KIND_WM, S, sigma), f"seq {k} n={S.size} sigma={sigma}")
+
+
+def test_batch_equals_single_builds_on_c4_prefix():
+    import torch
+    seqs = list(inputs.c4_batch(limit=48))
+    imgs = run_batch(seqs)
+    for k, ((S, sigma), g) in enumerate(zip(seqs, imgs)):
+        one, _ = B.build(B.KIND_WM, to_device(S), sigma)
+        torch.cuda.synchronize()
+        assert_same(g, one.cpu().numpy(), f"c4 seq {k} n={S.size} sigma={sigma}")
+
+
+def test_batch_rejects_small_output():
+    import torch
+    S = to_device(np.arange(1000, dtype=np.uint16))
+    d = B.wt_seq_desc()
+    d.S, d.n, d.sigma, d.sym_bytes = S.data_ptr(), 1000, 1000, 2
+    out = torch.empty(10, dtype=torch.uint8, device="cuda")
+    d.out, d.out_bytes = out.data_ptr(), 10
+    with pytest.raises(B.WaveletError) as e:
+        B.batch_plan(B.KIND_WM, [d])
+    assert e.value.code == B.WT_ENOSPC
