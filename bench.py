@@ -7,7 +7,9 @@ level).  One step = one complete wm_build (every level bitvector, every rank
 directory, every select sample, the image header) from the input already in
 HBM.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--copy-calibration]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py --workload c1|c3h|c3m|c4     (the other configurations)
+    python bench.py --copy-calibration           (1 GiB copy for PMC scaling)
 """
 from __future__ import annotations
 
@@ -125,6 +127,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3h", "c3m", "c4"])
+    ap.add_argument("--limit", type=int, default=8192, help="c4: number of sequences")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU form of this "
@@ -132,6 +136,12 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.steps)
+        return
+    if args.workload in ("c1", "c3h", "c3m"):
+        bench_tree(args)
+        return
+    if args.workload == "c4":
+        bench_batch(args)
         return
 
     import torch
@@ -202,6 +212,172 @@ def main():
 
 def info_passes(info):
     return -(-info.nlevels // info.tau)
+
+
+def tree_kernel_bytes(name, info, sym_bytes, kind):
+    """compulsory bytes of all launches of one level-by-level kernel in a build
+    (keys are 4-byte symbols after level 0; trees also carry 4-byte node ids)"""
+    D = info.arity_log2 if kind == 4 else 1
+    total = 0
+    for l in range(info.nlevels):
+        m = int(info.level_n[l])
+        w = sym_bytes if l == 0 else 4
+        bits = m * D / 8
+        if name == "lw_emit":
+            total += m * w + bits
+        elif name == "lw_directory":
+            total += bits * 2 + (m / 32 if kind != 4 else m * D / 8 * 0.19)
+        elif name == "lw_scatter" and l + 1 < info.nlevels:
+            node = 0 if l == 0 else 4
+            total += m * (w + node) + bits + int(info.level_n[l + 1]) * 8
+    return total
+
+
+def bench_tree(args):
+    """C1 (balanced tree, 2^20 uint8, sigma 256), C3 Huffman-shaped (2^26
+    uint16, sigma 4096, geometric 0.01) or C3 4-ary tree"""
+    import torch
+    from paper_1610_03524_amd import binding as B
+    from paper_1610_03524_amd import inputs
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    if args.workload == "c1":
+        Sn = inputs.c1_uniform()
+        sigma, kind, D, name = 256, B.KIND_WT, 0, "C1 balanced wavelet tree: n=2^20 uint8, sigma=256, uniform"
+        St = torch.from_numpy(Sn).to(dev)
+    else:
+        Sn = inputs.c3_geometric()
+        sigma = 4096
+        St = torch.from_numpy(Sn.view(np.int16)).to(dev)
+        if args.workload == "c3h":
+            kind, D, name = B.KIND_SHAPED, 0, "C3 Huffman-shaped wavelet tree: n=2^26 uint16, sigma=4096, geometric(0.01)"
+        else:
+            kind, D, name = B.KIND_MULTIARY, 2, "C3 4-ary wavelet tree: n=2^26 uint16, sigma=4096, geometric(0.01)"
+    n, sym = Sn.size, Sn.itemsize
+    codes = lens = counts = None
+    if kind == B.KIND_SHAPED:
+        counts = B.symbol_counts(St, sigma).cpu().numpy().astype(np.uint64)
+        codes, lens = B.huffman_codes(counts)
+    tune = B.make_tuning(flags=B.FLAG_PROFILE)
+    shape = B.make_shape(D, codes, lens, counts) if (D or codes is not None) else None
+    info = B.plan(kind, n, sigma, sym, shape, tune)
+    out = torch.empty(info.out_bytes, dtype=torch.uint8, device=dev)
+    ws = torch.empty(info.workspace_bytes, dtype=torch.uint8, device=dev)
+
+    def build_once():
+        rc = B.build_into(kind, St, sigma, out, ws, shape, tune, stream)
+        if rc != 0:
+            raise RuntimeError(B.strerror(rc))
+
+    for _ in range(args.warmup):
+        build_once()
+    torch.cuda.synchronize()
+    B.profile_read()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        build_once()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    prof = B.profile_read()
+    dom = max((k for k in prof if k.startswith("lw_")), key=lambda k: prof[k][1])
+    dom_ms = prof[dom][1] / prof[dom][0]
+    dom_bytes = tree_kernel_bytes(dom, info, sym, kind) / (prof[dom][0] / args.steps)
+    balg = algorithmic_bytes(info, n, sym)
+    t = ms / 1e3
+    print(json.dumps({
+        "metric": METRIC, "value": round(n * sym / t / 1e9, 3), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u16" if sym == 2 else "u8", "data": "synthetic",
+        "config": {"workload": name, "n": n, "sigma": sigma, "levels": info.nlevels,
+                   "path": "level-by-level (host-synchronizing node table)"},
+        "symbol_levels_per_s": round(symbol_levels(info) / t, 1),
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(dom_bytes / (dom_ms / 1e3) / 1e9, 2),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(dom_bytes / (dom_ms / 1e3) / 1e9 / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "alg_bytes_per_launch": int(dom_bytes), "avg_launch_ms": round(dom_ms, 4)},
+        "build_roofline": {"alg_bytes": balg, "achieved": round(balg / t / 1e9, 2),
+                           "frac": round(balg / t / 1e9 / HBM_PEAK_GBPS, 4)},
+        "kernel_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in sorted(prof.items())},
+    }), flush=True)
+
+
+def bench_batch(args):
+    """C4: wavelet matrices of 8192 uint32 sequences (n log-uniform in
+    [2^10, 2^22], sigma log-uniform in [4, 2^20]); one batched build against a
+    loop of per-sequence wm_build calls on one stream"""
+    import torch
+    from paper_1610_03524_amd import binding as B
+    from paper_1610_03524_amd import inputs, tune as T
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    ns, sig, children = inputs.c4_sizes()
+    k = min(args.limit, len(ns))
+    ns, sig = ns[:k], sig[:k]
+    offs = np.concatenate([[0], np.cumsum(ns)])
+    total = int(offs[-1])
+    t_gen = time.perf_counter()
+    big = torch.empty(total, dtype=torch.int32, device=dev)
+    for i in range(k):
+        S = inputs.c4_sequence(int(ns[i]), int(sig[i]), children[i])
+        big[int(offs[i]):int(offs[i + 1])].copy_(torch.from_numpy(S.view(np.int32)), non_blocking=False)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    infos = [B.plan(B.KIND_WM, int(ns[i]), int(sig[i]), 4) for i in range(k)]
+    out_off = np.concatenate([[0], np.cumsum([(inf.out_bytes + 255) // 256 * 256 for inf in infos])])
+    images = torch.empty(int(out_off[-1]), dtype=torch.uint8, device=dev)
+    descs = []
+    for i in range(k):
+        d = B.wt_seq_desc()
+        d.S = big.data_ptr() + 4 * int(offs[i])
+        d.n, d.sigma, d.sym_bytes = int(ns[i]), int(sig[i]), 4
+        d.out, d.out_bytes = images.data_ptr() + int(out_off[i]), infos[i].out_bytes
+        d.tau = T.choose_tau(int(ns[i]), int(sig[i]))
+        descs.append(d)
+    need = B.batch_plan(B.KIND_WM, descs)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    single_ws = torch.empty(max(inf.workspace_bytes for inf in infos), dtype=torch.uint8, device=dev)
+
+    def batched():
+        rc = B.batch_build(B.KIND_WM, descs, ws, stream=stream)
+        if rc != 0:
+            raise RuntimeError(B.strerror(rc))
+
+    lib = B.lib()
+
+    tunings = [B.make_tuning(tau=d.tau) for d in descs]
+    import ctypes
+
+    def plain():
+        for d, tn in zip(descs, tunings):
+            rc = lib.wm_build(d.S, d.n, d.sigma, 4, None, ctypes.byref(tn), d.out, d.out_bytes,
+                              single_ws.data_ptr(), single_ws.numel(), B._stream(stream))
+            if rc != 0:
+                raise RuntimeError(B.strerror(rc))
+
+    res = {}
+    for name, fn in (("batched", batched), ("plain", plain)):
+        fn()
+        torch.cuda.synchronize()
+        reps = max(1, args.steps // 5)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0) / reps
+    balg = sum(4 * int(ns[i]) + infos[i].out_bytes for i in range(k))
+    tb, tp = res["batched"], res["plain"]
+    print(json.dumps({
+        "metric": METRIC, "value": round(total * 4 / tb / 1e9, 3), "unit": "GB/s", "n_gpus": 1,
+        "steps": max(1, args.steps // 5), "warmup": 1, "ms_per_step": round(tb * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"C4 batched wavelet matrices: {k} uint32 sequences, n log-uniform [2^10, 2^22], "
+                               f"sigma log-uniform [4, 2^20]", "symbols": total},
+        "batched": {"s": round(tb, 4), "builds_per_s": round(k / tb, 1), "input_GBps": round(total * 4 / tb / 1e9, 2),
+                    "build_roofline_frac": round(balg / tb / 1e9 / HBM_PEAK_GBPS, 4)},
+        "plain": {"s": round(tp, 4), "builds_per_s": round(k / tp, 1), "input_GBps": round(total * 4 / tp / 1e9, 2)},
+        "speedup_batched_vs_plain": round(tp / tb, 3),
+        "input_generation_s": round(t_gen, 1),
+    }), flush=True)
 
 
 if __name__ == "__main__":

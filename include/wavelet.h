@@ -186,7 +186,9 @@ int wt_symbol_counts(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sig
  * exceeds 32. */
 int wt_huffman_codes(const uint64_t* counts, uint32_t sigma, uint64_t* codes, uint32_t* code_len);
 
-/* One sequence of a batched build.  S, out: dev pointers. */
+/* One sequence of a batched build.  S, out: dev pointers.  tau: key bits
+ * per pass for this sequence (0 = the batch tuning, else automatic); the
+ * image does not depend on it. */
 typedef struct wt_seq_desc {
     const void* S;
     uint64_t n;
@@ -194,6 +196,8 @@ typedef struct wt_seq_desc {
     uint32_t sym_bytes;
     void* out;
     uint64_t out_bytes;
+    uint32_t tau;
+    uint32_t reserved;
 } wt_seq_desc;
 
 /* Size of the workspace a batched build of `count` sequences needs. */
@@ -202,7 +206,8 @@ int wt_batch_plan(int kind, const wt_seq_desc* seqs, uint32_t count, const wt_tu
 
 /* Build wavelet matrices (kind WT_KIND_WM) of many sequences with a few
  * persistent launches; each image equals the one wm_build writes for that
- * sequence alone.  seqs: host array of count descriptors. */
+ * sequence alone.  seqs: host array of count descriptors.  Returns when the
+ * batch is complete (the host writes per-round descriptors into ws). */
 int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count,
                    void* ws, size_t ws_bytes, const wt_tuning* tune, void* stream);
 

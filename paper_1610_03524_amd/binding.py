@@ -42,7 +42,7 @@ class wt_plan_info(ctypes.Structure):
 
 class wt_seq_desc(ctypes.Structure):
     _fields_ = [("S", c_vp), ("n", c_u64), ("sigma", c_u32), ("sym_bytes", c_u32),
-                ("out", c_vp), ("out_bytes", c_u64)]
+                ("out", c_vp), ("out_bytes", c_u64), ("tau", c_u32), ("reserved", c_u32)]
 
 
 class wt_profile_entry(ctypes.Structure):

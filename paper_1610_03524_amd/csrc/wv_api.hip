@@ -355,6 +355,7 @@ int build_any(int kind, const void* S, uint64_t n, uint32_t sigma, uint32_t sym_
     }
 
     wv_lw_args a = lw_args(p, S, out, ws);
+    a.profile = prof;
     if (is_tree(kind)) {
         uint64_t* dcounts = at<uint64_t>(ws, p.ws_counts);
         WV_CHECK(wv_validate(S, n, sym_bytes, sigma, img, dcounts, s));

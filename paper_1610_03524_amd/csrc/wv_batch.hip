@@ -355,11 +355,14 @@ int make_batch_plan(const wt_seq_desc* seqs, uint32_t count, const wt_tuning* tu
     // H of every sequence first (zeroed by one fill every round)
     for (uint32_t i = 0; i < count; i++) {
         const wt_seq_desc& d = seqs[i];
+        wt_tuning t1 = tune ? *tune : wt_tuning{};
+        if (d.tau) t1.tau = d.tau;
+        t1.flags &= ~WT_FLAG_LEVELWISE;
         wv_wm_plan wp;
-        int rc = wv_wm_make_plan(d.n, d.sigma, d.sym_bytes, tune, wp);
+        int rc = wv_wm_make_plan(d.n, d.sigma, d.sym_bytes, &t1, wp);
         if (rc) return rc;
         wt_plan_info info;
-        rc = wt_plan(WT_KIND_WM, d.n, d.sigma, d.sym_bytes, nullptr, tune, &info);
+        rc = wt_plan(WT_KIND_WM, d.n, d.sigma, d.sym_bytes, nullptr, &t1, &info);
         if (rc) return rc;
         if (!d.S && d.n) return WT_EINVAL;
         if (!d.out || d.out_bytes < info.out_bytes) return WT_ENOSPC;

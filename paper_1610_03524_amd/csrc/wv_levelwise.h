@@ -45,6 +45,7 @@ struct wv_lw_args {
     wv_node_table nt;
     const uint32_t* codes;
     const uint32_t* lens;
+    bool profile;
     wv_keyfn keyfn(uint32_t l) const;
 };
 

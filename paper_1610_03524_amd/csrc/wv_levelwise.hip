@@ -165,16 +165,20 @@ hipError_t run_levels(const wv_lw_args& a, hipStream_t s)
         const wv_level& L = lay.lv[l];
         const uint64_t m = L.n;
         wv_keyfn f = a.keyfn(l);
-        e = first ? emit_level<T>(keys, m, f, a.image, L, a.dir.sb_ones, s)
-                  : emit_level<uint32_t>(keys, m, f, a.image, L, a.dir.sb_ones, s);
+        WV_TIMED(a.profile, s, "lw_emit",
+                 e = first ? emit_level<T>(keys, m, f, a.image, L, a.dir.sb_ones, s)
+                           : emit_level<uint32_t>(keys, m, f, a.image, L, a.dir.sb_ones, s));
         if (e != hipSuccess) return e;
-        if (kind == WT_KIND_MULTIARY) e = wv_multiary_counters(a.image, L, f.D, a.mdir, s);
-        else e = wv_binary_directory(a.image, l, L, a.dir, a.zl, s);
+        WV_TIMED(a.profile, s, "lw_directory",
+                 e = kind == WT_KIND_MULTIARY ? wv_multiary_counters(a.image, L, f.D, a.mdir, s)
+                                              : wv_binary_directory(a.image, l, L, a.dir, a.zl, s));
         if (e != hipSuccess) return e;
         if (l + 1 == a.nlevels) break;
-        e = first ? scatter_level<T>(keys, nodes_in, m, f, a.image, L, a.zl, a.nt, kind, kbuf[cur], nbuf[cur], s)
-                  : scatter_level<uint32_t>(keys, nodes_in, m, f, a.image, L, a.zl, a.nt, kind, kbuf[cur],
-                                            nbuf[cur], s);
+        WV_TIMED(a.profile, s, "lw_scatter",
+                 e = first ? scatter_level<T>(keys, nodes_in, m, f, a.image, L, a.zl, a.nt, kind, kbuf[cur],
+                                              nbuf[cur], s)
+                           : scatter_level<uint32_t>(keys, nodes_in, m, f, a.image, L, a.zl, a.nt, kind, kbuf[cur],
+                                                     nbuf[cur], s));
         if (e != hipSuccess) return e;
         keys = kbuf[cur];
         nodes_in = kind == WT_KIND_WM ? nullptr : nbuf[cur];
