@@ -8,7 +8,7 @@ directory, every select sample, the image header) from the input already in
 HBM.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-    python bench.py --workload c1|c3h|c3m|c4     (the other configurations)
+    python bench.py --workload c1|c3h|c3m|c4|c5  (the other configurations)
     python bench.py --copy-calibration           (1 GiB copy for PMC scaling)
 """
 from __future__ import annotations
@@ -127,7 +127,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3h", "c3m", "c4"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3h", "c3m", "c4", "c5"])
+    ap.add_argument("--horizon", type=float, default=2.0, help="c5: seconds of arrivals per rate")
+    ap.add_argument("--rates", default="100,200,500,1000,2000,5000", help="c5: build arrival rates /s")
     ap.add_argument("--limit", type=int, default=8192, help="c4: number of sequences")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -142,6 +144,9 @@ def main():
         return
     if args.workload == "c4":
         bench_batch(args)
+        return
+    if args.workload == "c5":
+        bench_serve(args)
         return
 
     import torch
@@ -378,6 +383,69 @@ def bench_batch(args):
         "speedup_batched_vs_plain": round(tp / tb, 3),
         "input_generation_s": round(t_gen, 1),
     }), flush=True)
+
+
+
+def bench_serve(args):
+    """C5: Poisson build requests (the C4 size mix) and query batches of 2^16
+    mixed access/rank/select on resident structures; continuous batching
+    against a plain one-request-at-a-time queue; p50/p99 latency and
+    throughput per arrival rate"""
+    import threading
+    import torch
+    from paper_1610_03524_amd import inputs, serve, tune as T
+    P = min(args.limit, 512)
+    ns, sig, children = inputs.c4_sizes()
+    host = [(inputs.c4_sequence(int(ns[i]), int(sig[i]), children[i]), int(sig[i])) for i in range(P)]
+    dev = [(torch.from_numpy(S.view(np.int32)).cuda(), sg) for S, sg in host]
+    rng = np.random.default_rng(5)
+    qb = [serve.make_query_batch(S, 1 << 16, rng) for S, _ in host]
+    torch.cuda.synchronize()
+    rows = []
+    for rate in [float(r) for r in args.rates.split(",")]:
+        bt, ids, qt = inputs.c5_requests(rate, args.horizon, seed=5, count=P)
+        events = sorted([(t, "b", int(i)) for t, i in zip(bt, ids)] + [(t, "q", -1) for t in qt])
+        for mode in ("continuous", "plain"):
+            srv = serve.WaveletServer(dev, hbm_budget=64 << 30, ws_bytes=4 << 30, mode=mode, tau_of=T.choose_tau)
+            srv.start()
+            pick = np.random.default_rng(int(rate))
+            t0 = time.perf_counter()
+            skipped = 0
+            for t, kind, i in events:
+                dt = t0 + t - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+                if kind == "b":
+                    srv.submit_build(i)
+                else:
+                    res = srv.resident_ids()
+                    if not res:
+                        skipped += 1
+                        continue
+                    tgt = res[pick.integers(0, len(res))]
+                    srv.submit_query(tgt, qb[tgt])
+            deadline = time.perf_counter() + 60
+            while any(not r.done for r in srv.all_reqs) and time.perf_counter() < deadline:
+                time.sleep(0.002)
+            t_end = time.perf_counter()
+            srv.close()
+            bl, ql = srv.latencies("build"), srv.latencies("query")
+            unfinished = sum(1 for r in srv.all_reqs if not r.done)
+            rows.append({"rate": rate, "mode": mode, "builds": int(len(bl)), "query_batches": int(len(ql)),
+                         "build_p50_ms": serve.percentile_ms(bl, 50), "build_p99_ms": serve.percentile_ms(bl, 99),
+                         "query_p50_ms": serve.percentile_ms(ql, 50), "query_p99_ms": serve.percentile_ms(ql, 99),
+                         "builds_per_s": round(len(bl) / (t_end - t0), 1),
+                         "queries_per_s": round(len(ql) * (1 << 16) / (t_end - t0), 1),
+                         "mean_batch": round(float(np.mean(srv.batches)), 2) if srv.batches else None,
+                         "unfinished": unfinished, "queries_skipped_no_structure": skipped})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+            del srv
+            torch.cuda.empty_cache()
+    print(json.dumps({
+        "metric": "serving p50/p99 latency and throughput (continuous batching vs plain queue)",
+        "workload": f"C5: Poisson builds from the C4 mix over a pool of {P} sequences, query batches of 2^16 "
+                    f"mixed access/rank/select at max(10, rate/10)/s, {args.horizon} s per rate, HBM budget 64 GiB",
+        "n_gpus": 1, "data": "synthetic", "rows": rows}), flush=True)
 
 
 if __name__ == "__main__":

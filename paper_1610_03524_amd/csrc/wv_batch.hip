@@ -342,7 +342,7 @@ struct BatchPlan {
     std::vector<uint32_t> order;     // sequences by decreasing n
     uint64_t off_desc = 0, desc_bytes = 0, off_queue = 0, ws_bytes = 0;
     uint64_t zero_lo = 0, zero_hi = 0;   // H region zeroed every round
-    uint32_t max_passes = 0;
+    uint32_t max_passes = 0, nphases = 0;
 };
 
 int make_batch_plan(const wt_seq_desc* seqs, uint32_t count, const wt_tuning* tune, BatchPlan& bp)
@@ -397,8 +397,11 @@ int make_batch_plan(const wt_seq_desc* seqs, uint32_t count, const wt_tuning* tu
     const uint64_t round_bytes = count * (sizeof(SeqRound) + 4) + 256;
     const uint64_t span_bytes = total_spans * (sizeof(SpanDesc) + 4) + 256;
     const uint64_t head_bytes = count * (sizeof(wv_layout_in) + sizeof(uint8_t*)) + 256;
-    bp.desc_bytes = std::max(round_bytes, std::max(span_bytes, head_bytes));
-    bp.off_desc = bump(bp.desc_bytes);
+    bp.desc_bytes = wv_round256(std::max(round_bytes, std::max(span_bytes, head_bytes)));
+    // one descriptor area per phase (header, every round's two groups, the
+    // directories), so no phase overwrites descriptors still being read
+    bp.nphases = 2 + 2 * bp.max_passes;
+    bp.off_desc = bump(bp.desc_bytes * bp.nphases);
     bp.ws_bytes = off;
     bp.order.resize(count);
     std::iota(bp.order.begin(), bp.order.end(), 0u);
@@ -434,12 +437,16 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
     if (!count) return WT_OK;
     if (!ws_ || ws_bytes < bp.ws_bytes) return WT_ENOSPC;
     uint8_t* ws = (uint8_t*)ws_;
-    uint8_t* desc = ws + bp.off_desc;
     uint32_t* queue = (uint32_t*)(ws + bp.off_queue);
 
+    // host copies of every phase's descriptors live until the final sync
+    std::vector<std::vector<uint8_t>> keep;
+    uint32_t phase = 0;
     // headers of every image
     {
-        std::vector<uint8_t> host(bp.desc_bytes, 0);
+        keep.emplace_back(bp.desc_bytes, 0);
+        std::vector<uint8_t>& host = keep.back();
+        uint8_t* desc = ws + bp.off_desc + bp.desc_bytes * phase++;
         uint8_t** imgs = (uint8_t**)host.data();
         wv_layout_in* lins = (wv_layout_in*)(host.data() + wv_round256(count * sizeof(uint8_t*)));
         for (uint32_t i = 0; i < count; i++) {
@@ -450,7 +457,6 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
         b_header_k<<<count, 256, 0, s>>>((uint8_t* const*)desc,
                                          (const wv_layout_in*)(desc + wv_round256(count * sizeof(uint8_t*))));
         WV_CHECK(hipGetLastError());
-        WV_CHECK(hipStreamSynchronize(s));
     }
 
     std::vector<const void*> cur_in(count);
@@ -460,7 +466,7 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
     for (uint32_t r = 0; r < bp.max_passes; r++) {
         // two groups: keys up to 16 bits (16-bit LDS keys) and wider ones
         for (int wide = 0; wide < 2; wide++) {
-            std::vector<uint8_t> host(bp.desc_bytes, 0);
+            uint8_t* desc = ws + bp.off_desc + bp.desc_bytes * phase++;
             std::vector<uint32_t> members;
             for (uint32_t i : bp.order) {
                 const SeqPlan& sp = bp.seq[i];
@@ -470,6 +476,8 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
                 members.push_back(i);
             }
             if (members.empty()) continue;
+            keep.emplace_back(bp.desc_bytes, 0);
+            std::vector<uint8_t>& host = keep.back();
             const uint32_t m = (uint32_t)members.size();
             SeqRound* q = (SeqRound*)host.data();
             uint32_t* first = (uint32_t*)(host.data() + wv_round256((uint64_t)m * sizeof(SeqRound)));
@@ -506,8 +514,6 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
             if (wide) b_pass_k<uint32_t><<<workers, NT, 0, s>>>(dq, dfirst, m, chunks, queue);
             else b_pass_k<uint16_t><<<workers, NT, 0, s>>>(dq, dfirst, m, chunks, queue);
             WV_CHECK(hipGetLastError());
-            // the descriptor area is rewritten next: wait for this group
-            WV_CHECK(hipStreamSynchronize(s));
             for (uint32_t k = 0; k < m; k++) {
                 const uint32_t i = members[k];
                 if (q[k].pa.pay_out) { cur_in[i] = q[k].pa.pay_out; cur_bytes[i] = q[k].out_bytes; }
@@ -517,7 +523,9 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
 
     // directories of every level of every sequence
     {
-        std::vector<uint8_t> host(bp.desc_bytes, 0);
+        keep.emplace_back(bp.desc_bytes, 0);
+        std::vector<uint8_t>& host = keep.back();
+        uint8_t* desc = ws + bp.off_desc + bp.desc_bytes * (bp.nphases - 1);
         uint32_t nspan = 0;
         for (uint32_t i = 0; i < count; i++) nspan += bp.seq[i].L;
         SpanDesc* sd = (SpanDesc*)host.data();

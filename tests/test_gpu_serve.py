@@ -1,0 +1,109 @@
+"""Serving: every build and query result in the continuous-batching mix is
+identical to the same request run alone; admission respects the budget."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from gpu_util import to_device
+from paper_1610_03524_amd import binding as B
+from paper_1610_03524_amd import serve
+
+pytestmark = pytest.mark.gpu
+
+
+def pool(k=24, seed=9):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(k):
+        n = int(2 ** rng.uniform(6, 17))
+        sigma = max(2, int(2 ** rng.uniform(1, 20)))
+        out.append((rng.integers(0, sigma, n).astype(np.uint32), sigma))
+    return out
+
+
+def alone(host, batches):
+    import torch
+    imgs = []
+    for S, sigma in host:
+        img, _ = B.build(B.KIND_WM, to_device(S), sigma)
+        imgs.append(img)
+    res = []
+    for t, args in batches:
+        pos, rc, ri, sc, sk = args
+        res.append((B.access(imgs[t], pos), B.rank(imgs[t], rc, ri), B.select(imgs[t], sc, sk)))
+    torch.cuda.synchronize()
+    return [i.cpu().numpy() for i in imgs], [tuple(x.cpu().numpy() for x in r) for r in res]
+
+
+@pytest.mark.parametrize("mode", ["continuous", "plain"])
+def test_results_same_alone_and_in_the_mix(mode):
+    import torch
+    host = pool()
+    rng = np.random.default_rng(1)
+    batches = [(t, serve.make_query_batch(host[t][0], 3000, rng)) for t in range(len(host)) for _ in range(2)]
+    want_imgs, want_q = alone(host, batches)
+    dev = [(to_device(S), sigma) for S, sigma in host]
+    srv = serve.WaveletServer(dev, hbm_budget=1 << 34, ws_bytes=1 << 28, mode=mode)
+    srv.start()
+    # builds arrive in bursts, every structure is built twice, queries are
+    # submitted as soon as their target is resident (so they overlap builds)
+    qreqs = []
+    pending = list(range(len(batches)))
+    for rep in range(2):
+        for i in range(len(host)):
+            srv.submit_build(i)
+            if i % 5 == 0:
+                time.sleep(0.001)
+            ready = [b for b in pending if srv.is_resident(batches[b][0])]
+            for b in ready[:2]:
+                qreqs.append((b, srv.submit_query(batches[b][0], batches[b][1])))
+                pending.remove(b)
+    deadline = time.time() + 60
+    while pending and time.time() < deadline:
+        for b in [b for b in pending if srv.is_resident(batches[b][0])]:
+            qreqs.append((b, srv.submit_query(batches[b][0], batches[b][1])))
+            pending.remove(b)
+        time.sleep(0.002)
+    while any(not r.done for r in srv.all_reqs) and time.time() < deadline:
+        time.sleep(0.005)
+    srv.close()
+    torch.cuda.synchronize()
+    assert not pending
+    for r in srv.all_reqs:
+        assert r.done and r.error == 0, (r.kind, r.seq, r.error)
+    for i in range(len(host)):
+        got = srv.resident[i].image.cpu().numpy()
+        assert np.array_equal(got, want_imgs[i]), f"image {i}"
+    for b, r in qreqs:
+        for g, w in zip(r.result, want_q[b]):
+            assert np.array_equal(g.cpu().numpy(), w), f"query batch {b}"
+    if mode == "continuous":
+        assert max(srv.batches) > 1   # builds were batched
+
+
+def test_budget_admission_and_eviction():
+    import torch
+    host = pool(12, seed=3)
+    dev = [(to_device(S), sigma) for S, sigma in host]
+    sizes = [B.plan(B.KIND_WM, S.size, sigma, 4).out_bytes for S, sigma in host]
+    budget = sorted(sizes)[-3] + sorted(sizes)[-4]   # two mid-size images fit
+    srv = serve.WaveletServer(dev, hbm_budget=budget, ws_bytes=1 << 28)
+    srv.start()
+    reqs = [srv.submit_build(i) for i in range(len(host))]
+    deadline = time.time() + 60
+    while any(not r.done for r in reqs) and time.time() < deadline:
+        time.sleep(0.005)
+    srv.close()
+    assert srv.used <= budget
+    for r, sz in zip(reqs, sizes):
+        if sz > budget:
+            assert r.error == B.WT_ENOSPC
+        else:
+            assert r.error == 0
+    # whatever stayed resident is exactly the image built alone
+    want, _ = alone(host, [])
+    for i, st in srv.resident.items():
+        assert np.array_equal(st.image.cpu().numpy(), want[i])
+    torch.cuda.synchronize()
