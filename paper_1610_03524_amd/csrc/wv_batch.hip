@@ -3,8 +3,8 @@
 //
 // Every sequence is built exactly as wm_build builds it alone (same passes,
 // same chunking rule, same image), but each step runs for all sequences in
-// one launch: the chunk histograms of every sequence, then one workgroup per
-// sequence turning its histograms into run offsets, then a persistent pass
+// one launch: the chunk histograms of every sequence, their prefix over the
+// chunks, every chunk's run offsets, then a persistent pass
 // kernel whose workgroups pull chunks of any sequence from a device-side
 // queue (largest sequences first), and finally the directories of every
 // level of every sequence.  Sequences with more levels take more rounds of
@@ -23,8 +23,10 @@ namespace {
 struct SeqRound {
     PassArgs pa;            // the pass of this round (G0 points to the sequence's table)
     uint32_t* H;            // [2^tau][K] digit counts of the chunks
+    uint32_t* tot;          // [2^tau] digit totals
     uint32_t* status;       // image status word (first round) or null
     uint32_t in_bytes, out_bytes, sigma, chunk0;   // chunk0: first global chunk index
+    uint32_t col0;          // first global (sequence, digit) column
 };
 
 struct SpanDesc {
@@ -65,66 +67,45 @@ b_hist_k(const SeqRound* __restrict__ seqs, const uint32_t* __restrict__ chunk0,
         wm_hist_part<uint32_t>(a.in, a.n, a.C, a.K, a.R, a.tau, a.keymask, q.H, q.status, q.sigma, b, part, h);
 }
 
-// one workgroup per sequence: prefix of every digit over the sequence's
-// chunks, then every chunk's run offsets (and zeroed boundary words)
+// exclusive prefix over the chunks of every (sequence, digit) column of H,
+// one wave per column; the column sums go to the sequence's totals
 __global__ void __launch_bounds__(HT)
-b_offsets_k(const SeqRound* __restrict__ seqs)
+b_scan_k(const SeqRound* __restrict__ seqs, const uint32_t* __restrict__ col0, uint32_t nseq, uint32_t ncols)
 {
-    __shared__ uint32_t ph[256], tot[256];
-    __shared__ uint32_t cj[MAXG], tj[MAXG], bs[MAXG];
-    const SeqRound& q = seqs[blockIdx.x];
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t item = blockIdx.x * (HT / 64) + (threadIdx.x >> 6);
+    if (item >= ncols) return;   // whole waves; no barriers below
+    const uint32_t s = owner_of(col0, nseq, item);
+    const SeqRound& q = seqs[s];
+    const uint32_t d = item - col0[s], K = q.pa.K;
+    uint32_t* h = q.H + (uint64_t)d * K;
+    uint32_t run = 0;
+    for (uint32_t base = 0; base < K; base += 64) {
+        const uint32_t i = base + lane;
+        const uint32_t v = i < K ? h[i] : 0u;
+        uint32_t t;
+        const uint32_t ex = wave_excl_scan(v, &t);
+        if (i < K) h[i] = run + ex;
+        run += t;
+    }
+    if (lane == 0) q.tot[d] = run;
+}
+
+// one workgroup per chunk of any sequence: the chunk's run offsets (and
+// zeroed boundary words)
+__global__ void __launch_bounds__(HT)
+b_offsets_k(const SeqRound* __restrict__ seqs, const uint32_t* __restrict__ chunk0, uint32_t nseq)
+{
+    __shared__ OffShared sh;
+    const uint32_t s = owner_of(chunk0, nseq, blockIdx.x);
+    const SeqRound& q = seqs[s];
     const PassArgs& a = q.pa;
-    const uint32_t tau = a.tau, K = a.K;
-    const uint32_t nd = 1u << tau, ngroups = (2u << tau) - 1u;
-    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    // totals per digit, then per key of every sub-level its start on the level
-    if (threadIdx.x < nd) {
-        uint32_t t = 0;
-        for (uint32_t b = 0; b < K; b++) t += q.H[(uint64_t)threadIdx.x * K + b];
-        tot[threadIdx.x] = t;
-        ph[threadIdx.x] = 0;
+    const uint32_t b = blockIdx.x - q.chunk0, tau = a.tau;
+    if (threadIdx.x < (1u << tau)) {
+        sh.cj[gidx(tau, threadIdx.x)] = q.H[(uint64_t)threadIdx.x * a.K + b];
+        sh.tj[gidx(tau, threadIdx.x)] = q.tot[threadIdx.x];
     }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < ngroups; i += HT) {
-        const uint32_t j = 31 - __clz(i + 1), u = i + 1 - (1u << j), span = 1u << (tau - j);
-        uint32_t s2 = 0;
-        for (uint32_t d = u * span; d < (u + 1) * span; d++) s2 += tot[d];
-        tj[i] = s2;
-    }
-    __syncthreads();
-    for (uint32_t j = wave; j <= tau; j += HT / 64) {
-        const uint32_t nk = 1u << j;
-        uint32_t run = 0;
-        for (uint32_t r0 = 0; r0 < nk; r0 += 64) {
-            const uint32_t r = r0 + lane;
-            const uint32_t u = r < nk ? brev(r, j) : 0;
-            const uint32_t v = r < nk ? tj[gidx(j, u)] : 0;
-            uint32_t t;
-            const uint32_t ex = wave_excl_scan(v, &t);
-            if (r < nk) bs[gidx(j, u)] = run + ex;
-            run += t;
-        }
-    }
-    __syncthreads();
-    for (uint32_t b = 0; b < K; b++) {
-        for (uint32_t i = threadIdx.x; i < ngroups; i += HT) {
-            const uint32_t j = 31 - __clz(i + 1), u = i + 1 - (1u << j), span = 1u << (tau - j);
-            uint32_t s1 = 0;
-            for (uint32_t d = u * span; d < (u + 1) * span; d++) s1 += ph[d];
-            cj[i] = s1;
-        }
-        __syncthreads();
-        for (uint32_t i = threadIdx.x; i < ngroups; i += HT) {
-            const uint32_t g0 = bs[i] + cj[i];
-            ((uint32_t*)a.G0)[(uint64_t)b * MAXG + i] = g0;
-            const uint32_t j = 31 - __clz(i + 1);
-            if (j < tau && (g0 & 63u) && g0 < a.n) a.words[j][g0 >> 6] = 0;
-        }
-        __syncthreads();
-        if (threadIdx.x < nd) ph[threadIdx.x] += q.H[(uint64_t)threadIdx.x * K + b];
-        __syncthreads();
-    }
-    if (threadIdx.x < tau && (a.n & 63u)) a.words[threadIdx.x][(a.n - 1) >> 6] = 0;
+    wm_chunk_offsets(sh, b, tau, a.n, (uint32_t*)a.G0, a.words);
 }
 
 // persistent pass: workgroups take chunks from the queue until it is empty
@@ -332,7 +313,7 @@ inline uint32_t width_of(uint32_t bits) { return bits <= 8 ? 1u : (bits <= 16 ? 
 struct SeqPlan {
     uint32_t L, tau, passes, K, C, sym_bytes, sigma;
     uint64_t n;
-    uint64_t off_H, off_G0, off_pay[2], off_dcnt, off_dpre;
+    uint64_t off_H, off_tot, off_G0, off_pay[2], off_dcnt, off_dpre;
     wv_layout_out lay;
     wv_layout_in lin;
 };
@@ -377,6 +358,7 @@ int make_batch_plan(const wt_seq_desc* seqs, uint32_t count, const wt_tuning* tu
     bp.zero_hi = off;
     for (uint32_t i = 0; i < count; i++) {
         SeqPlan& s = bp.seq[i];
+        s.off_tot = bump(256 * 4);
         s.off_G0 = bump((uint64_t)s.K * MAXG * 4);
         const uint32_t rem = s.L > s.tau ? s.L - s.tau : 0;
         const uint64_t pay = rem ? std::max<uint64_t>(s.n, 1) * width_of(rem) : 0;
@@ -394,7 +376,7 @@ int make_batch_plan(const wt_seq_desc* seqs, uint32_t count, const wt_tuning* tu
         wv_layout(s.lin, s.lay);
     }
     // descriptor area: the largest of (round arrays, span arrays, headers)
-    const uint64_t round_bytes = count * (sizeof(SeqRound) + 4) + 256;
+    const uint64_t round_bytes = count * (sizeof(SeqRound) + 8) + 512;
     const uint64_t span_bytes = total_spans * (sizeof(SpanDesc) + 4) + 256;
     const uint64_t head_bytes = count * (sizeof(wv_layout_in) + sizeof(uint8_t*)) + 256;
     bp.desc_bytes = wv_round256(std::max(round_bytes, std::max(span_bytes, head_bytes)));
@@ -438,6 +420,7 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
     if (!ws_ || ws_bytes < bp.ws_bytes) return WT_ENOSPC;
     uint8_t* ws = (uint8_t*)ws_;
     uint32_t* queue = (uint32_t*)(ws + bp.off_queue);
+    const bool prof = tune && (tune->flags & WT_FLAG_PROFILE);
 
     // host copies of every phase's descriptors live until the final sync
     std::vector<std::vector<uint8_t>> keep;
@@ -453,9 +436,11 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
             imgs[i] = (uint8_t*)seqs[i].out;
             lins[i] = bp.seq[i].lin;
         }
-        WV_CHECK(hipMemcpyAsync(desc, host.data(), bp.desc_bytes, hipMemcpyHostToDevice, s));
-        b_header_k<<<count, 256, 0, s>>>((uint8_t* const*)desc,
-                                         (const wv_layout_in*)(desc + wv_round256(count * sizeof(uint8_t*))));
+        WV_TIMED(prof, s, "b_desc_copy",
+                 WV_CHECK(hipMemcpyAsync(desc, host.data(), bp.desc_bytes, hipMemcpyHostToDevice, s)));
+        WV_TIMED(prof, s, "b_header",
+                 (b_header_k<<<count, 256, 0, s>>>((uint8_t* const*)desc,
+                                                   (const wv_layout_in*)(desc + wv_round256(count * sizeof(uint8_t*))))));
         WV_CHECK(hipGetLastError());
     }
 
@@ -481,7 +466,8 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
             const uint32_t m = (uint32_t)members.size();
             SeqRound* q = (SeqRound*)host.data();
             uint32_t* first = (uint32_t*)(host.data() + wv_round256((uint64_t)m * sizeof(SeqRound)));
-            uint32_t chunks = 0;
+            uint32_t* cfirst = first + wv_round256((uint64_t)m * 4) / 4;
+            uint32_t chunks = 0, cols = 0;
             for (uint32_t k = 0; k < m; k++) {
                 const uint32_t i = members[k];
                 const SeqPlan& sp = bp.seq[i];
@@ -494,6 +480,7 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
                 e.pa.n = (uint32_t)sp.n; e.pa.C = sp.C; e.pa.K = sp.K; e.pa.R = R; e.pa.tau = tau;
                 e.pa.keymask = r == 0 ? (sp.L >= 32 ? ~0u : ((1u << sp.L) - 1u)) : ~0u;
                 e.H = (uint32_t*)(ws + sp.off_H);
+                e.tot = (uint32_t*)(ws + sp.off_tot);
                 e.status = r == 0 ? (uint32_t*)((uint8_t*)seqs[i].out + 36) : nullptr;
                 e.in_bytes = cur_bytes[i];
                 e.out_bytes = rem ? width_of(rem) : 1;
@@ -501,18 +488,27 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
                 e.chunk0 = chunks;
                 first[k] = chunks;
                 chunks += sp.K;
+                e.col0 = cols;
+                cfirst[k] = cols;
+                cols += 1u << tau;
             }
-            WV_CHECK(hipMemcpyAsync(desc, host.data(), bp.desc_bytes, hipMemcpyHostToDevice, s));
+            WV_TIMED(prof, s, "b_desc_copy",
+                     WV_CHECK(hipMemcpyAsync(desc, host.data(), bp.desc_bytes, hipMemcpyHostToDevice, s)));
             const SeqRound* dq = (const SeqRound*)desc;
             const uint32_t* dfirst = (const uint32_t*)(desc + wv_round256((uint64_t)m * sizeof(SeqRound)));
+            const uint32_t* dcfirst = dfirst + wv_round256((uint64_t)m * 4) / 4;
             const uint64_t hz = (bp.zero_hi - bp.zero_lo) / 4;
-            b_zero_k<<<(uint32_t)std::min<uint64_t>(wv_cdiv(hz, 256), 4096), 256, 0, s>>>((uint32_t*)(ws + bp.zero_lo), hz);
-            b_zero_k<<<1, 64, 0, s>>>(queue, 1);
-            b_hist_k<<<chunks * HSPLIT, HT, 0, s>>>(dq, dfirst, m);
-            b_offsets_k<<<m, HT, 0, s>>>(dq);
+            const uint32_t zb = (uint32_t)std::min<uint64_t>(wv_cdiv(hz, 256), 4096);
+            WV_TIMED(prof, s, "b_zero",
+                     ((b_zero_k<<<zb, 256, 0, s>>>((uint32_t*)(ws + bp.zero_lo), hz)),
+                      (b_zero_k<<<1, 64, 0, s>>>(queue, 1))));
+            WV_TIMED(prof, s, "b_hist", (b_hist_k<<<chunks * HSPLIT, HT, 0, s>>>(dq, dfirst, m)));
+            WV_TIMED(prof, s, "b_scan", (b_scan_k<<<wv_cdiv(cols, HT / 64), HT, 0, s>>>(dq, dcfirst, m, cols)));
+            WV_TIMED(prof, s, "b_offsets", (b_offsets_k<<<chunks, HT, 0, s>>>(dq, dfirst, m)));
             const uint32_t workers = std::min<uint32_t>(chunks, 512);
-            if (wide) b_pass_k<uint32_t><<<workers, NT, 0, s>>>(dq, dfirst, m, chunks, queue);
-            else b_pass_k<uint16_t><<<workers, NT, 0, s>>>(dq, dfirst, m, chunks, queue);
+            WV_TIMED(prof, s, "b_pass",
+                     (wide ? (void)(b_pass_k<uint32_t><<<workers, NT, 0, s>>>(dq, dfirst, m, chunks, queue))
+                           : (void)(b_pass_k<uint16_t><<<workers, NT, 0, s>>>(dq, dfirst, m, chunks, queue))));
             WV_CHECK(hipGetLastError());
             for (uint32_t k = 0; k < m; k++) {
                 const uint32_t i = members[k];
@@ -551,12 +547,13 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
                 chunks += (uint32_t)dch;
             }
         }
-        WV_CHECK(hipMemcpyAsync(desc, host.data(), bp.desc_bytes, hipMemcpyHostToDevice, s));
+        WV_TIMED(prof, s, "b_desc_copy",
+                 WV_CHECK(hipMemcpyAsync(desc, host.data(), bp.desc_bytes, hipMemcpyHostToDevice, s)));
         const SpanDesc* dsd = (const SpanDesc*)desc;
         const uint32_t* dfirst = (const uint32_t*)(desc + wv_round256((uint64_t)nspan * sizeof(SpanDesc)));
-        if (chunks) b_dir_count_k<<<chunks, 256, 0, s>>>(dsd, dfirst, nspan);
-        b_dir_scan_k<<<nspan, 256, 0, s>>>(dsd);
-        if (chunks) b_dir_write_k<<<chunks, 256, 0, s>>>(dsd, dfirst, nspan);
+        if (chunks) WV_TIMED(prof, s, "b_dir_count", (b_dir_count_k<<<chunks, 256, 0, s>>>(dsd, dfirst, nspan)));
+        WV_TIMED(prof, s, "b_dir_scan", (b_dir_scan_k<<<nspan, 256, 0, s>>>(dsd)));
+        if (chunks) WV_TIMED(prof, s, "b_dir_write", (b_dir_write_k<<<chunks, 256, 0, s>>>(dsd, dfirst, nspan)));
         WV_CHECK(hipGetLastError());
         WV_CHECK(hipStreamSynchronize(s));
     }

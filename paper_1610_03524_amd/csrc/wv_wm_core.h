@@ -377,10 +377,57 @@ wm_scan_chunks_k(uint32_t* __restrict__ H, uint32_t K, uint32_t* __restrict__ to
     if (threadIdx.x == 0) totals[d] = run;
 }
 
-// every chunk's first offset of every run, and zero the boundary words
+// Run offsets of one chunk.  Run (j, u) holds the keys whose top j digit
+// bits are u on sub-level j of the pass; its start on the level is the total
+// of the runs before it in bit-reversed key order, and chunk b's part of it
+// starts after the run's keys of the chunks before b.  On entry cj[gidx(tau,
+// d)] holds digit d's count in the chunks before b and tj[gidx(tau, d)] its
+// total, for every d < 2^tau; the coarser runs are sums of their two halves.
+struct OffShared {
+    uint32_t cj[MAXG], tj[MAXG], bs[MAXG];
+};
+
+__device__ inline void wm_chunk_offsets(OffShared& sh, uint32_t b, uint32_t tau, uint32_t n, uint32_t* G0,
+                                        uint64_t* const* words)
+{
+    const uint32_t ngroups = (2u << tau) - 1u;
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    for (int j = (int)tau - 1; j >= 0; j--) {
+        if (threadIdx.x < (1u << j)) {
+            const uint32_t c = gidx(j + 1, 2 * threadIdx.x), g = gidx(j, threadIdx.x);
+            sh.cj[g] = sh.cj[c] + sh.cj[c + 1];
+            sh.tj[g] = sh.tj[c] + sh.tj[c + 1];
+        }
+        __syncthreads();
+    }
+    for (uint32_t j = wave; j <= tau; j += HT / 64) {
+        const uint32_t nk = 1u << j;
+        uint32_t run = 0;
+        for (uint32_t r0 = 0; r0 < nk; r0 += 64) {
+            const uint32_t r = r0 + lane;
+            const uint32_t u = r < nk ? brev(r, j) : 0;
+            const uint32_t v = r < nk ? sh.tj[gidx(j, u)] : 0;
+            uint32_t t;
+            const uint32_t ex = wave_excl_scan(v, &t);
+            if (r < nk) sh.bs[gidx(j, u)] = run + ex;
+            run += t;
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < ngroups; i += HT) {
+        const uint32_t g0 = sh.bs[i] + sh.cj[i];
+        G0[(uint64_t)b * MAXG + i] = g0;
+        const uint32_t j = 31 - __clz(i + 1);
+        // a word that two chunks share is or-ed into; it must start at zero
+        if (j < tau && (g0 & 63u) && g0 < n) words[j][g0 >> 6] = 0;
+    }
+    if (b == 0 && threadIdx.x < tau && (n & 63u)) words[threadIdx.x][(n - 1) >> 6] = 0;
+}
+
 struct OffArgs {
-    const uint32_t* PH;
-    const uint32_t* totals;
+    const uint32_t* PH;      // [2^tau][K] exclusive prefix of the counts over chunks
+    const uint32_t* totals;  // [2^tau]
     uint32_t* G0;
     uint64_t* words[8];
     uint32_t K, tau, n;
@@ -389,48 +436,13 @@ struct OffArgs {
 __global__ void __launch_bounds__(HT)
 wm_offsets_k(OffArgs a)
 {
-    __shared__ uint32_t ph[256], tot[256];
-    __shared__ uint32_t cj[MAXG], tj[MAXG], bs[MAXG];
+    __shared__ OffShared sh;
     const uint32_t b = blockIdx.x, tau = a.tau;
-    const uint32_t nd = 1u << tau, ngroups = (2u << tau) - 1u;
-    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (threadIdx.x < nd) {
-        ph[threadIdx.x] = a.PH[(uint64_t)threadIdx.x * a.K + b];
-        tot[threadIdx.x] = a.totals[threadIdx.x];
+    if (threadIdx.x < (1u << tau)) {
+        sh.cj[gidx(tau, threadIdx.x)] = a.PH[(uint64_t)threadIdx.x * a.K + b];
+        sh.tj[gidx(tau, threadIdx.x)] = a.totals[threadIdx.x];
     }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < ngroups; i += HT) {
-        const uint32_t j = 31 - __clz(i + 1);
-        const uint32_t u = i + 1 - (1u << j);
-        const uint32_t span = 1u << (tau - j);
-        uint32_t s1 = 0, s2 = 0;
-        for (uint32_t d = u * span; d < (u + 1) * span; d++) { s1 += ph[d]; s2 += tot[d]; }
-        cj[i] = s1;
-        tj[i] = s2;
-    }
-    __syncthreads();
-    // start of every key's run on its level: keys in bit-reversed order
-    for (uint32_t j = wave; j <= tau; j += HT / 64) {
-        const uint32_t nk = 1u << j;
-        uint32_t run = 0;
-        for (uint32_t r0 = 0; r0 < nk; r0 += 64) {
-            const uint32_t r = r0 + lane;
-            const uint32_t u = r < nk ? brev(r, j) : 0;
-            const uint32_t v = r < nk ? tj[gidx(j, u)] : 0;
-            uint32_t t;
-            const uint32_t ex = wave_excl_scan(v, &t);
-            if (r < nk) bs[gidx(j, u)] = run + ex;
-            run += t;
-        }
-    }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < ngroups; i += HT) {
-        const uint32_t g0 = bs[i] + cj[i];
-        a.G0[(uint64_t)b * MAXG + i] = g0;
-        const uint32_t j = 31 - __clz(i + 1);
-        if (j < tau && (g0 & 63u) && g0 < a.n) a.words[j][g0 >> 6] = 0;
-    }
-    if (b == 0 && threadIdx.x < tau && (a.n & 63u)) a.words[threadIdx.x][(a.n - 1) >> 6] = 0;
+    wm_chunk_offsets(sh, b, tau, a.n, a.G0, a.words);
 }
 
 
