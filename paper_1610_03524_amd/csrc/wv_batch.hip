@@ -110,7 +110,7 @@ b_offsets_k(const SeqRound* __restrict__ seqs, const uint32_t* __restrict__ chun
 
 // persistent pass: workgroups take chunks from the queue until it is empty
 template <typename KT_>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4)))
 b_pass_k(const SeqRound* __restrict__ seqs, const uint32_t* __restrict__ chunk0, uint32_t nseq,
          uint32_t nchunks, uint32_t* __restrict__ queue)
 {

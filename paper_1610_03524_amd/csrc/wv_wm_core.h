@@ -9,7 +9,7 @@ namespace {
 
 constexpr int NT = 512;             // threads of a pass workgroup
 constexpr int NWAVE = NT / 64;
-constexpr int E = 32;               // elements per thread per tile
+constexpr int E = 16;               // elements per thread per tile
 constexpr int T = NT * E;           // tile
 constexpr int TW = T / 64;          // bit words per tile level
 constexpr int MAXG = 511;           // run groups of sub-levels j = 0..8
@@ -139,8 +139,11 @@ __device__ void wm_pass_chunk(const PassArgs& a, uint32_t b, PassShared<KT_>& S)
         __syncthreads();
 
         for (uint32_t j = 0; j < tau; j++) {
-            // phase 1: bit j of every element, in the order of sub-level j
+            // phase 1: bit j of every element, in the order of sub-level j;
+            // each element also keeps its bit and the zeros before it in its
+            // word (one byte per element, four to a register)
             uint32_t xs[E];
+            uint32_t rz[E / 4];
             const uint32_t sh = R - 1 - j;
             for (int e = 0; e < E; e++) {
                 const uint32_t p = tid + NT * e;
@@ -148,13 +151,19 @@ __device__ void wm_pass_chunk(const PassArgs& a, uint32_t b, PassShared<KT_>& S)
             }
             for (int e = 0; e < E; e++) {
                 const uint32_t p = tid + NT * e;
-                const uint64_t ball = __ballot(p < tc && ((xs[e] >> sh) & 1u));
+                const uint32_t bit = p < tc ? ((xs[e] >> sh) & 1u) : 0u;
+                const uint64_t ball = __ballot(bit);
                 if (lane == 0) {
                     const uint32_t wi = e * NWAVE + wave;
                     lb[wi] = ball;
                     const uint32_t base = wi * 64;
                     zw[wi] = (base >= tc ? 0u : min(64u, tc - base)) - __popcll(ball);
                 }
+                // lanes past the tile end are above every valid lane
+                const uint32_t zb = __builtin_amdgcn_mbcnt_hi((uint32_t)(~ball >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)~ball, 0u));
+                const uint32_t byte = zb | (bit << 7);
+                rz[e >> 2] = (e & 3) ? (rz[e >> 2] | (byte << (8 * (e & 3)))) : byte;
             }
             const uint32_t nk = 1u << j;
             const uint32_t gb = gidx(j, 0);
@@ -190,22 +199,13 @@ __device__ void wm_pass_chunk(const PassArgs& a, uint32_t b, PassShared<KT_>& S)
             __syncthreads();
             // phase 3: partition, child runs, emit words
             const uint32_t ztot = zw[TW];
-            const uint64_t ltm = lanemask_lt();
-            for (int e0 = 0; e0 < E; e0 += 8) {
-                // eight words' ballots and zero prefixes first, then the moves
-                uint64_t balls[8];
-                uint32_t zws[8];
-                for (int k = 0; k < 8; k++) {
-                    const uint32_t wi = (e0 + k) * NWAVE + wave;
-                    balls[k] = lb[wi];
-                    zws[k] = zw[wi];
-                }
-                for (int k = 0; k < 8; k++) {
-                    const uint32_t p = tid + NT * (e0 + k);
+            {
+                for (int e = 0; e < E; e++) {
+                    const uint32_t p = tid + NT * e;
                     if (p < tc) {
-                        const uint32_t zb = zws[k] + (lane - __popcll(balls[k] & ltm));
-                        const uint32_t bit = (uint32_t)((balls[k] >> lane) & 1ull);
-                        buf[bit ? ztot + (p - zb) : zb] = (KT_)xs[e0 + k];
+                        const uint32_t byte = (rz[e >> 2] >> (8 * (e & 3))) & 0xFFu;
+                        const uint32_t zb = zw[e * NWAVE + wave] + (byte & 63u);
+                        buf[(byte & 128u) ? ztot + (p - zb) : zb] = (KT_)xs[e];
                     }
                 }
             }
