@@ -110,7 +110,7 @@ b_offsets_k(const SeqRound* __restrict__ seqs, const uint32_t* __restrict__ chun
 
 // persistent pass: workgroups take chunks from the queue until it is empty
 template <typename KT_>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6)))
 b_pass_k(const SeqRound* __restrict__ seqs, const uint32_t* __restrict__ chunk0, uint32_t nseq,
          uint32_t nchunks, uint32_t* __restrict__ queue)
 {
@@ -505,7 +505,7 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
             WV_TIMED(prof, s, "b_hist", (b_hist_k<<<chunks * HSPLIT, HT, 0, s>>>(dq, dfirst, m)));
             WV_TIMED(prof, s, "b_scan", (b_scan_k<<<wv_cdiv(cols, HT / 64), HT, 0, s>>>(dq, dcfirst, m, cols)));
             WV_TIMED(prof, s, "b_offsets", (b_offsets_k<<<chunks, HT, 0, s>>>(dq, dfirst, m)));
-            const uint32_t workers = std::min<uint32_t>(chunks, 512);
+            const uint32_t workers = std::min<uint32_t>(chunks, KMAX);
             WV_TIMED(prof, s, "b_pass",
                      (wide ? (void)(b_pass_k<uint32_t><<<workers, NT, 0, s>>>(dq, dfirst, m, chunks, queue))
                            : (void)(b_pass_k<uint16_t><<<workers, NT, 0, s>>>(dq, dfirst, m, chunks, queue))));

@@ -14,7 +14,7 @@ constexpr int T = NT * E;           // tile
 constexpr int TW = T / 64;          // bit words per tile level
 constexpr int MAXG = 511;           // run groups of sub-levels j = 0..8
 constexpr int HT = 256;             // histogram / scan threads
-constexpr uint32_t KMAX = 512;      // chunks (all resident: 2 per CU)
+constexpr uint32_t KMAX = 768;      // chunks: 3 resident pass workgroups on each of 256 CUs
 
 
 __device__ __host__ inline uint32_t gidx(uint32_t j, uint32_t u) { return (1u << j) - 1u + u; }
@@ -80,6 +80,9 @@ __device__ inline void load_tile(const void* in, uint32_t ts, uint32_t tc, uint3
         }
     }
     for (uint32_t p = nv * V + threadIdx.x; p < tc; p += NT) buf[p] = (KT_)(ld<IT>(in, (uint64_t)ts + p) & keymask);
+    // a partial tile is padded with keys whose every bit is one: on every
+    // sub-level they are ones behind all real ones, so they stay at the end
+    for (uint32_t p = tc + threadIdx.x; p < (uint32_t)T; p += NT) buf[p] = (KT_)~0u;
 }
 
 // zeros among the first s bits of the tile bit string (s <= tile length)
@@ -140,38 +143,29 @@ __device__ void wm_pass_chunk(const PassArgs& a, uint32_t b, PassShared<KT_>& S)
 
         for (uint32_t j = 0; j < tau; j++) {
             // phase 1: bit j of every element, in the order of sub-level j;
-            // each element also keeps its bit and the zeros before it in its
-            // word (one byte per element, four to a register)
+            // each element also keeps the zeros before it in its word (one
+            // byte per element, four to a register)
             uint32_t xs[E];
             uint32_t rz[E / 4];
+            uint64_t balls[E];
             const uint32_t sh = R - 1 - j;
+            for (int e = 0; e < E; e++) xs[e] = (uint32_t)buf[tid + NT * e];
             for (int e = 0; e < E; e++) {
-                const uint32_t p = tid + NT * e;
-                xs[e] = p < tc ? (uint32_t)buf[p] : 0u;
-            }
-            for (int e = 0; e < E; e++) {
-                const uint32_t p = tid + NT * e;
-                const uint32_t bit = p < tc ? ((xs[e] >> sh) & 1u) : 0u;
-                const uint64_t ball = __ballot(bit);
-                if (lane == 0) {
-                    const uint32_t wi = e * NWAVE + wave;
-                    lb[wi] = ball;
-                    const uint32_t base = wi * 64;
-                    zw[wi] = (base >= tc ? 0u : min(64u, tc - base)) - __popcll(ball);
-                }
-                // lanes past the tile end are above every valid lane
+                const uint64_t ball = __ballot((xs[e] >> sh) & 1u);
+                balls[e] = ball;
                 const uint32_t zb = __builtin_amdgcn_mbcnt_hi((uint32_t)(~ball >> 32),
                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)~ball, 0u));
-                const uint32_t byte = zb | (bit << 7);
-                rz[e >> 2] = (e & 3) ? (rz[e >> 2] | (byte << (8 * (e & 3)))) : byte;
+                rz[e >> 2] = (e & 3) ? (rz[e >> 2] | (zb << (8 * (e & 3)))) : zb;
             }
+            if (lane == 0)
+                for (int e = 0; e < E; e++) lb[e * NWAVE + wave] = balls[e];
             const uint32_t nk = 1u << j;
             const uint32_t gb = gidx(j, 0);
             __syncthreads();
             // phase 2: zero prefix over the words (wave 0), run slots (wave 1)
             if (wave == 0) {
                 uint32_t v[TW / 64];
-                for (uint32_t k = 0; k < TW / 64; k++) v[k] = zw[64 * k + lane];
+                for (uint32_t k = 0; k < TW / 64; k++) v[k] = 64u - (uint32_t)__popcll(lb[64 * k + lane]);
                 uint32_t run = 0;
                 for (uint32_t k = 0; k < TW / 64; k++) {
                     uint32_t tot;
@@ -199,15 +193,11 @@ __device__ void wm_pass_chunk(const PassArgs& a, uint32_t b, PassShared<KT_>& S)
             __syncthreads();
             // phase 3: partition, child runs, emit words
             const uint32_t ztot = zw[TW];
-            {
-                for (int e = 0; e < E; e++) {
-                    const uint32_t p = tid + NT * e;
-                    if (p < tc) {
-                        const uint32_t byte = (rz[e >> 2] >> (8 * (e & 3))) & 0xFFu;
-                        const uint32_t zb = zw[e * NWAVE + wave] + (byte & 63u);
-                        buf[(byte & 128u) ? ztot + (p - zb) : zb] = (KT_)xs[e];
-                    }
-                }
+            // (padding keys are ones on every sub-level and stay in place)
+            for (int e = 0; e < E; e++) {
+                const uint32_t p = tid + NT * e;
+                const uint32_t zb = zw[e * NWAVE + wave] + ((rz[e >> 2] >> (8 * (e & 3))) & 63u);
+                buf[((xs[e] >> sh) & 1u) ? ztot + (p - zb) : zb] = (KT_)xs[e];
             }
             // runs of sub-level j+1 split the runs of j by bit j; a child's
             // elements keep their order, zeros of the tile first

@@ -37,7 +37,7 @@
 namespace {
 
 template <typename IT, typename OT, typename KT_>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6)))
 wm_pass_k(PassArgs a)
 {
     __shared__ PassShared<KT_> sh;
