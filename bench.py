@@ -92,18 +92,30 @@ def pass_alg_bytes(info, n, sym_bytes):
     return per
 
 
-def traffic_from_profile(kernel_src):
+# the sources the pass kernel is compiled from
+PASS_SOURCES = ["paper_1610_03524_amd/csrc/wv_common.h", "paper_1610_03524_amd/csrc/wv_wm_core.h",
+                "paper_1610_03524_amd/csrc/wv_wm_passes.hip"]
+
+
+def pass_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in PASS_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_from_profile():
     """HBM bytes per launch of the pass kernel measured with rocprofv3 PMC
     counters (FETCH_SIZE, WRITE_SIZE), scaled by the same counters' reading
-    for a plain copy; null when the kernel source changed since"""
-    import hashlib
+    for a plain copy; null when the kernel's sources changed since"""
     path = os.path.join(ROOT, "profiles", "wm_pass_c2_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    digest = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
-    if rec.get("kernel_sha256") != digest:
+    if rec.get("kernel_sha256") != pass_source_digest():
         return None
     return rec.get("bytes_per_launch")
 
@@ -184,7 +196,7 @@ def main():
     alg_per_launch = sum(pass_alg_bytes(info, n, 4)) / info_passes(info)
     achieved = alg_per_launch / (per_launch_ms / 1e3) / 1e9
     balg = algorithmic_bytes(info, n, 4)
-    traffic = traffic_from_profile(os.path.join(ROOT, "paper_1610_03524_amd", "csrc", "wv_wm_passes.hip"))
+    traffic = traffic_from_profile()
     line = {
         "metric": METRIC,
         "value": round(n * 4 / t / 1e9, 3),
@@ -220,22 +232,35 @@ def info_passes(info):
 
 
 def tree_kernel_bytes(name, info, sym_bytes, kind):
-    """compulsory bytes of all launches of one level-by-level kernel in a build
-    (keys are 4-byte symbols after level 0; trees also carry 4-byte node ids)"""
-    D = info.arity_log2 if kind == 4 else 1
-    total = 0
-    for l in range(info.nlevels):
-        m = int(info.level_n[l])
-        w = sym_bytes if l == 0 else 4
-        bits = m * D / 8
-        if name == "lw_emit":
-            total += m * w + bits
-        elif name == "lw_directory":
-            total += bits * 2 + (m / 32 if kind != 4 else m * D / 8 * 0.19)
-        elif name == "lw_scatter" and l + 1 < info.nlevels:
-            node = 0 if l == 0 else 4
-            total += m * (w + node) + bits + int(info.level_n[l + 1]) * 8
-    return total
+    """compulsory bytes of all launches of one kernel in one tree build, or
+    None for a kernel without a stated figure.  The tree is gathered from the
+    levels of a wavelet matrix over its keys (the symbols, or the codewords
+    padded to the longest code for the shaped tree)."""
+    n = int(info.n)
+    K = int(info.key_bits)
+    D = int(info.arity_log2) if kind == 4 else 1
+    key_w = 4 if kind == 3 else sym_bytes
+    tree_bits = sum(int(info.level_n[l]) * D for l in range(info.nlevels))
+    if name == "wm_pass":
+        width = lambda bits: 1 if bits <= 8 else (2 if bits <= 16 else 4)
+        total, in_w = 0, key_w
+        for l0 in range(0, K, info.tau):
+            t = min(info.tau, K - l0)
+            rem = K - l0 - t
+            out_w = width(rem) if rem else 0
+            total += n * in_w + t * ((n + 63) // 64) * 8 + n * out_w
+            in_w = out_w
+        return total
+    if name == "wm_hist":
+        return sum(n * (key_w if l0 == 0 else (1 if K - l0 <= 8 else (2 if K - l0 <= 16 else 4)))
+                   for l0 in range(0, K, info.tau))
+    if name == "tree_perm":          # read the matrix runs, write the tree levels
+        return 2 * tree_bits // 8
+    if name == "tree_digits":        # read D matrix levels, write one digit level, per digit level
+        return info.nlevels * 2 * (n * D // 8)
+    if name == "tree_keys":          # read S, write the padded codes
+        return n * (sym_bytes + 4)
+    return None
 
 
 def bench_tree(args):
@@ -284,7 +309,7 @@ def bench_tree(args):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
     prof = B.profile_read()
-    dom = max((k for k in prof if k.startswith("lw_")), key=lambda k: prof[k][1])
+    dom = max((k for k in prof if tree_kernel_bytes(k, info, sym, kind) is not None), key=lambda k: prof[k][1])
     dom_ms = prof[dom][1] / prof[dom][0]
     dom_bytes = tree_kernel_bytes(dom, info, sym, kind) / (prof[dom][0] / args.steps)
     balg = algorithmic_bytes(info, n, sym)
@@ -294,7 +319,7 @@ def bench_tree(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u16" if sym == 2 else "u8", "data": "synthetic",
         "config": {"workload": name, "n": n, "sigma": sigma, "levels": info.nlevels,
-                   "path": "level-by-level (host-synchronizing node table)"},
+                   "path": "wavelet-matrix passes over the keys, runs moved to tree order"},
         "symbol_levels_per_s": round(symbol_levels(info) / t, 1),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(dom_bytes / (dom_ms / 1e3) / 1e9, 2),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s",

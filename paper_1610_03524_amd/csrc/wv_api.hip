@@ -11,6 +11,7 @@
 
 #include "wv_internal.h"
 #include "wv_levelwise.h"
+#include "wv_treeperm.h"
 #include "wv_wm_passes.h"
 
 namespace {
@@ -27,6 +28,11 @@ struct Plan {
     uint64_t ws_sb_ones = 0, ws_sb_pre = 0, ws_partial = 0, ws_counts = 0;
     uint64_t ws_nt_start = 0, ws_nt_cstart = 0, ws_nt_child = 0, node_bound = 0;
     uint64_t ws_codes = 0, ws_lens = 0, ws_wm = 0;
+    // trees gathered from matrix levels (balanced and shaped binary trees)
+    bool from_matrix = false;
+    uint64_t ws_tkeys = 0, ws_tmp = 0, tmp_stride = 0, ws_segs = 0, seg_bound = 0;
+    uint64_t ws_tmpimg = 0, ws_digits = 0, dstride = 0;   // multiary: matrix image, digit strings
+    wv_layout_out tlay{};
     uint64_t ws_bytes = 0;
     wv_wm_plan wm{};
 };
@@ -141,6 +147,59 @@ int make_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt
         int rc = wv_wm_make_plan(n, sigma, sym_bytes, tune, p.wm);
         if (rc) return rc;
         p.levelwise = !p.wm.enabled;
+    }
+    // balanced and shaped binary trees: matrix passes over the (padded) keys,
+    // then the runs of every level moved to tree order
+    // (multiary trees: digits of 1, 2 or 4 bits, which pack words exactly)
+    if ((kind == WT_KIND_WT || kind == WT_KIND_SHAPED || (kind == WT_KIND_MULTIARY && p.D != 3)) &&
+        !p.levelwise && n && p.key_bits <= 31) {
+        const uint32_t sig_k = kind == WT_KIND_WT ? sigma : (1u << p.key_bits);
+        const uint32_t sb_k = kind == WT_KIND_SHAPED ? 4u : sym_bytes;
+        p.from_matrix = wv_wm_make_plan(n, sig_k, sb_k, tune, p.wm) == WT_OK && p.wm.enabled &&
+                        p.wm.L == p.key_bits;
+    }
+    if (p.from_matrix && kind == WT_KIND_MULTIARY) {
+        p.tau = p.wm.tau;
+        p.ws_wm = bump(off, p.wm.ws_bytes);
+        wv_layout_in tl{};
+        tl.kind = WT_KIND_WM;
+        tl.arity_log2 = 1;
+        tl.nlevels = p.key_bits;
+        tl.key_bits = p.key_bits;
+        tl.sigma = sigma;
+        tl.n = n;
+        for (uint32_t l = 0; l < p.key_bits; l++) tl.level_n[l] = n;
+        wv_layout(tl, p.tlay);
+        p.ws_tmpimg = bump(off, p.tlay.image_bytes);
+        p.dstride = wv_round256((wv_cdiv(n * p.D, 64) + 1) * 8);   // one readable word past each string
+        p.ws_digits = bump(off, p.dstride * p.nlevels);
+        for (uint32_t b = 0; b < p.nlevels; b++)
+            p.seg_bound += std::min<uint64_t>((((uint64_t)sigma - 1) >> (p.key_bits - p.D * b)) + 1, n);
+        p.ws_segs = bump(off, p.seg_bound * sizeof(wv_perm_seg) + WV_MAX_LEVELS * sizeof(wv_perm_level) + 256);
+        p.ws_counts = bump(off, (uint64_t)sigma * 8);
+        p.ws_bytes = off;
+        return WT_OK;
+    }
+    if (p.from_matrix) {
+        p.tau = p.wm.tau;
+        p.ws_wm = bump(off, p.wm.ws_bytes);
+        p.tmp_stride = wv_round256(wv_bits_bytes(n) + 8);   // one readable word past each level
+        p.ws_tmp = bump(off, p.tmp_stride * p.key_bits);
+        if (kind == WT_KIND_SHAPED) p.ws_tkeys = bump(off, n * 4);
+        if (kind == WT_KIND_SHAPED) {
+            p.seg_bound = p.nnodes_image;
+        } else {
+            for (uint32_t l = 0; l < p.key_bits; l++)
+                p.seg_bound += std::min<uint64_t>((((uint64_t)sigma - 1) >> (p.key_bits - l)) + 1, n);
+        }
+        p.ws_segs = bump(off, p.seg_bound * sizeof(wv_perm_seg) + WV_MAX_LEVELS * sizeof(wv_perm_level) + 256);
+        p.ws_counts = bump(off, (uint64_t)sigma * 8);
+        if (kind == WT_KIND_SHAPED) {
+            p.ws_codes = bump(off, (uint64_t)sigma * 4);
+            p.ws_lens = bump(off, (uint64_t)sigma * 4);
+        }
+        p.ws_bytes = off;
+        return WT_OK;
     }
     if (kind == WT_KIND_WM && !p.levelwise) {
         p.tau = p.wm.tau;
@@ -334,6 +393,132 @@ int check_buffers(const Plan& p, const void* S, void* out, size_t out_bytes, voi
     return WT_OK;
 }
 
+// Balanced or shaped binary tree gathered from matrix levels: validate S and
+// count its symbols, derive every level's runs on the host, build the matrix
+// levels of the (padded) keys, move the runs, then the directories.
+int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8_t* img, uint8_t* ws, bool prof,
+                      hipStream_t s)
+{
+    const uint64_t n = p.n;
+    const uint32_t sigma = p.sigma, K = p.key_bits;
+    const bool shaped = p.kind == WT_KIND_SHAPED, multi = p.kind == WT_KIND_MULTIARY;
+    uint64_t* dcounts = at<uint64_t>(ws, p.ws_counts);
+    WV_CHECK(wv_validate(S, n, p.sym_bytes, sigma, img, dcounts, s));
+    std::vector<uint64_t> counts(sigma);
+    uint32_t status = 0;
+    WV_CHECK(hipMemcpyAsync(counts.data(), dcounts, (uint64_t)sigma * 8, hipMemcpyDeviceToHost, s));
+    WV_CHECK(hipMemcpyAsync(&status, img + 36, 4, hipMemcpyDeviceToHost, s));
+    WV_CHECK(hipStreamSynchronize(s));
+    if (status) return WT_ERANGE;
+
+    std::vector<uint8_t> rec, code_rec;
+    std::vector<uint32_t> c32, l32;
+    if (shaped) {
+        for (uint32_t x = 0; x < sigma; x++)
+            if (counts[x] != shape->counts[x]) return WT_EINVAL;
+        HostNodes H;
+        int rc = shaped_nodes(*shape, sigma, H, rec);
+        if (rc) return rc;
+        code_rec.assign((uint64_t)sigma * WV_CODE_BYTES, 0);
+        c32.resize(sigma);
+        l32.resize(sigma);
+        for (uint32_t x = 0; x < sigma; x++) {
+            const uint64_t c = shape->code_len[x] ? shape->codes[x] : 0;
+            const uint32_t len = shape->code_len[x];
+            std::memcpy(code_rec.data() + (uint64_t)x * WV_CODE_BYTES, &c, 8);
+            std::memcpy(code_rec.data() + (uint64_t)x * WV_CODE_BYTES + 8, &len, 4);
+            c32[x] = (uint32_t)c;
+            l32[x] = len;
+        }
+    }
+    std::vector<wv_perm_seg> segs;
+    std::vector<uint64_t> seg0;
+    wv_tree_segments(counts, K, shaped ? c32.data() : nullptr, shaped ? l32.data() : nullptr, segs, seg0);
+    // tree level t: matrix level t (binary), or digit level t from matrix
+    // level t*D with every run D bits per symbol (multiary)
+    const uint32_t D = multi ? p.D : 1u, T = multi ? p.nlevels : K;
+    if (multi) {
+        std::vector<wv_perm_seg> ms;
+        std::vector<uint64_t> m0(T + 1, 0);
+        for (uint32_t t = 0; t < T; t++) {
+            m0[t] = ms.size();
+            for (uint64_t k = seg0[t * D]; k < seg0[t * D + 1]; k++)
+                ms.push_back(wv_perm_seg{segs[k].dst * D, segs[k].src * D, segs[k].len * D});
+        }
+        m0[T] = ms.size();
+        segs.swap(ms);
+        seg0.swap(m0);
+    }
+    if (segs.size() > p.seg_bound) return WT_EUNSUP;
+    std::vector<wv_perm_level> lv(T);
+    uint64_t words = 0;
+    for (uint32_t l = 0; l < T; l++) {
+        lv[l].dst = (uint64_t*)(img + p.lay.lv[l].bits_off);
+        lv[l].src = multi ? at<uint64_t>(ws, p.ws_digits + l * p.dstride) : at<uint64_t>(ws, p.ws_tmp + l * p.tmp_stride);
+        lv[l].nbits = p.lay.lv[l].n * D;
+        lv[l].seg0 = seg0[l];
+        lv[l].nseg = seg0[l + 1] - seg0[l];
+        lv[l].word0 = words;
+        words += wv_cdiv(lv[l].nbits, 64);
+    }
+    uint8_t* dsegs = at<uint8_t>(ws, p.ws_segs);
+    wv_perm_level* dlv = (wv_perm_level*)dsegs;
+    wv_perm_seg* dseg = (wv_perm_seg*)(dsegs + wv_round256(WV_MAX_LEVELS * sizeof(wv_perm_level)));
+    WV_CHECK(hipMemcpyAsync(dlv, lv.data(), T * sizeof(wv_perm_level), hipMemcpyHostToDevice, s));
+    if (!segs.empty())
+        WV_CHECK(hipMemcpyAsync(dseg, segs.data(), segs.size() * sizeof(wv_perm_seg), hipMemcpyHostToDevice, s));
+    if (shaped) {
+        WV_CHECK(hipMemcpyAsync(at<void>(ws, p.ws_codes), c32.data(), (uint64_t)sigma * 4, hipMemcpyHostToDevice, s));
+        WV_CHECK(hipMemcpyAsync(at<void>(ws, p.ws_lens), l32.data(), (uint64_t)sigma * 4, hipMemcpyHostToDevice, s));
+        if (!rec.empty())
+            WV_CHECK(hipMemcpyAsync(img + p.lay.nodes_off, rec.data(), rec.size(), hipMemcpyHostToDevice, s));
+        WV_CHECK(hipMemcpyAsync(img + p.lay.codes_off, code_rec.data(), code_rec.size(), hipMemcpyHostToDevice, s));
+    }
+    // the host vectors above go out of scope: finish the copies first
+    WV_CHECK(hipStreamSynchronize(s));
+
+    const void* keys = S;
+    if (shaped) {
+        WV_TIMED(prof, s, "tree_keys",
+                 WV_CHECK(wv_tree_keys(S, n, p.sym_bytes, at<uint32_t>(ws, p.ws_codes), at<uint32_t>(ws, p.ws_lens),
+                                       K, at<uint32_t>(ws, p.ws_tkeys), s)));
+        keys = at<void>(ws, p.ws_tkeys);
+    }
+    if (multi) {
+        // the whole matrix (with directories) in the workspace, then the digits
+        uint8_t* timg = at<uint8_t>(ws, p.ws_tmpimg);
+        wv_dir_scratch unused{};
+        WV_CHECK(wv_wm_run(p.wm, S, timg, p.tlay, at<uint8_t>(ws, p.ws_wm), unused, s));
+        for (uint32_t t = 0; t < T; t++) {
+            wv_digit_levels dl{};
+            for (uint32_t k = 0; k < D; k++) {
+                dl.words[k] = (const uint64_t*)(timg + p.tlay.lv[t * D + k].bits_off);
+                dl.dir[k] = (const uint64_t*)(timg + p.tlay.lv[t * D + k].rank_off);
+            }
+            WV_TIMED(prof, s, "tree_digits",
+                     WV_CHECK(wv_tree_digits(dl, n, D, at<uint64_t>(ws, p.ws_digits + t * p.dstride), s)));
+        }
+    } else {
+        uint64_t* lw[WV_MAX_LEVELS];
+        for (uint32_t l = 0; l < K; l++) lw[l] = at<uint64_t>(ws, p.ws_tmp + l * p.tmp_stride);
+        WV_CHECK(wv_wm_levels(p.wm, keys, lw, (uint32_t*)(img + 36), at<uint8_t>(ws, p.ws_wm), s));
+    }
+    WV_TIMED(prof, s, "tree_perm", WV_CHECK(wv_tree_permute(dlv, T, dseg, words, s)));
+    uint8_t* dscr = at<uint8_t>(ws, p.ws_wm + p.wm.off_dir);
+    if (multi) {
+        wv_mdir_scratch md{at<uint32_t>(ws, p.ws_sb_ones), at<uint64_t>(ws, p.ws_sb_pre),
+                           at<uint64_t>(ws, p.ws_partial), at<uint64_t>(ws, p.ws_scalars + 16)};
+        for (uint32_t t = 0; t < T; t++)
+            WV_TIMED(prof, s, "mcounters", WV_CHECK(wv_multiary_counters(img, p.lay.lv[t], D, md, s)));
+    } else if (shaped) {
+        for (uint32_t l = 0; l < K; l++)
+            WV_CHECK(wv_span_directory(img, p.lay, l, 1, dscr, wv_span_dir_sizes(p.lay.lv[l].n, 1), s, prof));
+    } else {
+        WV_CHECK(wv_span_directory(img, p.lay, 0, K, dscr, p.wm.dir, s, prof));
+    }
+    return WT_OK;
+}
+
 int build_any(int kind, const void* S, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt_shape* shape,
               const wt_tuning* tune, void* out, size_t out_bytes, void* ws, size_t ws_bytes, hipStream_t s)
 {
@@ -345,6 +530,7 @@ int build_any(int kind, const void* S, uint64_t n, uint32_t sigma, uint32_t sym_
     uint8_t* img = (uint8_t*)out;
     const bool prof = tune && (tune->flags & WT_FLAG_PROFILE);
     WV_TIMED(prof, s, "header", WV_CHECK(wv_write_header(img, p.lin, s)));
+    if (p.from_matrix) return build_from_matrix(p, S, shape, img, (uint8_t*)ws, prof, s);
 
     if (kind == WT_KIND_WM && !p.levelwise) {
         // the first pass validates S while counting its digits

@@ -155,8 +155,8 @@ b_dir_count_k(const SpanDesc* __restrict__ spans, const uint32_t* __restrict__ c
     uint32_t o = 0;
     if (w0 < nw) o += __popcll(words[w0]);
     if (w0 + 1 < nw) o += __popcll(words[w0 + 1]);
-    for (int k = 32; k >= 1; k >>= 1) o += __shfl_xor(o, k, 64);
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = o;
+    o = wv_wave_incl_scan(o);   // lane 63 holds the wave's sum
+    if ((threadIdx.x & 63) == 63) part[threadIdx.x >> 6] = o;
     __syncthreads();
     if (threadIdx.x == 0) d.cnt[c] = part[0] + part[1] + part[2] + part[3];
 }

@@ -109,6 +109,39 @@ __host__ __device__ inline void wv_layout(const wv_layout_in& in, wv_layout_out&
 
 // ---- device helpers ---------------------------------------------------------
 
+// Inclusive scan of one value per lane over the 64 lanes of a wave, in
+// registers through DPP lane moves: a scan inside every row of 16 lanes
+// (shifts by 1, 2, 4, 8; lanes shifted in from outside the row read 0), then
+// the last lane of row 0 added to row 1 and of row 2 to row 3 (broadcast
+// 15), then lane 31 added to rows 2 and 3 (broadcast 31).  Every lane of the
+// wave must be active.
+__device__ inline uint32_t wv_wave_incl_scan(uint32_t v)
+{
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true);   // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true);   // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true);   // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true);   // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+
+// the same for 64-bit values: both halves move, the sum carries
+__device__ inline uint64_t wv_wave_incl_scan64(uint64_t v)
+{
+#define WV_DPP64(ctrl, rows, bound)                                                                  \
+    v += ((uint64_t)(uint32_t)__builtin_amdgcn_update_dpp(0, (int)(v >> 32), ctrl, rows, 0xf, bound) << 32) | \
+         (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, ctrl, rows, 0xf, bound)
+    WV_DPP64(0x111, 0xf, true);
+    WV_DPP64(0x112, 0xf, true);
+    WV_DPP64(0x114, 0xf, true);
+    WV_DPP64(0x118, 0xf, true);
+    WV_DPP64(0x142, 0xa, false);
+    WV_DPP64(0x143, 0xc, false);
+#undef WV_DPP64
+    return v;
+}
+
 template <typename T>
 __device__ inline uint32_t wv_load_sym(const void* S, uint64_t i)
 {

@@ -384,8 +384,8 @@ span_count_k(const uint8_t* __restrict__ image, SpanLevels a, uint32_t* __restri
     uint32_t o = 0;
     if (w0 < nw) o += __popcll(words[w0]);
     if (w0 + 1 < nw) o += __popcll(words[w0 + 1]);
-    for (int d = 32; d >= 1; d >>= 1) o += __shfl_xor(o, d, 64);
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = o;
+    o = wv_wave_incl_scan(o);   // lane 63 holds the wave's sum
+    if ((threadIdx.x & 63) == 63) part[threadIdx.x >> 6] = o;
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t s = 0;
@@ -411,11 +411,7 @@ span_write_k(uint8_t* __restrict__ image, SpanLevels a, const uint64_t* __restri
     const uint64_t x0 = w0 < nw ? words[w0] : 0ull, x1 = w0 + 1 < nw ? words[w0 + 1] : 0ull;
     const uint32_t o0 = __popcll(x0), o1 = __popcll(x1);
     // exclusive prefix of ones over the words of the chunk
-    uint32_t inc = o0 + o1;
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t t = __shfl_up(inc, d, 64);
-        if (lane >= (uint32_t)d) inc += t;
-    }
+    const uint32_t inc = wv_wave_incl_scan(o0 + o1);
     if (lane == 63) wpart[wave] = inc;
     __syncthreads();
     uint32_t off = 0;

@@ -13,23 +13,13 @@ constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
 
-__device__ inline uint64_t wave_incl_scan(uint64_t v)
-{
-    const int lane = threadIdx.x & 63;
-    for (int d = 1; d < 64; d <<= 1) {
-        uint64_t t = __shfl_up(v, d, 64);
-        if (lane >= d) v += t;
-    }
-    return v;
-}
-
 // exclusive scan of one value per thread across the block; returns the
 // exclusive prefix, *total gets the block sum
 __device__ inline uint64_t block_excl_scan(uint64_t v, uint64_t* total)
 {
     __shared__ uint64_t wsum[SCAN_THREADS / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint64_t inc = wave_incl_scan(v);
+    uint64_t inc = wv_wave_incl_scan64(v);
     if (lane == 63) wsum[wave] = inc;
     __syncthreads();
     uint64_t base = 0, tot = 0;

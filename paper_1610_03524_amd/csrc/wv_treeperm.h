@@ -1,0 +1,47 @@
+// wv_treeperm.h -- tree levels gathered from wavelet-matrix levels.
+#pragma once
+
+#include <vector>
+
+#include "wv_internal.h"
+
+// one kept run of a level: `len` bits from bit `src` of the matrix level go
+// to bit `dst` of the tree level (runs of a level ordered by dst, covering it)
+struct wv_perm_seg {
+    uint64_t dst, src, len;
+};
+
+// one tree level to gather
+struct wv_perm_level {
+    uint64_t* dst;          // tree level words (in the image)
+    const uint64_t* src;    // matrix level words (one readable word past the end)
+    uint64_t nbits;         // symbols on the tree level
+    uint64_t seg0, nseg;    // its runs in the segment array
+    uint64_t word0;         // first output word of the level in the launch
+};
+
+// Runs of every level 0..key_bits-1 from the symbol counts.  Balanced tree:
+// codes == nullptr, key = symbol.  Shaped tree: key = codes[x] padded at the
+// bottom to key_bits (the longest code length), symbols whose code is no
+// longer than l are left out of level l.  seg0[l] = first run of level l,
+// seg0[key_bits] = number of runs.
+void wv_tree_segments(const std::vector<uint64_t>& counts, uint32_t key_bits, const uint32_t* codes,
+                      const uint32_t* lens, std::vector<wv_perm_seg>& segs, std::vector<uint64_t>& seg0);
+
+// keys[i] = codes[S[i]] << (h - lens[S[i]]) (device arrays)
+hipError_t wv_tree_keys(const void* S, uint64_t n, uint32_t sym_bytes, const uint32_t* codes, const uint32_t* lens,
+                        uint32_t h, uint32_t* keys, hipStream_t s);
+
+// matrix levels bD .. bD+D-1 (words and rank directories) of one multiary level
+struct wv_digit_levels {
+    const uint64_t* words[4];
+    const uint64_t* dir[4];
+};
+
+// the digit string of one multiary level in the order of matrix level bD
+// (ceil(n*D/64) words; D = 1, 2 or 4)
+hipError_t wv_tree_digits(const wv_digit_levels& a, uint64_t n, uint32_t D, uint64_t* out, hipStream_t s);
+
+// gather every tree level (descriptors and runs already on the device)
+hipError_t wv_tree_permute(const wv_perm_level* lv_dev, uint32_t nlev, const wv_perm_seg* seg_dev,
+                           uint64_t total_words, hipStream_t s);

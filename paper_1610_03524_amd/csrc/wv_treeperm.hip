@@ -1,0 +1,225 @@
+// wv_treeperm.hip -- tree levels from wavelet-matrix levels.
+//
+// Level l of the balanced tree (Sec. 2) and level l of the wavelet matrix
+// (Sec. 4.3) hold the same runs: one run per group of symbols that share
+// their top l key bits, holding bit l of those symbols in input order.  The
+// tree lays the runs out in the numeric order of the groups, the matrix in
+// the order of the groups' bit-reversed prefixes (every matrix level is a
+// stable partition by the previous bit).  A tree level is therefore the
+// matrix level with its runs moved, and the matrix is what the multi-level
+// passes build fastest.
+//
+// A shaped tree (Sec. 4.3) is handled the same way over codewords padded at
+// the bottom to the longest code length h: a symbol whose code ends above
+// level l is a leaf there; its padded prefix cannot be the prefix of another
+// codeword (the code is prefix-free), so the groups of leaves are separate
+// runs, which the tree level simply leaves out.
+//
+// A multiary tree (Sec. 4.3) with D-bit digits keeps the binary levels bD:
+// its level b holds the same runs as matrix level bD, with each symbol's
+// digit (its bits on matrix levels bD .. bD+D-1) in place of one bit.
+//
+// The host derives, from the symbol counts, every kept run's bit offset on
+// the matrix level and on the tree level; one thread per output word gathers
+// its bits from the runs that cover it.
+#include <algorithm>
+#include <vector>
+
+#include "wv_treeperm.h"
+
+namespace {
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+tree_keys_k(const T* __restrict__ S, uint64_t n, const uint32_t* __restrict__ codes,
+            const uint32_t* __restrict__ lens, uint32_t h, uint32_t* __restrict__ keys)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t x = (uint32_t)S[i];
+    keys[i] = codes[x] << (h - lens[x]);
+}
+
+// `nb` (1..64) bits of a level bit string starting at bit `pos`; the array
+// has one readable word past its last word
+__device__ inline uint64_t bits_at(const uint64_t* __restrict__ w, uint64_t pos, uint32_t nb)
+{
+    const uint64_t i = pos >> 6;
+    const uint32_t o = (uint32_t)(pos & 63);
+    uint64_t v = w[i] >> o;
+    if (o && o + nb > 64) v |= w[i + 1] << (64 - o);
+    return nb >= 64 ? v : (v & ((1ull << nb) - 1ull));
+}
+
+__global__ void __launch_bounds__(256)
+perm_runs_k(const wv_perm_level* __restrict__ lv, uint32_t nlev, const wv_perm_seg* __restrict__ seg,
+            uint64_t total_words)
+{
+    const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= total_words) return;
+    uint32_t l = 0;
+    while (l + 1 < nlev && lv[l + 1].word0 <= t) l++;
+    const wv_perm_level L = lv[l];
+    const uint64_t w = t - L.word0;
+    const uint64_t p0 = w * 64, end = min(p0 + 64, L.nbits);
+    // the run holding bit p0: the last one starting at or before it
+    uint64_t lo = L.seg0, hi = L.seg0 + L.nseg - 1;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi + 1) >> 1;
+        if (seg[mid].dst <= p0) lo = mid; else hi = mid - 1;
+    }
+    uint64_t out = 0;
+    for (uint64_t p = p0, k = lo; p < end; k++) {
+        const wv_perm_seg g = seg[k];
+        const uint64_t in = p - g.dst;
+        const uint32_t take = (uint32_t)min(end - p, g.len - in);
+        out |= bits_at(L.src, g.src + in, take) << (p - p0);
+        p += take;
+    }
+    L.dst[w] = out;
+}
+
+// the low 64/D bits of x moved to bit positions 0, D, 2D, ... (D = 1, 2, 4)
+__device__ inline uint64_t spread(uint64_t x, uint32_t D)
+{
+    if (D == 2) {
+        x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+        x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+        x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
+        x = (x | (x << 2)) & 0x3333333333333333ull;
+        x = (x | (x << 1)) & 0x5555555555555555ull;
+    } else if (D == 4) {
+        x = (x | (x << 24)) & 0x000000FF000000FFull;
+        x = (x | (x << 12)) & 0x000F000F000F000Full;
+        x = (x | (x << 6)) & 0x0303030303030303ull;
+        x = (x | (x << 3)) & 0x1111111111111111ull;
+    }
+    return x;
+}
+
+// Digits of one multiary level, in the order of matrix level bD: the symbol
+// at position i there has its digit's D bits on matrix levels bD .. bD+D-1,
+// each level's position found from the previous one by the matrix map (a
+// zero moves to its rank among zeros, a one to Z + its rank among ones).
+// One wave per 64 positions; its 64 digits fill D words of the digit string
+// (digit e at bits D*e .. D*e+D-1, low bit first).
+__global__ void __launch_bounds__(256)
+digits_k(wv_digit_levels a, uint64_t n, uint32_t D, uint64_t nwords, uint64_t* __restrict__ out)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    const uint64_t base = i - lane;
+    if (base >= n) return;   // whole waves: the ballots below need every lane
+    uint32_t d = 0;
+    if (i < n) {
+        uint64_t p = i;
+        for (uint32_t k = 0; k < D; k++) {
+            const uint32_t bit = (uint32_t)(a.words[k][p >> 6] >> (p & 63)) & 1u;
+            d = (d << 1) | bit;
+            if (k + 1 < D) {
+                const uint64_t r0 = wv_rank0(a.words[k], a.dir[k], p);
+                p = bit ? wv_rank0(a.words[k], a.dir[k], n) + (p - r0) : r0;
+            }
+        }
+    }
+    const uint32_t per = 64 / D;
+    const uint64_t pmask = per == 64 ? ~0ull : ((1ull << per) - 1ull);
+    uint64_t bt[4];
+    for (uint32_t t = 0; t < 4; t++) bt[t] = t < D ? __ballot((d >> t) & 1u) : 0ull;
+    if (lane < D) {
+        uint64_t w = 0;
+        for (uint32_t t = 0; t < D; t++) w |= spread((bt[t] >> (lane * per)) & pmask, D) << t;
+        const uint64_t wi = (base / 64) * D + lane;
+        if (wi < nwords) out[wi] = w;
+    }
+}
+
+inline uint64_t brev_bits(uint64_t v, uint32_t nbits)
+{
+    uint64_t r = 0;
+    for (uint32_t b = 0; b < nbits; b++) r |= ((v >> b) & 1ull) << (nbits - 1 - b);
+    return r;
+}
+
+// groups of one level, in numeric order: (group, symbols, kept on the tree level)
+struct Group {
+    uint64_t g, count;
+    bool kept;
+};
+
+// matrix and tree offsets of the kept groups of one level
+void level_segments(const std::vector<Group>& gs, uint32_t l, std::vector<wv_perm_seg>& out)
+{
+    std::vector<uint32_t> order(gs.size());
+    for (uint32_t i = 0; i < order.size(); i++) order[i] = i;
+    std::sort(order.begin(), order.end(),
+              [&](uint32_t a, uint32_t b) { return brev_bits(gs[a].g, l) < brev_bits(gs[b].g, l); });
+    std::vector<uint64_t> src(gs.size());
+    uint64_t acc = 0;
+    for (uint32_t i : order) {
+        src[i] = acc;
+        acc += gs[i].count;
+    }
+    uint64_t dst = 0;
+    for (uint32_t i = 0; i < gs.size(); i++) {
+        if (!gs[i].kept || !gs[i].count) continue;
+        out.push_back(wv_perm_seg{dst, src[i], gs[i].count});
+        dst += gs[i].count;
+    }
+}
+
+}  // namespace
+
+void wv_tree_segments(const std::vector<uint64_t>& counts, uint32_t key_bits, const uint32_t* codes,
+                      const uint32_t* lens, std::vector<wv_perm_seg>& segs, std::vector<uint64_t>& seg0)
+{
+    // (padded key, symbols, code length) of every symbol present, by key
+    struct Sym { uint64_t key, count; uint32_t len; };
+    std::vector<Sym> sy;
+    for (uint64_t x = 0; x < counts.size(); x++) {
+        if (!counts[x]) continue;
+        if (codes) sy.push_back(Sym{(uint64_t)codes[x] << (key_bits - lens[x]), counts[x], lens[x]});
+        else sy.push_back(Sym{x, counts[x], key_bits});
+    }
+    std::sort(sy.begin(), sy.end(), [](const Sym& a, const Sym& b) { return a.key < b.key; });
+    segs.clear();
+    seg0.assign(key_bits + 1, 0);
+    std::vector<Group> gs;
+    for (uint32_t l = 0; l < key_bits; l++) {
+        seg0[l] = segs.size();
+        gs.clear();
+        for (const Sym& s : sy) {
+            const uint64_t g = l ? (s.key >> (key_bits - l)) : 0;
+            if (!gs.empty() && gs.back().g == g) gs.back().count += s.count;
+            else gs.push_back(Group{g, s.count, s.len > l});
+        }
+        level_segments(gs, l, segs);
+    }
+    seg0[key_bits] = segs.size();
+}
+
+hipError_t wv_tree_keys(const void* S, uint64_t n, uint32_t sym_bytes, const uint32_t* codes, const uint32_t* lens,
+                        uint32_t h, uint32_t* keys, hipStream_t s)
+{
+    if (!n) return hipSuccess;
+    const uint32_t g = (uint32_t)wv_cdiv(n, 256);
+    if (sym_bytes == 1) tree_keys_k<uint8_t><<<g, 256, 0, s>>>((const uint8_t*)S, n, codes, lens, h, keys);
+    else if (sym_bytes == 2) tree_keys_k<uint16_t><<<g, 256, 0, s>>>((const uint16_t*)S, n, codes, lens, h, keys);
+    else tree_keys_k<uint32_t><<<g, 256, 0, s>>>((const uint32_t*)S, n, codes, lens, h, keys);
+    return hipGetLastError();
+}
+
+hipError_t wv_tree_digits(const wv_digit_levels& a, uint64_t n, uint32_t D, uint64_t* out, hipStream_t s)
+{
+    if (!n) return hipSuccess;
+    digits_k<<<(uint32_t)wv_cdiv(n, 256), 256, 0, s>>>(a, n, D, wv_cdiv(n * D, 64), out);
+    return hipGetLastError();
+}
+
+hipError_t wv_tree_permute(const wv_perm_level* lv_dev, uint32_t nlev, const wv_perm_seg* seg_dev,
+                           uint64_t total_words, hipStream_t s)
+{
+    if (!total_words) return hipSuccess;
+    perm_runs_k<<<(uint32_t)wv_cdiv(total_words, 256), 256, 0, s>>>(lv_dev, nlev, seg_dev, total_words);
+    return hipGetLastError();
+}

@@ -49,16 +49,12 @@ __device__ inline uint64_t lanemask_lt()
     return lane ? (~0ull >> (64 - lane)) : 0ull;
 }
 
-// exclusive scan of up to 64 values held by one wave (lane l holds v)
+// exclusive scan of the 64 values held by one wave (lane l holds v); every
+// lane must be active
 __device__ inline uint32_t wave_excl_scan(uint32_t v, uint32_t* total)
 {
-    const uint32_t lane = threadIdx.x & 63;
-    uint32_t inc = v;
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t t = __shfl_up(inc, d, 64);
-        if (lane >= (uint32_t)d) inc += t;
-    }
-    *total = __shfl(inc, 63, 64);
+    const uint32_t inc = wv_wave_incl_scan(v);
+    *total = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
     return inc - v;
 }
 
@@ -143,19 +139,18 @@ __device__ void wm_pass_chunk(const PassArgs& a, uint32_t b, PassShared<KT_>& S)
 
         for (uint32_t j = 0; j < tau; j++) {
             // phase 1: bit j of every element, in the order of sub-level j;
-            // each element also keeps the zeros before it in its word (one
-            // byte per element, four to a register)
+            // each element also keeps the zeros before it in its word
             uint32_t xs[E];
-            uint32_t rz[E / 4];
+            uint32_t rz[E];
             uint64_t balls[E];
+            bool bit[E];
             const uint32_t sh = R - 1 - j;
             for (int e = 0; e < E; e++) xs[e] = (uint32_t)buf[tid + NT * e];
             for (int e = 0; e < E; e++) {
-                const uint64_t ball = __ballot((xs[e] >> sh) & 1u);
+                bit[e] = (xs[e] >> sh) & 1u;
+                const uint64_t ball = __ballot(bit[e]);
                 balls[e] = ball;
-                const uint32_t zb = __builtin_amdgcn_mbcnt_hi((uint32_t)(~ball >> 32),
-                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)~ball, 0u));
-                rz[e >> 2] = (e & 3) ? (rz[e >> 2] | (zb << (8 * (e & 3)))) : zb;
+                rz[e] = __builtin_amdgcn_mbcnt_hi((uint32_t)(~ball >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)~ball, 0u));
             }
             if (lane == 0)
                 for (int e = 0; e < E; e++) lb[e * NWAVE + wave] = balls[e];
@@ -196,8 +191,8 @@ __device__ void wm_pass_chunk(const PassArgs& a, uint32_t b, PassShared<KT_>& S)
             // (padding keys are ones on every sub-level and stay in place)
             for (int e = 0; e < E; e++) {
                 const uint32_t p = tid + NT * e;
-                const uint32_t zb = zw[e * NWAVE + wave] + ((rz[e >> 2] >> (8 * (e & 3))) & 63u);
-                buf[((xs[e] >> sh) & 1u) ? ztot + (p - zb) : zb] = (KT_)xs[e];
+                const uint32_t zb = zw[e * NWAVE + wave] + rz[e];
+                buf[bit[e] ? ztot + (p - zb) : zb] = (KT_)xs[e];
             }
             // runs of sub-level j+1 split the runs of j by bit j; a child's
             // elements keep their order, zeros of the tile first

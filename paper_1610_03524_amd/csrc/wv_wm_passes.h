@@ -18,6 +18,11 @@ struct wv_wm_plan {
 // Decide how the multi-level passes build this matrix.
 int wv_wm_make_plan(uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt_tuning* tune, wv_wm_plan& p);
 
+// The level bits only: level l's words go to level_words[l] (host array of
+// device pointers, ceil(n/64) words each); a symbol >= sigma sets *status.
+hipError_t wv_wm_levels(const wv_wm_plan& p, const void* S, uint64_t* const* level_words, uint32_t* status,
+                        uint8_t* ws, hipStream_t s);
+
 // Build every level, directory and select sample of the matrix into `image`.
 hipError_t wv_wm_run(const wv_wm_plan& p, const void* S, uint8_t* image, const wv_layout_out& lay,
                      uint8_t* ws, const wv_dir_scratch& dir, hipStream_t s);

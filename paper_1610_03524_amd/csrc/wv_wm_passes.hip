@@ -139,14 +139,13 @@ int wv_wm_make_plan(uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt_tun
     return WT_OK;
 }
 
-hipError_t wv_wm_run(const wv_wm_plan& p, const void* S, uint8_t* image, const wv_layout_out& lay, uint8_t* ws,
-                     const wv_dir_scratch&, hipStream_t s)
+hipError_t wv_wm_levels(const wv_wm_plan& p, const void* S, uint64_t* const* level_words, uint32_t* status,
+                        uint8_t* ws, hipStream_t s)
 {
     const uint32_t L = p.L, n = (uint32_t)p.n;
     uint32_t* H = (uint32_t*)(ws + p.off_H);
     uint32_t* tot = (uint32_t*)(ws + p.off_tot);
     uint32_t* G0 = (uint32_t*)(ws + p.off_G0);
-    uint32_t* status = (uint32_t*)(image + 36);
     const Geometry geo{p.K, p.C};
     const void* in = S;
     uint32_t in_bytes = p.sym_bytes;
@@ -165,7 +164,7 @@ hipError_t wv_wm_run(const wv_wm_plan& p, const void* S, uint8_t* image, const w
             oa.PH = H;
             oa.totals = tot;
             oa.G0 = G0;
-            for (uint32_t j = 0; j < tau; j++) oa.words[j] = (uint64_t*)(image + lay.lv[l0 + j].bits_off);
+            for (uint32_t j = 0; j < tau; j++) oa.words[j] = level_words[l0 + j];
             oa.K = geo.K;
             oa.tau = tau;
             oa.n = n;
@@ -193,5 +192,15 @@ hipError_t wv_wm_run(const wv_wm_plan& p, const void* S, uint8_t* image, const w
             side ^= 1;
         }
     }
-    return wv_span_directory(image, lay, 0, L, ws + p.off_dir, p.dir, s, p.profile);
+    return hipSuccess;
+}
+
+hipError_t wv_wm_run(const wv_wm_plan& p, const void* S, uint8_t* image, const wv_layout_out& lay, uint8_t* ws,
+                     const wv_dir_scratch&, hipStream_t s)
+{
+    uint64_t* words[WV_MAX_LEVELS];
+    for (uint32_t l = 0; l < p.L; l++) words[l] = (uint64_t*)(image + lay.lv[l].bits_off);
+    hipError_t e = wv_wm_levels(p, S, words, (uint32_t*)(image + 36), ws, s);
+    if (e != hipSuccess) return e;
+    return wv_span_directory(image, lay, 0, p.L, ws + p.off_dir, p.dir, s, p.profile);
 }

@@ -221,23 +221,25 @@ class WaveletServer:
                         self.used -= nb
                 self.lock.notify_all()
 
-    def _run_query(self, r, stream):
-        """launch one mixed batch: args = (pos, rank c, rank i, select c, select k)"""
+    def _take_structure(self, r, stream):
+        """(under the lock) the structure a query reads, or None.  The
+        caller's reference keeps the image alive if it is evicted while the
+        query runs; record_stream keeps its memory from being reused before
+        the query stream is past this point."""
         st = self.resident.get(r.seq)
-        if st is None:
-            return False
-        st.last_use = time.perf_counter()
-        # the image may be evicted while the query runs: its memory must not
-        # be reused before the query stream is past this point
-        st.image.record_stream(stream)
+        if st is not None:
+            st.last_use = time.perf_counter()
+            st.image.record_stream(stream)
+        return st
+
+    def _run_query(self, r, st, stream):
+        """launch one mixed batch: args = (pos, rank c, rank i, select c, select k)"""
         pos, rc, ri, sc, sk = r.args
         with self.torch.cuda.stream(stream):
             r.result = (B.access(st.image, pos, stream=stream), B.rank(st.image, rc, ri, stream=stream),
                         B.select(st.image, sc, sk, stream=stream))
-        return True
 
     def _query_loop(self):
-        torch = self.torch
         while True:
             with self.lock:
                 while not self.queries and not self.closing:
@@ -245,12 +247,13 @@ class WaveletServer:
                 if self.closing and not self.queries:
                     return
                 r = self.queries.popleft()
-                ok = self._run_query(r, self.query_stream)
-            if ok:
+                st = self._take_structure(r, self.query_stream)
+            if st is not None:
+                self._run_query(r, st, self.query_stream)
                 self.query_stream.synchronize()
-            r.done = time.perf_counter()
-            if not ok:
+            else:
                 r.error = B.WT_EINVAL
+            r.done = time.perf_counter()
 
     def _plain_loop(self):
         torch = self.torch
@@ -290,12 +293,13 @@ class WaveletServer:
                         self.used -= ob
             else:
                 with self.lock:
-                    ok = self._run_query(r, self.build_stream)
-                if ok:
+                    st = self._take_structure(r, self.build_stream)
+                if st is not None:
+                    self._run_query(r, st, self.build_stream)
                     self.build_stream.synchronize()
-                r.done = time.perf_counter()
-                if not ok:
+                else:
                     r.error = B.WT_EINVAL
+                r.done = time.perf_counter()
 
     # ---- results ----------------------------------------------------------------------
     def latencies(self, kind):

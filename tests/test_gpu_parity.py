@@ -127,3 +127,44 @@ def test_wm_passes_widths(sigma, dt):
     for blocks in (0, 2):
         g = gpu_image(B.KIND_WM, S, sigma, tune=B.make_tuning(blocks=blocks))
         assert_same(g, o, f"sigma={sigma} blocks={blocks}")
+
+
+def fibonacci_sequence(nsym, rng):
+    """symbol s appears F(s + 1) times (F(1) = F(2) = 1), shuffled: its
+    Huffman tree is a path, so the codes reach nsym - 1 bits"""
+    f = [1, 1]
+    while len(f) < nsym:
+        f.append(f[-1] + f[-2])
+    S = np.repeat(np.arange(nsym, dtype=np.uint8), f[:nsym])
+    rng.shuffle(S)
+    return S
+
+
+@pytest.mark.parametrize("nsym", [20, 30, 32, 33])
+def test_shaped_long_codes(nsym):
+    """code lengths up to 31 bits (gathered from matrix levels over padded
+    codes, most runs of the deep levels being leaves) and 32 bits (the
+    one-level-per-pass builder)"""
+    S = fibonacci_sequence(nsym, np.random.default_rng(nsym))
+    (gc, gl), (oc, ol) = shaped_inputs(S, nsym)
+    assert int(gl.max()) == nsym - 1
+    g = gpu_image(B.KIND_SHAPED, S, nsym, codes=gc, lens=gl)
+    o = oracle_image(B.KIND_SHAPED, S, nsym, codes=oc, lens=ol)
+    assert_same(g, o, f"shaped fibonacci nsym={nsym}")
+
+
+@pytest.mark.parametrize("kind", [B.KIND_WT, B.KIND_SHAPED])
+def test_trees_many_chunks(kind):
+    """7M symbols, 17 key bits: three passes, every chunk two tiles long"""
+    rng = np.random.default_rng(17)
+    sigma, n = 65537, 7_000_003
+    if kind == B.KIND_WT:
+        S = rng.integers(0, sigma, n).astype(np.uint32)
+        g = gpu_image(kind, S, sigma)
+        o = oracle_image(kind, S, sigma)
+    else:
+        S = np.minimum(rng.geometric(0.0005, n) - 1, sigma - 1).astype(np.uint32)
+        (gc, gl), (oc, ol) = shaped_inputs(S, sigma)
+        g = gpu_image(kind, S, sigma, codes=gc, lens=gl)
+        o = oracle_image(kind, S, sigma, codes=oc, lens=ol)
+    assert_same(g, o, f"kind={kind} n={n}")
