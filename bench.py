@@ -427,8 +427,10 @@ def bench_serve(args):
     qb = [serve.make_query_batch(S, 1 << 16, rng) for S, _ in host]
     torch.cuda.synchronize()
     rows = []
-    for rate in [float(r) for r in args.rates.split(",")]:
-        bt, ids, qt = inputs.c5_requests(rate, args.horizon, seed=5, count=P)
+    # warm-up of both modes (first launches, allocator, streams), not recorded
+    rates = [("warmup", 1000.0, 0.5)] + [("run", float(r), args.horizon) for r in args.rates.split(",")]
+    for tag, rate, horizon in rates:
+        bt, ids, qt = inputs.c5_requests(rate, horizon, seed=5, count=P)
         events = sorted([(t, "b", int(i)) for t, i in zip(bt, ids)] + [(t, "q", -1) for t in qt])
         for mode in ("continuous", "plain"):
             srv = serve.WaveletServer(dev, hbm_budget=64 << 30, ws_bytes=4 << 30, mode=mode, tau_of=T.choose_tau)
@@ -456,6 +458,9 @@ def bench_serve(args):
             srv.close()
             bl, ql = srv.latencies("build"), srv.latencies("query")
             unfinished = sum(1 for r in srv.all_reqs if not r.done)
+            if tag == "warmup":
+                del srv
+                continue
             rows.append({"rate": rate, "mode": mode, "builds": int(len(bl)), "query_batches": int(len(ql)),
                          "build_p50_ms": serve.percentile_ms(bl, 50), "build_p99_ms": serve.percentile_ms(bl, 99),
                          "query_p50_ms": serve.percentile_ms(ql, 50), "query_p99_ms": serve.percentile_ms(ql, 99),

@@ -46,6 +46,38 @@ uint64_t bump(uint64_t& off, uint64_t bytes)
     return at;
 }
 
+// The coded symbols of a shape, ordered by codeword padded at the bottom to
+// the longest code length h.  In that order a codeword shares its top lcp
+// bits with its predecessor and adds len - 1 - lcp new proper prefixes (tree
+// nodes), and the code is prefix-free iff no codeword's top len bits equal
+// its successor's.
+struct Coded {
+    uint64_t key;
+    uint32_t len, sym;
+};
+
+int sorted_codes(const wt_shape& sh, uint32_t sigma, uint32_t h, std::vector<Coded>& cs, uint64_t* nnodes)
+{
+    cs.clear();
+    for (uint32_t x = 0; x < sigma; x++)
+        if (sh.code_len[x]) cs.push_back(Coded{(uint64_t)sh.codes[x] << (h - sh.code_len[x]), sh.code_len[x], x});
+    std::sort(cs.begin(), cs.end(), [](const Coded& a, const Coded& b) { return a.key < b.key; });
+    uint64_t nodes = 0;
+    for (size_t i = 0; i < cs.size(); i++) {
+        uint32_t lcp = 0;
+        if (i) {
+            const uint64_t x = cs[i - 1].key ^ cs[i].key;
+            lcp = x ? (uint32_t)__builtin_clzll(x) - (64 - h) : h;
+            if (lcp >= std::min(cs[i - 1].len, cs[i].len)) return WT_EINVAL;   // one code is a prefix of the other
+            nodes += cs[i].len - 1 - lcp;
+        } else {
+            nodes += cs[i].len;
+        }
+    }
+    *nnodes = nodes;
+    return WT_OK;
+}
+
 int make_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt_shape* shape,
               const wt_tuning* tune, Plan& p)
 {
@@ -108,13 +140,9 @@ int make_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt
     for (uint32_t l = 0; l < p.nlevels; l++) p.lin.level_n[l] = level_n[l];
     if (kind == WT_KIND_SHAPED) {
         // internal nodes: distinct proper prefixes of the codewords
-        std::vector<std::pair<uint32_t, uint64_t>> keys;
-        for (uint32_t s = 0; s < sigma; s++)
-            for (uint32_t l = 0; l < shape->code_len[s]; l++)
-                keys.emplace_back(l, l ? shape->codes[s] >> (shape->code_len[s] - l) : 0ull);
-        std::sort(keys.begin(), keys.end());
-        keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
-        p.nnodes_image = keys.size();
+        std::vector<Coded> cs;
+        const int rc = sorted_codes(*shape, sigma, p.key_bits, cs, &p.nnodes_image);
+        if (rc) return rc;
         p.lin.nnodes = p.nnodes_image;
     }
     wv_layout(p.lin, p.lay);
@@ -285,69 +313,82 @@ int balanced_nodes(const std::vector<uint64_t>& counts, uint32_t sigma, uint32_t
 // Shaped tree (Sec. 4.3): internal nodes are the proper codeword prefixes,
 // ordered by (level, prefix); the start of a node on its level is the number
 // of symbols of that level under smaller prefixes.  Also fills the image's
-// node-table records.
+// node-table records.  Built level by level from the codewords in padded
+// order, in which the prefixes of one length come out sorted.
 int shaped_nodes(const wt_shape& sh, uint32_t sigma, HostNodes& H, std::vector<uint8_t>& rec)
 {
-    std::vector<std::pair<uint32_t, uint64_t>> keys;
-    for (uint32_t s = 0; s < sigma; s++)
-        for (uint32_t l = 0; l < sh.code_len[s]; l++)
-            keys.emplace_back(l, l ? sh.codes[s] >> (sh.code_len[s] - l) : 0ull);
-    std::sort(keys.begin(), keys.end());
-    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
-    const uint64_t N = keys.size();
-    auto find = [&](uint32_t l, uint64_t p) -> int64_t {
-        auto it = std::lower_bound(keys.begin(), keys.end(), std::make_pair(l, p));
-        if (it == keys.end() || it->first != l || it->second != p) return -1;
-        return it - keys.begin();
-    };
-    std::map<std::pair<uint32_t, uint64_t>, uint32_t> leaf;   // (len, code) -> symbol
-    for (uint32_t s = 0; s < sigma; s++) {
-        if (!sh.code_len[s]) continue;
-        auto k = std::make_pair(sh.code_len[s], sh.codes[s]);
-        if (leaf.count(k) || find(k.first, k.second) >= 0) return WT_EINVAL;   // not prefix-free
-        leaf[k] = s;
+    uint32_t h = 0;
+    for (uint32_t x = 0; x < sigma; x++) h = std::max(h, sh.code_len[x]);
+    std::vector<Coded> cs;
+    uint64_t N = 0;
+    int rc = sorted_codes(sh, sigma, h, cs, &N);
+    if (rc) return rc;
+    // per level: node prefixes (sorted), their symbol counts, and the leaves
+    // (code, symbol) whose codes end one level below
+    std::vector<std::vector<uint64_t>> pre(h), cnt(h);
+    std::vector<std::vector<std::pair<uint64_t, uint32_t>>> leaf(h + 1);
+    for (uint32_t l = 0; l < h; l++) {
+        for (const Coded& c : cs) {
+            if (c.len <= l) continue;
+            const uint64_t q = c.key >> (h - l);
+            if (pre[l].empty() || pre[l].back() != q) {
+                pre[l].push_back(q);
+                cnt[l].push_back(0);
+            }
+            cnt[l].back() += sh.counts[c.sym];
+        }
     }
-    std::vector<uint64_t> cnt(N, 0), start(N, 0);
-    for (uint32_t s = 0; s < sigma; s++)
-        for (uint32_t l = 0; l < sh.code_len[s]; l++)
-            cnt[find(l, l ? sh.codes[s] >> (sh.code_len[s] - l) : 0ull)] += sh.counts[s];
-    uint64_t run = 0;
-    for (uint64_t t = 0; t < N; t++) {
-        if (t == 0 || keys[t].first != keys[t - 1].first) run = 0;
-        start[t] = run;
-        run += cnt[t];
-    }
+    for (const Coded& c : cs) leaf[c.len].push_back({c.key >> (h - c.len), c.sym});
+    std::vector<uint64_t> base(h + 1, 0);
+    for (uint32_t l = 0; l < h; l++) base[l + 1] = base[l] + pre[l].size();
+    if (base[h] != N) return WT_EINVAL;
     H.start.assign(N, 0);
     H.child_start.assign(2 * N, 0);
     H.child.assign(2 * N, WV_NONE);
     rec.assign(N * WV_NODE_BYTES, 0);
-    for (uint64_t t = 0; t < N; t++) {
-        H.start[t] = (uint32_t)start[t];
-        uint32_t ch[2];
-        for (uint32_t b = 0; b < 2; b++) {
-            const uint32_t l1 = keys[t].first + 1;
-            const uint64_t q = keys[t].second * 2 + b;
-            uint32_t c = WV_NONE;
-            uint64_t cs = 0;
-            auto lf = leaf.find(std::make_pair(l1, q));
-            if (lf != leaf.end()) {
-                c = WV_LEAF | lf->second;
-            } else {
-                const int64_t k = find(l1, q);
-                if (k >= 0) { c = (uint32_t)k; cs = start[k]; }
-            }
-            ch[b] = c;
-            H.child[2 * t + b] = c;
-            H.child_start[2 * t + b] = (uint32_t)cs;
+    std::vector<uint64_t> start(N, 0);
+    for (uint32_t l = 0; l < h; l++) {
+        uint64_t run = 0;
+        for (uint64_t k = 0; k < pre[l].size(); k++) {
+            start[base[l] + k] = run;
+            run += cnt[l][k];
         }
-        uint8_t* e = rec.data() + t * WV_NODE_BYTES;
-        const uint32_t lev = keys[t].first, pre = (uint32_t)keys[t].second;
-        std::memcpy(e + 0, &start[t], 8);
-        std::memcpy(e + 8, &cnt[t], 8);
-        std::memcpy(e + 16, &ch[0], 4);
-        std::memcpy(e + 20, &ch[1], 4);
-        std::memcpy(e + 24, &lev, 4);
-        std::memcpy(e + 28, &pre, 4);
+    }
+    for (uint32_t l = 0; l < h; l++) {
+        for (uint64_t k = 0; k < pre[l].size(); k++) {
+            const uint64_t t = base[l] + k;
+            H.start[t] = (uint32_t)start[t];
+            uint32_t ch[2];
+            for (uint32_t b = 0; b < 2; b++) {
+                const uint64_t q = pre[l][k] * 2 + b;
+                uint32_t c = WV_NONE;
+                uint64_t cs_ = 0;
+                const auto& lv = leaf[l + 1];
+                auto lf = std::lower_bound(lv.begin(), lv.end(), std::make_pair(q, 0u));
+                if (lf != lv.end() && lf->first == q) {
+                    c = WV_LEAF | lf->second;
+                } else if (l + 1 < h) {
+                    const auto& nx = pre[l + 1];
+                    auto it = std::lower_bound(nx.begin(), nx.end(), q);
+                    if (it != nx.end() && *it == q) {
+                        const uint64_t id = base[l + 1] + (it - nx.begin());
+                        c = (uint32_t)id;
+                        cs_ = start[id];
+                    }
+                }
+                ch[b] = c;
+                H.child[2 * t + b] = c;
+                H.child_start[2 * t + b] = (uint32_t)cs_;
+            }
+            uint8_t* e = rec.data() + t * WV_NODE_BYTES;
+            const uint32_t lev = l, pr = (uint32_t)pre[l][k];
+            std::memcpy(e + 0, &start[t], 8);
+            std::memcpy(e + 8, &cnt[l][k], 8);
+            std::memcpy(e + 16, &ch[0], 4);
+            std::memcpy(e + 20, &ch[1], 4);
+            std::memcpy(e + 24, &lev, 4);
+            std::memcpy(e + 28, &pr, 4);
+        }
     }
     return WT_OK;
 }

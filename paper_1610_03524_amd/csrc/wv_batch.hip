@@ -321,9 +321,14 @@ struct SeqPlan {
 struct BatchPlan {
     std::vector<SeqPlan> seq;
     std::vector<uint32_t> order;     // sequences by decreasing n
-    uint64_t off_desc = 0, desc_bytes = 0, off_queue = 0, ws_bytes = 0;
+    uint64_t off_desc = 0, off_queue = 0, ws_bytes = 0;
     uint64_t zero_lo = 0, zero_hi = 0;   // H region zeroed every round
     uint32_t max_passes = 0, nphases = 0;
+    // descriptor area of every phase (header, every round's two groups, the
+    // directories): offset inside the descriptor region and members
+    std::vector<uint64_t> phase_off;
+    std::vector<uint32_t> phase_members;
+    uint64_t desc_total = 0;
 };
 
 int make_batch_plan(const wt_seq_desc* seqs, uint32_t count, const wt_tuning* tune, BatchPlan& bp)
@@ -375,19 +380,35 @@ int make_batch_plan(const wt_seq_desc* seqs, uint32_t count, const wt_tuning* tu
         for (uint32_t l = 0; l < s.L; l++) s.lin.level_n[l] = s.n;
         wv_layout(s.lin, s.lay);
     }
-    // descriptor area: the largest of (round arrays, span arrays, headers)
-    const uint64_t round_bytes = count * (sizeof(SeqRound) + 8) + 512;
-    const uint64_t span_bytes = total_spans * (sizeof(SpanDesc) + 4) + 256;
-    const uint64_t head_bytes = count * (sizeof(wv_layout_in) + sizeof(uint8_t*)) + 256;
-    bp.desc_bytes = wv_round256(std::max(round_bytes, std::max(span_bytes, head_bytes)));
-    // one descriptor area per phase (header, every round's two groups, the
-    // directories), so no phase overwrites descriptors still being read
-    bp.nphases = 2 + 2 * bp.max_passes;
-    bp.off_desc = bump(bp.desc_bytes * bp.nphases);
-    bp.ws_bytes = off;
     bp.order.resize(count);
     std::iota(bp.order.begin(), bp.order.end(), 0u);
     std::stable_sort(bp.order.begin(), bp.order.end(), [&](uint32_t a, uint32_t b) { return bp.seq[a].n > bp.seq[b].n; });
+    // one descriptor area per phase, each sized for its members, so no phase
+    // overwrites descriptors still being read and one copy moves them all
+    bp.nphases = 2 + 2 * bp.max_passes;
+    bp.phase_off.assign(bp.nphases + 1, 0);
+    bp.phase_members.assign(bp.nphases, 0);
+    auto area = [&](uint32_t ph, uint64_t bytes) {
+        bp.phase_off[ph] = bp.desc_total;
+        bp.desc_total += wv_round256(bytes);
+    };
+    area(0, wv_round256(count * sizeof(uint8_t*)) + count * sizeof(wv_layout_in));
+    for (uint32_t r = 0; r < bp.max_passes; r++) {
+        for (int wide = 0; wide < 2; wide++) {
+            const uint32_t ph = 1 + 2 * r + wide;
+            uint32_t m = 0;
+            for (uint32_t i = 0; i < count; i++) {
+                const SeqPlan& sp = bp.seq[i];
+                if (r < sp.passes && ((sp.L - r * sp.tau > 16) == (wide == 1))) m++;
+            }
+            bp.phase_members[ph] = m;
+            area(ph, wv_round256((uint64_t)m * sizeof(SeqRound)) + wv_round256((uint64_t)m * 4) + (uint64_t)m * 4);
+        }
+    }
+    area(bp.nphases - 1, wv_round256(total_spans * sizeof(SpanDesc)) + total_spans * 4);
+    bp.phase_off[bp.nphases] = bp.desc_total;
+    bp.off_desc = bump(bp.desc_total);
+    bp.ws_bytes = off;
     (void)total_chunks;
     (void)total_dch;
     return WT_OK;
@@ -422,111 +443,86 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
     uint32_t* queue = (uint32_t*)(ws + bp.off_queue);
     const bool prof = tune && (tune->flags & WT_FLAG_PROFILE);
 
-    // host copies of every phase's descriptors live until the final sync
-    std::vector<std::vector<uint8_t>> keep;
-    uint32_t phase = 0;
-    // headers of every image
+    // every phase's descriptors are known on the host up front: they are
+    // written into one host buffer, copied with one call, then every kernel
+    // is launched back to back
+    std::vector<uint8_t> hd(bp.desc_total, 0);
+    auto host_area = [&](uint32_t ph) { return hd.data() + bp.phase_off[ph]; };
+    auto dev_area = [&](uint32_t ph) { return ws + bp.off_desc + bp.phase_off[ph]; };
+
+    // phase 0: headers of every image
     {
-        keep.emplace_back(bp.desc_bytes, 0);
-        std::vector<uint8_t>& host = keep.back();
-        uint8_t* desc = ws + bp.off_desc + bp.desc_bytes * phase++;
-        uint8_t** imgs = (uint8_t**)host.data();
-        wv_layout_in* lins = (wv_layout_in*)(host.data() + wv_round256(count * sizeof(uint8_t*)));
+        uint8_t** imgs = (uint8_t**)host_area(0);
+        wv_layout_in* lins = (wv_layout_in*)(host_area(0) + wv_round256(count * sizeof(uint8_t*)));
         for (uint32_t i = 0; i < count; i++) {
             imgs[i] = (uint8_t*)seqs[i].out;
             lins[i] = bp.seq[i].lin;
         }
-        WV_TIMED(prof, s, "b_desc_copy",
-                 WV_CHECK(hipMemcpyAsync(desc, host.data(), bp.desc_bytes, hipMemcpyHostToDevice, s)));
-        WV_TIMED(prof, s, "b_header",
-                 (b_header_k<<<count, 256, 0, s>>>((uint8_t* const*)desc,
-                                                   (const wv_layout_in*)(desc + wv_round256(count * sizeof(uint8_t*))))));
-        WV_CHECK(hipGetLastError());
     }
-
-    std::vector<const void*> cur_in(count);
-    std::vector<uint32_t> cur_bytes(count);
-    for (uint32_t i = 0; i < count; i++) { cur_in[i] = seqs[i].S; cur_bytes[i] = seqs[i].sym_bytes; }
-
-    for (uint32_t r = 0; r < bp.max_passes; r++) {
-        // two groups: keys up to 16 bits (16-bit LDS keys) and wider ones
-        for (int wide = 0; wide < 2; wide++) {
-            uint8_t* desc = ws + bp.off_desc + bp.desc_bytes * phase++;
-            std::vector<uint32_t> members;
-            for (uint32_t i : bp.order) {
-                const SeqPlan& sp = bp.seq[i];
-                if (r >= sp.passes) continue;
-                const uint32_t R = sp.L - r * sp.tau;
-                if ((R > 16) != (wide == 1)) continue;
-                members.push_back(i);
-            }
-            if (members.empty()) continue;
-            keep.emplace_back(bp.desc_bytes, 0);
-            std::vector<uint8_t>& host = keep.back();
-            const uint32_t m = (uint32_t)members.size();
-            SeqRound* q = (SeqRound*)host.data();
-            uint32_t* first = (uint32_t*)(host.data() + wv_round256((uint64_t)m * sizeof(SeqRound)));
-            uint32_t* cfirst = first + wv_round256((uint64_t)m * 4) / 4;
-            uint32_t chunks = 0, cols = 0;
-            for (uint32_t k = 0; k < m; k++) {
-                const uint32_t i = members[k];
-                const SeqPlan& sp = bp.seq[i];
-                const uint32_t l0 = r * sp.tau, tau = std::min(sp.tau, sp.L - l0), R = sp.L - l0, rem = R - tau;
-                SeqRound& e = q[k];
-                e.pa.in = cur_in[i];
-                e.pa.pay_out = rem ? (void*)(ws + sp.off_pay[r & 1]) : nullptr;
-                for (uint32_t j = 0; j < tau; j++) e.pa.words[j] = (uint64_t*)((uint8_t*)seqs[i].out + sp.lay.lv[l0 + j].bits_off);
-                e.pa.G0 = (const uint32_t*)(ws + sp.off_G0);
-                e.pa.n = (uint32_t)sp.n; e.pa.C = sp.C; e.pa.K = sp.K; e.pa.R = R; e.pa.tau = tau;
-                e.pa.keymask = r == 0 ? (sp.L >= 32 ? ~0u : ((1u << sp.L) - 1u)) : ~0u;
-                e.H = (uint32_t*)(ws + sp.off_H);
-                e.tot = (uint32_t*)(ws + sp.off_tot);
-                e.status = r == 0 ? (uint32_t*)((uint8_t*)seqs[i].out + 36) : nullptr;
-                e.in_bytes = cur_bytes[i];
-                e.out_bytes = rem ? width_of(rem) : 1;
-                e.sigma = sp.sigma;
-                e.chunk0 = chunks;
-                first[k] = chunks;
-                chunks += sp.K;
-                e.col0 = cols;
-                cfirst[k] = cols;
-                cols += 1u << tau;
-            }
-            WV_TIMED(prof, s, "b_desc_copy",
-                     WV_CHECK(hipMemcpyAsync(desc, host.data(), bp.desc_bytes, hipMemcpyHostToDevice, s)));
-            const SeqRound* dq = (const SeqRound*)desc;
-            const uint32_t* dfirst = (const uint32_t*)(desc + wv_round256((uint64_t)m * sizeof(SeqRound)));
-            const uint32_t* dcfirst = dfirst + wv_round256((uint64_t)m * 4) / 4;
-            const uint64_t hz = (bp.zero_hi - bp.zero_lo) / 4;
-            const uint32_t zb = (uint32_t)std::min<uint64_t>(wv_cdiv(hz, 256), 4096);
-            WV_TIMED(prof, s, "b_zero",
-                     ((b_zero_k<<<zb, 256, 0, s>>>((uint32_t*)(ws + bp.zero_lo), hz)),
-                      (b_zero_k<<<1, 64, 0, s>>>(queue, 1))));
-            WV_TIMED(prof, s, "b_hist", (b_hist_k<<<chunks * HSPLIT, HT, 0, s>>>(dq, dfirst, m)));
-            WV_TIMED(prof, s, "b_scan", (b_scan_k<<<wv_cdiv(cols, HT / 64), HT, 0, s>>>(dq, dcfirst, m, cols)));
-            WV_TIMED(prof, s, "b_offsets", (b_offsets_k<<<chunks, HT, 0, s>>>(dq, dfirst, m)));
-            const uint32_t workers = std::min<uint32_t>(chunks, KMAX);
-            WV_TIMED(prof, s, "b_pass",
-                     (wide ? (void)(b_pass_k<uint32_t><<<workers, NT, 0, s>>>(dq, dfirst, m, chunks, queue))
-                           : (void)(b_pass_k<uint16_t><<<workers, NT, 0, s>>>(dq, dfirst, m, chunks, queue))));
-            WV_CHECK(hipGetLastError());
-            for (uint32_t k = 0; k < m; k++) {
-                const uint32_t i = members[k];
-                if (q[k].pa.pay_out) { cur_in[i] = q[k].pa.pay_out; cur_bytes[i] = q[k].out_bytes; }
+    // rounds of passes: two groups per round, keys up to 16 bits (16-bit LDS
+    // keys) and wider ones
+    struct Group { uint32_t phase, m, chunks, cols; bool wide; };
+    std::vector<Group> groups;
+    {
+        std::vector<const void*> cur_in(count);
+        std::vector<uint32_t> cur_bytes(count);
+        for (uint32_t i = 0; i < count; i++) { cur_in[i] = seqs[i].S; cur_bytes[i] = seqs[i].sym_bytes; }
+        uint32_t phase = 1;
+        for (uint32_t r = 0; r < bp.max_passes; r++) {
+            for (int wide = 0; wide < 2; wide++, phase++) {
+                std::vector<uint32_t> members;
+                for (uint32_t i : bp.order) {
+                    const SeqPlan& sp = bp.seq[i];
+                    if (r >= sp.passes) continue;
+                    const uint32_t R = sp.L - r * sp.tau;
+                    if ((R > 16) != (wide == 1)) continue;
+                    members.push_back(i);
+                }
+                if (members.empty()) continue;
+                const uint32_t m = (uint32_t)members.size();
+                if (m != bp.phase_members[phase]) return WT_EINVAL;   // the plan and the build disagree
+                SeqRound* q = (SeqRound*)host_area(phase);
+                uint32_t* first = (uint32_t*)(host_area(phase) + wv_round256((uint64_t)m * sizeof(SeqRound)));
+                uint32_t* cfirst = first + wv_round256((uint64_t)m * 4) / 4;
+                uint32_t chunks = 0, cols = 0;
+                for (uint32_t k = 0; k < m; k++) {
+                    const uint32_t i = members[k];
+                    const SeqPlan& sp = bp.seq[i];
+                    const uint32_t l0 = r * sp.tau, tau = std::min(sp.tau, sp.L - l0), R = sp.L - l0, rem = R - tau;
+                    SeqRound& e = q[k];
+                    e.pa.in = cur_in[i];
+                    e.pa.pay_out = rem ? (void*)(ws + sp.off_pay[r & 1]) : nullptr;
+                    for (uint32_t j = 0; j < tau; j++)
+                        e.pa.words[j] = (uint64_t*)((uint8_t*)seqs[i].out + sp.lay.lv[l0 + j].bits_off);
+                    e.pa.G0 = (const uint32_t*)(ws + sp.off_G0);
+                    e.pa.n = (uint32_t)sp.n; e.pa.C = sp.C; e.pa.K = sp.K; e.pa.R = R; e.pa.tau = tau;
+                    e.pa.keymask = r == 0 ? (sp.L >= 32 ? ~0u : ((1u << sp.L) - 1u)) : ~0u;
+                    e.H = (uint32_t*)(ws + sp.off_H);
+                    e.tot = (uint32_t*)(ws + sp.off_tot);
+                    e.status = r == 0 ? (uint32_t*)((uint8_t*)seqs[i].out + 36) : nullptr;
+                    e.in_bytes = cur_bytes[i];
+                    e.out_bytes = rem ? width_of(rem) : 1;
+                    e.sigma = sp.sigma;
+                    e.chunk0 = chunks;
+                    first[k] = chunks;
+                    chunks += sp.K;
+                    e.col0 = cols;
+                    cfirst[k] = cols;
+                    cols += 1u << tau;
+                    if (e.pa.pay_out) { cur_in[i] = e.pa.pay_out; cur_bytes[i] = e.out_bytes; }
+                }
+                groups.push_back(Group{phase, m, chunks, cols, wide == 1});
             }
         }
     }
-
-    // directories of every level of every sequence
+    // last phase: the directories of every level of every sequence
+    const uint32_t dphase = bp.nphases - 1;
+    uint32_t nspan = 0, dchunks = 0;
     {
-        keep.emplace_back(bp.desc_bytes, 0);
-        std::vector<uint8_t>& host = keep.back();
-        uint8_t* desc = ws + bp.off_desc + bp.desc_bytes * (bp.nphases - 1);
-        uint32_t nspan = 0;
         for (uint32_t i = 0; i < count; i++) nspan += bp.seq[i].L;
-        SpanDesc* sd = (SpanDesc*)host.data();
-        uint32_t* first = (uint32_t*)(host.data() + wv_round256((uint64_t)nspan * sizeof(SpanDesc)));
-        uint32_t k = 0, chunks = 0;
+        SpanDesc* sd = (SpanDesc*)host_area(dphase);
+        uint32_t* first = (uint32_t*)(host_area(dphase) + wv_round256((uint64_t)nspan * sizeof(SpanDesc)));
+        uint32_t k = 0;
         for (uint32_t i = 0; i < count; i++) {
             const SeqPlan& sp = bp.seq[i];
             const uint64_t dch = wv_cdiv(wv_cdiv(sp.n, 64), SDW);
@@ -542,21 +538,49 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
                 d.cnt = (uint32_t*)(ws + sp.off_dcnt) + l * std::max<uint64_t>(dch, 1);
                 d.pre = (uint64_t*)(ws + sp.off_dpre) + l * std::max<uint64_t>(dch, 1);
                 d.level = l;
-                d.chunk0 = chunks;
-                first[k] = chunks;
-                chunks += (uint32_t)dch;
+                d.chunk0 = dchunks;
+                first[k] = dchunks;
+                dchunks += (uint32_t)dch;
             }
         }
-        WV_TIMED(prof, s, "b_desc_copy",
-                 WV_CHECK(hipMemcpyAsync(desc, host.data(), bp.desc_bytes, hipMemcpyHostToDevice, s)));
+    }
+
+    WV_TIMED(prof, s, "b_desc_copy",
+             WV_CHECK(hipMemcpyAsync(ws + bp.off_desc, hd.data(), hd.size(), hipMemcpyHostToDevice, s)));
+    WV_TIMED(prof, s, "b_header",
+             (b_header_k<<<count, 256, 0, s>>>((uint8_t* const*)dev_area(0),
+                                               (const wv_layout_in*)(dev_area(0) + wv_round256(count * sizeof(uint8_t*))))));
+    WV_CHECK(hipGetLastError());
+    for (const Group& g : groups) {
+        uint8_t* desc = dev_area(g.phase);
+        const SeqRound* dq = (const SeqRound*)desc;
+        const uint32_t* dfirst = (const uint32_t*)(desc + wv_round256((uint64_t)g.m * sizeof(SeqRound)));
+        const uint32_t* dcfirst = dfirst + wv_round256((uint64_t)g.m * 4) / 4;
+        const uint64_t hz = (bp.zero_hi - bp.zero_lo) / 4;
+        const uint32_t zb = (uint32_t)std::min<uint64_t>(wv_cdiv(hz, 256), 4096);
+        WV_TIMED(prof, s, "b_zero",
+                 ((b_zero_k<<<zb, 256, 0, s>>>((uint32_t*)(ws + bp.zero_lo), hz)),
+                  (b_zero_k<<<1, 64, 0, s>>>(queue, 1))));
+        WV_TIMED(prof, s, "b_hist", (b_hist_k<<<g.chunks * HSPLIT, HT, 0, s>>>(dq, dfirst, g.m)));
+        WV_TIMED(prof, s, "b_scan", (b_scan_k<<<wv_cdiv(g.cols, HT / 64), HT, 0, s>>>(dq, dcfirst, g.m, g.cols)));
+        WV_TIMED(prof, s, "b_offsets", (b_offsets_k<<<g.chunks, HT, 0, s>>>(dq, dfirst, g.m)));
+        const uint32_t workers = std::min<uint32_t>(g.chunks, KMAX);
+        WV_TIMED(prof, s, "b_pass",
+                 (g.wide ? (void)(b_pass_k<uint32_t><<<workers, NT, 0, s>>>(dq, dfirst, g.m, g.chunks, queue))
+                         : (void)(b_pass_k<uint16_t><<<workers, NT, 0, s>>>(dq, dfirst, g.m, g.chunks, queue))));
+        WV_CHECK(hipGetLastError());
+    }
+    {
+        uint8_t* desc = dev_area(dphase);
         const SpanDesc* dsd = (const SpanDesc*)desc;
         const uint32_t* dfirst = (const uint32_t*)(desc + wv_round256((uint64_t)nspan * sizeof(SpanDesc)));
-        if (chunks) WV_TIMED(prof, s, "b_dir_count", (b_dir_count_k<<<chunks, 256, 0, s>>>(dsd, dfirst, nspan)));
+        if (dchunks) WV_TIMED(prof, s, "b_dir_count", (b_dir_count_k<<<dchunks, 256, 0, s>>>(dsd, dfirst, nspan)));
         WV_TIMED(prof, s, "b_dir_scan", (b_dir_scan_k<<<nspan, 256, 0, s>>>(dsd)));
-        if (chunks) WV_TIMED(prof, s, "b_dir_write", (b_dir_write_k<<<chunks, 256, 0, s>>>(dsd, dfirst, nspan)));
+        if (dchunks) WV_TIMED(prof, s, "b_dir_write", (b_dir_write_k<<<dchunks, 256, 0, s>>>(dsd, dfirst, nspan)));
         WV_CHECK(hipGetLastError());
-        WV_CHECK(hipStreamSynchronize(s));
     }
+    // the host descriptor buffer is read by the copy above: finish first
+    WV_CHECK(hipStreamSynchronize(s));
     return WT_OK;
 }
 

@@ -184,9 +184,9 @@ __device__ inline uint64_t wv_rank0(const uint64_t* __restrict__ words,
 __device__ inline uint32_t wv_count_digit(uint64_t w, uint32_t D, uint32_t g, uint32_t t)
 {
     if (t == 0) return 0;
-    // low-bit-of-every-digit mask
-    uint64_t lowm = 0;
-    for (uint32_t s = 0; s < 64 / D; s++) lowm |= 1ull << (s * D);
+    // low-bit-of-every-digit mask: bits 0, D, 2D, ... of the P = 64/D digits
+    const uint32_t used = (64u / D) * D;
+    const uint64_t lowm = (used >= 64 ? ~0ull : ((1ull << used) - 1ull)) / ((1ull << D) - 1ull);
     uint64_t pat = lowm * (uint64_t)g;
     uint64_t x = w ^ pat;               // digit == g  <=>  digit of x == 0
     uint64_t any = x;

@@ -120,48 +120,46 @@ dir_finish_k(uint8_t* __restrict__ image, uint32_t level, wv_level L,
 
 // ---- multiary counters -------------------------------------------------------
 
+// multiary counters, one wave per range of 64 words (lane = word)
 __global__ void __launch_bounds__(DIR_THREADS)
 mcount_k(const uint64_t* __restrict__ words, uint64_t m, uint32_t D, uint32_t* __restrict__ rng_cnt)
 {
-    const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t r = ((uint64_t)blockIdx.x * DIR_THREADS + threadIdx.x) >> 6;
     const uint32_t P = 64u / D, d = 1u << D;
     const uint64_t nr = wv_mranges(m, D), nw = wv_cdiv(m, P);
-    if (r >= nr) return;
-    uint32_t c[16];
-    for (uint32_t g = 0; g < 16; g++) c[g] = 0;
-    for (uint64_t wi = 64 * r; wi < 64 * r + 64 && wi < nw; wi++) {
-        const uint64_t w = words[wi];
-        const uint64_t left = m - wi * P;
-        const uint32_t valid = left >= P ? P : (uint32_t)left;
-        for (uint32_t g = 0; g < d; g++) c[g] += wv_count_digit(w, D, g, valid);
+    if (r >= nr) return;   // whole waves: the scans below need every lane
+    const uint64_t wi = 64 * r + lane;
+    const uint64_t w = wi < nw ? words[wi] : 0ull;
+    const uint32_t t = wi < nw ? (uint32_t)min<uint64_t>(P, m - wi * P) : 0u;
+    for (uint32_t g = 0; g < d; g++) {
+        const uint32_t inc = wv_wave_incl_scan(wv_count_digit(w, D, g, t));
+        if (lane == 63) rng_cnt[r * d + g] = inc;
     }
-    for (uint32_t g = 0; g < d; g++) rng_cnt[r * d + g] = c[g];
 }
 
 __global__ void __launch_bounds__(DIR_THREADS)
 mwrite_k(uint8_t* __restrict__ image, wv_level L, uint32_t D, const uint64_t* __restrict__ rng_pre)
 {
-    const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t r = ((uint64_t)blockIdx.x * DIR_THREADS + threadIdx.x) >> 6;
     const uint64_t m = L.n;
     const uint32_t P = 64u / D, d = 1u << D;
     const uint64_t nr = wv_mranges(m, D), nsub = wv_msubs(m, D), nw = wv_cdiv(m, P);
-    if (r >= nr) return;
+    if (r >= nr) return;   // whole waves
     const uint64_t* words = (const uint64_t*)(image + L.bits_off);
     uint64_t* rng = (uint64_t*)(image + L.rank_off);
     uint16_t* sub = (uint16_t*)(image + L.rank_off + (nr + 1) * d * 8);
-    for (uint32_t g = 0; g < d; g++) rng[r * d + g] = rng_pre[r * d + g];
-    uint32_t c[16];
-    for (uint32_t g = 0; g < 16; g++) c[g] = 0;
-    for (uint32_t s = 0; s < 8; s++) {
-        const uint64_t sk = 8 * r + s;
-        if (sk >= nsub) break;
-        for (uint32_t g = 0; g < d; g++) sub[sk * d + g] = (uint16_t)c[g];
-        for (uint64_t wi = sk * 8; wi < sk * 8 + 8 && wi < nw; wi++) {
-            const uint64_t w = words[wi];
-            const uint64_t left = m - wi * P;
-            const uint32_t valid = left >= P ? P : (uint32_t)left;
-            for (uint32_t g = 0; g < d; g++) c[g] += wv_count_digit(w, D, g, valid);
-        }
+    if (lane < d) rng[r * d + lane] = rng_pre[r * d + lane];
+    const uint64_t wi = 64 * r + lane;
+    const uint64_t w = wi < nw ? words[wi] : 0ull;
+    const uint32_t t = wi < nw ? (uint32_t)min<uint64_t>(P, m - wi * P) : 0u;
+    // a sub-range of 8 words stores every digit's count from the range start
+    const uint64_t sk = 8 * r + (lane >> 3);
+    for (uint32_t g = 0; g < d; g++) {
+        const uint32_t v = wv_count_digit(w, D, g, t);
+        const uint32_t ex = wv_wave_incl_scan(v) - v;
+        if ((lane & 7) == 0 && sk < nsub) sub[sk * d + g] = (uint16_t)ex;
     }
 }
 
@@ -328,11 +326,11 @@ hipError_t wv_multiary_counters(uint8_t* image, const wv_level& L, uint32_t D,
 {
     const uint64_t nr = wv_mranges(L.n, D);
     const uint32_t d = 1u << D;
-    if (nr) mcount_k<<<(uint32_t)wv_cdiv(nr, DIR_THREADS), DIR_THREADS, 0, s>>>(
+    if (nr) mcount_k<<<(uint32_t)wv_cdiv(nr, DIR_THREADS / 64), DIR_THREADS, 0, s>>>(
         (const uint64_t*)(image + L.bits_off), L.n, D, sc.rng_cnt);
     hipError_t e = wv_scan_u32(sc.rng_cnt, sc.rng_pre, nr, d, sc.partial, sc.totals, s);
     if (e != hipSuccess) return e;
-    if (nr) mwrite_k<<<(uint32_t)wv_cdiv(nr, DIR_THREADS), DIR_THREADS, 0, s>>>(image, L, D, sc.rng_pre);
+    if (nr) mwrite_k<<<(uint32_t)wv_cdiv(nr, DIR_THREADS / 64), DIR_THREADS, 0, s>>>(image, L, D, sc.rng_pre);
     mfinish_k<<<1, 64, 0, s>>>(image, L, D, sc.totals);
     return hipGetLastError();
 }

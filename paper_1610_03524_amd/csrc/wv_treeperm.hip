@@ -101,44 +101,77 @@ __device__ inline uint64_t spread(uint64_t x, uint32_t D)
 // at position i there has its digit's D bits on matrix levels bD .. bD+D-1,
 // each level's position found from the previous one by the matrix map (a
 // zero moves to its rank among zeros, a one to Z + its rank among ones).
-// One wave per 64 positions; its 64 digits fill D words of the digit string
-// (digit e at bits D*e .. D*e+D-1, low bit first).
+// A wave takes DW consecutive words of level bD (64 positions each, padding
+// bits 0): one rank query per word and the zeros below each lane give every
+// position's place on the next level; the loads of the DW words are issued
+// together.  The 64 digits of a word fill D words of the digit string (digit
+// e at bits D*e .. D*e+D-1, low bit first).
+constexpr uint32_t DW = 8;
+
+template <uint32_t D>
 __global__ void __launch_bounds__(256)
-digits_k(wv_digit_levels a, uint64_t n, uint32_t D, uint64_t nwords, uint64_t* __restrict__ out)
+digits_k(wv_digit_levels a, uint64_t n, uint64_t nwords, uint64_t* __restrict__ out)
 {
     const uint32_t lane = threadIdx.x & 63;
-    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    const uint64_t base = i - lane;
-    if (base >= n) return;   // whole waves: the ballots below need every lane
-    uint32_t d = 0;
-    if (i < n) {
-        uint64_t p = i;
-        for (uint32_t k = 0; k < D; k++) {
-            const uint32_t bit = (uint32_t)(a.words[k][p >> 6] >> (p & 63)) & 1u;
-            d = (d << 1) | bit;
-            if (k + 1 < D) {
-                const uint64_t r0 = wv_rank0(a.words[k], a.dir[k], p);
-                p = bit ? wv_rank0(a.words[k], a.dir[k], n) + (p - r0) : r0;
+    const uint64_t wave = ((uint64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const uint64_t nw0 = wv_cdiv(n, 64);
+    const uint64_t bw = wave * DW;
+    if (bw >= nw0) return;   // whole waves: the ballots below need every lane
+    uint64_t w0[DW], rb[DW];
+#pragma unroll
+    for (uint32_t j = 0; j < DW; j++) w0[j] = bw + j < nw0 ? a.words[0][bw + j] : 0ull;
+    uint32_t d[DW];
+#pragma unroll
+    for (uint32_t j = 0; j < DW; j++) d[j] = (uint32_t)(w0[j] >> lane) & 1u;
+    if (D > 1) {
+#pragma unroll
+        for (uint32_t j = 0; j < DW; j++) rb[j] = bw + j < nw0 ? wv_rank0(a.words[0], a.dir[0], (bw + j) * 64) : 0ull;
+        const uint64_t Z0 = wv_rank0(a.words[0], a.dir[0], n);
+        uint64_t p[DW];
+#pragma unroll
+        for (uint32_t j = 0; j < DW; j++) {
+            const uint64_t i = (bw + j) * 64 + lane;
+            const uint64_t r0 = rb[j] + __builtin_amdgcn_mbcnt_hi((uint32_t)(~w0[j] >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)~w0[j], 0u));
+            p[j] = d[j] ? Z0 + (i - r0) : r0;
+        }
+#pragma unroll
+        for (uint32_t k = 1; k < D; k++) {
+            const uint64_t Zk = k + 1 < D ? wv_rank0(a.words[k], a.dir[k], n) : 0ull;
+#pragma unroll
+            for (uint32_t j = 0; j < DW; j++) {
+                if ((bw + j) * 64 + lane >= n) continue;
+                const uint32_t bit = (uint32_t)(a.words[k][p[j] >> 6] >> (p[j] & 63)) & 1u;
+                d[j] = (d[j] << 1) | bit;
+                if (k + 1 < D) {
+                    const uint64_t rk = wv_rank0(a.words[k], a.dir[k], p[j]);
+                    p[j] = bit ? Zk + (p[j] - rk) : rk;
+                }
             }
         }
     }
     const uint32_t per = 64 / D;
     const uint64_t pmask = per == 64 ? ~0ull : ((1ull << per) - 1ull);
-    uint64_t bt[4];
-    for (uint32_t t = 0; t < 4; t++) bt[t] = t < D ? __ballot((d >> t) & 1u) : 0ull;
-    if (lane < D) {
-        uint64_t w = 0;
-        for (uint32_t t = 0; t < D; t++) w |= spread((bt[t] >> (lane * per)) & pmask, D) << t;
-        const uint64_t wi = (base / 64) * D + lane;
-        if (wi < nwords) out[wi] = w;
+#pragma unroll
+    for (uint32_t j = 0; j < DW; j++) {
+        if (bw + j >= nw0) break;   // uniform
+        const uint32_t dj = (bw + j) * 64 + lane < n ? d[j] : 0u;
+        uint64_t bt[D];
+#pragma unroll
+        for (uint32_t t = 0; t < D; t++) bt[t] = __ballot((dj >> t) & 1u);
+        if (lane < D) {
+            uint64_t w = 0;
+#pragma unroll
+            for (uint32_t t = 0; t < D; t++) w |= spread((bt[t] >> (lane * per)) & pmask, D) << t;
+            const uint64_t wi = (bw + j) * D + lane;
+            if (wi < nwords) out[wi] = w;
+        }
     }
 }
 
 inline uint64_t brev_bits(uint64_t v, uint32_t nbits)
 {
-    uint64_t r = 0;
-    for (uint32_t b = 0; b < nbits; b++) r |= ((v >> b) & 1ull) << (nbits - 1 - b);
-    return r;
+    return nbits ? __builtin_bitreverse64(v) >> (64 - nbits) : 0ull;
 }
 
 // groups of one level, in numeric order: (group, symbols, kept on the tree level)
@@ -150,15 +183,15 @@ struct Group {
 // matrix and tree offsets of the kept groups of one level
 void level_segments(const std::vector<Group>& gs, uint32_t l, std::vector<wv_perm_seg>& out)
 {
-    std::vector<uint32_t> order(gs.size());
-    for (uint32_t i = 0; i < order.size(); i++) order[i] = i;
-    std::sort(order.begin(), order.end(),
-              [&](uint32_t a, uint32_t b) { return brev_bits(gs[a].g, l) < brev_bits(gs[b].g, l); });
+    // matrix order: by bit-reversed group
+    std::vector<std::pair<uint64_t, uint32_t>> order(gs.size());
+    for (uint32_t i = 0; i < order.size(); i++) order[i] = {brev_bits(gs[i].g, l), i};
+    std::sort(order.begin(), order.end());
     std::vector<uint64_t> src(gs.size());
     uint64_t acc = 0;
-    for (uint32_t i : order) {
-        src[i] = acc;
-        acc += gs[i].count;
+    for (const auto& o : order) {
+        src[o.second] = acc;
+        acc += gs[o.second].count;
     }
     uint64_t dst = 0;
     for (uint32_t i = 0; i < gs.size(); i++) {
@@ -212,7 +245,12 @@ hipError_t wv_tree_keys(const void* S, uint64_t n, uint32_t sym_bytes, const uin
 hipError_t wv_tree_digits(const wv_digit_levels& a, uint64_t n, uint32_t D, uint64_t* out, hipStream_t s)
 {
     if (!n) return hipSuccess;
-    digits_k<<<(uint32_t)wv_cdiv(n, 256), 256, 0, s>>>(a, n, D, wv_cdiv(n * D, 64), out);
+    const uint32_t g = (uint32_t)wv_cdiv(wv_cdiv(wv_cdiv(n, 64), DW), 4);   // 4 waves per block
+    const uint64_t nw = wv_cdiv(n * D, 64);
+    if (D == 1) digits_k<1><<<g, 256, 0, s>>>(a, n, nw, out);
+    else if (D == 2) digits_k<2><<<g, 256, 0, s>>>(a, n, nw, out);
+    else if (D == 4) digits_k<4><<<g, 256, 0, s>>>(a, n, nw, out);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

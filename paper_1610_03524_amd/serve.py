@@ -24,6 +24,7 @@ from __future__ import annotations
 
 import collections
 import ctypes
+import sys
 import threading
 import time
 from dataclasses import dataclass, field
@@ -31,6 +32,9 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import binding as B
+
+
+SWITCH_INTERVAL_S = 2e-4
 
 
 @dataclass
@@ -107,6 +111,11 @@ class WaveletServer:
 
     # ---- workers ------------------------------------------------------------------
     def start(self):
+        # Python hands the interpreter between threads every switch interval
+        # (5 ms by default); a worker woken while another thread runs Python
+        # code would wait that long, so the server shortens it while running
+        self._switch = sys.getswitchinterval()
+        sys.setswitchinterval(SWITCH_INTERVAL_S)
         if self.mode == "continuous":
             self.threads = [threading.Thread(target=self._build_loop, daemon=True),
                             threading.Thread(target=self._query_loop, daemon=True)]
@@ -121,6 +130,7 @@ class WaveletServer:
             self.lock.notify_all()
         for t in self.threads:
             t.join()
+        sys.setswitchinterval(self._switch)
 
     def _costs(self, seq):
         """(image bytes, batch-workspace bytes) of one sequence, cached; the

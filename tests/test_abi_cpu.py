@@ -87,3 +87,32 @@ def test_plan_errors():
                                                       np.array([1, 1, 1])))
     assert e.value.code == B.WT_ERANGE
     assert "out of range" in B.strerror(B.WT_ERANGE)
+
+
+@pytest.mark.parametrize("codes, lens", [
+    ([0, 1, 2], [1, 2, 2]),      # "0" is a prefix of "01"
+    ([1, 1, 0], [2, 2, 1]),      # the same codeword twice
+    ([0, 0, 3], [2, 3, 2]),      # "00" is a prefix of "000"
+])
+def test_plan_rejects_codes_that_are_not_prefix_free(codes, lens):
+    with pytest.raises(B.WaveletError) as e:
+        B.plan(B.KIND_SHAPED, 3, 3, 1, B.make_shape(0, np.array(codes), np.array(lens), np.array([1, 1, 1])))
+    assert e.value.code == B.WT_EINVAL
+
+
+def test_plan_counts_shaped_nodes():
+    """internal nodes = distinct proper prefixes of the codewords, counted
+    from the codewords in padded order"""
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        counts = rng.integers(0, 50, int(rng.integers(2, 300)))
+        counts[rng.integers(0, counts.size)] += 1
+        codes, lens = B.huffman_codes(counts)
+        prefixes = {(l, int(c) >> (int(k) - l)) for c, k in zip(codes, lens) for l in range(int(k))}
+        img_bytes = B.plan(B.KIND_SHAPED, int(counts.sum()), counts.size, 2,
+                           B.make_shape(0, codes, lens, counts)).out_bytes
+        oimg = oracle.build_image(oracle.KIND_SHAPED,
+                                  np.repeat(np.arange(counts.size), counts).astype(np.uint16), counts.size,
+                                  codes=codes, lens=lens)
+        assert img_bytes == oimg.size
+        assert int(oimg[64:72].view(np.uint64)[0]) == len(prefixes)
