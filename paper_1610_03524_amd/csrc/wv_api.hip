@@ -25,7 +25,7 @@ struct Plan {
     wv_layout_out lay{};
     // workspace regions (byte offsets)
     uint64_t ws_scalars = 0, ws_keys_a = 0, ws_keys_b = 0, ws_nodes_a = 0, ws_nodes_b = 0;
-    uint64_t ws_sb_ones = 0, ws_sb_pre = 0, ws_partial = 0, ws_counts = 0;
+    uint64_t ws_sb_ones = 0, ws_sb_pre = 0, ws_partial = 0, ws_counts = 0, ws_mtot = 0;
     uint64_t ws_nt_start = 0, ws_nt_cstart = 0, ws_nt_child = 0, node_bound = 0;
     uint64_t ws_codes = 0, ws_lens = 0, ws_wm = 0;
     // trees gathered from matrix levels (balanced and shaped binary trees)
@@ -165,12 +165,15 @@ int make_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt
     const uint32_t d = 1u << p.D;
     const uint64_t ns = wv_cdiv(n, WV_SB_BITS);
     const uint64_t nr = kind == WT_KIND_MULTIARY ? wv_mranges(n, p.D) : 0;
-    const uint64_t dir_items = std::max<uint64_t>(std::max(ns, nr * d), 1);
+    // multiary counters are built for all levels at once: M * d columns
+    const uint64_t mcols = kind == WT_KIND_MULTIARY ? (uint64_t)d * p.nlevels : 0;
+    const uint64_t dir_items = std::max<uint64_t>(std::max(ns, nr * mcols), 1);
     uint64_t off = 0;
     p.ws_scalars = bump(off, 256);
     p.ws_sb_ones = bump(off, dir_items * 4);
     p.ws_sb_pre = bump(off, dir_items * 8);
-    p.ws_partial = bump(off, 8 * std::max(wv_scan_partials(ns, 1), wv_scan_partials(nr, d)));
+    p.ws_partial = bump(off, 8 * std::max(wv_scan_partials(ns, 1), wv_scan_partials(nr, (uint32_t)mcols)));
+    p.ws_mtot = bump(off, 8 * std::max<uint64_t>(mcols, 1));
     if (kind == WT_KIND_WM && !p.levelwise) {
         int rc = wv_wm_make_plan(n, sigma, sym_bytes, tune, p.wm);
         if (rc) return rc;
@@ -417,7 +420,7 @@ wv_lw_args lw_args(const Plan& p, const void* S, void* out, void* ws)
     a.mdir.rng_cnt = a.dir.sb_ones;
     a.mdir.rng_pre = a.dir.sb_pre;
     a.mdir.partial = a.dir.partial;
-    a.mdir.totals = at<uint64_t>(ws, p.ws_scalars + 16);
+    a.mdir.totals = at<uint64_t>(ws, p.ws_mtot);
     a.zl = at<uint64_t>(ws, p.ws_scalars);
     a.nt.start = at<uint32_t>(ws, p.ws_nt_start);
     a.nt.child_start = at<uint32_t>(ws, p.ws_nt_cstart);
@@ -548,12 +551,11 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
     uint8_t* dscr = at<uint8_t>(ws, p.ws_wm + p.wm.off_dir);
     if (multi) {
         wv_mdir_scratch md{at<uint32_t>(ws, p.ws_sb_ones), at<uint64_t>(ws, p.ws_sb_pre),
-                           at<uint64_t>(ws, p.ws_partial), at<uint64_t>(ws, p.ws_scalars + 16)};
-        for (uint32_t t = 0; t < T; t++)
-            WV_TIMED(prof, s, "mcounters", WV_CHECK(wv_multiary_counters(img, p.lay.lv[t], D, md, s)));
+                           at<uint64_t>(ws, p.ws_partial), at<uint64_t>(ws, p.ws_mtot)};
+        WV_TIMED(prof, s, "mcounters", WV_CHECK(wv_multiary_counters(img, p.lay.lv, T, D, md, s)));
     } else if (shaped) {
-        for (uint32_t l = 0; l < K; l++)
-            WV_CHECK(wv_span_directory(img, p.lay, l, 1, dscr, wv_span_dir_sizes(p.lay.lv[l].n, 1), s, prof));
+        // level 0 is the longest
+        WV_CHECK(wv_span_directory(img, p.lay, 0, K, dscr, wv_span_dir_sizes(p.lay.lv[0].n, K), s, prof));
     } else {
         WV_CHECK(wv_span_directory(img, p.lay, 0, K, dscr, p.wm.dir, s, prof));
     }

@@ -120,55 +120,63 @@ dir_finish_k(uint8_t* __restrict__ image, uint32_t level, wv_level L,
 
 // ---- multiary counters -------------------------------------------------------
 
-// multiary counters, one wave per range of 64 words (lane = word)
+// Multiary counters of M levels of m digits at once (level t = blockIdx.y),
+// one wave per range of 64 words (lane = word).  Range counts and prefixes
+// are laid out [range][level][digit].
+struct MLevels {
+    uint64_t bits_off[WV_MAX_LEVELS], rank_off[WV_MAX_LEVELS];
+    uint64_t m;
+    uint32_t M, D;
+};
+
 __global__ void __launch_bounds__(DIR_THREADS)
-mcount_k(const uint64_t* __restrict__ words, uint64_t m, uint32_t D, uint32_t* __restrict__ rng_cnt)
+mcount_k(const uint8_t* __restrict__ image, MLevels a, uint32_t* __restrict__ rng_cnt)
 {
-    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t lane = threadIdx.x & 63, t = blockIdx.y;
     const uint64_t r = ((uint64_t)blockIdx.x * DIR_THREADS + threadIdx.x) >> 6;
-    const uint32_t P = 64u / D, d = 1u << D;
-    const uint64_t nr = wv_mranges(m, D), nw = wv_cdiv(m, P);
+    const uint32_t D = a.D, P = 64u / D, d = 1u << D;
+    const uint64_t m = a.m, nr = wv_mranges(m, D), nw = wv_cdiv(m, P);
     if (r >= nr) return;   // whole waves: the scans below need every lane
+    const uint64_t* words = (const uint64_t*)(image + a.bits_off[t]);
     const uint64_t wi = 64 * r + lane;
     const uint64_t w = wi < nw ? words[wi] : 0ull;
-    const uint32_t t = wi < nw ? (uint32_t)min<uint64_t>(P, m - wi * P) : 0u;
+    const uint32_t c = wi < nw ? (uint32_t)min<uint64_t>(P, m - wi * P) : 0u;
     for (uint32_t g = 0; g < d; g++) {
-        const uint32_t inc = wv_wave_incl_scan(wv_count_digit(w, D, g, t));
-        if (lane == 63) rng_cnt[r * d + g] = inc;
+        const uint32_t inc = wv_wave_incl_scan(wv_count_digit(w, D, g, c));
+        if (lane == 63) rng_cnt[(r * a.M + t) * d + g] = inc;
     }
 }
 
 __global__ void __launch_bounds__(DIR_THREADS)
-mwrite_k(uint8_t* __restrict__ image, wv_level L, uint32_t D, const uint64_t* __restrict__ rng_pre)
+mwrite_k(uint8_t* __restrict__ image, MLevels a, const uint64_t* __restrict__ rng_pre)
 {
-    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t lane = threadIdx.x & 63, t = blockIdx.y;
     const uint64_t r = ((uint64_t)blockIdx.x * DIR_THREADS + threadIdx.x) >> 6;
-    const uint64_t m = L.n;
-    const uint32_t P = 64u / D, d = 1u << D;
-    const uint64_t nr = wv_mranges(m, D), nsub = wv_msubs(m, D), nw = wv_cdiv(m, P);
+    const uint32_t D = a.D, P = 64u / D, d = 1u << D;
+    const uint64_t m = a.m, nr = wv_mranges(m, D), nsub = wv_msubs(m, D), nw = wv_cdiv(m, P);
     if (r >= nr) return;   // whole waves
-    const uint64_t* words = (const uint64_t*)(image + L.bits_off);
-    uint64_t* rng = (uint64_t*)(image + L.rank_off);
-    uint16_t* sub = (uint16_t*)(image + L.rank_off + (nr + 1) * d * 8);
-    if (lane < d) rng[r * d + lane] = rng_pre[r * d + lane];
+    const uint64_t* words = (const uint64_t*)(image + a.bits_off[t]);
+    uint64_t* rng = (uint64_t*)(image + a.rank_off[t]);
+    uint16_t* sub = (uint16_t*)(image + a.rank_off[t] + (nr + 1) * d * 8);
+    if (lane < d) rng[r * d + lane] = rng_pre[(r * a.M + t) * d + lane];
     const uint64_t wi = 64 * r + lane;
     const uint64_t w = wi < nw ? words[wi] : 0ull;
-    const uint32_t t = wi < nw ? (uint32_t)min<uint64_t>(P, m - wi * P) : 0u;
+    const uint32_t c = wi < nw ? (uint32_t)min<uint64_t>(P, m - wi * P) : 0u;
     // a sub-range of 8 words stores every digit's count from the range start
     const uint64_t sk = 8 * r + (lane >> 3);
     for (uint32_t g = 0; g < d; g++) {
-        const uint32_t v = wv_count_digit(w, D, g, t);
+        const uint32_t v = wv_count_digit(w, D, g, c);
         const uint32_t ex = wv_wave_incl_scan(v) - v;
         if ((lane & 7) == 0 && sk < nsub) sub[sk * d + g] = (uint16_t)ex;
     }
 }
 
-__global__ void mfinish_k(uint8_t* __restrict__ image, wv_level L, uint32_t D, const uint64_t* __restrict__ totals)
+__global__ void mfinish_k(uint8_t* __restrict__ image, MLevels a, const uint64_t* __restrict__ totals)
 {
-    const uint32_t d = 1u << D;
-    const uint64_t nr = wv_mranges(L.n, D);
-    uint64_t* rng = (uint64_t*)(image + L.rank_off);
-    if (threadIdx.x < d) rng[nr * d + threadIdx.x] = totals[threadIdx.x];
+    const uint32_t t = blockIdx.x, d = 1u << a.D;
+    const uint64_t nr = wv_mranges(a.m, a.D);
+    uint64_t* rng = (uint64_t*)(image + a.rank_off[t]);
+    if (threadIdx.x < d) rng[nr * d + threadIdx.x] = totals[t * d + threadIdx.x];
 }
 
 // ---- header ------------------------------------------------------------------
@@ -321,17 +329,26 @@ hipError_t wv_binary_directory(uint8_t* image, uint32_t level, const wv_level& L
     return hipGetLastError();
 }
 
-hipError_t wv_multiary_counters(uint8_t* image, const wv_level& L, uint32_t D,
+hipError_t wv_multiary_counters(uint8_t* image, const wv_level* lv, uint32_t M, uint32_t D,
                                 const wv_mdir_scratch& sc, hipStream_t s)
 {
-    const uint64_t nr = wv_mranges(L.n, D);
+    if (!M) return hipSuccess;
+    MLevels a{};
+    a.m = lv[0].n;
+    a.M = M;
+    a.D = D;
+    for (uint32_t t = 0; t < M; t++) {
+        a.bits_off[t] = lv[t].bits_off;
+        a.rank_off[t] = lv[t].rank_off;
+    }
+    const uint64_t nr = wv_mranges(a.m, D);
     const uint32_t d = 1u << D;
-    if (nr) mcount_k<<<(uint32_t)wv_cdiv(nr, DIR_THREADS / 64), DIR_THREADS, 0, s>>>(
-        (const uint64_t*)(image + L.bits_off), L.n, D, sc.rng_cnt);
-    hipError_t e = wv_scan_u32(sc.rng_cnt, sc.rng_pre, nr, d, sc.partial, sc.totals, s);
+    const dim3 grid((uint32_t)wv_cdiv(nr, DIR_THREADS / 64), M);
+    if (nr) mcount_k<<<grid, DIR_THREADS, 0, s>>>(image, a, sc.rng_cnt);
+    hipError_t e = wv_scan_u32(sc.rng_cnt, sc.rng_pre, nr, M * d, sc.partial, sc.totals, s);
     if (e != hipSuccess) return e;
-    if (nr) mwrite_k<<<(uint32_t)wv_cdiv(nr, DIR_THREADS / 64), DIR_THREADS, 0, s>>>(image, L, D, sc.rng_pre);
-    mfinish_k<<<1, 64, 0, s>>>(image, L, D, sc.totals);
+    if (nr) mwrite_k<<<grid, DIR_THREADS, 0, s>>>(image, a, sc.rng_pre);
+    mfinish_k<<<M, 64, 0, s>>>(image, a, sc.totals);
     return hipGetLastError();
 }
 
@@ -367,7 +384,7 @@ constexpr uint32_t SD_W = 2 * SD_T;            // words per chunk (64 superblock
 
 struct SpanLevels {
     uint64_t bits_off[WV_MAX_LEVELS], rank_off[WV_MAX_LEVELS], sel0_off[WV_MAX_LEVELS], sel1_off[WV_MAX_LEVELS];
-    uint64_t n, nsel;
+    uint64_t n[WV_MAX_LEVELS], nsel[WV_MAX_LEVELS];   // per level (chunks past a level's end count 0)
     uint32_t l0, nl;
 };
 
@@ -376,7 +393,7 @@ span_count_k(const uint8_t* __restrict__ image, SpanLevels a, uint32_t* __restri
 {
     __shared__ uint32_t part[SD_T / 64];
     const uint32_t c = blockIdx.x, l = blockIdx.y;
-    const uint64_t nw = wv_cdiv(a.n, 64);
+    const uint64_t nw = wv_cdiv(a.n[l], 64);
     const uint64_t* words = (const uint64_t*)(image + a.bits_off[l]);
     const uint64_t w0 = (uint64_t)c * SD_W + 2 * threadIdx.x;
     uint32_t o = 0;
@@ -399,7 +416,7 @@ span_write_k(uint8_t* __restrict__ image, SpanLevels a, const uint64_t* __restri
     __shared__ uint64_t zex[SD_W];   // zeros in [0, min(64w, n)) per word of the chunk
     const uint32_t c = blockIdx.x, l = blockIdx.y;
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint64_t n = a.n, nw = wv_cdiv(n, 64), ns = wv_cdiv(n, WV_SB_BITS);
+    const uint64_t n = a.n[l], nw = wv_cdiv(n, 64), ns = wv_cdiv(n, WV_SB_BITS);
     const uint64_t* words = (const uint64_t*)(image + a.bits_off[l]);
     uint64_t* dir = (uint64_t*)(image + a.rank_off[l]);
     uint64_t* sel0 = (uint64_t*)(image + a.sel0_off[l]);
@@ -454,7 +471,7 @@ __global__ void __launch_bounds__(SD_T)
 span_finish_k(uint8_t* __restrict__ image, SpanLevels a, const uint64_t* __restrict__ totals)
 {
     const uint32_t l = blockIdx.x;
-    const uint64_t n = a.n, ns = wv_cdiv(n, WV_SB_BITS);
+    const uint64_t n = a.n[l], ns = wv_cdiv(n, WV_SB_BITS);
     const uint64_t ones = totals[l], zeros = n - ones;
     uint64_t* dir = (uint64_t*)(image + a.rank_off[l]);
     uint64_t* sel0 = (uint64_t*)(image + a.sel0_off[l]);
@@ -466,8 +483,8 @@ span_finish_k(uint8_t* __restrict__ image, SpanLevels a, const uint64_t* __restr
         desc[1] = zeros;
         desc[2] = ones;
     }
-    for (uint64_t k = wv_cdiv(ones, WV_SEL_STRIDE) + threadIdx.x; k < a.nsel; k += SD_T) sel1[k] = n;
-    for (uint64_t k = wv_cdiv(zeros, WV_SEL_STRIDE) + threadIdx.x; k < a.nsel; k += SD_T) sel0[k] = n;
+    for (uint64_t k = wv_cdiv(ones, WV_SEL_STRIDE) + threadIdx.x; k < a.nsel[l]; k += SD_T) sel1[k] = n;
+    for (uint64_t k = wv_cdiv(zeros, WV_SEL_STRIDE) + threadIdx.x; k < a.nsel[l]; k += SD_T) sel0[k] = n;
 }
 
 }  // namespace
@@ -496,11 +513,11 @@ hipError_t wv_span_directory(uint8_t* image, const wv_layout_out& lay, uint32_t 
 {
     if (!nl) return hipSuccess;
     SpanLevels a{};
-    a.n = lay.lv[l0].n;
-    a.nsel = lay.lv[l0].nsel;
     a.l0 = l0;
     a.nl = nl;
     for (uint32_t l = 0; l < nl; l++) {
+        a.n[l] = lay.lv[l0 + l].n;
+        a.nsel[l] = lay.lv[l0 + l].nsel;
         a.bits_off[l] = lay.lv[l0 + l].bits_off;
         a.rank_off[l] = lay.lv[l0 + l].rank_off;
         a.sel0_off[l] = lay.lv[l0 + l].sel0_off;

@@ -40,9 +40,10 @@ hipError_t wv_binary_directory(uint8_t* image, uint32_t level, const wv_level& L
 hipError_t wv_count_superblocks(const uint8_t* image, const wv_level& L, uint32_t* sb_ones,
                                 hipStream_t s);
 
-// Directories of several binary levels of n bits each (levels l0..l0+nl-1)
-// with one launch per step: per-chunk ones counts, a column-wise prefix sum,
-// then every chunk writes its superblocks and select samples.
+// Directories of several binary levels (levels l0..l0+nl-1, sizes from the
+// layout) with one launch per step: per-chunk ones counts, a column-wise
+// prefix sum, then every chunk writes its superblocks and select samples.
+// The sizes come from the longest level, n.
 struct wv_span_dir {
     uint64_t nchunks, nl;
     uint64_t off_cnt, off_pre, off_part, off_tot, bytes;
@@ -51,14 +52,14 @@ wv_span_dir wv_span_dir_sizes(uint64_t n, uint32_t nl);
 hipError_t wv_span_directory(uint8_t* image, const wv_layout_out& lay, uint32_t l0, uint32_t nl,
                              uint8_t* scratch, const wv_span_dir& sz, hipStream_t s, bool prof = false);
 
-// per-digit counters of one multiary level
+// per-digit counters of M multiary levels of the same length (from lv[0])
 struct wv_mdir_scratch {
-    uint32_t* rng_cnt;   // ranges * d
-    uint64_t* rng_pre;   // ranges * d
-    uint64_t* partial;   // wv_scan_partials(ranges, d)
-    uint64_t* totals;    // d
+    uint32_t* rng_cnt;   // ranges * M * d
+    uint64_t* rng_pre;   // ranges * M * d
+    uint64_t* partial;   // wv_scan_partials(ranges, M * d)
+    uint64_t* totals;    // M * d
 };
-hipError_t wv_multiary_counters(uint8_t* image, const wv_level& L, uint32_t D,
+hipError_t wv_multiary_counters(uint8_t* image, const wv_level* lv, uint32_t M, uint32_t D,
                                 const wv_mdir_scratch& sc, hipStream_t s);
 
 // ---- header (wv_directory.hip) ---------------------------------------------

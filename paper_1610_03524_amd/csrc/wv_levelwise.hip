@@ -170,7 +170,7 @@ hipError_t run_levels(const wv_lw_args& a, hipStream_t s)
                            : emit_level<uint32_t>(keys, m, f, a.image, L, a.dir.sb_ones, s));
         if (e != hipSuccess) return e;
         WV_TIMED(a.profile, s, "lw_directory",
-                 e = kind == WT_KIND_MULTIARY ? wv_multiary_counters(a.image, L, f.D, a.mdir, s)
+                 e = kind == WT_KIND_MULTIARY ? wv_multiary_counters(a.image, &L, 1, f.D, a.mdir, s)
                                               : wv_binary_directory(a.image, l, L, a.dir, a.zl, s));
         if (e != hipSuccess) return e;
         if (l + 1 == a.nlevels) break;

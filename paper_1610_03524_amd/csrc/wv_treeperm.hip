@@ -169,6 +169,64 @@ digits_k(wv_digit_levels a, uint64_t n, uint64_t nwords, uint64_t* __restrict__ 
     }
 }
 
+// The same for 2-bit digits with no rank query per word: a workgroup takes
+// DG words of level bD, scans their zero counts, and needs the rank only at
+// its first word; every position's place on level bD+1 is then that rank
+// plus the zeros before its word in the workgroup plus those below it in
+// its word.  Each wave walks 64 of the words, eight at a time, so the only
+// global load per word (the bit on level bD+1) is issued eight at once.
+constexpr uint32_t DG = 256;
+
+__global__ void __launch_bounds__(DG)
+digits2_k(wv_digit_levels a, uint64_t n, uint64_t nwords, uint64_t* __restrict__ out)
+{
+    __shared__ uint64_t sw[DG];
+    __shared__ uint32_t sz[DG];
+    __shared__ uint32_t wsum[DG / 64];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t nw0 = wv_cdiv(n, 64);
+    const uint64_t c0 = (uint64_t)blockIdx.x * DG;
+    const uint64_t wi = c0 + tid;
+    const uint64_t w = wi < nw0 ? a.words[0][wi] : 0ull;
+    const uint32_t valid = wi < nw0 ? (uint32_t)min<uint64_t>(64, n - wi * 64) : 0u;
+    const uint32_t z = valid - (uint32_t)__popcll(w);   // padding bits are 0
+    const uint32_t inc = wv_wave_incl_scan(z);
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t off = 0;
+    for (uint32_t k = 0; k < wave; k++) off += wsum[k];
+    sw[tid] = w;
+    sz[tid] = off + inc - z;
+    const uint64_t r0c = wv_rank0(a.words[0], a.dir[0], c0 * 64);
+    const uint64_t Z0 = wv_rank0(a.words[0], a.dir[0], n);
+    __syncthreads();
+    const uint64_t pmask = 0xFFFFFFFFull;
+    for (uint32_t j0 = 0; j0 < 64; j0 += 8) {
+        uint32_t d[8];
+#pragma unroll
+        for (uint32_t u = 0; u < 8; u++) {
+            const uint32_t k = wave * 64 + j0 + u;
+            const uint64_t w0 = sw[k];
+            const uint64_t pos = (c0 + k) * 64 + lane;
+            const uint32_t bit = (uint32_t)(w0 >> lane) & 1u;
+            const uint64_t r0 = r0c + sz[k] +
+                                __builtin_amdgcn_mbcnt_hi((uint32_t)(~w0 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)~w0, 0u));
+            const uint64_t p = bit ? Z0 + (pos - r0) : r0;
+            d[u] = pos < n ? ((bit << 1) | ((uint32_t)(a.words[1][p >> 6] >> (p & 63)) & 1u)) : 0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < 8; u++) {
+            const uint64_t k = c0 + wave * 64 + j0 + u;
+            if (k >= nw0) break;   // uniform
+            const uint64_t b0 = __ballot(d[u] & 1u), b1 = __ballot((d[u] >> 1) & 1u);
+            if (lane < 2) {
+                const uint64_t wd = spread((b0 >> (lane * 32)) & pmask, 2) | (spread((b1 >> (lane * 32)) & pmask, 2) << 1);
+                if (k * 2 + lane < nwords) out[k * 2 + lane] = wd;
+            }
+        }
+    }
+}
+
 inline uint64_t brev_bits(uint64_t v, uint32_t nbits)
 {
     return nbits ? __builtin_bitreverse64(v) >> (64 - nbits) : 0ull;
@@ -248,7 +306,7 @@ hipError_t wv_tree_digits(const wv_digit_levels& a, uint64_t n, uint32_t D, uint
     const uint32_t g = (uint32_t)wv_cdiv(wv_cdiv(wv_cdiv(n, 64), DW), 4);   // 4 waves per block
     const uint64_t nw = wv_cdiv(n * D, 64);
     if (D == 1) digits_k<1><<<g, 256, 0, s>>>(a, n, nw, out);
-    else if (D == 2) digits_k<2><<<g, 256, 0, s>>>(a, n, nw, out);
+    else if (D == 2) digits2_k<<<(uint32_t)wv_cdiv(wv_cdiv(n, 64), DG), DG, 0, s>>>(a, n, nw, out);
     else if (D == 4) digits_k<4><<<g, 256, 0, s>>>(a, n, nw, out);
     else return hipErrorInvalidValue;
     return hipGetLastError();

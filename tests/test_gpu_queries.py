@@ -52,7 +52,8 @@ def run_queries(img, S, sigma, rng, m=3000):
     assert np.array_equal(gs, bs), "select"
 
 
-@pytest.mark.parametrize("kind,D", [(B.KIND_WM, 0), (B.KIND_WT, 0), (B.KIND_MULTIARY, 2), (B.KIND_MULTIARY, 3),
+@pytest.mark.parametrize("kind,D", [(B.KIND_WM, 0), (B.KIND_WT, 0), (B.KIND_MULTIARY, 1), (B.KIND_MULTIARY, 2),
+                                    (B.KIND_MULTIARY, 3), (B.KIND_MULTIARY, 4),
                                     (B.KIND_SHAPED, 0)])
 @pytest.mark.parametrize("sigma", [1, 2, 7, 256, 4096, 65536])
 def test_queries_match_brute_force(kind, D, sigma):
