@@ -59,3 +59,12 @@ def describe_diff(a: np.ndarray, b: np.ndarray) -> str:
 
 def assert_same(gpu: np.ndarray, ora: np.ndarray, what=""):
     assert gpu.size == ora.size and np.array_equal(gpu, ora), f"{what}: {describe_diff(gpu, ora)}"
+
+
+def shaped_codes(S, sigma):
+    """codewords for the GPU build from the library (device counts + host
+    Huffman), and for the oracle from the oracle's own counts and Huffman."""
+    counts = B.symbol_counts(to_device(S), sigma).cpu().numpy().astype(np.uint64)
+    gcodes, glens = B.huffman_codes(counts)
+    ocodes, olens = oracle.huffman(oracle.symbol_counts(S, sigma))
+    return (gcodes, glens), (ocodes, olens)

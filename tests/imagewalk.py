@@ -310,3 +310,59 @@ class Image:
                     lo = mid + 1
             return lo
         raise ValueError("kind")
+
+
+class MatrixWalk:
+    """Wavelet-matrix queries through the rank directories alone, for images
+    too large to expand (a zero at position i of level l moves to rank0(i),
+    a one to Z_l + rank1(i))."""
+
+    def __init__(self, img, nlevels):
+        self.img, self.L = img, nlevels
+        self.lv = [self.level(l) for l in range(nlevels)]
+
+    def level(self, l):
+        """(n, zeros, ones, bits_off, rank_off, sel0_off, sel1_off, nsel)"""
+        d = self.img[256 + 64 * l:256 + 64 * (l + 1)].view(np.uint64)
+        return [int(x) for x in d[:8]]
+
+    def words(self, l):
+        n, off = self.lv[l][0], self.lv[l][3]
+        return self.img[off:off + 8 * ((n + 63) // 64)].view(np.uint64)
+
+    def rank0(self, l, i):
+        """zeros in [0, i) of level l"""
+        roff = self.lv[l][4]
+        k, q = divmod(i, 512)
+        d = self.img[roff + 16 * k:roff + 16 * k + 16].view(np.uint64)
+        r = int(d[0])
+        if q >= 64:
+            r += (int(d[1]) >> (9 * (q // 64 - 1))) & 511
+        t = q % 64
+        if t:
+            w = int(self.words(l)[i // 64])
+            r += t - bin(w & ((1 << t) - 1)).count("1")
+        return r
+
+    def bit(self, l, i):
+        return (int(self.words(l)[i // 64]) >> (i % 64)) & 1
+
+    def access(self, i):
+        x = 0
+        for l in range(self.L):
+            b = self.bit(l, i)
+            x = (x << 1) | b
+            r0 = self.rank0(l, i)
+            i = self.lv[l][1] + (i - r0) if b else r0
+        return x
+
+    def rank(self, c, i):
+        """occurrences of c in positions 0..i"""
+        s, e = 0, i + 1
+        for l in range(self.L):
+            if (c >> (self.L - 1 - l)) & 1:
+                z = self.lv[l][1]
+                s, e = z + s - self.rank0(l, s), z + e - self.rank0(l, e)
+            else:
+                s, e = self.rank0(l, s), self.rank0(l, e)
+        return e - s

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import assert_same, gpu_image, oracle_image, to_device
+from gpu_util import assert_same, gpu_image, oracle_image, shaped_codes, to_device
 from paper_1610_03524_amd import binding as B
 
 pytestmark = pytest.mark.gpu
@@ -31,13 +31,7 @@ def patterns(n, sigma, rng):
         yield "one_rare", rare
 
 
-def shaped_inputs(S, sigma):
-    """codewords for the GPU build from the library (device counts + host
-    Huffman), and for the oracle from the oracle's own counts and Huffman."""
-    counts = B.symbol_counts(to_device(S), sigma).cpu().numpy().astype(np.uint64)
-    gcodes, glens = B.huffman_codes(counts)
-    ocodes, olens = oracle.huffman(oracle.symbol_counts(S, sigma))
-    return (gcodes, glens), (ocodes, olens)
+shaped_inputs = shaped_codes
 
 
 @pytest.mark.parametrize("kind", [B.KIND_WM, B.KIND_WT])

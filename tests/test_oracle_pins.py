@@ -441,3 +441,20 @@ def test_layout(kind, D):
     for a, b in spans:
         covered[a:b] = True
     assert not buf[~covered].any(), "bytes outside every array must be zero"
+
+
+def test_matrix_walk_on_oracle_images():
+    """the directory-only matrix reader of the full-size GPU tests, on oracle
+    images: access equals S, rank equals counts over S"""
+    from imagewalk import MatrixWalk
+    rng = np.random.default_rng(9)
+    for sigma, n in [(2, 1000), (300, 5000), (1 << 16, 70001)]:
+        S = rng.integers(0, sigma, n).astype(np.uint32)
+        img = oracle.build_image(oracle.KIND_WM, S, sigma)
+        L = max(1, (sigma - 1).bit_length())
+        w = MatrixWalk(img, L)
+        for i in rng.integers(0, n, 200):
+            assert w.access(int(i)) == int(S[i])
+        for c_src, i in zip(rng.integers(0, n, 50), rng.integers(0, n, 50)):
+            c = int(S[c_src])
+            assert w.rank(c, int(i)) == int(np.count_nonzero(S[:i + 1] == c))
