@@ -75,6 +75,62 @@ def cpu_baseline_wm(S_dev, sigma, target_s=15.0):
                       f"{dt:.1f} s single-threaded"}
 
 
+def device_copy_gbps(reps=10):
+    """bytes read + written per second by a plain 1 GiB device-to-device copy:
+    the bandwidth ceiling measured on this machine, beside the nominal peak"""
+    import torch
+    a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 2 * (1 << 30) * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return round(gbps, 1)
+
+
+def per_build_times(build_once, stream, reps=20):
+    """every build timed alone with events, 512 MiB written between builds so
+    that no input or output is left in the L2 or MALL; median, p10, p90"""
+    import torch
+    flush = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+    ms = []
+    for r in range(reps):
+        flush.fill_(r & 0xFF)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        build_once()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    del flush
+    q = np.percentile(ms, [50, 10, 90])
+    return {"reps": reps, "median_ms": round(float(q[0]), 4), "p10_ms": round(float(q[1]), 4),
+            "p90_ms": round(float(q[2]), 4), "flush": "512 MiB written before every build"}
+
+
+def cpu_baseline_oracle(kind, S, sigma, D=0, codes=None, lens=None, target_s=10.0):
+    """the oracle (single-threaded C, -O2) on a prefix of S grown towards
+    ~target_s seconds; GB/s of input"""
+    import oracle
+    n_s = min(S.size, 1 << 18)
+    while True:
+        t = time.perf_counter()
+        oracle.build_image(kind, S[:n_s], sigma, max(D, 1), codes=codes, lens=lens)
+        dt = time.perf_counter() - t
+        if dt >= target_s / 4 or n_s >= S.size:
+            break
+        n_s = int(min(S.size, n_s * max(2.0, target_s / max(dt, 1e-3))))
+    return {"value": round(n_s * S.itemsize / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n_s} symbols of the same input, {dt:.1f} s single-threaded"}
+
+
 def pass_alg_bytes(info, n, sym_bytes):
     """compulsory bytes of every launch of the partition pass kernel: read its
     input sequence once (S, then the compacted remaining keys), write its
@@ -189,6 +245,10 @@ def main():
     prof = B.profile_read()
     assert B.check(out, stream) == B.WT_OK
     t = ms / 1e3
+    plain_tune = B.make_tuning()
+    per_build = per_build_times(lambda: B.build_into(B.KIND_WM, S, sigma, out, ws, tune=plain_tune, stream=stream),
+                                stream)
+    copy_gbps = device_copy_gbps()
 
     # dominant kernel: the partition pass, timed live with HIP events
     launches, pass_ms = prof["wm_pass"]
@@ -217,9 +277,14 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "wm_pass", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": traffic, "alg_bytes_per_launch": int(alg_per_launch),
-                     "avg_launch_ms": round(per_launch_ms, 4)},
+                     "amplification": round(traffic / alg_per_launch, 3) if traffic else None,
+                     "avg_launch_ms": round(per_launch_ms, 4),
+                     "frac_of_device_copy": round(achieved / copy_gbps, 4)},
         "build_roofline": {"alg_bytes": balg, "achieved": round(balg / t / 1e9, 2),
-                           "frac": round(balg / t / 1e9 / HBM_PEAK_GBPS, 4)},
+                           "frac": round(balg / t / 1e9 / HBM_PEAK_GBPS, 4),
+                           "frac_of_device_copy": round(balg / t / 1e9 / copy_gbps, 4)},
+        "device_copy_GBps": copy_gbps,
+        "per_build": per_build,
         "kernel_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in sorted(prof.items())},
     }
     if not args.no_cpu_baseline:
@@ -314,7 +379,7 @@ def bench_tree(args):
     dom_bytes = tree_kernel_bytes(dom, info, sym, kind) / (prof[dom][0] / args.steps)
     balg = algorithmic_bytes(info, n, sym)
     t = ms / 1e3
-    print(json.dumps({
+    line = {
         "metric": METRIC, "value": round(n * sym / t / 1e9, 3), "unit": "GB/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u16" if sym == 2 else "u8", "data": "synthetic",
@@ -328,7 +393,12 @@ def bench_tree(args):
         "build_roofline": {"alg_bytes": balg, "achieved": round(balg / t / 1e9, 2),
                            "frac": round(balg / t / 1e9 / HBM_PEAK_GBPS, 4)},
         "kernel_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in sorted(prof.items())},
-    }), flush=True)
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        okind = {B.KIND_WT: oracle.KIND_WT, B.KIND_SHAPED: oracle.KIND_SHAPED, B.KIND_MULTIARY: oracle.KIND_MULTI}[kind]
+        line["cpu_baseline"] = cpu_baseline_oracle(okind, Sn, sigma, D, codes, lens)
+    print(json.dumps(line), flush=True)
 
 
 def bench_batch(args):
@@ -384,8 +454,20 @@ def bench_batch(args):
             if rc != 0:
                 raise RuntimeError(B.strerror(rc))
 
+    # the same loop spread round-robin over 4 streams, one workspace each
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    ws4 = [torch.empty_like(single_ws) for _ in streams]
+
+    def plain4():
+        for q, (d, tn) in enumerate(zip(descs, tunings)):
+            st, w = streams[q % 4], ws4[q % 4]
+            rc = lib.wm_build(d.S, d.n, d.sigma, 4, None, ctypes.byref(tn), d.out, d.out_bytes,
+                              w.data_ptr(), w.numel(), B._stream(st))
+            if rc != 0:
+                raise RuntimeError(B.strerror(rc))
+
     res = {}
-    for name, fn in (("batched", batched), ("plain", plain)):
+    for name, fn in (("batched", batched), ("plain", plain), ("plain_4_streams", plain4)):
         fn()
         torch.cuda.synchronize()
         reps = max(1, args.steps // 5)
@@ -395,8 +477,8 @@ def bench_batch(args):
         torch.cuda.synchronize()
         res[name] = (time.perf_counter() - t0) / reps
     balg = sum(4 * int(ns[i]) + infos[i].out_bytes for i in range(k))
-    tb, tp = res["batched"], res["plain"]
-    print(json.dumps({
+    tb, tp, t4 = res["batched"], res["plain"], res["plain_4_streams"]
+    line = {
         "metric": METRIC, "value": round(total * 4 / tb / 1e9, 3), "unit": "GB/s", "n_gpus": 1,
         "steps": max(1, args.steps // 5), "warmup": 1, "ms_per_step": round(tb * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
@@ -405,9 +487,43 @@ def bench_batch(args):
         "batched": {"s": round(tb, 4), "builds_per_s": round(k / tb, 1), "input_GBps": round(total * 4 / tb / 1e9, 2),
                     "build_roofline_frac": round(balg / tb / 1e9 / HBM_PEAK_GBPS, 4)},
         "plain": {"s": round(tp, 4), "builds_per_s": round(k / tp, 1), "input_GBps": round(total * 4 / tp / 1e9, 2)},
+        "plain_4_streams": {"s": round(t4, 4), "builds_per_s": round(k / t4, 1),
+                            "input_GBps": round(total * 4 / t4 / 1e9, 2)},
         "speedup_batched_vs_plain": round(tp / tb, 3),
+        "speedup_batched_vs_plain_4_streams": round(t4 / tb, 3),
         "input_generation_s": round(t_gen, 1),
-    }), flush=True)
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_batch(ns, sig, children)
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_batch(ns, sig, children, target_s=10.0, threads=16):
+    """the oracle over the first C4 sequences on a pool of host threads (one
+    sequence per task; the C library releases the interpreter while it runs),
+    and single-threaded on the same sample; GB/s of input"""
+    import concurrent.futures as cf
+    import oracle
+    from paper_1610_03524_amd import inputs
+    seqs, total = [], 0
+    for i in range(len(ns)):
+        seqs.append((inputs.c4_sequence(int(ns[i]), int(sig[i]), children[i]), int(sig[i])))
+        total += int(ns[i])
+        if total >= 1 << 26:
+            break
+    nbytes = sum(S.size * 4 for S, _ in seqs)
+    t = time.perf_counter()
+    for S, sg in seqs:
+        oracle.build_image(oracle.KIND_WM, S, sg)
+    t1 = time.perf_counter() - t
+    t = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda a: oracle.build_image(oracle.KIND_WM, *a), seqs))
+    tp = time.perf_counter() - t
+    return {"value": round(nbytes / tp / 1e9, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "single_thread_GBps": round(nbytes / t1 / 1e9, 4),
+            "sample": f"first {len(seqs)} C4 sequences ({nbytes // 4} symbols): {tp:.1f} s on {threads} "
+                      f"threads, {t1:.1f} s on one"}
 
 
 
