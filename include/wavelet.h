@@ -109,8 +109,9 @@ typedef struct wt_shape {
 
 typedef struct wt_tuning {
     uint32_t tau;      /* key bits per partition pass, 1..8 (0 = automatic) */
-    uint32_t tile;     /* elements per tile (0 = automatic)                 */
-    uint32_t blocks;   /* workgroups per pass (0 = automatic)               */
+    uint32_t tile;     /* reserved, ignored: a pass tile is 8192 keys       */
+    uint32_t blocks;   /* chunks (workgroups) per pass (0 = automatic: one
+                          per tile, at most 768 = 3 per CU)                 */
     uint32_t flags;    /* WT_FLAG_*                                         */
 } wt_tuning;
 
@@ -129,8 +130,9 @@ typedef struct wt_plan_info {
 } wt_plan_info;
 
 /* Size a build (Sec. 2 problem statement; host only, no device work).
- * shape: NULL for WT/WM; codes+code_len+counts for SHAPED; arity for
- * MULTIARY.  tune may be NULL.  Fills *info. */
+ * shape: NULL for WT/WM; codes+code_len+counts for SHAPED (the codewords
+ * must be prefix-free, else WT_EINVAL); arity for MULTIARY.  tune may be
+ * NULL.  Fills *info. */
 int wt_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes,
             const wt_shape* shape, const wt_tuning* tune, wt_plan_info* info);
 
@@ -138,8 +140,9 @@ int wt_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes,
  * set, the tree shaped by those codewords (Sec. 4.3, Thm. 4.4).
  * S: dev, n symbols of sym_bytes each.  out: dev, out_bytes >= plan
  * out_bytes, receives the image.  ws: dev scratch of ws_bytes >= plan
- * workspace_bytes.  Shaped builds synchronize `stream` once (symbol counts
- * are checked against shape->counts; a mismatch returns WT_EINVAL). */
+ * workspace_bytes.  Synchronizes `stream` once: the symbol counts are read
+ * back to place the tree's runs (shaped: they must equal shape->counts,
+ * else WT_EINVAL; a symbol >= sigma returns WT_ERANGE at that point). */
 int wt_build(const void* S, uint64_t n, uint32_t sigma, uint32_t sym_bytes,
              const wt_shape* shape, const wt_tuning* tune,
              void* out, size_t out_bytes, void* ws, size_t ws_bytes, void* stream);
@@ -152,7 +155,7 @@ int wm_build(const void* S, uint64_t n, uint32_t sigma, uint32_t sym_bytes,
 
 /* Build a balanced multiary wavelet tree of degree 2^shape->arity_log2
  * (Sec. 4.3, Thm. 4.5) with per-digit rank counters (Sec. 5.2).  Same
- * arguments as wt_build.  Synchronizes `stream` once (node table). */
+ * arguments as wt_build.  Synchronizes `stream` once (symbol counts). */
 int multiary_build(const void* S, uint64_t n, uint32_t sigma, uint32_t sym_bytes,
                    const wt_shape* shape, const wt_tuning* tune,
                    void* out, size_t out_bytes, void* ws, size_t ws_bytes, void* stream);
