@@ -446,86 +446,38 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
     const uint64_t n = p.n;
     const uint32_t sigma = p.sigma, K = p.key_bits;
     const bool shaped = p.kind == WT_KIND_SHAPED, multi = p.kind == WT_KIND_MULTIARY;
+    const uint32_t D = multi ? p.D : 1u, T = multi ? p.nlevels : K;
+    // 1. symbol counts and status to the host (waited for in step 3)
     uint64_t* dcounts = at<uint64_t>(ws, p.ws_counts);
     WV_CHECK(wv_validate(S, n, p.sym_bytes, sigma, img, dcounts, s));
     std::vector<uint64_t> counts(sigma);
     uint32_t status = 0;
     WV_CHECK(hipMemcpyAsync(counts.data(), dcounts, (uint64_t)sigma * 8, hipMemcpyDeviceToHost, s));
     WV_CHECK(hipMemcpyAsync(&status, img + 36, 4, hipMemcpyDeviceToHost, s));
-    WV_CHECK(hipStreamSynchronize(s));
-    if (status) return WT_ERANGE;
+    hipEvent_t have_counts = nullptr;
+    WV_CHECK(hipEventCreateWithFlags(&have_counts, hipEventDisableTiming));
+    struct EventGuard {
+        hipEvent_t e;
+        ~EventGuard() { hipEventDestroy(e); }
+    } guard{have_counts};
+    WV_CHECK(hipEventRecord(have_counts, s));
 
-    std::vector<uint8_t> rec, code_rec;
+    // 2. the matrix levels need no counts: launch them now, so that they run
+    // while the host lays out the tree
     std::vector<uint32_t> c32, l32;
+    const void* keys = S;
     if (shaped) {
-        for (uint32_t x = 0; x < sigma; x++)
-            if (counts[x] != shape->counts[x]) return WT_EINVAL;
-        HostNodes H;
-        int rc = shaped_nodes(*shape, sigma, H, rec);
-        if (rc) return rc;
-        code_rec.assign((uint64_t)sigma * WV_CODE_BYTES, 0);
         c32.resize(sigma);
         l32.resize(sigma);
         for (uint32_t x = 0; x < sigma; x++) {
-            const uint64_t c = shape->code_len[x] ? shape->codes[x] : 0;
-            const uint32_t len = shape->code_len[x];
-            std::memcpy(code_rec.data() + (uint64_t)x * WV_CODE_BYTES, &c, 8);
-            std::memcpy(code_rec.data() + (uint64_t)x * WV_CODE_BYTES + 8, &len, 4);
-            c32[x] = (uint32_t)c;
-            l32[x] = len;
+            l32[x] = shape->code_len[x];
+            c32[x] = l32[x] ? (uint32_t)shape->codes[x] : 0u;
         }
-    }
-    std::vector<wv_perm_seg> segs;
-    std::vector<uint64_t> seg0;
-    wv_tree_segments(counts, K, shaped ? c32.data() : nullptr, shaped ? l32.data() : nullptr, segs, seg0);
-    // tree level t: matrix level t (binary), or digit level t from matrix
-    // level t*D with every run D bits per symbol (multiary)
-    const uint32_t D = multi ? p.D : 1u, T = multi ? p.nlevels : K;
-    if (multi) {
-        std::vector<wv_perm_seg> ms;
-        std::vector<uint64_t> m0(T + 1, 0);
-        for (uint32_t t = 0; t < T; t++) {
-            m0[t] = ms.size();
-            for (uint64_t k = seg0[t * D]; k < seg0[t * D + 1]; k++)
-                ms.push_back(wv_perm_seg{segs[k].dst * D, segs[k].src * D, segs[k].len * D});
-        }
-        m0[T] = ms.size();
-        segs.swap(ms);
-        seg0.swap(m0);
-    }
-    if (segs.size() > p.seg_bound) return WT_EUNSUP;
-    std::vector<wv_perm_level> lv(T);
-    uint64_t words = 0;
-    for (uint32_t l = 0; l < T; l++) {
-        lv[l].dst = (uint64_t*)(img + p.lay.lv[l].bits_off);
-        lv[l].src = multi ? at<uint64_t>(ws, p.ws_digits + l * p.dstride) : at<uint64_t>(ws, p.ws_tmp + l * p.tmp_stride);
-        lv[l].nbits = p.lay.lv[l].n * D;
-        lv[l].seg0 = seg0[l];
-        lv[l].nseg = seg0[l + 1] - seg0[l];
-        lv[l].word0 = words;
-        words += wv_cdiv(lv[l].nbits, 64);
-    }
-    uint8_t* dsegs = at<uint8_t>(ws, p.ws_segs);
-    wv_perm_level* dlv = (wv_perm_level*)dsegs;
-    wv_perm_seg* dseg = (wv_perm_seg*)(dsegs + wv_round256(WV_MAX_LEVELS * sizeof(wv_perm_level)));
-    WV_CHECK(hipMemcpyAsync(dlv, lv.data(), T * sizeof(wv_perm_level), hipMemcpyHostToDevice, s));
-    if (!segs.empty())
-        WV_CHECK(hipMemcpyAsync(dseg, segs.data(), segs.size() * sizeof(wv_perm_seg), hipMemcpyHostToDevice, s));
-    if (shaped) {
         WV_CHECK(hipMemcpyAsync(at<void>(ws, p.ws_codes), c32.data(), (uint64_t)sigma * 4, hipMemcpyHostToDevice, s));
         WV_CHECK(hipMemcpyAsync(at<void>(ws, p.ws_lens), l32.data(), (uint64_t)sigma * 4, hipMemcpyHostToDevice, s));
-        if (!rec.empty())
-            WV_CHECK(hipMemcpyAsync(img + p.lay.nodes_off, rec.data(), rec.size(), hipMemcpyHostToDevice, s));
-        WV_CHECK(hipMemcpyAsync(img + p.lay.codes_off, code_rec.data(), code_rec.size(), hipMemcpyHostToDevice, s));
-    }
-    // the host vectors above go out of scope: finish the copies first
-    WV_CHECK(hipStreamSynchronize(s));
-
-    const void* keys = S;
-    if (shaped) {
         WV_TIMED(prof, s, "tree_keys",
-                 WV_CHECK(wv_tree_keys(S, n, p.sym_bytes, at<uint32_t>(ws, p.ws_codes), at<uint32_t>(ws, p.ws_lens),
-                                       K, at<uint32_t>(ws, p.ws_tkeys), s)));
+                 WV_CHECK(wv_tree_keys(S, n, p.sym_bytes, sigma, at<uint32_t>(ws, p.ws_codes),
+                                       at<uint32_t>(ws, p.ws_lens), K, at<uint32_t>(ws, p.ws_tkeys), s)));
         keys = at<void>(ws, p.ws_tkeys);
     }
     if (multi) {
@@ -547,6 +499,74 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
         for (uint32_t l = 0; l < K; l++) lw[l] = at<uint64_t>(ws, p.ws_tmp + l * p.tmp_stride);
         WV_CHECK(wv_wm_levels(p.wm, keys, lw, (uint32_t*)(img + 36), at<uint8_t>(ws, p.ws_wm), s));
     }
+
+    // 3. the counts: on an error, let the launched work finish before
+    // returning (it writes into the caller's buffers)
+    WV_CHECK(hipEventSynchronize(have_counts));
+    int rc = status ? WT_ERANGE : WT_OK;
+    if (!rc && shaped)
+        for (uint32_t x = 0; x < sigma && !rc; x++)
+            if (counts[x] != shape->counts[x]) rc = WT_EINVAL;
+    std::vector<uint8_t> rec, code_rec;
+    if (!rc && shaped) {
+        HostNodes H;
+        rc = shaped_nodes(*shape, sigma, H, rec);
+        code_rec.assign((uint64_t)sigma * WV_CODE_BYTES, 0);
+        for (uint32_t x = 0; x < sigma; x++) {
+            const uint64_t c = c32[x];
+            std::memcpy(code_rec.data() + (uint64_t)x * WV_CODE_BYTES, &c, 8);
+            std::memcpy(code_rec.data() + (uint64_t)x * WV_CODE_BYTES + 8, &l32[x], 4);
+        }
+    }
+    // 4. every level's runs, from the counts
+    std::vector<wv_perm_seg> segs;
+    std::vector<uint64_t> seg0;
+    if (!rc) {
+        wv_tree_segments(counts, K, shaped ? c32.data() : nullptr, shaped ? l32.data() : nullptr, segs, seg0);
+        // tree level t: matrix level t (binary), or digit level t from matrix
+        // level t*D with every run D bits per symbol (multiary)
+        if (multi) {
+            std::vector<wv_perm_seg> ms;
+            std::vector<uint64_t> m0(T + 1, 0);
+            for (uint32_t t = 0; t < T; t++) {
+                m0[t] = ms.size();
+                for (uint64_t k = seg0[t * D]; k < seg0[t * D + 1]; k++)
+                    ms.push_back(wv_perm_seg{segs[k].dst * D, segs[k].src * D, segs[k].len * D});
+            }
+            m0[T] = ms.size();
+            segs.swap(ms);
+            seg0.swap(m0);
+        }
+        if (segs.size() > p.seg_bound) rc = WT_EUNSUP;
+    }
+    if (rc) {
+        WV_CHECK(hipStreamSynchronize(s));
+        return rc;
+    }
+    std::vector<wv_perm_level> lv(T);
+    uint64_t words = 0;
+    for (uint32_t l = 0; l < T; l++) {
+        lv[l].dst = (uint64_t*)(img + p.lay.lv[l].bits_off);
+        lv[l].src = multi ? at<uint64_t>(ws, p.ws_digits + l * p.dstride) : at<uint64_t>(ws, p.ws_tmp + l * p.tmp_stride);
+        lv[l].nbits = p.lay.lv[l].n * D;
+        lv[l].seg0 = seg0[l];
+        lv[l].nseg = seg0[l + 1] - seg0[l];
+        lv[l].word0 = words;
+        words += wv_cdiv(lv[l].nbits, 64);
+    }
+    uint8_t* dsegs = at<uint8_t>(ws, p.ws_segs);
+    wv_perm_level* dlv = (wv_perm_level*)dsegs;
+    wv_perm_seg* dseg = (wv_perm_seg*)(dsegs + wv_round256(WV_MAX_LEVELS * sizeof(wv_perm_level)));
+    WV_CHECK(hipMemcpyAsync(dlv, lv.data(), T * sizeof(wv_perm_level), hipMemcpyHostToDevice, s));
+    if (!segs.empty())
+        WV_CHECK(hipMemcpyAsync(dseg, segs.data(), segs.size() * sizeof(wv_perm_seg), hipMemcpyHostToDevice, s));
+    if (shaped) {
+        if (!rec.empty())
+            WV_CHECK(hipMemcpyAsync(img + p.lay.nodes_off, rec.data(), rec.size(), hipMemcpyHostToDevice, s));
+        WV_CHECK(hipMemcpyAsync(img + p.lay.codes_off, code_rec.data(), code_rec.size(), hipMemcpyHostToDevice, s));
+    }
+
+    // 5. runs to tree order, then the directories
     WV_TIMED(prof, s, "tree_perm", WV_CHECK(wv_tree_permute(dlv, T, dseg, words, s)));
     uint8_t* dscr = at<uint8_t>(ws, p.ws_wm + p.wm.off_dir);
     if (multi) {
@@ -559,6 +579,8 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
     } else {
         WV_CHECK(wv_span_directory(img, p.lay, 0, K, dscr, p.wm.dir, s, prof));
     }
+    // the host arrays copied above go out of scope
+    WV_CHECK(hipStreamSynchronize(s));
     return WT_OK;
 }
 

@@ -28,9 +28,9 @@ struct wv_perm_level {
 void wv_tree_segments(const std::vector<uint64_t>& counts, uint32_t key_bits, const uint32_t* codes,
                       const uint32_t* lens, std::vector<wv_perm_seg>& segs, std::vector<uint64_t>& seg0);
 
-// keys[i] = codes[S[i]] << (h - lens[S[i]]) (device arrays)
-hipError_t wv_tree_keys(const void* S, uint64_t n, uint32_t sym_bytes, const uint32_t* codes, const uint32_t* lens,
-                        uint32_t h, uint32_t* keys, hipStream_t s);
+// keys[i] = codes[S[i]] << (h - lens[S[i]]) (device arrays; 0 for S[i] >= sigma)
+hipError_t wv_tree_keys(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma, const uint32_t* codes,
+                        const uint32_t* lens, uint32_t h, uint32_t* keys, hipStream_t s);
 
 // matrix levels bD .. bD+D-1 (words and rank directories) of one multiary level
 struct wv_digit_levels {

@@ -31,13 +31,14 @@ namespace {
 
 template <typename T>
 __global__ void __launch_bounds__(256)
-tree_keys_k(const T* __restrict__ S, uint64_t n, const uint32_t* __restrict__ codes,
+tree_keys_k(const T* __restrict__ S, uint64_t n, uint32_t sigma, const uint32_t* __restrict__ codes,
             const uint32_t* __restrict__ lens, uint32_t h, uint32_t* __restrict__ keys)
 {
     const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     const uint32_t x = (uint32_t)S[i];
-    keys[i] = codes[x] << (h - lens[x]);
+    // a symbol >= sigma has been flagged by the validation; its key is 0
+    keys[i] = x < sigma ? codes[x] << (h - lens[x]) : 0u;
 }
 
 // `nb` (1..64) bits of a level bit string starting at bit `pos`; the array
@@ -289,14 +290,14 @@ void wv_tree_segments(const std::vector<uint64_t>& counts, uint32_t key_bits, co
     seg0[key_bits] = segs.size();
 }
 
-hipError_t wv_tree_keys(const void* S, uint64_t n, uint32_t sym_bytes, const uint32_t* codes, const uint32_t* lens,
-                        uint32_t h, uint32_t* keys, hipStream_t s)
+hipError_t wv_tree_keys(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma, const uint32_t* codes,
+                        const uint32_t* lens, uint32_t h, uint32_t* keys, hipStream_t s)
 {
     if (!n) return hipSuccess;
     const uint32_t g = (uint32_t)wv_cdiv(n, 256);
-    if (sym_bytes == 1) tree_keys_k<uint8_t><<<g, 256, 0, s>>>((const uint8_t*)S, n, codes, lens, h, keys);
-    else if (sym_bytes == 2) tree_keys_k<uint16_t><<<g, 256, 0, s>>>((const uint16_t*)S, n, codes, lens, h, keys);
-    else tree_keys_k<uint32_t><<<g, 256, 0, s>>>((const uint32_t*)S, n, codes, lens, h, keys);
+    if (sym_bytes == 1) tree_keys_k<uint8_t><<<g, 256, 0, s>>>((const uint8_t*)S, n, sigma, codes, lens, h, keys);
+    else if (sym_bytes == 2) tree_keys_k<uint16_t><<<g, 256, 0, s>>>((const uint16_t*)S, n, sigma, codes, lens, h, keys);
+    else tree_keys_k<uint32_t><<<g, 256, 0, s>>>((const uint32_t*)S, n, sigma, codes, lens, h, keys);
     return hipGetLastError();
 }
 
