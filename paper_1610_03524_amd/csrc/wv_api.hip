@@ -552,7 +552,15 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
         lv[l].seg0 = seg0[l];
         lv[l].nseg = seg0[l + 1] - seg0[l];
         lv[l].word0 = words;
-        words += wv_cdiv(lv[l].nbits, 64);
+        lv[l].sub = nullptr;
+        if (multi) {
+            // whole 64-word counter ranges per level; sub-range counters follow the range counters
+            const uint64_t nr = wv_mranges(p.lay.lv[l].n, D);
+            lv[l].sub = (uint16_t*)(img + p.lay.lv[l].rank_off + (nr + 1) * (8ull << D));
+            words += nr * 64;
+        } else {
+            words += wv_cdiv(lv[l].nbits, 64);
+        }
     }
     uint8_t* dsegs = at<uint8_t>(ws, p.ws_segs);
     wv_perm_level* dlv = (wv_perm_level*)dsegs;
@@ -567,12 +575,14 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
     }
 
     // 5. runs to tree order, then the directories
-    WV_TIMED(prof, s, "tree_perm", WV_CHECK(wv_tree_permute(dlv, T, dseg, words, s)));
+    // multiary: the gather also counts digits per range and sub-range
+    const wv_mdir_scratch md{at<uint32_t>(ws, p.ws_sb_ones), at<uint64_t>(ws, p.ws_sb_pre),
+                             at<uint64_t>(ws, p.ws_partial), at<uint64_t>(ws, p.ws_mtot)};
+    const wv_perm_counts pc{md.rng_cnt, n, D, T};
+    WV_TIMED(prof, s, "tree_perm", WV_CHECK(wv_tree_permute(dlv, T, dseg, words, multi ? &pc : nullptr, s)));
     uint8_t* dscr = at<uint8_t>(ws, p.ws_wm + p.wm.off_dir);
     if (multi) {
-        wv_mdir_scratch md{at<uint32_t>(ws, p.ws_sb_ones), at<uint64_t>(ws, p.ws_sb_pre),
-                           at<uint64_t>(ws, p.ws_partial), at<uint64_t>(ws, p.ws_mtot)};
-        WV_TIMED(prof, s, "mcounters", WV_CHECK(wv_multiary_counters(img, p.lay.lv, T, D, md, s)));
+        WV_TIMED(prof, s, "mcounters", WV_CHECK(wv_multiary_ranges(img, p.lay.lv, T, D, md, s)));
     } else if (shaped) {
         // level 0 is the longest
         WV_CHECK(wv_span_directory(img, p.lay, 0, K, dscr, wv_span_dir_sizes(p.lay.lv[0].n, K), s, prof));

@@ -171,6 +171,18 @@ mwrite_k(uint8_t* __restrict__ image, MLevels a, const uint64_t* __restrict__ rn
     }
 }
 
+// range counters from the scanned range counts (one thread per entry)
+__global__ void __launch_bounds__(DIR_THREADS)
+mrange_k(uint8_t* __restrict__ image, MLevels a, const uint64_t* __restrict__ rng_pre)
+{
+    const uint32_t t = blockIdx.y, d = 1u << a.D;
+    const uint64_t i = (uint64_t)blockIdx.x * DIR_THREADS + threadIdx.x;
+    const uint64_t nr = wv_mranges(a.m, a.D);
+    if (i >= nr * d) return;
+    uint64_t* rng = (uint64_t*)(image + a.rank_off[t]);
+    rng[i] = rng_pre[((i / d) * a.M + t) * d + i % d];
+}
+
 __global__ void mfinish_k(uint8_t* __restrict__ image, MLevels a, const uint64_t* __restrict__ totals)
 {
     const uint32_t t = blockIdx.x, d = 1u << a.D;
@@ -259,6 +271,9 @@ header_k(uint8_t* __restrict__ img, wv_layout_in in)
 
 constexpr uint32_t LDS_HIST_MAX = 8192;
 
+// Symbols checked against sigma and counted (an LDS histogram per workgroup
+// when sigma is small).  The input is read in 16-byte pieces, four in flight
+// per thread, when it is 16-byte aligned; the rest symbol by symbol.
 template <typename T>
 __global__ void __launch_bounds__(DIR_THREADS)
 validate_k(const void* __restrict__ S, uint64_t n, uint32_t sigma, uint32_t* __restrict__ status,
@@ -271,15 +286,41 @@ validate_k(const void* __restrict__ S, uint64_t n, uint32_t sigma, uint32_t* __r
         __syncthreads();
     }
     bool bad = false;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const uint32_t x = wv_load_sym<T>(S, i);
-        if (x >= sigma) { bad = true; continue; }
-        if (counts) {
-            if (lds) atomicAdd(&h[x], 1u);
-            else atomicAdd(&counts[x], 1ull);
+    auto take = [&](uint32_t x) {
+        if (x >= sigma) bad = true;
+        else if (lds) atomicAdd(&h[x], 1u);
+        else if (counts) atomicAdd(&counts[x], 1ull);
+    };
+    auto take16 = [&](const uint4& v) {
+        const uint32_t q[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            if (sizeof(T) == 4) {
+                take(q[k]);
+            } else if (sizeof(T) == 2) {
+                take(q[k] & 0xFFFFu);
+                take(q[k] >> 16);
+            } else {
+#pragma unroll
+                for (int b = 0; b < 4; b++) take((q[k] >> (8 * b)) & 0xFFu);
+            }
         }
+    };
+    constexpr uint32_t PER = 16 / sizeof(T);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t t0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t nv = ((uintptr_t)S & 15u) == 0 ? n / PER : 0;   // whole 16-byte pieces
+    const uint4* __restrict__ S4 = (const uint4*)S;
+    uint64_t i = t0;
+    for (; i + 3 * stride < nv; i += 4 * stride) {
+        uint4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) v[u] = S4[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < 4; u++) take16(v[u]);
     }
+    for (; i < nv; i += stride) take16(S4[i]);
+    for (uint64_t k = nv * PER + t0; k < n; k += stride) take(wv_load_sym<T>(S, k));
     if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0 && status) atomicOr(status, 1u);
     if (lds) {
         __syncthreads();
@@ -352,6 +393,27 @@ hipError_t wv_multiary_counters(uint8_t* image, const wv_level* lv, uint32_t M, 
     return hipGetLastError();
 }
 
+hipError_t wv_multiary_ranges(uint8_t* image, const wv_level* lv, uint32_t M, uint32_t D,
+                              const wv_mdir_scratch& sc, hipStream_t s)
+{
+    if (!M) return hipSuccess;
+    MLevels a{};
+    a.m = lv[0].n;
+    a.M = M;
+    a.D = D;
+    for (uint32_t t = 0; t < M; t++) {
+        a.bits_off[t] = lv[t].bits_off;
+        a.rank_off[t] = lv[t].rank_off;
+    }
+    const uint64_t nr = wv_mranges(a.m, D);
+    const uint32_t d = 1u << D;
+    hipError_t e = wv_scan_u32(sc.rng_cnt, sc.rng_pre, nr, M * d, sc.partial, sc.totals, s);
+    if (e != hipSuccess) return e;
+    if (nr) mrange_k<<<dim3((uint32_t)wv_cdiv(nr * d, DIR_THREADS), M), DIR_THREADS, 0, s>>>(image, a, sc.rng_pre);
+    mfinish_k<<<M, 64, 0, s>>>(image, a, sc.totals);
+    return hipGetLastError();
+}
+
 hipError_t wv_write_header(uint8_t* image, const wv_layout_in& in, hipStream_t s)
 {
     header_k<<<1, DIR_THREADS, 0, s>>>(image, in);
@@ -368,7 +430,7 @@ hipError_t wv_validate(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t s
         if (e != hipSuccess) return e;
     }
     if (!n) return hipSuccess;
-    const uint32_t grid = grid_for(n, DIR_THREADS * 16, 2048);
+    const uint32_t grid = grid_for(n, DIR_THREADS * 64, 2048);
     if (sym_bytes == 1) validate_k<uint8_t><<<grid, DIR_THREADS, 0, s>>>(S, n, sigma, status, c);
     else if (sym_bytes == 2) validate_k<uint16_t><<<grid, DIR_THREADS, 0, s>>>(S, n, sigma, status, c);
     else validate_k<uint32_t><<<grid, DIR_THREADS, 0, s>>>(S, n, sigma, status, c);

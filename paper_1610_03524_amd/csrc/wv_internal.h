@@ -61,6 +61,10 @@ struct wv_mdir_scratch {
 };
 hipError_t wv_multiary_counters(uint8_t* image, const wv_level* lv, uint32_t M, uint32_t D,
                                 const wv_mdir_scratch& sc, hipStream_t s);
+// the range counters alone, once sc.rng_cnt holds every range's digit counts
+// and the sub-range counters are written (by the gather of the tree levels)
+hipError_t wv_multiary_ranges(uint8_t* image, const wv_level* lv, uint32_t M, uint32_t D,
+                              const wv_mdir_scratch& sc, hipStream_t s);
 
 // ---- header (wv_directory.hip) ---------------------------------------------
 // header, level descriptors (zeros/ones left 0) and zeroed gaps between arrays

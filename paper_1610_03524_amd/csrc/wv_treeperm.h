@@ -18,6 +18,18 @@ struct wv_perm_level {
     uint64_t nbits;         // symbols on the tree level
     uint64_t seg0, nseg;    // its runs in the segment array
     uint64_t word0;         // first output word of the level in the launch
+    uint16_t* sub;          // multiary: the level's sub-range counters (counting launch only)
+};
+
+// Counters of multiary levels taken while gathering them: every level holds
+// m digits of D bits, starts on a multiple of 64 words in the launch and
+// covers wv_mranges(m, D) * 64 words of it (the words past its end are
+// skipped).  rng_cnt[(r * M + l) * 2^D + g] receives the number of digits g in
+// range r of level l, and each level's sub-range counters are written.
+struct wv_perm_counts {
+    uint32_t* rng_cnt;
+    uint64_t m;
+    uint32_t D, M;
 };
 
 // Runs of every level 0..key_bits-1 from the symbol counts.  Balanced tree:
@@ -42,6 +54,7 @@ struct wv_digit_levels {
 // (ceil(n*D/64) words; D = 1, 2 or 4)
 hipError_t wv_tree_digits(const wv_digit_levels& a, uint64_t n, uint32_t D, uint64_t* out, hipStream_t s);
 
-// gather every tree level (descriptors and runs already on the device)
+// gather every tree level (descriptors and runs already on the device); with
+// `counts`, the levels are multiary and their counters are taken on the way
 hipError_t wv_tree_permute(const wv_perm_level* lv_dev, uint32_t nlev, const wv_perm_seg* seg_dev,
-                           uint64_t total_words, hipStream_t s);
+                           uint64_t total_words, const wv_perm_counts* counts, hipStream_t s);

@@ -52,32 +52,61 @@ __device__ inline uint64_t bits_at(const uint64_t* __restrict__ w, uint64_t pos,
     return nb >= 64 ? v : (v & ((1ull << nb) - 1ull));
 }
 
+// One thread per output word: the run holding its first bit is found by a
+// binary search over the level's runs, then its bits are gathered run by run.
+// COUNT (multiary levels, every level starting on a wave): each wave is one
+// 64-word range of one level, and its scans of the per-word digit counts give
+// the range totals and the counts before every 8-word sub-range (Sec. 5's
+// two-level counters, taken here instead of in a second pass over the level).
+template <bool COUNT>
 __global__ void __launch_bounds__(256)
 perm_runs_k(const wv_perm_level* __restrict__ lv, uint32_t nlev, const wv_perm_seg* __restrict__ seg,
-            uint64_t total_words)
+            uint64_t total_words, wv_perm_counts cnt)
 {
     const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= total_words) return;
+    if (t >= total_words) return;   // with COUNT total_words is a multiple of 64: whole waves
     uint32_t l = 0;
     while (l + 1 < nlev && lv[l + 1].word0 <= t) l++;
     const wv_perm_level L = lv[l];
     const uint64_t w = t - L.word0;
-    const uint64_t p0 = w * 64, end = min(p0 + 64, L.nbits);
-    // the run holding bit p0: the last one starting at or before it
-    uint64_t lo = L.seg0, hi = L.seg0 + L.nseg - 1;
-    while (lo < hi) {
-        const uint64_t mid = (lo + hi + 1) >> 1;
-        if (seg[mid].dst <= p0) lo = mid; else hi = mid - 1;
-    }
+    const uint64_t nw = wv_cdiv(L.nbits, 64);
     uint64_t out = 0;
-    for (uint64_t p = p0, k = lo; p < end; k++) {
-        const wv_perm_seg g = seg[k];
-        const uint64_t in = p - g.dst;
-        const uint32_t take = (uint32_t)min(end - p, g.len - in);
-        out |= bits_at(L.src, g.src + in, take) << (p - p0);
-        p += take;
+    if (w < nw) {
+        const uint64_t p0 = w * 64, end = min(p0 + 64, L.nbits);
+        // the run holding bit p0: the last one starting at or before it
+        uint64_t lo = L.seg0, hi = L.seg0 + L.nseg - 1;
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi + 1) >> 1;
+            if (seg[mid].dst <= p0) lo = mid; else hi = mid - 1;
+        }
+        for (uint64_t p = p0, k = lo; p < end; k++) {
+            const wv_perm_seg g = seg[k];
+            const uint64_t in = p - g.dst;
+            const uint32_t take = (uint32_t)min(end - p, g.len - in);
+            out |= bits_at(L.src, g.src + in, take) << (p - p0);
+            p += take;
+        }
+        L.dst[w] = out;
     }
-    L.dst[w] = out;
+    if (COUNT) {
+        const uint32_t lane = threadIdx.x & 63, D = cnt.D, P = 64u / D, d = 1u << D;
+        const uint64_t r = w >> 6, sk = w >> 3;
+        const uint32_t c = w < nw ? (uint32_t)min<uint64_t>(P, cnt.m - w * P) : 0u;
+        const bool subw = (lane & 7) == 0 && sk < wv_msubs(cnt.m, D);
+        for (uint32_t g0 = 0; g0 < d; g0 += 4) {
+            uint64_t pack = 0;   // up to four 16-bit sub-range counters
+            for (uint32_t gg = 0; gg < 4 && g0 + gg < d; gg++) {
+                const uint32_t v = wv_count_digit(out, D, g0 + gg, c);
+                const uint32_t inc = wv_wave_incl_scan(v);
+                if (lane == 63) cnt.rng_cnt[(r * cnt.M + l) * d + g0 + gg] = inc;
+                pack |= (uint64_t)(inc - v) << (16 * gg);
+            }
+            if (subw) {
+                if (d == 2) *(uint32_t*)(L.sub + sk * d) = (uint32_t)pack;
+                else *(uint64_t*)(L.sub + sk * d + g0) = pack;
+            }
+        }
+    }
 }
 
 // the low 64/D bits of x moved to bit positions 0, D, 2D, ... (D = 1, 2, 4)
@@ -128,20 +157,21 @@ digits_k(wv_digit_levels a, uint64_t n, uint64_t nwords, uint64_t* __restrict__ 
 #pragma unroll
         for (uint32_t j = 0; j < DW; j++) rb[j] = bw + j < nw0 ? wv_rank0(a.words[0], a.dir[0], (bw + j) * 64) : 0ull;
         const uint64_t Z0 = wv_rank0(a.words[0], a.dir[0], n);
+        // positions past n follow position 0 (their digits are masked below),
+        // so every lane loads and the loads of the DW words go out together
         uint64_t p[DW];
 #pragma unroll
         for (uint32_t j = 0; j < DW; j++) {
             const uint64_t i = (bw + j) * 64 + lane;
             const uint64_t r0 = rb[j] + __builtin_amdgcn_mbcnt_hi((uint32_t)(~w0[j] >> 32),
                                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)~w0[j], 0u));
-            p[j] = d[j] ? Z0 + (i - r0) : r0;
+            p[j] = i < n ? (d[j] ? Z0 + (i - r0) : r0) : 0ull;
         }
 #pragma unroll
         for (uint32_t k = 1; k < D; k++) {
             const uint64_t Zk = k + 1 < D ? wv_rank0(a.words[k], a.dir[k], n) : 0ull;
 #pragma unroll
             for (uint32_t j = 0; j < DW; j++) {
-                if ((bw + j) * 64 + lane >= n) continue;
                 const uint32_t bit = (uint32_t)(a.words[k][p[j] >> 6] >> (p[j] & 63)) & 1u;
                 d[j] = (d[j] << 1) | bit;
                 if (k + 1 < D) {
@@ -170,62 +200,81 @@ digits_k(wv_digit_levels a, uint64_t n, uint64_t nwords, uint64_t* __restrict__ 
     }
 }
 
-// The same for 2-bit digits with no rank query per word: a workgroup takes
-// DG words of level bD, scans their zero counts, and needs the rank only at
-// its first word; every position's place on level bD+1 is then that rank
-// plus the zeros before its word in the workgroup plus those below it in
-// its word.  Each wave walks 64 of the words, eight at a time, so the only
-// global load per word (the bit on level bD+1) is issued eight at once.
+// The low popcount(m) bits of x, in order, moved to the set positions of m
+// (bit expand, the inverse of compress; the parallel-suffix network of
+// Hacker's Delight, Sec. 7-5): six masks from m, then six shift-and-merge steps.
+__device__ inline uint64_t expand64(uint64_t x, uint64_t m)
+{
+    const uint64_t m0 = m;
+    uint64_t mk = ~m << 1;   // a one where the next lower bit is a zero of m
+    uint64_t mv[6];
+#pragma unroll
+    for (int i = 0; i < 6; i++) {
+        // parallel suffix: bit b of mp = parity of the zeros of m below b
+        uint64_t mp = mk ^ (mk << 1);
+        mp ^= mp << 2;
+        mp ^= mp << 4;
+        mp ^= mp << 8;
+        mp ^= mp << 16;
+        mp ^= mp << 32;
+        mv[i] = mp & m;                               // bits that move by 2^i
+        m = (m ^ mv[i]) | (mv[i] >> (1 << i));
+        mk &= ~mp;
+    }
+#pragma unroll
+    for (int i = 5; i >= 0; i--) {
+        const uint64_t t = x << (1 << i);
+        x = (x & ~mv[i]) | (t & mv[i]);
+    }
+    return x & m0;
+}
+
+// 64 bits of a level from bit `pos` (pos < n); the word after the last is not
+// read (bits past n are never used)
+__device__ inline uint64_t bits64(const uint64_t* __restrict__ w, uint64_t pos, uint64_t nw)
+{
+    const uint64_t i = pos >> 6;
+    const uint32_t o = (uint32_t)(pos & 63);
+    const uint64_t lo = w[i], hi = w[min(i + 1, nw - 1)];
+    return o ? (lo >> o) | (hi << (64 - o)) : lo;
+}
+
+// The same for 2-bit digits, one thread per word of level bD and no rank
+// query per word: the zeros of word k go, in order, to consecutive positions
+// of level bD+1 from zr (the zeros before the word), its ones to consecutive
+// positions from Z + (64k - zr).  The low digit bits of the word are therefore
+// the 64 bits of level bD+1 at zr expanded onto its zeros, merged with the 64
+// bits at Z + 64k - zr expanded onto its ones.  A workgroup scans its words'
+// zero counts and needs one rank query, at its first word.
 constexpr uint32_t DG = 256;
 
 __global__ void __launch_bounds__(DG)
 digits2_k(wv_digit_levels a, uint64_t n, uint64_t nwords, uint64_t* __restrict__ out)
 {
-    __shared__ uint64_t sw[DG];
-    __shared__ uint32_t sz[DG];
     __shared__ uint32_t wsum[DG / 64];
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t nw0 = wv_cdiv(n, 64);
     const uint64_t c0 = (uint64_t)blockIdx.x * DG;
-    const uint64_t wi = c0 + tid;
-    const uint64_t w = wi < nw0 ? a.words[0][wi] : 0ull;
-    const uint32_t valid = wi < nw0 ? (uint32_t)min<uint64_t>(64, n - wi * 64) : 0u;
+    const uint64_t k = c0 + tid;
+    const uint64_t r0c = wv_rank0(a.words[0], a.dir[0], c0 * 64);
+    const uint64_t Z0 = wv_rank0(a.words[0], a.dir[0], n);
+    const uint64_t w = k < nw0 ? a.words[0][k] : 0ull;
+    const uint32_t valid = k < nw0 ? (uint32_t)min<uint64_t>(64, n - k * 64) : 0u;
+    const uint64_t vm = valid >= 64 ? ~0ull : ((1ull << valid) - 1ull);
     const uint32_t z = valid - (uint32_t)__popcll(w);   // padding bits are 0
     const uint32_t inc = wv_wave_incl_scan(z);
     if (lane == 63) wsum[wave] = inc;
     __syncthreads();
+    if (k >= nw0) return;
     uint32_t off = 0;
-    for (uint32_t k = 0; k < wave; k++) off += wsum[k];
-    sw[tid] = w;
-    sz[tid] = off + inc - z;
-    const uint64_t r0c = wv_rank0(a.words[0], a.dir[0], c0 * 64);
-    const uint64_t Z0 = wv_rank0(a.words[0], a.dir[0], n);
-    __syncthreads();
-    const uint64_t pmask = 0xFFFFFFFFull;
-    for (uint32_t j0 = 0; j0 < 64; j0 += 8) {
-        uint32_t d[8];
-#pragma unroll
-        for (uint32_t u = 0; u < 8; u++) {
-            const uint32_t k = wave * 64 + j0 + u;
-            const uint64_t w0 = sw[k];
-            const uint64_t pos = (c0 + k) * 64 + lane;
-            const uint32_t bit = (uint32_t)(w0 >> lane) & 1u;
-            const uint64_t r0 = r0c + sz[k] +
-                                __builtin_amdgcn_mbcnt_hi((uint32_t)(~w0 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)~w0, 0u));
-            const uint64_t p = bit ? Z0 + (pos - r0) : r0;
-            d[u] = pos < n ? ((bit << 1) | ((uint32_t)(a.words[1][p >> 6] >> (p & 63)) & 1u)) : 0u;
-        }
-#pragma unroll
-        for (uint32_t u = 0; u < 8; u++) {
-            const uint64_t k = c0 + wave * 64 + j0 + u;
-            if (k >= nw0) break;   // uniform
-            const uint64_t b0 = __ballot(d[u] & 1u), b1 = __ballot((d[u] >> 1) & 1u);
-            if (lane < 2) {
-                const uint64_t wd = spread((b0 >> (lane * 32)) & pmask, 2) | (spread((b1 >> (lane * 32)) & pmask, 2) << 1);
-                if (k * 2 + lane < nwords) out[k * 2 + lane] = wd;
-            }
-        }
-    }
+    for (uint32_t q = 0; q < wave; q++) off += wsum[q];
+    const uint64_t zr = r0c + off + inc - z;   // zeros of level bD before word k
+    const uint64_t A = bits64(a.words[1], min(zr, n - 1), nw0);
+    const uint64_t B = bits64(a.words[1], min(Z0 + (k * 64 - zr), n - 1), nw0);
+    const uint64_t lo = expand64(A, ~w & vm) | expand64(B, w);
+    // digit e of the word at bits 2e (level bD+1) and 2e+1 (level bD)
+    out[2 * k] = spread(lo & 0xFFFFFFFFull, 2) | (spread(w & 0xFFFFFFFFull, 2) << 1);
+    if (2 * k + 1 < nwords) out[2 * k + 1] = spread(lo >> 32, 2) | (spread(w >> 32, 2) << 1);
 }
 
 inline uint64_t brev_bits(uint64_t v, uint32_t nbits)
@@ -314,9 +363,15 @@ hipError_t wv_tree_digits(const wv_digit_levels& a, uint64_t n, uint32_t D, uint
 }
 
 hipError_t wv_tree_permute(const wv_perm_level* lv_dev, uint32_t nlev, const wv_perm_seg* seg_dev,
-                           uint64_t total_words, hipStream_t s)
+                           uint64_t total_words, const wv_perm_counts* counts, hipStream_t s)
 {
     if (!total_words) return hipSuccess;
-    perm_runs_k<<<(uint32_t)wv_cdiv(total_words, 256), 256, 0, s>>>(lv_dev, nlev, seg_dev, total_words);
+    const uint32_t g = (uint32_t)wv_cdiv(total_words, 256);
+    if (counts) {
+        if (total_words % 64 || (counts->D != 1 && counts->D != 2 && counts->D != 4)) return hipErrorInvalidValue;
+        perm_runs_k<true><<<g, 256, 0, s>>>(lv_dev, nlev, seg_dev, total_words, *counts);
+    } else {
+        perm_runs_k<false><<<g, 256, 0, s>>>(lv_dev, nlev, seg_dev, total_words, wv_perm_counts{});
+    }
     return hipGetLastError();
 }
