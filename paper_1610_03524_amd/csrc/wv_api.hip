@@ -30,7 +30,7 @@ struct Plan {
     uint64_t ws_codes = 0, ws_lens = 0, ws_wm = 0;
     // trees gathered from matrix levels (balanced and shaped binary trees)
     bool from_matrix = false;
-    uint64_t ws_tkeys = 0, ws_tmp = 0, tmp_stride = 0, ws_segs = 0, seg_bound = 0;
+    uint64_t ws_tkeys = 0, ws_tmp = 0, tmp_stride = 0, ws_segs = 0, seg_bound = 0, tile_bound = 0;
     uint64_t ws_tmpimg = 0, ws_digits = 0, dstride = 0;   // multiary: matrix image, digit strings
     wv_layout_out tlay{};
     uint64_t ws_bytes = 0;
@@ -76,6 +76,12 @@ int sorted_codes(const wt_shape& sh, uint32_t sigma, uint32_t h, std::vector<Cod
     }
     *nnodes = nodes;
     return WT_OK;
+}
+
+// workspace of the gather's level descriptors, runs and tile table
+inline uint64_t seg_bytes(uint64_t segs, uint64_t tiles)
+{
+    return wv_round256(WV_MAX_LEVELS * sizeof(wv_perm_level)) + wv_round256(segs * sizeof(wv_perm_seg)) + tiles * 4 + 256;
 }
 
 int make_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt_shape* shape,
@@ -206,7 +212,8 @@ int make_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt
         p.ws_digits = bump(off, p.dstride * p.nlevels);
         for (uint32_t b = 0; b < p.nlevels; b++)
             p.seg_bound += std::min<uint64_t>((((uint64_t)sigma - 1) >> (p.key_bits - p.D * b)) + 1, n);
-        p.ws_segs = bump(off, p.seg_bound * sizeof(wv_perm_seg) + WV_MAX_LEVELS * sizeof(wv_perm_level) + 256);
+        p.tile_bound = wv_tree_tile_bound(n, p.D, p.nlevels);
+        p.ws_segs = bump(off, seg_bytes(p.seg_bound, p.tile_bound));
         p.ws_counts = bump(off, (uint64_t)sigma * 8);
         p.ws_bytes = off;
         return WT_OK;
@@ -223,7 +230,8 @@ int make_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt
             for (uint32_t l = 0; l < p.key_bits; l++)
                 p.seg_bound += std::min<uint64_t>((((uint64_t)sigma - 1) >> (p.key_bits - l)) + 1, n);
         }
-        p.ws_segs = bump(off, p.seg_bound * sizeof(wv_perm_seg) + WV_MAX_LEVELS * sizeof(wv_perm_level) + 256);
+        p.tile_bound = wv_tree_tile_bound(n, 1, p.key_bits);
+        p.ws_segs = bump(off, seg_bytes(p.seg_bound, p.tile_bound));
         p.ws_counts = bump(off, (uint64_t)sigma * 8);
         if (kind == WT_KIND_SHAPED) {
             p.ws_codes = bump(off, (uint64_t)sigma * 4);
@@ -544,30 +552,34 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
         return rc;
     }
     std::vector<wv_perm_level> lv(T);
-    uint64_t words = 0;
     for (uint32_t l = 0; l < T; l++) {
         lv[l].dst = (uint64_t*)(img + p.lay.lv[l].bits_off);
         lv[l].src = multi ? at<uint64_t>(ws, p.ws_digits + l * p.dstride) : at<uint64_t>(ws, p.ws_tmp + l * p.tmp_stride);
         lv[l].nbits = p.lay.lv[l].n * D;
         lv[l].seg0 = seg0[l];
         lv[l].nseg = seg0[l + 1] - seg0[l];
-        lv[l].word0 = words;
         lv[l].sub = nullptr;
-        if (multi) {
-            // whole 64-word counter ranges per level; sub-range counters follow the range counters
-            const uint64_t nr = wv_mranges(p.lay.lv[l].n, D);
-            lv[l].sub = (uint16_t*)(img + p.lay.lv[l].rank_off + (nr + 1) * (8ull << D));
-            words += nr * 64;
-        } else {
-            words += wv_cdiv(lv[l].nbits, 64);
-        }
+        // multiary: the sub-range counters follow the range counters
+        if (multi) lv[l].sub = (uint16_t*)(img + p.lay.lv[l].rank_off + (wv_mranges(p.lay.lv[l].n, D) + 1) * (8ull << D));
     }
+    std::vector<uint32_t> tile0, tile_seg;
+    wv_tree_tiles(lv, segs, multi, tile0, tile_seg);
+    if (tile_seg.size() > p.tile_bound) {
+        WV_CHECK(hipStreamSynchronize(s));
+        return WT_EUNSUP;
+    }
+    // descriptors, runs and tiles in one copy
+    const uint64_t seg_at = wv_round256(WV_MAX_LEVELS * sizeof(wv_perm_level));
+    const uint64_t tile_at = seg_at + wv_round256(segs.size() * sizeof(wv_perm_seg));
+    std::vector<uint8_t> stage(tile_at + tile_seg.size() * 4);
+    std::memcpy(stage.data(), lv.data(), T * sizeof(wv_perm_level));
+    if (!segs.empty()) std::memcpy(stage.data() + seg_at, segs.data(), segs.size() * sizeof(wv_perm_seg));
+    if (!tile_seg.empty()) std::memcpy(stage.data() + tile_at, tile_seg.data(), tile_seg.size() * 4);
     uint8_t* dsegs = at<uint8_t>(ws, p.ws_segs);
-    wv_perm_level* dlv = (wv_perm_level*)dsegs;
-    wv_perm_seg* dseg = (wv_perm_seg*)(dsegs + wv_round256(WV_MAX_LEVELS * sizeof(wv_perm_level)));
-    WV_CHECK(hipMemcpyAsync(dlv, lv.data(), T * sizeof(wv_perm_level), hipMemcpyHostToDevice, s));
-    if (!segs.empty())
-        WV_CHECK(hipMemcpyAsync(dseg, segs.data(), segs.size() * sizeof(wv_perm_seg), hipMemcpyHostToDevice, s));
+    WV_CHECK(hipMemcpyAsync(dsegs, stage.data(), stage.size(), hipMemcpyHostToDevice, s));
+    const wv_perm_level* dlv = (const wv_perm_level*)dsegs;
+    const wv_perm_seg* dseg = (const wv_perm_seg*)(dsegs + seg_at);
+    const uint32_t* dtile = (const uint32_t*)(dsegs + tile_at);
     if (shaped) {
         if (!rec.empty())
             WV_CHECK(hipMemcpyAsync(img + p.lay.nodes_off, rec.data(), rec.size(), hipMemcpyHostToDevice, s));
@@ -579,7 +591,8 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
     const wv_mdir_scratch md{at<uint32_t>(ws, p.ws_sb_ones), at<uint64_t>(ws, p.ws_sb_pre),
                              at<uint64_t>(ws, p.ws_partial), at<uint64_t>(ws, p.ws_mtot)};
     const wv_perm_counts pc{md.rng_cnt, n, D, T};
-    WV_TIMED(prof, s, "tree_perm", WV_CHECK(wv_tree_permute(dlv, T, dseg, words, multi ? &pc : nullptr, s)));
+    WV_TIMED(prof, s, "tree_perm",
+             WV_CHECK(wv_tree_permute(dlv, T, dseg, dtile, tile0.data(), multi ? &pc : nullptr, s)));
     uint8_t* dscr = at<uint8_t>(ws, p.ws_wm + p.wm.off_dir);
     if (multi) {
         WV_TIMED(prof, s, "mcounters", WV_CHECK(wv_multiary_ranges(img, p.lay.lv, T, D, md, s)));

@@ -43,14 +43,19 @@ __host__ __device__ inline uint32_t wv_key_bits(uint32_t sigma)
 __host__ __device__ inline uint64_t wv_bits_bytes(uint64_t m) { return wv_cdiv(m, 64) * 8; }
 __host__ __device__ inline uint64_t wv_rank_bytes(uint64_t m) { return (wv_cdiv(m, WV_SB_BITS) + 1) * 16; }
 __host__ __device__ inline uint64_t wv_nsel(uint64_t m) { return wv_cdiv(m, WV_SEL_STRIDE) + 1; }
-__host__ __device__ inline uint32_t wv_digits_per_word(uint32_t D) { return 64u / D; }
-__host__ __device__ inline uint64_t wv_mbits_bytes(uint64_t m, uint32_t D)
+__host__ __device__ inline uint32_t wv_digits_per_word(uint32_t D) { return D == 3 ? 21u : 64u >> (D >> 1); }
+// ceil(m / (words * digits per word)); a shift for D = 1, 2, 4 (no 64-bit
+// division on the device)
+__host__ __device__ inline uint64_t wv_mdiv_words(uint64_t m, uint32_t D, uint32_t words_log2)
 {
-    return wv_cdiv(m, wv_digits_per_word(D)) * 8;
+    if (D == 3) return wv_cdiv(m, (21ull << words_log2));
+    const uint32_t sh = words_log2 + 6 - (D >> 1);
+    return (m + (1ull << sh) - 1) >> sh;
 }
+__host__ __device__ inline uint64_t wv_mbits_bytes(uint64_t m, uint32_t D) { return wv_mdiv_words(m, D, 0) * 8; }
 // multiary counters: range = 64 words, sub-range = 8 words
-__host__ __device__ inline uint64_t wv_mranges(uint64_t m, uint32_t D) { return wv_cdiv(m, 64ull * wv_digits_per_word(D)); }
-__host__ __device__ inline uint64_t wv_msubs(uint64_t m, uint32_t D) { return wv_cdiv(m, 8ull * wv_digits_per_word(D)); }
+__host__ __device__ inline uint64_t wv_mranges(uint64_t m, uint32_t D) { return wv_mdiv_words(m, D, 6); }
+__host__ __device__ inline uint64_t wv_msubs(uint64_t m, uint32_t D) { return wv_mdiv_words(m, D, 3); }
 __host__ __device__ inline uint64_t wv_mrank_bytes(uint64_t m, uint32_t D)
 {
     uint64_t d = 1ull << D;
@@ -185,8 +190,9 @@ __device__ inline uint32_t wv_count_digit(uint64_t w, uint32_t D, uint32_t g, ui
 {
     if (t == 0) return 0;
     // low-bit-of-every-digit mask: bits 0, D, 2D, ... of the P = 64/D digits
-    const uint32_t used = (64u / D) * D;
-    const uint64_t lowm = (used >= 64 ? ~0ull : ((1ull << used) - 1ull)) / ((1ull << D) - 1ull);
+    // (D = 1..4; a constant per width, no division)
+    const uint64_t lowm = D == 1 ? ~0ull : D == 2 ? 0x5555555555555555ull
+                        : D == 3 ? 0x1249249249249249ull : 0x1111111111111111ull;
     uint64_t pat = lowm * (uint64_t)g;
     uint64_t x = w ^ pat;               // digit == g  <=>  digit of x == 0
     uint64_t any = x;
@@ -200,7 +206,7 @@ __device__ inline uint32_t wv_count_digit(uint64_t w, uint32_t D, uint32_t g, ui
 __device__ inline uint64_t wv_mrank(const uint64_t* __restrict__ words, const uint8_t* __restrict__ cnt,
                                     uint64_t m, uint32_t D, uint32_t g, uint64_t i)
 {
-    const uint32_t P = 64u / D;
+    const uint32_t P = wv_digits_per_word(D);
     const uint64_t d = 1ull << D;
     const uint64_t nr = wv_mranges(m, D);
     const uint64_t* rng = (const uint64_t*)cnt;

@@ -134,7 +134,7 @@ mcount_k(const uint8_t* __restrict__ image, MLevels a, uint32_t* __restrict__ rn
 {
     const uint32_t lane = threadIdx.x & 63, t = blockIdx.y;
     const uint64_t r = ((uint64_t)blockIdx.x * DIR_THREADS + threadIdx.x) >> 6;
-    const uint32_t D = a.D, P = 64u / D, d = 1u << D;
+    const uint32_t D = a.D, P = wv_digits_per_word(D), d = 1u << D;
     const uint64_t m = a.m, nr = wv_mranges(m, D), nw = wv_cdiv(m, P);
     if (r >= nr) return;   // whole waves: the scans below need every lane
     const uint64_t* words = (const uint64_t*)(image + a.bits_off[t]);
@@ -152,7 +152,7 @@ mwrite_k(uint8_t* __restrict__ image, MLevels a, const uint64_t* __restrict__ rn
 {
     const uint32_t lane = threadIdx.x & 63, t = blockIdx.y;
     const uint64_t r = ((uint64_t)blockIdx.x * DIR_THREADS + threadIdx.x) >> 6;
-    const uint32_t D = a.D, P = 64u / D, d = 1u << D;
+    const uint32_t D = a.D, P = wv_digits_per_word(D), d = 1u << D;
     const uint64_t m = a.m, nr = wv_mranges(m, D), nsub = wv_msubs(m, D), nw = wv_cdiv(m, P);
     if (r >= nr) return;   // whole waves
     const uint64_t* words = (const uint64_t*)(image + a.bits_off[t]);
@@ -430,7 +430,7 @@ hipError_t wv_validate(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t s
         if (e != hipSuccess) return e;
     }
     if (!n) return hipSuccess;
-    const uint32_t grid = grid_for(n, DIR_THREADS * 64, 2048);
+    const uint32_t grid = grid_for(n, DIR_THREADS * 64, 1024);
     if (sym_bytes == 1) validate_k<uint8_t><<<grid, DIR_THREADS, 0, s>>>(S, n, sigma, status, c);
     else if (sym_bytes == 2) validate_k<uint16_t><<<grid, DIR_THREADS, 0, s>>>(S, n, sigma, status, c);
     else validate_k<uint32_t><<<grid, DIR_THREADS, 0, s>>>(S, n, sigma, status, c);

@@ -15,22 +15,38 @@ struct wv_perm_seg {
 struct wv_perm_level {
     uint64_t* dst;          // tree level words (in the image)
     const uint64_t* src;    // matrix level words (one readable word past the end)
-    uint64_t nbits;         // symbols on the tree level
+    uint64_t nbits;         // bits on the tree level
     uint64_t seg0, nseg;    // its runs in the segment array
-    uint64_t word0;         // first output word of the level in the launch
     uint16_t* sub;          // multiary: the level's sub-range counters (counting launch only)
 };
 
 // Counters of multiary levels taken while gathering them: every level holds
-// m digits of D bits, starts on a multiple of 64 words in the launch and
-// covers wv_mranges(m, D) * 64 words of it (the words past its end are
-// skipped).  rng_cnt[(r * M + l) * 2^D + g] receives the number of digits g in
-// range r of level l, and each level's sub-range counters are written.
+// m digits of D bits.  rng_cnt[(r * M + l) * 2^D + g] receives the number of
+// digits g in 64-word range r of level l, and each level's sub-range counters
+// are written.
 struct wv_perm_counts {
     uint32_t* rng_cnt;
     uint64_t m;
     uint32_t D, M;
 };
+
+// output words per workgroup of the gather (one per thread)
+constexpr uint32_t WV_PERM_TILE = 256;
+
+// The gather's tiles: level l covers tiles tile0[l] .. tile0[l+1]-1 (its
+// words, or with `counting` its whole 64-word counter ranges, in tiles of
+// WV_PERM_TILE words), and tile_seg[t] is the run holding the first bit of
+// tile t (the last run of its level when the tile starts past the level's
+// bits).  Returns the number of tiles.
+uint32_t wv_tree_tiles(const std::vector<wv_perm_level>& lv, const std::vector<wv_perm_seg>& segs, bool counting,
+                       std::vector<uint32_t>& tile0, std::vector<uint32_t>& tile_seg);
+
+// upper bound of the tiles of nlev levels of at most n symbols of D bits
+inline uint64_t wv_tree_tile_bound(uint64_t n, uint32_t D, uint32_t nlev)
+{
+    const uint64_t words = wv_cdiv(wv_cdiv(n * D, 64), 64) * 64;
+    return (uint64_t)nlev * (wv_cdiv(words, WV_PERM_TILE) + 1) + 1;
+}
 
 // Runs of every level 0..key_bits-1 from the symbol counts.  Balanced tree:
 // codes == nullptr, key = symbol.  Shaped tree: key = codes[x] padded at the
@@ -54,7 +70,9 @@ struct wv_digit_levels {
 // (ceil(n*D/64) words; D = 1, 2 or 4)
 hipError_t wv_tree_digits(const wv_digit_levels& a, uint64_t n, uint32_t D, uint64_t* out, hipStream_t s);
 
-// gather every tree level (descriptors and runs already on the device); with
-// `counts`, the levels are multiary and their counters are taken on the way
+// gather every tree level (descriptors, runs and tile_seg already on the
+// device; tile0 on the host, nlev + 1 entries); with `counts`, the levels are
+// multiary and their counters are taken on the way
 hipError_t wv_tree_permute(const wv_perm_level* lv_dev, uint32_t nlev, const wv_perm_seg* seg_dev,
-                           uint64_t total_words, const wv_perm_counts* counts, hipStream_t s);
+                           const uint32_t* tile_seg_dev, const uint32_t* tile0, const wv_perm_counts* counts,
+                           hipStream_t s);

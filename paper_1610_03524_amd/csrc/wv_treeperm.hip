@@ -52,35 +52,44 @@ __device__ inline uint64_t bits_at(const uint64_t* __restrict__ w, uint64_t pos,
     return nb >= 64 ? v : (v & ((1ull << nb) - 1ull));
 }
 
-// One thread per output word: the run holding its first bit is found by a
-// binary search over the level's runs, then its bits are gathered run by run.
-// COUNT (multiary levels, every level starting on a wave): each wave is one
-// 64-word range of one level, and its scans of the per-word digit counts give
-// the range totals and the counts before every 8-word sub-range (Sec. 5's
-// two-level counters, taken here instead of in a second pass over the level).
+struct PermArgs {
+    const wv_perm_level* lv;
+    const wv_perm_seg* seg;
+    const uint32_t* tile_seg;
+    uint32_t tile0[WV_MAX_LEVELS + 1];
+    uint32_t nlev;
+    wv_perm_counts cnt;
+};
+
+// One thread per output word, a workgroup per tile of one level: the run
+// holding the word's first bit is searched among the runs that cover the tile
+// (from the tile's first run to the next tile's), then its bits are gathered
+// run by run.  COUNT (multiary levels): each wave is one 64-word range of one
+// level, and its scans of the per-word digit counts give the range totals and
+// the counts before every 8-word sub-range (Sec. 5's two-level counters,
+// taken here instead of in a second pass over the level).
 template <bool COUNT>
-__global__ void __launch_bounds__(256)
-perm_runs_k(const wv_perm_level* __restrict__ lv, uint32_t nlev, const wv_perm_seg* __restrict__ seg,
-            uint64_t total_words, wv_perm_counts cnt)
+__global__ void __launch_bounds__(WV_PERM_TILE)
+perm_runs_k(PermArgs a)
 {
-    const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= total_words) return;   // with COUNT total_words is a multiple of 64: whole waves
+    const uint32_t b = blockIdx.x;
     uint32_t l = 0;
-    while (l + 1 < nlev && lv[l + 1].word0 <= t) l++;
-    const wv_perm_level L = lv[l];
-    const uint64_t w = t - L.word0;
+    while (l + 1 < a.nlev && a.tile0[l + 1] <= b) l++;   // uniform
+    const wv_perm_level L = a.lv[l];
+    const uint64_t w = (uint64_t)(b - a.tile0[l]) * WV_PERM_TILE + threadIdx.x;
     const uint64_t nw = wv_cdiv(L.nbits, 64);
     uint64_t out = 0;
     if (w < nw) {
         const uint64_t p0 = w * 64, end = min(p0 + 64, L.nbits);
         // the run holding bit p0: the last one starting at or before it
-        uint64_t lo = L.seg0, hi = L.seg0 + L.nseg - 1;
+        uint64_t lo = a.tile_seg[b];
+        uint64_t hi = b + 1 < a.tile0[l + 1] ? a.tile_seg[b + 1] : L.seg0 + L.nseg - 1;
         while (lo < hi) {
             const uint64_t mid = (lo + hi + 1) >> 1;
-            if (seg[mid].dst <= p0) lo = mid; else hi = mid - 1;
+            if (a.seg[mid].dst <= p0) lo = mid; else hi = mid - 1;
         }
         for (uint64_t p = p0, k = lo; p < end; k++) {
-            const wv_perm_seg g = seg[k];
+            const wv_perm_seg g = a.seg[k];
             const uint64_t in = p - g.dst;
             const uint32_t take = (uint32_t)min(end - p, g.len - in);
             out |= bits_at(L.src, g.src + in, take) << (p - p0);
@@ -89,8 +98,10 @@ perm_runs_k(const wv_perm_level* __restrict__ lv, uint32_t nlev, const wv_perm_s
         L.dst[w] = out;
     }
     if (COUNT) {
-        const uint32_t lane = threadIdx.x & 63, D = cnt.D, P = 64u / D, d = 1u << D;
+        const wv_perm_counts& cnt = a.cnt;
+        const uint32_t lane = threadIdx.x & 63, D = cnt.D, P = wv_digits_per_word(D), d = 1u << D;
         const uint64_t r = w >> 6, sk = w >> 3;
+        if (r >= wv_mranges(cnt.m, D)) return;   // whole waves
         const uint32_t c = w < nw ? (uint32_t)min<uint64_t>(P, cnt.m - w * P) : 0u;
         const bool subw = (lane & 7) == 0 && sk < wv_msubs(cnt.m, D);
         for (uint32_t g0 = 0; g0 < d; g0 += 4) {
@@ -362,16 +373,47 @@ hipError_t wv_tree_digits(const wv_digit_levels& a, uint64_t n, uint32_t D, uint
     return hipGetLastError();
 }
 
-hipError_t wv_tree_permute(const wv_perm_level* lv_dev, uint32_t nlev, const wv_perm_seg* seg_dev,
-                           uint64_t total_words, const wv_perm_counts* counts, hipStream_t s)
+uint32_t wv_tree_tiles(const std::vector<wv_perm_level>& lv, const std::vector<wv_perm_seg>& segs, bool counting,
+                       std::vector<uint32_t>& tile0, std::vector<uint32_t>& tile_seg)
 {
-    if (!total_words) return hipSuccess;
-    const uint32_t g = (uint32_t)wv_cdiv(total_words, 256);
+    tile0.assign(lv.size() + 1, 0);
+    tile_seg.clear();
+    for (uint32_t l = 0; l < lv.size(); l++) {
+        const wv_perm_level& L = lv[l];
+        tile0[l] = (uint32_t)tile_seg.size();
+        const uint64_t words = counting ? wv_cdiv(wv_cdiv(L.nbits, 64), 64) * 64 : wv_cdiv(L.nbits, 64);
+        if (!L.nseg) continue;   // no bits, no tiles
+        const uint64_t tiles = wv_cdiv(words, WV_PERM_TILE), last = L.seg0 + L.nseg - 1;
+        uint64_t k = L.seg0;
+        for (uint64_t t = 0; t < tiles; t++) {
+            const uint64_t p = t * WV_PERM_TILE * 64;
+            while (k < last && segs[k + 1].dst <= p) k++;
+            tile_seg.push_back((uint32_t)k);
+        }
+    }
+    tile0[lv.size()] = (uint32_t)tile_seg.size();
+    return tile0[lv.size()];
+}
+
+hipError_t wv_tree_permute(const wv_perm_level* lv_dev, uint32_t nlev, const wv_perm_seg* seg_dev,
+                           const uint32_t* tile_seg_dev, const uint32_t* tile0, const wv_perm_counts* counts,
+                           hipStream_t s)
+{
+    if (!nlev || nlev > WV_MAX_LEVELS) return nlev ? hipErrorInvalidValue : hipSuccess;
+    const uint32_t tiles = tile0[nlev];
+    if (!tiles) return hipSuccess;
+    PermArgs a{};
+    a.lv = lv_dev;
+    a.seg = seg_dev;
+    a.tile_seg = tile_seg_dev;
+    for (uint32_t l = 0; l <= nlev; l++) a.tile0[l] = tile0[l];
+    a.nlev = nlev;
     if (counts) {
-        if (total_words % 64 || (counts->D != 1 && counts->D != 2 && counts->D != 4)) return hipErrorInvalidValue;
-        perm_runs_k<true><<<g, 256, 0, s>>>(lv_dev, nlev, seg_dev, total_words, *counts);
+        if (counts->D != 1 && counts->D != 2 && counts->D != 4) return hipErrorInvalidValue;
+        a.cnt = *counts;
+        perm_runs_k<true><<<tiles, WV_PERM_TILE, 0, s>>>(a);
     } else {
-        perm_runs_k<false><<<g, 256, 0, s>>>(lv_dev, nlev, seg_dev, total_words, wv_perm_counts{});
+        perm_runs_k<false><<<tiles, WV_PERM_TILE, 0, s>>>(a);
     }
     return hipGetLastError();
 }
