@@ -331,6 +331,12 @@ struct BatchPlan {
     uint64_t desc_total = 0;
 };
 
+// most tiles per chunk of a batched build, and the chunks each resident pass
+// workgroup should get at least (a sequence's chunk count is also capped at
+// the resident pass workgroups, as for one build)
+constexpr uint64_t BATCH_CHUNK_TILES = 16;
+constexpr uint64_t BATCH_CHUNKS_PER_WORKER = 4;
+
 int make_batch_plan(const wt_seq_desc* seqs, uint32_t count, const wt_tuning* tune, BatchPlan& bp)
 {
     bp.seq.resize(count);
@@ -338,12 +344,21 @@ int make_batch_plan(const wt_seq_desc* seqs, uint32_t count, const wt_tuning* tu
     auto bump = [&](uint64_t bytes) { uint64_t at = off; off = wv_round256(off + bytes); return at; };
     bp.off_queue = bump(256);
     uint64_t total_chunks = 0, total_spans = 0, total_dch = 0;
+    // One persistent launch serves every sequence, so a chunk can span many
+    // tiles: fewer chunks mean fewer histogram workgroups, offset tables and
+    // shared boundary words.  Chunks grow only while every pass workgroup
+    // still gets about BATCH_CHUNKS_PER_WORKER of them.
+    uint64_t total_tiles = 0;
+    for (uint32_t i = 0; i < count; i++) total_tiles += wv_cdiv(seqs[i].n ? seqs[i].n : 1, T);
+    const uint64_t tiles_per_chunk =
+        std::min<uint64_t>(BATCH_CHUNK_TILES, std::max<uint64_t>(1, total_tiles / ((uint64_t)KMAX * BATCH_CHUNKS_PER_WORKER)));
     // H of every sequence first (zeroed by one fill every round)
     for (uint32_t i = 0; i < count; i++) {
         const wt_seq_desc& d = seqs[i];
         wt_tuning t1 = tune ? *tune : wt_tuning{};
         if (d.tau) t1.tau = d.tau;
         t1.flags &= ~WT_FLAG_LEVELWISE;
+        if (!t1.blocks) t1.blocks = (uint32_t)std::max<uint64_t>(1, wv_cdiv(wv_cdiv(d.n ? d.n : 1, T), tiles_per_chunk));
         wv_wm_plan wp;
         int rc = wv_wm_make_plan(d.n, d.sigma, d.sym_bytes, &t1, wp);
         if (rc) return rc;
