@@ -33,6 +33,13 @@ struct Plan {
     uint64_t ws_tkeys = 0, ws_tmp = 0, tmp_stride = 0, ws_segs = 0, seg_bound = 0, tile_bound = 0;
     uint64_t ws_tmpimg = 0, ws_digits = 0, dstride = 0;   // multiary: matrix image, digit strings
     wv_layout_out tlay{};
+    // shaped trees split at level h1: matrix A over the top h1 bits of every
+    // codeword (p.wm), matrix B over the whole codewords of the nlong symbols
+    // whose codes are longer than h1 (wmb)
+    uint32_t h1 = 0;
+    uint64_t nlong = 0, ws_lkeys = 0, ws_btmp = 0, btmp_stride = 0, ws_wmb = 0;
+    uint64_t ws_bcnt = 0, ws_boff = 0, ws_bpart = 0, nkblocks = 0, ws_sdir = 0;   // ws_sdir: directory scratch, all levels
+    wv_wm_plan wmb{};
     uint64_t ws_bytes = 0;
     wv_wm_plan wm{};
 };
@@ -215,6 +222,48 @@ int make_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt
         p.tile_bound = wv_tree_tile_bound(n, p.D, p.nlevels);
         p.ws_segs = bump(off, seg_bytes(p.seg_bound, p.tile_bound));
         p.ws_counts = bump(off, (uint64_t)sigma * 8);
+        p.ws_bytes = off;
+        return WT_OK;
+    }
+    if (p.from_matrix && kind == WT_KIND_SHAPED && p.key_bits > WV_SPLIT_BITS) {
+        // codes longer than WV_SPLIT_BITS are rare in a skewed alphabet: the
+        // first matrix then needs 16-bit keys and fewer passes, and the deep
+        // levels come from a small second matrix over those symbols alone
+        uint64_t nlong = 0;
+        for (uint32_t x = 0; x < sigma; x++)
+            if (shape->code_len[x] > WV_SPLIT_BITS) nlong += shape->counts[x];
+        wv_wm_plan a{}, b{};
+        if (nlong * WV_SPLIT_SHARE <= n && wv_wm_make_plan(n, 1u << WV_SPLIT_BITS, 2, tune, a) == WT_OK && a.enabled &&
+            (!nlong || (wv_wm_make_plan(nlong, 1u << p.key_bits, 4, tune, b) == WT_OK && b.enabled))) {
+            p.h1 = WV_SPLIT_BITS;
+            p.nlong = nlong;
+            p.wm = a;
+            p.wmb = b;
+        }
+    }
+    if (p.from_matrix && p.h1) {
+        p.tau = p.wm.tau;
+        p.ws_wm = bump(off, p.wm.ws_bytes);
+        p.tmp_stride = wv_round256(wv_bits_bytes(n) + 8);   // one readable word past each level
+        p.ws_tmp = bump(off, p.tmp_stride * p.h1);
+        p.ws_tkeys = bump(off, n * 2);
+        p.nkblocks = wv_tree_key_blocks(n);
+        p.ws_bcnt = bump(off, p.nkblocks * 4);
+        p.ws_boff = bump(off, p.nkblocks * 8 + 8);
+        p.ws_bpart = bump(off, 8 * wv_scan_partials(p.nkblocks, 1) + 8);
+        if (p.nlong) {
+            p.ws_wmb = bump(off, p.wmb.ws_bytes);
+            p.btmp_stride = wv_round256(wv_bits_bytes(p.nlong) + 8);
+            p.ws_btmp = bump(off, p.btmp_stride * p.key_bits);
+            p.ws_lkeys = bump(off, p.nlong * 4);
+        }
+        p.seg_bound = p.nnodes_image;
+        p.tile_bound = wv_tree_tile_bound(n, 1, p.key_bits);
+        p.ws_segs = bump(off, seg_bytes(p.seg_bound, p.tile_bound));
+        p.ws_counts = bump(off, (uint64_t)sigma * 8);
+        p.ws_codes = bump(off, (uint64_t)sigma * 4);
+        p.ws_lens = bump(off, (uint64_t)sigma * 4);
+        p.ws_sdir = bump(off, wv_span_dir_sizes(n, p.key_bits).bytes);
         p.ws_bytes = off;
         return WT_OK;
     }
@@ -483,9 +532,24 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
         }
         WV_CHECK(hipMemcpyAsync(at<void>(ws, p.ws_codes), c32.data(), (uint64_t)sigma * 4, hipMemcpyHostToDevice, s));
         WV_CHECK(hipMemcpyAsync(at<void>(ws, p.ws_lens), l32.data(), (uint64_t)sigma * 4, hipMemcpyHostToDevice, s));
-        WV_TIMED(prof, s, "tree_keys",
-                 WV_CHECK(wv_tree_keys(S, n, p.sym_bytes, sigma, at<uint32_t>(ws, p.ws_codes),
-                                       at<uint32_t>(ws, p.ws_lens), K, at<uint32_t>(ws, p.ws_tkeys), s)));
+        const uint32_t* dc = at<uint32_t>(ws, p.ws_codes);
+        const uint32_t* dl = at<uint32_t>(ws, p.ws_lens);
+        if (p.h1) {
+            // top h1 bits of every codeword, then the long codewords compacted
+            uint64_t* boff = at<uint64_t>(ws, p.ws_boff);
+            WV_TIMED(prof, s, "tree_keys",
+                     WV_CHECK(wv_tree_keys_split(S, n, p.sym_bytes, sigma, dc, dl, K, p.h1, at<uint16_t>(ws, p.ws_tkeys),
+                                                 at<uint32_t>(ws, p.ws_bcnt), s)));
+            WV_TIMED(prof, s, "tree_keys",
+                     WV_CHECK(wv_scan_u32(at<uint32_t>(ws, p.ws_bcnt), boff, p.nkblocks, 1, at<uint64_t>(ws, p.ws_bpart),
+                                          boff + p.nkblocks, s)));
+            WV_TIMED(prof, s, "tree_keys",
+                     WV_CHECK(wv_tree_long_keys(S, n, p.sym_bytes, sigma, dc, dl, K, p.h1, boff,
+                                                at<uint32_t>(ws, p.ws_lkeys), p.nlong, s)));
+        } else {
+            WV_TIMED(prof, s, "tree_keys",
+                     WV_CHECK(wv_tree_keys(S, n, p.sym_bytes, sigma, dc, dl, K, at<uint32_t>(ws, p.ws_tkeys), s)));
+        }
         keys = at<void>(ws, p.ws_tkeys);
     }
     if (multi) {
@@ -501,6 +565,15 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
             }
             WV_TIMED(prof, s, "tree_digits",
                      WV_CHECK(wv_tree_digits(dl, n, D, at<uint64_t>(ws, p.ws_digits + t * p.dstride), s)));
+        }
+    } else if (p.h1) {
+        // S itself was validated above; the keys need no check
+        uint64_t* lw[WV_MAX_LEVELS];
+        for (uint32_t l = 0; l < p.h1; l++) lw[l] = at<uint64_t>(ws, p.ws_tmp + l * p.tmp_stride);
+        WV_CHECK(wv_wm_levels(p.wm, keys, lw, nullptr, at<uint8_t>(ws, p.ws_wm), s));
+        if (p.nlong) {
+            for (uint32_t l = 0; l < K; l++) lw[l] = at<uint64_t>(ws, p.ws_btmp + l * p.btmp_stride);
+            WV_CHECK(wv_wm_levels(p.wmb, at<void>(ws, p.ws_lkeys), lw, nullptr, at<uint8_t>(ws, p.ws_wmb), s));
         }
     } else {
         uint64_t* lw[WV_MAX_LEVELS];
@@ -531,6 +604,21 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
     std::vector<uint64_t> seg0;
     if (!rc) {
         wv_tree_segments(counts, K, shaped ? c32.data() : nullptr, shaped ? l32.data() : nullptr, segs, seg0);
+        if (p.h1) {
+            // levels from h1 on hold the long-code symbols only, as matrix B
+            std::vector<uint64_t> cl(counts);
+            for (uint32_t x = 0; x < sigma; x++)
+                if (l32[x] <= p.h1) cl[x] = 0;
+            std::vector<wv_perm_seg> sb;
+            std::vector<uint64_t> s0b;
+            wv_tree_segments(cl, K, c32.data(), l32.data(), sb, s0b);
+            segs.resize(seg0[p.h1]);
+            for (uint32_t l = p.h1; l < K; l++) {
+                seg0[l] = segs.size();
+                segs.insert(segs.end(), sb.begin() + s0b[l], sb.begin() + s0b[l + 1]);
+            }
+            seg0[K] = segs.size();
+        }
         // tree level t: matrix level t (binary), or digit level t from matrix
         // level t*D with every run D bits per symbol (multiary)
         if (multi) {
@@ -554,7 +642,9 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
     std::vector<wv_perm_level> lv(T);
     for (uint32_t l = 0; l < T; l++) {
         lv[l].dst = (uint64_t*)(img + p.lay.lv[l].bits_off);
-        lv[l].src = multi ? at<uint64_t>(ws, p.ws_digits + l * p.dstride) : at<uint64_t>(ws, p.ws_tmp + l * p.tmp_stride);
+        lv[l].src = multi ? at<uint64_t>(ws, p.ws_digits + l * p.dstride)
+                  : (p.h1 && l >= p.h1) ? at<uint64_t>(ws, p.ws_btmp + l * p.btmp_stride)
+                                        : at<uint64_t>(ws, p.ws_tmp + l * p.tmp_stride);
         lv[l].nbits = p.lay.lv[l].n * D;
         lv[l].seg0 = seg0[l];
         lv[l].nseg = seg0[l + 1] - seg0[l];
@@ -593,7 +683,7 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
     const wv_perm_counts pc{md.rng_cnt, n, D, T};
     WV_TIMED(prof, s, "tree_perm",
              WV_CHECK(wv_tree_permute(dlv, T, dseg, dtile, tile0.data(), multi ? &pc : nullptr, s)));
-    uint8_t* dscr = at<uint8_t>(ws, p.ws_wm + p.wm.off_dir);
+    uint8_t* dscr = p.h1 ? at<uint8_t>(ws, p.ws_sdir) : at<uint8_t>(ws, p.ws_wm + p.wm.off_dir);
     if (multi) {
         WV_TIMED(prof, s, "mcounters", WV_CHECK(wv_multiary_ranges(img, p.lay.lv, T, D, md, s)));
     } else if (shaped) {

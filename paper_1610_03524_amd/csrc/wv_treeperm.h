@@ -60,6 +60,30 @@ void wv_tree_segments(const std::vector<uint64_t>& counts, uint32_t key_bits, co
 hipError_t wv_tree_keys(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma, const uint32_t* codes,
                         const uint32_t* lens, uint32_t h, uint32_t* keys, hipStream_t s);
 
+// Shaped trees with codes longer than WV_SPLIT_BITS whose symbols make at most
+// 1/WV_SPLIT_SHARE of the sequence are built from two matrices: one over the
+// top WV_SPLIT_BITS bits of every padded codeword (levels above the split),
+// one over the whole codewords of the long-code symbols alone, in input order
+// (the levels below it, where only those symbols remain).
+constexpr uint32_t WV_SPLIT_BITS = 16;
+constexpr uint64_t WV_SPLIT_SHARE = 8;
+
+// blocks of the two key kernels below
+uint64_t wv_tree_key_blocks(uint64_t n);
+
+// keys[i] = top h1 bits of codes[S[i]] padded to h bits (0 for S[i] >= sigma);
+// bcnt[b] = symbols of block b whose code is longer than h1
+hipError_t wv_tree_keys_split(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma, const uint32_t* codes,
+                              const uint32_t* lens, uint32_t h, uint32_t h1, uint16_t* keys, uint32_t* bcnt,
+                              hipStream_t s);
+
+// lkeys[r] = padded codeword of the r-th symbol (in input order) whose code is
+// longer than h1, boff = exclusive prefix of bcnt; ranks >= nlong are not
+// written (a sequence whose counts differ from the shape is rejected later)
+hipError_t wv_tree_long_keys(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma, const uint32_t* codes,
+                             const uint32_t* lens, uint32_t h, uint32_t h1, const uint64_t* boff, uint32_t* lkeys,
+                             uint64_t nlong, hipStream_t s);
+
 // matrix levels bD .. bD+D-1 (words and rank directories) of one multiary level
 struct wv_digit_levels {
     const uint64_t* words[4];

@@ -41,6 +41,85 @@ tree_keys_k(const T* __restrict__ S, uint64_t n, uint32_t sigma, const uint32_t*
     keys[i] = x < sigma ? codes[x] << (h - lens[x]) : 0u;
 }
 
+// Split shaped build: a block takes KB_E elements per thread, strided by the
+// block size so that every load instruction reads consecutive symbols; the
+// loads use a clamped index so that all of them are in flight at once.
+constexpr uint32_t KB_T = 256, KB_E = 16, KB = KB_T * KB_E;
+
+template <typename T>
+__global__ void __launch_bounds__(KB_T)
+tree_keys_split_k(const T* __restrict__ S, uint64_t n, uint32_t sigma, const uint32_t* __restrict__ codes,
+                  const uint32_t* __restrict__ lens, uint32_t h, uint32_t h1, uint16_t* __restrict__ keys,
+                  uint32_t* __restrict__ bcnt)
+{
+    __shared__ uint32_t wc[KB_T / 64];
+    const uint64_t b0 = (uint64_t)blockIdx.x * KB;
+    uint32_t xs[KB_E];
+#pragma unroll
+    for (uint32_t e = 0; e < KB_E; e++) xs[e] = (uint32_t)S[min(b0 + e * KB_T + threadIdx.x, n - 1)];
+    uint32_t c = 0;
+#pragma unroll
+    for (uint32_t e = 0; e < KB_E; e++) {
+        const uint64_t i = b0 + e * KB_T + threadIdx.x;
+        const uint32_t x = xs[e];
+        const bool ok = i < n && x < sigma;
+        const uint32_t len = ok ? lens[x] : 0u;
+        if (i < n) keys[i] = ok ? (uint16_t)((codes[x] << (h - len)) >> (h - h1)) : (uint16_t)0;
+        c += (uint32_t)__popcll(__ballot(ok && len > h1));
+    }
+    if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (uint32_t w = 0; w < KB_T / 64; w++) t += wc[w];
+        bcnt[blockIdx.x] = t;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(KB_T)
+tree_long_keys_k(const T* __restrict__ S, uint64_t n, uint32_t sigma, const uint32_t* __restrict__ codes,
+                 const uint32_t* __restrict__ lens, uint32_t h, uint32_t h1, const uint64_t* __restrict__ boff,
+                 uint32_t* __restrict__ lkeys, uint64_t nlong)
+{
+    __shared__ uint32_t pre[KB_E * (KB_T / 64)];
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t b0 = (uint64_t)blockIdx.x * KB;
+    uint32_t xs[KB_E];
+    uint64_t bl[KB_E];
+#pragma unroll
+    for (uint32_t e = 0; e < KB_E; e++) xs[e] = (uint32_t)S[min(b0 + e * KB_T + threadIdx.x, n - 1)];
+#pragma unroll
+    for (uint32_t e = 0; e < KB_E; e++) {
+        const uint64_t i = b0 + e * KB_T + threadIdx.x;
+        const bool lg = i < n && xs[e] < sigma && lens[xs[e]] > h1;
+        bl[e] = __ballot(lg);
+    }
+    // long symbols before every (element row, wave) slice of the block, in
+    // input order (row-major: element i = b0 + e * KB_T + wave * 64 + lane)
+    if (lane == 0)
+        for (uint32_t e = 0; e < KB_E; e++) pre[e * (KB_T / 64) + wave] = (uint32_t)__popcll(bl[e]);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (uint32_t k = 0; k < KB_E * (KB_T / 64); k++) {
+            const uint32_t v = pre[k];
+            pre[k] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    const uint64_t base = boff[blockIdx.x];
+#pragma unroll
+    for (uint32_t e = 0; e < KB_E; e++) {
+        if (!((bl[e] >> lane) & 1ull)) continue;
+        const uint64_t r = base + pre[e * (KB_T / 64) + wave] +
+                           __builtin_amdgcn_mbcnt_hi((uint32_t)(bl[e] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bl[e], 0u));
+        const uint32_t x = xs[e];
+        if (r < nlong) lkeys[r] = codes[x] << (h - lens[x]);
+    }
+}
+
 // `nb` (1..64) bits of a level bit string starting at bit `pos`; the array
 // has one readable word past its last word
 __device__ inline uint64_t bits_at(const uint64_t* __restrict__ w, uint64_t pos, uint32_t nb)
@@ -358,6 +437,38 @@ hipError_t wv_tree_keys(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t 
     if (sym_bytes == 1) tree_keys_k<uint8_t><<<g, 256, 0, s>>>((const uint8_t*)S, n, sigma, codes, lens, h, keys);
     else if (sym_bytes == 2) tree_keys_k<uint16_t><<<g, 256, 0, s>>>((const uint16_t*)S, n, sigma, codes, lens, h, keys);
     else tree_keys_k<uint32_t><<<g, 256, 0, s>>>((const uint32_t*)S, n, sigma, codes, lens, h, keys);
+    return hipGetLastError();
+}
+
+uint64_t wv_tree_key_blocks(uint64_t n) { return wv_cdiv(n ? n : 1, KB); }
+
+hipError_t wv_tree_keys_split(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma, const uint32_t* codes,
+                              const uint32_t* lens, uint32_t h, uint32_t h1, uint16_t* keys, uint32_t* bcnt,
+                              hipStream_t s)
+{
+    if (!n) return hipSuccess;
+    const uint32_t g = (uint32_t)wv_tree_key_blocks(n);
+    if (sym_bytes == 1)
+        tree_keys_split_k<uint8_t><<<g, KB_T, 0, s>>>((const uint8_t*)S, n, sigma, codes, lens, h, h1, keys, bcnt);
+    else if (sym_bytes == 2)
+        tree_keys_split_k<uint16_t><<<g, KB_T, 0, s>>>((const uint16_t*)S, n, sigma, codes, lens, h, h1, keys, bcnt);
+    else
+        tree_keys_split_k<uint32_t><<<g, KB_T, 0, s>>>((const uint32_t*)S, n, sigma, codes, lens, h, h1, keys, bcnt);
+    return hipGetLastError();
+}
+
+hipError_t wv_tree_long_keys(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma, const uint32_t* codes,
+                             const uint32_t* lens, uint32_t h, uint32_t h1, const uint64_t* boff, uint32_t* lkeys,
+                             uint64_t nlong, hipStream_t s)
+{
+    if (!n || !nlong) return hipSuccess;
+    const uint32_t g = (uint32_t)wv_tree_key_blocks(n);
+    if (sym_bytes == 1)
+        tree_long_keys_k<uint8_t><<<g, KB_T, 0, s>>>((const uint8_t*)S, n, sigma, codes, lens, h, h1, boff, lkeys, nlong);
+    else if (sym_bytes == 2)
+        tree_long_keys_k<uint16_t><<<g, KB_T, 0, s>>>((const uint16_t*)S, n, sigma, codes, lens, h, h1, boff, lkeys, nlong);
+    else
+        tree_long_keys_k<uint32_t><<<g, KB_T, 0, s>>>((const uint32_t*)S, n, sigma, codes, lens, h, h1, boff, lkeys, nlong);
     return hipGetLastError();
 }
 

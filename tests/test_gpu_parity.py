@@ -162,3 +162,31 @@ def test_trees_many_chunks(kind):
         g = gpu_image(kind, S, sigma, codes=gc, lens=gl)
         o = oracle_image(kind, S, sigma, codes=oc, lens=ol)
     assert_same(g, o, f"kind={kind} n={n}")
+
+
+def split_case(counts, long_len, rng):
+    """a shuffled sequence over four symbols with codes 0, 10, 110 0..0 and
+    111 1..1 (the last two long_len bits long)"""
+    codes = np.array([0, 0b10, 0b110 << (long_len - 3), (1 << long_len) - 1], dtype=np.uint64)
+    lens = np.array([1, 2, long_len, long_len], dtype=np.uint32)
+    S = np.repeat(np.arange(4, dtype=np.uint8), counts)
+    rng.shuffle(S)
+    return S, codes, lens
+
+
+@pytest.mark.parametrize("name,counts", [
+    ("split, few long", [70001, 30000, 5, 3]),       # deep levels from the small second matrix
+    ("split, no long", [50000, 20001, 0, 0]),        # long codes that never occur
+    ("no split, many long", [4000, 3000, 2500, 1501]),
+    ("two symbols", [1, 0, 1, 0]),                   # too few for a split
+])
+@pytest.mark.parametrize("long_len", [17, 20, 31])
+def test_shaped_split_at_16_bits(name, counts, long_len):
+    """shaped trees deeper than 16 levels: levels above 16 from a matrix over
+    16-bit key prefixes of every symbol, the deeper ones from a matrix over the
+    long-code symbols alone (when they are at most 1/8 of the sequence)"""
+    S, codes, lens = split_case(counts, long_len, np.random.default_rng(long_len + sum(counts)))
+    o = oracle_image(B.KIND_SHAPED, S, 4, codes=codes, lens=lens)
+    for tune in (None, B.make_tuning(tau=3, blocks=2)):
+        g = gpu_image(B.KIND_SHAPED, S, 4, codes=codes, lens=lens, tune=tune)
+        assert_same(g, o, f"{name} long_len={long_len} tune={tune is not None}")
