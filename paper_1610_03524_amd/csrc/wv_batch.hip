@@ -53,7 +53,7 @@ __device__ inline uint32_t owner_of(const uint32_t* first, uint32_t count, uint3
 __global__ void __launch_bounds__(HT)
 b_hist_k(const SeqRound* __restrict__ seqs, const uint32_t* __restrict__ chunk0, uint32_t nseq)
 {
-    __shared__ uint32_t h[HT / 64][256];
+    __shared__ uint32_t h[HWORDS];
     const uint32_t item = blockIdx.x / HSPLIT, part = blockIdx.x % HSPLIT;
     const uint32_t s = owner_of(chunk0, nseq, item);
     const SeqRound& q = seqs[s];

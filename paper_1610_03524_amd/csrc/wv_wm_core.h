@@ -264,6 +264,13 @@ __device__ void wm_pass_chunk(const PassArgs& a, uint32_t b, PassShared<KT_>& S)
 
 constexpr uint32_t HSPLIT = 8;       // histogram workgroups per chunk
 constexpr uint32_t HUNROLL = 4;      // 16-byte loads in flight per thread
+// LDS histograms of a workgroup: HCOPY per wave, lane l adding into copy
+// l % HCOPY, so that lanes holding the same frequent digit seldom hit one
+// address in one atomic; copies HSTRIDE words apart put a bin's copies in
+// different banks
+constexpr uint32_t HCOPY = 4;
+constexpr uint32_t HSTRIDE = 257;
+constexpr uint32_t HWORDS = (HT / 64) * HCOPY * HSTRIDE;
 
 __device__ inline uint32_t sym_of(const uint32_t* wds, uint32_t k, uint32_t size)
 {
@@ -277,12 +284,13 @@ template <typename IT>
 __device__ void wm_hist_part(const void* __restrict__ in, uint32_t n, uint32_t C, uint32_t K, uint32_t R,
                              uint32_t tau, uint32_t keymask, uint32_t* __restrict__ H,
                              uint32_t* __restrict__ status, uint32_t sigma, uint32_t b, uint32_t part,
-                             uint32_t (*h)[256])
+                             uint32_t* h)
 {
     const uint32_t wave = threadIdx.x >> 6;
     const uint32_t cs = b * C, ce = min(n, cs + C);
     const uint32_t dshift = R - tau, dmask = (1u << tau) - 1u;
-    for (uint32_t i = threadIdx.x; i < (HT / 64) * 256; i += HT) (&h[0][0])[i] = 0;
+    for (uint32_t i = threadIdx.x; i < HWORDS; i += HT) h[i] = 0;
+    uint32_t* hw = h + (wave * HCOPY + (threadIdx.x & (HCOPY - 1))) * HSTRIDE;
     __syncthreads();
     bool bad = false;
     constexpr uint32_t V = 16 / sizeof(IT);
@@ -310,27 +318,27 @@ __device__ void wm_hist_part(const void* __restrict__ in, uint32_t n, uint32_t C
                 bad |= x >= sigma;
                 const uint32_t d = ((x & keymask) >> dshift) & dmask;
                 if (d != cur) {
-                    atomicAdd(&h[wave][cur], run);
+                    atomicAdd(&hw[cur], run);
                     cur = d;
                     run = 0;
                 }
                 run++;
             }
-            atomicAdd(&h[wave][cur], run);
+            atomicAdd(&hw[cur], run);
         }
     }
     if (part == HSPLIT - 1) {
         for (uint32_t i = cs + nvec * V + threadIdx.x; i < ce; i += HT) {
             const uint32_t x = ld<IT>(in, i);
             bad |= x >= sigma;
-            atomicAdd(&h[wave][((x & keymask) >> dshift) & dmask], 1u);
+            atomicAdd(&hw[((x & keymask) >> dshift) & dmask], 1u);
         }
     }
     if (status && __ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(status, 1u);
     __syncthreads();
     if (threadIdx.x <= dmask) {
         uint32_t c = 0;
-        for (uint32_t w = 0; w < HT / 64; w++) c += h[w][threadIdx.x];
+        for (uint32_t k = 0; k < (HT / 64) * HCOPY; k++) c += h[k * HSTRIDE + threadIdx.x];
         if (c) atomicAdd(&H[(uint64_t)threadIdx.x * K + b], c);
     }
 }

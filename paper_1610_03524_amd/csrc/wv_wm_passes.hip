@@ -49,7 +49,7 @@ __global__ void __launch_bounds__(HT)
 wm_hist_k(const void* __restrict__ in, uint32_t n, uint32_t C, uint32_t K, uint32_t R, uint32_t tau,
           uint32_t keymask, uint32_t* __restrict__ H, uint32_t* __restrict__ status, uint32_t sigma)
 {
-    __shared__ uint32_t h[HT / 64][256];
+    __shared__ uint32_t h[HWORDS];
     wm_hist_part<IT>(in, n, C, K, R, tau, keymask, H, status, sigma, blockIdx.x / HSPLIT, blockIdx.x % HSPLIT, h);
 }
 
