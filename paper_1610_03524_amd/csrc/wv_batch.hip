@@ -110,7 +110,7 @@ b_offsets_k(const SeqRound* __restrict__ seqs, const uint32_t* __restrict__ chun
 
 // persistent pass: workgroups take chunks from the queue until it is empty
 template <typename KT_>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8)))
 b_pass_k(const SeqRound* __restrict__ seqs, const uint32_t* __restrict__ chunk0, uint32_t nseq,
          uint32_t nchunks, uint32_t* __restrict__ queue)
 {
@@ -126,15 +126,31 @@ b_pass_k(const SeqRound* __restrict__ seqs, const uint32_t* __restrict__ chunk0,
         const SeqRound& q = seqs[s];
         const uint32_t b = item - q.chunk0;
         const uint32_t ib = q.in_bytes, ob = q.out_bytes;
-        if (ib == 1) {
-            wm_pass_chunk<uint8_t, uint8_t, KT_>(q.pa, b, sh);
-        } else if (ib == 2) {
-            if (ob == 2) wm_pass_chunk<uint16_t, uint16_t, KT_>(q.pa, b, sh);
-            else wm_pass_chunk<uint16_t, uint8_t, KT_>(q.pa, b, sh);
+        // any input width (the first pass reads S as stored); the payload
+        // width follows the remaining key bits: at most 15 with 16-bit keys,
+        // at least 9 with 32-bit keys (17 or more bits, tau <= 8)
+        if constexpr (sizeof(KT_) == 2) {
+            if (ib == 1) {
+                if (ob == 2) wm_pass_chunk<uint8_t, uint16_t, KT_>(q.pa, b, sh);
+                else wm_pass_chunk<uint8_t, uint8_t, KT_>(q.pa, b, sh);
+            } else if (ib == 2) {
+                if (ob == 2) wm_pass_chunk<uint16_t, uint16_t, KT_>(q.pa, b, sh);
+                else wm_pass_chunk<uint16_t, uint8_t, KT_>(q.pa, b, sh);
+            } else {
+                if (ob == 2) wm_pass_chunk<uint32_t, uint16_t, KT_>(q.pa, b, sh);
+                else wm_pass_chunk<uint32_t, uint8_t, KT_>(q.pa, b, sh);
+            }
         } else {
-            if (ob == 4) wm_pass_chunk<uint32_t, uint32_t, KT_>(q.pa, b, sh);
-            else if (ob == 2) wm_pass_chunk<uint32_t, uint16_t, KT_>(q.pa, b, sh);
-            else wm_pass_chunk<uint32_t, uint8_t, KT_>(q.pa, b, sh);
+            if (ib == 1) {
+                if (ob == 4) wm_pass_chunk<uint8_t, uint32_t, KT_>(q.pa, b, sh);
+                else wm_pass_chunk<uint8_t, uint16_t, KT_>(q.pa, b, sh);
+            } else if (ib == 2) {
+                if (ob == 4) wm_pass_chunk<uint16_t, uint32_t, KT_>(q.pa, b, sh);
+                else wm_pass_chunk<uint16_t, uint16_t, KT_>(q.pa, b, sh);
+            } else {
+                if (ob == 4) wm_pass_chunk<uint32_t, uint32_t, KT_>(q.pa, b, sh);
+                else wm_pass_chunk<uint32_t, uint16_t, KT_>(q.pa, b, sh);
+            }
         }
         __syncthreads();
     }
@@ -579,7 +595,7 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
         WV_TIMED(prof, s, "b_hist", (b_hist_k<<<g.chunks * HSPLIT, HT, 0, s>>>(dq, dfirst, g.m)));
         WV_TIMED(prof, s, "b_scan", (b_scan_k<<<wv_cdiv(g.cols, HT / 64), HT, 0, s>>>(dq, dcfirst, g.m, g.cols)));
         WV_TIMED(prof, s, "b_offsets", (b_offsets_k<<<g.chunks, HT, 0, s>>>(dq, dfirst, g.m)));
-        const uint32_t workers = std::min<uint32_t>(g.chunks, KMAX);
+        const uint32_t workers = std::min<uint32_t>(g.chunks, g.wide ? KRES32 : KRES16);
         WV_TIMED(prof, s, "b_pass",
                  (g.wide ? (void)(b_pass_k<uint32_t><<<workers, NT, 0, s>>>(dq, dfirst, g.m, g.chunks, queue))
                          : (void)(b_pass_k<uint16_t><<<workers, NT, 0, s>>>(dq, dfirst, g.m, g.chunks, queue))));

@@ -14,7 +14,11 @@ constexpr int T = NT * E;           // tile
 constexpr int TW = T / 64;          // bit words per tile level
 constexpr int MAXG = 511;           // run groups of sub-levels j = 0..8
 constexpr int HT = 256;             // histogram / scan threads
-constexpr uint32_t KMAX = 768;      // chunks: 3 resident pass workgroups on each of 256 CUs
+// resident pass workgroups on the 256 CUs: four per CU (8 waves per SIMD
+// within 64 VGPRs) with 16-bit keys in LDS, three with 32-bit keys (LDS-bound)
+constexpr uint32_t KRES16 = 1024;
+constexpr uint32_t KRES32 = 768;
+constexpr uint32_t KMAX = KRES16;    // most chunks of one build by default
 
 
 __device__ __host__ inline uint32_t gidx(uint32_t j, uint32_t u) { return (1u << j) - 1u + u; }

@@ -37,7 +37,7 @@
 namespace {
 
 template <typename IT, typename OT, typename KT_>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8)))
 wm_pass_k(PassArgs a)
 {
     __shared__ PassShared<KT_> sh;
@@ -59,10 +59,12 @@ struct Geometry {
     uint32_t K, C;
 };
 
-Geometry geometry(uint64_t n, uint32_t blocks)
+// K chunks of C keys (a multiple of the tile); by default one chunk per
+// resident workgroup of the first pass (whose keys are the widest)
+Geometry geometry(uint64_t n, uint32_t blocks, uint32_t L)
 {
     const uint64_t tiles = wv_cdiv(n ? n : 1, T);
-    uint64_t K = blocks ? blocks : KMAX;
+    uint64_t K = blocks ? blocks : (L > 16 ? KRES32 : KRES16);
     K = std::min<uint64_t>(K, tiles);
     const uint64_t C = wv_cdiv(wv_cdiv(n ? n : 1, K), T) * T;
     return Geometry{(uint32_t)wv_cdiv(n ? n : 1, C), (uint32_t)C};
@@ -112,7 +114,7 @@ int wv_wm_make_plan(uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt_tun
         tau = (L + passes - 1) / passes;
     }
     tau = std::min(tau, L);
-    const Geometry geo = geometry(n, tune ? tune->blocks : 0);
+    const Geometry geo = geometry(n, tune ? tune->blocks : 0, L);
     p.enabled = true;
     p.profile = tune && (tune->flags & WT_FLAG_PROFILE);
     p.tau = tau;

@@ -11,17 +11,19 @@ from paper_1610_03524_amd import inputs
 pytestmark = pytest.mark.gpu
 
 
-def run_batch(seqs, tune=None):
-    """seqs: list of (numpy S, sigma); returns list of images (numpy)"""
+def run_batch(seqs, tune=None, taus=None):
+    """seqs: list of (numpy S, sigma); taus: per-sequence pass widths (0 =
+    default); returns list of images (numpy)"""
     import torch
     dev = [to_device(S) for S, _ in seqs]
     outs, descs = [], []
-    for (S, sigma), St in zip(seqs, dev):
+    for k, ((S, sigma), St) in enumerate(zip(seqs, dev)):
         info = B.plan(B.KIND_WM, S.size, sigma, S.itemsize, tune=tune)
         out = torch.empty(info.out_bytes, dtype=torch.uint8, device="cuda")
         d = B.wt_seq_desc()
         d.S, d.n, d.sigma, d.sym_bytes = St.data_ptr(), S.size, sigma, S.itemsize
         d.out, d.out_bytes = out.data_ptr(), info.out_bytes
+        d.tau = taus[k] if taus else 0
         outs.append(out)
         descs.append(d)
     need = B.batch_plan(B.KIND_WM, descs, tune)
@@ -69,3 +71,20 @@ def test_batch_rejects_small_output():
     with pytest.raises(B.WaveletError) as e:
         B.batch_plan(B.KIND_WM, [d])
     assert e.value.code == B.WT_ENOSPC
+
+
+def test_batch_every_input_and_payload_width():
+    """8- and 16-bit symbols under wide alphabets and narrow passes leave
+    16- or 32-bit remaining keys after the first pass (every combination of
+    input width and payload width of both key widths in LDS)"""
+    rng = np.random.default_rng(45)
+    seqs, taus = [], []
+    for dt, top in ((np.uint8, 256), (np.uint16, 65536), (np.uint32, 1 << 20)):
+        for sigma in (300, 4096, 1 << 17, 1 << 20):
+            for tau in (0, 2, 3, 8):
+                n = int(rng.integers(20000, 90000))
+                seqs.append((rng.integers(0, min(sigma, top), n).astype(dt), sigma))
+                taus.append(tau)
+    imgs = run_batch(seqs, taus=taus)
+    for k, ((S, sigma), g) in enumerate(zip(seqs, imgs)):
+        assert_same(g, oracle_image(B.KIND_WM, S, sigma), f"seq {k} {S.dtype} sigma={sigma} tau={taus[k]}")
