@@ -38,7 +38,7 @@ struct Plan {
     // whose codes are longer than h1 (wmb)
     uint32_t h1 = 0;
     uint64_t nlong = 0, ws_lkeys = 0, ws_btmp = 0, btmp_stride = 0, ws_wmb = 0;
-    uint64_t ws_bcnt = 0, ws_boff = 0, ws_bpart = 0, nkblocks = 0, ws_sdir = 0;   // ws_sdir: directory scratch, all levels
+    uint64_t ws_bcnt = 0, ws_boff = 0, ws_bpart = 0, nkblocks = 0, ws_sdir = 0, ws_ktab = 0;   // ws_sdir: directory scratch, all levels
     wv_wm_plan wmb{};
     uint64_t ws_bytes = 0;
     wv_wm_plan wm{};
@@ -264,6 +264,7 @@ int make_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt
         p.ws_codes = bump(off, (uint64_t)sigma * 4);
         p.ws_lens = bump(off, (uint64_t)sigma * 4);
         p.ws_sdir = bump(off, wv_span_dir_sizes(n, p.key_bits).bytes);
+        p.ws_ktab = bump(off, (uint64_t)sigma * 4);
         p.ws_bytes = off;
         return WT_OK;
     }
@@ -521,7 +522,7 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
 
     // 2. the matrix levels need no counts: launch them now, so that they run
     // while the host lays out the tree
-    std::vector<uint32_t> c32, l32;
+    std::vector<uint32_t> c32, l32, ktab;   // host arrays copied from: alive until the final synchronization
     const void* keys = S;
     if (shaped) {
         c32.resize(sigma);
@@ -536,15 +537,18 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
         const uint32_t* dl = at<uint32_t>(ws, p.ws_lens);
         if (p.h1) {
             // top h1 bits of every codeword, then the long codewords compacted
+            wv_split_table(c32.data(), l32.data(), sigma, K, p.h1, ktab);
+            WV_CHECK(hipMemcpyAsync(at<void>(ws, p.ws_ktab), ktab.data(), (uint64_t)sigma * 4, hipMemcpyHostToDevice, s));
+            const uint32_t* dk = at<uint32_t>(ws, p.ws_ktab);
             uint64_t* boff = at<uint64_t>(ws, p.ws_boff);
             WV_TIMED(prof, s, "tree_keys",
-                     WV_CHECK(wv_tree_keys_split(S, n, p.sym_bytes, sigma, dc, dl, K, p.h1, at<uint16_t>(ws, p.ws_tkeys),
+                     WV_CHECK(wv_tree_keys_split(S, n, p.sym_bytes, sigma, dk, at<uint16_t>(ws, p.ws_tkeys),
                                                  at<uint32_t>(ws, p.ws_bcnt), s)));
             WV_TIMED(prof, s, "tree_keys",
                      WV_CHECK(wv_scan_u32(at<uint32_t>(ws, p.ws_bcnt), boff, p.nkblocks, 1, at<uint64_t>(ws, p.ws_bpart),
                                           boff + p.nkblocks, s)));
             WV_TIMED(prof, s, "tree_keys",
-                     WV_CHECK(wv_tree_long_keys(S, n, p.sym_bytes, sigma, dc, dl, K, p.h1, boff,
+                     WV_CHECK(wv_tree_long_keys(S, n, p.sym_bytes, sigma, dk, dc, dl, K, boff,
                                                 at<uint32_t>(ws, p.ws_lkeys), p.nlong, s)));
         } else {
             WV_TIMED(prof, s, "tree_keys",

@@ -71,18 +71,25 @@ constexpr uint64_t WV_SPLIT_SHARE = 8;
 // blocks of the two key kernels below
 uint64_t wv_tree_key_blocks(uint64_t n);
 
-// keys[i] = top h1 bits of codes[S[i]] padded to h bits (0 for S[i] >= sigma);
-// bcnt[b] = symbols of block b whose code is longer than h1
-hipError_t wv_tree_keys_split(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma, const uint32_t* codes,
-                              const uint32_t* lens, uint32_t h, uint32_t h1, uint16_t* keys, uint32_t* bcnt,
-                              hipStream_t s);
+// the split table of every symbol x < sigma: the top h1 bits of its code
+// padded to h bits, plus WV_SPLIT_LONG when the code is longer than h1 (0 for
+// symbols without a code)
+constexpr uint32_t WV_SPLIT_LONG = 1u << 16;
+void wv_split_table(const uint32_t* codes, const uint32_t* lens, uint32_t sigma, uint32_t h, uint32_t h1,
+                    std::vector<uint32_t>& tab);
 
-// lkeys[r] = padded codeword of the r-th symbol (in input order) whose code is
-// longer than h1, boff = exclusive prefix of bcnt; ranks >= nlong are not
-// written (a sequence whose counts differ from the shape is rejected later)
-hipError_t wv_tree_long_keys(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma, const uint32_t* codes,
-                             const uint32_t* lens, uint32_t h, uint32_t h1, const uint64_t* boff, uint32_t* lkeys,
-                             uint64_t nlong, hipStream_t s);
+// keys[i] = the low 16 bits of ktab[S[i]] (0 for S[i] >= sigma); bcnt[b] =
+// symbols of block b whose code is longer than h1
+hipError_t wv_tree_keys_split(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma, const uint32_t* ktab,
+                              uint16_t* keys, uint32_t* bcnt, hipStream_t s);
+
+// lkeys[r] = padded codeword (codes[x] << (h - lens[x])) of the r-th symbol,
+// in input order, whose code is longer than h1; boff = exclusive prefix of
+// bcnt.  Ranks >= nlong are not written (a sequence whose counts differ from
+// the shape is rejected later).
+hipError_t wv_tree_long_keys(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma, const uint32_t* ktab,
+                             const uint32_t* codes, const uint32_t* lens, uint32_t h, const uint64_t* boff,
+                             uint32_t* lkeys, uint64_t nlong, hipStream_t s);
 
 // matrix levels bD .. bD+D-1 (words and rank directories) of one multiary level
 struct wv_digit_levels {

@@ -41,82 +41,156 @@ tree_keys_k(const T* __restrict__ S, uint64_t n, uint32_t sigma, const uint32_t*
     keys[i] = x < sigma ? codes[x] << (h - lens[x]) : 0u;
 }
 
-// Split shaped build: a block takes KB_E elements per thread, strided by the
-// block size so that every load instruction reads consecutive symbols; the
-// loads use a clamped index so that all of them are in flight at once.
-constexpr uint32_t KB_T = 256, KB_E = 16, KB = KB_T * KB_E;
+// Split shaped build.  A block takes KB symbols; with 16-byte aligned input
+// every thread reads V = 16 / sizeof(T) consecutive symbols per row with one
+// load (rows of KB_T * V symbols), else (and in a ragged last block) one
+// symbol per thread per row.
+constexpr uint32_t KB_T = 256, KB = 4096;
+
+template <typename T>
+struct SymVec {
+    static constexpr uint32_t V = 16 / sizeof(T);
+    T v[V];
+};
+
+// symbols [i, i + V) of the block's row (`vec`: one 16-byte load)
+template <typename T>
+__device__ inline void load_syms(const T* __restrict__ S, uint64_t i, uint64_t n, bool vec, SymVec<T>& out)
+{
+    constexpr uint32_t V = SymVec<T>::V;
+    if (vec) {
+        const uint4 q = *(const uint4*)(S + i);
+        __builtin_memcpy(out.v, &q, 16);
+    } else {
+#pragma unroll
+        for (uint32_t k = 0; k < V; k++) out.v[k] = i + k < n ? S[i + k] : (T)0;
+    }
+}
+
+// The split table of a symbol: its top h1 code bits, bit 16 set when its code
+// is longer than h1 (0 for symbols without a code).  Staged in LDS when sigma
+// is small; the workgroups then loop over the blocks of KB symbols.
+constexpr uint32_t KTAB_LDS = 8192;
+constexpr uint32_t KB_GRID = 1280;   // five resident workgroups per CU
+
+__device__ inline const uint32_t* stage_table(const uint32_t* __restrict__ ktab, uint32_t sigma, uint32_t* lds)
+{
+    if (sigma > KTAB_LDS) return ktab;
+    for (uint32_t x = threadIdx.x; x < sigma; x += KB_T) lds[x] = ktab[x];
+    __syncthreads();
+    return lds;
+}
 
 template <typename T>
 __global__ void __launch_bounds__(KB_T)
-tree_keys_split_k(const T* __restrict__ S, uint64_t n, uint32_t sigma, const uint32_t* __restrict__ codes,
-                  const uint32_t* __restrict__ lens, uint32_t h, uint32_t h1, uint16_t* __restrict__ keys,
-                  uint32_t* __restrict__ bcnt)
+tree_keys_split_k(const T* __restrict__ S, uint64_t n, uint32_t sigma, const uint32_t* __restrict__ ktab,
+                  uint16_t* __restrict__ keys, uint32_t* __restrict__ bcnt, uint64_t nblocks)
 {
+    constexpr uint32_t V = SymVec<T>::V, ROWS = KB / (KB_T * V);
+    __shared__ uint32_t tab_s[KTAB_LDS];
     __shared__ uint32_t wc[KB_T / 64];
-    const uint64_t b0 = (uint64_t)blockIdx.x * KB;
-    uint32_t xs[KB_E];
+    const uint32_t* tab = stage_table(ktab, sigma, tab_s);
+    for (uint64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+        const uint64_t b0 = blk * KB;
+        const bool vec = (((uintptr_t)S & 15u) == 0) && b0 + KB <= n;
+        SymVec<T> sv[ROWS];
 #pragma unroll
-    for (uint32_t e = 0; e < KB_E; e++) xs[e] = (uint32_t)S[min(b0 + e * KB_T + threadIdx.x, n - 1)];
-    uint32_t c = 0;
+        for (uint32_t r = 0; r < ROWS; r++) load_syms(S, b0 + (r * KB_T + threadIdx.x) * V, n, vec, sv[r]);
+        uint32_t c = 0;
 #pragma unroll
-    for (uint32_t e = 0; e < KB_E; e++) {
-        const uint64_t i = b0 + e * KB_T + threadIdx.x;
-        const uint32_t x = xs[e];
-        const bool ok = i < n && x < sigma;
-        const uint32_t len = ok ? lens[x] : 0u;
-        if (i < n) keys[i] = ok ? (uint16_t)((codes[x] << (h - len)) >> (h - h1)) : (uint16_t)0;
-        c += (uint32_t)__popcll(__ballot(ok && len > h1));
-    }
-    if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t t = 0;
-        for (uint32_t w = 0; w < KB_T / 64; w++) t += wc[w];
-        bcnt[blockIdx.x] = t;
+        for (uint32_t r = 0; r < ROWS; r++) {
+            const uint64_t i0 = b0 + (r * KB_T + threadIdx.x) * V;
+            uint16_t kk[V];
+#pragma unroll
+            for (uint32_t k = 0; k < V; k++) {
+                const uint32_t x = (uint32_t)sv[r].v[k];
+                const uint32_t t = i0 + k < n && x < sigma ? tab[x] : 0u;
+                kk[k] = (uint16_t)t;
+                c += t >> 16;
+            }
+            if (vec) {
+                // V 16-bit keys: 32 bytes (8-bit symbols), 16 (16-bit) or 8 (32-bit)
+                if constexpr (V >= 8) {
+#pragma unroll
+                    for (uint32_t k = 0; k < V; k += 8) {
+                        uint4 q;
+                        __builtin_memcpy(&q, kk + k, 16);
+                        *(uint4*)(keys + i0 + k) = q;
+                    }
+                } else {
+                    uint2 q;
+                    __builtin_memcpy(&q, kk, 8);
+                    *(uint2*)(keys + i0) = q;
+                }
+            } else {
+#pragma unroll
+                for (uint32_t k = 0; k < V; k++)
+                    if (i0 + k < n) keys[i0 + k] = kk[k];
+            }
+        }
+        c = wv_wave_incl_scan(c);
+        if ((threadIdx.x & 63) == 63) wc[threadIdx.x >> 6] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t t = 0;
+            for (uint32_t w = 0; w < KB_T / 64; w++) t += wc[w];
+            bcnt[blk] = t;
+        }
+        __syncthreads();
     }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(KB_T)
-tree_long_keys_k(const T* __restrict__ S, uint64_t n, uint32_t sigma, const uint32_t* __restrict__ codes,
-                 const uint32_t* __restrict__ lens, uint32_t h, uint32_t h1, const uint64_t* __restrict__ boff,
-                 uint32_t* __restrict__ lkeys, uint64_t nlong)
+tree_long_keys_k(const T* __restrict__ S, uint64_t n, uint32_t sigma, const uint32_t* __restrict__ ktab,
+                 const uint32_t* __restrict__ codes, const uint32_t* __restrict__ lens, uint32_t h,
+                 const uint64_t* __restrict__ boff, uint32_t* __restrict__ lkeys, uint64_t nlong, uint64_t nblocks)
 {
-    __shared__ uint32_t pre[KB_E * (KB_T / 64)];
+    constexpr uint32_t V = SymVec<T>::V, ROWS = KB / (KB_T * V);
+    __shared__ uint32_t tab_s[KTAB_LDS];
+    __shared__ uint32_t wsum[ROWS][KB_T / 64];
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint64_t b0 = (uint64_t)blockIdx.x * KB;
-    uint32_t xs[KB_E];
-    uint64_t bl[KB_E];
+    const uint32_t* tab = stage_table(ktab, sigma, tab_s);
+    for (uint64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+        const uint64_t b0 = blk * KB;
+        const bool vec = (((uintptr_t)S & 15u) == 0) && b0 + KB <= n;
+        SymVec<T> sv[ROWS];
 #pragma unroll
-    for (uint32_t e = 0; e < KB_E; e++) xs[e] = (uint32_t)S[min(b0 + e * KB_T + threadIdx.x, n - 1)];
+        for (uint32_t r = 0; r < ROWS; r++) load_syms(S, b0 + (r * KB_T + threadIdx.x) * V, n, vec, sv[r]);
+        // long symbols per thread and row; symbols are in input order row by
+        // row, thread by thread inside a row
+        uint32_t lm[ROWS], inc[ROWS];   // lm: bit k = symbol k of the thread's row piece is long
 #pragma unroll
-    for (uint32_t e = 0; e < KB_E; e++) {
-        const uint64_t i = b0 + e * KB_T + threadIdx.x;
-        const bool lg = i < n && xs[e] < sigma && lens[xs[e]] > h1;
-        bl[e] = __ballot(lg);
-    }
-    // long symbols before every (element row, wave) slice of the block, in
-    // input order (row-major: element i = b0 + e * KB_T + wave * 64 + lane)
-    if (lane == 0)
-        for (uint32_t e = 0; e < KB_E; e++) pre[e * (KB_T / 64) + wave] = (uint32_t)__popcll(bl[e]);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t run = 0;
-        for (uint32_t k = 0; k < KB_E * (KB_T / 64); k++) {
-            const uint32_t v = pre[k];
-            pre[k] = run;
-            run += v;
+        for (uint32_t r = 0; r < ROWS; r++) {
+            const uint64_t i0 = b0 + (r * KB_T + threadIdx.x) * V;
+            uint32_t m = 0;
+#pragma unroll
+            for (uint32_t k = 0; k < V; k++) {
+                const uint32_t x = (uint32_t)sv[r].v[k];
+                if (i0 + k < n && x < sigma && (tab[x] & WV_SPLIT_LONG)) m |= 1u << k;
+            }
+            lm[r] = m;
+            inc[r] = wv_wave_incl_scan((uint32_t)__popc(m));
+            if (lane == 63) wsum[r][wave] = inc[r];
         }
-    }
-    __syncthreads();
-    const uint64_t base = boff[blockIdx.x];
+        __syncthreads();
+        uint64_t base = boff[blk];
 #pragma unroll
-    for (uint32_t e = 0; e < KB_E; e++) {
-        if (!((bl[e] >> lane) & 1ull)) continue;
-        const uint64_t r = base + pre[e * (KB_T / 64) + wave] +
-                           __builtin_amdgcn_mbcnt_hi((uint32_t)(bl[e] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bl[e], 0u));
-        const uint32_t x = xs[e];
-        if (r < nlong) lkeys[r] = codes[x] << (h - lens[x]);
+        for (uint32_t r = 0; r < ROWS; r++) {
+            uint64_t rank = base + inc[r] - (uint32_t)__popc(lm[r]);
+            for (uint32_t w = 0; w < wave; w++) rank += wsum[r][w];
+            if (lm[r]) {
+#pragma unroll
+                for (uint32_t k = 0; k < V; k++) {
+                    if (!((lm[r] >> k) & 1u)) continue;
+                    const uint32_t x = (uint32_t)sv[r].v[k];
+                    if (rank < nlong) lkeys[rank] = codes[x] << (h - lens[x]);
+                    rank++;
+                }
+            }
+            for (uint32_t w = 0; w < KB_T / 64; w++) base += wsum[r][w];
+        }
+        __syncthreads();
     }
 }
 
@@ -442,33 +516,42 @@ hipError_t wv_tree_keys(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t 
 
 uint64_t wv_tree_key_blocks(uint64_t n) { return wv_cdiv(n ? n : 1, KB); }
 
-hipError_t wv_tree_keys_split(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma, const uint32_t* codes,
-                              const uint32_t* lens, uint32_t h, uint32_t h1, uint16_t* keys, uint32_t* bcnt,
-                              hipStream_t s)
+void wv_split_table(const uint32_t* codes, const uint32_t* lens, uint32_t sigma, uint32_t h, uint32_t h1,
+                    std::vector<uint32_t>& tab)
+{
+    tab.assign(sigma, 0u);
+    for (uint32_t x = 0; x < sigma; x++)
+        if (lens[x]) tab[x] = ((codes[x] << (h - lens[x])) >> (h - h1)) | (lens[x] > h1 ? WV_SPLIT_LONG : 0u);
+}
+
+hipError_t wv_tree_keys_split(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma, const uint32_t* ktab,
+                              uint16_t* keys, uint32_t* bcnt, hipStream_t s)
 {
     if (!n) return hipSuccess;
-    const uint32_t g = (uint32_t)wv_tree_key_blocks(n);
+    const uint64_t nb = wv_tree_key_blocks(n);
+    const uint32_t g = (uint32_t)std::min<uint64_t>(nb, KB_GRID);
     if (sym_bytes == 1)
-        tree_keys_split_k<uint8_t><<<g, KB_T, 0, s>>>((const uint8_t*)S, n, sigma, codes, lens, h, h1, keys, bcnt);
+        tree_keys_split_k<uint8_t><<<g, KB_T, 0, s>>>((const uint8_t*)S, n, sigma, ktab, keys, bcnt, nb);
     else if (sym_bytes == 2)
-        tree_keys_split_k<uint16_t><<<g, KB_T, 0, s>>>((const uint16_t*)S, n, sigma, codes, lens, h, h1, keys, bcnt);
+        tree_keys_split_k<uint16_t><<<g, KB_T, 0, s>>>((const uint16_t*)S, n, sigma, ktab, keys, bcnt, nb);
     else
-        tree_keys_split_k<uint32_t><<<g, KB_T, 0, s>>>((const uint32_t*)S, n, sigma, codes, lens, h, h1, keys, bcnt);
+        tree_keys_split_k<uint32_t><<<g, KB_T, 0, s>>>((const uint32_t*)S, n, sigma, ktab, keys, bcnt, nb);
     return hipGetLastError();
 }
 
-hipError_t wv_tree_long_keys(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma, const uint32_t* codes,
-                             const uint32_t* lens, uint32_t h, uint32_t h1, const uint64_t* boff, uint32_t* lkeys,
-                             uint64_t nlong, hipStream_t s)
+hipError_t wv_tree_long_keys(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma, const uint32_t* ktab,
+                             const uint32_t* codes, const uint32_t* lens, uint32_t h, const uint64_t* boff,
+                             uint32_t* lkeys, uint64_t nlong, hipStream_t s)
 {
     if (!n || !nlong) return hipSuccess;
-    const uint32_t g = (uint32_t)wv_tree_key_blocks(n);
+    const uint64_t nb = wv_tree_key_blocks(n);
+    const uint32_t g = (uint32_t)std::min<uint64_t>(nb, KB_GRID);
     if (sym_bytes == 1)
-        tree_long_keys_k<uint8_t><<<g, KB_T, 0, s>>>((const uint8_t*)S, n, sigma, codes, lens, h, h1, boff, lkeys, nlong);
+        tree_long_keys_k<uint8_t><<<g, KB_T, 0, s>>>((const uint8_t*)S, n, sigma, ktab, codes, lens, h, boff, lkeys, nlong, nb);
     else if (sym_bytes == 2)
-        tree_long_keys_k<uint16_t><<<g, KB_T, 0, s>>>((const uint16_t*)S, n, sigma, codes, lens, h, h1, boff, lkeys, nlong);
+        tree_long_keys_k<uint16_t><<<g, KB_T, 0, s>>>((const uint16_t*)S, n, sigma, ktab, codes, lens, h, boff, lkeys, nlong, nb);
     else
-        tree_long_keys_k<uint32_t><<<g, KB_T, 0, s>>>((const uint32_t*)S, n, sigma, codes, lens, h, h1, boff, lkeys, nlong);
+        tree_long_keys_k<uint32_t><<<g, KB_T, 0, s>>>((const uint32_t*)S, n, sigma, ktab, codes, lens, h, boff, lkeys, nlong, nb);
     return hipGetLastError();
 }
 

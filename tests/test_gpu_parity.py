@@ -181,11 +181,14 @@ def split_case(counts, long_len, rng):
     ("two symbols", [1, 0, 1, 0]),                   # too few for a split
 ])
 @pytest.mark.parametrize("long_len", [17, 20, 31])
-def test_shaped_split_at_16_bits(name, counts, long_len):
+@pytest.mark.parametrize("dt", [np.uint8, np.uint16, np.uint32])
+def test_shaped_split_at_16_bits(name, counts, long_len, dt):
     """shaped trees deeper than 16 levels: levels above 16 from a matrix over
     16-bit key prefixes of every symbol, the deeper ones from a matrix over the
-    long-code symbols alone (when they are at most 1/8 of the sequence)"""
+    long-code symbols alone (when they are at most 1/8 of the sequence); every
+    symbol width (16-byte loads of 16, 8 or 4 symbols, ragged last block)"""
     S, codes, lens = split_case(counts, long_len, np.random.default_rng(long_len + sum(counts)))
+    S = S.astype(dt)
     o = oracle_image(B.KIND_SHAPED, S, 4, codes=codes, lens=lens)
     for tune in (None, B.make_tuning(tau=3, blocks=2)):
         g = gpu_image(B.KIND_SHAPED, S, 4, codes=codes, lens=lens, tune=tune)
