@@ -507,7 +507,7 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
     const uint32_t D = multi ? p.D : 1u, T = multi ? p.nlevels : K;
     // 1. symbol counts and status to the host (waited for in step 3)
     uint64_t* dcounts = at<uint64_t>(ws, p.ws_counts);
-    WV_CHECK(wv_validate(S, n, p.sym_bytes, sigma, img, dcounts, s));
+    WV_TIMED(prof, s, "validate", WV_CHECK(wv_validate(S, n, p.sym_bytes, sigma, img, dcounts, s)));
     std::vector<uint64_t> counts(sigma);
     uint32_t status = 0;
     WV_CHECK(hipMemcpyAsync(counts.data(), dcounts, (uint64_t)sigma * 8, hipMemcpyDeviceToHost, s));
@@ -557,10 +557,32 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
         keys = at<void>(ws, p.ws_tkeys);
     }
     if (multi) {
-        // the whole matrix (with directories) in the workspace, then the digits
+        // the matrix levels in the workspace, then the digits: 2-bit digits
+        // need only the zeros before every 256-word block of the levels 2t,
+        // 16-ary digits query the matrix's rank directories
         uint8_t* timg = at<uint8_t>(ws, p.ws_tmpimg);
-        wv_dir_scratch unused{};
-        WV_CHECK(wv_wm_run(p.wm, S, timg, p.tlay, at<uint8_t>(ws, p.ws_wm), unused, s));
+        const uint64_t *zpre = nullptr, *ztot = nullptr;
+        if (D == 4) {
+            wv_dir_scratch unused{};
+            WV_CHECK(wv_wm_run(p.wm, S, timg, p.tlay, at<uint8_t>(ws, p.ws_wm), unused, s));
+        } else {
+            uint64_t* lw[WV_MAX_LEVELS];
+            for (uint32_t l = 0; l < K; l++) lw[l] = (uint64_t*)(timg + p.tlay.lv[l].bits_off);
+            WV_CHECK(wv_wm_levels(p.wm, S, lw, nullptr, at<uint8_t>(ws, p.ws_wm), s));
+            if (D == 2) {
+                // scratch of the digit counters, not used before the gather
+                wv_digit_words dw{};
+                for (uint32_t t = 0; t < T; t++) dw.w[t] = lw[2 * t];
+                uint32_t* cnt = at<uint32_t>(ws, p.ws_sb_ones);
+                uint64_t* pre = at<uint64_t>(ws, p.ws_sb_pre);
+                uint64_t* tot = at<uint64_t>(ws, p.ws_mtot);
+                WV_TIMED(prof, s, "tree_digits", WV_CHECK(wv_digit_zero_counts(dw, n, T, cnt, s)));
+                WV_TIMED(prof, s, "tree_digits",
+                         WV_CHECK(wv_scan_u32(cnt, pre, wv_digit_blocks(n), T, at<uint64_t>(ws, p.ws_partial), tot, s)));
+                zpre = pre;
+                ztot = tot;
+            }
+        }
         for (uint32_t t = 0; t < T; t++) {
             wv_digit_levels dl{};
             for (uint32_t k = 0; k < D; k++) {
@@ -568,7 +590,7 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
                 dl.dir[k] = (const uint64_t*)(timg + p.tlay.lv[t * D + k].rank_off);
             }
             WV_TIMED(prof, s, "tree_digits",
-                     WV_CHECK(wv_tree_digits(dl, n, D, at<uint64_t>(ws, p.ws_digits + t * p.dstride), s)));
+                     WV_CHECK(wv_tree_digits(dl, n, D, at<uint64_t>(ws, p.ws_digits + t * p.dstride), zpre, ztot, t, T, s)));
         }
     } else if (p.h1) {
         // S itself was validated above; the keys need no check

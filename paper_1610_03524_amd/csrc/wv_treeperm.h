@@ -97,9 +97,24 @@ struct wv_digit_levels {
     const uint64_t* dir[4];
 };
 
+// words of the matrix levels 2t of a 4-ary tree (t < T)
+struct wv_digit_words {
+    const uint64_t* w[WV_MAX_LEVELS / 2];
+};
+
+// workgroups of the 2-bit digit kernel (and rows of the zero counts below)
+uint64_t wv_digit_blocks(uint64_t n);
+
+// cnt[b * T + t] = zeros in block b of matrix level 2t (blocks of 256 words)
+hipError_t wv_digit_zero_counts(const wv_digit_words& a, uint64_t n, uint32_t T, uint32_t* cnt, hipStream_t s);
+
 // the digit string of one multiary level in the order of matrix level bD
-// (ceil(n*D/64) words; D = 1, 2 or 4)
-hipError_t wv_tree_digits(const wv_digit_levels& a, uint64_t n, uint32_t D, uint64_t* out, hipStream_t s);
+// (ceil(n*D/64) words; D = 1, 2 or 4).  D = 2 takes the zeros before every
+// block of level 2t from zpre[b * T + t] (the exclusive scan of the zero
+// counts above) and the level's zeros from ztot[t] instead of rank queries;
+// D = 4 queries the rank directories in `a`.
+hipError_t wv_tree_digits(const wv_digit_levels& a, uint64_t n, uint32_t D, uint64_t* out, const uint64_t* zpre,
+                          const uint64_t* ztot, uint32_t t, uint32_t T, hipStream_t s);
 
 // gather every tree level (descriptors, runs and tile_seg already on the
 // device; tile0 on the host, nlev + 1 entries); with `counts`, the levels are

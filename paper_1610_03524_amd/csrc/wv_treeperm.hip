@@ -409,19 +409,21 @@ __device__ inline uint64_t bits64(const uint64_t* __restrict__ w, uint64_t pos, 
 // positions from Z + (64k - zr).  The low digit bits of the word are therefore
 // the 64 bits of level bD+1 at zr expanded onto its zeros, merged with the 64
 // bits at Z + 64k - zr expanded onto its ones.  A workgroup scans its words'
-// zero counts and needs one rank query, at its first word.
+// zero counts; the zeros before its first word and Z come from a scan of the
+// zero counts of every workgroup (digit_zeros_k).
 constexpr uint32_t DG = 256;
 
 __global__ void __launch_bounds__(DG)
-digits2_k(wv_digit_levels a, uint64_t n, uint64_t nwords, uint64_t* __restrict__ out)
+digits2_k(wv_digit_levels a, uint64_t n, uint64_t nwords, uint64_t* __restrict__ out, const uint64_t* __restrict__ zpre,
+          const uint64_t* __restrict__ ztot, uint32_t t, uint32_t T)
 {
     __shared__ uint32_t wsum[DG / 64];
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t nw0 = wv_cdiv(n, 64);
     const uint64_t c0 = (uint64_t)blockIdx.x * DG;
     const uint64_t k = c0 + tid;
-    const uint64_t r0c = wv_rank0(a.words[0], a.dir[0], c0 * 64);
-    const uint64_t Z0 = wv_rank0(a.words[0], a.dir[0], n);
+    const uint64_t r0c = zpre[(uint64_t)blockIdx.x * T + t];   // zeros of level 2t before the block
+    const uint64_t Z0 = ztot[t];
     const uint64_t w = k < nw0 ? a.words[0][k] : 0ull;
     const uint32_t valid = k < nw0 ? (uint32_t)min<uint64_t>(64, n - k * 64) : 0u;
     const uint64_t vm = valid >= 64 ? ~0ull : ((1ull << valid) - 1ull);
@@ -514,7 +516,40 @@ hipError_t wv_tree_keys(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t 
     return hipGetLastError();
 }
 
+namespace {
+
+// zeros of every DG-word block of the levels 2t (t < T), column t of row b
+__global__ void __launch_bounds__(DG)
+digit_zeros_k(wv_digit_words a, uint64_t n, uint32_t T, uint32_t* __restrict__ cnt)
+{
+    __shared__ uint32_t wsum[DG / 64];
+    const uint32_t t = blockIdx.y;
+    const uint64_t nw0 = wv_cdiv(n, 64);
+    const uint64_t k = (uint64_t)blockIdx.x * DG + threadIdx.x;
+    uint32_t z = 0;
+    if (k < nw0) z = (uint32_t)min<uint64_t>(64, n - k * 64) - (uint32_t)__popcll(a.w[t][k]);   // padding bits are 0
+    z = wv_wave_incl_scan(z);
+    if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = z;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t s = 0;
+        for (uint32_t w = 0; w < DG / 64; w++) s += wsum[w];
+        cnt[(uint64_t)blockIdx.x * T + t] = s;
+    }
+}
+
+}  // namespace
+
 uint64_t wv_tree_key_blocks(uint64_t n) { return wv_cdiv(n ? n : 1, KB); }
+
+uint64_t wv_digit_blocks(uint64_t n) { return wv_cdiv(wv_cdiv(n ? n : 1, 64), DG); }
+
+hipError_t wv_digit_zero_counts(const wv_digit_words& a, uint64_t n, uint32_t T, uint32_t* cnt, hipStream_t s)
+{
+    if (!n || !T) return hipSuccess;
+    digit_zeros_k<<<dim3((uint32_t)wv_digit_blocks(n), T), DG, 0, s>>>(a, n, T, cnt);
+    return hipGetLastError();
+}
 
 void wv_split_table(const uint32_t* codes, const uint32_t* lens, uint32_t sigma, uint32_t h, uint32_t h1,
                     std::vector<uint32_t>& tab)
@@ -555,13 +590,14 @@ hipError_t wv_tree_long_keys(const void* S, uint64_t n, uint32_t sym_bytes, uint
     return hipGetLastError();
 }
 
-hipError_t wv_tree_digits(const wv_digit_levels& a, uint64_t n, uint32_t D, uint64_t* out, hipStream_t s)
+hipError_t wv_tree_digits(const wv_digit_levels& a, uint64_t n, uint32_t D, uint64_t* out, const uint64_t* zpre,
+                          const uint64_t* ztot, uint32_t t, uint32_t T, hipStream_t s)
 {
     if (!n) return hipSuccess;
     const uint32_t g = (uint32_t)wv_cdiv(wv_cdiv(wv_cdiv(n, 64), DW), 4);   // 4 waves per block
     const uint64_t nw = wv_cdiv(n * D, 64);
     if (D == 1) digits_k<1><<<g, 256, 0, s>>>(a, n, nw, out);
-    else if (D == 2) digits2_k<<<(uint32_t)wv_cdiv(wv_cdiv(n, 64), DG), DG, 0, s>>>(a, n, nw, out);
+    else if (D == 2) digits2_k<<<(uint32_t)wv_digit_blocks(n), DG, 0, s>>>(a, n, nw, out, zpre, ztot, t, T);
     else if (D == 4) digits_k<4><<<g, 256, 0, s>>>(a, n, nw, out);
     else return hipErrorInvalidValue;
     return hipGetLastError();
