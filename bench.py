@@ -306,25 +306,34 @@ def tree_kernel_bytes(name, info, sym_bytes, kind):
     D = int(info.arity_log2) if kind == 4 else 1
     key_w = 4 if kind == 3 else sym_bytes
     tree_bits = sum(int(info.level_n[l]) * D for l in range(info.nlevels))
+    width = lambda bits: 1 if bits <= 8 else (2 if bits <= 16 else 4)
+    # the matrices built: (symbols, key bits, key width, pass width); a shaped
+    # tree split at h1 bits has one over the top h1 code bits of every symbol
+    # (16-bit keys) and one over the whole codes of the long-code symbols
+    h1, nlong = int(info.split_bits), int(info.split_long)
+    if h1:
+        passes_b = (K + 7) // 8
+        mats = [(n, h1, 2, int(info.tau))] + ([(nlong, K, 4, (K + passes_b - 1) // passes_b)] if nlong else [])
+    else:
+        mats = [(n, K, key_w, int(info.tau))]
     if name == "wm_pass":
-        width = lambda bits: 1 if bits <= 8 else (2 if bits <= 16 else 4)
-        total, in_w = 0, key_w
-        for l0 in range(0, K, info.tau):
-            t = min(info.tau, K - l0)
-            rem = K - l0 - t
-            out_w = width(rem) if rem else 0
-            total += n * in_w + t * ((n + 63) // 64) * 8 + n * out_w
-            in_w = out_w
+        total = 0
+        for m, L, in_w, tau in mats:
+            for l0 in range(0, L, tau):
+                t = min(tau, L - l0)
+                rem = L - l0 - t
+                out_w = width(rem) if rem else 0
+                total += m * in_w + t * ((m + 63) // 64) * 8 + m * out_w
+                in_w = out_w
         return total
     if name == "wm_hist":
-        return sum(n * (key_w if l0 == 0 else (1 if K - l0 <= 8 else (2 if K - l0 <= 16 else 4)))
-                   for l0 in range(0, K, info.tau))
+        return sum(m * (w if l0 == 0 else width(L - l0)) for m, L, w, tau in mats for l0 in range(0, L, tau))
     if name == "tree_perm":          # read the matrix runs, write the tree levels
         return 2 * tree_bits // 8
     if name == "tree_digits":        # read D matrix levels, write one digit level, per digit level
         return info.nlevels * 2 * (n * D // 8)
-    if name == "tree_keys":          # read S, write the padded codes
-        return n * (sym_bytes + 4)
+    if name == "tree_keys":          # read S, write the padded codes (split: read S twice, write 16-bit keys)
+        return n * (2 * sym_bytes + 2) + nlong * 4 if h1 else n * (sym_bytes + 4)
     return None
 
 

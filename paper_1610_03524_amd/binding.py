@@ -37,7 +37,8 @@ class wt_tuning(ctypes.Structure):
 class wt_plan_info(ctypes.Structure):
     _fields_ = [("kind", c_u32), ("nlevels", c_u32), ("key_bits", c_u32), ("arity_log2", c_u32),
                 ("n", c_u64), ("sigma", c_u32), ("tau", c_u32), ("out_bytes", c_u64),
-                ("workspace_bytes", c_u64), ("level_n", c_u64 * 32)]
+                ("workspace_bytes", c_u64), ("level_n", c_u64 * 32), ("split_bits", c_u32),
+                ("reserved0", c_u32), ("split_long", c_u64)]
 
 
 class wt_seq_desc(ctypes.Structure):

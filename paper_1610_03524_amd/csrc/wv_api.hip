@@ -836,6 +836,8 @@ int wt_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt_s
     info->out_bytes = p.lay.image_bytes;
     info->workspace_bytes = p.ws_bytes;
     for (uint32_t l = 0; l < p.nlevels; l++) info->level_n[l] = p.lay.lv[l].n;
+    info->split_bits = p.h1;
+    info->split_long = p.nlong;
     return WT_OK;
 }
 
