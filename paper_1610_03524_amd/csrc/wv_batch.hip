@@ -34,10 +34,11 @@ struct SpanDesc {
     uint64_t n, bits_off, rank_off, sel0_off, sel1_off, nsel;
     uint32_t* cnt;          // ones per directory chunk
     uint64_t* pre;          // exclusive prefix of cnt
-    uint32_t level, chunk0; // level index, first global directory chunk
+    uint32_t level, chunk0; // level index, first directory workgroup of the span
 };
 
 constexpr uint32_t SDW = 512;   // words per directory chunk
+constexpr uint32_t SDG = 8;     // directory chunks per workgroup (one descriptor search each)
 
 // global item -> owner, over an exclusive prefix array of `count` owners
 __device__ inline uint32_t owner_of(const uint32_t* first, uint32_t count, uint32_t item)
@@ -161,23 +162,32 @@ b_pass_k(const SeqRound* __restrict__ seqs, const uint32_t* __restrict__ chunk0,
 __global__ void __launch_bounds__(256)
 b_dir_count_k(const SpanDesc* __restrict__ spans, const uint32_t* __restrict__ chunk0, uint32_t nspan)
 {
-    __shared__ uint32_t part[4];
+    __shared__ uint32_t part[SDG][4];
     const uint32_t s = owner_of(chunk0, nspan, blockIdx.x);
     const SpanDesc& d = spans[s];
-    const uint32_t c = blockIdx.x - d.chunk0;
-    const uint64_t nw = wv_cdiv(d.n, 64);
+    const uint64_t nw = wv_cdiv(d.n, 64), nch = wv_cdiv(nw, SDW);
+    const uint64_t c0 = (uint64_t)(blockIdx.x - d.chunk0) * SDG;
     const uint64_t* words = (const uint64_t*)(d.image + d.bits_off);
-    const uint64_t w0 = (uint64_t)c * SDW + 2 * threadIdx.x;
-    uint32_t o = 0;
-    if (w0 < nw) o += __popcll(words[w0]);
-    if (w0 + 1 < nw) o += __popcll(words[w0 + 1]);
-    o = wv_wave_incl_scan(o);   // lane 63 holds the wave's sum
-    if ((threadIdx.x & 63) == 63) part[threadIdx.x >> 6] = o;
+    // the SDG chunks' words in flight together (index clamped, masked after)
+    uint64_t x[SDG][2];
+#pragma unroll
+    for (uint32_t g = 0; g < SDG; g++) {
+        const uint64_t w0 = (c0 + g) * SDW + 2 * threadIdx.x;
+        x[g][0] = words[min(w0, nw - 1)];
+        x[g][1] = words[min(w0 + 1, nw - 1)];
+    }
+#pragma unroll
+    for (uint32_t g = 0; g < SDG; g++) {
+        const uint64_t w0 = (c0 + g) * SDW + 2 * threadIdx.x;
+        uint32_t o = (w0 < nw ? (uint32_t)__popcll(x[g][0]) : 0u) + (w0 + 1 < nw ? (uint32_t)__popcll(x[g][1]) : 0u);
+        o = wv_wave_incl_scan(o);   // lane 63 holds the wave's sum
+        if ((threadIdx.x & 63) == 63) part[g][threadIdx.x >> 6] = o;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) d.cnt[c] = part[0] + part[1] + part[2] + part[3];
+    if (threadIdx.x < SDG && c0 + threadIdx.x < nch)
+        d.cnt[c0 + threadIdx.x] = part[threadIdx.x][0] + part[threadIdx.x][1] + part[threadIdx.x][2] + part[threadIdx.x][3];
 }
 
-// one workgroup per span: prefix of its chunk counts, sentinels, descriptor
 __global__ void __launch_bounds__(256)
 b_dir_scan_k(const SpanDesc* __restrict__ spans)
 {
@@ -227,50 +237,53 @@ b_dir_write_k(const SpanDesc* __restrict__ spans, const uint32_t* __restrict__ c
     __shared__ uint64_t zex[SDW];
     const uint32_t s = owner_of(chunk0, nspan, blockIdx.x);
     const SpanDesc& d = spans[s];
-    const uint32_t c = blockIdx.x - d.chunk0;
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint64_t n = d.n, nw = wv_cdiv(n, 64), ns = wv_cdiv(n, WV_SB_BITS);
+    const uint64_t n = d.n, nw = wv_cdiv(n, 64), ns = wv_cdiv(n, WV_SB_BITS), nch = wv_cdiv(nw, SDW);
     const uint64_t* words = (const uint64_t*)(d.image + d.bits_off);
     uint64_t* dir = (uint64_t*)(d.image + d.rank_off);
     uint64_t* sel0 = (uint64_t*)(d.image + d.sel0_off);
     uint64_t* sel1 = (uint64_t*)(d.image + d.sel1_off);
-    const uint64_t cw = (uint64_t)c * SDW, w0 = cw + 2 * threadIdx.x;
-    const uint64_t x0 = w0 < nw ? words[w0] : 0ull, x1 = w0 + 1 < nw ? words[w0 + 1] : 0ull;
-    const uint32_t o0 = __popcll(x0), o1 = __popcll(x1);
-    uint32_t tot;
-    const uint32_t ex = wave_excl_scan(o0 + o1, &tot);
-    if (lane == 0) wpart[wave] = tot;
-    __syncthreads();
-    uint32_t off = 0;
-    for (uint32_t k = 0; k < wave; k++) off += wpart[k];
-    const uint64_t ob0 = d.pre[c] + off + ex, ob1 = ob0 + o0;
-    const uint64_t z0 = min(64 * w0, n) - ob0, z1 = min(64 * (w0 + 1), n) - ob1;
-    zex[2 * threadIdx.x] = z0;
-    zex[2 * threadIdx.x + 1] = z1;
-    const uint64_t xs[2] = {x0, x1}, obs[2] = {ob0, ob1}, zbs[2] = {z0, z1};
-    const uint32_t os[2] = {o0, o1};
-    for (int qd = 0; qd < 2; qd++) {
-        const uint64_t w = w0 + qd;
-        if (w >= nw) break;
-        const uint64_t t1 = wv_cdiv(obs[qd], WV_SEL_STRIDE) * WV_SEL_STRIDE;
-        if (t1 < obs[qd] + os[qd]) sel1[t1 / WV_SEL_STRIDE] = 64 * w + wv_select_in_word(xs[qd], (uint32_t)(t1 - obs[qd]));
-        const uint64_t valid = min((uint64_t)64, n - 64 * w);
-        const uint64_t vm = valid >= 64 ? ~0ull : ((1ull << valid) - 1ull);
-        const uint32_t zc = (uint32_t)valid - os[qd];
-        const uint64_t t0 = wv_cdiv(zbs[qd], WV_SEL_STRIDE) * WV_SEL_STRIDE;
-        if (t0 < zbs[qd] + zc)
-            sel0[t0 / WV_SEL_STRIDE] = 64 * w + wv_select_in_word(~xs[qd] & vm, (uint32_t)(t0 - zbs[qd]));
-    }
-    __syncthreads();
-    if (threadIdx.x < SDW / 8) {
-        const uint64_t k = cw / 8 + threadIdx.x;
-        if (k < ns) {
-            const uint64_t zb = zex[8 * threadIdx.x];
-            uint64_t blk = 0;
-            for (uint32_t qd = 1; qd < 8; qd++) blk |= (zex[8 * threadIdx.x + qd] - zb) << (9 * (qd - 1));
-            dir[2 * k] = zb;
-            dir[2 * k + 1] = blk;
+    const uint64_t c0 = (uint64_t)(blockIdx.x - d.chunk0) * SDG;
+    for (uint64_t c = c0; c < min(nch, c0 + SDG); c++) {   // uniform
+        const uint64_t cw = c * SDW, w0 = cw + 2 * threadIdx.x;
+        const uint64_t x0 = w0 < nw ? words[w0] : 0ull, x1 = w0 + 1 < nw ? words[w0 + 1] : 0ull;
+        const uint32_t o0 = __popcll(x0), o1 = __popcll(x1);
+        uint32_t tot;
+        const uint32_t ex = wave_excl_scan(o0 + o1, &tot);
+        if (lane == 0) wpart[wave] = tot;
+        __syncthreads();
+        uint32_t off = 0;
+        for (uint32_t k = 0; k < wave; k++) off += wpart[k];
+        const uint64_t ob0 = d.pre[c] + off + ex, ob1 = ob0 + o0;
+        const uint64_t z0 = min(64 * w0, n) - ob0, z1 = min(64 * (w0 + 1), n) - ob1;
+        zex[2 * threadIdx.x] = z0;
+        zex[2 * threadIdx.x + 1] = z1;
+        const uint64_t xs[2] = {x0, x1}, obs[2] = {ob0, ob1}, zbs[2] = {z0, z1};
+        const uint32_t os[2] = {o0, o1};
+        for (int qd = 0; qd < 2; qd++) {
+            const uint64_t w = w0 + qd;
+            if (w >= nw) break;
+            const uint64_t t1 = wv_cdiv(obs[qd], WV_SEL_STRIDE) * WV_SEL_STRIDE;
+            if (t1 < obs[qd] + os[qd]) sel1[t1 / WV_SEL_STRIDE] = 64 * w + wv_select_in_word(xs[qd], (uint32_t)(t1 - obs[qd]));
+            const uint64_t valid = min((uint64_t)64, n - 64 * w);
+            const uint64_t vm = valid >= 64 ? ~0ull : ((1ull << valid) - 1ull);
+            const uint32_t zc = (uint32_t)valid - os[qd];
+            const uint64_t t0 = wv_cdiv(zbs[qd], WV_SEL_STRIDE) * WV_SEL_STRIDE;
+            if (t0 < zbs[qd] + zc)
+                sel0[t0 / WV_SEL_STRIDE] = 64 * w + wv_select_in_word(~xs[qd] & vm, (uint32_t)(t0 - zbs[qd]));
         }
+        __syncthreads();
+        if (threadIdx.x < SDW / 8) {
+            const uint64_t k = cw / 8 + threadIdx.x;
+            if (k < ns) {
+                const uint64_t zb = zex[8 * threadIdx.x];
+                uint64_t blk = 0;
+                for (uint32_t qd = 1; qd < 8; qd++) blk |= (zex[8 * threadIdx.x + qd] - zb) << (9 * (qd - 1));
+                dir[2 * k] = zb;
+                dir[2 * k + 1] = blk;
+            }
+        }
+        __syncthreads();   // zex and wpart are rewritten by the next chunk
     }
 }
 
@@ -548,7 +561,7 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
     }
     // last phase: the directories of every level of every sequence
     const uint32_t dphase = bp.nphases - 1;
-    uint32_t nspan = 0, dchunks = 0;
+    uint32_t nspan = 0, dchunks = 0;   // dchunks: directory workgroups (SDG chunks each)
     {
         for (uint32_t i = 0; i < count; i++) nspan += bp.seq[i].L;
         SpanDesc* sd = (SpanDesc*)host_area(dphase);
@@ -571,7 +584,7 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
                 d.level = l;
                 d.chunk0 = dchunks;
                 first[k] = dchunks;
-                dchunks += (uint32_t)dch;
+                dchunks += (uint32_t)wv_cdiv(dch, SDG);
             }
         }
     }
