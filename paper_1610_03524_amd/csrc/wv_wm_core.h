@@ -101,6 +101,7 @@ struct PassShared {
     KT_ buf[T];
     uint64_t lb[TW + 1];
     uint32_t zw[TW + 1];
+    alignas(16) uint32_t zt[TW];   // zw of word e * NWAVE + w at zt[w * E + e]
     uint32_t cnt[MAXG], ls[MAXG], g[MAXG], fw[MAXG];
     uint64_t carry[2][255];
     uint32_t sp[129];
@@ -170,6 +171,10 @@ __device__ void wm_pass_chunk(const PassArgs& a, uint32_t b, PassShared<KT_>& S)
                     uint32_t tot;
                     const uint32_t ex = wave_excl_scan(v[k], &tot);
                     zw[64 * k + lane] = run + ex;
+                    {
+                        const uint32_t w = 64 * k + lane;
+                        S.zt[(w % NWAVE) * E + w / NWAVE] = run + ex;
+                    }
                     run += tot;
                 }
                 if (lane == 0) zw[TW] = run;
@@ -193,10 +198,20 @@ __device__ void wm_pass_chunk(const PassArgs& a, uint32_t b, PassShared<KT_>& S)
             // phase 3: partition, child runs, emit words
             const uint32_t ztot = zw[TW];
             // (padding keys are ones on every sub-level and stay in place)
-            for (int e = 0; e < E; e++) {
-                const uint32_t p = tid + NT * e;
-                const uint32_t zb = zw[e * NWAVE + wave] + rz[e];
-                buf[bit[e] ? ztot + (p - zb) : zb] = (KT_)xs[e];
+            {
+                const uint4* zt4 = (const uint4*)(S.zt + wave * E);
+#pragma unroll
+                for (int q = 0; q < E / 4; q++) {
+                    const uint4 z4 = zt4[q];
+                    const uint32_t zz[4] = {z4.x, z4.y, z4.z, z4.w};
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        const int e = 4 * q + u;
+                        const uint32_t p = tid + NT * e;
+                        const uint32_t zb = zz[u] + rz[e];
+                        buf[bit[e] ? ztot + (p - zb) : zb] = (KT_)xs[e];
+                    }
+                }
             }
             // runs of sub-level j+1 split the runs of j by bit j; a child's
             // elements keep their order, zeros of the tile first
