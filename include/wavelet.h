@@ -111,7 +111,10 @@ typedef struct wt_tuning {
     uint32_t tau;      /* key bits per partition pass, 1..8 (0 = automatic) */
     uint32_t tile;     /* reserved, ignored: a pass tile is 8192 keys       */
     uint32_t blocks;   /* chunks (workgroups) per pass (0 = automatic: one
-                          per tile, at most 768 = 3 per CU)                 */
+                          per tile, at most the resident pass workgroups:
+                          1024 = 4 per CU when the first pass's keys fit 16
+                          bits, else 768 = 3 per CU; a batch sizes its
+                          chunks by the whole batch)                        */
     uint32_t flags;    /* WT_FLAG_*                                         */
 } wt_tuning;
 
