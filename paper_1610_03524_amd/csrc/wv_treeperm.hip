@@ -15,13 +15,20 @@
 // codeword (the code is prefix-free), so the groups of leaves are separate
 // runs, which the tree level simply leaves out.
 //
+// A deep shaped tree whose long codes are rare is gathered from two matrices:
+// the levels above the split from a matrix over the top bits of every
+// codeword, the deeper ones from a matrix over the long-code symbols alone
+// (only they reach those levels, each group of them in input order).
+//
 // A multiary tree (Sec. 4.3) with D-bit digits keeps the binary levels bD:
 // its level b holds the same runs as matrix level bD, with each symbol's
 // digit (its bits on matrix levels bD .. bD+D-1) in place of one bit.
 //
 // The host derives, from the symbol counts, every kept run's bit offset on
-// the matrix level and on the tree level; one thread per output word gathers
-// its bits from the runs that cover it.
+// the matrix level and on the tree level, and the first run of every 256-word
+// tile of the tree levels; one thread per output word gathers its bits from
+// the runs that cover it, and for a multiary tree the same launch counts the
+// digits of every counter range (Sec. 5's rank counters).
 #include <algorithm>
 #include <vector>
 
