@@ -149,7 +149,8 @@ int wt_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes,
  * set, the tree shaped by those codewords (Sec. 4.3, Thm. 4.4).
  * S: dev, n symbols of sym_bytes each.  out: dev, out_bytes >= plan
  * out_bytes, receives the image.  ws: dev scratch of ws_bytes >= plan
- * workspace_bytes.  Synchronizes `stream` once: the symbol counts are read
+ * workspace_bytes.  S, out and ws must be 16-byte aligned (device
+ * allocations are), else WT_EINVAL before any device work.  Synchronizes `stream` once: the symbol counts are read
  * back to place the tree's runs (shaped: they must equal shape->counts,
  * else WT_EINVAL; a symbol >= sigma returns WT_ERANGE at that point). */
 int wt_build(const void* S, uint64_t n, uint32_t sigma, uint32_t sym_bytes,
@@ -198,7 +199,8 @@ int wt_symbol_counts(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sig
  * exceeds 32. */
 int wt_huffman_codes(const uint64_t* counts, uint32_t sigma, uint64_t* codes, uint32_t* code_len);
 
-/* One sequence of a batched build.  S, out: dev pointers.  tau: key bits
+/* One sequence of a batched build.  S, out: dev pointers, 16-byte aligned
+ * (as is the batch workspace; else WT_EINVAL).  tau: key bits
  * per pass for this sequence (0 = the batch tuning, else automatic); the
  * image does not depend on it. */
 typedef struct wt_seq_desc {

@@ -491,6 +491,8 @@ wv_lw_args lw_args(const Plan& p, const void* S, void* out, void* ws)
 int check_buffers(const Plan& p, const void* S, void* out, size_t out_bytes, void* ws, size_t ws_bytes)
 {
     if ((!S && p.n) || !out || (!ws && p.ws_bytes)) return WT_EINVAL;
+    // the kernels read S and the workspace in 16-byte pieces
+    if (((uintptr_t)S | (uintptr_t)out | (uintptr_t)ws) & 15u) return WT_EINVAL;
     if (out_bytes < p.lay.image_bytes || ws_bytes < p.ws_bytes) return WT_ENOSPC;
     return WT_OK;
 }

@@ -395,6 +395,7 @@ int make_batch_plan(const wt_seq_desc* seqs, uint32_t count, const wt_tuning* tu
         rc = wt_plan(WT_KIND_WM, d.n, d.sigma, d.sym_bytes, nullptr, &t1, &info);
         if (rc) return rc;
         if (!d.S && d.n) return WT_EINVAL;
+        if (((uintptr_t)d.S | (uintptr_t)d.out) & 15u) return WT_EINVAL;   // read and written in 16-byte pieces
         if (!d.out || d.out_bytes < info.out_bytes) return WT_ENOSPC;
         SeqPlan& s = bp.seq[i];
         s.L = wp.L; s.tau = wp.tau; s.K = wp.K; s.C = wp.C; s.n = d.n; s.sym_bytes = d.sym_bytes; s.sigma = d.sigma;
@@ -483,6 +484,7 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
     if (rc) return rc;
     if (!count) return WT_OK;
     if (!ws_ || ws_bytes < bp.ws_bytes) return WT_ENOSPC;
+    if ((uintptr_t)ws_ & 15u) return WT_EINVAL;
     uint8_t* ws = (uint8_t*)ws_;
     uint32_t* queue = (uint32_t*)(ws + bp.off_queue);
     const bool prof = tune && (tune->flags & WT_FLAG_PROFILE);

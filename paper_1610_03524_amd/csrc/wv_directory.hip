@@ -459,8 +459,11 @@ span_count_k(const uint8_t* __restrict__ image, SpanLevels a, uint32_t* __restri
     const uint64_t* words = (const uint64_t*)(image + a.bits_off[l]);
     const uint64_t w0 = (uint64_t)c * SD_W + 2 * threadIdx.x;
     uint32_t o = 0;
-    if (w0 < nw) o += __popcll(words[w0]);
-    if (w0 + 1 < nw) o += __popcll(words[w0 + 1]);
+    if (nw) {   // uniform: a level of a shaped tree can be empty
+        // both loads in flight (index clamped, masked after)
+        const uint64_t x0 = words[min(w0, nw - 1)], x1 = words[min(w0 + 1, nw - 1)];
+        o = (w0 < nw ? (uint32_t)__popcll(x0) : 0u) + (w0 + 1 < nw ? (uint32_t)__popcll(x1) : 0u);
+    }
     o = wv_wave_incl_scan(o);   // lane 63 holds the wave's sum
     if ((threadIdx.x & 63) == 63) part[threadIdx.x >> 6] = o;
     __syncthreads();

@@ -116,3 +116,18 @@ def test_plan_counts_shaped_nodes():
                                   codes=codes, lens=lens)
         assert img_bytes == oimg.size
         assert int(oimg[64:72].view(np.uint64)[0]) == len(prefixes)
+
+
+def test_misaligned_buffers_are_rejected_before_device_work():
+    """S, out and ws must be 16-byte aligned: addresses that are not are
+    refused on the host, before any device call (none is made here)"""
+    L = B.lib()
+    big = 1 << 30
+    for S, out, ws in ((0x10001, 0x20000, 0x30000), (0x10000, 0x20008, 0x30000), (0x10000, 0x20000, 0x30004)):
+        for fn in (L.wm_build, L.wt_build):
+            assert fn(S, 1000, 100, 1, None, None, out, big, ws, big, None) == B.WT_EINVAL
+    d = B.wt_seq_desc()
+    d.S, d.n, d.sigma, d.sym_bytes, d.out, d.out_bytes = 0x10002, 1000, 100, 1, 0x20000, big
+    with pytest.raises(B.WaveletError) as e:
+        B.batch_plan(B.KIND_WM, [d])
+    assert e.value.code == B.WT_EINVAL
