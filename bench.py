@@ -287,9 +287,45 @@ def main():
         "per_build": per_build,
         "kernel_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in sorted(prof.items())},
     }
+    line["queries"] = query_rates(out, S, n, sigma, info.nlevels, stream)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_wm(S, sigma)
     print(json.dumps(line), flush=True)
+
+
+def query_rates(img, S, n, sigma, levels, stream, m=1 << 22, reps=5):
+    """Batched access / rank / select on the built matrix, outside the timed
+    build step: m queries per kind from the same input (uniform positions,
+    symbols drawn from S, select ranks uniform in [1, occurrences]).  Each
+    query reads, per level, a bit word and a directory entry: two 64-byte
+    lines of random access, the algorithmic bytes of the line rate below
+    (select reads more: it searches the level's select samples)."""
+    import torch
+    from paper_1610_03524_amd import binding as B
+    dev = S.device
+    g = torch.Generator(device=dev)
+    g.manual_seed(10)
+    pos = torch.randint(0, n, (m,), device=dev, generator=g, dtype=torch.int64)
+    c = S[torch.randint(0, n, (m,), device=dev, generator=g, dtype=torch.int64)].to(torch.int32)
+    counts = torch.bincount(S, minlength=sigma)
+    k = (torch.rand(m, device=dev, generator=g) * counts[c.long()]).long() + 1
+    got = B.access(img, pos[:1 << 16], stream).to(torch.int64)
+    assert torch.equal(got, S[pos[:1 << 16]].to(torch.int64)), "access differs from S"
+    kinds = {"access": lambda: B.access(img, pos, stream), "rank": lambda: B.rank(img, c, pos, stream),
+             "select": lambda: B.select(img, c, k, stream)}
+    out = {"queries_per_batch": m, "levels": levels}
+    for name, fn in kinds.items():
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        lines = m * levels * 2 * 64
+        out[name] = {"queries_per_s": round(m / dt, 1), "ms_per_batch": round(dt * 1e3, 3),
+                     "line_GBps": round(lines / dt / 1e9, 1), "frac": round(lines / dt / 1e9 / HBM_PEAK_GBPS, 4)}
+    return out
 
 
 def info_passes(info):
