@@ -518,7 +518,7 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
     WV_CHECK(hipEventCreateWithFlags(&have_counts, hipEventDisableTiming));
     struct EventGuard {
         hipEvent_t e;
-        ~EventGuard() { hipEventDestroy(e); }
+        ~EventGuard() { (void)hipEventDestroy(e); }
     } guard{have_counts};
     WV_CHECK(hipEventRecord(have_counts, s));
 

@@ -111,12 +111,9 @@ b_offsets_k(const SeqRound* __restrict__ seqs, const uint32_t* __restrict__ chun
 
 // persistent pass: workgroups take chunks from the queue until it is empty
 template <typename KT_>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8)))
-b_pass_k(const SeqRound* __restrict__ seqs, const uint32_t* __restrict__ chunk0, uint32_t nseq,
-         uint32_t nchunks, uint32_t* __restrict__ queue)
+__device__ void b_pass_body(const SeqRound* __restrict__ seqs, const uint32_t* __restrict__ chunk0, uint32_t nseq,
+                            uint32_t nchunks, uint32_t* __restrict__ queue, PassShared<KT_>& sh, uint32_t& item_s)
 {
-    __shared__ PassShared<KT_> sh;
-    __shared__ uint32_t item_s;
     for (;;) {
         if (threadIdx.x == 0) item_s = atomicAdd(queue, 1u);
         __syncthreads();
@@ -156,6 +153,26 @@ b_pass_k(const SeqRound* __restrict__ seqs, const uint32_t* __restrict__ chunk0,
         __syncthreads();
     }
 }
+
+// 16-bit keys in LDS: four workgroups per CU; 32-bit keys: three (LDS-bound)
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8)))
+b_pass16_k(const SeqRound* __restrict__ seqs, const uint32_t* __restrict__ chunk0, uint32_t nseq,
+           uint32_t nchunks, uint32_t* __restrict__ queue)
+{
+    __shared__ PassShared<uint16_t> sh;
+    __shared__ uint32_t item_s;
+    b_pass_body<uint16_t>(seqs, chunk0, nseq, nchunks, queue, sh, item_s);
+}
+
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6)))
+b_pass32_k(const SeqRound* __restrict__ seqs, const uint32_t* __restrict__ chunk0, uint32_t nseq,
+           uint32_t nchunks, uint32_t* __restrict__ queue)
+{
+    __shared__ PassShared<uint32_t> sh;
+    __shared__ uint32_t item_s;
+    b_pass_body<uint32_t>(seqs, chunk0, nseq, nchunks, queue, sh, item_s);
+}
+
 
 // ---- directories of every (sequence, level) ------------------------------------
 
@@ -612,8 +629,8 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
         WV_TIMED(prof, s, "b_offsets", (b_offsets_k<<<g.chunks, HT, 0, s>>>(dq, dfirst, g.m)));
         const uint32_t workers = std::min<uint32_t>(g.chunks, g.wide ? KRES32 : KRES16);
         WV_TIMED(prof, s, "b_pass",
-                 (g.wide ? (void)(b_pass_k<uint32_t><<<workers, NT, 0, s>>>(dq, dfirst, g.m, g.chunks, queue))
-                         : (void)(b_pass_k<uint16_t><<<workers, NT, 0, s>>>(dq, dfirst, g.m, g.chunks, queue))));
+                 (g.wide ? (void)(b_pass32_k<<<workers, NT, 0, s>>>(dq, dfirst, g.m, g.chunks, queue))
+                         : (void)(b_pass16_k<<<workers, NT, 0, s>>>(dq, dfirst, g.m, g.chunks, queue))));
         WV_CHECK(hipGetLastError());
     }
     {

@@ -60,7 +60,7 @@ void wv_prof_after(int slot, hipStream_t s, const char* name)
     if (slot < 0) return;
     std::lock_guard<std::mutex> lk(g_mu);
     g_pending[slot].name = name;
-    hipEventRecord(g_pending[slot].b, s);
+    (void)hipEventRecord(g_pending[slot].b, s);   // a failed record shows as a missing entry
 }
 
 extern "C" int wt_profile_read(wt_profile_entry* out, uint32_t cap, uint32_t* count)

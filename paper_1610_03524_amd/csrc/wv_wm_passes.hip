@@ -36,12 +36,22 @@
 
 namespace {
 
-template <typename IT, typename OT, typename KT_>
+// 16-bit keys in LDS: four workgroups per CU (8 waves per SIMD, 64 VGPRs);
+// 32-bit keys: LDS holds three workgroups per CU, so 6 waves per SIMD
+template <typename IT, typename OT>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8)))
-wm_pass_k(PassArgs a)
+wm_pass16_k(PassArgs a)
 {
-    __shared__ PassShared<KT_> sh;
-    wm_pass_chunk<IT, OT, KT_>(a, blockIdx.x, sh);
+    __shared__ PassShared<uint16_t> sh;
+    wm_pass_chunk<IT, OT, uint16_t>(a, blockIdx.x, sh);
+}
+
+template <typename IT, typename OT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6)))
+wm_pass32_k(PassArgs a)
+{
+    __shared__ PassShared<uint32_t> sh;
+    wm_pass_chunk<IT, OT, uint32_t>(a, blockIdx.x, sh);
 }
 
 template <typename IT>
@@ -73,8 +83,8 @@ Geometry geometry(uint64_t n, uint32_t blocks, uint32_t L)
 template <typename IT, typename OT>
 void launch_pass(const PassArgs& a, hipStream_t s)
 {
-    if (a.R <= 16) wm_pass_k<IT, OT, uint16_t><<<a.K, NT, 0, s>>>(a);
-    else wm_pass_k<IT, OT, uint32_t><<<a.K, NT, 0, s>>>(a);
+    if (a.R <= 16) wm_pass16_k<IT, OT><<<a.K, NT, 0, s>>>(a);
+    else wm_pass32_k<IT, OT><<<a.K, NT, 0, s>>>(a);
 }
 
 template <typename IT>
