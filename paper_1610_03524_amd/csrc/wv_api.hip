@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -497,6 +498,54 @@ int check_buffers(const Plan& p, const void* S, void* out, size_t out_bytes, voi
     return WT_OK;
 }
 
+// Pinned host buffers for the symbol counts a tree build reads back: a copy
+// into pageable memory holds the host until it completes, so the matrix
+// passes would be launched only after the validation.  Buffers are reused
+// until the process ends; one that a failed build may still be copying into
+// is not returned.
+class PinnedBuf {
+public:
+    explicit PinnedBuf(size_t bytes)
+    {
+        std::lock_guard<std::mutex> lk(mu());
+        auto& fr = pool();
+        for (size_t i = 0; i < fr.size(); i++)
+            if (fr[i].second >= bytes) {
+                p_ = fr[i].first;
+                n_ = fr[i].second;
+                fr.erase(fr.begin() + (long)i);
+                return;
+            }
+        n_ = std::max<size_t>(bytes, 4096);
+        if (hipHostMalloc(&p_, n_, hipHostMallocDefault) != hipSuccess) p_ = nullptr;
+    }
+    ~PinnedBuf()
+    {
+        if (!p_ || !idle_) return;
+        std::lock_guard<std::mutex> lk(mu());
+        pool().push_back({p_, n_});
+    }
+    void* get() const { return p_; }
+    void idle() { idle_ = true; }   // no copy into it is pending any more
+    PinnedBuf(const PinnedBuf&) = delete;
+    PinnedBuf& operator=(const PinnedBuf&) = delete;
+
+private:
+    static std::mutex& mu()
+    {
+        static std::mutex m;
+        return m;
+    }
+    static std::vector<std::pair<void*, size_t>>& pool()
+    {
+        static std::vector<std::pair<void*, size_t>> v;
+        return v;
+    }
+    void* p_ = nullptr;
+    size_t n_ = 0;
+    bool idle_ = false;
+};
+
 // Balanced or shaped binary tree gathered from matrix levels: validate S and
 // count its symbols, derive every level's runs on the host, build the matrix
 // levels of the (padded) keys, move the runs, then the directories.
@@ -510,10 +559,13 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
     // 1. symbol counts and status to the host (waited for in step 3)
     uint64_t* dcounts = at<uint64_t>(ws, p.ws_counts);
     WV_TIMED(prof, s, "validate", WV_CHECK(wv_validate(S, n, p.sym_bytes, sigma, img, dcounts, s)));
-    std::vector<uint64_t> counts(sigma);
-    uint32_t status = 0;
-    WV_CHECK(hipMemcpyAsync(counts.data(), dcounts, (uint64_t)sigma * 8, hipMemcpyDeviceToHost, s));
-    WV_CHECK(hipMemcpyAsync(&status, img + 36, 4, hipMemcpyDeviceToHost, s));
+    // [status word][counts], pinned when possible (else a pageable array)
+    PinnedBuf pin(((uint64_t)sigma + 1) * 8);
+    std::vector<uint64_t> unpinned(pin.get() ? 0 : (uint64_t)sigma + 1);
+    uint64_t* hc = pin.get() ? (uint64_t*)pin.get() : unpinned.data();
+    hc[0] = 0;
+    WV_CHECK(hipMemcpyAsync(hc + 1, dcounts, (uint64_t)sigma * 8, hipMemcpyDeviceToHost, s));
+    WV_CHECK(hipMemcpyAsync(hc, img + 36, 4, hipMemcpyDeviceToHost, s));
     hipEvent_t have_counts = nullptr;
     WV_CHECK(hipEventCreateWithFlags(&have_counts, hipEventDisableTiming));
     struct EventGuard {
@@ -612,6 +664,9 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
     // 3. the counts: on an error, let the launched work finish before
     // returning (it writes into the caller's buffers)
     WV_CHECK(hipEventSynchronize(have_counts));
+    const uint32_t status = (uint32_t)hc[0];
+    const std::vector<uint64_t> counts(hc + 1, hc + 1 + sigma);
+    pin.idle();
     int rc = status ? WT_ERANGE : WT_OK;
     if (!rc && shaped)
         for (uint32_t x = 0; x < sigma && !rc; x++)
