@@ -498,54 +498,6 @@ int check_buffers(const Plan& p, const void* S, void* out, size_t out_bytes, voi
     return WT_OK;
 }
 
-// Pinned host buffers for the symbol counts a tree build reads back: a copy
-// into pageable memory holds the host until it completes, so the matrix
-// passes would be launched only after the validation.  Buffers are reused
-// until the process ends; one that a failed build may still be copying into
-// is not returned.
-class PinnedBuf {
-public:
-    explicit PinnedBuf(size_t bytes)
-    {
-        std::lock_guard<std::mutex> lk(mu());
-        auto& fr = pool();
-        for (size_t i = 0; i < fr.size(); i++)
-            if (fr[i].second >= bytes) {
-                p_ = fr[i].first;
-                n_ = fr[i].second;
-                fr.erase(fr.begin() + (long)i);
-                return;
-            }
-        n_ = std::max<size_t>(bytes, 4096);
-        if (hipHostMalloc(&p_, n_, hipHostMallocDefault) != hipSuccess) p_ = nullptr;
-    }
-    ~PinnedBuf()
-    {
-        if (!p_ || !idle_) return;
-        std::lock_guard<std::mutex> lk(mu());
-        pool().push_back({p_, n_});
-    }
-    void* get() const { return p_; }
-    void idle() { idle_ = true; }   // no copy into it is pending any more
-    PinnedBuf(const PinnedBuf&) = delete;
-    PinnedBuf& operator=(const PinnedBuf&) = delete;
-
-private:
-    static std::mutex& mu()
-    {
-        static std::mutex m;
-        return m;
-    }
-    static std::vector<std::pair<void*, size_t>>& pool()
-    {
-        static std::vector<std::pair<void*, size_t>> v;
-        return v;
-    }
-    void* p_ = nullptr;
-    size_t n_ = 0;
-    bool idle_ = false;
-};
-
 // Balanced or shaped binary tree gathered from matrix levels: validate S and
 // count its symbols, derive every level's runs on the host, build the matrix
 // levels of the (padded) keys, move the runs, then the directories.

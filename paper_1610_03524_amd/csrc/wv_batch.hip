@@ -12,6 +12,7 @@
 // The host writes the per-round descriptor arrays into the workspace and the
 // call returns when the batch is complete.
 #include <algorithm>
+#include <cstring>
 #include <numeric>
 #include <vector>
 
@@ -509,8 +510,12 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
     // every phase's descriptors are known on the host up front: they are
     // written into one host buffer, copied with one call, then every kernel
     // is launched back to back
-    std::vector<uint8_t> hd(bp.desc_total, 0);
-    auto host_area = [&](uint32_t ph) { return hd.data() + bp.phase_off[ph]; };
+    // every descriptor of the build, copied with one call from pinned memory
+    PinnedBuf pin(bp.desc_total);
+    std::vector<uint8_t> unpinned(pin.get() ? 0 : bp.desc_total);
+    uint8_t* hd = pin.get() ? (uint8_t*)pin.get() : unpinned.data();
+    std::memset(hd, 0, bp.desc_total);
+    auto host_area = [&](uint32_t ph) { return hd + bp.phase_off[ph]; };
     auto dev_area = [&](uint32_t ph) { return ws + bp.off_desc + bp.phase_off[ph]; };
 
     // phase 0: headers of every image
@@ -609,7 +614,7 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
     }
 
     WV_TIMED(prof, s, "b_desc_copy",
-             WV_CHECK(hipMemcpyAsync(ws + bp.off_desc, hd.data(), hd.size(), hipMemcpyHostToDevice, s)));
+             WV_CHECK(hipMemcpyAsync(ws + bp.off_desc, hd, bp.desc_total, hipMemcpyHostToDevice, s)));
     WV_TIMED(prof, s, "b_header",
              (b_header_k<<<count, 256, 0, s>>>((uint8_t* const*)dev_area(0),
                                                (const wv_layout_in*)(dev_area(0) + wv_round256(count * sizeof(uint8_t*))))));
@@ -644,6 +649,7 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
     }
     // the host descriptor buffer is read by the copy above: finish first
     WV_CHECK(hipStreamSynchronize(s));
+    pin.idle();
     return WT_OK;
 }
 

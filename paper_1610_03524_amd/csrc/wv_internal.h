@@ -2,6 +2,11 @@
 // libwavelet (not part of the C-ABI).
 #pragma once
 
+#include <algorithm>
+#include <mutex>
+#include <utility>
+#include <vector>
+
 #include "wv_common.h"
 
 // ---- optional per-kernel timing (wv_profile.hip) ----------------------------
@@ -65,6 +70,55 @@ hipError_t wv_multiary_counters(uint8_t* image, const wv_level* lv, uint32_t M, 
 // and the sub-range counters are written (by the gather of the tree levels)
 hipError_t wv_multiary_ranges(uint8_t* image, const wv_level* lv, uint32_t M, uint32_t D,
                               const wv_mdir_scratch& sc, hipStream_t s);
+
+// ---- pinned host staging -------------------------------------------------------
+// Pinned host buffers for copies a build issues between launches (the symbol
+// counts a tree build reads back, the descriptors of a batch): a copy from or
+// to pageable memory holds the host until it completes.  Buffers are reused
+// until the process ends; one that a failed build may still be copying is
+// not returned.
+class PinnedBuf {
+public:
+    explicit PinnedBuf(size_t bytes)
+    {
+        std::lock_guard<std::mutex> lk(mu());
+        auto& fr = pool();
+        for (size_t i = 0; i < fr.size(); i++)
+            if (fr[i].second >= bytes) {
+                p_ = fr[i].first;
+                n_ = fr[i].second;
+                fr.erase(fr.begin() + (long)i);
+                return;
+            }
+        n_ = std::max<size_t>(bytes, 4096);
+        if (hipHostMalloc(&p_, n_, hipHostMallocDefault) != hipSuccess) p_ = nullptr;
+    }
+    ~PinnedBuf()
+    {
+        if (!p_ || !idle_) return;
+        std::lock_guard<std::mutex> lk(mu());
+        pool().push_back({p_, n_});
+    }
+    void* get() const { return p_; }
+    void idle() { idle_ = true; }   // no copy into it is pending any more
+    PinnedBuf(const PinnedBuf&) = delete;
+    PinnedBuf& operator=(const PinnedBuf&) = delete;
+
+private:
+    static std::mutex& mu()
+    {
+        static std::mutex m;
+        return m;
+    }
+    static std::vector<std::pair<void*, size_t>>& pool()
+    {
+        static std::vector<std::pair<void*, size_t>> v;
+        return v;
+    }
+    void* p_ = nullptr;
+    size_t n_ = 0;
+    bool idle_ = false;
+};
 
 // ---- header (wv_directory.hip) ---------------------------------------------
 // header, level descriptors (zeros/ones left 0) and zeroed gaps between arrays
