@@ -241,8 +241,16 @@ def profile_read(cap: int = 64) -> dict:
     return {arr[i].name.decode(): (arr[i].launches, arr[i].ms) for i in range(min(cap, cnt.value))}
 
 
+def desc_array(descs):
+    """descs as the C array the batch calls take (a ctypes array is used as is,
+    so a caller that builds several batches of the same sequences marshals once)"""
+    if isinstance(descs, ctypes.Array):
+        return descs
+    return (wt_seq_desc * len(descs))(*descs)
+
+
 def batch_plan(kind: int, descs, tune=None) -> int:
-    arr = (wt_seq_desc * len(descs))(*descs)
+    arr = desc_array(descs)
     ws = ctypes.c_uint64(0)
     _check(lib().wt_batch_plan(kind, arr, len(descs), ctypes.byref(tune) if tune else None, ctypes.byref(ws)),
            "wt_batch_plan")
@@ -250,6 +258,6 @@ def batch_plan(kind: int, descs, tune=None) -> int:
 
 
 def batch_build(kind: int, descs, ws, tune=None, stream=None) -> int:
-    arr = (wt_seq_desc * len(descs))(*descs)
+    arr = desc_array(descs)
     return lib().wt_batch_build(kind, arr, len(descs), _ptr(ws), ws.numel(),
                                 ctypes.byref(tune) if tune else None, _stream(stream))

@@ -361,9 +361,25 @@ struct SeqPlan {
     uint32_t L, tau, passes, K, C, sym_bytes, sigma;
     uint64_t n;
     uint64_t off_H, off_tot, off_G0, off_pay[2], off_dcnt, off_dpre;
-    wv_layout_out lay;
-    wv_layout_in lin;
+    // image layout: every level of a matrix has n bits, so level l's arrays
+    // sit at level 0's offsets + l * lstride
+    uint64_t bits0, rank0, sel00, sel10, lstride, nsel, image_bytes;
+    wv_level lv(uint32_t l) const
+    {
+        const uint64_t d = (uint64_t)l * lstride;
+        return wv_level{n, bits0 + d, rank0 + d, sel00 + d, sel10 + d, nsel};
+    }
 };
+
+// the layout input of a matrix image of n symbols and L levels
+inline wv_layout_in matrix_layout_in(uint64_t n, uint32_t sigma, uint32_t L)
+{
+    wv_layout_in in{};
+    in.kind = WT_KIND_WM; in.arity_log2 = 1; in.nlevels = L; in.key_bits = L;
+    in.sigma = sigma; in.n = n;
+    for (uint32_t l = 0; l < L; l++) in.level_n[l] = n;
+    return in;
+}
 
 struct BatchPlan {
     std::vector<SeqPlan> seq;
@@ -406,16 +422,24 @@ int make_batch_plan(const wt_seq_desc* seqs, uint32_t count, const wt_tuning* tu
         if (d.tau) t1.tau = d.tau;
         t1.flags &= ~WT_FLAG_LEVELWISE;
         if (!t1.blocks) t1.blocks = (uint32_t)std::max<uint64_t>(1, wv_cdiv(wv_cdiv(d.n ? d.n : 1, T), tiles_per_chunk));
+        // the argument checks of wt_plan for a matrix
+        if (d.sigma == 0 || (d.sym_bytes != 1 && d.sym_bytes != 2 && d.sym_bytes != 4)) return WT_EINVAL;
+        if (d.n >= (1ull << 32)) return WT_EUNSUP;
         wv_wm_plan wp;
         int rc = wv_wm_make_plan(d.n, d.sigma, d.sym_bytes, &t1, wp);
         if (rc) return rc;
-        wt_plan_info info;
-        rc = wt_plan(WT_KIND_WM, d.n, d.sigma, d.sym_bytes, nullptr, &t1, &info);
-        if (rc) return rc;
         if (!d.S && d.n) return WT_EINVAL;
         if (((uintptr_t)d.S | (uintptr_t)d.out) & 15u) return WT_EINVAL;   // read and written in 16-byte pieces
-        if (!d.out || d.out_bytes < info.out_bytes) return WT_ENOSPC;
         SeqPlan& s = bp.seq[i];
+        {
+            wv_layout_out lay;
+            wv_layout(matrix_layout_in(d.n, d.sigma, wp.L), lay);
+            s.bits0 = lay.lv[0].bits_off; s.rank0 = lay.lv[0].rank_off;
+            s.sel00 = lay.lv[0].sel0_off; s.sel10 = lay.lv[0].sel1_off; s.nsel = lay.lv[0].nsel;
+            s.lstride = wp.L > 1 ? lay.lv[1].bits_off - lay.lv[0].bits_off : 0;
+            s.image_bytes = lay.image_bytes;
+        }
+        if (!d.out || d.out_bytes < s.image_bytes) return WT_ENOSPC;
         s.L = wp.L; s.tau = wp.tau; s.K = wp.K; s.C = wp.C; s.n = d.n; s.sym_bytes = d.sym_bytes; s.sigma = d.sigma;
         s.passes = d.n ? (s.L + s.tau - 1) / s.tau : 0;
         bp.max_passes = std::max(bp.max_passes, s.passes);
@@ -437,11 +461,6 @@ int make_batch_plan(const wt_seq_desc* seqs, uint32_t count, const wt_tuning* tu
         s.off_dpre = bump(std::max<uint64_t>(dch, 1) * s.L * 8);
         total_spans += s.L;
         total_dch += dch * s.L;
-        s.lin = wv_layout_in{};
-        s.lin.kind = WT_KIND_WM; s.lin.arity_log2 = 1; s.lin.nlevels = s.L; s.lin.key_bits = s.L;
-        s.lin.sigma = s.sigma; s.lin.n = s.n;
-        for (uint32_t l = 0; l < s.L; l++) s.lin.level_n[l] = s.n;
-        wv_layout(s.lin, s.lay);
     }
     bp.order.resize(count);
     std::iota(bp.order.begin(), bp.order.end(), 0u);
@@ -524,7 +543,7 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
         wv_layout_in* lins = (wv_layout_in*)(host_area(0) + wv_round256(count * sizeof(uint8_t*)));
         for (uint32_t i = 0; i < count; i++) {
             imgs[i] = (uint8_t*)seqs[i].out;
-            lins[i] = bp.seq[i].lin;
+            lins[i] = matrix_layout_in(bp.seq[i].n, bp.seq[i].sigma, bp.seq[i].L);
         }
     }
     // rounds of passes: two groups per round, keys up to 16 bits (16-bit LDS
@@ -561,7 +580,7 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
                     e.pa.in = cur_in[i];
                     e.pa.pay_out = rem ? (void*)(ws + sp.off_pay[r & 1]) : nullptr;
                     for (uint32_t j = 0; j < tau; j++)
-                        e.pa.words[j] = (uint64_t*)((uint8_t*)seqs[i].out + sp.lay.lv[l0 + j].bits_off);
+                        e.pa.words[j] = (uint64_t*)((uint8_t*)seqs[i].out + sp.lv(l0 + j).bits_off);
                     e.pa.G0 = (const uint32_t*)(ws + sp.off_G0);
                     e.pa.n = (uint32_t)sp.n; e.pa.C = sp.C; e.pa.K = sp.K; e.pa.R = R; e.pa.tau = tau;
                     e.pa.keymask = r == 0 ? (sp.L >= 32 ? ~0u : ((1u << sp.L) - 1u)) : ~0u;
@@ -598,11 +617,12 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
                 SpanDesc& d = sd[k];
                 d.image = (uint8_t*)seqs[i].out;
                 d.n = sp.n;
-                d.bits_off = sp.lay.lv[l].bits_off;
-                d.rank_off = sp.lay.lv[l].rank_off;
-                d.sel0_off = sp.lay.lv[l].sel0_off;
-                d.sel1_off = sp.lay.lv[l].sel1_off;
-                d.nsel = sp.lay.lv[l].nsel;
+                const wv_level lvl = sp.lv(l);
+                d.bits_off = lvl.bits_off;
+                d.rank_off = lvl.rank_off;
+                d.sel0_off = lvl.sel0_off;
+                d.sel1_off = lvl.sel1_off;
+                d.nsel = lvl.nsel;
                 d.cnt = (uint32_t*)(ws + sp.off_dcnt) + l * std::max<uint64_t>(dch, 1);
                 d.pre = (uint64_t*)(ws + sp.off_dpre) + l * std::max<uint64_t>(dch, 1);
                 d.level = l;
