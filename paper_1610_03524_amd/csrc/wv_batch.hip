@@ -1,16 +1,18 @@
 // wv_batch.hip -- wavelet matrices of many sequences with a few persistent
 // launches.
 //
-// Every sequence is built exactly as wm_build builds it alone (same passes,
-// same chunking rule, same image), but each step runs for all sequences in
-// one launch: the chunk histograms of every sequence, their prefix over the
+// Every sequence is built with the passes of wm_build and into the image
+// wm_build writes (chunks are sized by the whole batch), but each step runs
+// for all sequences in one launch: the chunk histograms of every sequence, their prefix over the
 // chunks, every chunk's run offsets, then a persistent pass
 // kernel whose workgroups pull chunks of any sequence from a device-side
 // queue (largest sequences first), and finally the directories of every
 // level of every sequence.  Sequences with more levels take more rounds of
 // passes; a round only holds the sequences that still have levels to build.
-// The host writes the per-round descriptor arrays into the workspace and the
-// call returns when the batch is complete.
+// The host writes the descriptors of every phase into a pinned buffer; a
+// phase is copied and launched as soon as it is written, so the host fills
+// later phases while earlier ones run.  The call returns when the batch is
+// complete.
 #include <algorithm>
 #include <cstring>
 #include <numeric>
@@ -466,7 +468,7 @@ int make_batch_plan(const wt_seq_desc* seqs, uint32_t count, const wt_tuning* tu
     std::iota(bp.order.begin(), bp.order.end(), 0u);
     std::stable_sort(bp.order.begin(), bp.order.end(), [&](uint32_t a, uint32_t b) { return bp.seq[a].n > bp.seq[b].n; });
     // one descriptor area per phase, each sized for its members, so no phase
-    // overwrites descriptors still being read and one copy moves them all
+    // overwrites descriptors still being read
     bp.nphases = 2 + 2 * bp.max_passes;
     bp.phase_off.assign(bp.nphases + 1, 0);
     bp.phase_members.assign(bp.nphases, 0);
@@ -526,18 +528,23 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
     uint32_t* queue = (uint32_t*)(ws + bp.off_queue);
     const bool prof = tune && (tune->flags & WT_FLAG_PROFILE);
 
-    // every phase's descriptors are known on the host up front: they are
-    // written into one host buffer, copied with one call, then every kernel
-    // is launched back to back
-    // every descriptor of the build, copied with one call from pinned memory
+    // every descriptor of the build, in one pinned host buffer with an area
+    // per phase
     PinnedBuf pin(bp.desc_total);
     std::vector<uint8_t> unpinned(pin.get() ? 0 : bp.desc_total);
     uint8_t* hd = pin.get() ? (uint8_t*)pin.get() : unpinned.data();
-    std::memset(hd, 0, bp.desc_total);
     auto host_area = [&](uint32_t ph) { return hd + bp.phase_off[ph]; };
     auto dev_area = [&](uint32_t ph) { return ws + bp.off_desc + bp.phase_off[ph]; };
+    auto area_bytes = [&](uint32_t ph) { return bp.phase_off[ph + 1] - bp.phase_off[ph]; };
+    // a phase's descriptors go to the device as soon as they are written and
+    // its kernels are launched at once, so later phases are filled on the host
+    // while earlier ones run (each phase reads only its own area)
+    auto copy_area = [&](uint32_t ph) {
+        return hipMemcpyAsync(dev_area(ph), host_area(ph), area_bytes(ph), hipMemcpyHostToDevice, s);
+    };
 
     // phase 0: headers of every image
+    std::memset(host_area(0), 0, area_bytes(0));
     {
         uint8_t** imgs = (uint8_t**)host_area(0);
         wv_layout_in* lins = (wv_layout_in*)(host_area(0) + wv_round256(count * sizeof(uint8_t*)));
@@ -546,10 +553,33 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
             lins[i] = matrix_layout_in(bp.seq[i].n, bp.seq[i].sigma, bp.seq[i].L);
         }
     }
+    WV_TIMED(prof, s, "b_desc_copy", WV_CHECK(copy_area(0)));
+    WV_TIMED(prof, s, "b_header",
+             (b_header_k<<<count, 256, 0, s>>>((uint8_t* const*)dev_area(0),
+                                               (const wv_layout_in*)(dev_area(0) + wv_round256(count * sizeof(uint8_t*))))));
+    WV_CHECK(hipGetLastError());
     // rounds of passes: two groups per round, keys up to 16 bits (16-bit LDS
     // keys) and wider ones
     struct Group { uint32_t phase, m, chunks, cols; bool wide; };
-    std::vector<Group> groups;
+    auto launch_group = [&](const Group& g) {
+        uint8_t* desc = dev_area(g.phase);
+        const SeqRound* dq = (const SeqRound*)desc;
+        const uint32_t* dfirst = (const uint32_t*)(desc + wv_round256((uint64_t)g.m * sizeof(SeqRound)));
+        const uint32_t* dcfirst = dfirst + wv_round256((uint64_t)g.m * 4) / 4;
+        const uint64_t hz = (bp.zero_hi - bp.zero_lo) / 4;
+        const uint32_t zb = (uint32_t)std::min<uint64_t>(wv_cdiv(hz, 256), 4096);
+        WV_TIMED(prof, s, "b_zero",
+                 ((b_zero_k<<<zb, 256, 0, s>>>((uint32_t*)(ws + bp.zero_lo), hz)),
+                  (b_zero_k<<<1, 64, 0, s>>>(queue, 1))));
+        WV_TIMED(prof, s, "b_hist", (b_hist_k<<<g.chunks * HSPLIT, HT, 0, s>>>(dq, dfirst, g.m)));
+        WV_TIMED(prof, s, "b_scan", (b_scan_k<<<wv_cdiv(g.cols, HT / 64), HT, 0, s>>>(dq, dcfirst, g.m, g.cols)));
+        WV_TIMED(prof, s, "b_offsets", (b_offsets_k<<<g.chunks, HT, 0, s>>>(dq, dfirst, g.m)));
+        const uint32_t workers = std::min<uint32_t>(g.chunks, g.wide ? KRES32 : KRES16);
+        WV_TIMED(prof, s, "b_pass",
+                 (g.wide ? (void)(b_pass32_k<<<workers, NT, 0, s>>>(dq, dfirst, g.m, g.chunks, queue))
+                         : (void)(b_pass16_k<<<workers, NT, 0, s>>>(dq, dfirst, g.m, g.chunks, queue))));
+        return hipGetLastError();
+    };
     {
         std::vector<const void*> cur_in(count);
         std::vector<uint32_t> cur_bytes(count);
@@ -567,7 +597,11 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
                 }
                 if (members.empty()) continue;
                 const uint32_t m = (uint32_t)members.size();
-                if (m != bp.phase_members[phase]) return WT_EINVAL;   // the plan and the build disagree
+                if (m != bp.phase_members[phase]) {   // the plan and the build disagree
+                    (void)hipStreamSynchronize(s);     // earlier phases may be running
+                    return WT_EINVAL;
+                }
+                std::memset(host_area(phase), 0, area_bytes(phase));
                 SeqRound* q = (SeqRound*)host_area(phase);
                 uint32_t* first = (uint32_t*)(host_area(phase) + wv_round256((uint64_t)m * sizeof(SeqRound)));
                 uint32_t* cfirst = first + wv_round256((uint64_t)m * 4) / 4;
@@ -598,7 +632,9 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
                     cols += 1u << tau;
                     if (e.pa.pay_out) { cur_in[i] = e.pa.pay_out; cur_bytes[i] = e.out_bytes; }
                 }
-                groups.push_back(Group{phase, m, chunks, cols, wide == 1});
+                const Group g{phase, m, chunks, cols, wide == 1};
+                WV_TIMED(prof, s, "b_desc_copy", WV_CHECK(copy_area(phase)));
+                WV_CHECK(launch_group(g));
             }
         }
     }
@@ -607,6 +643,7 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
     uint32_t nspan = 0, dchunks = 0;   // dchunks: directory workgroups (SDG chunks each)
     {
         for (uint32_t i = 0; i < count; i++) nspan += bp.seq[i].L;
+        std::memset(host_area(dphase), 0, area_bytes(dphase));
         SpanDesc* sd = (SpanDesc*)host_area(dphase);
         uint32_t* first = (uint32_t*)(host_area(dphase) + wv_round256((uint64_t)nspan * sizeof(SpanDesc)));
         uint32_t k = 0;
@@ -633,31 +670,7 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
         }
     }
 
-    WV_TIMED(prof, s, "b_desc_copy",
-             WV_CHECK(hipMemcpyAsync(ws + bp.off_desc, hd, bp.desc_total, hipMemcpyHostToDevice, s)));
-    WV_TIMED(prof, s, "b_header",
-             (b_header_k<<<count, 256, 0, s>>>((uint8_t* const*)dev_area(0),
-                                               (const wv_layout_in*)(dev_area(0) + wv_round256(count * sizeof(uint8_t*))))));
-    WV_CHECK(hipGetLastError());
-    for (const Group& g : groups) {
-        uint8_t* desc = dev_area(g.phase);
-        const SeqRound* dq = (const SeqRound*)desc;
-        const uint32_t* dfirst = (const uint32_t*)(desc + wv_round256((uint64_t)g.m * sizeof(SeqRound)));
-        const uint32_t* dcfirst = dfirst + wv_round256((uint64_t)g.m * 4) / 4;
-        const uint64_t hz = (bp.zero_hi - bp.zero_lo) / 4;
-        const uint32_t zb = (uint32_t)std::min<uint64_t>(wv_cdiv(hz, 256), 4096);
-        WV_TIMED(prof, s, "b_zero",
-                 ((b_zero_k<<<zb, 256, 0, s>>>((uint32_t*)(ws + bp.zero_lo), hz)),
-                  (b_zero_k<<<1, 64, 0, s>>>(queue, 1))));
-        WV_TIMED(prof, s, "b_hist", (b_hist_k<<<g.chunks * HSPLIT, HT, 0, s>>>(dq, dfirst, g.m)));
-        WV_TIMED(prof, s, "b_scan", (b_scan_k<<<wv_cdiv(g.cols, HT / 64), HT, 0, s>>>(dq, dcfirst, g.m, g.cols)));
-        WV_TIMED(prof, s, "b_offsets", (b_offsets_k<<<g.chunks, HT, 0, s>>>(dq, dfirst, g.m)));
-        const uint32_t workers = std::min<uint32_t>(g.chunks, g.wide ? KRES32 : KRES16);
-        WV_TIMED(prof, s, "b_pass",
-                 (g.wide ? (void)(b_pass32_k<<<workers, NT, 0, s>>>(dq, dfirst, g.m, g.chunks, queue))
-                         : (void)(b_pass16_k<<<workers, NT, 0, s>>>(dq, dfirst, g.m, g.chunks, queue))));
-        WV_CHECK(hipGetLastError());
-    }
+    WV_TIMED(prof, s, "b_desc_copy", WV_CHECK(copy_area(dphase)));
     {
         uint8_t* desc = dev_area(dphase);
         const SpanDesc* dsd = (const SpanDesc*)desc;
