@@ -475,60 +475,65 @@ span_count_k(const uint8_t* __restrict__ image, SpanLevels a, uint32_t* __restri
 }
 
 __global__ void __launch_bounds__(SD_T)
-span_write_k(uint8_t* __restrict__ image, SpanLevels a, const uint64_t* __restrict__ pre)
+span_write_k(uint8_t* __restrict__ image, SpanLevels a, const uint64_t* __restrict__ pre, uint32_t nchunks)
 {
     __shared__ uint32_t wpart[SD_T / 64];
     __shared__ uint64_t zex[SD_W];   // zeros in [0, min(64w, n)) per word of the chunk
-    const uint32_t c = blockIdx.x, l = blockIdx.y;
+    const uint32_t l = blockIdx.y;
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint64_t n = a.n[l], nw = wv_cdiv(n, 64), ns = wv_cdiv(n, WV_SB_BITS);
     const uint64_t* words = (const uint64_t*)(image + a.bits_off[l]);
     uint64_t* dir = (uint64_t*)(image + a.rank_off[l]);
     uint64_t* sel0 = (uint64_t*)(image + a.sel0_off[l]);
     uint64_t* sel1 = (uint64_t*)(image + a.sel1_off[l]);
-    const uint64_t cw = (uint64_t)c * SD_W;
-    const uint64_t w0 = cw + 2 * threadIdx.x;
-    const uint64_t x0 = w0 < nw ? words[w0] : 0ull, x1 = w0 + 1 < nw ? words[w0 + 1] : 0ull;
-    const uint32_t o0 = __popcll(x0), o1 = __popcll(x1);
-    // exclusive prefix of ones over the words of the chunk
-    const uint32_t inc = wv_wave_incl_scan(o0 + o1);
-    if (lane == 63) wpart[wave] = inc;
-    __syncthreads();
-    uint32_t off = 0;
-    for (uint32_t k = 0; k < wave; k++) off += wpart[k];
-    const uint64_t ob0 = pre[(uint64_t)c * a.nl + l] + off + inc - (o0 + o1);   // ones before word w0
-    const uint64_t ob1 = ob0 + o0;
-    const uint64_t z0 = min(64 * w0, n) - ob0, z1 = min(64 * (w0 + 1), n) - ob1;
-    zex[2 * threadIdx.x] = z0;
-    zex[2 * threadIdx.x + 1] = z1;
-    // sampled select: the one / zero of ordinal 4096k inside one of my words
-    const uint64_t xs[2] = {x0, x1};
-    const uint32_t os[2] = {o0, o1};
-    const uint64_t obs[2] = {ob0, ob1}, zbs[2] = {z0, z1};
-    for (int q = 0; q < 2; q++) {
-        const uint64_t w = w0 + q;
-        if (w >= nw) break;
-        const uint64_t t1 = wv_cdiv(obs[q], WV_SEL_STRIDE) * WV_SEL_STRIDE;
-        if (t1 < obs[q] + os[q])
-            sel1[t1 / WV_SEL_STRIDE] = 64 * w + wv_select_in_word(xs[q], (uint32_t)(t1 - obs[q]));
-        const uint64_t valid = min((uint64_t)64, n - 64 * w);
-        const uint64_t vm = valid >= 64 ? ~0ull : ((1ull << valid) - 1ull);
-        const uint32_t zc = (uint32_t)valid - os[q];
-        const uint64_t t0 = wv_cdiv(zbs[q], WV_SEL_STRIDE) * WV_SEL_STRIDE;
-        if (t0 < zbs[q] + zc)
-            sel0[t0 / WV_SEL_STRIDE] = 64 * w + wv_select_in_word(~xs[q] & vm, (uint32_t)(t0 - zbs[q]));
-    }
-    __syncthreads();
-    // one thread per superblock of the chunk
-    if (threadIdx.x < SD_W / 8) {
-        const uint64_t k = cw / 8 + threadIdx.x;
-        if (k < ns) {
-            const uint64_t zb = zex[8 * threadIdx.x];
-            uint64_t blk = 0;
-            for (uint32_t q = 1; q < 8; q++) blk |= (zex[8 * threadIdx.x + q] - zb) << (9 * (q - 1));
-            dir[2 * k] = zb;
-            dir[2 * k + 1] = blk;
+    for (uint32_t gi = 0; gi < 4; gi++) {   // four chunks per workgroup
+        const uint32_t c = blockIdx.x * 4 + gi;
+        if (c >= nchunks) break;   // uniform
+        const uint64_t cw = (uint64_t)c * SD_W;
+        const uint64_t w0 = cw + 2 * threadIdx.x;
+        const uint64_t x0 = w0 < nw ? words[w0] : 0ull, x1 = w0 + 1 < nw ? words[w0 + 1] : 0ull;
+        const uint32_t o0 = __popcll(x0), o1 = __popcll(x1);
+        // exclusive prefix of ones over the words of the chunk
+        const uint32_t inc = wv_wave_incl_scan(o0 + o1);
+        if (lane == 63) wpart[wave] = inc;
+        __syncthreads();
+        uint32_t off = 0;
+        for (uint32_t k = 0; k < wave; k++) off += wpart[k];
+        const uint64_t ob0 = pre[(uint64_t)c * a.nl + l] + off + inc - (o0 + o1);   // ones before word w0
+        const uint64_t ob1 = ob0 + o0;
+        const uint64_t z0 = min(64 * w0, n) - ob0, z1 = min(64 * (w0 + 1), n) - ob1;
+        zex[2 * threadIdx.x] = z0;
+        zex[2 * threadIdx.x + 1] = z1;
+        // sampled select: the one / zero of ordinal 4096k inside one of my words
+        const uint64_t xs[2] = {x0, x1};
+        const uint32_t os[2] = {o0, o1};
+        const uint64_t obs[2] = {ob0, ob1}, zbs[2] = {z0, z1};
+        for (int q = 0; q < 2; q++) {
+            const uint64_t w = w0 + q;
+            if (w >= nw) break;
+            const uint64_t t1 = wv_cdiv(obs[q], WV_SEL_STRIDE) * WV_SEL_STRIDE;
+            if (t1 < obs[q] + os[q])
+                sel1[t1 / WV_SEL_STRIDE] = 64 * w + wv_select_in_word(xs[q], (uint32_t)(t1 - obs[q]));
+            const uint64_t valid = min((uint64_t)64, n - 64 * w);
+            const uint64_t vm = valid >= 64 ? ~0ull : ((1ull << valid) - 1ull);
+            const uint32_t zc = (uint32_t)valid - os[q];
+            const uint64_t t0 = wv_cdiv(zbs[q], WV_SEL_STRIDE) * WV_SEL_STRIDE;
+            if (t0 < zbs[q] + zc)
+                sel0[t0 / WV_SEL_STRIDE] = 64 * w + wv_select_in_word(~xs[q] & vm, (uint32_t)(t0 - zbs[q]));
         }
+        __syncthreads();
+        // one thread per superblock of the chunk
+        if (threadIdx.x < SD_W / 8) {
+            const uint64_t k = cw / 8 + threadIdx.x;
+            if (k < ns) {
+                const uint64_t zb = zex[8 * threadIdx.x];
+                uint64_t blk = 0;
+                for (uint32_t q = 1; q < 8; q++) blk |= (zex[8 * threadIdx.x + q] - zb) << (9 * (q - 1));
+                dir[2 * k] = zb;
+                dir[2 * k + 1] = blk;
+            }
+        }
+        __syncthreads();   // wpart and zex are rewritten by the next chunk
     }
 }
 
@@ -597,7 +602,7 @@ hipError_t wv_span_directory(uint8_t* image, const wv_layout_out& lay, uint32_t 
     WV_TIMED(prof, s, "dir_scan",
              e = wv_scan_u32(cnt, pre, sz.nchunks, nl, (uint64_t*)(scratch + sz.off_part), tot, s));
     if (e != hipSuccess) return e;
-    if (sz.nchunks) WV_TIMED(prof, s, "dir_write", (span_write_k<<<grid, SD_T, 0, s>>>(image, a, pre)));
+    if (sz.nchunks) WV_TIMED(prof, s, "dir_write", (span_write_k<<<dim3((uint32_t)wv_cdiv(sz.nchunks, 4), nl), SD_T, 0, s>>>(image, a, pre, (uint32_t)sz.nchunks)));
     WV_TIMED(prof, s, "dir_finish", (span_finish_k<<<nl, SD_T, 0, s>>>(image, a, tot)));
     return hipGetLastError();
 }
