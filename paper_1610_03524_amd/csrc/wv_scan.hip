@@ -2,7 +2,8 @@
 // of Sec. 2: returns (0, X0, X0+X1, ...) and the overall sum).
 //
 // Reduce-then-scan over tiles of 2048 items: per-tile sums, one block scans
-// the tile sums, then every tile rescans its items with its base.  Several
+// the tile sums, then every tile rescans its items with its base (one
+// workgroup per column does it all when a column fits one tile).  Several
 // independent columns can be scanned at once: item i of column c is
 // in[i * ncols + c].
 #include "wv_internal.h"
@@ -86,6 +87,30 @@ scan_down_k(const uint32_t* __restrict__ in, uint64_t count, uint32_t ncols,
     }
 }
 
+// the whole scan of one column in one workgroup, when it fits one tile
+__global__ void __launch_bounds__(SCAN_THREADS)
+scan_one_k(const uint32_t* __restrict__ in, uint64_t count, uint32_t ncols, uint64_t* __restrict__ out,
+           uint64_t* __restrict__ totals)
+{
+    const uint32_t col = blockIdx.x;
+    const uint64_t base = (uint64_t)threadIdx.x * SCAN_ITEMS;
+    uint32_t v[SCAN_ITEMS];
+    uint64_t s = 0;
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+        const uint64_t i = base + k;
+        v[k] = i < count ? in[i * ncols + col] : 0u;
+        s += v[k];
+    }
+    uint64_t tot;
+    uint64_t ex = block_excl_scan(s, &tot);
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+        const uint64_t i = base + k;
+        if (i < count) out[i * ncols + col] = ex;
+        ex += v[k];
+    }
+    if (threadIdx.x == 0) totals[col] = tot;
+}
+
 }  // namespace
 
 uint64_t wv_scan_partials(uint64_t count, uint32_t ncols)
@@ -98,6 +123,10 @@ hipError_t wv_scan_u32(const uint32_t* in, uint64_t* out, uint64_t count, uint32
                        uint64_t* partial, uint64_t* totals, hipStream_t s)
 {
     const uint64_t parts = wv_cdiv(count ? count : 1, SCAN_TILE);
+    if (parts == 1) {   // one tile per column: one launch
+        scan_one_k<<<ncols, SCAN_THREADS, 0, s>>>(in, count, ncols, out, totals);
+        return hipGetLastError();
+    }
     dim3 grid((uint32_t)parts, ncols);
     // count == 0 still runs one reduce block per column, which writes 0
     scan_reduce_k<<<grid, SCAN_THREADS, 0, s>>>(in, count, ncols, partial);
