@@ -1,0 +1,46 @@
+"""Seeded random builds: kind, size, alphabet, symbol width, pass width and
+chunk count drawn together, every image equal to the oracle's byte for byte
+(combinations the targeted tests do not enumerate, e.g. a split shaped tree
+under a forced pass width, or many chunks of a few tiles)."""
+import numpy as np
+import pytest
+
+from gpu_util import assert_same, gpu_image, oracle_image, shaped_codes
+from paper_1610_03524_amd import binding as B
+
+pytestmark = pytest.mark.gpu
+
+
+def draw(rng):
+    kind = int(rng.choice([B.KIND_WM, B.KIND_WT, B.KIND_SHAPED, B.KIND_MULTIARY]))
+    n = int(2 ** rng.uniform(0, 18.2)) if rng.random() > 0.05 else 0
+    sigma = max(1, int(2 ** rng.uniform(0, 20)))
+    need = 1 if sigma <= 256 else (2 if sigma <= 65536 else 4)
+    width = int(rng.choice([w for w in (1, 2, 4) if w >= need]))
+    dt = {1: np.uint8, 2: np.uint16, 4: np.uint32}[width]
+    if kind == B.KIND_SHAPED or rng.random() < 0.3:   # skewed symbols: deep shaped trees
+        S = np.minimum(rng.geometric(min(0.5, 8.0 / sigma + 1e-4), n) - 1, sigma - 1).astype(dt)
+    else:
+        S = rng.integers(0, sigma, n).astype(dt)
+    tau = int(rng.choice([0, 0, 1, 2, 3, 5, 7, 8]))
+    blocks = int(rng.choice([0, 0, 1, 2, 5, 33]))
+    D = int(rng.integers(1, 5)) if kind == B.KIND_MULTIARY else 0
+    return kind, S, sigma, tau, blocks, D
+
+
+@pytest.mark.parametrize("seed", range(48))
+def test_random_build_equals_oracle(seed):
+    rng = np.random.default_rng(5000 + seed)
+    kind, S, sigma, tau, blocks, D = draw(rng)
+    tune = B.make_tuning(tau=tau, blocks=blocks)
+    what = f"seed={seed} kind={kind} n={S.size} sigma={sigma} {S.dtype} tau={tau} blocks={blocks} D={D}"
+    if kind == B.KIND_SHAPED:
+        if S.size == 0:
+            pytest.skip("a shaped tree needs at least one coded symbol")
+        (gc, gl), (oc, ol) = shaped_codes(S, sigma)
+        g = gpu_image(kind, S, sigma, codes=gc, lens=gl, tune=tune)
+        o = oracle_image(kind, S, sigma, codes=oc, lens=ol)
+    else:
+        g = gpu_image(kind, S, sigma, D, tune=tune)
+        o = oracle_image(kind, S, sigma, D)
+    assert_same(g, o, what)
