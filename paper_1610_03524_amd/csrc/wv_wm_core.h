@@ -143,19 +143,16 @@ __device__ void wm_pass_chunk(const PassArgs& a, uint32_t b, PassShared<KT_>& S)
         __syncthreads();
 
         for (uint32_t j = 0; j < tau; j++) {
-            // phase 1: bit j of every element, in the order of sub-level j;
-            // each element also keeps the zeros before it in its word
+            // phase 1: bit j of every element, in the order of sub-level j
+            // (one ballot word per 64 elements)
             uint32_t xs[E];
-            uint32_t rz[E];
             uint64_t balls[E];
             bool bit[E];
             const uint32_t sh = R - 1 - j;
             for (int e = 0; e < E; e++) xs[e] = (uint32_t)buf[tid + NT * e];
             for (int e = 0; e < E; e++) {
                 bit[e] = (xs[e] >> sh) & 1u;
-                const uint64_t ball = __ballot(bit[e]);
-                balls[e] = ball;
-                rz[e] = __builtin_amdgcn_mbcnt_hi((uint32_t)(~ball >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)~ball, 0u));
+                balls[e] = __ballot(bit[e]);
             }
             if (lane == 0)
                 for (int e = 0; e < E; e++) lb[e * NWAVE + wave] = balls[e];
@@ -197,8 +194,11 @@ __device__ void wm_pass_chunk(const PassArgs& a, uint32_t b, PassShared<KT_>& S)
             __syncthreads();
             // phase 3: partition, child runs, emit words
             const uint32_t ztot = zw[TW];
-            // (padding keys are ones on every sub-level and stay in place)
-            {
+            // every element moves to its place in the order of sub-level
+            // j+1 (padding keys are ones on every sub-level and stay in
+            // place); the last sub-level's order is needed only for the
+            // payload of the next pass
+            if (j + 1 < tau || a.pay_out) {
                 const uint4* zt4 = (const uint4*)(S.zt + wave * E);
 #pragma unroll
                 for (int q = 0; q < E / 4; q++) {
@@ -208,7 +208,12 @@ __device__ void wm_pass_chunk(const PassArgs& a, uint32_t b, PassShared<KT_>& S)
                     for (int u = 0; u < 4; u++) {
                         const int e = 4 * q + u;
                         const uint32_t p = tid + NT * e;
-                        const uint32_t zb = zz[u] + rz[e];
+                        // zeros before the element in the tile: its word's
+                        // prefix plus the zeros of lower lanes (mbcnt adds
+                        // its count to the prefix)
+                        const uint64_t nb = ~balls[e];
+                        const uint32_t zb = __builtin_amdgcn_mbcnt_hi((uint32_t)(nb >> 32),
+                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)nb, zz[u]));
                         buf[bit[e] ? ztot + (p - zb) : zb] = (KT_)xs[e];
                     }
                 }
