@@ -150,9 +150,13 @@ int wt_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes,
  * S: dev, n symbols of sym_bytes each.  out: dev, out_bytes >= plan
  * out_bytes, receives the image.  ws: dev scratch of ws_bytes >= plan
  * workspace_bytes.  S, out and ws must be 16-byte aligned (device
- * allocations are), else WT_EINVAL before any device work.  Synchronizes `stream` once: the symbol counts are read
- * back to place the tree's runs (shaped: they must equal shape->counts,
- * else WT_EINVAL; a symbol >= sigma returns WT_ERANGE at that point). */
+ * allocations are), else WT_EINVAL before any device work.  Waits once
+ * during the build for the symbol counts, read back to place the tree's
+ * runs (shaped: they must equal shape->counts, else WT_EINVAL; a symbol >=
+ * sigma returns WT_ERANGE at that point), and returns after synchronizing
+ * `stream`, the build complete.  A shaped tree split into two matrices
+ * builds the smaller one on a second stream the library keeps per device,
+ * forked from and joined back into `stream` with events. */
 int wt_build(const void* S, uint64_t n, uint32_t sigma, uint32_t sym_bytes,
              const wt_shape* shape, const wt_tuning* tune,
              void* out, size_t out_bytes, void* ws, size_t ws_bytes, void* stream);
@@ -165,7 +169,8 @@ int wm_build(const void* S, uint64_t n, uint32_t sigma, uint32_t sym_bytes,
 
 /* Build a balanced multiary wavelet tree of degree 2^shape->arity_log2
  * (Sec. 4.3, Thm. 4.5) with per-digit rank counters (Sec. 5.2).  Same
- * arguments as wt_build.  Synchronizes `stream` once (symbol counts). */
+ * arguments as wt_build; waits for the symbol counts the same way and
+ * returns after synchronizing `stream`. */
 int multiary_build(const void* S, uint64_t n, uint32_t sigma, uint32_t sym_bytes,
                    const wt_shape* shape, const wt_tuning* tune,
                    void* out, size_t out_bytes, void* ws, size_t ws_bytes, void* stream);

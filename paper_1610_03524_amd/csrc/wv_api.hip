@@ -262,10 +262,11 @@ int make_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt
         p.tile_bound = wv_tree_tile_bound(n, 1, p.key_bits);
         p.ws_segs = bump(off, seg_bytes(p.seg_bound, p.tile_bound));
         p.ws_counts = bump(off, (uint64_t)sigma * 8);
+        // codes, lengths and key table next to each other: one upload
         p.ws_codes = bump(off, (uint64_t)sigma * 4);
         p.ws_lens = bump(off, (uint64_t)sigma * 4);
-        p.ws_sdir = bump(off, wv_span_dir_sizes(n, p.key_bits).bytes);
         p.ws_ktab = bump(off, (uint64_t)sigma * 4);
+        p.ws_sdir = bump(off, wv_span_dir_sizes(n, p.key_bits).bytes);
         p.ws_bytes = off;
         return WT_OK;
     }
@@ -385,73 +386,66 @@ int shaped_nodes(const wt_shape& sh, uint32_t sigma, HostNodes& H, std::vector<u
     uint64_t N = 0;
     int rc = sorted_codes(sh, sigma, h, cs, &N);
     if (rc) return rc;
-    // per level: node prefixes (sorted), their symbol counts, and the leaves
-    // (code, symbol) whose codes end one level below
-    std::vector<std::vector<uint64_t>> pre(h), cnt(h);
-    std::vector<std::vector<std::pair<uint64_t, uint32_t>>> leaf(h + 1);
-    for (uint32_t l = 0; l < h; l++) {
-        for (const Coded& c : cs) {
-            if (c.len <= l) continue;
-            const uint64_t q = c.key >> (h - l);
-            if (pre[l].empty() || pre[l].back() != q) {
-                pre[l].push_back(q);
-                cnt[l].push_back(0);
-            }
-            cnt[l].back() += sh.counts[c.sym];
-        }
-    }
-    for (const Coded& c : cs) leaf[c.len].push_back({c.key >> (h - c.len), c.sym});
-    std::vector<uint64_t> base(h + 1, 0);
-    for (uint32_t l = 0; l < h; l++) base[l + 1] = base[l] + pre[l].size();
-    if (base[h] != N) return WT_EINVAL;
+    // symbols before every position of the key order
+    std::vector<uint64_t> pc(cs.size() + 1, 0);
+    for (size_t i = 0; i < cs.size(); i++) pc[i + 1] = pc[i] + sh.counts[cs[i].sym];
     H.start.assign(N, 0);
     H.child_start.assign(2 * N, 0);
     H.child.assign(2 * N, WV_NONE);
     rec.assign(N * WV_NODE_BYTES, 0);
-    std::vector<uint64_t> start(N, 0);
-    for (uint32_t l = 0; l < h; l++) {
-        uint64_t run = 0;
-        for (uint64_t k = 0; k < pre[l].size(); k++) {
-            start[base[l] + k] = run;
-            run += cnt[l][k];
-        }
-    }
-    for (uint32_t l = 0; l < h; l++) {
-        for (uint64_t k = 0; k < pre[l].size(); k++) {
-            const uint64_t t = base[l] + k;
-            H.start[t] = (uint32_t)start[t];
+    // level by level, nodes in key order: a node is the range of codewords
+    // sharing its prefix; its children split the range by the next key bit,
+    // a child holding one codeword that ends there is that symbol's leaf
+    struct Node { uint32_t a, b; uint64_t start; };
+    std::vector<Node> cur, nxt;
+    if (!cs.empty()) cur.push_back(Node{0, (uint32_t)cs.size(), 0});
+    uint64_t base = 0;
+    for (uint32_t l = 0; l < h && !cur.empty(); l++) {
+        const uint64_t nbase = base + cur.size();
+        if (nbase > N) return WT_EINVAL;
+        const uint32_t bit = h - 1 - l;
+        nxt.clear();
+        uint64_t nrun = 0;
+        for (uint64_t k = 0; k < cur.size(); k++) {
+            const Node nd = cur[k];
+            const uint64_t t = base + k;
+            const uint64_t cnt = pc[nd.b] - pc[nd.a];
+            const uint32_t m = (uint32_t)(std::partition_point(cs.begin() + nd.a, cs.begin() + nd.b,
+                                                               [&](const Coded& c) { return !((c.key >> bit) & 1u); }) -
+                                          cs.begin());
+            const uint32_t lo[2] = {nd.a, m}, hi[2] = {m, nd.b};
             uint32_t ch[2];
-            for (uint32_t b = 0; b < 2; b++) {
-                const uint64_t q = pre[l][k] * 2 + b;
+            for (uint32_t e = 0; e < 2; e++) {
                 uint32_t c = WV_NONE;
-                uint64_t cs_ = 0;
-                const auto& lv = leaf[l + 1];
-                auto lf = std::lower_bound(lv.begin(), lv.end(), std::make_pair(q, 0u));
-                if (lf != lv.end() && lf->first == q) {
-                    c = WV_LEAF | lf->second;
-                } else if (l + 1 < h) {
-                    const auto& nx = pre[l + 1];
-                    auto it = std::lower_bound(nx.begin(), nx.end(), q);
-                    if (it != nx.end() && *it == q) {
-                        const uint64_t id = base[l + 1] + (it - nx.begin());
-                        c = (uint32_t)id;
-                        cs_ = start[id];
-                    }
+                uint64_t cst = 0;
+                if (hi[e] - lo[e] == 1 && cs[lo[e]].len == l + 1) {
+                    c = WV_LEAF | cs[lo[e]].sym;
+                } else if (hi[e] > lo[e]) {
+                    const uint64_t id = nbase + nxt.size();
+                    if (id >= N) return WT_EINVAL;
+                    c = (uint32_t)id;
+                    cst = nrun;
+                    nxt.push_back(Node{lo[e], hi[e], nrun});
+                    nrun += pc[hi[e]] - pc[lo[e]];
                 }
-                ch[b] = c;
-                H.child[2 * t + b] = c;
-                H.child_start[2 * t + b] = (uint32_t)cs_;
+                ch[e] = c;
+                H.child[2 * t + e] = c;
+                H.child_start[2 * t + e] = (uint32_t)cst;
             }
+            H.start[t] = (uint32_t)nd.start;
             uint8_t* e = rec.data() + t * WV_NODE_BYTES;
-            const uint32_t lev = l, pr = (uint32_t)pre[l][k];
-            std::memcpy(e + 0, &start[t], 8);
-            std::memcpy(e + 8, &cnt[l][k], 8);
+            const uint32_t lev = l, pr = l ? (uint32_t)(cs[nd.a].key >> (h - l)) : 0u;
+            std::memcpy(e + 0, &nd.start, 8);
+            std::memcpy(e + 8, &cnt, 8);
             std::memcpy(e + 16, &ch[0], 4);
             std::memcpy(e + 20, &ch[1], 4);
             std::memcpy(e + 24, &lev, 4);
             std::memcpy(e + 28, &pr, 4);
         }
+        base = nbase;
+        cur.swap(nxt);
     }
+    if (base != N || !cur.empty()) return WT_EINVAL;
     return WT_OK;
 }
 
@@ -525,10 +519,25 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
         ~EventGuard() { (void)hipEventDestroy(e); }
     } guard{have_counts};
     WV_CHECK(hipEventRecord(have_counts, s));
+    // fork / join of the side stream (split shaped trees)
+    struct ForkEvents {
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~ForkEvents()
+        {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } fork;
+    if (p.h1 && p.nlong)
+        for (hipEvent_t& x : fork.e) WV_CHECK(hipEventCreateWithFlags(&x, hipEventDisableTiming));
 
     // 2. the matrix levels need no counts: launch them now, so that they run
     // while the host lays out the tree
-    std::vector<uint32_t> c32, l32, ktab;   // host arrays copied from: alive until the final synchronization
+    std::vector<uint32_t> c32, l32, ktab;
+    // host buffers of the uploads: pinned (pooled) when possible, released
+    // to the pool once the stream has passed the copies
+    PinnedBuf up_codes(shaped ? ((p.h1 ? p.ws_ktab : p.ws_lens) - p.ws_codes + (uint64_t)sigma * 4) : 0);
+    std::vector<uint8_t> up_codes_v, up_late_v;
     const void* keys = S;
     if (shaped) {
         c32.resize(sigma);
@@ -537,14 +546,19 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
             l32[x] = shape->code_len[x];
             c32[x] = l32[x] ? (uint32_t)shape->codes[x] : 0u;
         }
-        WV_CHECK(hipMemcpyAsync(at<void>(ws, p.ws_codes), c32.data(), (uint64_t)sigma * 4, hipMemcpyHostToDevice, s));
-        WV_CHECK(hipMemcpyAsync(at<void>(ws, p.ws_lens), l32.data(), (uint64_t)sigma * 4, hipMemcpyHostToDevice, s));
+        if (p.h1) wv_split_table(c32.data(), l32.data(), sigma, K, p.h1, ktab);   // top h1 bits of every codeword
+        // codes, lengths (and key table) in the workspace layout, one copy
+        const uint64_t span = (p.h1 ? p.ws_ktab : p.ws_lens) - p.ws_codes + (uint64_t)sigma * 4;
+        if (!up_codes.get()) up_codes_v.resize(span);
+        uint8_t* hb = up_codes.get() ? (uint8_t*)up_codes.get() : up_codes_v.data();
+        std::memcpy(hb, c32.data(), (uint64_t)sigma * 4);
+        std::memcpy(hb + (p.ws_lens - p.ws_codes), l32.data(), (uint64_t)sigma * 4);
+        if (p.h1) std::memcpy(hb + (p.ws_ktab - p.ws_codes), ktab.data(), (uint64_t)sigma * 4);
+        WV_CHECK(hipMemcpyAsync(at<void>(ws, p.ws_codes), hb, span, hipMemcpyHostToDevice, s));
         const uint32_t* dc = at<uint32_t>(ws, p.ws_codes);
         const uint32_t* dl = at<uint32_t>(ws, p.ws_lens);
         if (p.h1) {
-            // top h1 bits of every codeword, then the long codewords compacted
-            wv_split_table(c32.data(), l32.data(), sigma, K, p.h1, ktab);
-            WV_CHECK(hipMemcpyAsync(at<void>(ws, p.ws_ktab), ktab.data(), (uint64_t)sigma * 4, hipMemcpyHostToDevice, s));
+            // the 16-bit keys, then the long codewords compacted
             const uint32_t* dk = at<uint32_t>(ws, p.ws_ktab);
             uint64_t* boff = at<uint64_t>(ws, p.ws_boff);
             WV_TIMED(prof, s, "tree_keys",
@@ -600,13 +614,27 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
         }
     } else if (p.h1) {
         // S itself was validated above; the keys need no check
+        // the small matrix of the long codes on a side stream: its short,
+        // launch-bound passes overlap the big matrix's passes (forked after
+        // the keys, joined before anything reads its levels)
+        hipStream_t s2 = p.nlong ? wv_side_stream() : nullptr;
+        if (p.nlong) {
+            uint64_t* lwb[WV_MAX_LEVELS];
+            for (uint32_t l = 0; l < K; l++) lwb[l] = at<uint64_t>(ws, p.ws_btmp + l * p.btmp_stride);
+            const void* lk = at<void>(ws, p.ws_lkeys);
+            if (s2) {
+                WV_CHECK(hipEventRecord(fork.e[0], s));
+                WV_CHECK(hipStreamWaitEvent(s2, fork.e[0], 0));
+                WV_CHECK(wv_wm_levels(p.wmb, lk, lwb, nullptr, at<uint8_t>(ws, p.ws_wmb), s2));
+                WV_CHECK(hipEventRecord(fork.e[1], s2));
+            } else {
+                WV_CHECK(wv_wm_levels(p.wmb, lk, lwb, nullptr, at<uint8_t>(ws, p.ws_wmb), s));
+            }
+        }
         uint64_t* lw[WV_MAX_LEVELS];
         for (uint32_t l = 0; l < p.h1; l++) lw[l] = at<uint64_t>(ws, p.ws_tmp + l * p.tmp_stride);
         WV_CHECK(wv_wm_levels(p.wm, keys, lw, nullptr, at<uint8_t>(ws, p.ws_wm), s));
-        if (p.nlong) {
-            for (uint32_t l = 0; l < K; l++) lw[l] = at<uint64_t>(ws, p.ws_btmp + l * p.btmp_stride);
-            WV_CHECK(wv_wm_levels(p.wmb, at<void>(ws, p.ws_lkeys), lw, nullptr, at<uint8_t>(ws, p.ws_wmb), s));
-        }
+        if (s2) WV_CHECK(hipStreamWaitEvent(s, fork.e[1], 0));
     } else {
         uint64_t* lw[WV_MAX_LEVELS];
         for (uint32_t l = 0; l < K; l++) lw[l] = at<uint64_t>(ws, p.ws_tmp + l * p.tmp_stride);
@@ -693,22 +721,30 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
         WV_CHECK(hipStreamSynchronize(s));
         return WT_EUNSUP;
     }
-    // descriptors, runs and tiles in one copy
+    // descriptors, runs and tiles in one copy; the node and code tables of a
+    // shaped tree behind them in the same host buffer
     const uint64_t seg_at = wv_round256(WV_MAX_LEVELS * sizeof(wv_perm_level));
     const uint64_t tile_at = seg_at + wv_round256(segs.size() * sizeof(wv_perm_seg));
-    std::vector<uint8_t> stage(tile_at + tile_seg.size() * 4);
-    std::memcpy(stage.data(), lv.data(), T * sizeof(wv_perm_level));
-    if (!segs.empty()) std::memcpy(stage.data() + seg_at, segs.data(), segs.size() * sizeof(wv_perm_seg));
-    if (!tile_seg.empty()) std::memcpy(stage.data() + tile_at, tile_seg.data(), tile_seg.size() * 4);
+    const uint64_t stage_bytes = tile_at + tile_seg.size() * 4;
+    const uint64_t rec_at = wv_round256(stage_bytes), code_at = rec_at + wv_round256(rec.size());
+    const uint64_t late_bytes = code_at + code_rec.size();
+    PinnedBuf late(late_bytes);
+    if (!late.get()) up_late_v.resize(late_bytes);
+    uint8_t* stage = late.get() ? (uint8_t*)late.get() : up_late_v.data();
+    std::memcpy(stage, lv.data(), T * sizeof(wv_perm_level));
+    if (!segs.empty()) std::memcpy(stage + seg_at, segs.data(), segs.size() * sizeof(wv_perm_seg));
+    if (!tile_seg.empty()) std::memcpy(stage + tile_at, tile_seg.data(), tile_seg.size() * 4);
+    if (!rec.empty()) std::memcpy(stage + rec_at, rec.data(), rec.size());
+    if (!code_rec.empty()) std::memcpy(stage + code_at, code_rec.data(), code_rec.size());
     uint8_t* dsegs = at<uint8_t>(ws, p.ws_segs);
-    WV_CHECK(hipMemcpyAsync(dsegs, stage.data(), stage.size(), hipMemcpyHostToDevice, s));
+    WV_CHECK(hipMemcpyAsync(dsegs, stage, stage_bytes, hipMemcpyHostToDevice, s));
     const wv_perm_level* dlv = (const wv_perm_level*)dsegs;
     const wv_perm_seg* dseg = (const wv_perm_seg*)(dsegs + seg_at);
     const uint32_t* dtile = (const uint32_t*)(dsegs + tile_at);
     if (shaped) {
         if (!rec.empty())
-            WV_CHECK(hipMemcpyAsync(img + p.lay.nodes_off, rec.data(), rec.size(), hipMemcpyHostToDevice, s));
-        WV_CHECK(hipMemcpyAsync(img + p.lay.codes_off, code_rec.data(), code_rec.size(), hipMemcpyHostToDevice, s));
+            WV_CHECK(hipMemcpyAsync(img + p.lay.nodes_off, stage + rec_at, rec.size(), hipMemcpyHostToDevice, s));
+        WV_CHECK(hipMemcpyAsync(img + p.lay.codes_off, stage + code_at, code_rec.size(), hipMemcpyHostToDevice, s));
     }
 
     // 5. runs to tree order, then the directories
@@ -727,8 +763,10 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
     } else {
         WV_CHECK(wv_span_directory(img, p.lay, 0, K, dscr, p.wm.dir, s, prof));
     }
-    // the host arrays copied above go out of scope
+    // the host buffers copied from go out of scope
     WV_CHECK(hipStreamSynchronize(s));
+    up_codes.idle();
+    late.idle();
     return WT_OK;
 }
 
@@ -811,6 +849,18 @@ int build_any(int kind, const void* S, uint64_t n, uint32_t sigma, uint32_t sym_
 }
 
 }  // namespace
+
+hipStream_t wv_side_stream()
+{
+    static std::mutex mu;
+    static std::vector<hipStream_t> streams;   // by device
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    if (streams.size() <= (size_t)dev) streams.resize((size_t)dev + 1, nullptr);
+    if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess) streams[dev] = nullptr;
+    return streams[dev];
+}
 
 extern "C" {
 

@@ -73,14 +73,16 @@ hipError_t wv_multiary_ranges(uint8_t* image, const wv_level* lv, uint32_t M, ui
 
 // ---- pinned host staging -------------------------------------------------------
 // Pinned host buffers for copies a build issues between launches (the symbol
-// counts a tree build reads back, the descriptors of a batch): a copy from or
-// to pageable memory holds the host until it completes.  Buffers are reused
+// counts a tree build reads back and the tables it uploads, the descriptors
+// of a batch): a copy from or to pageable memory holds the host until it
+// completes.  Buffers are reused
 // until the process ends; one that a failed build may still be copying is
 // not returned.
 class PinnedBuf {
 public:
     explicit PinnedBuf(size_t bytes)
     {
+        if (!bytes) return;   // nothing to hold
         std::lock_guard<std::mutex> lk(mu());
         auto& fr = pool();
         for (size_t i = 0; i < fr.size(); i++)
@@ -119,6 +121,11 @@ private:
     size_t n_ = 0;
     bool idle_ = false;
 };
+
+// A second stream of the current device for work a build forks off its own
+// stream and joins again with events (created on first use, default
+// priority, never destroyed); nullptr when it cannot be created.
+hipStream_t wv_side_stream();
 
 // ---- header (wv_directory.hip) ---------------------------------------------
 // header, level descriptors (zeros/ones left 0) and zeroed gaps between arrays

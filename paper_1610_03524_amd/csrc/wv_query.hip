@@ -266,16 +266,18 @@ __device__ uint64_t q_rank(const QImg& q, uint32_t c, uint64_t i)
 __device__ uint64_t q_select(const QImg& q, uint32_t c, uint64_t k)
 {
     if (k == 0 || c >= q.sigma || q.n == 0) return U64MAX;
-    const uint64_t total = q_count_prefix(q, c, q.n);
-    if (k > total) return U64MAX;
     const uint32_t L = q.nlevels;
+    // matrix and balanced tree: one descent gives the symbol's range [s, e)
+    // below the last level, so its length is the symbol's count
     if (q.kind == WT_KIND_WM) {
-        uint64_t s = 0;
+        uint64_t s = 0, e = q.n;
         for (uint32_t l = 0; l < L; l++) {
             const uint32_t b = (c >> (L - 1 - l)) & 1u;
-            const uint64_t zs = rank0(q, l, s);
-            s = b ? q.lv[l].zeros + s - zs : zs;
+            const uint64_t zs = rank0(q, l, s), ze = rank0(q, l, e);
+            if (b) { s = q.lv[l].zeros + s - zs; e = q.lv[l].zeros + e - ze; }
+            else { s = zs; e = ze; }
         }
+        if (k > e - s) return U64MAX;
         uint64_t p = s + k - 1;
         for (uint32_t l = L; l-- > 0;) {
             const uint32_t b = (c >> (L - 1 - l)) & 1u;
@@ -292,6 +294,7 @@ __device__ uint64_t q_select(const QImg& q, uint32_t c, uint64_t k)
             const uint64_t zs = rank0(q, l, s), ze = rank0(q, l, e);
             if (!b) e = s + (ze - zs); else s = s + (ze - zs);
         }
+        if (k > e - s) return U64MAX;
         uint64_t p = s + k - 1, child = s;
         for (uint32_t l = L; l-- > 0;) {
             const uint32_t b = (c >> (L - 1 - l)) & 1u;
@@ -301,6 +304,8 @@ __device__ uint64_t q_select(const QImg& q, uint32_t c, uint64_t k)
         }
         return p;
     }
+    const uint64_t total = q_count_prefix(q, c, q.n);
+    if (k > total) return U64MAX;
     if (q.kind == WT_KIND_SHAPED) {
         uint64_t code;
         uint32_t len;

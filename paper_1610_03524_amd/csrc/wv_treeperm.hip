@@ -450,37 +450,15 @@ digits2_k(wv_digit_levels a, uint64_t n, uint64_t nwords, uint64_t* __restrict__
     if (2 * k + 1 < nwords) out[2 * k + 1] = spread(lo >> 32, 2) | (spread(w >> 32, 2) << 1);
 }
 
-inline uint64_t brev_bits(uint64_t v, uint32_t nbits)
-{
-    return nbits ? __builtin_bitreverse64(v) >> (64 - nbits) : 0ull;
-}
-
-// groups of one level, in numeric order: (group, symbols, kept on the tree level)
+// One group of a level: the symbols [a, b) of the key-sorted symbol list
+// sharing the level's key prefix (live: on the tree level), or a block of
+// symbols whose codes have ended (dead: left out of the level, padded with
+// zeros below their code)
 struct Group {
-    uint64_t g, count;
-    bool kept;
+    uint32_t a, b;
+    uint64_t count;
+    bool live;
 };
-
-// matrix and tree offsets of the kept groups of one level
-void level_segments(const std::vector<Group>& gs, uint32_t l, std::vector<wv_perm_seg>& out)
-{
-    // matrix order: by bit-reversed group
-    std::vector<std::pair<uint64_t, uint32_t>> order(gs.size());
-    for (uint32_t i = 0; i < order.size(); i++) order[i] = {brev_bits(gs[i].g, l), i};
-    std::sort(order.begin(), order.end());
-    std::vector<uint64_t> src(gs.size());
-    uint64_t acc = 0;
-    for (const auto& o : order) {
-        src[o.second] = acc;
-        acc += gs[o.second].count;
-    }
-    uint64_t dst = 0;
-    for (uint32_t i = 0; i < gs.size(); i++) {
-        if (!gs[i].kept || !gs[i].count) continue;
-        out.push_back(wv_perm_seg{dst, src[i], gs[i].count});
-        dst += gs[i].count;
-    }
-}
 
 }  // namespace
 
@@ -496,18 +474,74 @@ void wv_tree_segments(const std::vector<uint64_t>& counts, uint32_t key_bits, co
         else sy.push_back(Sym{x, counts[x], key_bits});
     }
     std::sort(sy.begin(), sy.end(), [](const Sym& a, const Sym& b) { return a.key < b.key; });
+    const uint32_t ns = (uint32_t)sy.size();
+    std::vector<uint64_t> pre(ns + 1, 0);
+    for (uint32_t i = 0; i < ns; i++) pre[i + 1] = pre[i] + sy[i].count;
     segs.clear();
     seg0.assign(key_bits + 1, 0);
-    std::vector<Group> gs;
+    if (!ns) return;
+    // a group with one symbol whose code ends at or above level l is dead
+    auto make = [&](uint32_t a, uint32_t b, uint32_t l) {
+        return Group{a, b, pre[b] - pre[a], !(b - a == 1 && sy[a].len <= l)};
+    };
+    // Level l of the matrix orders the groups by their bit-reversed prefix,
+    // which is the order of level l-1 stably partitioned by key bit l-1: the
+    // zero children of every group in that order, then the one children.
+    // A dead symbol's padding bits are zeros, so dead symbols next to each
+    // other stay next to each other and are kept as one block.
+    std::vector<Group> morder{make(0, ns, 0)}, zeros, ones;   // matrix order
+    std::vector<Group> num, nnum;                              // live groups by key
+    if (morder[0].live) num.push_back(morder[0]);
+    std::vector<uint64_t> src_at(ns, 0);
+    auto push = [](std::vector<Group>& v, const Group& g) {
+        if (!g.live && !v.empty() && !v.back().live) v.back().count += g.count;
+        else v.push_back(g);
+    };
     for (uint32_t l = 0; l < key_bits; l++) {
         seg0[l] = segs.size();
-        gs.clear();
-        for (const Sym& s : sy) {
-            const uint64_t g = l ? (s.key >> (key_bits - l)) : 0;
-            if (!gs.empty() && gs.back().g == g) gs.back().count += s.count;
-            else gs.push_back(Group{g, s.count, s.len > l});
+        uint64_t acc = 0;
+        for (const Group& g : morder) {
+            if (g.live) src_at[g.a] = acc;
+            acc += g.count;
         }
-        level_segments(gs, l, segs);
+        uint64_t dst = 0;
+        for (const Group& g : num) {
+            segs.push_back(wv_perm_seg{dst, src_at[g.a], g.count});
+            dst += g.count;
+        }
+        if (l + 1 == key_bits) break;
+        // split every live group by key bit l (counted from the top)
+        const uint32_t sh = key_bits - 1 - l;
+        auto split = [&](const Group& g) {
+            return (uint32_t)(std::partition_point(sy.begin() + g.a, sy.begin() + g.b,
+                                                   [&](const Sym& y) { return !((y.key >> sh) & 1u); }) - sy.begin());
+        };
+        zeros.clear();
+        ones.clear();
+        for (const Group& g : morder) {
+            if (!g.live) {
+                push(zeros, g);
+                continue;
+            }
+            const uint32_t m = split(g);
+            if (m > g.a) push(zeros, make(g.a, m, l + 1));
+            if (m < g.b) push(ones, make(m, g.b, l + 1));
+        }
+        morder.swap(zeros);
+        for (const Group& g : ones) push(morder, g);
+        nnum.clear();
+        for (const Group& g : num) {
+            const uint32_t m = split(g);
+            if (m > g.a) {
+                const Group c = make(g.a, m, l + 1);
+                if (c.live) nnum.push_back(c);
+            }
+            if (m < g.b) {
+                const Group c = make(m, g.b, l + 1);
+                if (c.live) nnum.push_back(c);
+            }
+        }
+        num.swap(nnum);
     }
     seg0[key_bits] = segs.size();
 }
