@@ -343,15 +343,13 @@ def tree_kernel_bytes(name, info, sym_bytes, kind):
     key_w = 4 if kind == 3 else sym_bytes
     tree_bits = sum(int(info.level_n[l]) * D for l in range(info.nlevels))
     width = lambda bits: 1 if bits <= 8 else (2 if bits <= 16 else 4)
-    # the matrices built: (symbols, key bits, key width, pass width); a shaped
-    # tree split at h1 bits has one over the top h1 code bits of every symbol
-    # (16-bit keys) and one over the whole codes of the long-code symbols
+    # the matrix whose passes are timed as "wm_pass" / "wm_hist": (symbols,
+    # key bits, key width, pass width).  A shaped tree split at h1 bits builds
+    # it over the top h1 code bits of every symbol (16-bit keys); its second
+    # matrix, over the whole codes of the long-code symbols, runs on a side
+    # stream and is timed as one entry ("side_matrix")
     h1, nlong = int(info.split_bits), int(info.split_long)
-    if h1:
-        passes_b = (K + 7) // 8
-        mats = [(n, h1, 2, int(info.tau))] + ([(nlong, K, 4, (K + passes_b - 1) // passes_b)] if nlong else [])
-    else:
-        mats = [(n, K, key_w, int(info.tau))]
+    mats = [(n, h1, 2, int(info.tau))] if h1 else [(n, K, key_w, int(info.tau))]
     if name == "wm_pass":
         total = 0
         for m, L, in_w, tau in mats:

@@ -623,9 +623,13 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
             for (uint32_t l = 0; l < K; l++) lwb[l] = at<uint64_t>(ws, p.ws_btmp + l * p.btmp_stride);
             const void* lk = at<void>(ws, p.ws_lkeys);
             if (s2) {
+                // timed as a whole: per-kernel events on the side stream
+                // would count the time its kernels wait for the CUs
+                wv_wm_plan pb = p.wmb;
+                pb.profile = false;
                 WV_CHECK(hipEventRecord(fork.e[0], s));
                 WV_CHECK(hipStreamWaitEvent(s2, fork.e[0], 0));
-                WV_CHECK(wv_wm_levels(p.wmb, lk, lwb, nullptr, at<uint8_t>(ws, p.ws_wmb), s2));
+                WV_TIMED(prof, s2, "side_matrix", WV_CHECK(wv_wm_levels(pb, lk, lwb, nullptr, at<uint8_t>(ws, p.ws_wmb), s2)));
                 WV_CHECK(hipEventRecord(fork.e[1], s2));
             } else {
                 WV_CHECK(wv_wm_levels(p.wmb, lk, lwb, nullptr, at<uint8_t>(ws, p.ws_wmb), s));
