@@ -286,7 +286,7 @@ __device__ void wm_pass_chunk(const PassArgs& a, uint32_t b, PassShared<KT_>& S)
     }
 }
 
-constexpr uint32_t HSPLIT = 8;       // histogram workgroups per chunk
+constexpr uint32_t HSPLIT = 2;       // histogram workgroups per chunk
 constexpr uint32_t HUNROLL = 4;      // 16-byte loads in flight per thread
 // LDS histograms of a workgroup: HCOPY per wave, lane l adding into copy
 // l % HCOPY, so that lanes holding the same frequent digit seldom hit one
