@@ -478,7 +478,7 @@ __global__ void __launch_bounds__(SD_T)
 span_write_k(uint8_t* __restrict__ image, SpanLevels a, const uint64_t* __restrict__ pre, uint32_t nchunks)
 {
     __shared__ uint32_t wpart[SD_T / 64];
-    __shared__ uint64_t zex[SD_W];   // zeros in [0, min(64w, n)) per word of the chunk
+    __shared__ uint32_t zex[SD_W];   // zeros of the chunk before each of its words (up to the level's end)
     const uint32_t l = blockIdx.y;
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint64_t n = a.n[l], nw = wv_cdiv(n, 64), ns = wv_cdiv(n, WV_SB_BITS);
@@ -486,12 +486,36 @@ span_write_k(uint8_t* __restrict__ image, SpanLevels a, const uint64_t* __restri
     uint64_t* dir = (uint64_t*)(image + a.rank_off[l]);
     uint64_t* sel0 = (uint64_t*)(image + a.sel0_off[l]);
     uint64_t* sel1 = (uint64_t*)(image + a.sel1_off[l]);
+    constexpr uint32_t SM = WV_SEL_STRIDE - 1;
+    // my two words of chunk c (16-byte aligned: the first is even)
+    auto load2 = [&](uint32_t c, uint64_t& y0, uint64_t& y1) {
+        const uint64_t w = (uint64_t)c * SD_W + 2 * threadIdx.x;
+        y0 = y1 = 0;
+        if (w + 1 < nw) {
+            const ulonglong2 v = *(const ulonglong2*)(words + w);
+            y0 = v.x;
+            y1 = v.y;
+        } else if (w < nw) {
+            y0 = words[w];
+        }
+    };
+    uint64_t nx0 = 0, nx1 = 0;
+    if (blockIdx.x * 4 < nchunks) load2(blockIdx.x * 4, nx0, nx1);
     for (uint32_t gi = 0; gi < 4; gi++) {   // four chunks per workgroup
         const uint32_t c = blockIdx.x * 4 + gi;
         if (c >= nchunks) break;   // uniform
+        // this chunk's words were loaded one chunk ahead; load the next now
+        const uint64_t x0 = nx0, x1 = nx1;
+        if (gi + 1 < 4 && c + 1 < nchunks) load2(c + 1, nx0, nx1);
         const uint64_t cw = (uint64_t)c * SD_W;
-        const uint64_t w0 = cw + 2 * threadIdx.x;
-        const uint64_t x0 = w0 < nw ? words[w0] : 0ull, x1 = w0 + 1 < nw ? words[w0 + 1] : 0ull;
+        // counts inside the chunk fit 32 bits; the chunk's base counts are
+        // added where a global position is written
+        const uint64_t cbits = min(64 * cw, n);
+        const uint32_t nloc = (uint32_t)min<uint64_t>(n - cbits, 64ull * SD_W);   // level bits in the chunk
+        const uint64_t obase = pre[(uint64_t)c * a.nl + l];                       // ones before the chunk
+        const uint64_t zbase = cbits - obase;                                     // zeros before the chunk
+        const uint32_t wl = 2 * threadIdx.x;                                      // my first word, chunk-local
+        const uint64_t w0 = cw + wl;
         const uint32_t o0 = __popcll(x0), o1 = __popcll(x1);
         // exclusive prefix of ones over the words of the chunk
         const uint32_t inc = wv_wave_incl_scan(o0 + o1);
@@ -499,38 +523,38 @@ span_write_k(uint8_t* __restrict__ image, SpanLevels a, const uint64_t* __restri
         __syncthreads();
         uint32_t off = 0;
         for (uint32_t k = 0; k < wave; k++) off += wpart[k];
-        const uint64_t ob0 = pre[(uint64_t)c * a.nl + l] + off + inc - (o0 + o1);   // ones before word w0
-        const uint64_t ob1 = ob0 + o0;
-        const uint64_t z0 = min(64 * w0, n) - ob0, z1 = min(64 * (w0 + 1), n) - ob1;
-        zex[2 * threadIdx.x] = z0;
-        zex[2 * threadIdx.x + 1] = z1;
-        // sampled select: the one / zero of ordinal 4096k inside one of my words
+        const uint32_t ob0 = off + inc - (o0 + o1), ob1 = ob0 + o0;   // ones before my words
+        const uint32_t z0 = min(64u * wl, nloc) - ob0, z1 = min(64u * (wl + 1), nloc) - ob1;
+        zex[wl] = z0;
+        zex[wl + 1] = z1;
+        // sampled select: the one / zero of ordinal 4096k inside one of my
+        // words lies `dist` after the word's first one / zero
         const uint64_t xs[2] = {x0, x1};
-        const uint32_t os[2] = {o0, o1};
-        const uint64_t obs[2] = {ob0, ob1}, zbs[2] = {z0, z1};
+        const uint32_t os[2] = {o0, o1}, obs[2] = {ob0, ob1}, zbs[2] = {z0, z1};
+        const uint32_t obm = (uint32_t)(obase & SM), zbm = (uint32_t)(zbase & SM);
         for (int q = 0; q < 2; q++) {
             const uint64_t w = w0 + q;
             if (w >= nw) break;
-            const uint64_t t1 = wv_cdiv(obs[q], WV_SEL_STRIDE) * WV_SEL_STRIDE;
-            if (t1 < obs[q] + os[q])
-                sel1[t1 / WV_SEL_STRIDE] = 64 * w + wv_select_in_word(xs[q], (uint32_t)(t1 - obs[q]));
-            const uint64_t valid = min((uint64_t)64, n - 64 * w);
+            const uint32_t d1 = (WV_SEL_STRIDE - ((obm + obs[q]) & SM)) & SM;
+            if (d1 < os[q])
+                sel1[(obase + obs[q] + d1) / WV_SEL_STRIDE] = 64 * w + wv_select_in_word(xs[q], d1);
+            const uint32_t valid = min(64u, nloc - 64u * (wl + q));
             const uint64_t vm = valid >= 64 ? ~0ull : ((1ull << valid) - 1ull);
-            const uint32_t zc = (uint32_t)valid - os[q];
-            const uint64_t t0 = wv_cdiv(zbs[q], WV_SEL_STRIDE) * WV_SEL_STRIDE;
-            if (t0 < zbs[q] + zc)
-                sel0[t0 / WV_SEL_STRIDE] = 64 * w + wv_select_in_word(~xs[q] & vm, (uint32_t)(t0 - zbs[q]));
+            const uint32_t zc = valid - os[q];
+            const uint32_t d0 = (WV_SEL_STRIDE - ((zbm + zbs[q]) & SM)) & SM;
+            if (d0 < zc)
+                sel0[(zbase + zbs[q] + d0) / WV_SEL_STRIDE] = 64 * w + wv_select_in_word(~xs[q] & vm, d0);
         }
         __syncthreads();
-        // one thread per superblock of the chunk
+        // one thread per superblock of the chunk: zeros before it, and the
+        // zeros before each of its words 1..7 relative to that (9 bits each)
         if (threadIdx.x < SD_W / 8) {
             const uint64_t k = cw / 8 + threadIdx.x;
             if (k < ns) {
-                const uint64_t zb = zex[8 * threadIdx.x];
+                const uint32_t zb = zex[8 * threadIdx.x];
                 uint64_t blk = 0;
-                for (uint32_t q = 1; q < 8; q++) blk |= (zex[8 * threadIdx.x + q] - zb) << (9 * (q - 1));
-                dir[2 * k] = zb;
-                dir[2 * k + 1] = blk;
+                for (uint32_t q = 1; q < 8; q++) blk |= (uint64_t)(zex[8 * threadIdx.x + q] - zb) << (9 * (q - 1));
+                *(ulonglong2*)(dir + 2 * k) = make_ulonglong2(zbase + zb, blk);   // 16-byte aligned
             }
         }
         __syncthreads();   // wpart and zex are rewritten by the next chunk
