@@ -1,7 +1,11 @@
 """Seeded random builds: kind, size, alphabet, symbol width, pass width and
 chunk count drawn together, every image equal to the oracle's byte for byte
 (combinations the targeted tests do not enumerate, e.g. a split shaped tree
-under a forced pass width, or many chunks of a few tiles)."""
+under a forced pass width, or many chunks of a few tiles); and random
+batches, every sequence's image equal to the oracle's.  WV_RANDOM_DRAWS and
+WV_RANDOM_BATCHES set how many (48 and 8 by default)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -28,7 +32,7 @@ def draw(rng):
     return kind, S, sigma, tau, blocks, D
 
 
-@pytest.mark.parametrize("seed", range(48))
+@pytest.mark.parametrize("seed", range(int(os.environ.get("WV_RANDOM_DRAWS", "48"))))
 def test_random_build_equals_oracle(seed):
     rng = np.random.default_rng(5000 + seed)
     kind, S, sigma, tau, blocks, D = draw(rng)
@@ -44,3 +48,24 @@ def test_random_build_equals_oracle(seed):
         g = gpu_image(kind, S, sigma, D, tune=tune)
         o = oracle_image(kind, S, sigma, D)
     assert_same(g, o, what)
+
+
+@pytest.mark.parametrize("seed", range(int(os.environ.get("WV_RANDOM_BATCHES", "8"))))
+def test_random_batch_equals_oracle(seed):
+    from test_gpu_batch import run_batch
+    rng = np.random.default_rng(90000 + seed)
+    seqs, taus = [], []
+    for _ in range(int(rng.integers(1, 40))):
+        n = int(2 ** rng.uniform(0, 18)) if rng.random() > 0.05 else int(rng.integers(0, 3))
+        sigma = max(1, int(2 ** rng.uniform(0, 20)))
+        need = 1 if sigma <= 256 else (2 if sigma <= 65536 else 4)
+        dt = {1: np.uint8, 2: np.uint16, 4: np.uint32}[int(rng.choice([w for w in (1, 2, 4) if w >= need]))]
+        if rng.random() < 0.3:
+            S = np.minimum(rng.geometric(min(0.5, 4.0 / sigma + 1e-4), n) - 1, sigma - 1).astype(dt)
+        else:
+            S = rng.integers(0, sigma, n).astype(dt)
+        seqs.append((S, sigma))
+        taus.append(int(rng.choice([0, 0, 1, 2, 3, 5, 7, 8])))
+    imgs = run_batch(seqs, taus=taus)
+    for k, ((S, sigma), g) in enumerate(zip(seqs, imgs)):
+        assert_same(g, oracle_image(B.KIND_WM, S, sigma), f"batch {seed} seq {k} n={S.size} sigma={sigma} tau={taus[k]}")
