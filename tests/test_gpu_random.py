@@ -2,8 +2,10 @@
 chunk count drawn together, every image equal to the oracle's byte for byte
 (combinations the targeted tests do not enumerate, e.g. a split shaped tree
 under a forced pass width, or many chunks of a few tiles); and random
-batches, every sequence's image equal to the oracle's.  WV_RANDOM_DRAWS and
-WV_RANDOM_BATCHES set how many (48 and 8 by default)."""
+batches, every sequence's image equal to the oracle's; and large draws
+(n from 2^18 to 2^23, hundreds of chunks).  WV_RANDOM_DRAWS,
+WV_RANDOM_BATCHES and WV_RANDOM_LARGE set how many (48, 8 and 2 by
+default)."""
 import os
 
 import numpy as np
@@ -69,3 +71,30 @@ def test_random_batch_equals_oracle(seed):
     imgs = run_batch(seqs, taus=taus)
     for k, ((S, sigma), g) in enumerate(zip(seqs, imgs)):
         assert_same(g, oracle_image(B.KIND_WM, S, sigma), f"batch {seed} seq {k} n={S.size} sigma={sigma} tau={taus[k]}")
+
+
+@pytest.mark.parametrize("seed", range(int(os.environ.get("WV_RANDOM_LARGE", "2"))))
+def test_random_large_build_equals_oracle(seed):
+    rng = np.random.default_rng(777000 + seed)
+    kind = int(rng.choice([B.KIND_WM, B.KIND_WT, B.KIND_SHAPED, B.KIND_MULTIARY]))
+    n = int(2 ** rng.uniform(18, 23))
+    sigma = max(2, int(2 ** rng.uniform(1, 20)))
+    need = 1 if sigma <= 256 else (2 if sigma <= 65536 else 4)
+    dt = {1: np.uint8, 2: np.uint16, 4: np.uint32}[int(rng.choice([w for w in (1, 2, 4) if w >= need]))]
+    if kind == B.KIND_SHAPED or rng.random() < 0.4:
+        S = np.minimum(rng.geometric(min(0.5, 8.0 / sigma + 1e-4), n) - 1, sigma - 1).astype(dt)
+    else:
+        S = rng.integers(0, sigma, n).astype(dt)
+    tau = int(rng.choice([0, 0, 0, 3, 5, 7, 8]))
+    blocks = int(rng.choice([0, 0, 0, 7, 100]))
+    D = int(rng.integers(1, 5)) if kind == B.KIND_MULTIARY else 0
+    tune = B.make_tuning(tau=tau, blocks=blocks)
+    what = f"seed={seed} kind={kind} n={n} sigma={sigma} {S.dtype} tau={tau} blocks={blocks} D={D}"
+    if kind == B.KIND_SHAPED:
+        (gc, gl), (oc, ol) = shaped_codes(S, sigma)
+        g = gpu_image(kind, S, sigma, codes=gc, lens=gl, tune=tune)
+        o = oracle_image(kind, S, sigma, codes=oc, lens=ol)
+    else:
+        g = gpu_image(kind, S, sigma, D, tune=tune)
+        o = oracle_image(kind, S, sigma, D)
+    assert_same(g, o, what)
