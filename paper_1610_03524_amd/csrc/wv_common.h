@@ -213,11 +213,18 @@ __device__ inline uint64_t wv_mrank(const uint64_t* __restrict__ words, const ui
     const uint16_t* sub = (const uint16_t*)(cnt + (nr + 1) * d * 8);
     const uint64_t rk = i / (64ull * P);
     uint64_t r = rng[rk * d + g];
+    // the sub-range holding i; for i = m at a sub-range boundary inside the
+    // last range there is no such sub-range, and the words are counted from
+    // the range start
     const uint64_t sk = i / (8ull * P);
-    if (sk < wv_msubs(m, D) && (sk * 8ull * P) < m) r += sub[sk * d + g];
+    uint64_t w0 = rk * 64;
+    if (sk < wv_msubs(m, D)) {
+        r += sub[sk * d + g];
+        w0 = sk * 8;
+    }
     const uint64_t wk = i / P;
-    // whole words between the sub-range start and the word holding i
-    for (uint64_t w = sk * 8; w < wk; w++) r += wv_count_digit(words[w], D, g, P);
+    // whole words between the (sub-)range start and the word holding i
+    for (uint64_t w = w0; w < wk; w++) r += wv_count_digit(words[w], D, g, P);
     const uint32_t t = (uint32_t)(i - wk * P);
     if (t) r += wv_count_digit(words[wk], D, g, t);
     return r;

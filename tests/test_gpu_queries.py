@@ -79,3 +79,18 @@ def test_select_sparse_and_dense_levels():
     for kind in (B.KIND_WM, B.KIND_WT):
         img, _ = B.build(kind, to_device(S), 2)
         run_queries(img, S, 2, rng)
+
+
+@pytest.mark.parametrize("D", [1, 2, 3, 4])
+@pytest.mark.parametrize("subs", [1, 3, 9, 994])
+def test_multiary_queries_when_n_ends_a_sub_range(D, subs):
+    """n a whole number of 8-word sub-ranges but not of 64-word ranges: a
+    rank at position n has no sub-range counter and counts its words from the
+    range start (every descent asks for the rank at the level's end)"""
+    P = 21 if D == 3 else 64 >> (D >> 1)
+    n = subs * 8 * P
+    for sigma in (5, 570):
+        rng = np.random.default_rng(n + sigma + D)
+        S = rng.integers(0, sigma, n).astype(dtype_for(sigma))
+        img, _ = B.build(B.KIND_MULTIARY, to_device(S), sigma, arity_log2=D)
+        run_queries(img, S, sigma, rng)
