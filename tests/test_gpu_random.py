@@ -2,10 +2,12 @@
 chunk count drawn together, every image equal to the oracle's byte for byte
 (combinations the targeted tests do not enumerate, e.g. a split shaped tree
 under a forced pass width, or many chunks of a few tiles); and random
-batches, every sequence's image equal to the oracle's; and large draws
-(n from 2^18 to 2^23, hundreds of chunks).  WV_RANDOM_DRAWS,
-WV_RANDOM_BATCHES and WV_RANDOM_LARGE set how many (48, 8 and 2 by
-default)."""
+batches, every sequence's image equal to the oracle's; large draws (n from
+2^18 to 2^23, hundreds of chunks); and draws whose n sits on a boundary of
+words, superblocks, select samples, tiles or multiary (sub-)ranges, built
+against the oracle and queried against brute force.  WV_RANDOM_DRAWS,
+WV_RANDOM_BATCHES, WV_RANDOM_LARGE and WV_RANDOM_BOUNDARY set how many (48,
+8, 2 and 16 by default)."""
 import os
 
 import numpy as np
@@ -98,3 +100,49 @@ def test_random_large_build_equals_oracle(seed):
         g = gpu_image(kind, S, sigma, D, tune=tune)
         o = oracle_image(kind, S, sigma, D)
     assert_same(g, o, what)
+
+
+def boundary_draw(rng, sigma_lg, kinds=(B.KIND_WM, B.KIND_WT, B.KIND_SHAPED, B.KIND_MULTIARY)):
+    kind = int(rng.choice(list(kinds)))
+    D = int(rng.integers(1, 5)) if kind == B.KIND_MULTIARY else 0
+    P = 21 if D == 3 else (64 >> (D >> 1) if D else 64)
+    unit = int(rng.choice([64, 512, 4096, 8192, 8 * P, 64 * P, 256 * 64]))
+    n = max(1, unit * int(rng.integers(1, 24)) + int(rng.choice([-1, 0, 0, 1])))
+    sigma = max(1, int(2 ** rng.uniform(0, sigma_lg)))
+    need = 1 if sigma <= 256 else (2 if sigma <= 65536 else 4)
+    dt = {1: np.uint8, 2: np.uint16, 4: np.uint32}[int(rng.choice([w for w in (1, 2, 4) if w >= need]))]
+    if kind == B.KIND_SHAPED or rng.random() < 0.3:
+        S = np.minimum(rng.geometric(min(0.5, 8.0 / sigma + 1e-4), n) - 1, sigma - 1).astype(dt)
+    else:
+        S = rng.integers(0, sigma, n).astype(dt)
+    return kind, D, S, sigma, f"kind={kind} D={D} n={n} unit={unit} sigma={sigma} {S.dtype}"
+
+
+@pytest.mark.parametrize("seed", range(int(os.environ.get("WV_RANDOM_BOUNDARY", "16"))))
+def test_boundary_build_equals_oracle(seed):
+    rng = np.random.default_rng(444000 + seed)
+    kind, D, S, sigma, what = boundary_draw(rng, 20)
+    tune = B.make_tuning(tau=int(rng.choice([0, 0, 2, 5, 8])), blocks=int(rng.choice([0, 0, 1, 3])))
+    if kind == B.KIND_SHAPED:
+        (gc, gl), (oc, ol) = shaped_codes(S, sigma)
+        g = gpu_image(kind, S, sigma, codes=gc, lens=gl, tune=tune)
+        o = oracle_image(kind, S, sigma, codes=oc, lens=ol)
+    else:
+        g = gpu_image(kind, S, sigma, D, tune=tune)
+        o = oracle_image(kind, S, sigma, D)
+    assert_same(g, o, f"seed={seed} {what}")
+
+
+@pytest.mark.parametrize("seed", range(int(os.environ.get("WV_RANDOM_BOUNDARY", "16"))))
+def test_boundary_queries_match_brute_force(seed):
+    from gpu_util import to_device
+    from test_gpu_queries import run_queries
+    rng = np.random.default_rng(333000 + seed)
+    kind, D, S, sigma, what = boundary_draw(rng, 16)
+    if kind == B.KIND_SHAPED:
+        (gc, gl), _ = shaped_codes(S, sigma)
+        counts = B.symbol_counts(to_device(S), sigma).cpu().numpy()
+        img, _ = B.build(kind, to_device(S), sigma, codes=gc, code_len=gl, counts=counts)
+    else:
+        img, _ = B.build(kind, to_device(S), sigma, arity_log2=D)
+    run_queries(img, S, sigma, rng)
