@@ -7,7 +7,8 @@ batches, every sequence's image equal to the oracle's; large draws (n from
 words, superblocks, select samples, tiles or multiary (sub-)ranges, built
 against the oracle and queried against brute force.  WV_RANDOM_DRAWS,
 WV_RANDOM_BATCHES, WV_RANDOM_LARGE and WV_RANDOM_BOUNDARY set how many (48,
-8, 2 and 16 by default)."""
+8, 2 and 16 by default); WV_RANDOM_LEVELWISE draws (8 by default) go through
+the level-by-level builder."""
 import os
 
 import numpy as np
@@ -36,11 +37,9 @@ def draw(rng):
     return kind, S, sigma, tau, blocks, D
 
 
-@pytest.mark.parametrize("seed", range(int(os.environ.get("WV_RANDOM_DRAWS", "48"))))
-def test_random_build_equals_oracle(seed):
-    rng = np.random.default_rng(5000 + seed)
+def check_draw(rng, seed, flags=0):
     kind, S, sigma, tau, blocks, D = draw(rng)
-    tune = B.make_tuning(tau=tau, blocks=blocks)
+    tune = B.make_tuning(tau=tau, blocks=blocks, flags=flags)
     what = f"seed={seed} kind={kind} n={S.size} sigma={sigma} {S.dtype} tau={tau} blocks={blocks} D={D}"
     if kind == B.KIND_SHAPED:
         if S.size == 0:
@@ -52,6 +51,16 @@ def test_random_build_equals_oracle(seed):
         g = gpu_image(kind, S, sigma, D, tune=tune)
         o = oracle_image(kind, S, sigma, D)
     assert_same(g, o, what)
+
+
+@pytest.mark.parametrize("seed", range(int(os.environ.get("WV_RANDOM_DRAWS", "48"))))
+def test_random_build_equals_oracle(seed):
+    check_draw(np.random.default_rng(5000 + seed), seed)
+
+
+@pytest.mark.parametrize("seed", range(int(os.environ.get("WV_RANDOM_LEVELWISE", "8"))))
+def test_random_levelwise_build_equals_oracle(seed):
+    check_draw(np.random.default_rng(8000000 + seed), seed, B.FLAG_LEVELWISE)
 
 
 @pytest.mark.parametrize("seed", range(int(os.environ.get("WV_RANDOM_BATCHES", "8"))))
