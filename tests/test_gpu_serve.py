@@ -1,5 +1,6 @@
 """Serving: every build and query result in the continuous-batching mix is
 identical to the same request run alone; admission respects the budget."""
+import os
 import threading
 import time
 
@@ -107,3 +108,49 @@ def test_budget_admission_and_eviction():
     for i, st in srv.resident.items():
         assert np.array_equal(st.image.cpu().numpy(), want[i])
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("seed", range(int(os.environ.get("WV_RANDOM_SERVE", "4"))))
+@pytest.mark.parametrize("mode", ["continuous", "plain"])
+def test_random_mix_same_as_alone(seed, mode):
+    """random pools, query batch sizes, repeats and burst timing; every image
+    and every query result equal to the request run alone"""
+    import torch
+    rng = np.random.default_rng(12345 + seed)
+    host = pool(int(rng.integers(4, 40)), seed=1000 + seed)
+    nb = int(rng.integers(1, 4))
+    batches = [(t, serve.make_query_batch(host[t][0], int(rng.integers(1, 4000)), rng))
+               for t in range(len(host)) for _ in range(nb)]
+    want_imgs, want_q = alone(host, batches)
+    dev = [(to_device(S), sigma) for S, sigma in host]
+    srv = serve.WaveletServer(dev, hbm_budget=1 << 34, ws_bytes=1 << 28, mode=mode)
+    srv.start()
+    qreqs, pending = [], list(range(len(batches)))
+    burst = int(rng.integers(1, 9))
+    pause = float(rng.choice([0.0, 0.0005, 0.002]))
+    for _ in range(int(rng.integers(1, 4))):
+        for i in rng.permutation(len(host)):
+            srv.submit_build(int(i))
+            if i % burst == 0 and pause:
+                time.sleep(pause)
+            for b in [b for b in pending if srv.is_resident(batches[b][0])][:3]:
+                qreqs.append((b, srv.submit_query(batches[b][0], batches[b][1])))
+                pending.remove(b)
+    deadline = time.time() + 60
+    while pending and time.time() < deadline:
+        for b in [b for b in pending if srv.is_resident(batches[b][0])]:
+            qreqs.append((b, srv.submit_query(batches[b][0], batches[b][1])))
+            pending.remove(b)
+        time.sleep(0.001)
+    while any(not r.done for r in srv.all_reqs) and time.time() < deadline:
+        time.sleep(0.002)
+    srv.close()
+    torch.cuda.synchronize()
+    assert not pending
+    for r in srv.all_reqs:
+        assert r.done and r.error == 0, (r.kind, r.seq, r.error)
+    for i in range(len(host)):
+        assert np.array_equal(srv.resident[i].image.cpu().numpy(), want_imgs[i]), f"image {i}"
+    for b, r in qreqs:
+        for g, w in zip(r.result, want_q[b]):
+            assert np.array_equal(g.cpu().numpy(), w), f"query batch {b}"
