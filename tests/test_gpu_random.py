@@ -8,7 +8,8 @@ words, superblocks, select samples, tiles or multiary (sub-)ranges, built
 against the oracle and queried against brute force.  WV_RANDOM_DRAWS,
 WV_RANDOM_BATCHES, WV_RANDOM_LARGE and WV_RANDOM_BOUNDARY set how many (48,
 8, 2 and 16 by default); WV_RANDOM_LEVELWISE draws (8 by default) go through
-the level-by-level builder."""
+the level-by-level builder; WV_RANDOM_RANGE draws (12 by default) plant one
+symbol >= sigma, which every kind and the batch must report."""
 import os
 
 import numpy as np
@@ -155,3 +156,54 @@ def test_boundary_queries_match_brute_force(seed):
     else:
         img, _ = B.build(kind, to_device(S), sigma, arity_log2=D)
     run_queries(img, S, sigma, rng)
+
+
+@pytest.mark.parametrize("seed", range(int(os.environ.get("WV_RANDOM_RANGE", "12"))))
+def test_random_symbol_out_of_range_is_reported(seed):
+    from gpu_util import to_device
+    rng = np.random.default_rng(616000 + seed)
+    n = int(2 ** rng.uniform(0, 20))
+    sigma = max(1, int(2 ** rng.uniform(0, 16)))
+    dt = np.uint8 if sigma < 256 else (np.uint16 if sigma < 65536 else np.uint32)
+    S = rng.integers(0, sigma, n).astype(dt)
+    bad = S.copy()
+    i = int(rng.integers(0, n))
+    bad[i] = int(rng.choice([sigma, min(np.iinfo(dt).max, 2 * sigma + 3), np.iinfo(dt).max]))
+    what = f"seed={seed} n={n} sigma={sigma} {dt.__name__} bad S[{i}]={int(bad[i])}"
+    img, _ = B.build(B.KIND_WM, to_device(bad), sigma)
+    assert B.check(img) == B.WT_ERANGE, what
+    for kind, D in ((B.KIND_WT, 0), (B.KIND_MULTIARY, int(rng.integers(1, 5))), (B.KIND_SHAPED, 0)):
+        with pytest.raises(B.WaveletError) as e:
+            if kind == B.KIND_SHAPED:
+                (gc, gl), _ = shaped_codes(S, sigma)
+                counts = B.symbol_counts(to_device(S), sigma).cpu().numpy()
+                B.build(kind, to_device(bad), sigma, codes=gc, code_len=gl, counts=counts)
+            else:
+                B.build(kind, to_device(bad), sigma, arity_log2=D)
+        assert e.value.code == B.WT_ERANGE, f"{what} kind={kind} D={D}"
+    # in a batch only the bad sequence is flagged; the others are built as alone
+    seqs = [(S, sigma), (bad, sigma), (S[: n // 2 + 1].copy(), sigma)]
+    imgs = run_batch_status(seqs)
+    assert [st for st, _ in imgs] == [B.WT_OK, B.WT_ERANGE, B.WT_OK], what
+    assert_same(imgs[0][1], oracle_image(B.KIND_WM, S, sigma), what)
+    assert_same(imgs[2][1], oracle_image(B.KIND_WM, seqs[2][0], sigma), what)
+
+
+def run_batch_status(seqs):
+    """a batch of matrices; (status, image) per sequence"""
+    import torch
+    from gpu_util import to_device
+    dev = [to_device(S) for S, _ in seqs]
+    outs, descs = [], []
+    for (S, sigma), St in zip(seqs, dev):
+        info = B.plan(B.KIND_WM, S.size, sigma, S.itemsize)
+        out = torch.empty(info.out_bytes, dtype=torch.uint8, device="cuda")
+        d = B.wt_seq_desc()
+        d.S, d.n, d.sigma, d.sym_bytes = St.data_ptr(), S.size, sigma, S.itemsize
+        d.out, d.out_bytes = out.data_ptr(), info.out_bytes
+        outs.append(out)
+        descs.append(d)
+    ws = torch.empty(max(B.batch_plan(B.KIND_WM, descs), 1), dtype=torch.uint8, device="cuda")
+    assert B.batch_build(B.KIND_WM, descs, ws) == B.WT_OK
+    torch.cuda.synchronize()
+    return [(B.check(o), o.cpu().numpy()) for o in outs]
