@@ -154,3 +154,46 @@ def test_random_mix_same_as_alone(seed, mode):
     for b, r in qreqs:
         for g, w in zip(r.result, want_q[b]):
             assert np.array_equal(g.cpu().numpy(), w), f"query batch {b}"
+
+
+@pytest.mark.parametrize("seed", range(int(os.environ.get("WV_RANDOM_EVICT", "4"))))
+@pytest.mark.parametrize("mode", ["continuous", "plain"])
+def test_random_mix_under_a_small_budget(seed, mode):
+    """budgets of one to four images: structures are evicted and rebuilt
+    while queries run; a query either finds its structure (results as alone)
+    or reports WT_EINVAL, resident images are as alone, usage stays within
+    the budget"""
+    import torch
+    rng = np.random.default_rng(777777 + seed)
+    host = pool(int(rng.integers(6, 30)), seed=5000 + seed)
+    sizes = [B.plan(B.KIND_WM, S.size, sigma, 4).out_bytes for S, sigma in host]
+    budget = int(max(sizes) * rng.uniform(1.0, 4.0)) + 4096
+    batches = [(t, serve.make_query_batch(host[t][0], int(rng.integers(1, 2000)), rng)) for t in range(len(host))]
+    want_imgs, want_q = alone(host, batches)
+    dev = [(to_device(S), sigma) for S, sigma in host]
+    srv = serve.WaveletServer(dev, hbm_budget=budget, ws_bytes=1 << 28, mode=mode)
+    srv.start()
+    qreqs = []
+    for _ in range(2):
+        for i in rng.permutation(len(host)):
+            srv.submit_build(int(i))
+            if rng.random() < 0.3:
+                time.sleep(0.0005)
+            for b in range(len(batches)):
+                if rng.random() < 0.1 and srv.is_resident(batches[b][0]):
+                    qreqs.append((b, srv.submit_query(batches[b][0], batches[b][1])))
+    deadline = time.time() + 60
+    while any(not r.done for r in srv.all_reqs) and time.time() < deadline:
+        time.sleep(0.002)
+    srv.close()
+    torch.cuda.synchronize()
+    assert all(r.done for r in srv.all_reqs)
+    assert srv.used <= budget
+    for b, r in qreqs:
+        if r.error == B.WT_EINVAL:
+            continue
+        assert r.error == 0
+        for g, w in zip(r.result, want_q[b]):
+            assert np.array_equal(g.cpu().numpy(), w), f"query batch {b}"
+    for i, st in list(srv.resident.items()):
+        assert np.array_equal(st.image.cpu().numpy(), want_imgs[i]), f"image {i}"
