@@ -131,3 +131,66 @@ def test_misaligned_buffers_are_rejected_before_device_work():
     with pytest.raises(B.WaveletError) as e:
         B.batch_plan(B.KIND_WM, [d])
     assert e.value.code == B.WT_EINVAL
+
+
+def expected_shape_verdict(codes, lens, counts, n):
+    """the plan's verdict on a codeword set, from its stated rules: per
+    symbol in order, a code longer than 32 bits is unsupported, a code with
+    bits above its length is invalid, a symbol that occurs without a code is
+    out of range; then the lengths must not all be 0 and the counts must add
+    up to n; then no codeword may be a prefix of another (checked here pair by
+    pair)"""
+    for c, l, k in zip(codes, lens, counts):
+        if l > 32:
+            return B.WT_EUNSUP
+        if l and (c >> l):
+            return B.WT_EINVAL
+        if k and not l:
+            return B.WT_ERANGE
+    if max(lens) == 0 or sum(counts) != n:
+        return B.WT_EINVAL
+    coded = [(c, l) for c, l in zip(codes, lens) if l]
+    for i in range(len(coded)):
+        for j in range(len(coded)):
+            (ci, li), (cj, lj) = coded[i], coded[j]
+            if i != j and li <= lj and (cj >> (lj - li)) == ci:
+                return B.WT_EINVAL
+    return B.WT_OK
+
+
+@pytest.mark.parametrize("seed", range(400))
+def test_plan_verdict_on_random_codeword_sets(seed):
+    rng = np.random.default_rng(424242 + seed)
+    sigma = int(rng.integers(1, 40))
+    if rng.random() < 0.5:   # a valid Huffman code, perturbed
+        counts = rng.integers(0, 20, sigma)
+        counts[rng.integers(0, sigma)] += 1
+        codes, lens = B.huffman_codes(counts)
+        codes, lens = [int(c) for c in codes], [int(l) for l in lens]
+        for _ in range(int(rng.integers(0, 3))):
+            s = int(rng.integers(0, sigma))
+            what = int(rng.integers(0, 4))
+            if what == 0:
+                lens[s] = int(rng.integers(0, 36))
+            elif what == 1:
+                codes[s] = int(rng.integers(0, 1 << 12))
+            elif what == 2:
+                counts[s] = int(rng.integers(0, 5))
+            else:
+                codes[s] ^= 1
+        counts = [int(k) for k in counts]
+    else:                    # arbitrary codewords
+        lens = [int(rng.integers(0, 8)) if rng.random() < 0.95 else int(rng.integers(30, 36)) for _ in range(sigma)]
+        codes = [int(rng.integers(0, 1 << max(l, 1))) if rng.random() < 0.9 else int(rng.integers(0, 1 << 10))
+                 for l in lens]
+        counts = [int(rng.integers(0, 4)) for _ in range(sigma)]
+    n = sum(counts) + (int(rng.integers(-1, 2)) if rng.random() < 0.1 else 0)
+    n = max(n, 0)
+    want = expected_shape_verdict(codes, lens, counts, n)
+    shape = B.make_shape(0, np.array(codes, dtype=np.uint64), np.array(lens), np.array(counts))
+    try:
+        B.plan(B.KIND_SHAPED, n, sigma, 1, shape)
+        got = B.WT_OK
+    except B.WaveletError as e:
+        got = e.code
+    assert got == want, (sigma, codes, lens, counts, n)
