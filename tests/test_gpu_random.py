@@ -9,7 +9,9 @@ against the oracle and queried against brute force.  WV_RANDOM_DRAWS,
 WV_RANDOM_BATCHES, WV_RANDOM_LARGE and WV_RANDOM_BOUNDARY set how many (48,
 8, 2 and 16 by default); WV_RANDOM_LEVELWISE draws (8 by default) go through
 the level-by-level builder; WV_RANDOM_RANGE draws (12 by default) plant one
-symbol >= sigma, which every kind and the batch must report."""
+symbol >= sigma, which every kind and the batch must report; WV_RANDOM_CODES
+draws (8 by default) build shaped trees from random prefix-free codes (random
+code trees up to 32 bits, not always full) and query them."""
 import os
 
 import numpy as np
@@ -207,3 +209,45 @@ def run_batch_status(seqs):
     assert B.batch_build(B.KIND_WM, descs, ws) == B.WT_OK
     torch.cuda.synchronize()
     return [(B.check(o), o.cpu().numpy()) for o in outs]
+
+
+def random_code_tree(rng, sigma, maxlen):
+    """codewords of a random binary code tree (leaves split at random, often
+    along one deep path), some dropped so that the code need not be full,
+    given to a random subset of the symbols"""
+    leaves = [(0, 0)]
+    deep = rng.random() < 0.5
+    while len(leaves) < sigma:
+        cand = [k for k, (c, l) in enumerate(leaves) if l < maxlen]
+        if not cand:
+            break
+        k = cand[-1] if deep and rng.random() < 0.7 else int(rng.choice(cand))
+        c, l = leaves.pop(k)
+        leaves += [(2 * c, l + 1), (2 * c + 1, l + 1)]
+    rng.shuffle(leaves)
+    if rng.random() < 0.3 and len(leaves) > 2:
+        leaves = leaves[: int(rng.integers(1, len(leaves)))]
+    codes = np.zeros(sigma, np.uint64)
+    lens = np.zeros(sigma, np.uint32)
+    for s_, (c, l) in zip(rng.permutation(sigma)[: len(leaves)], leaves):
+        codes[s_], lens[s_] = c, l
+    return codes, lens
+
+
+@pytest.mark.parametrize("seed", range(int(os.environ.get("WV_RANDOM_CODES", "8"))))
+def test_shaped_tree_from_random_prefix_free_code(seed):
+    from gpu_util import to_device
+    from test_gpu_queries import run_queries
+    rng = np.random.default_rng(909000 + seed)
+    sigma = int(rng.integers(2, 600))
+    codes, lens = random_code_tree(rng, sigma, int(rng.choice([8, 16, 24, 32])))
+    if lens.max() == 0:
+        pytest.skip("no codeword of positive length")
+    counts = np.where(lens > 0, rng.integers(0, 400, sigma) * (rng.random(sigma) < 0.8), 0).astype(np.uint64)
+    if counts.sum() == 0:
+        counts[int(np.flatnonzero(lens)[0])] = 1
+    S = rng.permutation(np.repeat(np.arange(sigma), counts.astype(np.int64))).astype(np.uint16)
+    img, _ = B.build(B.KIND_SHAPED, to_device(S), sigma, codes=codes, code_len=lens, counts=counts)
+    assert_same(img.cpu().numpy(), oracle_image(B.KIND_SHAPED, S, sigma, codes=codes, lens=lens),
+                f"seed={seed} sigma={sigma} n={S.size} h={int(lens.max())}")
+    run_queries(img, S, sigma, rng)
