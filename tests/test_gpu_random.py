@@ -11,7 +11,9 @@ WV_RANDOM_BATCHES, WV_RANDOM_LARGE and WV_RANDOM_BOUNDARY set how many (48,
 the level-by-level builder; WV_RANDOM_RANGE draws (12 by default) plant one
 symbol >= sigma, which every kind and the batch must report; WV_RANDOM_CODES
 draws (8 by default) build shaped trees from random prefix-free codes (random
-code trees up to 32 bits, not always full) and query them."""
+code trees up to 32 bits, not always full) and query them; WV_RANDOM_THREADS
+(6 by default) draws per thread are built by four host threads at once, each
+on its own stream."""
 import os
 
 import numpy as np
@@ -251,3 +253,48 @@ def test_shaped_tree_from_random_prefix_free_code(seed):
     assert_same(img.cpu().numpy(), oracle_image(B.KIND_SHAPED, S, sigma, codes=codes, lens=lens),
                 f"seed={seed} sigma={sigma} n={S.size} h={int(lens.max())}")
     run_queries(img, S, sigma, rng)
+
+
+def test_concurrent_builds_from_several_threads():
+    """the library's shared host state (pinned buffer pool, side stream,
+    profile records) under builds of every kind from four threads, each on
+    its own stream"""
+    import threading
+    import torch
+    from gpu_util import to_device
+    rounds = int(os.environ.get("WV_RANDOM_THREADS", "6"))
+    results, errors = [], []
+
+    def worker(tid):
+        try:
+            st = torch.cuda.Stream()
+            for r in range(rounds):
+                rng = np.random.default_rng(31337 * (tid + 1) + r)
+                kind, S, sigma, tau, blocks, D = draw(rng)
+                if S.size == 0 and kind == B.KIND_SHAPED:
+                    continue
+                tune = B.make_tuning(tau=tau, blocks=blocks)
+                with torch.cuda.stream(st):
+                    St = to_device(S)
+                    if kind == B.KIND_SHAPED:
+                        (gc, gl), (oc, ol) = shaped_codes(S, sigma)
+                        counts = B.symbol_counts(St, sigma, stream=st).cpu().numpy().astype(np.uint64)
+                        img, _ = B.build(kind, St, sigma, codes=gc, code_len=gl, counts=counts, tune=tune, stream=st)
+                        want = (kind, S, sigma, 0, oc, ol)
+                    else:
+                        img, _ = B.build(kind, St, sigma, arity_log2=D, tune=tune, stream=st)
+                        want = (kind, S, sigma, D, None, None)
+                    st.synchronize()
+                    results.append((img.cpu().numpy(), want, f"thread {tid} round {r} kind={kind} n={S.size}"))
+        except Exception as e:   # reported after the join
+            errors.append(repr(e))
+
+    threads = [threading.Thread(target=worker, args=(t,)) for t in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    for g, (kind, S, sigma, D, oc, ol), what in results:
+        o = oracle_image(kind, S, sigma, codes=oc, lens=ol) if kind == B.KIND_SHAPED else oracle_image(kind, S, sigma, D)
+        assert_same(g, o, what)
