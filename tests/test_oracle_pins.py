@@ -321,13 +321,12 @@ def test_huffman_tie_rule_small():
     assert codes.tolist() == [0b10, 0b1110, 0b1111, 0b110, 0, 0b0]
 
 
-@pytest.mark.parametrize("seed", range(6))
-def test_shaped_closed_form_and_nodes(seed):
-    rng = np.random.default_rng(50 + seed)
-    sigma = [3, 17, 100, 4096, 2, 64][seed]
-    n = [1, 200, 2000, 5000, 64, 777][seed]
-    S = np.minimum(rng.geometric(0.05, n) - 1, sigma - 1).astype(np.uint16)
-    codes, lens = oracle.huffman(oracle.symbol_counts(S, sigma))
+def check_shaped(S, sigma, codes, lens, queries_upto=300):
+    """Every level, node record and code-table entry of a shaped image against
+    closed forms from the codewords (Sec. 4.3, arbitrarily-shaped trees):
+    level l holds bit l of the codewords longer than l, stably sorted by their
+    l-bit prefix; a node (l, P) starts after the level-l symbols whose prefix is
+    smaller than P, whether or not any symbol under P occurs in S."""
     img = Image(oracle.build_image(KIND_SHAPED, S, sigma, codes=codes, lens=lens))
     h = int(lens.max())
     assert img.nlevels == h == img.key_bits
@@ -351,13 +350,15 @@ def test_shaped_closed_form_and_nodes(seed):
     assert [(nd["level"], nd["prefix"]) for nd in nodes] == keys
     keyset = set(keys)
     leaves = {(int(l64[s]), int(c64[s])): int(s) for s in np.flatnonzero(lens)}
+    empty = 0
     for nd in nodes:
         l, p = nd["level"], nd["prefix"]
         sel = ls > l
         pre = (cs >> np.maximum(ls - l, 0)) if l else np.zeros_like(cs)
         members = sel & (pre == p)
         assert nd["count"] == int(members.sum())
-        assert nd["start"] == int((sel & (pre < p)).sum())
+        assert nd["start"] == int((sel & (pre < p)).sum()), (l, p)
+        empty += nd["count"] == 0
         for b in (0, 1):
             ch = nd["child"][b]
             q = 2 * p + b
@@ -368,10 +369,83 @@ def test_shaped_closed_form_and_nodes(seed):
             else:
                 assert ch == 0xFFFFFFFF
     # queries walked through the image on a prefix of S (brute force is O(n))
-    m = min(n, 300)
-    sub = S[:m]
-    img2 = Image(oracle.build_image(KIND_SHAPED, sub, sigma, codes=codes, lens=lens))
-    check_queries(img2, sub, sigma, all_symbols=False)
+    m = min(S.size, queries_upto)
+    if m:
+        sub = S[:m]
+        img2 = Image(oracle.build_image(KIND_SHAPED, sub, sigma, codes=codes, lens=lens))
+        check_queries(img2, sub, sigma, all_symbols=sigma <= 64)
+    return empty
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_shaped_closed_form_and_nodes(seed):
+    rng = np.random.default_rng(50 + seed)
+    sigma = [3, 17, 100, 4096, 2, 64][seed]
+    n = [1, 200, 2000, 5000, 64, 777][seed]
+    S = np.minimum(rng.geometric(0.05, n) - 1, sigma - 1).astype(np.uint16)
+    codes, lens = oracle.huffman(oracle.symbol_counts(S, sigma))
+    check_shaped(S, sigma, codes, lens)
+
+
+def _code_prefix(codes, lens, s, l):
+    return int(codes[s]) >> (int(lens[s]) - l) if l else 0
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_shaped_empty_nodes(seed):
+    """Codewords given to symbols that never occur in S make empty nodes,
+    and a whole absent subtree makes a chain of them; their start offsets
+    (and every other record) must follow the closed form."""
+    rng = np.random.default_rng(900 + seed)
+    sigma = [5, 9, 16, 33, 100, 257, 4096, 12][seed]
+    # every symbol gets a codeword (Huffman over counts + 1) ...
+    w = rng.integers(1, 50, sigma).astype(np.uint64)
+    codes, lens = oracle.huffman(w)
+    assert (lens > 0).all()
+    # ... but the symbols under one internal prefix, plus a few others, never
+    # occur in S (full code, absent subtree and absent leaves)
+    coded = np.flatnonzero(lens)
+    s0 = int(rng.choice(coded))
+    l0 = int(rng.integers(1, max(2, int(lens[s0]))))
+    l0 = min(l0, int(lens[s0]) - 1) if lens[s0] > 1 else 0
+    p0 = _code_prefix(codes, lens, s0, l0)
+    absent = {int(s) for s in coded if lens[s] > l0 and _code_prefix(codes, lens, s, l0) == p0}
+    absent |= {int(s) for s in rng.choice(coded, size=max(1, sigma // 5), replace=False)}
+    present = np.array(sorted(set(range(sigma)) - absent), dtype=np.int64)
+    if present.size == 0:
+        present = np.array([int(coded[0])])
+    n = int(rng.integers(1, 3000))
+    S = present[rng.integers(0, present.size, n)].astype(np.uint16)
+    empty = check_shaped(S, sigma, codes, lens)
+    assert empty > 0
+
+
+@pytest.mark.parametrize("variant", range(4))
+def test_shaped_empty_nodes_incomplete_code(variant):
+    """Empty nodes under a prefix code that is not full: unary-like codes with
+    the deepest or a middle codeword's symbol absent."""
+    sigma = 6
+    # 0 -> 0, 1 -> 10, 2 -> 110, 3 -> 1110, 4 -> 11110, 5 -> 111110 (1111111 unused)
+    lens = np.arange(1, sigma + 1, dtype=np.uint32)
+    codes = np.array([(1 << int(l)) - 2 for l in lens], dtype=np.uint64)
+    rng = np.random.default_rng(77 + variant)
+    absent = [{5}, {4, 5}, {0, 5}, {1, 2, 3, 4, 5}][variant]
+    present = np.array([s for s in range(sigma) if s not in absent])
+    S = present[rng.integers(0, present.size, 40)].astype(np.uint8)
+    empty = check_shaped(S, sigma, codes, lens)
+    assert empty > 0
+
+
+def test_exhaustive_tiny_queries_absent_codewords():
+    """Brute force on every tiny input, with a codeword for every symbol of
+    the alphabet whether or not it occurs (so most inputs have empty nodes)."""
+    for sigma, S in tiny_cases():
+        if S.size == 0 or sigma < 2:
+            continue
+        codes, lens = oracle.huffman(np.arange(1, sigma + 1, dtype=np.uint64))
+        img = Image(oracle.build_image(KIND_SHAPED, S, sigma, codes=codes, lens=lens))
+        assert img.n == S.size and img.status == 0
+        check_queries(img, S, sigma)
 
 
 def test_shaped_incomplete_code():
