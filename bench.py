@@ -72,7 +72,7 @@ def cpu_baseline_wm(S_dev, sigma, target_s=15.0):
         dt = time.perf_counter() - t
     return {"value": round(n_s * 4 / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"first {n_s} symbols of the same input, full wavelet matrix with directories, "
-                      f"{dt:.1f} s single-threaded"}
+                      f"{dt:.1f} s single-threaded", **host_cpu()}
 
 
 def device_copy_gbps(reps=10):
@@ -128,24 +128,55 @@ def cpu_baseline_oracle(kind, S, sigma, D=0, codes=None, lens=None, target_s=10.
             break
         n_s = int(min(S.size, n_s * max(2.0, target_s / max(dt, 1e-3))))
     return {"value": round(n_s * S.itemsize / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n_s} symbols of the same input, {dt:.1f} s single-threaded"}
+            "sample": f"first {n_s} symbols of the same input, {dt:.1f} s single-threaded", **host_cpu()}
 
 
 def pass_alg_bytes(info, n, sym_bytes):
-    """compulsory bytes of every launch of the partition pass kernel: read its
-    input sequence once (S, then the compacted remaining keys), write its
-    levels' bits once and, except for the last pass, the remaining keys"""
+    """algorithmic (compulsory) bytes of every launch of the partition pass
+    kernel: the first pass reads S once, and every pass writes the bits of its
+    levels once.  The compacted remaining keys one pass writes and the next
+    reads are intermediate traffic: they appear in the measured traffic (and
+    so in the amplification), never here."""
     L, tau = info.nlevels, info.tau
-    width = lambda bits: 1 if bits <= 8 else (2 if bits <= 16 else 4)
     per = []
-    in_w = sym_bytes
     for l0 in range(0, L, tau):
         t = min(tau, L - l0)
-        rem = L - l0 - t
-        out_w = width(rem) if rem else 0
-        per.append(n * in_w + t * ((n + 63) // 64) * 8 + n * out_w)
-        in_w = out_w
+        per.append((n * sym_bytes if l0 == 0 else 0) + t * ((n + 63) // 64) * 8)
     return per
+
+
+def pass_payload_bytes(info, n):
+    """bytes of compacted remaining keys the passes write and read back (not
+    algorithmic; reported beside the roofline only)"""
+    L, tau = info.nlevels, info.tau
+    width = lambda bits: 1 if bits <= 8 else (2 if bits <= 16 else 4)
+    total = 0
+    for l0 in range(0, L, tau):
+        rem = L - l0 - min(tau, L - l0)
+        if rem:
+            total += 2 * n * width(rem)
+    return total
+
+
+def host_cpu():
+    """the host CPU model (lscpu / cpuinfo), the cores this process may run on
+    and the worker threads a pool uses here (the CPU share the box gives one
+    GPU caps it: OMP_NUM_THREADS)"""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count() or 1
+    share = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    return {"cpu_model": model, "nproc": nproc, "pool_threads": min(nproc, share) if share > 0 else nproc}
 
 
 # the sources the pass kernel is compiled from
@@ -255,6 +286,7 @@ def main():
     per_launch_ms = pass_ms / launches
     alg_per_launch = sum(pass_alg_bytes(info, n, 4)) / info_passes(info)
     achieved = alg_per_launch / (per_launch_ms / 1e3) / 1e9
+    payload_per_launch = pass_payload_bytes(info, n) / info_passes(info)
     balg = algorithmic_bytes(info, n, 4)
     traffic = traffic_from_profile()
     line = {
@@ -277,7 +309,9 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "wm_pass", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": traffic, "alg_bytes_per_launch": int(alg_per_launch),
+                     "alg_bytes_rule": "first pass reads S once; every pass writes its levels' bits once",
                      "amplification": round(traffic / alg_per_launch, 3) if traffic else None,
+                     "payload_bytes_per_launch": int(payload_per_launch),
                      "avg_launch_ms": round(per_launch_ms, 4),
                      "frac_of_device_copy": round(achieved / copy_gbps, 4)},
         "build_roofline": {"alg_bytes": balg, "achieved": round(balg / t / 1e9, 2),
@@ -342,32 +376,32 @@ def tree_kernel_bytes(name, info, sym_bytes, kind):
     D = int(info.arity_log2) if kind == 4 else 1
     key_w = 4 if kind == 3 else sym_bytes
     tree_bits = sum(int(info.level_n[l]) * D for l in range(info.nlevels))
-    width = lambda bits: 1 if bits <= 8 else (2 if bits <= 16 else 4)
     # the matrix whose passes are timed as "wm_pass" / "wm_hist": (symbols,
     # key bits, key width, pass width).  A shaped tree split at h1 bits builds
     # it over the top h1 code bits of every symbol (16-bit keys); its second
     # matrix, over the whole codes of the long-code symbols, runs on a side
     # stream and is timed as one entry ("side_matrix")
-    h1, nlong = int(info.split_bits), int(info.split_long)
+    h1 = int(info.split_bits)
     mats = [(n, h1, 2, int(info.tau))] if h1 else [(n, K, key_w, int(info.tau))]
     if name == "wm_pass":
+        # the same rule as the matrix build: the first pass reads its keys
+        # once and every pass writes its levels' bits once (the matrix levels
+        # carry exactly the tree's bits, in another order of runs); the
+        # compacted keys between passes are intermediate
         total = 0
         for m, L, in_w, tau in mats:
             for l0 in range(0, L, tau):
                 t = min(tau, L - l0)
-                rem = L - l0 - t
-                out_w = width(rem) if rem else 0
-                total += m * in_w + t * ((m + 63) // 64) * 8 + m * out_w
-                in_w = out_w
+                total += (m * in_w if l0 == 0 else 0) + t * ((m + 63) // 64) * 8
         return total
-    if name == "wm_hist":
-        return sum(m * (w if l0 == 0 else width(L - l0)) for m, L, w, tau in mats for l0 in range(0, L, tau))
-    if name == "tree_perm":          # read the matrix runs, write the tree levels
-        return 2 * tree_bits // 8
-    if name == "tree_digits":        # read D matrix levels, write one digit level, per digit level
-        return info.nlevels * 2 * (n * D // 8)
-    if name == "tree_keys":          # read S, write the padded codes (split: read S twice, write 16-bit keys)
-        return n * (2 * sym_bytes + 2) + nlong * 4 if h1 else n * (sym_bytes + 4)
+    if name == "wm_hist":            # histograms read S (first pass) once
+        return sum(m * w for m, L, w, tau in mats)
+    if name == "tree_perm":          # write the tree levels once (reading the matrix runs is intermediate)
+        return tree_bits // 8
+    if name == "tree_digits":        # write one digit level per digit level (its matrix reads are intermediate)
+        return info.nlevels * (n * D // 8)
+    if name == "tree_keys":          # read S once (the codes it writes are intermediate)
+        return n * sym_bytes
     return None
 
 
@@ -512,29 +546,35 @@ def bench_batch(args):
             if rc != 0:
                 raise RuntimeError(B.strerror(rc))
 
-    res = {}
+    res, spread = {}, {}
+    reps = max(5, args.steps // 4)
     for name, fn in (("batched", batched), ("plain", plain), ("plain_4_streams", plain4)):
         fn()
         torch.cuda.synchronize()
-        reps = max(1, args.steps // 5)
-        t0 = time.perf_counter()
+        each = []
         for _ in range(reps):
+            t0 = time.perf_counter()
             fn()
-        torch.cuda.synchronize()
-        res[name] = (time.perf_counter() - t0) / reps
+            torch.cuda.synchronize()
+            each.append(time.perf_counter() - t0)
+        res[name] = float(np.median(each))
+        spread[name] = [round(float(v), 4) for v in np.percentile(each, [10, 90])]
     balg = sum(4 * int(ns[i]) + infos[i].out_bytes for i in range(k))
     tb, tp, t4 = res["batched"], res["plain"], res["plain_4_streams"]
     line = {
         "metric": METRIC, "value": round(total * 4 / tb / 1e9, 3), "unit": "GB/s", "n_gpus": 1,
-        "steps": max(1, args.steps // 5), "warmup": 1, "ms_per_step": round(tb * 1e3, 3), "higher_is_better": True,
+        "steps": reps, "warmup": 1, "ms_per_step": round(tb * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"C4 batched wavelet matrices: {k} uint32 sequences, n log-uniform [2^10, 2^22], "
                                f"sigma log-uniform [4, 2^20]", "symbols": total},
-        "batched": {"s": round(tb, 4), "builds_per_s": round(k / tb, 1), "input_GBps": round(total * 4 / tb / 1e9, 2),
+        "batched": {"s": round(tb, 4), "p10_p90_s": spread["batched"], "builds_per_s": round(k / tb, 1),
+                    "input_GBps": round(total * 4 / tb / 1e9, 2),
                     "build_roofline_frac": round(balg / tb / 1e9 / HBM_PEAK_GBPS, 4)},
-        "plain": {"s": round(tp, 4), "builds_per_s": round(k / tp, 1), "input_GBps": round(total * 4 / tp / 1e9, 2)},
-        "plain_4_streams": {"s": round(t4, 4), "builds_per_s": round(k / t4, 1),
-                            "input_GBps": round(total * 4 / t4 / 1e9, 2)},
+        "plain": {"s": round(tp, 4), "p10_p90_s": spread["plain"], "builds_per_s": round(k / tp, 1),
+                  "input_GBps": round(total * 4 / tp / 1e9, 2)},
+        "plain_4_streams": {"s": round(t4, 4), "p10_p90_s": spread["plain_4_streams"],
+                            "builds_per_s": round(k / t4, 1), "input_GBps": round(total * 4 / t4 / 1e9, 2)},
+        "timing": f"median of {reps} timed repetitions of each form after one untimed one",
         "speedup_batched_vs_plain": round(tp / tb, 3),
         "speedup_batched_vs_plain_4_streams": round(t4 / tb, 3),
         "input_generation_s": round(t_gen, 1),
@@ -544,13 +584,16 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline_batch(ns, sig, children, target_s=10.0, threads=16):
+def cpu_baseline_batch(ns, sig, children, target_s=10.0):
     """the oracle over the first C4 sequences on a pool of host threads (one
     sequence per task; the C library releases the interpreter while it runs),
-    and single-threaded on the same sample; GB/s of input"""
+    one per core this process may use up to the machine's CPU share, and
+    single-threaded on the same sample; GB/s of input"""
     import concurrent.futures as cf
     import oracle
     from paper_1610_03524_amd import inputs
+    cpu = host_cpu()
+    threads = cpu["pool_threads"]
     seqs, total = [], 0
     for i in range(len(ns)):
         seqs.append((inputs.c4_sequence(int(ns[i]), int(sig[i]), children[i]), int(sig[i])))
@@ -569,7 +612,7 @@ def cpu_baseline_batch(ns, sig, children, target_s=10.0, threads=16):
     return {"value": round(nbytes / tp / 1e9, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
             "single_thread_GBps": round(nbytes / t1 / 1e9, 4),
             "sample": f"first {len(seqs)} C4 sequences ({nbytes // 4} symbols): {tp:.1f} s on {threads} "
-                      f"threads, {t1:.1f} s on one"}
+                      f"threads, {t1:.1f} s on one", **cpu}
 
 
 

@@ -119,6 +119,48 @@ def _ptr(t):
     return t.data_ptr()
 
 
+# element types the header declares for every device argument (signedness is
+# not checked: tests and callers view unsigned data through torch's signed
+# types of the same width)
+_SYM_DTYPES = ("uint8", "int8", "int16", "uint16", "int32", "uint32")
+_U64 = ("int64", "uint64")
+_U32 = ("int32", "uint32")
+_U8 = ("uint8", "int8")
+
+
+def _arg(t, name: str, dtypes, what: str):
+    """Reject, before any pointer reaches the library, an argument that is not a
+    contiguous device tensor of one of the element types the header declares
+    (a host array or a strided view would be read as device memory of another
+    shape).  Raises WaveletError(WT_EINVAL)."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise WaveletError(WT_EINVAL, f"{what}: {name} must be a torch tensor, got {type(t).__name__}")
+    dt = str(t.dtype).replace("torch.", "")
+    if dt not in dtypes:
+        raise WaveletError(WT_EINVAL, f"{what}: {name} has dtype {dt}, expected one of {', '.join(dtypes)}")
+    if not t.is_contiguous():
+        raise WaveletError(WT_EINVAL, f"{what}: {name} must be contiguous")
+    return t
+
+
+def _same_len(what: str, **named):
+    sizes = {k: v.numel() for k, v in named.items()}
+    if len(set(sizes.values())) > 1:
+        raise WaveletError(WT_EINVAL, f"{what}: lengths differ: {sizes}")
+
+
+def _on_device(what: str, *ts):
+    """every tensor in device memory, all on one device (checked after the
+    element types and lengths)"""
+    for t in ts:
+        if t.device.type != "cuda":
+            raise WaveletError(WT_EINVAL, f"{what}: arguments must be device tensors, got {t.device}")
+    devs = {str(t.device) for t in ts}
+    if len(devs) > 1:
+        raise WaveletError(WT_EINVAL, f"{what}: arguments on different devices: {sorted(devs)}")
+
+
 def _stream(stream):
     import torch
     if stream is None:
@@ -167,6 +209,10 @@ def _build_fn(kind: int):
 
 def build_into(kind: int, S, sigma: int, out, ws, shape=None, tune=None, stream=None) -> int:
     """Call wt_build / wm_build / multiary_build on caller-owned buffers."""
+    _arg(S, "S", _SYM_DTYPES, "build")
+    _arg(out, "out", _U8, "build")
+    _arg(ws, "ws", _U8, "build")
+    _on_device("build", S, out, ws)
     fn = _build_fn(kind)
     return fn(_ptr(S), S.numel(), sigma, _sym_bytes(S), ctypes.byref(shape) if shape else None,
               ctypes.byref(tune) if tune else None, _ptr(out), out.numel(), _ptr(ws), ws.numel(),
@@ -186,11 +232,16 @@ def build(kind: int, S, sigma: int, arity_log2: int = 0, codes=None, code_len=No
 
 
 def check(image, stream=None) -> int:
+    _arg(image, "image", _U8, "wt_check")
+    _on_device("wt_check", image)
     return lib().wt_check(_ptr(image), _stream(stream))
 
 
 def access(image, pos, stream=None):
     import torch
+    _arg(image, "image", _U8, "wt_access")
+    _arg(pos, "pos", _U64, "wt_access")
+    _on_device("wt_access", image, pos)
     res = torch.empty(pos.numel(), dtype=torch.int32, device=pos.device)
     _check(lib().wt_access(_ptr(image), _ptr(pos), _ptr(res), pos.numel(), _stream(stream)), "wt_access")
     return res
@@ -198,6 +249,11 @@ def access(image, pos, stream=None):
 
 def rank(image, c, i, stream=None):
     import torch
+    _arg(image, "image", _U8, "wt_rank")
+    _arg(c, "c", _U32, "wt_rank")
+    _arg(i, "i", _U64, "wt_rank")
+    _same_len("wt_rank", c=c, i=i)
+    _on_device("wt_rank", image, c, i)
     res = torch.empty(i.numel(), dtype=torch.int64, device=i.device)
     _check(lib().wt_rank(_ptr(image), _ptr(c), _ptr(i), _ptr(res), i.numel(), _stream(stream)), "wt_rank")
     return res
@@ -205,6 +261,11 @@ def rank(image, c, i, stream=None):
 
 def select(image, c, k, stream=None):
     import torch
+    _arg(image, "image", _U8, "wt_select")
+    _arg(c, "c", _U32, "wt_select")
+    _arg(k, "k", _U64, "wt_select")
+    _same_len("wt_select", c=c, k=k)
+    _on_device("wt_select", image, c, k)
     res = torch.empty(k.numel(), dtype=torch.int64, device=k.device)
     _check(lib().wt_select(_ptr(image), _ptr(c), _ptr(k), _ptr(res), k.numel(), _stream(stream)), "wt_select")
     return res
@@ -212,6 +273,8 @@ def select(image, c, k, stream=None):
 
 def symbol_counts(S, sigma: int, stream=None):
     import torch
+    _arg(S, "S", _SYM_DTYPES, "wt_symbol_counts")
+    _on_device("wt_symbol_counts", S)
     counts = torch.empty(sigma, dtype=torch.int64, device=S.device)
     _check(lib().wt_symbol_counts(_ptr(S), S.numel(), _sym_bytes(S), sigma, _ptr(counts), _stream(stream)),
            "wt_symbol_counts")
@@ -228,6 +291,8 @@ def huffman_codes(counts: np.ndarray):
 
 
 def image_bytes(image, stream=None) -> int:
+    _arg(image, "image", _U8, "wt_image_bytes")
+    _on_device("wt_image_bytes", image)
     b = ctypes.c_uint64(0)
     _check(lib().wt_image_bytes(_ptr(image), ctypes.byref(b), _stream(stream)), "wt_image_bytes")
     return b.value
@@ -239,6 +304,18 @@ def profile_read(cap: int = 64) -> dict:
     cnt = ctypes.c_uint32(0)
     _check(lib().wt_profile_read(arr, cap, ctypes.byref(cnt)), "wt_profile_read")
     return {arr[i].name.decode(): (arr[i].launches, arr[i].ms) for i in range(min(cap, cnt.value))}
+
+
+def make_desc(S, sigma: int, out, tau: int = 0) -> wt_seq_desc:
+    """One batch descriptor over a device sequence and its image buffer,
+    checked like the arguments of a single build."""
+    _arg(S, "S", _SYM_DTYPES, "wt_seq_desc")
+    _arg(out, "out", _U8, "wt_seq_desc")
+    _on_device("wt_seq_desc", S, out)
+    d = wt_seq_desc()
+    d.S, d.n, d.sigma, d.sym_bytes = S.data_ptr(), S.numel(), sigma, S.element_size()
+    d.out, d.out_bytes, d.tau = out.data_ptr(), out.numel(), tau
+    return d
 
 
 def desc_array(descs):
@@ -258,6 +335,8 @@ def batch_plan(kind: int, descs, tune=None) -> int:
 
 
 def batch_build(kind: int, descs, ws, tune=None, stream=None) -> int:
+    _arg(ws, "ws", _U8, "wt_batch_build")
+    _on_device("wt_batch_build", ws)
     arr = desc_array(descs)
     return lib().wt_batch_build(kind, arr, len(descs), _ptr(ws), ws.numel(),
                                 ctypes.byref(tune) if tune else None, _stream(stream))

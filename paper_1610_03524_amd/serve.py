@@ -19,6 +19,12 @@ Every result is the same as when the request runs alone: a build writes the
 image wm_build writes, and a query reads an image that is complete before
 the query is launched (the query worker only sees structures whose build has
 finished).  Latency = completion time - arrival time.
+
+A request that cannot be served fails alone: its error code is set and the
+worker goes on.  A sequence the library refuses (bad sigma, too long) fails
+at admission with the plan's code; a built image whose status word reports a
+symbol >= sigma fails with WT_ERANGE and is not made resident; an exception
+while building or querying fails the requests it was serving.
 """
 from __future__ import annotations
 
@@ -73,7 +79,11 @@ class WaveletServer:
         self.ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
         self.resident: dict[int, Structure] = {}
         self.used = 0
-        self.lock = threading.Condition()
+        self.lock = threading.Lock()
+        # one condition per worker on the shared lock, so that a submitted
+        # build wakes only the build worker and a query only the query worker
+        self.build_cv = threading.Condition(self.lock)
+        self.query_cv = threading.Condition(self.lock) if mode == "continuous" else self.build_cv
         self.builds = collections.deque()
         self.queries = collections.deque()
         self.all_reqs: list[Request] = []
@@ -88,7 +98,7 @@ class WaveletServer:
             r = Request(len(self.all_reqs), "build", time.perf_counter(), seq=seq)
             self.all_reqs.append(r)
             (self.builds if self.mode == "continuous" else self.queries).append(r)
-            self.lock.notify_all()
+            self.build_cv.notify()
             return r
 
     def submit_query(self, target: int, args) -> Request:
@@ -98,7 +108,7 @@ class WaveletServer:
             r = Request(len(self.all_reqs), "query", time.perf_counter(), seq=target, qtype="mixed", args=args)
             self.all_reqs.append(r)
             self.queries.append(r)
-            self.lock.notify_all()
+            self.query_cv.notify()
             return r
 
     def is_resident(self, sid: int) -> bool:
@@ -127,7 +137,8 @@ class WaveletServer:
     def close(self):
         with self.lock:
             self.closing = True
-            self.lock.notify_all()
+            self.build_cv.notify_all()
+            self.query_cv.notify_all()
         for t in self.threads:
             t.join()
         sys.setswitchinterval(self._switch)
@@ -167,7 +178,12 @@ class WaveletServer:
         while self.builds and len(take) < self.max_batch:
             r = self.builds[0]
             S, sigma = self.seqs[r.seq]
-            ob, wsb = self._costs(r.seq)
+            try:
+                ob, wsb = self._costs(r.seq)
+            except B.WaveletError as e:
+                self.builds.popleft()
+                r.error, r.done = e.code, time.perf_counter()
+                continue
             if ob > self.budget:
                 self.builds.popleft()
                 r.error, r.done = B.WT_ENOSPC, time.perf_counter()
@@ -194,12 +210,39 @@ class WaveletServer:
             nbytes.append(ob)
         return take, descs, imgs, nbytes
 
-    def _build_loop(self):
+    def _statuses(self, imgs, rc):
+        """per-image status after a build call that returned rc: the call's
+        code if it failed, else WT_ERANGE for an image whose header status word
+        (what wt_check reads) reports a symbol >= sigma"""
+        if rc != B.WT_OK:
+            return [rc] * len(imgs)
+        if len(imgs) == 1:
+            return [B.check(imgs[0], stream=self.build_stream)]
         torch = self.torch
+        with torch.cuda.stream(self.build_stream):
+            words = torch.cat([img[36:40] for img in imgs]).view(torch.int32).cpu().numpy()
+        return [B.WT_OK if w == 0 else B.WT_ERANGE for w in words]
+
+    def _launch_builds(self, descs, imgs):
+        torch = self.torch
+        with torch.cuda.stream(self.build_stream):
+            if len(descs) == 1:
+                # a batch of one: the single-sequence build has less set-up
+                d = descs[0]
+                tn = B.make_tuning(tau=d.tau)
+                rc = B.lib().wm_build(d.S, d.n, d.sigma, d.sym_bytes, None, ctypes.byref(tn), d.out,
+                                      d.out_bytes, self.ws.data_ptr(), self.ws.numel(),
+                                      B._stream(self.build_stream))
+            else:
+                rc = B.batch_build(B.KIND_WM, descs, self.ws, stream=self.build_stream)
+            self.build_stream.synchronize()
+        return self._statuses(imgs, rc)
+
+    def _build_loop(self):
         while True:
             with self.lock:
                 while not self.builds and not self.closing:
-                    self.lock.wait()
+                    self.build_cv.wait()
                 if self.closing and not self.builds:
                     return
                 take, descs, imgs, nbytes = self._admit()
@@ -207,21 +250,14 @@ class WaveletServer:
             if not take:
                 time.sleep(0.0005)
                 continue
-            with torch.cuda.stream(self.build_stream):
-                if len(descs) == 1:
-                    # a batch of one: the single-sequence build has less set-up
-                    d = descs[0]
-                    tn = B.make_tuning(tau=d.tau)
-                    rc = B.lib().wm_build(d.S, d.n, d.sigma, d.sym_bytes, None, ctypes.byref(tn), d.out,
-                                          d.out_bytes, self.ws.data_ptr(), self.ws.numel(),
-                                          B._stream(self.build_stream))
-                    self.build_stream.synchronize()
-                else:
-                    rc = B.batch_build(B.KIND_WM, descs, self.ws, stream=self.build_stream)
+            try:
+                codes = self._launch_builds(descs, imgs)
+            except Exception as e:   # fail this batch, keep serving
+                codes = [getattr(e, "code", B.WT_EHIP)] * len(take)
             t = time.perf_counter()
             with self.lock:
                 self.batches.append(len(take))
-                for r, img, nb in zip(take, imgs, nbytes):
+                for r, img, nb, rc in zip(take, imgs, nbytes, codes):
                     r.done, r.error = t, rc
                     if rc == B.WT_OK:
                         old = self.resident.pop(r.seq, None)
@@ -230,7 +266,6 @@ class WaveletServer:
                         self.resident[r.seq] = Structure(img, nb, t)
                     else:
                         self.used -= nb
-                self.lock.notify_all()
 
     def _take_structure(self, r, stream):
         """(under the lock) the structure a query reads, or None.  The
@@ -250,66 +285,78 @@ class WaveletServer:
             r.result = (B.access(st.image, pos, stream=stream), B.rank(st.image, rc, ri, stream=stream),
                         B.select(st.image, sc, sk, stream=stream))
 
+    def _serve_query(self, r, st, stream):
+        if st is None:
+            r.error = B.WT_EINVAL
+            return
+        try:
+            self._run_query(r, st, stream)
+            stream.synchronize()
+        except Exception as e:   # fail this query, keep serving
+            r.result, r.error = None, getattr(e, "code", B.WT_EHIP)
+
     def _query_loop(self):
         while True:
             with self.lock:
                 while not self.queries and not self.closing:
-                    self.lock.wait()
+                    self.query_cv.wait()
                 if self.closing and not self.queries:
                     return
                 r = self.queries.popleft()
                 st = self._take_structure(r, self.query_stream)
-            if st is not None:
-                self._run_query(r, st, self.query_stream)
-                self.query_stream.synchronize()
-            else:
-                r.error = B.WT_EINVAL
+            self._serve_query(r, st, self.query_stream)
             r.done = time.perf_counter()
 
-    def _plain_loop(self):
+    def _plain_build(self, r):
         torch = self.torch
-        lib = B.lib()
+        S, sigma = self.seqs[r.seq]
+        try:
+            tn = B.make_tuning(tau=self.tau_of(S.numel(), sigma))
+            info = B.plan(B.KIND_WM, S.numel(), sigma, S.element_size(), tune=tn)
+        except B.WaveletError as e:
+            r.error, r.done = e.code, time.perf_counter()
+            return
+        ob = info.out_bytes
+        if ob > self.budget or self.ws.numel() < info.workspace_bytes:
+            r.error, r.done = B.WT_ENOSPC, time.perf_counter()
+            return
+        with self.lock:
+            self._evict_for(ob, keep=set())
+            self.used += ob
+        try:
+            with torch.cuda.stream(self.build_stream):
+                img = torch.empty(ob, dtype=torch.uint8, device="cuda")
+            rc = B.lib().wm_build(S.data_ptr(), S.numel(), sigma, S.element_size(), None,
+                                  ctypes.byref(tn), img.data_ptr(), ob, self.ws.data_ptr(),
+                                  self.ws.numel(), B._stream(self.build_stream))
+            self.build_stream.synchronize()
+            r.error = self._statuses([img], rc)[0]
+        except Exception as e:   # fail this build, keep serving
+            r.error = getattr(e, "code", B.WT_EHIP)
+        r.done = time.perf_counter()
+        with self.lock:
+            if r.error == B.WT_OK:
+                old = self.resident.pop(r.seq, None)
+                if old is not None:
+                    self.used -= old.nbytes
+                self.resident[r.seq] = Structure(img, ob, r.done)
+            else:
+                self.used -= ob
+
+    def _plain_loop(self):
         while True:
             with self.lock:
                 while not self.queries and not self.closing:
-                    self.lock.wait()
+                    self.build_cv.wait()
                 if self.closing and not self.queries:
                     return
                 r = self.queries.popleft()
             if r.kind == "build":
-                S, sigma = self.seqs[r.seq]
-                ob = self._image_bytes(r.seq)
-                with self.lock:
-                    self._evict_for(ob, keep=set())
-                    self.used += ob
-                with torch.cuda.stream(self.build_stream):
-                    img = torch.empty(ob, dtype=torch.uint8, device="cuda")
-                tn = B.make_tuning(tau=self.tau_of(S.numel(), sigma))
-                info = B.plan(B.KIND_WM, S.numel(), sigma, S.element_size(), tune=tn)
-                if self.ws.numel() < info.workspace_bytes:
-                    r.error = B.WT_ENOSPC
-                else:
-                    r.error = lib.wm_build(S.data_ptr(), S.numel(), sigma, S.element_size(), None,
-                                           ctypes.byref(tn), img.data_ptr(), ob, self.ws.data_ptr(),
-                                           self.ws.numel(), B._stream(self.build_stream))
-                self.build_stream.synchronize()
-                r.done = time.perf_counter()
-                with self.lock:
-                    if r.error == B.WT_OK:
-                        old = self.resident.pop(r.seq, None)
-                        if old is not None:
-                            self.used -= old.nbytes
-                        self.resident[r.seq] = Structure(img, ob, r.done)
-                    else:
-                        self.used -= ob
+                self._plain_build(r)
             else:
                 with self.lock:
                     st = self._take_structure(r, self.build_stream)
-                if st is not None:
-                    self._run_query(r, st, self.build_stream)
-                    self.build_stream.synchronize()
-                else:
-                    r.error = B.WT_EINVAL
+                self._serve_query(r, st, self.build_stream)
                 r.done = time.perf_counter()
 
     # ---- results ----------------------------------------------------------------------

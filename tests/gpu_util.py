@@ -68,3 +68,31 @@ def shaped_codes(S, sigma):
     gcodes, glens = B.huffman_codes(counts)
     ocodes, olens = oracle.huffman(oracle.symbol_counts(S, sigma))
     return (gcodes, glens), (ocodes, olens)
+
+
+def brute_queries(S: np.ndarray, args):
+    """access / rank / select of one mixed batch answered on S itself, by the
+    definitions of Sec. 2 (rank inclusive, select 1-based), in the element
+    types the binding returns (access int32 view of u32, rank and select
+    int64 views of u64)"""
+    pos, rc, ri, sc, sk = (np.asarray(a.cpu().numpy(), dtype=np.int64) for a in args)
+    n = S.size
+    x = S.astype(np.int64)
+    acc = np.where(pos < n, x[np.minimum(pos, max(n - 1, 0))] if n else 0, 0xFFFFFFFF)
+    acc = acc.astype(np.uint32).view(np.int32)
+    order = np.argsort(x, kind="stable")          # positions grouped by symbol, increasing
+    key = x[order] * (n + 1) + order
+    sym = x[order]
+
+    def first(c):
+        return np.searchsorted(sym, c, side="left")
+
+    def count(c):
+        return np.searchsorted(sym, c, side="right") - first(c)
+
+    rnk = np.searchsorted(key, rc * (n + 1) + ri, side="right") - first(rc)
+    rnk = np.where(ri < n, rnk, -1).astype(np.int64)
+    cnt = count(sc)
+    ok = (sk >= 1) & (sk <= cnt)
+    sel = np.where(ok, order[np.minimum(first(sc) + sk - 1, max(n - 1, 0))] if n else 0, -1).astype(np.int64)
+    return acc, rnk, sel

@@ -194,3 +194,43 @@ def test_plan_verdict_on_random_codeword_sets(seed):
     except B.WaveletError as e:
         got = e.code
     assert got == want, (sigma, codes, lens, counts, n)
+
+
+def test_binding_rejects_bad_arguments_before_the_library():
+    """The binding refuses, with WT_EINVAL and before any pointer reaches the
+    library, arguments the header does not allow: host arrays, element types
+    of another width, strided views, paired arrays of different lengths, and
+    host tensors (no GPU is needed: every case is refused on the host)."""
+    import torch
+    img = torch.zeros(4096, dtype=torch.uint8)
+    pos64 = torch.zeros(8, dtype=torch.int64)
+    c32 = torch.zeros(8, dtype=torch.int32)
+
+    def refused(fn, *args, match):
+        with pytest.raises(B.WaveletError) as e:
+            fn(*args)
+        assert e.value.code == B.WT_EINVAL and match in str(e.value), str(e.value)
+
+    refused(B.access, img.numpy(), pos64, match="torch tensor")
+    refused(B.access, img, pos64.to(torch.int32), match="dtype int32")
+    refused(B.access, img, torch.zeros(16, dtype=torch.int64)[::2], match="contiguous")
+    refused(B.access, img.to(torch.int64), pos64, match="dtype int64")
+    refused(B.access, img, pos64, match="device tensors")
+    refused(B.rank, img, c32.to(torch.int64), pos64, match="dtype int64")
+    refused(B.rank, img, c32, pos64.to(torch.int32), match="dtype int32")
+    refused(B.rank, img, c32[:5], pos64, match="lengths differ")
+    refused(B.rank, img, c32, pos64, match="device tensors")
+    refused(B.select, img, c32, pos64[:3], match="lengths differ")
+    refused(B.select, img, c32, pos64.float(), match="dtype float32")
+    refused(B.select, img, c32, pos64, match="device tensors")
+    S = torch.zeros(100, dtype=torch.int32)
+    ws = torch.zeros(1 << 16, dtype=torch.uint8)
+    refused(B.build_into, B.KIND_WM, S.to(torch.int64), 100, img, ws, match="dtype int64")
+    refused(B.build_into, B.KIND_WM, S[::2], 100, img, ws, match="contiguous")
+    refused(B.build_into, B.KIND_WM, S, 100, img.to(torch.int32), ws, match="dtype int32")
+    refused(B.build_into, B.KIND_WM, S, 100, img, ws, match="device tensors")
+    refused(B.symbol_counts, S.double(), 100, match="dtype float64")
+    refused(B.check, img, match="device tensors")
+    refused(B.image_bytes, img[::2], match="contiguous")
+    refused(B.make_desc, S, 100, img, match="device tensors")
+    refused(B.batch_build, B.KIND_WM, [], ws.to(torch.int16), match="dtype int16")

@@ -1,5 +1,7 @@
 """Serving: every build and query result in the continuous-batching mix is
-identical to the same request run alone; admission respects the budget."""
+identical to the same request run alone -- the oracle's image and the
+brute-force answers on S -- and a request that cannot be served fails alone;
+admission respects the budget."""
 import os
 import threading
 import time
@@ -7,7 +9,8 @@ import time
 import numpy as np
 import pytest
 
-from gpu_util import to_device
+import oracle
+from gpu_util import brute_queries, to_device
 from paper_1610_03524_amd import binding as B
 from paper_1610_03524_amd import serve
 
@@ -25,17 +28,11 @@ def pool(k=24, seed=9):
 
 
 def alone(host, batches):
-    import torch
-    imgs = []
-    for S, sigma in host:
-        img, _ = B.build(B.KIND_WM, to_device(S), sigma)
-        imgs.append(img)
-    res = []
-    for t, args in batches:
-        pos, rc, ri, sc, sk = args
-        res.append((B.access(imgs[t], pos), B.rank(imgs[t], rc, ri), B.select(imgs[t], sc, sk)))
-    torch.cuda.synchronize()
-    return [i.cpu().numpy() for i in imgs], [tuple(x.cpu().numpy() for x in r) for r in res]
+    """what every request returns when run alone, from the definitions: the
+    oracle's image of each sequence and brute-force answers on S"""
+    imgs = [oracle.build_image(oracle.KIND_WM, S, sigma) for S, sigma in host]
+    res = [brute_queries(host[t][0], args) for t, args in batches]
+    return imgs, res
 
 
 @pytest.mark.parametrize("mode", ["continuous", "plain"])
@@ -197,3 +194,61 @@ def test_random_mix_under_a_small_budget(seed, mode):
             assert np.array_equal(g.cpu().numpy(), w), f"query batch {b}"
     for i, st in list(srv.resident.items()):
         assert np.array_equal(st.image.cpu().numpy(), want_imgs[i]), f"image {i}"
+
+
+@pytest.mark.parametrize("mode", ["continuous", "plain"])
+def test_bad_requests_fail_alone(mode):
+    """a sequence the library refuses (sigma = 0) and one holding a symbol >=
+    sigma, in a mix of good ones: the two fail with their own codes (WT_EINVAL
+    at admission, WT_ERANGE from the image status) and are never resident;
+    every other build equals the oracle and every query brute force, and the
+    workers keep serving after them"""
+    import torch
+    host = pool(10, seed=21)
+    bad_sigma = len(host)
+    S0 = host[0][0].copy()
+    host.append((S0, 0))                       # refused by the plan
+    rng = np.random.default_rng(5)
+    S1 = rng.integers(0, 300, 5000).astype(np.uint32)
+    S1[1234] = 300                             # one symbol == sigma
+    host.append((S1, 300))
+    bad_range = len(host) - 1
+    good = [i for i in range(len(host)) if i not in (bad_sigma, bad_range)]
+    batches = [(t, serve.make_query_batch(host[t][0], 1500, rng)) for t in good]
+    want_imgs = {i: oracle.build_image(oracle.KIND_WM, *host[i]) for i in good}
+    want_q = [brute_queries(host[t][0], args) for t, args in batches]
+    dev = [(to_device(S), sigma) for S, sigma in host]
+    srv = serve.WaveletServer(dev, hbm_budget=1 << 34, ws_bytes=1 << 28, mode=mode)
+    srv.start()
+    order = [bad_sigma] + good[:4] + [bad_range] + good[4:] + [bad_sigma, bad_range]
+    reqs = {}
+    for i in order:
+        reqs.setdefault(i, []).append(srv.submit_build(i))
+    deadline = time.time() + 60
+    while any(not r.done for r in srv.all_reqs) and time.time() < deadline:
+        time.sleep(0.002)
+    qreqs = [(b, srv.submit_query(t, args)) for b, (t, args) in enumerate(batches)]
+    while any(not r.done for r in srv.all_reqs) and time.time() < deadline:
+        time.sleep(0.002)
+    srv.close()
+    torch.cuda.synchronize()
+    assert all(r.done for r in srv.all_reqs)
+    assert all(r.error == B.WT_EINVAL for r in reqs[bad_sigma])
+    assert all(r.error == B.WT_ERANGE for r in reqs[bad_range])
+    assert bad_sigma not in srv.resident and bad_range not in srv.resident
+    for i in good:
+        assert all(r.error == 0 for r in reqs[i]), i
+        assert np.array_equal(srv.resident[i].image.cpu().numpy(), want_imgs[i]), f"image {i}"
+    for b, r in qreqs:
+        assert r.error == 0
+        for g, w in zip(r.result, want_q[b]):
+            assert np.array_equal(g.cpu().numpy(), w), f"query batch {b}"
+    # a query on a structure that was never built fails alone as well
+    srv2 = serve.WaveletServer(dev, hbm_budget=1 << 34, ws_bytes=1 << 28, mode=mode)
+    srv2.start()
+    q = srv2.submit_query(bad_range, batches[0][1])
+    ok = srv2.submit_build(good[0])
+    while not (q.done and ok.done) and time.time() < deadline:
+        time.sleep(0.002)
+    srv2.close()
+    assert q.error == B.WT_EINVAL and ok.error == 0
