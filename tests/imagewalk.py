@@ -366,3 +366,26 @@ class MatrixWalk:
             else:
                 s, e = self.rank0(l, s), self.rank0(l, e)
         return e - s
+
+
+def array_digests(buf: np.ndarray) -> dict:
+    """SHA-256 of the whole image and of every array in it (header with the
+    level descriptors, then per level its bits, rank directory and select
+    samples, or a multiary level's digits and counters), keyed by name in
+    image order; used to compare images too large to keep two copies of"""
+    import hashlib
+    b = np.ascontiguousarray(np.asarray(buf, dtype=np.uint8))
+    img = Image(b)
+    out = {"image": hashlib.sha256(b.tobytes()).hexdigest()}
+    head = img.levels_off + 64 * img.nlevels
+    out["header"] = hashlib.sha256(b[:head].tobytes()).hexdigest()
+    for l, lv in enumerate(img.levels):
+        m = lv["n"]
+        spans = [("bits", lv["bits_off"], 8 * (-(-m // 64))),
+                 ("rank", lv["rank_off"], 16 * (-(-m // 512) + 1)),
+                 ("sel0", lv["sel0_off"], 8 * lv["nsel"]),
+                 ("sel1", lv["sel1_off"], 8 * lv["nsel"])]
+        for name, off, size in spans:
+            if off:
+                out[f"level{l}.{name}"] = hashlib.sha256(b[off:off + size].tobytes()).hexdigest()
+    return out
