@@ -175,6 +175,24 @@ int multiary_build(const void* S, uint64_t n, uint32_t sigma, uint32_t sym_bytes
                    const wt_shape* shape, const wt_tuning* tune,
                    void* out, size_t out_bytes, void* ws, size_t ws_bytes, void* stream);
 
+/* Wavelet matrix build for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same build and image as wm_build, with the workspace taken
+ * from a library-owned device array of WT_NOALLOC_SCRATCH_BYTES per GPU
+ * (placed when the library is loaded on that GPU and held until the process
+ * ends) instead of a caller buffer.  S and out as for wm_build; no tuning
+ * flags beyond tau / blocks / WT_FLAG_LEVELWISE (WT_FLAG_PROFILE is ignored).
+ * Returns WT_ENOSPC, before any device work, when the build needs more
+ * workspace than the array holds (about n <= 2^22 symbols of 32 bits; the
+ * bound is the plan's workspace_bytes).  Calls no allocating routine.  Every
+ * call on one GPU uses that GPU's one array, so calls that overlap on one GPU
+ * (on different streams, or from different threads) race and must be
+ * serialized by the caller; each call writes every workspace byte it reads
+ * before reading it. */
+#define WT_NOALLOC_SCRATCH_BYTES (64u << 20)
+int wm_build_noalloc(const void* S, uint64_t n, uint32_t sigma, uint32_t sym_bytes,
+                     const wt_tuning* tune, void* out, size_t out_bytes, void* stream);
+
 /* Synchronize `stream` and read the status word of a built image (dev).
  * Returns WT_OK, or WT_ERANGE if a symbol >= sigma was seen. */
 int wt_check(const void* image, void* stream);

@@ -66,6 +66,7 @@ _SIGS = {
                          ctypes.c_size_t, c_vp]),
     "multiary_build": (c_int, [c_vp, c_u64, c_u32, c_u32, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp,
                                ctypes.c_size_t, c_vp]),
+    "wm_build_noalloc": (c_int, [c_vp, c_u64, c_u32, c_u32, c_vp, c_vp, ctypes.c_size_t, c_vp]),
     "wt_check": (c_int, [c_vp, c_vp]),
     "wt_access": (c_int, [c_vp, c_vp, c_vp, c_u64, c_vp]),
     "wt_rank": (c_int, [c_vp, c_vp, c_vp, c_vp, c_u64, c_vp]),

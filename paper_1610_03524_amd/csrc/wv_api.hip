@@ -854,6 +854,37 @@ int build_any(int kind, const void* S, uint64_t n, uint32_t sigma, uint32_t sym_
 
 }  // namespace
 
+// ---- the allocation-free matrix build --------------------------------------
+//
+// Workspace of wm_build_noalloc: one array per device in the code object
+// (placed by the loader, held until the process ends).  In host code the
+// array's name is not a device address; its address on each device is looked
+// up once per device, with that device current, and only that address is
+// passed to kernels.
+static __device__ __align__(256) uint8_t scratch[WT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+// device address of `scratch` on the current device (nullptr on failure)
+void* noalloc_scratch()
+{
+    static std::mutex mu;
+    static void* ptr[NOALLOC_MAX_DEVICES] = {};
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        ptr[dev] = p;
+    }
+    return ptr[dev];
+}
+
+}  // namespace
+
 hipStream_t wv_side_stream()
 {
     static std::mutex mu;
@@ -924,6 +955,22 @@ int multiary_build(const void* S, uint64_t n, uint32_t sigma, uint32_t sym_bytes
 {
     if (!shape || shape->codes) return WT_EINVAL;
     return build_any(WT_KIND_MULTIARY, S, n, sigma, sym_bytes, shape, tune, out, out_bytes, ws, ws_bytes,
+                     (hipStream_t)stream);
+}
+
+int wm_build_noalloc(const void* S, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt_tuning* tune,
+                     void* out, size_t out_bytes, void* stream)
+{
+    // per-kernel timing records events; this entry point takes no such option
+    wt_tuning t = tune ? *tune : wt_tuning{};
+    t.flags &= ~WT_FLAG_PROFILE;
+    Plan p;
+    int rc = make_plan(WT_KIND_WM, n, sigma, sym_bytes, nullptr, &t, p);
+    if (rc) return rc;
+    if (p.ws_bytes > WT_NOALLOC_SCRATCH_BYTES) return WT_ENOSPC;
+    void* ws = noalloc_scratch();
+    if (!ws) return WT_EHIP;
+    return build_any(WT_KIND_WM, S, n, sigma, sym_bytes, nullptr, &t, out, out_bytes, ws, WT_NOALLOC_SCRATCH_BYTES,
                      (hipStream_t)stream);
 }
 

@@ -234,3 +234,13 @@ def test_binding_rejects_bad_arguments_before_the_library():
     refused(B.image_bytes, img[::2], match="contiguous")
     refused(B.make_desc, S, 100, img, match="device tensors")
     refused(B.batch_build, B.KIND_WM, [], ws.to(torch.int16), match="dtype int16")
+
+
+def test_no_alloc_build_refuses_sizes_beyond_its_scratch():
+    """wm_build_noalloc refuses, on the host and before any device call (no
+    GPU is needed here), a build whose workspace exceeds the library's scratch
+    array, and invalid arguments as wm_build does"""
+    L = B.lib()
+    assert L.wm_build_noalloc(0x10000, 1 << 28, 1 << 16, 4, None, 0x20000, 1 << 31, None) == B.WT_ENOSPC
+    assert L.wm_build_noalloc(0x10000, 1000, 0, 4, None, 0x20000, 1 << 20, None) == B.WT_EINVAL
+    assert L.wm_build_noalloc(0x10000, 1000, 100, 3, None, 0x20000, 1 << 20, None) == B.WT_EINVAL
