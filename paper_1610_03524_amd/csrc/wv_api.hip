@@ -41,6 +41,11 @@ struct Plan {
     uint64_t nlong = 0, ws_lkeys = 0, ws_btmp = 0, btmp_stride = 0, ws_wmb = 0;
     uint64_t ws_bcnt = 0, ws_boff = 0, ws_bpart = 0, nkblocks = 0, ws_sdir = 0, ws_ktab = 0;   // ws_sdir: directory scratch, all levels
     wv_wm_plan wmb{};
+    // balanced binary and multiary trees: runs derived on the device
+    bool dev_runs = false;
+    wv_group_ws gz{};
+    uint64_t ws_group = 0;
+    uint64_t ws_scounts = 0;   // shaped trees: the shape's counts, checked on the device
     uint64_t ws_bytes = 0;
     wv_wm_plan wm{};
 };
@@ -218,10 +223,16 @@ int make_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt
         p.ws_tmpimg = bump(off, p.tlay.image_bytes);
         p.dstride = wv_round256((wv_cdiv(n * p.D, 64) + 1) * 8);   // one readable word past each string
         p.ws_digits = bump(off, p.dstride * p.nlevels);
-        for (uint32_t b = 0; b < p.nlevels; b++)
-            p.seg_bound += std::min<uint64_t>((((uint64_t)sigma - 1) >> (p.key_bits - p.D * b)) + 1, n);
-        p.tile_bound = wv_tree_tile_bound(n, p.D, p.nlevels);
-        p.ws_segs = bump(off, seg_bytes(p.seg_bound, p.tile_bound));
+        if (p.key_bits <= WV_GROUP_MAX_BITS) {
+            p.dev_runs = true;
+            p.gz = wv_group_ws_sizes(p.key_bits);
+            p.ws_group = bump(off, p.gz.bytes);
+        } else {
+            for (uint32_t b = 0; b < p.nlevels; b++)
+                p.seg_bound += std::min<uint64_t>((((uint64_t)sigma - 1) >> (p.key_bits - p.D * b)) + 1, n);
+            p.tile_bound = wv_tree_tile_bound(n, p.D, p.nlevels);
+            p.ws_segs = bump(off, seg_bytes(p.seg_bound, p.tile_bound));
+        }
         p.ws_counts = bump(off, (uint64_t)sigma * 8);
         p.ws_bytes = off;
         return WT_OK;
@@ -262,10 +273,11 @@ int make_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt
         p.tile_bound = wv_tree_tile_bound(n, 1, p.key_bits);
         p.ws_segs = bump(off, seg_bytes(p.seg_bound, p.tile_bound));
         p.ws_counts = bump(off, (uint64_t)sigma * 8);
-        // codes, lengths and key table next to each other: one upload
+        // codes, lengths, key table and the shape's counts next to each other: one upload
         p.ws_codes = bump(off, (uint64_t)sigma * 4);
         p.ws_lens = bump(off, (uint64_t)sigma * 4);
         p.ws_ktab = bump(off, (uint64_t)sigma * 4);
+        p.ws_scounts = bump(off, (uint64_t)sigma * 8);
         p.ws_sdir = bump(off, wv_span_dir_sizes(n, p.key_bits).bytes);
         p.ws_bytes = off;
         return WT_OK;
@@ -278,16 +290,24 @@ int make_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt
         if (kind == WT_KIND_SHAPED) p.ws_tkeys = bump(off, n * 4);
         if (kind == WT_KIND_SHAPED) {
             p.seg_bound = p.nnodes_image;
+        } else if (p.key_bits <= WV_GROUP_MAX_BITS) {
+            p.dev_runs = true;
+            p.gz = wv_group_ws_sizes(p.key_bits);
+            p.ws_group = bump(off, p.gz.bytes);
         } else {
             for (uint32_t l = 0; l < p.key_bits; l++)
                 p.seg_bound += std::min<uint64_t>((((uint64_t)sigma - 1) >> (p.key_bits - l)) + 1, n);
         }
-        p.tile_bound = wv_tree_tile_bound(n, 1, p.key_bits);
-        p.ws_segs = bump(off, seg_bytes(p.seg_bound, p.tile_bound));
+        if (!p.dev_runs) {
+            p.tile_bound = wv_tree_tile_bound(n, 1, p.key_bits);
+            p.ws_segs = bump(off, seg_bytes(p.seg_bound, p.tile_bound));
+        }
         p.ws_counts = bump(off, (uint64_t)sigma * 8);
         if (kind == WT_KIND_SHAPED) {
+            // codes, lengths and the shape's counts next to each other: one upload
             p.ws_codes = bump(off, (uint64_t)sigma * 4);
             p.ws_lens = bump(off, (uint64_t)sigma * 4);
+            p.ws_scounts = bump(off, (uint64_t)sigma * 8);
         }
         p.ws_bytes = off;
         return WT_OK;
@@ -495,48 +515,166 @@ int check_buffers(const Plan& p, const void* S, void* out, size_t out_bytes, voi
 // Balanced or shaped binary tree gathered from matrix levels: validate S and
 // count its symbols, derive every level's runs on the host, build the matrix
 // levels of the (padded) keys, move the runs, then the directories.
+// Events for stream forks and joins, kept in a pool for the process
+std::mutex& event_mu()
+{
+    static std::mutex m;
+    return m;
+}
+std::vector<hipEvent_t>& event_pool()
+{
+    static std::vector<hipEvent_t> v;
+    return v;
+}
+hipEvent_t take_event()
+{
+    {
+        std::lock_guard<std::mutex> lk(event_mu());
+        auto& v = event_pool();
+        if (!v.empty()) {
+            hipEvent_t e = v.back();
+            v.pop_back();
+            return e;
+        }
+    }
+    hipEvent_t e = nullptr;
+    return hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess ? e : nullptr;
+}
+void give_event(hipEvent_t e)
+{
+    std::lock_guard<std::mutex> lk(event_mu());
+    event_pool().push_back(e);
+}
+
+// Balanced binary and multiary trees: the matrix passes over the symbols (and
+// the digit strings of a multiary tree), every level's runs derived on the
+// device from the symbol counts, the gather to tree order, the directories.
+// Every step is a launch on `s`: nothing is copied to or from the host and
+// nothing waits, so the build can be captured in a graph.
+int build_balanced_dev(const Plan& p, const void* S, uint8_t* img, uint8_t* ws, bool prof, hipStream_t s)
+{
+    const uint64_t n = p.n;
+    const uint32_t sigma = p.sigma, K = p.key_bits;
+    const bool multi = p.kind == WT_KIND_MULTIARY;
+    const uint32_t D = multi ? p.D : 1u, T = multi ? p.nlevels : K;
+    uint64_t* dcounts = at<uint64_t>(ws, p.ws_counts);
+    WV_TIMED(prof, s, "validate", WV_CHECK(wv_validate(S, n, p.sym_bytes, sigma, img, dcounts, s)));
+    if (multi) {
+        uint8_t* timg = at<uint8_t>(ws, p.ws_tmpimg);
+        const uint64_t *zpre = nullptr, *ztot = nullptr;
+        if (D == 4) {
+            wv_dir_scratch unused{};
+            WV_CHECK(wv_wm_run(p.wm, S, timg, p.tlay, at<uint8_t>(ws, p.ws_wm), unused, s));
+        } else {
+            uint64_t* lw[WV_MAX_LEVELS];
+            for (uint32_t l = 0; l < K; l++) lw[l] = (uint64_t*)(timg + p.tlay.lv[l].bits_off);
+            WV_CHECK(wv_wm_levels(p.wm, S, lw, nullptr, at<uint8_t>(ws, p.ws_wm), s));
+            if (D == 2) {
+                wv_digit_words dw{};
+                for (uint32_t t = 0; t < T; t++) dw.w[t] = lw[2 * t];
+                uint32_t* cnt = at<uint32_t>(ws, p.ws_sb_ones);
+                uint64_t* pre = at<uint64_t>(ws, p.ws_sb_pre);
+                uint64_t* tot = at<uint64_t>(ws, p.ws_mtot);
+                WV_TIMED(prof, s, "tree_digits", WV_CHECK(wv_digit_zero_counts(dw, n, T, cnt, s)));
+                WV_TIMED(prof, s, "tree_digits",
+                         WV_CHECK(wv_scan_u32(cnt, pre, wv_digit_blocks(n), T, at<uint64_t>(ws, p.ws_partial), tot, s)));
+                zpre = pre;
+                ztot = tot;
+            }
+        }
+        for (uint32_t t = 0; t < T; t++) {
+            wv_digit_levels dl{};
+            for (uint32_t k = 0; k < D; k++) {
+                dl.words[k] = (const uint64_t*)(timg + p.tlay.lv[t * D + k].bits_off);
+                dl.dir[k] = (const uint64_t*)(timg + p.tlay.lv[t * D + k].rank_off);
+            }
+            WV_TIMED(prof, s, "tree_digits",
+                     WV_CHECK(wv_tree_digits(dl, n, D, at<uint64_t>(ws, p.ws_digits + t * p.dstride), zpre, ztot, t, T, s)));
+        }
+    } else {
+        uint64_t* lw[WV_MAX_LEVELS];
+        for (uint32_t l = 0; l < K; l++) lw[l] = at<uint64_t>(ws, p.ws_tmp + l * p.tmp_stride);
+        WV_CHECK(wv_wm_levels(p.wm, S, lw, nullptr, at<uint8_t>(ws, p.ws_wm), s));
+    }
+    uint8_t* gws = at<uint8_t>(ws, p.ws_group);
+    WV_TIMED(prof, s, "tree_runs", WV_CHECK(wv_tree_group_runs(dcounts, sigma, K, gws, p.gz, s)));
+    wv_group_level lv[WV_MAX_LEVELS];
+    for (uint32_t t = 0; t < T; t++) {
+        lv[t].dst = (uint64_t*)(img + p.lay.lv[t].bits_off);
+        lv[t].src = multi ? at<uint64_t>(ws, p.ws_digits + t * p.dstride) : at<uint64_t>(ws, p.ws_tmp + t * p.tmp_stride);
+        lv[t].nbits = p.lay.lv[t].n * D;
+        lv[t].l = t * D;
+        // multiary: the sub-range counters follow the range counters
+        lv[t].sub = multi ? (uint16_t*)(img + p.lay.lv[t].rank_off + (wv_mranges(p.lay.lv[t].n, D) + 1) * (8ull << D))
+                          : nullptr;
+    }
+    const wv_mdir_scratch md{at<uint32_t>(ws, p.ws_sb_ones), at<uint64_t>(ws, p.ws_sb_pre),
+                             at<uint64_t>(ws, p.ws_partial), at<uint64_t>(ws, p.ws_mtot)};
+    const wv_perm_counts pc{md.rng_cnt, n, D, T};
+    WV_TIMED(prof, s, "tree_perm", WV_CHECK(wv_tree_permute_groups(lv, T, K, D, gws, p.gz, multi ? &pc : nullptr, s)));
+    if (multi) WV_TIMED(prof, s, "mcounters", WV_CHECK(wv_multiary_ranges(img, p.lay.lv, T, D, md, s)));
+    else WV_CHECK(wv_span_directory(img, p.lay, 0, K, at<uint8_t>(ws, p.ws_wm + p.wm.off_dir), p.wm.dir, s, prof));
+    return WT_OK;
+}
+
 int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8_t* img, uint8_t* ws, bool prof,
                       hipStream_t s)
 {
+    if (p.dev_runs) return build_balanced_dev(p, S, img, ws, prof, s);
     const uint64_t n = p.n;
     const uint32_t sigma = p.sigma, K = p.key_bits;
     const bool shaped = p.kind == WT_KIND_SHAPED, multi = p.kind == WT_KIND_MULTIARY;
     const uint32_t D = multi ? p.D : 1u, T = multi ? p.nlevels : K;
-    // 1. symbol counts and status to the host (waited for in step 3)
+    // 1. symbol counts (and status).  A shaped tree takes its counts from the
+    // shape, which fixes the level sizes, and the device only checks them
+    // (image status); a balanced tree over more than WV_GROUP_MAX_BITS key
+    // bits reads them back to lay out its runs on the host (waited for in
+    // step 3)
+    const bool readback = !shaped;
     uint64_t* dcounts = at<uint64_t>(ws, p.ws_counts);
     WV_TIMED(prof, s, "validate", WV_CHECK(wv_validate(S, n, p.sym_bytes, sigma, img, dcounts, s)));
     // [status word][counts], pinned when possible (else a pageable array)
-    PinnedBuf pin(((uint64_t)sigma + 1) * 8);
-    std::vector<uint64_t> unpinned(pin.get() ? 0 : (uint64_t)sigma + 1);
+    PinnedBuf pin(readback ? ((uint64_t)sigma + 1) * 8 : 0, s);
+    std::vector<uint64_t> unpinned(readback && !pin.get() ? (uint64_t)sigma + 1 : 0);
     uint64_t* hc = pin.get() ? (uint64_t*)pin.get() : unpinned.data();
-    hc[0] = 0;
-    WV_CHECK(hipMemcpyAsync(hc + 1, dcounts, (uint64_t)sigma * 8, hipMemcpyDeviceToHost, s));
-    WV_CHECK(hipMemcpyAsync(hc, img + 36, 4, hipMemcpyDeviceToHost, s));
     hipEvent_t have_counts = nullptr;
-    WV_CHECK(hipEventCreateWithFlags(&have_counts, hipEventDisableTiming));
     struct EventGuard {
         hipEvent_t e;
-        ~EventGuard() { (void)hipEventDestroy(e); }
-    } guard{have_counts};
-    WV_CHECK(hipEventRecord(have_counts, s));
-    // fork / join of the side stream (split shaped trees)
+        ~EventGuard()
+        {
+            if (e) (void)hipEventDestroy(e);
+        }
+    } guard{nullptr};
+    if (readback) {
+        hc[0] = 0;
+        WV_CHECK(hipMemcpyAsync(hc + 1, dcounts, (uint64_t)sigma * 8, hipMemcpyDeviceToHost, s));
+        WV_CHECK(hipMemcpyAsync(hc, img + 36, 4, hipMemcpyDeviceToHost, s));
+        WV_CHECK(hipEventCreateWithFlags(&have_counts, hipEventDisableTiming));
+        guard.e = have_counts;
+        WV_CHECK(hipEventRecord(have_counts, s));
+    }
+    // fork / join of the side stream (split shaped trees): events from a pool,
+    // given back when the call returns (a wait already queued on an event is
+    // not affected when the event is recorded again, and destroying an event
+    // that the device has not reached yet would hold the host)
     struct ForkEvents {
         hipEvent_t e[2] = {nullptr, nullptr};
         ~ForkEvents()
         {
             for (hipEvent_t x : e)
-                if (x) (void)hipEventDestroy(x);
+                if (x) give_event(x);
         }
     } fork;
     if (p.h1 && p.nlong)
-        for (hipEvent_t& x : fork.e) WV_CHECK(hipEventCreateWithFlags(&x, hipEventDisableTiming));
+        for (hipEvent_t& x : fork.e)
+            if (!(x = take_event())) return WT_EHIP;
 
     // 2. the matrix levels need no counts: launch them now, so that they run
     // while the host lays out the tree
     std::vector<uint32_t> c32, l32, ktab;
     // host buffers of the uploads: pinned (pooled) when possible, released
     // to the pool once the stream has passed the copies
-    PinnedBuf up_codes(shaped ? ((p.h1 ? p.ws_ktab : p.ws_lens) - p.ws_codes + (uint64_t)sigma * 4) : 0);
+    PinnedBuf up_codes(shaped ? (p.ws_scounts - p.ws_codes + (uint64_t)sigma * 8) : 0, s);
     std::vector<uint8_t> up_codes_v, up_late_v;
     const void* keys = S;
     if (shaped) {
@@ -547,14 +685,19 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
             c32[x] = l32[x] ? (uint32_t)shape->codes[x] : 0u;
         }
         if (p.h1) wv_split_table(c32.data(), l32.data(), sigma, K, p.h1, ktab);   // top h1 bits of every codeword
-        // codes, lengths (and key table) in the workspace layout, one copy
-        const uint64_t span = (p.h1 ? p.ws_ktab : p.ws_lens) - p.ws_codes + (uint64_t)sigma * 4;
+        // codes, lengths (and key table) and the shape's counts in the
+        // workspace layout, one copy; the device checks its counts against
+        // the shape's (image status)
+        const uint64_t span = p.ws_scounts - p.ws_codes + (uint64_t)sigma * 8;
         if (!up_codes.get()) up_codes_v.resize(span);
         uint8_t* hb = up_codes.get() ? (uint8_t*)up_codes.get() : up_codes_v.data();
         std::memcpy(hb, c32.data(), (uint64_t)sigma * 4);
         std::memcpy(hb + (p.ws_lens - p.ws_codes), l32.data(), (uint64_t)sigma * 4);
         if (p.h1) std::memcpy(hb + (p.ws_ktab - p.ws_codes), ktab.data(), (uint64_t)sigma * 4);
-        WV_CHECK(hipMemcpyAsync(at<void>(ws, p.ws_codes), hb, span, hipMemcpyHostToDevice, s));
+        std::memcpy(hb + (p.ws_scounts - p.ws_codes), shape->counts, (uint64_t)sigma * 8);
+        if (up_codes.get()) WV_CHECK(wv_upload(at<void>(ws, p.ws_codes), hb, span, s));
+        else WV_CHECK(hipMemcpyAsync(at<void>(ws, p.ws_codes), hb, span, hipMemcpyHostToDevice, s));
+        WV_CHECK(wv_check_counts(dcounts, at<uint64_t>(ws, p.ws_scounts), sigma, img, s));
         const uint32_t* dc = at<uint32_t>(ws, p.ws_codes);
         const uint32_t* dl = at<uint32_t>(ws, p.ws_lens);
         if (p.h1) {
@@ -614,10 +757,15 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
         }
     } else if (p.h1) {
         // S itself was validated above; the keys need no check
-        // the small matrix of the long codes on a side stream: its short,
-        // launch-bound passes overlap the big matrix's passes (forked after
-        // the keys, joined before anything reads its levels)
+        // the big matrix first, then the small matrix of the long codes on a
+        // side stream: its short, launch-bound passes are queued while the
+        // big matrix's first pass runs and fill in beside it (forked after the
+        // keys, joined before anything reads its levels)
         hipStream_t s2 = p.nlong ? wv_side_stream() : nullptr;
+        if (s2) WV_CHECK(hipEventRecord(fork.e[0], s));
+        uint64_t* lwa[WV_MAX_LEVELS];
+        for (uint32_t l = 0; l < p.h1; l++) lwa[l] = at<uint64_t>(ws, p.ws_tmp + l * p.tmp_stride);
+        WV_CHECK(wv_wm_levels(p.wm, keys, lwa, nullptr, at<uint8_t>(ws, p.ws_wm), s));
         if (p.nlong) {
             uint64_t* lwb[WV_MAX_LEVELS];
             for (uint32_t l = 0; l < K; l++) lwb[l] = at<uint64_t>(ws, p.ws_btmp + l * p.btmp_stride);
@@ -627,7 +775,6 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
                 // would count the time its kernels wait for the CUs
                 wv_wm_plan pb = p.wmb;
                 pb.profile = false;
-                WV_CHECK(hipEventRecord(fork.e[0], s));
                 WV_CHECK(hipStreamWaitEvent(s2, fork.e[0], 0));
                 WV_TIMED(prof, s2, "side_matrix", WV_CHECK(wv_wm_levels(pb, lk, lwb, nullptr, at<uint8_t>(ws, p.ws_wmb), s2)));
                 WV_CHECK(hipEventRecord(fork.e[1], s2));
@@ -635,9 +782,6 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
                 WV_CHECK(wv_wm_levels(p.wmb, lk, lwb, nullptr, at<uint8_t>(ws, p.ws_wmb), s));
             }
         }
-        uint64_t* lw[WV_MAX_LEVELS];
-        for (uint32_t l = 0; l < p.h1; l++) lw[l] = at<uint64_t>(ws, p.ws_tmp + l * p.tmp_stride);
-        WV_CHECK(wv_wm_levels(p.wm, keys, lw, nullptr, at<uint8_t>(ws, p.ws_wm), s));
         if (s2) WV_CHECK(hipStreamWaitEvent(s, fork.e[1], 0));
     } else {
         uint64_t* lw[WV_MAX_LEVELS];
@@ -645,16 +789,30 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
         WV_CHECK(wv_wm_levels(p.wm, keys, lw, (uint32_t*)(img + 36), at<uint8_t>(ws, p.ws_wm), s));
     }
 
-    // 3. the counts: on an error, let the launched work finish before
-    // returning (it writes into the caller's buffers)
-    WV_CHECK(hipEventSynchronize(have_counts));
-    const uint32_t status = (uint32_t)hc[0];
-    const std::vector<uint64_t> counts(hc + 1, hc + 1 + sigma);
-    pin.idle();
+    // 3. the counts (a shaped tree's from the shape, nothing to wait for)
+    uint32_t status = 0;
+    std::vector<uint64_t> counts;
+    if (readback) {
+        WV_CHECK(hipEventSynchronize(have_counts));
+        status = (uint32_t)hc[0];
+        counts.assign(hc + 1, hc + 1 + sigma);
+        pin.idle();
+    } else {
+        counts.assign(shape->counts, shape->counts + sigma);
+    }
     int rc = status ? WT_ERANGE : WT_OK;
-    if (!rc && shaped)
-        for (uint32_t x = 0; x < sigma && !rc; x++)
-            if (counts[x] != shape->counts[x]) rc = WT_EINVAL;
+    // work already launched writes into the caller's buffers: on an error a
+    // shaped build leaves it queued (its uploads retire with the stream), the
+    // other path lets it finish
+    auto fail = [&](int code) {
+        if (shaped && !up_codes_v.size() && !up_late_v.size()) {
+            up_codes.retire(s);
+            return code;
+        }
+        (void)hipStreamSynchronize(s);
+        up_codes.idle();
+        return code;
+    };
     std::vector<uint8_t> rec, code_rec;
     if (!rc && shaped) {
         HostNodes H;
@@ -702,10 +860,7 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
         }
         if (segs.size() > p.seg_bound) rc = WT_EUNSUP;
     }
-    if (rc) {
-        WV_CHECK(hipStreamSynchronize(s));
-        return rc;
-    }
+    if (rc) return fail(rc);
     std::vector<wv_perm_level> lv(T);
     for (uint32_t l = 0; l < T; l++) {
         lv[l].dst = (uint64_t*)(img + p.lay.lv[l].bits_off);
@@ -721,10 +876,7 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
     }
     std::vector<uint32_t> tile0, tile_seg;
     wv_tree_tiles(lv, segs, multi, tile0, tile_seg);
-    if (tile_seg.size() > p.tile_bound) {
-        WV_CHECK(hipStreamSynchronize(s));
-        return WT_EUNSUP;
-    }
+    if (tile_seg.size() > p.tile_bound) return fail(WT_EUNSUP);
     // descriptors, runs and tiles in one copy; the node and code tables of a
     // shaped tree behind them in the same host buffer
     const uint64_t seg_at = wv_round256(WV_MAX_LEVELS * sizeof(wv_perm_level));
@@ -732,7 +884,7 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
     const uint64_t stage_bytes = tile_at + tile_seg.size() * 4;
     const uint64_t rec_at = wv_round256(stage_bytes), code_at = rec_at + wv_round256(rec.size());
     const uint64_t late_bytes = code_at + code_rec.size();
-    PinnedBuf late(late_bytes);
+    PinnedBuf late(late_bytes, s);
     if (!late.get()) up_late_v.resize(late_bytes);
     uint8_t* stage = late.get() ? (uint8_t*)late.get() : up_late_v.data();
     std::memcpy(stage, lv.data(), T * sizeof(wv_perm_level));
@@ -741,14 +893,17 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
     if (!rec.empty()) std::memcpy(stage + rec_at, rec.data(), rec.size());
     if (!code_rec.empty()) std::memcpy(stage + code_at, code_rec.data(), code_rec.size());
     uint8_t* dsegs = at<uint8_t>(ws, p.ws_segs);
-    WV_CHECK(hipMemcpyAsync(dsegs, stage, stage_bytes, hipMemcpyHostToDevice, s));
+    auto upload = [&](void* dst, const void* src, uint64_t bytes) {
+        return late.get() ? wv_upload(dst, src, bytes, s) : hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+    };
+    WV_CHECK(upload(dsegs, stage, stage_bytes));
     const wv_perm_level* dlv = (const wv_perm_level*)dsegs;
     const wv_perm_seg* dseg = (const wv_perm_seg*)(dsegs + seg_at);
     const uint32_t* dtile = (const uint32_t*)(dsegs + tile_at);
     if (shaped) {
         if (!rec.empty())
-            WV_CHECK(hipMemcpyAsync(img + p.lay.nodes_off, stage + rec_at, rec.size(), hipMemcpyHostToDevice, s));
-        WV_CHECK(hipMemcpyAsync(img + p.lay.codes_off, stage + code_at, code_rec.size(), hipMemcpyHostToDevice, s));
+            WV_CHECK(upload(img + p.lay.nodes_off, stage + rec_at, rec.size()));
+        WV_CHECK(upload(img + p.lay.codes_off, stage + code_at, code_rec.size()));
     }
 
     // 5. runs to tree order, then the directories
@@ -767,10 +922,16 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
     } else {
         WV_CHECK(wv_span_directory(img, p.lay, 0, K, dscr, p.wm.dir, s, prof));
     }
-    // the host buffers copied from go out of scope
-    WV_CHECK(hipStreamSynchronize(s));
-    up_codes.idle();
-    late.idle();
+    // the host buffers copied from: pinned ones retire with the stream (the
+    // call does not wait), pageable fallbacks must be waited for
+    if (up_codes_v.size() || up_late_v.size()) {
+        WV_CHECK(hipStreamSynchronize(s));
+        up_codes.idle();
+        late.idle();
+    } else {
+        up_codes.retire(s);
+        late.retire(s);
+    }
     return WT_OK;
 }
 
@@ -980,7 +1141,8 @@ int wt_check(const void* image, void* stream)
     uint32_t status = 0;
     WV_CHECK(hipStreamSynchronize((hipStream_t)stream));
     WV_CHECK(hipMemcpy(&status, (const uint8_t*)image + 36, 4, hipMemcpyDeviceToHost));
-    return status ? WT_ERANGE : WT_OK;
+    if (status & WV_STATUS_RANGE) return WT_ERANGE;
+    return status ? WT_EINVAL : WT_OK;
 }
 
 int wt_image_bytes(const void* image, uint64_t* bytes, void* stream)

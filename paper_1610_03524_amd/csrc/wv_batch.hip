@@ -530,7 +530,7 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
 
     // every descriptor of the build, in one pinned host buffer with an area
     // per phase
-    PinnedBuf pin(bp.desc_total);
+    PinnedBuf pin(bp.desc_total, s);
     std::vector<uint8_t> unpinned(pin.get() ? 0 : bp.desc_total);
     uint8_t* hd = pin.get() ? (uint8_t*)pin.get() : unpinned.data();
     auto host_area = [&](uint32_t ph) { return hd + bp.phase_off[ph]; };
@@ -540,6 +540,7 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
     // its kernels are launched at once, so later phases are filled on the host
     // while earlier ones run (each phase reads only its own area)
     auto copy_area = [&](uint32_t ph) {
+        if (pin.get()) return wv_upload(dev_area(ph), host_area(ph), area_bytes(ph), s);
         return hipMemcpyAsync(dev_area(ph), host_area(ph), area_bytes(ph), hipMemcpyHostToDevice, s);
     };
 
@@ -598,7 +599,8 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
                 if (members.empty()) continue;
                 const uint32_t m = (uint32_t)members.size();
                 if (m != bp.phase_members[phase]) {   // the plan and the build disagree
-                    (void)hipStreamSynchronize(s);     // earlier phases may be running
+                    if (pin.get()) pin.retire(s);      // earlier phases may be running
+                    else (void)hipStreamSynchronize(s);
                     return WT_EINVAL;
                 }
                 std::memset(host_area(phase), 0, area_bytes(phase));
@@ -680,9 +682,11 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
         if (dchunks) WV_TIMED(prof, s, "b_dir_write", (b_dir_write_k<<<dchunks, 256, 0, s>>>(dsd, dfirst, nspan)));
         WV_CHECK(hipGetLastError());
     }
-    // the host descriptor buffer is read by the copy above: finish first
-    WV_CHECK(hipStreamSynchronize(s));
-    pin.idle();
+    // the copies above read the host descriptors: the pinned buffer returns
+    // to the pool once the stream is past them (a pageable fallback, used only
+    // when no pinned memory could be had, must be waited for)
+    if (pin.get()) pin.retire(s);
+    else WV_CHECK(hipStreamSynchronize(s));
     return WT_OK;
 }
 

@@ -437,6 +437,54 @@ hipError_t wv_validate(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t s
     return hipGetLastError();
 }
 
+namespace {
+
+// status bit 1 when a symbol's count differs from the one the shape gave
+__global__ void counts_match_k(const uint64_t* __restrict__ got, const uint64_t* __restrict__ want, uint32_t sigma,
+                               uint32_t* __restrict__ status)
+{
+    bool bad = false;
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < sigma; x += gridDim.x * blockDim.x)
+        bad |= got[x] != want[x];
+    if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(status, WV_STATUS_COUNTS);
+}
+
+}  // namespace
+
+namespace {
+
+// dst[i] = src[i] for `bytes` bytes, src in pinned host memory (read by the
+// device directly); 16-byte pieces, then the tail
+__global__ void upload_k(uint8_t* __restrict__ dst, const uint8_t* __restrict__ src, uint64_t bytes)
+{
+    const uint64_t n16 = bytes / 16;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+        ((uint4*)dst)[i] = ((const uint4*)src)[i];
+    for (uint64_t i = n16 * 16 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < bytes; i += stride) dst[i] = src[i];
+}
+
+}  // namespace
+
+hipError_t wv_upload(void* dst, const void* pinned, uint64_t bytes, hipStream_t s)
+{
+    if (!bytes) return hipSuccess;
+    if (((uintptr_t)dst | (uintptr_t)pinned) & 15u) return hipErrorInvalidValue;
+    void* src = nullptr;
+    hipError_t e = hipHostGetDevicePointer(&src, const_cast<void*>(pinned), 0);
+    if (e != hipSuccess) return e;
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(wv_cdiv(bytes, 16 * 256), 1), 256);
+    upload_k<<<grid, 256, 0, s>>>((uint8_t*)dst, (const uint8_t*)src, bytes);
+    return hipGetLastError();
+}
+
+hipError_t wv_check_counts(const uint64_t* got, const uint64_t* want, uint32_t sigma, uint8_t* image, hipStream_t s)
+{
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(wv_cdiv(sigma, DIR_THREADS), 256);
+    counts_match_k<<<std::max(grid, 1u), DIR_THREADS, 0, s>>>(got, want, sigma, (uint32_t*)(image + 36));
+    return hipGetLastError();
+}
+
 // ---- directories of several levels in one launch per step ----------------------
 
 namespace {

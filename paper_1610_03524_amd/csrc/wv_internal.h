@@ -72,26 +72,38 @@ hipError_t wv_multiary_ranges(uint8_t* image, const wv_level* lv, uint32_t M, ui
                               const wv_mdir_scratch& sc, hipStream_t s);
 
 // ---- pinned host staging -------------------------------------------------------
-// Pinned host buffers for copies a build issues between launches (the symbol
-// counts a tree build reads back and the tables it uploads, the descriptors
-// of a batch): a copy from or to pageable memory holds the host until it
-// completes.  Buffers are reused
-// until the process ends; one that a failed build may still be copying is
-// not returned.
+// Pinned host buffers for copies a build issues between launches (the tables
+// a shaped tree build uploads, the descriptors of a batch): a copy from
+// pageable memory holds the host until it completes.  Buffers are pooled
+// until the process ends.  A build never waits for its copies: it retires
+// the buffer, which records an event on the stream and returns the buffer to
+// the pool once that event has completed (checked when a buffer is next
+// taken).  Under stream capture the buffer is kept for good instead, since
+// the captured copies read it at every replay of the graph.
 class PinnedBuf {
 public:
-    explicit PinnedBuf(size_t bytes)
+    // `s`: the stream the copies will be queued on (no completed-copy check
+    // while it is being captured)
+    // At most CAP buffers wait for their copies: a caller that runs further
+    // ahead of the device waits for the oldest of them instead of allocating
+    // more pinned memory (an allocation costs far more than a build's copies).
+    static constexpr size_t CAP = 8;
+    PinnedBuf(size_t bytes, hipStream_t s)
     {
         if (!bytes) return;   // nothing to hold
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        const bool capturing = hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
         std::lock_guard<std::mutex> lk(mu());
-        auto& fr = pool();
-        for (size_t i = 0; i < fr.size(); i++)
-            if (fr[i].second >= bytes) {
-                p_ = fr[i].first;
-                n_ = fr[i].second;
-                fr.erase(fr.begin() + (long)i);
-                return;
+        if (!capturing) {
+            reclaim();
+            if (!take(bytes) && pending().size() >= CAP) {
+                // wait for the oldest retired buffer (the events complete in
+                // stream order on one stream; any completed one is reclaimed)
+                (void)hipEventSynchronize(pending().front().done);
+                reclaim();
             }
+        }
+        if (p_ || take(bytes)) return;
         n_ = std::max<size_t>(bytes, 4096);
         if (hipHostMalloc(&p_, n_, hipHostMallocDefault) != hipSuccess) p_ = nullptr;
     }
@@ -102,11 +114,32 @@ public:
         pool().push_back({p_, n_});
     }
     void* get() const { return p_; }
-    void idle() { idle_ = true; }   // no copy into it is pending any more
+    void idle() { idle_ = true; }   // no copy from or into it is pending any more
+    // copies from or into the buffer are queued on s: it goes back to the
+    // pool when s has passed them (or never, while s is being captured)
+    void retire(hipStream_t s)
+    {
+        if (!p_ || idle_) return;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;   // kept
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return;   // kept
+        if (hipEventRecord(e, s) != hipSuccess) {
+            (void)hipEventDestroy(e);
+            return;   // kept
+        }
+        std::lock_guard<std::mutex> lk(mu());
+        pending().push_back(Pending{p_, n_, e});
+    }
     PinnedBuf(const PinnedBuf&) = delete;
     PinnedBuf& operator=(const PinnedBuf&) = delete;
 
 private:
+    struct Pending {
+        void* p;
+        size_t n;
+        hipEvent_t done;
+    };
     static std::mutex& mu()
     {
         static std::mutex m;
@@ -117,10 +150,49 @@ private:
         static std::vector<std::pair<void*, size_t>> v;
         return v;
     }
+    static std::vector<Pending>& pending()
+    {
+        static std::vector<Pending> v;
+        return v;
+    }
+    // (under the lock) a pooled buffer of at least `bytes`, the smallest
+    bool take(size_t bytes)
+    {
+        auto& fr = pool();
+        size_t best = fr.size();
+        for (size_t i = 0; i < fr.size(); i++)
+            if (fr[i].second >= bytes && (best == fr.size() || fr[i].second < fr[best].second)) best = i;
+        if (best == fr.size()) return false;
+        p_ = fr[best].first;
+        n_ = fr[best].second;
+        fr.erase(fr.begin() + (long)best);
+        return true;
+    }
+    // (under the lock) retired buffers whose copies are done back to the pool
+    static void reclaim()
+    {
+        auto& pd = pending();
+        size_t k = 0;
+        for (size_t i = 0; i < pd.size(); i++) {
+            if (hipEventQuery(pd[i].done) == hipSuccess) {
+                (void)hipEventDestroy(pd[i].done);
+                pool().push_back({pd[i].p, pd[i].n});
+            } else {
+                pd[k++] = pd[i];
+            }
+        }
+        pd.resize(k);
+    }
     void* p_ = nullptr;
     size_t n_ = 0;
     bool idle_ = false;
 };
+
+// Copy `bytes` from a pinned host buffer (hipHostMalloc) to device memory with
+// a kernel that reads the host memory directly, ordered on s like any launch
+// (no copy engine between the kernels of a build, and a kernel node when s is
+// captured).  Both pointers 16-byte aligned.
+hipError_t wv_upload(void* dst, const void* pinned, uint64_t bytes, hipStream_t s);
 
 // A second stream of the current device for work a build forks off its own
 // stream and joins again with events (created on first use, default
@@ -134,3 +206,9 @@ hipError_t wv_write_header(uint8_t* image, const wv_layout_in& in, hipStream_t s
 hipError_t wv_validate(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma,
                        uint8_t* image, uint64_t* counts /*nullable*/, hipStream_t s);
 hipError_t wv_fill_u64(uint64_t* p, uint64_t count, uint64_t value, hipStream_t s);
+// status word of the image header: bit 0 a symbol >= sigma, bit 1 symbol
+// counts that differ from those a shape gave
+constexpr uint32_t WV_STATUS_RANGE = 1u;
+constexpr uint32_t WV_STATUS_COUNTS = 2u;
+// sets WV_STATUS_COUNTS when got[x] != want[x] for some x < sigma (dev arrays)
+hipError_t wv_check_counts(const uint64_t* got, const uint64_t* want, uint32_t sigma, uint8_t* image, hipStream_t s);

@@ -116,6 +116,45 @@ hipError_t wv_digit_zero_counts(const wv_digit_words& a, uint64_t n, uint32_t T,
 hipError_t wv_tree_digits(const wv_digit_levels& a, uint64_t n, uint32_t D, uint64_t* out, const uint64_t* zpre,
                           const uint64_t* ztot, uint32_t t, uint32_t T, hipStream_t s);
 
+// ---- runs of balanced trees, derived on the device --------------------------
+//
+// A balanced tree (binary, or multiary with D-bit digits) over K-bit keys,
+// K <= WV_GROUP_MAX_BITS: the run of key prefix g (the top l key bits) on
+// binary level l starts, in tree order, after the symbols with a smaller
+// prefix, C[g << (K-l)] with C the exclusive prefix of the symbol counts over
+// the key space; in the matrix order it starts after the groups whose prefix
+// read bit-reversed is smaller (the matrix orders a level by the reversed
+// prefix), P[2^l - 1 + brev(g)] - P[2^l - 1] with P the exclusive prefix of
+// every level's group counts laid out in bit-reversed order.  No host copy:
+// the whole tree build stays ordered on its stream.
+constexpr uint32_t WV_GROUP_MAX_BITS = 20;
+
+// workspace of the derivation for K key bits (bytes, 256-aligned pieces)
+struct wv_group_ws {
+    uint64_t off_cnt, off_C, off_V, off_P, off_part, off_tot, bytes;
+};
+wv_group_ws wv_group_ws_sizes(uint32_t K);
+
+// C and P from the symbol counts (dev, sigma entries; symbols >= sigma are
+// not counted, so C[2^K] < n flags them and the gather below leaves the
+// uncovered bits 0)
+hipError_t wv_tree_group_runs(const uint64_t* counts, uint32_t sigma, uint32_t K, uint8_t* ws,
+                              const wv_group_ws& z, hipStream_t s);
+
+// one tree level of the gather below (passed by value)
+struct wv_group_level {
+    uint64_t* dst;          // tree level words (in the image)
+    const uint64_t* src;    // matrix level words, or the digit string in matrix order (one readable word past the end)
+    uint64_t nbits;         // bits on the tree level
+    uint16_t* sub;          // multiary: the level's sub-range counters
+    uint32_t l;             // binary level of its runs (t * D)
+};
+
+// gather every tree level, runs from C and P; with `counts` the levels are
+// multiary (D = counts->D bits per symbol) and their counters are taken on the way
+hipError_t wv_tree_permute_groups(const wv_group_level* lv, uint32_t nlev, uint32_t K, uint32_t D, const uint8_t* ws,
+                                  const wv_group_ws& z, const wv_perm_counts* counts, hipStream_t s);
+
 // gather every tree level (descriptors, runs and tile_seg already on the
 // device; tile0 on the host, nlev + 1 entries); with `counts`, the levels are
 // multiary and their counters are taken on the way

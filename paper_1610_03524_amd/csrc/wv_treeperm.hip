@@ -280,6 +280,100 @@ perm_runs_k(PermArgs a)
     }
 }
 
+// ---- balanced trees: runs from the symbol counts, on the device ----------------
+
+__device__ inline uint32_t brev_bits(uint32_t v, uint32_t nbits) { return nbits ? (__brev(v) >> (32 - nbits)) : 0u; }
+
+// the symbol counts as 32-bit values over the whole key space (0 past sigma)
+__global__ void group_counts_k(const uint64_t* __restrict__ counts, uint32_t sigma, uint32_t keys,
+                               uint32_t* __restrict__ cnt)
+{
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < keys; x += gridDim.x * blockDim.x)
+        cnt[x] = x < sigma ? (uint32_t)counts[x] : 0u;
+}
+
+// V[2^l - 1 + r] = symbols under the prefix brev(r) on level l, for l < K
+__global__ void group_levels_k(const uint64_t* __restrict__ C, uint32_t K, uint32_t* __restrict__ V)
+{
+    const uint32_t total = (1u << K) - 1u;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        const uint32_t l = 31 - __clz(i + 1);
+        const uint32_t g = brev_bits(i + 1 - (1u << l), l);
+        const uint32_t sh = K - l;
+        V[i] = (uint32_t)(C[(uint64_t)(g + 1) << sh] - C[(uint64_t)g << sh]);
+    }
+}
+
+struct GroupArgs {
+    wv_group_level lv[WV_MAX_LEVELS];
+    uint32_t tile0[WV_MAX_LEVELS + 1];
+    uint32_t nlev, K, D;
+    const uint64_t* C;
+    const uint64_t* P;
+    wv_perm_counts cnt;
+};
+
+// One thread per output word, a workgroup per 256-word tile of one level: the
+// group holding each run of the word is found by a binary search in C (the
+// last prefix starting at or before the symbol), its place in the matrix
+// order read from P, and its bits gathered.  COUNT as in perm_runs_k.
+template <bool COUNT>
+__global__ void __launch_bounds__(WV_PERM_TILE)
+perm_groups_k(GroupArgs a)
+{
+    const uint32_t b = blockIdx.x;
+    uint32_t t = 0;
+    while (t + 1 < a.nlev && a.tile0[t + 1] <= b) t++;   // uniform
+    const wv_group_level L = a.lv[t];
+    const uint64_t w = (uint64_t)(b - a.tile0[t]) * WV_PERM_TILE + threadIdx.x;
+    const uint64_t nw = wv_cdiv(L.nbits, 64);
+    const uint32_t D = a.D, dsh = D == 1 ? 0u : (D == 2 ? 1u : 2u);
+    uint64_t out = 0;
+    if (w < nw) {
+        const uint64_t p0 = w * 64, end = min(p0 + 64, L.nbits);
+        const uint32_t l = L.l, sh = a.K - l;
+        const uint32_t G = 1u << l, base = G - 1u;
+        const uint64_t pbase = a.P[base];
+        for (uint64_t p = p0; p < end;) {
+            const uint64_t q = p >> dsh;   // symbol position
+            uint32_t lo = 0, hi = G - 1u;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi + 1u) >> 1;
+                if (a.C[(uint64_t)mid << sh] <= q) lo = mid; else hi = mid - 1u;
+            }
+            const uint64_t start = a.C[(uint64_t)lo << sh], stop = a.C[(uint64_t)(lo + 1) << sh];
+            if (stop <= q) break;   // counts short of the level (a symbol >= sigma): the rest stays 0
+            const uint64_t src = a.P[base + brev_bits(lo, l)] - pbase;
+            const uint64_t in = p - (start << dsh);
+            const uint32_t take = (uint32_t)min(end - p, ((stop - start) << dsh) - in);
+            out |= bits_at(L.src, (src << dsh) + in, take) << (p - p0);
+            p += take;
+        }
+        L.dst[w] = out;
+    }
+    if (COUNT) {
+        const wv_perm_counts& cnt = a.cnt;
+        const uint32_t lane = threadIdx.x & 63, P = wv_digits_per_word(D), d = 1u << D;
+        const uint64_t r = w >> 6, sk = w >> 3;
+        if (r >= wv_mranges(cnt.m, D)) return;   // whole waves
+        const uint32_t c = w < nw ? (uint32_t)min<uint64_t>(P, cnt.m - w * P) : 0u;
+        const bool subw = (lane & 7) == 0 && sk < wv_msubs(cnt.m, D);
+        for (uint32_t g0 = 0; g0 < d; g0 += 4) {
+            uint64_t pack = 0;   // up to four 16-bit sub-range counters
+            for (uint32_t gg = 0; gg < 4 && g0 + gg < d; gg++) {
+                const uint32_t v = wv_count_digit(out, D, g0 + gg, c);
+                const uint32_t inc = wv_wave_incl_scan(v);
+                if (lane == 63) cnt.rng_cnt[(r * cnt.M + t) * d + g0 + gg] = inc;
+                pack |= (uint64_t)(inc - v) << (16 * gg);
+            }
+            if (subw) {
+                if (d == 2) *(uint32_t*)(L.sub + sk * d) = (uint32_t)pack;
+                else *(uint64_t*)(L.sub + sk * d + g0) = pack;
+            }
+        }
+    }
+}
+
 // the low 64/D bits of x moved to bit positions 0, D, 2D, ... (D = 1, 2, 4)
 __device__ inline uint64_t spread(uint64_t x, uint32_t D)
 {
@@ -664,6 +758,74 @@ uint32_t wv_tree_tiles(const std::vector<wv_perm_level>& lv, const std::vector<w
     }
     tile0[lv.size()] = (uint32_t)tile_seg.size();
     return tile0[lv.size()];
+}
+
+wv_group_ws wv_group_ws_sizes(uint32_t K)
+{
+    wv_group_ws z{};
+    const uint64_t keys = 1ull << K;
+    uint64_t off = 0;
+    auto bump = [&](uint64_t bytes) { const uint64_t at = off; off = wv_round256(off + bytes); return at; };
+    z.off_cnt = bump(keys * 4);
+    z.off_C = bump((keys + 1) * 8);
+    z.off_V = bump(keys * 4);
+    z.off_P = bump(keys * 8);
+    z.off_part = bump(8 * wv_scan_partials(keys, 1));
+    z.off_tot = bump(8);
+    z.bytes = off;
+    return z;
+}
+
+hipError_t wv_tree_group_runs(const uint64_t* counts, uint32_t sigma, uint32_t K, uint8_t* ws,
+                              const wv_group_ws& z, hipStream_t s)
+{
+    if (K > WV_GROUP_MAX_BITS) return hipErrorInvalidValue;
+    const uint32_t keys = 1u << K;
+    uint32_t* cnt = (uint32_t*)(ws + z.off_cnt);
+    uint64_t* C = (uint64_t*)(ws + z.off_C);
+    uint32_t* V = (uint32_t*)(ws + z.off_V);
+    uint64_t* P = (uint64_t*)(ws + z.off_P);
+    uint64_t* part = (uint64_t*)(ws + z.off_part);
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(wv_cdiv(keys, 256), 1024);
+    group_counts_k<<<grid, 256, 0, s>>>(counts, sigma, keys, cnt);
+    hipError_t e = wv_scan_u32(cnt, C, keys, 1, part, C + keys, s);   // C[keys] = symbols counted
+    if (e != hipSuccess) return e;
+    if (keys > 1) {
+        group_levels_k<<<grid, 256, 0, s>>>(C, K, V);
+        e = wv_scan_u32(V, P, keys - 1, 1, part, (uint64_t*)(ws + z.off_tot), s);
+        if (e != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
+hipError_t wv_tree_permute_groups(const wv_group_level* lv, uint32_t nlev, uint32_t K, uint32_t D, const uint8_t* ws,
+                                  const wv_group_ws& z, const wv_perm_counts* counts, hipStream_t s)
+{
+    if (!nlev || nlev > WV_MAX_LEVELS) return nlev ? hipErrorInvalidValue : hipSuccess;
+    if (D != 1 && D != 2 && D != 4) return hipErrorInvalidValue;
+    GroupArgs a{};
+    uint32_t tiles = 0;
+    for (uint32_t t = 0; t < nlev; t++) {
+        a.lv[t] = lv[t];
+        a.tile0[t] = tiles;
+        const uint64_t nw = wv_cdiv(lv[t].nbits, 64);
+        const uint64_t words = counts ? wv_cdiv(nw, 64) * 64 : nw;
+        if (lv[t].nbits) tiles += (uint32_t)wv_cdiv(words, WV_PERM_TILE);
+    }
+    a.tile0[nlev] = tiles;
+    a.nlev = nlev;
+    a.K = K;
+    a.D = D;
+    a.C = (const uint64_t*)(ws + z.off_C);
+    a.P = (const uint64_t*)(ws + z.off_P);
+    if (!tiles) return hipSuccess;
+    if (counts) {
+        a.cnt = *counts;
+        perm_groups_k<true><<<tiles, WV_PERM_TILE, 0, s>>>(a);
+    } else {
+        perm_groups_k<false><<<tiles, WV_PERM_TILE, 0, s>>>(a);
+    }
+    return hipGetLastError();
 }
 
 hipError_t wv_tree_permute(const wv_perm_level* lv_dev, uint32_t nlev, const wv_perm_seg* seg_dev,

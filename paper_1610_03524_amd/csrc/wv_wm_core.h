@@ -19,6 +19,10 @@ constexpr int HT = 256;             // histogram / scan threads
 constexpr uint32_t KRES16 = 1024;
 constexpr uint32_t KRES32 = 768;
 constexpr uint32_t KMAX = KRES16;    // most chunks of one build by default
+// bytes of the word -> run table of a sub-level (TW words plus one partial
+// word for each of at most 128 runs), a multiple of 256: WRW words per lane
+constexpr uint32_t WRB = (TW + 128 + 255) / 256 * 256;
+constexpr uint32_t WRW = WRB / 256;
 
 
 __device__ __host__ inline uint32_t gidx(uint32_t j, uint32_t u) { return (1u << j) - 1u + u; }
@@ -60,6 +64,26 @@ __device__ inline uint32_t wave_excl_scan(uint32_t v, uint32_t* total)
     const uint32_t inc = wv_wave_incl_scan(v);
     *total = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
     return inc - v;
+}
+
+// inclusive max-scan of the 64 values held by one wave (every lane active)
+__device__ inline uint32_t wave_incl_max(uint32_t v)
+{
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true));   // row_shr:1
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true));   // row_shr:2
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true));   // row_shr:4
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true));   // row_shr:8
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return v;
+}
+
+// LDS writes of this wave visible to its other lanes
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <typename IT, typename KT_>
@@ -105,6 +129,10 @@ struct PassShared {
     uint32_t cnt[MAXG], ls[MAXG], g[MAXG], fw[MAXG];
     uint64_t carry[2][255];
     uint32_t sp[129];
+    // run (index inside its sub-level) owning each word a sub-level writes:
+    // at most TW words plus one partial word per run (runs of one sub-level
+    // number at most 128)
+    alignas(16) uint8_t wr[WRB];
 };
 
 // One chunk b of one pass (see the file comment of wv_wm_passes.hip).
@@ -176,6 +204,13 @@ __device__ void wm_pass_chunk(const PassArgs& a, uint32_t b, PassShared<KT_>& S)
                 }
                 if (lane == 0) zw[TW] = run;
             } else if (wave == 1) {
+                // words every run of sub-level j completes in this tile, their
+                // prefix, and the run owning each of those words: a run's
+                // first word marks its index, and a forward max over the
+                // table fills the words after it (run indices increase)
+                uint32_t* wr4 = (uint32_t*)S.wr;
+                for (uint32_t k = 0; k < WRW; k++) wr4[WRW * lane + k] = 0;
+                wave_lds_sync();
                 uint32_t run = 0;
                 for (uint32_t u0 = 0; u0 < nk; u0 += 64) {
                     const uint32_t u = u0 + lane;
@@ -186,10 +221,30 @@ __device__ void wm_pass_chunk(const PassArgs& a, uint32_t b, PassShared<KT_>& S)
                     }
                     uint32_t tot;
                     const uint32_t ex = wave_excl_scan(v, &tot);
-                    if (u < nk) sp[u] = run + ex;
+                    if (u < nk) {
+                        sp[u] = run + ex;
+                        if (v) S.wr[run + ex] = (uint8_t)u;
+                    }
                     run += tot;
                 }
                 if (lane == 0) sp[nk] = run;
+                wave_lds_sync();
+                uint32_t q[WRW], m = 0;
+                for (uint32_t k = 0; k < WRW; k++) {
+                    q[k] = wr4[WRW * lane + k];
+                    for (uint32_t b = 0; b < 4; b++) {     // forward max inside the lane's bytes
+                        m = max(m, (q[k] >> (8 * b)) & 0xFFu);
+                        q[k] = (q[k] & ~(0xFFu << (8 * b))) | (m << (8 * b));
+                    }
+                }
+                const uint32_t incl = wave_incl_max(m);
+                const uint32_t prev = (uint32_t)__shfl_up((int)incl, 1);
+                const uint32_t ex = lane ? prev : 0u;
+                for (uint32_t k = 0; k < WRW; k++) {
+                    uint32_t r = 0;
+                    for (uint32_t b = 0; b < 4; b++) r |= max(ex, (q[k] >> (8 * b)) & 0xFFu) << (8 * b);
+                    wr4[WRW * lane + k] = r;
+                }
             }
             __syncthreads();
             // phase 3: partition, child runs, emit words
@@ -222,7 +277,9 @@ __device__ void wm_pass_chunk(const PassArgs& a, uint32_t b, PassShared<KT_>& S)
             // elements keep their order, zeros of the tile first
             const uint32_t gc = gidx(j + 1, 0);
             uint64_t* words = a.words[j];
-            for (uint32_t u = tid; u < nk; u += NT) {
+            // child runs on the last threads, words on the threads after the
+            // first two waves (which did the scans of this sub-level)
+            for (uint32_t u = NT - 1 - tid; u < nk; u += NT) {
                 const uint32_t s0 = ls[gb + u], c = cnt[gb + u];
                 const uint32_t zs = local_rank0(lb, zw, s0), ze = local_rank0(lb, zw, s0 + c);
                 cnt[gc + 2 * u] = ze - zs;
@@ -243,12 +300,8 @@ __device__ void wm_pass_chunk(const PassArgs& a, uint32_t b, PassShared<KT_>& S)
                 carry[cpar ^ 1][gi] = v;
             }
             const uint32_t total = sp[nk];
-            for (uint32_t s = tid; s < total; s += NT) {
-                uint32_t lo = 0, hi = nk - 1;
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi + 1) >> 1;
-                    if (sp[mid] <= s) lo = mid; else hi = mid - 1;
-                }
+            for (uint32_t s = (tid + NT - 128) % NT; s < total; s += NT) {
+                const uint32_t lo = S.wr[s];
                 const uint32_t gi = gb + lo;
                 const uint32_t i = s - sp[lo];
                 const uint32_t gg = g[gi];

@@ -96,3 +96,16 @@ def brute_queries(S: np.ndarray, args):
     ok = (sk >= 1) & (sk <= cnt)
     sel = np.where(ok, order[np.minimum(first(sc) + sk - 1, max(n - 1, 0))] if n else 0, -1).astype(np.int64)
     return acc, rnk, sel
+
+
+def build_status(kind, St, sigma, **kw):
+    """status a build reports for a device sequence: the launch's return code
+    when it refuses, else what wt_check reads from the image (a symbol >= sigma
+    or counts that differ from the shape's are found on the device)"""
+    import torch
+    try:
+        img, _ = B.build(kind, St, sigma, **kw)
+    except B.WaveletError as e:
+        torch.cuda.synchronize()
+        return e.code
+    return B.check(img)

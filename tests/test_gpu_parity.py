@@ -78,14 +78,36 @@ def test_levelwise_equals_default(kind):
 
 
 def test_symbol_out_of_range_sets_status():
+    """a symbol >= sigma is found on the device: every stream-ordered build
+    returns WT_OK and wt_check reports WT_ERANGE; the level-by-level tree path,
+    which reads the counts back, returns it directly"""
     import torch
     S = to_device(np.array([0, 1, 7, 2], dtype=np.uint8))
-    for kind in (B.KIND_WM,):
-        img, _ = B.build(kind, S, 5)
-        assert B.check(img) == B.WT_ERANGE
+    for kind, D in ((B.KIND_WM, 0), (B.KIND_WT, 0), (B.KIND_MULTIARY, 2), (B.KIND_MULTIARY, 1)):
+        img, _ = B.build(kind, S, 5, arity_log2=D)
+        assert B.check(img) == B.WT_ERANGE, (kind, D)
     with pytest.raises(B.WaveletError) as e:
-        B.build(B.KIND_WT, S, 5)
+        B.build(B.KIND_MULTIARY, S, 5, arity_log2=3)
     assert e.value.code == B.WT_ERANGE
+    torch.cuda.synchronize()
+
+
+def test_shaped_counts_that_differ_from_the_shape_are_reported():
+    """the shape's counts fix the level sizes; a sequence whose counts differ
+    is found on the device and wt_check returns WT_EINVAL (the image is then
+    unspecified, but the build stays in bounds)"""
+    import torch
+    rng = np.random.default_rng(8)
+    S = rng.integers(0, 40, 5000).astype(np.uint8)
+    counts = oracle.symbol_counts(S, 40)
+    codes, lens = oracle.huffman(counts)
+    T = S.copy()
+    T[17] = (T[17] + 1) % 40               # same length, one count moved
+    img, _ = B.build(B.KIND_SHAPED, to_device(T), 40, codes=codes, code_len=lens, counts=counts)
+    assert B.check(img) == B.WT_EINVAL
+    img, _ = B.build(B.KIND_SHAPED, to_device(S), 40, codes=codes, code_len=lens, counts=counts)
+    assert B.check(img) == B.WT_OK
+    assert_same(img.cpu().numpy(), oracle.build_image(oracle.KIND_SHAPED, S, 40, codes=codes, lens=lens), "shaped")
     torch.cuda.synchronize()
 
 
