@@ -32,7 +32,11 @@
  *   - Return value: WT_OK or a negative WT_E* code.  Argument errors are
  *     reported before anything is launched.  A symbol >= sigma is found on
  *     the device: the build then marks the image header and wt_check()
- *     returns WT_ERANGE (the rest of the image is unspecified).
+ *     returns WT_ERANGE (the rest of the image is unspecified); a shaped
+ *     tree whose sequence has other counts than shape->counts is marked the
+ *     same way and wt_check() returns WT_EINVAL.
+ *   - Builds do not wait on the host (except the level-by-level tree path,
+ *     below), so a caller may capture any build into a HIP graph.
  *   - Limits: n < 2^32, sigma >= 1, sym_bytes in {1, 2, 4}, at most 32
  *     levels, codeword length <= 32.
  */
@@ -63,8 +67,9 @@ extern "C" {
 /* ---- image layout (little endian) ----------------------------------------
  * Header, 256 bytes at offset 0:
  *   u32 magic 0x54564157 ("WAVT"), u32 version 1, u32 kind, u32 arity_log2,
- *   u64 n, u32 sigma, u32 nlevels, u32 key_bits, u32 status (0 ok, 1 = a
- *   symbol >= sigma was seen), u64 image_bytes, u64 levels_off (= 256),
+ *   u64 n, u32 sigma, u32 nlevels, u32 key_bits, u32 status (0 ok; bit 0:
+ *   a symbol >= sigma was seen; bit 1: the symbol counts differ from those
+ *   the shape gave), u64 image_bytes, u64 levels_off (= 256),
  *   u64 nodes_off, u64 nnodes, u64 codes_off, u64 ncoded; rest zero.
  * Level descriptors, 64 bytes each, at levels_off + 64*l:
  *   u64 n_l, u64 zeros, u64 ones, u64 bits_off, u64 rank_off, u64 sel0_off,
@@ -150,13 +155,17 @@ int wt_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes,
  * S: dev, n symbols of sym_bytes each.  out: dev, out_bytes >= plan
  * out_bytes, receives the image.  ws: dev scratch of ws_bytes >= plan
  * workspace_bytes.  S, out and ws must be 16-byte aligned (device
- * allocations are), else WT_EINVAL before any device work.  Waits once
- * during the build for the symbol counts, read back to place the tree's
- * runs (shaped: they must equal shape->counts, else WT_EINVAL; a symbol >=
- * sigma returns WT_ERANGE at that point), and returns after synchronizing
- * `stream`, the build complete.  A shaped tree split into two matrices
- * builds the smaller one on a second stream the library keeps per device,
- * forked from and joined back into `stream` with events. */
+ * allocations are), else WT_EINVAL before any device work.  Asynchronous on
+ * `stream`: a balanced tree derives the place of every run from the symbol
+ * counts on the device (key bits <= 20; a wider alphabet reads the counts
+ * back and waits, as does the level-by-level path); a shaped tree places its
+ * runs from shape->counts on the host before launching, uploads its tables
+ * from pinned host buffers that return to the library's pool once `stream`
+ * has passed them (kept for good when `stream` is being captured), and the
+ * device checks the counts (wt_check: WT_EINVAL if they differ).  A shaped
+ * tree split into two matrices builds the smaller one on a second stream
+ * the library keeps per device, forked from and joined back into `stream`
+ * with events. */
 int wt_build(const void* S, uint64_t n, uint32_t sigma, uint32_t sym_bytes,
              const wt_shape* shape, const wt_tuning* tune,
              void* out, size_t out_bytes, void* ws, size_t ws_bytes, void* stream);
@@ -169,8 +178,9 @@ int wm_build(const void* S, uint64_t n, uint32_t sigma, uint32_t sym_bytes,
 
 /* Build a balanced multiary wavelet tree of degree 2^shape->arity_log2
  * (Sec. 4.3, Thm. 4.5) with per-digit rank counters (Sec. 5.2).  Same
- * arguments as wt_build; waits for the symbol counts the same way and
- * returns after synchronizing `stream`. */
+ * arguments as wt_build; asynchronous in the same way for D = 1, 2, 4
+ * (8-ary trees take the level-by-level path, which waits for the counts
+ * and returns WT_ERANGE directly). */
 int multiary_build(const void* S, uint64_t n, uint32_t sigma, uint32_t sym_bytes,
                    const wt_shape* shape, const wt_tuning* tune,
                    void* out, size_t out_bytes, void* ws, size_t ws_bytes, void* stream);
@@ -194,7 +204,8 @@ int wm_build_noalloc(const void* S, uint64_t n, uint32_t sigma, uint32_t sym_byt
                      const wt_tuning* tune, void* out, size_t out_bytes, void* stream);
 
 /* Synchronize `stream` and read the status word of a built image (dev).
- * Returns WT_OK, or WT_ERANGE if a symbol >= sigma was seen. */
+ * Returns WT_OK; WT_ERANGE if a symbol >= sigma was seen; WT_EINVAL if a
+ * shaped tree's symbol counts differ from shape->counts. */
 int wt_check(const void* image, void* stream);
 
 /* Batched queries on a built image (dev), m queries, all arrays dev.
@@ -243,8 +254,11 @@ int wt_batch_plan(int kind, const wt_seq_desc* seqs, uint32_t count, const wt_tu
 
 /* Build wavelet matrices (kind WT_KIND_WM) of many sequences with a few
  * persistent launches; each image equals the one wm_build writes for that
- * sequence alone.  seqs: host array of count descriptors.  Returns when the
- * batch is complete (the host writes per-round descriptors into ws). */
+ * sequence alone.  seqs: host array of count descriptors (read during the
+ * call only).  Asynchronous on `stream`: the per-round descriptors are
+ * staged in a pinned host buffer that a kernel copies into ws; the buffer
+ * returns to the library's pool once `stream` has passed the copies (kept
+ * for good when `stream` is being captured). */
 int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count,
                    void* ws, size_t ws_bytes, const wt_tuning* tune, void* stream);
 
