@@ -41,6 +41,9 @@ struct Plan {
     uint64_t nlong = 0, ws_lkeys = 0, ws_btmp = 0, btmp_stride = 0, ws_wmb = 0;
     uint64_t ws_bcnt = 0, ws_boff = 0, ws_bpart = 0, nkblocks = 0, ws_sdir = 0, ws_ktab = 0;   // ws_sdir: directory scratch, all levels
     wv_wm_plan wmb{};
+    // balanced trees of at most 8 key bits built in one pass straight into
+    // tree order (domain decomposition), no matrix levels in between
+    bool direct_tree = false;
     // balanced binary and multiary trees: runs derived on the device
     bool dev_runs = false;
     wv_group_ws gz{};
@@ -197,6 +200,24 @@ int make_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt
         int rc = wv_wm_make_plan(n, sigma, sym_bytes, tune, p.wm);
         if (rc) return rc;
         p.levelwise = !p.wm.enabled;
+    }
+    // Balanced trees whose key bits one pass covers (sigma <= 256): the
+    // domain decomposition of Sec. 4.2.  The chunks of the pass are the K
+    // sub-sequences; each chunk's run of a node goes to the node's start in
+    // tree order plus the node's symbols in the chunks before it (prefix sums
+    // over the per-chunk counts), the words two chunks share are OR-ed.  The
+    // levels are written straight into the image.
+    if (kind == WT_KIND_WT && !p.levelwise && n && L <= 8) {
+        wv_wm_plan a{};
+        if (wv_wm_make_plan(n, sigma, sym_bytes, tune, a) == WT_OK && a.enabled && a.tau == a.L) {
+            a.tree_order = true;
+            p.direct_tree = true;
+            p.wm = a;
+            p.tau = a.tau;
+            p.ws_wm = bump(off, a.ws_bytes);
+            p.ws_bytes = off;
+            return WT_OK;
+        }
     }
     // balanced and shaped binary trees: matrix passes over the (padded) keys,
     // then the runs of every level moved to tree order
@@ -948,7 +969,7 @@ int build_any(int kind, const void* S, uint64_t n, uint32_t sigma, uint32_t sym_
     WV_TIMED(prof, s, "header", WV_CHECK(wv_write_header(img, p.lin, s)));
     if (p.from_matrix) return build_from_matrix(p, S, shape, img, (uint8_t*)ws, prof, s);
 
-    if (kind == WT_KIND_WM && !p.levelwise) {
+    if ((kind == WT_KIND_WM && !p.levelwise) || p.direct_tree) {
         // the first pass validates S while counting its digits
         wv_dir_scratch dir{at<uint32_t>(ws, p.ws_sb_ones), at<uint64_t>(ws, p.ws_sb_pre),
                            at<uint64_t>(ws, p.ws_partial), at<uint64_t>(ws, p.ws_scalars + 8)};

@@ -457,8 +457,10 @@ struct OffShared {
     uint32_t cj[MAXG], tj[MAXG], bs[MAXG];
 };
 
+// natural: runs in key order (the tree order of a balanced tree's level,
+// Sec. 2) instead of the matrix's bit-reversed order (Sec. 4.3)
 __device__ inline void wm_chunk_offsets(OffShared& sh, uint32_t b, uint32_t tau, uint32_t n, uint32_t* G0,
-                                        uint64_t* const* words)
+                                        uint64_t* const* words, bool natural = false)
 {
     const uint32_t ngroups = (2u << tau) - 1u;
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -476,7 +478,7 @@ __device__ inline void wm_chunk_offsets(OffShared& sh, uint32_t b, uint32_t tau,
         uint32_t run = 0;
         for (uint32_t r0 = 0; r0 < nk; r0 += 64) {
             const uint32_t r = r0 + lane;
-            const uint32_t u = r < nk ? brev(r, j) : 0;
+            const uint32_t u = r < nk ? (natural ? r : brev(r, j)) : 0;
             const uint32_t v = r < nk ? sh.tj[gidx(j, u)] : 0;
             uint32_t t;
             const uint32_t ex = wave_excl_scan(v, &t);
@@ -501,6 +503,7 @@ struct OffArgs {
     uint32_t* G0;
     uint64_t* words[8];
     uint32_t K, tau, n;
+    uint32_t natural;        // runs in key order (a tree built in one pass)
 };
 
 __global__ void __launch_bounds__(HT)
@@ -512,7 +515,7 @@ wm_offsets_k(OffArgs a)
         sh.cj[gidx(tau, threadIdx.x)] = a.PH[(uint64_t)threadIdx.x * a.K + b];
         sh.tj[gidx(tau, threadIdx.x)] = a.totals[threadIdx.x];
     }
-    wm_chunk_offsets(sh, b, tau, a.n, a.G0, a.words);
+    wm_chunk_offsets(sh, b, tau, a.n, a.G0, a.words, a.natural != 0);
 }
 
 

@@ -13,6 +13,11 @@ struct wv_wm_plan {
     wv_span_dir dir;
     uint64_t ws_bytes;     // workspace the passes need
     bool profile;          // bracket the launches with timing events
+    // Place every run of every level in key order: the levels of a balanced
+    // tree built directly when one pass covers all its key bits (the domain
+    // decomposition of Sec. 4.2: every chunk's runs go to their node at the
+    // node's start plus the node's symbols in earlier chunks)
+    bool tree_order;
 };
 
 // Decide how the multi-level passes build this matrix.

@@ -126,6 +126,7 @@ int wv_wm_make_plan(uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt_tun
     tau = std::min(tau, L);
     const Geometry geo = geometry(n, tune ? tune->blocks : 0, L);
     p.enabled = true;
+    p.tree_order = false;
     p.profile = tune && (tune->flags & WT_FLAG_PROFILE);
     p.tau = tau;
     p.L = L;
@@ -180,6 +181,7 @@ hipError_t wv_wm_levels(const wv_wm_plan& p, const void* S, uint64_t* const* lev
             oa.K = geo.K;
             oa.tau = tau;
             oa.n = n;
+            oa.natural = p.tree_order ? 1u : 0u;
             WV_TIMED(pr, s, "wm_offsets", (wm_offsets_k<<<geo.K, HT, 0, s>>>(oa)));
             PassArgs pa{};
             pa.in = in;

@@ -215,3 +215,31 @@ def test_shaped_split_at_16_bits(name, counts, long_len, dt):
     for tune in (None, B.make_tuning(tau=3, blocks=2)):
         g = gpu_image(B.KIND_SHAPED, S, 4, codes=codes, lens=lens, tune=tune)
         assert_same(g, o, f"{name} long_len={long_len} tune={tune is not None}")
+
+
+DD_CASES = [(1, 1, 0), (2, 1000, 0), (3, 8191, 3), (5, 8192, 7), (8, 8193, 2), (17, 65537, 5), (100, 300001, 40),
+            (255, 1 << 20, 128), (256, (1 << 20) + 12345, 0), (256, 5 * 8192 * 3 + 1, 15), (7, 3 * 8192, 3)]
+
+
+@pytest.mark.parametrize("sigma,n,blocks", DD_CASES)
+def test_balanced_tree_by_domain_decomposition(sigma, n, blocks):
+    """Balanced trees over at most 8 key bits are built in one pass straight
+    into tree order (Sec. 4.2): the K chunks of the pass are built alone and
+    their runs of every node placed by prefix sums over the per-chunk counts,
+    the words shared by two chunks OR-ed.  Every chunk count (blocks = 0:
+    automatic) gives the oracle's image, and so does the matrix-and-gather
+    path forced with a narrower pass."""
+    import torch
+    rng = np.random.default_rng(sigma * 7919 + n)
+    S = rng.integers(0, sigma, n).astype(np.uint8 if sigma <= 256 else np.uint16)
+    want = oracle_image(B.KIND_WT, S, sigma)
+    tune = B.make_tuning(blocks=blocks)
+    info = B.plan(B.KIND_WT, n, sigma, S.itemsize, tune=tune)
+    L = max(1, (sigma - 1).bit_length())
+    assert info.tau == L   # one pass covers every level
+    assert_same(gpu_image(B.KIND_WT, S, sigma, tune=tune), want, f"direct sigma={sigma} n={n} blocks={blocks}")
+    if L >= 3:
+        narrow = B.make_tuning(tau=L - 1, blocks=blocks)
+        assert B.plan(B.KIND_WT, n, sigma, S.itemsize, tune=narrow).tau == L - 1
+        assert_same(gpu_image(B.KIND_WT, S, sigma, tune=narrow), want, f"matrix path sigma={sigma} n={n}")
+    torch.cuda.synchronize()
