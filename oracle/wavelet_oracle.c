@@ -20,7 +20,9 @@
  *     Jacobson's ranges and sub-ranges, here 512-bit ranges and 64-bit
  *     sub-ranges) and sampled select (Sec. 5.1, "Select": the sampling layer
  *     of Clark's structure, here every 4096th one and every 4096th zero);
- *   - per-digit rank counters on multiary levels (Sec. 5.2, "Rank");
+ *   - per-digit rank counters on multiary levels (Sec. 5.2, "Rank") and
+ *     per-digit sampled select (Sec. 5.2, "Select": the range symbols, every
+ *     4096th occurrence of each digit value);
  *   - canonical Huffman codewords, the shape used for Huffman-shaped trees.
  *
  * Every structure is a deterministic function of (S, sigma, kind, shape);
@@ -134,7 +136,11 @@ static uint64_t lay_out(olevel* lv, unsigned nlev, int multiary, unsigned D,
             lv[l].sel1_off = off;
             off = round256(off + lv[l].nsel * 8);
         } else {
-            lv[l].nsel = lv[l].sel0_off = lv[l].sel1_off = 0;
+            /* generalized select: d arrays of nsel samples, digit-major */
+            lv[l].nsel = bin_nsel(m);
+            lv[l].sel0_off = off;
+            off = round256(off + ((uint64_t)1 << D) * lv[l].nsel * 8);
+            lv[l].sel1_off = 0;
         }
     }
     *nodes_off = *codes_off = 0;
@@ -241,6 +247,19 @@ static void write_multi_level(uint8_t* img, olevel* lv, const uint8_t* g, unsign
     }
     /* the sentinel range entry k = nsb holds the totals */
     for (uint64_t c = 0; c < d; c++) put_u64(sb + (nsb * d + c) * 8, cnt[c]);
+    /* Generalized select (Sec. 5.2, "Select"): a separate sampled structure
+       for every character, here every digit value c: the position of the
+       occurrence of c whose 0-based ordinal is 4096k (the range symbols of
+       c), then m in the entries past the last one */
+    uint8_t* sel = img + lv->sel0_off;
+    uint64_t seen[16] = {0};
+    for (uint64_t c = 0; c < d; c++)
+        for (uint64_t k = 0; k < lv->nsel; k++) put_u64(sel + (c * lv->nsel + k) * 8, m);
+    for (uint64_t t = 0; t < m; t++) {
+        uint64_t c = g[t];
+        if (seen[c] % O_SEL_STRIDE == 0) put_u64(sel + (c * lv->nsel + seen[c] / O_SEL_STRIDE) * 8, t);
+        seen[c]++;
+    }
 }
 
 static void write_header(uint8_t* img, int kind, unsigned arity_log2, uint64_t n,

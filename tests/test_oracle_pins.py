@@ -500,6 +500,7 @@ def test_layout(kind, D):
             spans.append((lv["bits_off"], lv["bits_off"] + 8 * (-(-m // p))))
             nsb, nb = -(-m // (64 * p)), -(-m // (8 * p))
             spans.append((lv["rank_off"], lv["rank_off"] + (nsb + 1) * d * 8 + nb * d * 2))
+            spans.append((lv["sel0_off"], lv["sel0_off"] + d * lv["nsel"] * 8))
         else:
             spans.append((lv["bits_off"], lv["bits_off"] + 8 * (-(-m // 64))))
             spans.append((lv["rank_off"], lv["rank_off"] + 16 * (-(-m // 512) + 1)))
@@ -532,3 +533,29 @@ def test_matrix_walk_on_oracle_images():
         for c_src, i in zip(rng.integers(0, n, 50), rng.integers(0, n, 50)):
             c = int(S[c_src])
             assert w.rank(c, int(i)) == int(np.count_nonzero(S[:i + 1] == c))
+
+
+@pytest.mark.parametrize("D", [1, 2, 3, 4])
+def test_multiary_select_samples(D):
+    """Per-digit select samples of every multiary level (Sec. 5.2, "Select":
+    a sampled structure per character): for every digit value c the position
+    of its occurrences of ordinal 0, 4096, 8192, ... (numpy flatnonzero), then
+    the level length as sentinel, ceil(n/4096)+1 entries per digit"""
+    rng = np.random.default_rng(90 + D)
+    for sigma, n in [(3, 20000), (16, 50001), (200, 9000), (1 << 12, 30000), (2, 4096), (5, 1)]:
+        # skewed digits, so some values are dense and some sparse
+        S = np.minimum(rng.geometric(0.2, n) - 1, sigma - 1).astype(np.uint16)
+        img = Image(oracle.build_image(KIND_MULTI, S, sigma, D))
+        want_digits = multi_closed_form(S, sigma, D)
+        for l, lv in enumerate(img.levels):
+            m = lv["n"]
+            nsel = -(-m // 4096) + 1
+            assert lv["nsel"] == nsel and lv["sel0_off"] % 256 == 0 and lv["sel1_off"] == 0
+            dig = want_digits[l]
+            tab = np.frombuffer(img.buf[lv["sel0_off"]:lv["sel0_off"] + 8 * nsel * (1 << D)].tobytes(),
+                                dtype=np.uint64).reshape(1 << D, nsel)
+            for c in range(1 << D):
+                pos = np.flatnonzero(dig == c)[::4096]
+                want = np.full(nsel, m, dtype=np.uint64)
+                want[:pos.size] = pos
+                assert np.array_equal(tab[c], want), (sigma, n, D, l, c)
