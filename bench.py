@@ -340,11 +340,12 @@ def query_rates(img, S, n, sigma, levels, stream, m=1 << 22, reps=5):
     g = torch.Generator(device=dev)
     g.manual_seed(10)
     pos = torch.randint(0, n, (m,), device=dev, generator=g, dtype=torch.int64)
-    c = S[torch.randint(0, n, (m,), device=dev, generator=g, dtype=torch.int64)].to(torch.int32)
-    counts = torch.bincount(S, minlength=sigma)
+    Sl = S.to(torch.int64) & ((1 << (8 * S.element_size())) - 1)   # stored unsigned
+    c = Sl[torch.randint(0, n, (m,), device=dev, generator=g, dtype=torch.int64)].to(torch.int32)
+    counts = torch.bincount(Sl, minlength=sigma)
     k = (torch.rand(m, device=dev, generator=g) * counts[c.long()]).long() + 1
     got = B.access(img, pos[:1 << 16], stream).to(torch.int64)
-    assert torch.equal(got, S[pos[:1 << 16]].to(torch.int64)), "access differs from S"
+    assert torch.equal(got, Sl[pos[:1 << 16]]), "access differs from S"
     kinds = {"access": lambda: B.access(img, pos, stream), "rank": lambda: B.rank(img, c, pos, stream),
              "select": lambda: B.select(img, c, k, stream)}
     out = {"queries_per_batch": m, "levels": levels}
@@ -471,6 +472,7 @@ def bench_tree(args):
                            "frac": round(balg / t / 1e9 / HBM_PEAK_GBPS, 4)},
         "kernel_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in sorted(prof.items())},
     }
+    line["queries"] = query_rates(out, St, n, sigma, info.nlevels, stream, m=1 << 20)
     if not args.no_cpu_baseline:
         import oracle
         okind = {B.KIND_WT: oracle.KIND_WT, B.KIND_SHAPED: oracle.KIND_SHAPED, B.KIND_MULTIARY: oracle.KIND_MULTI}[kind]

@@ -73,7 +73,8 @@ extern "C" {
  *   u64 nodes_off, u64 nnodes, u64 codes_off, u64 ncoded; rest zero.
  * Level descriptors, 64 bytes each, at levels_off + 64*l:
  *   u64 n_l, u64 zeros, u64 ones, u64 bits_off, u64 rank_off, u64 sel0_off,
- *   u64 sel1_off, u64 nsel.   (multiary: zeros = ones = sel* = nsel = 0)
+ *   u64 sel1_off, u64 nsel.   (multiary: zeros = ones = sel1_off = 0;
+ *   sel0_off = the per-digit select samples, nsel entries per digit value)
  * Arrays, each starting on a 256-byte boundary, level after level:
  *   binary level  bits: ceil(n_l/64) u64 words, bit i at bit (i%64) of word
  *                 i/64 (LSB first), padding bits 0;
@@ -88,7 +89,10 @@ extern "C" {
  *                 (ceil(n_l/64P)+1) x d u64 = count of each digit before
  *                 every 64-word range (last entry = totals), followed by
  *                 ceil(n_l/8P) x d u16 = count of each digit from the start
- *                 of its range to the start of every 8-word sub-range.
+ *                 of its range to the start of every 8-word sub-range;
+ *                 then the generalized select samples (Sec. 5.2, "Select"):
+ *                 for every digit value c (c-major) nsel = ceil(n_l/4096)+1
+ *                 u64: position of the c of 0-based ordinal 4096k, then n_l.
  *   shaped trees  node table (32 B per internal node, ordered by (level,
  *                 prefix)): u64 start in its level, u64 count, u32 child[2]
  *                 (node index, or 0x80000000|symbol for a leaf, 0xFFFFFFFF

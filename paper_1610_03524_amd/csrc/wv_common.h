@@ -99,7 +99,11 @@ __host__ __device__ inline void wv_layout(const wv_layout_in& in, wv_layout_out&
             L.sel1_off = off;
             off = wv_round256(off + L.nsel * 8);
         } else {
-            L.nsel = L.sel0_off = L.sel1_off = 0;
+            // generalized select: 2^D arrays of nsel samples, digit-major
+            L.nsel = wv_nsel(m);
+            L.sel0_off = off;
+            off = wv_round256(off + (8ull << D) * L.nsel);
+            L.sel1_off = 0;
         }
     }
     out.nodes_off = out.codes_off = 0;
@@ -185,8 +189,9 @@ __device__ inline uint64_t wv_rank0(const uint64_t* __restrict__ words,
     return r;
 }
 
-// number of digits equal to g among the first t (< P) digits of word w
-__device__ inline uint32_t wv_count_digit(uint64_t w, uint32_t D, uint32_t g, uint32_t t)
+// the low bit of every digit equal to g among the first t (< P) digits of
+// word w (bit D*i for digit i)
+__device__ inline uint64_t wv_digit_mask(uint64_t w, uint32_t D, uint32_t g, uint32_t t)
 {
     if (t == 0) return 0;
     // low-bit-of-every-digit mask: bits 0, D, 2D, ... of the P = 64/D digits
@@ -199,7 +204,21 @@ __device__ inline uint32_t wv_count_digit(uint64_t w, uint32_t D, uint32_t g, ui
     for (uint32_t b = 1; b < D; b++) any |= x >> b;
     uint64_t eq = ~any & lowm;
     uint64_t keep = (t * D >= 64) ? ~0ull : ((1ull << (t * D)) - 1ull);
-    return (uint32_t)__popcll(eq & keep);
+    return eq & keep;
+}
+
+// number of digits equal to g among the first t (< P) digits of word w
+__device__ inline uint32_t wv_count_digit(uint64_t w, uint32_t D, uint32_t g, uint32_t t)
+{
+    return (uint32_t)__popcll(wv_digit_mask(w, D, g, t));
+}
+
+// index of the digit of value g with 0-based ordinal j in word w (j below
+// the word's count of g among its first t digits)
+__device__ inline uint32_t wv_digit_select(uint64_t w, uint32_t D, uint32_t g, uint32_t t, uint32_t j)
+{
+    const uint32_t b = wv_select_in_word(wv_digit_mask(w, D, g, t), j);
+    return D == 1 ? b : (D == 2 ? b >> 1 : (D == 4 ? b >> 2 : b / 3u));
 }
 
 // digit g count in [0, i) of a multiary level from its counters and words
@@ -228,4 +247,44 @@ __device__ inline uint64_t wv_mrank(const uint64_t* __restrict__ words, const ui
     const uint32_t t = (uint32_t)(i - wk * P);
     if (t) r += wv_count_digit(words[wk], D, g, t);
     return r;
+}
+
+
+// Generalized select on a multiary level (Sec. 5.2, "Select"): position of
+// the digit g of 0-based ordinal o (o below the level's count of g).  The
+// digit's sample of ordinal 4096*floor(o/4096) and the next one bound the
+// 64-word ranges to search (binary search on the range counters), then the
+// sub-range counters and the words of one sub-range give the position.
+__device__ inline uint64_t wv_mselect(const uint64_t* __restrict__ words, const uint8_t* __restrict__ cnt,
+                                      const uint64_t* __restrict__ sel, uint64_t nsel, uint64_t m, uint32_t D,
+                                      uint32_t g, uint64_t o)
+{
+    const uint32_t P = wv_digits_per_word(D);
+    const uint64_t d = 1ull << D;
+    const uint64_t nr = wv_mranges(m, D), nsub = wv_msubs(m, D);
+    const uint64_t* rng = (const uint64_t*)cnt;
+    const uint16_t* sub = (const uint16_t*)(cnt + (nr + 1) * d * 8);
+    const uint64_t k = o / WV_SEL_STRIDE;
+    const uint64_t p0 = sel[g * nsel + k], p1 = sel[g * nsel + k + 1];
+    const uint64_t RD = 64ull * P;   // digits per range
+    uint64_t lo = p0 / RD, hi = p1 >= m ? nr - 1 : p1 / RD;
+    while (lo < hi) {   // the last range starting with at most o digits g before it
+        const uint64_t mid = (lo + hi + 1) >> 1;
+        if (rng[mid * d + g] <= o) lo = mid; else hi = mid - 1;
+    }
+    uint64_t before = rng[lo * d + g];
+    uint64_t w = lo * 64;
+    for (uint64_t sk = lo * 8 + 1; sk < lo * 8 + 8 && sk < nsub; sk++) {
+        const uint64_t b = rng[lo * d + g] + sub[sk * d + g];
+        if (b > o) break;
+        before = b;
+        w = sk * 8;
+    }
+    const uint64_t nw = wv_cdiv(m, P);
+    for (;; w++) {   // the word holding it is at most 7 words on
+        const uint32_t t = (uint32_t)min<uint64_t>(P, m - w * P);
+        const uint32_t c = wv_count_digit(words[w], D, g, t);
+        if (before + c > o || w + 1 >= nw) return w * P + wv_digit_select(words[w], D, g, t, (uint32_t)(o - before));
+        before += c;
+    }
 }

@@ -124,10 +124,62 @@ dir_finish_k(uint8_t* __restrict__ image, uint32_t level, wv_level L,
 // one wave per range of 64 words (lane = word).  Range counts and prefixes
 // are laid out [range][level][digit].
 struct MLevels {
-    uint64_t bits_off[WV_MAX_LEVELS], rank_off[WV_MAX_LEVELS];
-    uint64_t m;
+    uint64_t bits_off[WV_MAX_LEVELS], rank_off[WV_MAX_LEVELS], sel_off[WV_MAX_LEVELS];
+    uint64_t m, nsel;
     uint32_t M, D;
 };
+
+// Generalized select samples (Sec. 5.2, "Select"): every digit value's
+// occurrences of ordinal 4096k, found from the finished range counters: one
+// wave per 64-word range, which holds at most one sample of each value (a
+// range has at most 64 * 64 digits); lane = word.
+__global__ void __launch_bounds__(DIR_THREADS)
+msel_k(uint8_t* __restrict__ image, MLevels a)
+{
+    const uint32_t lane = threadIdx.x & 63, t = blockIdx.y;
+    const uint64_t r = ((uint64_t)blockIdx.x * DIR_THREADS + threadIdx.x) >> 6;
+    const uint32_t D = a.D, P = wv_digits_per_word(D), d = 1u << D;
+    const uint64_t m = a.m, nr = wv_mranges(m, D), nw = wv_cdiv(m, P);
+    if (r >= nr) return;   // whole waves: the scans below need every lane
+    const uint64_t* words = (const uint64_t*)(image + a.bits_off[t]);
+    const uint64_t* rng = (const uint64_t*)(image + a.rank_off[t]);
+    uint64_t* sel = (uint64_t*)(image + a.sel_off[t]);
+    const uint64_t wi = 64 * r + lane;
+    const uint64_t w = wi < nw ? words[wi] : 0ull;
+    const uint32_t c = wi < nw ? (uint32_t)min<uint64_t>(P, m - wi * P) : 0u;
+    for (uint32_t g = 0; g < d; g++) {
+        const uint32_t v = wv_count_digit(w, D, g, c);
+        const uint32_t inc = wv_wave_incl_scan(v);
+        const uint64_t base = rng[r * d + g];                          // digits g before the range
+        const uint64_t o = wv_cdiv(base, WV_SEL_STRIDE) * WV_SEL_STRIDE;   // the next sampled ordinal
+        if (o >= base + inc - v && o < base + inc)
+            sel[g * a.nsel + o / WV_SEL_STRIDE] = wi * P + wv_digit_select(w, D, g, c, (uint32_t)(o - (base + inc - v)));
+    }
+}
+
+// samples past each value's last one: the level length
+__global__ void __launch_bounds__(DIR_THREADS)
+msel_fill_k(uint8_t* __restrict__ image, MLevels a)
+{
+    const uint32_t t = blockIdx.y, d = 1u << a.D;
+    const uint64_t nr = wv_mranges(a.m, a.D);
+    const uint64_t* rng = (const uint64_t*)(image + a.rank_off[t]);
+    uint64_t* sel = (uint64_t*)(image + a.sel_off[t]);
+    for (uint64_t i = (uint64_t)blockIdx.x * DIR_THREADS + threadIdx.x; i < d * a.nsel; i += (uint64_t)gridDim.x * DIR_THREADS) {
+        const uint64_t g = i / a.nsel, k = i % a.nsel;
+        if (k >= wv_cdiv(rng[nr * d + g], WV_SEL_STRIDE)) sel[i] = a.m;
+    }
+}
+
+hipError_t launch_msel(uint8_t* image, const MLevels& a, hipStream_t s)
+{
+    const uint64_t nr = wv_mranges(a.m, a.D);
+    const uint64_t d = 1ull << a.D;
+    if (nr) msel_k<<<dim3((uint32_t)wv_cdiv(nr, DIR_THREADS / 64), a.M), DIR_THREADS, 0, s>>>(image, a);
+    msel_fill_k<<<dim3((uint32_t)std::min<uint64_t>(wv_cdiv(d * a.nsel, DIR_THREADS), 1024), a.M), DIR_THREADS, 0, s>>>(
+        image, a);
+    return hipGetLastError();
+}
 
 __global__ void __launch_bounds__(DIR_THREADS)
 mcount_k(const uint8_t* __restrict__ image, MLevels a, uint32_t* __restrict__ rng_cnt)
@@ -216,6 +268,9 @@ header_k(uint8_t* __restrict__ img, wv_layout_in in)
                 span_hi[s++] = L.sel0_off + 8 * L.nsel;
                 span_lo[s] = L.sel1_off;
                 span_hi[s++] = L.sel1_off + 8 * L.nsel;
+            } else {
+                span_lo[s] = L.sel0_off;
+                span_hi[s++] = L.sel0_off + (8ull << in.arity_log2) * L.nsel;
             }
         }
         if (in.kind == WT_KIND_SHAPED) {
@@ -378,9 +433,11 @@ hipError_t wv_multiary_counters(uint8_t* image, const wv_level* lv, uint32_t M, 
     a.m = lv[0].n;
     a.M = M;
     a.D = D;
+    a.nsel = lv[0].nsel;
     for (uint32_t t = 0; t < M; t++) {
         a.bits_off[t] = lv[t].bits_off;
         a.rank_off[t] = lv[t].rank_off;
+        a.sel_off[t] = lv[t].sel0_off;
     }
     const uint64_t nr = wv_mranges(a.m, D);
     const uint32_t d = 1u << D;
@@ -390,7 +447,7 @@ hipError_t wv_multiary_counters(uint8_t* image, const wv_level* lv, uint32_t M, 
     if (e != hipSuccess) return e;
     if (nr) mwrite_k<<<grid, DIR_THREADS, 0, s>>>(image, a, sc.rng_pre);
     mfinish_k<<<M, 64, 0, s>>>(image, a, sc.totals);
-    return hipGetLastError();
+    return launch_msel(image, a, s);
 }
 
 hipError_t wv_multiary_ranges(uint8_t* image, const wv_level* lv, uint32_t M, uint32_t D,
@@ -401,9 +458,11 @@ hipError_t wv_multiary_ranges(uint8_t* image, const wv_level* lv, uint32_t M, ui
     a.m = lv[0].n;
     a.M = M;
     a.D = D;
+    a.nsel = lv[0].nsel;
     for (uint32_t t = 0; t < M; t++) {
         a.bits_off[t] = lv[t].bits_off;
         a.rank_off[t] = lv[t].rank_off;
+        a.sel_off[t] = lv[t].sel0_off;
     }
     const uint64_t nr = wv_mranges(a.m, D);
     const uint32_t d = 1u << D;
@@ -411,7 +470,7 @@ hipError_t wv_multiary_ranges(uint8_t* image, const wv_level* lv, uint32_t M, ui
     if (e != hipSuccess) return e;
     if (nr) mrange_k<<<dim3((uint32_t)wv_cdiv(nr * d, DIR_THREADS), M), DIR_THREADS, 0, s>>>(image, a, sc.rng_pre);
     mfinish_k<<<M, 64, 0, s>>>(image, a, sc.totals);
-    return hipGetLastError();
+    return launch_msel(image, a, s);
 }
 
 hipError_t wv_write_header(uint8_t* image, const wv_layout_in& in, hipStream_t s)

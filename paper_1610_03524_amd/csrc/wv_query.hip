@@ -324,13 +324,30 @@ __device__ uint64_t q_select(const QImg& q, uint32_t c, uint64_t k)
         }
         return rel;
     }
-    // multiary: smallest p with count(c in [0, p]) >= k
-    uint64_t lo = 0, hi = q.n - 1;
-    while (lo < hi) {
-        const uint64_t mid = (lo + hi) / 2;
-        if (q_count_prefix(q, c, mid + 1) >= k) hi = mid; else lo = mid + 1;
+    // multiary: the descent gives c's node start on every level; walking up,
+    // the rel-th symbol of a child node is the (rel+1)-th digit of its value
+    // in the parent node: a generalized select on that level (Sec. 5.2)
+    uint64_t starts[WV_MAX_LEVELS];
+    uint64_t s = 0, e = q.n;
+    for (uint32_t l = 0; l < L; l++) {
+        starts[l] = s;
+        const uint32_t g = (c >> (q.D * (L - 1 - l))) & ((1u << q.D) - 1u);
+        uint64_t below = 0;
+        for (uint32_t cc = 0; cc < g; cc++) below += mrank(q, l, cc, e) - mrank(q, l, cc, s);
+        const uint64_t gs = mrank(q, l, g, s);
+        const uint64_t cs = s + below;
+        e = cs + mrank(q, l, g, e) - gs;
+        s = cs;
     }
-    return lo;
+    uint64_t rel = k - 1;
+    for (uint32_t l = L; l-- > 0;) {
+        const uint32_t g = (c >> (q.D * (L - 1 - l))) & ((1u << q.D) - 1u);
+        const uint64_t st = starts[l];
+        const QLevel& lv = q.lv[l];
+        rel = wv_mselect(words_of(q, l), q.img + lv.rank_off, (const uint64_t*)(q.img + lv.sel0_off), lv.nsel, lv.n,
+                         q.D, g, mrank(q, l, g, st) + rel) - st;
+    }
+    return rel;
 }
 
 __global__ void __launch_bounds__(Q_THREADS)

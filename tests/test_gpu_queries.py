@@ -2,7 +2,8 @@
 import numpy as np
 import pytest
 
-from gpu_util import to_device
+import oracle
+from gpu_util import assert_same, to_device
 from paper_1610_03524_amd import binding as B
 from test_gpu_parity import dtype_for, shaped_inputs
 
@@ -94,3 +95,39 @@ def test_multiary_queries_when_n_ends_a_sub_range(D, subs):
         S = rng.integers(0, sigma, n).astype(dtype_for(sigma))
         img, _ = B.build(B.KIND_MULTIARY, to_device(S), sigma, arity_log2=D)
         run_queries(img, S, sigma, rng)
+
+
+@pytest.mark.parametrize("D", [1, 2, 3, 4])
+def test_multiary_select_through_digit_samples(D):
+    """Select on multiary trees walks up with the generalized select of every
+    level (Sec. 5.2): a digit value's sample of ordinal 4096*floor(o/4096),
+    the range and sub-range counters, then the words.  Skewed symbols give
+    dense values (many samples) and sparse ones (samples many ranges apart);
+    every answer equals brute force on S and the image the oracle's."""
+    import torch
+    rng = np.random.default_rng(300 + D)
+    n, sigma = 400003, 1500
+    S = np.minimum(rng.geometric(0.004, n) - 1, sigma - 1).astype(np.uint16)
+    St = to_device(S)
+    img, _ = B.build(B.KIND_MULTIARY, St, sigma, arity_log2=D)
+    torch.cuda.synchronize()
+    assert_same(img.cpu().numpy(), oracle.build_image(oracle.KIND_MULTI, S, sigma, D), f"D={D}")
+    vals, cnts = np.unique(S, return_counts=True)
+    cs, ks = [], []
+    for c, cnt in zip(vals, cnts):
+        picks = {1, int(cnt)} | {int(x) for x in rng.integers(1, cnt + 1, 6)}
+        picks |= {k for k in (4096, 4097, 8192, 8191) if k <= cnt}
+        for k in picks:
+            cs.append(int(c))
+            ks.append(k)
+    cs.append(int(vals[0])); ks.append(int(cnts[0]) + 1)          # past the count
+    cs.append(sigma - 1 if (sigma - 1) not in set(vals.tolist()) else 0); ks.append(1)
+    c = np.array(cs, dtype=np.int64)
+    k = np.array(ks, dtype=np.int64)
+    got = B.select(img, torch.from_numpy(c.astype(np.int32)).cuda(), torch.from_numpy(k).cuda()).cpu().numpy()
+    order = np.argsort(S, kind="stable")
+    first = np.searchsorted(S[order], c, side="left")
+    last = np.searchsorted(S[order], c, side="right")
+    ok = (k >= 1) & (k <= last - first)
+    want = np.where(ok, order[np.minimum(first + k - 1, n - 1)], -1)
+    assert np.array_equal(got, want.astype(np.int64)), f"D={D}: {np.count_nonzero(got != want)} wrong"
