@@ -237,6 +237,18 @@ int wt_symbol_counts(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sig
  * exceeds 32. */
 int wt_huffman_codes(const uint64_t* counts, uint32_t sigma, uint64_t* codes, uint32_t* code_len);
 
+/* The same codewords computed on the device (the paper notes Huffman
+ * codewords can be generated in parallel, Sec. 4.3), from device counts,
+ * e.g. those of wt_symbol_counts: counts, codes, code_len (sigma entries
+ * each) and status (one entry) are dev arrays; asynchronous on `stream`, one
+ * workgroup, no workspace.  *status becomes WT_OK, or WT_EUNSUP when a length
+ * exceeds 32 (codes and lengths then 0).  Returns WT_EUNSUP for sigma above
+ * WT_HUFFMAN_DEV_MAX_SIGMA (use wt_huffman_codes), WT_EINVAL for sigma 0 or
+ * a null pointer. */
+#define WT_HUFFMAN_DEV_MAX_SIGMA 4096u
+int wt_huffman_codes_dev(const uint64_t* counts, uint32_t sigma, uint64_t* codes, uint32_t* code_len,
+                         int32_t* status, void* stream);
+
 /* One sequence of a batched build.  S, out: dev pointers, 16-byte aligned
  * (as is the batch workspace; else WT_EINVAL).  tau: key bits
  * per pass for this sequence (0 = the batch tuning, else automatic); the

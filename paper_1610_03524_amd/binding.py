@@ -73,6 +73,7 @@ _SIGS = {
     "wt_select": (c_int, [c_vp, c_vp, c_vp, c_vp, c_u64, c_vp]),
     "wt_symbol_counts": (c_int, [c_vp, c_u64, c_u32, c_u32, c_vp, c_vp]),
     "wt_huffman_codes": (c_int, [c_vp, c_u32, c_vp, c_vp]),
+    "wt_huffman_codes_dev": (c_int, [c_vp, c_u32, c_vp, c_vp, c_vp, c_vp]),
     "wt_batch_plan": (c_int, [c_int, c_vp, c_u32, c_vp, c_vp]),
     "wt_batch_build": (c_int, [c_int, c_vp, c_u32, c_vp, ctypes.c_size_t, c_vp, c_vp]),
     "wt_image_bytes": (c_int, [c_vp, c_vp, c_vp]),
@@ -289,6 +290,22 @@ def huffman_codes(counts: np.ndarray):
     _check(lib().wt_huffman_codes(counts.ctypes.data, counts.size, codes.ctypes.data, lens.ctypes.data),
            "wt_huffman_codes")
     return codes, lens
+
+
+def huffman_codes_dev(counts, stream=None):
+    """canonical Huffman codewords computed on the device from device counts
+    (int64 tensor of sigma); returns (codes int64, lengths int32, status int32)
+    device tensors, not synchronized"""
+    import torch
+    _arg(counts, "counts", _U64, "wt_huffman_codes_dev")
+    _on_device("wt_huffman_codes_dev", counts)
+    sigma = counts.numel()
+    codes = torch.empty(sigma, dtype=torch.int64, device=counts.device)
+    lens = torch.empty(sigma, dtype=torch.int32, device=counts.device)
+    status = torch.empty(1, dtype=torch.int32, device=counts.device)
+    _check(lib().wt_huffman_codes_dev(_ptr(counts), sigma, _ptr(codes), _ptr(lens), _ptr(status), _stream(stream)),
+           "wt_huffman_codes_dev")
+    return codes, lens, status
 
 
 def image_bytes(image, stream=None) -> int:

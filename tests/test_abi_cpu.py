@@ -244,3 +244,14 @@ def test_no_alloc_build_refuses_sizes_beyond_its_scratch():
     assert L.wm_build_noalloc(0x10000, 1 << 28, 1 << 16, 4, None, 0x20000, 1 << 31, None) == B.WT_ENOSPC
     assert L.wm_build_noalloc(0x10000, 1000, 0, 4, None, 0x20000, 1 << 20, None) == B.WT_EINVAL
     assert L.wm_build_noalloc(0x10000, 1000, 100, 3, None, 0x20000, 1 << 20, None) == B.WT_EINVAL
+
+
+def test_device_huffman_refuses_on_the_host():
+    """wt_huffman_codes_dev checks its arguments before launching (no GPU
+    needed): sigma above its one-workgroup limit, sigma 0, null pointers"""
+    L = B.lib()
+    p = 0x10000
+    assert L.wt_huffman_codes_dev(p, 4097, p, p, p, None) == B.WT_EUNSUP
+    assert L.wt_huffman_codes_dev(p, 0, p, p, p, None) == B.WT_EINVAL
+    assert L.wt_huffman_codes_dev(None, 10, p, p, p, None) == B.WT_EINVAL
+    assert L.wt_huffman_codes_dev(p, 10, p, p, None, None) == B.WT_EINVAL
