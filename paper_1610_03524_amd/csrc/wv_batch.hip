@@ -120,39 +120,17 @@ __device__ void b_pass_body(const SeqRound* __restrict__ seqs, const uint32_t* _
     for (;;) {
         if (threadIdx.x == 0) item_s = atomicAdd(queue, 1u);
         __syncthreads();
-        const uint32_t item = item_s;
+        // uniform across the workgroup: the descriptor loads below are scalar
+        const uint32_t item = (uint32_t)__builtin_amdgcn_readfirstlane((int)item_s);
         __syncthreads();
         if (item >= nchunks) break;
-        const uint32_t s = owner_of(chunk0, nseq, item);
+        const uint32_t s = (uint32_t)__builtin_amdgcn_readfirstlane((int)owner_of(chunk0, nseq, item));
         const SeqRound& q = seqs[s];
         const uint32_t b = item - q.chunk0;
-        const uint32_t ib = q.in_bytes, ob = q.out_bytes;
-        // any input width (the first pass reads S as stored); the payload
-        // width follows the remaining key bits: at most 15 with 16-bit keys,
-        // at least 9 with 32-bit keys (17 or more bits, tau <= 8)
-        if constexpr (sizeof(KT_) == 2) {
-            if (ib == 1) {
-                if (ob == 2) wm_pass_chunk<uint8_t, uint16_t, KT_>(q.pa, b, sh);
-                else wm_pass_chunk<uint8_t, uint8_t, KT_>(q.pa, b, sh);
-            } else if (ib == 2) {
-                if (ob == 2) wm_pass_chunk<uint16_t, uint16_t, KT_>(q.pa, b, sh);
-                else wm_pass_chunk<uint16_t, uint8_t, KT_>(q.pa, b, sh);
-            } else {
-                if (ob == 2) wm_pass_chunk<uint32_t, uint16_t, KT_>(q.pa, b, sh);
-                else wm_pass_chunk<uint32_t, uint8_t, KT_>(q.pa, b, sh);
-            }
-        } else {
-            if (ib == 1) {
-                if (ob == 4) wm_pass_chunk<uint8_t, uint32_t, KT_>(q.pa, b, sh);
-                else wm_pass_chunk<uint8_t, uint16_t, KT_>(q.pa, b, sh);
-            } else if (ib == 2) {
-                if (ob == 4) wm_pass_chunk<uint16_t, uint32_t, KT_>(q.pa, b, sh);
-                else wm_pass_chunk<uint16_t, uint16_t, KT_>(q.pa, b, sh);
-            } else {
-                if (ob == 4) wm_pass_chunk<uint32_t, uint32_t, KT_>(q.pa, b, sh);
-                else wm_pass_chunk<uint32_t, uint16_t, KT_>(q.pa, b, sh);
-            }
-        }
+        // any input width (the first pass reads S as stored) and payload
+        // width: both are read at run time, so the kernel holds one copy of
+        // the pass
+        wm_pass_chunk<KT_>(q.pa, b, sh);
         __syncthreads();
     }
 }
@@ -625,6 +603,8 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
                     e.status = r == 0 ? (uint32_t*)((uint8_t*)seqs[i].out + 36) : nullptr;
                     e.in_bytes = cur_bytes[i];
                     e.out_bytes = rem ? width_of(rem) : 1;
+                    e.pa.in_bytes = e.in_bytes;
+                    e.pa.out_bytes = e.out_bytes;
                     e.sigma = sp.sigma;
                     e.chunk0 = chunks;
                     first[k] = chunks;

@@ -37,6 +37,8 @@ struct PassArgs {
     uint32_t n, C, K;       // elements, chunk length (multiple of T), chunks
     uint32_t R, tau;        // key bits still to do, digit bits of this pass
     uint32_t keymask;       // applied to the loaded keys
+    uint32_t in_bytes;      // width of the input keys (1, 2, 4)
+    uint32_t out_bytes;     // width of the compacted remaining keys written (1, 2, 4)
 };
 
 template <typename T_>
@@ -109,6 +111,17 @@ __device__ inline void load_tile(const void* in, uint32_t ts, uint32_t tc, uint3
     for (uint32_t p = tc + threadIdx.x; p < (uint32_t)T; p += NT) buf[p] = (KT_)~0u;
 }
 
+// the tile's keys from input of any width (a switch per tile: the kernels
+// hold one copy of the pass for every width)
+template <typename KT_>
+__device__ inline void load_tile_any(const void* in, uint32_t in_bytes, uint32_t ts, uint32_t tc, uint32_t keymask,
+                                     KT_* buf)
+{
+    if (in_bytes == 1) load_tile<uint8_t, KT_>(in, ts, tc, keymask, buf);
+    else if (in_bytes == 2) load_tile<uint16_t, KT_>(in, ts, tc, keymask, buf);
+    else load_tile<uint32_t, KT_>(in, ts, tc, keymask, buf);
+}
+
 // zeros among the first s bits of the tile bit string (s <= tile length)
 __device__ inline uint32_t local_rank0(const uint64_t* lb, const uint32_t* zw, uint32_t s)
 {
@@ -136,7 +149,7 @@ struct PassShared {
 };
 
 // One chunk b of one pass (see the file comment of wv_wm_passes.hip).
-template <typename IT, typename OT, typename KT_>
+template <typename KT_>
 __device__ void wm_pass_chunk(const PassArgs& a, uint32_t b, PassShared<KT_>& S)
 {
     KT_* buf = S.buf;
@@ -166,7 +179,7 @@ __device__ void wm_pass_chunk(const PassArgs& a, uint32_t b, PassShared<KT_>& S)
 
     for (uint32_t ts = cstart; ts < cend; ts += T) {
         const uint32_t tc = min((uint32_t)T, cend - ts);
-        load_tile<IT, KT_>(a.in, ts, tc, a.keymask, buf);
+        load_tile_any<KT_>(a.in, a.in_bytes, ts, tc, a.keymask, buf);
         if (tid == 0) { cnt[0] = tc; ls[0] = 0; }
         __syncthreads();
 
@@ -317,12 +330,16 @@ __device__ void wm_pass_chunk(const PassArgs& a, uint32_t b, PassShared<KT_>& S)
         }
         // remaining key bits to the order of the next pass
         if (a.pay_out) {
+            const uint32_t ob = a.out_bytes;
             for (int e = 0; e < E; e++) {
                 const uint32_t p = tid + NT * e;
                 if (p < tc) {
                     const uint32_t x = buf[p];
                     const uint32_t gi = gidx(tau, (x >> dshift) & dmask);
-                    ((OT*)a.pay_out)[g[gi] + (p - ls[gi])] = (OT)(x & pmask);
+                    const uint32_t at = g[gi] + (p - ls[gi]);
+                    if (ob == 1) ((uint8_t*)a.pay_out)[at] = (uint8_t)(x & pmask);
+                    else if (ob == 2) ((uint16_t*)a.pay_out)[at] = (uint16_t)(x & pmask);
+                    else ((uint32_t*)a.pay_out)[at] = x & pmask;
                 }
             }
         }

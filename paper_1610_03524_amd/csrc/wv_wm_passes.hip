@@ -38,20 +38,18 @@ namespace {
 
 // 16-bit keys in LDS: four workgroups per CU (8 waves per SIMD, 64 VGPRs);
 // 32-bit keys: LDS holds three workgroups per CU, so 6 waves per SIMD
-template <typename IT, typename OT>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8)))
 wm_pass16_k(PassArgs a)
 {
     __shared__ PassShared<uint16_t> sh;
-    wm_pass_chunk<IT, OT, uint16_t>(a, blockIdx.x, sh);
+    wm_pass_chunk<uint16_t>(a, blockIdx.x, sh);
 }
 
-template <typename IT, typename OT>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6)))
 wm_pass32_k(PassArgs a)
 {
     __shared__ PassShared<uint32_t> sh;
-    wm_pass_chunk<IT, OT, uint32_t>(a, blockIdx.x, sh);
+    wm_pass_chunk<uint32_t>(a, blockIdx.x, sh);
 }
 
 template <typename IT>
@@ -80,20 +78,10 @@ Geometry geometry(uint64_t n, uint32_t blocks, uint32_t L)
     return Geometry{(uint32_t)wv_cdiv(n ? n : 1, C), (uint32_t)C};
 }
 
-template <typename IT, typename OT>
 void launch_pass(const PassArgs& a, hipStream_t s)
 {
-    if (a.R <= 16) wm_pass16_k<IT, OT><<<a.K, NT, 0, s>>>(a);
-    else wm_pass32_k<IT, OT><<<a.K, NT, 0, s>>>(a);
-}
-
-template <typename IT>
-void launch_pass_out(const PassArgs& a, uint32_t out_bytes, hipStream_t s)
-{
-    if (!a.pay_out) launch_pass<IT, uint8_t>(a, s);
-    else if (out_bytes == 1) launch_pass<IT, uint8_t>(a, s);
-    else if (out_bytes == 2) launch_pass<IT, uint16_t>(a, s);
-    else launch_pass<IT, uint32_t>(a, s);
+    if (a.R <= 16) wm_pass16_k<<<a.K, NT, 0, s>>>(a);
+    else wm_pass32_k<<<a.K, NT, 0, s>>>(a);
 }
 
 __global__ void zero_u32_k(uint32_t* p, uint32_t count)
@@ -194,10 +182,9 @@ hipError_t wv_wm_levels(const wv_wm_plan& p, const void* S, uint64_t* const* lev
             pa.R = R;
             pa.tau = tau;
             pa.keymask = keymask;
-            WV_TIMED(pr, s, "wm_pass",
-                     if (in_bytes == 1) launch_pass_out<uint8_t>(pa, width_bytes(rem), s);
-                     else if (in_bytes == 2) launch_pass_out<uint16_t>(pa, width_bytes(rem), s);
-                     else launch_pass_out<uint32_t>(pa, width_bytes(rem), s));
+            pa.in_bytes = in_bytes;
+            pa.out_bytes = width_bytes(rem);
+            WV_TIMED(pr, s, "wm_pass", launch_pass(pa, s));
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
             in = pa.pay_out;
