@@ -250,7 +250,7 @@ def main():
 
     import torch
     from paper_1610_03524_amd import binding as B
-    from paper_1610_03524_amd import inputs
+    from paper_1610_03524_amd import inputs, tune as T
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
@@ -258,7 +258,8 @@ def main():
     n = 1 << 28
     S = inputs.c2_zipf(n=n, sigma=sigma, seed=2, device=dev)
     torch.cuda.synchronize()
-    tune = B.make_tuning(flags=B.FLAG_PROFILE)
+    tau, tile = T.choose_tuning(n, sigma)   # the tuner's choice for this shape (0 = automatic)
+    tune = B.make_tuning(tau=tau, tile=tile, flags=B.FLAG_PROFILE)
     info = B.plan(B.KIND_WM, n, sigma, 4, tune=tune)
     out = torch.empty(info.out_bytes, dtype=torch.uint8, device=dev)
     ws = torch.empty(info.workspace_bytes, dtype=torch.uint8, device=dev)
@@ -276,7 +277,7 @@ def main():
     prof = B.profile_read()
     assert B.check(out, stream) == B.WT_OK
     t = ms / 1e3
-    plain_tune = B.make_tuning()
+    plain_tune = B.make_tuning(tau=tau, tile=tile)
     per_build = per_build_times(lambda: B.build_into(B.KIND_WM, S, sigma, out, ws, tune=plain_tune, stream=stream),
                                 stream)
     copy_gbps = device_copy_gbps()
@@ -304,7 +305,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "C2 wavelet matrix: n=2^28 uint32, sigma=2^16, Zipf(s=1.1) over a permuted "
                                "alphabet, 16 levels + rank directory + select samples",
-                   "n": n, "sigma": sigma, "levels": info.nlevels, "tau": info.tau},
+                   "n": n, "sigma": sigma, "levels": info.nlevels, "tau": info.tau,
+                   "tiles_per_chunk": tile or "automatic"},
         "symbol_levels_per_s": round(symbol_levels(info) / t, 1),
         "roofline": {"bound": "hbm", "kernel": "wm_pass", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
@@ -515,12 +517,14 @@ def bench_batch(args):
         d.tau = T.choose_tau(int(ns[i]), int(sig[i]))
         descs.append(d)
     descs = B.desc_array(descs)   # marshalled once, outside the timed calls
-    need = B.batch_plan(B.KIND_WM, descs)
+    batch_tile = T.choose_batch_tile()
+    batch_tune = B.make_tuning(tile=batch_tile)
+    need = B.batch_plan(B.KIND_WM, descs, batch_tune)
     ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
     single_ws = torch.empty(max(inf.workspace_bytes for inf in infos), dtype=torch.uint8, device=dev)
 
     def batched():
-        rc = B.batch_build(B.KIND_WM, descs, ws, stream=stream)
+        rc = B.batch_build(B.KIND_WM, descs, ws, batch_tune, stream=stream)
         if rc != 0:
             raise RuntimeError(B.strerror(rc))
 
@@ -561,8 +565,42 @@ def bench_batch(args):
             each.append(time.perf_counter() - t0)
         res[name] = float(np.median(each))
         spread[name] = [round(float(v), 4) for v in np.percentile(each, [10, 90])]
+    # kernel launches of one batch, from the library's own per-kernel counters
+    B.profile_read()
+    rc = B.batch_build(B.KIND_WM, descs, ws, B.make_tuning(tile=batch_tile, flags=B.FLAG_PROFILE), stream=stream)
+    if rc != 0:
+        raise RuntimeError(B.strerror(rc))
+    torch.cuda.synchronize()
+    launches = {name: int(v[0]) for name, v in sorted(B.profile_read().items())}
+    # the same batch captured once in a HIP graph and replayed: one graph
+    # launch per batch, and the images equal the eager ones
+    batched()
+    torch.cuda.synchronize()
+    eager_images = images.clone()
+    gs = torch.cuda.Stream()
+    gs.wait_stream(stream)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=gs, capture_error_mode="relaxed"):
+        rc = B.batch_build(B.KIND_WM, descs, ws, batch_tune, stream=gs)
+    if rc != 0:
+        raise RuntimeError(B.strerror(rc))
+    images.fill_(0xA5)
+    torch.cuda.synchronize()
+    graph.replay()
+    torch.cuda.synchronize()
+    if not torch.equal(images, eager_images):
+        raise RuntimeError("graph-replayed batch differs from the eager batch")
+    del eager_images
+    each = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        graph.replay()
+        torch.cuda.synchronize()
+        each.append(time.perf_counter() - t0)
+    res["graph"] = float(np.median(each))
+    spread["graph"] = [round(float(v), 4) for v in np.percentile(each, [10, 90])]
     balg = sum(4 * int(ns[i]) + infos[i].out_bytes for i in range(k))
-    tb, tp, t4 = res["batched"], res["plain"], res["plain_4_streams"]
+    tb, tp, t4, tg = res["batched"], res["plain"], res["plain_4_streams"], res["graph"]
     line = {
         "metric": METRIC, "value": round(total * 4 / tb / 1e9, 3), "unit": "GB/s", "n_gpus": 1,
         "steps": reps, "warmup": 1, "ms_per_step": round(tb * 1e3, 3), "higher_is_better": True,
@@ -571,7 +609,12 @@ def bench_batch(args):
                                f"sigma log-uniform [4, 2^20]", "symbols": total},
         "batched": {"s": round(tb, 4), "p10_p90_s": spread["batched"], "builds_per_s": round(k / tb, 1),
                     "input_GBps": round(total * 4 / tb / 1e9, 2),
-                    "build_roofline_frac": round(balg / tb / 1e9 / HBM_PEAK_GBPS, 4)},
+                    "build_roofline_frac": round(balg / tb / 1e9 / HBM_PEAK_GBPS, 4),
+                    "tiles_per_chunk": batch_tile or "automatic",
+                    "kernel_launches": sum(launches.values()), "launches_by_kernel": launches},
+        "batched_graph_replay": {"s": round(tg, 4), "p10_p90_s": spread["graph"], "builds_per_s": round(k / tg, 1),
+                                 "input_GBps": round(total * 4 / tg / 1e9, 2), "graph_launches": 1,
+                                 "images_equal_eager": True},
         "plain": {"s": round(tp, 4), "p10_p90_s": spread["plain"], "builds_per_s": round(k / tp, 1),
                   "input_GBps": round(total * 4 / tp / 1e9, 2)},
         "plain_4_streams": {"s": round(t4, 4), "p10_p90_s": spread["plain_4_streams"],

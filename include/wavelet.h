@@ -118,12 +118,15 @@ typedef struct wt_shape {
 
 typedef struct wt_tuning {
     uint32_t tau;      /* key bits per partition pass, 1..8 (0 = automatic) */
-    uint32_t tile;     /* reserved, ignored: a pass tile is 8192 keys       */
+    uint32_t tile;     /* tiles of 8192 keys per chunk (0 = automatic);
+                          ignored when `blocks` is set                      */
     uint32_t blocks;   /* chunks (workgroups) per pass (0 = automatic: one
                           per tile, at most the resident pass workgroups:
                           1024 = 4 per CU when the first pass's keys fit 16
-                          bits, else 768 = 3 per CU; a batch sizes its
-                          chunks by the whole batch)                        */
+                          bits, else 768 = 3 per CU; a batch without `tile`
+                          sizes its chunks by the whole batch: up to 16
+                          tiles, while every resident pass workgroup still
+                          gets about 4 chunks)                              */
     uint32_t flags;    /* WT_FLAG_*                                         */
 } wt_tuning;
 
@@ -271,10 +274,14 @@ int wt_batch_plan(int kind, const wt_seq_desc* seqs, uint32_t count, const wt_tu
 /* Build wavelet matrices (kind WT_KIND_WM) of many sequences with a few
  * persistent launches; each image equals the one wm_build writes for that
  * sequence alone.  seqs: host array of count descriptors (read during the
- * call only).  Asynchronous on `stream`: the per-round descriptors are
- * staged in a pinned host buffer that a kernel copies into ws; the buffer
- * returns to the library's pool once `stream` has passed the copies (kept
- * for good when `stream` is being captured). */
+ * call only).  Asynchronous on `stream`: every descriptor of the batch is
+ * written into a pinned host buffer before the first launch and one kernel
+ * copies it into ws; the buffer returns to the library's pool once `stream`
+ * has passed that copy (kept for good when `stream` is being captured).
+ * Launches per batch: 2 + 4 per group + 3, a group being the sequences of
+ * one round of passes whose keys fit 16 bits, or those whose keys do not
+ * (a round of passes holds every sequence with levels left to build).
+ * tune->tile: tiles per chunk for every sequence of the batch. */
 int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count,
                    void* ws, size_t ws_bytes, const wt_tuning* tune, void* stream);
 

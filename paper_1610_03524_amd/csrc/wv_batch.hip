@@ -9,10 +9,14 @@
 // queue (largest sequences first), and finally the directories of every
 // level of every sequence.  Sequences with more levels take more rounds of
 // passes; a round only holds the sequences that still have levels to build.
-// The host writes the descriptors of every phase into a pinned buffer; a
-// phase is copied and launched as soon as it is written, so the host fills
-// later phases while earlier ones run.  The call returns when the batch is
-// complete.
+// The host writes the descriptors of every phase into one pinned buffer
+// before the first launch; one kernel copies them to the workspace, and the
+// call returns once everything is queued (stream-ordered, so a batch can be
+// captured in a graph).  Launches: the copy, the headers (which also clear
+// the histogram area and the work queues), four per group of a round
+// (histograms, their prefix, run offsets, the persistent pass, which clears
+// the histogram area again for the next group) and three for the
+// directories.
 #include <algorithm>
 #include <cstring>
 #include <numeric>
@@ -42,6 +46,13 @@ struct SpanDesc {
 
 constexpr uint32_t SDW = 512;   // words per directory chunk
 constexpr uint32_t SDG = 8;     // directory chunks per workgroup (one descriptor search each)
+
+// grid-stride clear of count words (every workgroup of the launch takes part)
+__device__ inline void grid_zero(uint32_t* p, uint64_t count)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
 
 // global item -> owner, over an exclusive prefix array of `count` owners
 __device__ inline uint32_t owner_of(const uint32_t* first, uint32_t count, uint32_t item)
@@ -112,10 +123,13 @@ b_offsets_k(const SeqRound* __restrict__ seqs, const uint32_t* __restrict__ chun
     wm_chunk_offsets(sh, b, tau, a.n, (uint32_t*)a.G0, a.words);
 }
 
-// persistent pass: workgroups take chunks from the queue until it is empty
+// persistent pass: workgroups take chunks from the queue until it is empty,
+// then clear the histogram area for the next group (its histograms were read
+// by the offsets launch before this one)
 template <typename KT_>
 __device__ void b_pass_body(const SeqRound* __restrict__ seqs, const uint32_t* __restrict__ chunk0, uint32_t nseq,
-                            uint32_t nchunks, uint32_t* __restrict__ queue, PassShared<KT_>& sh, uint32_t& item_s)
+                            uint32_t nchunks, uint32_t* __restrict__ queue, uint32_t* __restrict__ zero,
+                            uint64_t nzero, PassShared<KT_>& sh, uint32_t& item_s)
 {
     for (;;) {
         if (threadIdx.x == 0) item_s = atomicAdd(queue, 1u);
@@ -133,25 +147,26 @@ __device__ void b_pass_body(const SeqRound* __restrict__ seqs, const uint32_t* _
         wm_pass_chunk<KT_>(q.pa, b, sh);
         __syncthreads();
     }
+    grid_zero(zero, nzero);
 }
 
 // 16-bit keys in LDS: four workgroups per CU; 32-bit keys: three (LDS-bound)
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8)))
 b_pass16_k(const SeqRound* __restrict__ seqs, const uint32_t* __restrict__ chunk0, uint32_t nseq,
-           uint32_t nchunks, uint32_t* __restrict__ queue)
+           uint32_t nchunks, uint32_t* __restrict__ queue, uint32_t* __restrict__ zero, uint64_t nzero)
 {
     __shared__ PassShared<uint16_t> sh;
     __shared__ uint32_t item_s;
-    b_pass_body<uint16_t>(seqs, chunk0, nseq, nchunks, queue, sh, item_s);
+    b_pass_body<uint16_t>(seqs, chunk0, nseq, nchunks, queue, zero, nzero, sh, item_s);
 }
 
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6)))
 b_pass32_k(const SeqRound* __restrict__ seqs, const uint32_t* __restrict__ chunk0, uint32_t nseq,
-           uint32_t nchunks, uint32_t* __restrict__ queue)
+           uint32_t nchunks, uint32_t* __restrict__ queue, uint32_t* __restrict__ zero, uint64_t nzero)
 {
     __shared__ PassShared<uint32_t> sh;
     __shared__ uint32_t item_s;
-    b_pass_body<uint32_t>(seqs, chunk0, nseq, nchunks, queue, sh, item_s);
+    b_pass_body<uint32_t>(seqs, chunk0, nseq, nchunks, queue, zero, nzero, sh, item_s);
 }
 
 
@@ -286,8 +301,12 @@ b_dir_write_k(const SpanDesc* __restrict__ spans, const uint32_t* __restrict__ c
 }
 
 __global__ void __launch_bounds__(256)
-b_header_k(uint8_t* const* __restrict__ images, const wv_layout_in* __restrict__ lins)
+b_header_k(uint8_t* const* __restrict__ images, const wv_layout_in* __restrict__ lins, uint32_t count,
+           uint32_t* __restrict__ zero, uint64_t nzero)
 {
+    // the work queues and the histogram area start at zero
+    grid_zero(zero, nzero);
+    if (blockIdx.x >= count) return;   // whole workgroups; clearing only
     // same header writer as a single build, one workgroup per image
     __shared__ wv_layout_out lay;
     __shared__ uint64_t span_lo[4 * WV_MAX_LEVELS + 4], span_hi[4 * WV_MAX_LEVELS + 4];
@@ -327,12 +346,6 @@ b_header_k(uint8_t* const* __restrict__ images, const wv_layout_in* __restrict__
         for (uint64_t b = span_hi[s] + threadIdx.x; b < span_lo[s + 1]; b += blockDim.x) img[b] = 0;
 }
 
-__global__ void b_zero_k(uint32_t* p, uint64_t count)
-{
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
-        p[i] = 0;
-}
-
 inline uint32_t width_of(uint32_t bits) { return bits <= 8 ? 1u : (bits <= 16 ? 2u : 4u); }
 
 // ---- host planning -----------------------------------------------------------------
@@ -365,7 +378,7 @@ struct BatchPlan {
     std::vector<SeqPlan> seq;
     std::vector<uint32_t> order;     // sequences by decreasing n
     uint64_t off_desc = 0, off_queue = 0, ws_bytes = 0;
-    uint64_t zero_lo = 0, zero_hi = 0;   // H region zeroed every round
+    uint64_t zero_lo = 0, zero_hi = 0;   // H region, cleared before every group
     uint32_t max_passes = 0, nphases = 0;
     // descriptor area of every phase (header, every round's two groups, the
     // directories): offset inside the descriptor region and members
@@ -385,7 +398,9 @@ int make_batch_plan(const wt_seq_desc* seqs, uint32_t count, const wt_tuning* tu
     bp.seq.resize(count);
     uint64_t off = 0;
     auto bump = [&](uint64_t bytes) { uint64_t at = off; off = wv_round256(off + bytes); return at; };
-    bp.off_queue = bump(256);
+    // one work-queue counter per phase (at most 2 + 2 * 32 phases), then the
+    // histogram areas: the header launch clears both at once
+    bp.off_queue = bump(4 * (2 + 2 * 32));
     uint64_t total_chunks = 0, total_spans = 0, total_dch = 0;
     // One persistent launch serves every sequence, so a chunk can span many
     // tiles: fewer chunks mean fewer histogram workgroups, offset tables and
@@ -394,7 +409,9 @@ int make_batch_plan(const wt_seq_desc* seqs, uint32_t count, const wt_tuning* tu
     uint64_t total_tiles = 0;
     for (uint32_t i = 0; i < count; i++) total_tiles += wv_cdiv(seqs[i].n ? seqs[i].n : 1, T);
     const uint64_t tiles_per_chunk =
-        std::min<uint64_t>(BATCH_CHUNK_TILES, std::max<uint64_t>(1, total_tiles / ((uint64_t)KMAX * BATCH_CHUNKS_PER_WORKER)));
+        tune && tune->tile ? tune->tile
+                           : std::min<uint64_t>(BATCH_CHUNK_TILES,
+                                                std::max<uint64_t>(1, total_tiles / ((uint64_t)KMAX * BATCH_CHUNKS_PER_WORKER)));
     // H of every sequence first (zeroed by one fill every round)
     for (uint32_t i = 0; i < count; i++) {
         const wt_seq_desc& d = seqs[i];
@@ -402,6 +419,7 @@ int make_batch_plan(const wt_seq_desc* seqs, uint32_t count, const wt_tuning* tu
         if (d.tau) t1.tau = d.tau;
         t1.flags &= ~WT_FLAG_LEVELWISE;
         if (!t1.blocks) t1.blocks = (uint32_t)std::max<uint64_t>(1, wv_cdiv(wv_cdiv(d.n ? d.n : 1, T), tiles_per_chunk));
+        t1.tile = 0;
         // the argument checks of wt_plan for a matrix
         if (d.sigma == 0 || (d.sym_bytes != 1 && d.sym_bytes != 2 && d.sym_bytes != 4)) return WT_EINVAL;
         if (d.n >= (1ull << 32)) return WT_EUNSUP;
@@ -503,27 +521,18 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
     if (!ws_ || ws_bytes < bp.ws_bytes) return WT_ENOSPC;
     if ((uintptr_t)ws_ & 15u) return WT_EINVAL;
     uint8_t* ws = (uint8_t*)ws_;
-    uint32_t* queue = (uint32_t*)(ws + bp.off_queue);
     const bool prof = tune && (tune->flags & WT_FLAG_PROFILE);
 
     // every descriptor of the build, in one pinned host buffer with an area
-    // per phase
+    // per phase, all written before the first launch
     PinnedBuf pin(bp.desc_total, s);
     std::vector<uint8_t> unpinned(pin.get() ? 0 : bp.desc_total);
     uint8_t* hd = pin.get() ? (uint8_t*)pin.get() : unpinned.data();
     auto host_area = [&](uint32_t ph) { return hd + bp.phase_off[ph]; };
     auto dev_area = [&](uint32_t ph) { return ws + bp.off_desc + bp.phase_off[ph]; };
-    auto area_bytes = [&](uint32_t ph) { return bp.phase_off[ph + 1] - bp.phase_off[ph]; };
-    // a phase's descriptors go to the device as soon as they are written and
-    // its kernels are launched at once, so later phases are filled on the host
-    // while earlier ones run (each phase reads only its own area)
-    auto copy_area = [&](uint32_t ph) {
-        if (pin.get()) return wv_upload(dev_area(ph), host_area(ph), area_bytes(ph), s);
-        return hipMemcpyAsync(dev_area(ph), host_area(ph), area_bytes(ph), hipMemcpyHostToDevice, s);
-    };
+    std::memset(hd, 0, bp.desc_total);
 
     // phase 0: headers of every image
-    std::memset(host_area(0), 0, area_bytes(0));
     {
         uint8_t** imgs = (uint8_t**)host_area(0);
         wv_layout_in* lins = (wv_layout_in*)(host_area(0) + wv_round256(count * sizeof(uint8_t*)));
@@ -532,33 +541,10 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
             lins[i] = matrix_layout_in(bp.seq[i].n, bp.seq[i].sigma, bp.seq[i].L);
         }
     }
-    WV_TIMED(prof, s, "b_desc_copy", WV_CHECK(copy_area(0)));
-    WV_TIMED(prof, s, "b_header",
-             (b_header_k<<<count, 256, 0, s>>>((uint8_t* const*)dev_area(0),
-                                               (const wv_layout_in*)(dev_area(0) + wv_round256(count * sizeof(uint8_t*))))));
-    WV_CHECK(hipGetLastError());
     // rounds of passes: two groups per round, keys up to 16 bits (16-bit LDS
     // keys) and wider ones
     struct Group { uint32_t phase, m, chunks, cols; bool wide; };
-    auto launch_group = [&](const Group& g) {
-        uint8_t* desc = dev_area(g.phase);
-        const SeqRound* dq = (const SeqRound*)desc;
-        const uint32_t* dfirst = (const uint32_t*)(desc + wv_round256((uint64_t)g.m * sizeof(SeqRound)));
-        const uint32_t* dcfirst = dfirst + wv_round256((uint64_t)g.m * 4) / 4;
-        const uint64_t hz = (bp.zero_hi - bp.zero_lo) / 4;
-        const uint32_t zb = (uint32_t)std::min<uint64_t>(wv_cdiv(hz, 256), 4096);
-        WV_TIMED(prof, s, "b_zero",
-                 ((b_zero_k<<<zb, 256, 0, s>>>((uint32_t*)(ws + bp.zero_lo), hz)),
-                  (b_zero_k<<<1, 64, 0, s>>>(queue, 1))));
-        WV_TIMED(prof, s, "b_hist", (b_hist_k<<<g.chunks * HSPLIT, HT, 0, s>>>(dq, dfirst, g.m)));
-        WV_TIMED(prof, s, "b_scan", (b_scan_k<<<wv_cdiv(g.cols, HT / 64), HT, 0, s>>>(dq, dcfirst, g.m, g.cols)));
-        WV_TIMED(prof, s, "b_offsets", (b_offsets_k<<<g.chunks, HT, 0, s>>>(dq, dfirst, g.m)));
-        const uint32_t workers = std::min<uint32_t>(g.chunks, g.wide ? KRES32 : KRES16);
-        WV_TIMED(prof, s, "b_pass",
-                 (g.wide ? (void)(b_pass32_k<<<workers, NT, 0, s>>>(dq, dfirst, g.m, g.chunks, queue))
-                         : (void)(b_pass16_k<<<workers, NT, 0, s>>>(dq, dfirst, g.m, g.chunks, queue))));
-        return hipGetLastError();
-    };
+    std::vector<Group> groups;
     {
         std::vector<const void*> cur_in(count);
         std::vector<uint32_t> cur_bytes(count);
@@ -577,11 +563,9 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
                 if (members.empty()) continue;
                 const uint32_t m = (uint32_t)members.size();
                 if (m != bp.phase_members[phase]) {   // the plan and the build disagree
-                    if (pin.get()) pin.retire(s);      // earlier phases may be running
-                    else (void)hipStreamSynchronize(s);
+                    pin.idle();   // nothing was queued
                     return WT_EINVAL;
                 }
-                std::memset(host_area(phase), 0, area_bytes(phase));
                 SeqRound* q = (SeqRound*)host_area(phase);
                 uint32_t* first = (uint32_t*)(host_area(phase) + wv_round256((uint64_t)m * sizeof(SeqRound)));
                 uint32_t* cfirst = first + wv_round256((uint64_t)m * 4) / 4;
@@ -614,9 +598,7 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
                     cols += 1u << tau;
                     if (e.pa.pay_out) { cur_in[i] = e.pa.pay_out; cur_bytes[i] = e.out_bytes; }
                 }
-                const Group g{phase, m, chunks, cols, wide == 1};
-                WV_TIMED(prof, s, "b_desc_copy", WV_CHECK(copy_area(phase)));
-                WV_CHECK(launch_group(g));
+                groups.push_back(Group{phase, m, chunks, cols, wide == 1});
             }
         }
     }
@@ -625,7 +607,6 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
     uint32_t nspan = 0, dchunks = 0;   // dchunks: directory workgroups (SDG chunks each)
     {
         for (uint32_t i = 0; i < count; i++) nspan += bp.seq[i].L;
-        std::memset(host_area(dphase), 0, area_bytes(dphase));
         SpanDesc* sd = (SpanDesc*)host_area(dphase);
         uint32_t* first = (uint32_t*)(host_area(dphase) + wv_round256((uint64_t)nspan * sizeof(SpanDesc)));
         uint32_t k = 0;
@@ -652,7 +633,40 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
         }
     }
 
-    WV_TIMED(prof, s, "b_desc_copy", WV_CHECK(copy_area(dphase)));
+    // nothing has been launched before this point: every error above leaves
+    // the stream untouched
+    WV_TIMED(prof, s, "b_desc_copy",
+             WV_CHECK(pin.get() ? wv_upload(ws + bp.off_desc, hd, bp.desc_total, s)
+                                : hipMemcpyAsync(ws + bp.off_desc, hd, bp.desc_total, hipMemcpyHostToDevice, s)));
+    uint32_t* hzero = (uint32_t*)(ws + bp.zero_lo);
+    const uint64_t nhzero = (bp.zero_hi - bp.zero_lo) / 4;
+    {
+        const uint64_t nz = (bp.zero_hi - bp.off_queue) / 4;
+        const uint32_t zb = (uint32_t)std::min<uint64_t>(wv_cdiv(nz, 256 * 16), 4096);
+        WV_TIMED(prof, s, "b_header",
+                 (b_header_k<<<count + zb, 256, 0, s>>>((uint8_t* const*)dev_area(0),
+                                                        (const wv_layout_in*)(dev_area(0) + wv_round256(count * sizeof(uint8_t*))),
+                                                        count, (uint32_t*)(ws + bp.off_queue), nz)));
+        WV_CHECK(hipGetLastError());
+    }
+    for (size_t gi = 0; gi < groups.size(); gi++) {
+        const Group& g = groups[gi];
+        uint8_t* desc = dev_area(g.phase);
+        const SeqRound* dq = (const SeqRound*)desc;
+        const uint32_t* dfirst = (const uint32_t*)(desc + wv_round256((uint64_t)g.m * sizeof(SeqRound)));
+        const uint32_t* dcfirst = dfirst + wv_round256((uint64_t)g.m * 4) / 4;
+        uint32_t* queue = (uint32_t*)(ws + bp.off_queue) + g.phase;
+        // the last group leaves the histogram area as it is
+        const uint64_t nz = gi + 1 < groups.size() ? nhzero : 0;
+        WV_TIMED(prof, s, "b_hist", (b_hist_k<<<g.chunks * HSPLIT, HT, 0, s>>>(dq, dfirst, g.m)));
+        WV_TIMED(prof, s, "b_scan", (b_scan_k<<<wv_cdiv(g.cols, HT / 64), HT, 0, s>>>(dq, dcfirst, g.m, g.cols)));
+        WV_TIMED(prof, s, "b_offsets", (b_offsets_k<<<g.chunks, HT, 0, s>>>(dq, dfirst, g.m)));
+        const uint32_t workers = std::min<uint32_t>(g.chunks, g.wide ? KRES32 : KRES16);
+        WV_TIMED(prof, s, "b_pass",
+                 (g.wide ? (void)(b_pass32_k<<<workers, NT, 0, s>>>(dq, dfirst, g.m, g.chunks, queue, hzero, nz))
+                         : (void)(b_pass16_k<<<workers, NT, 0, s>>>(dq, dfirst, g.m, g.chunks, queue, hzero, nz))));
+        WV_CHECK(hipGetLastError());
+    }
     {
         uint8_t* desc = dev_area(dphase);
         const SpanDesc* dsd = (const SpanDesc*)desc;
@@ -662,9 +676,9 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
         if (dchunks) WV_TIMED(prof, s, "b_dir_write", (b_dir_write_k<<<dchunks, 256, 0, s>>>(dsd, dfirst, nspan)));
         WV_CHECK(hipGetLastError());
     }
-    // the copies above read the host descriptors: the pinned buffer returns
-    // to the pool once the stream is past them (a pageable fallback, used only
-    // when no pinned memory could be had, must be waited for)
+    // the upload reads the host descriptors: the pinned buffer returns to the
+    // pool once the stream is past it (a pageable fallback, used only when no
+    // pinned memory could be had, must be waited for)
     if (pin.get()) pin.retire(s);
     else WV_CHECK(hipStreamSynchronize(s));
     return WT_OK;

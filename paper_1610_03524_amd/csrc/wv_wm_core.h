@@ -95,6 +95,23 @@ __device__ inline void load_tile(const void* in, uint32_t ts, uint32_t tc, uint3
     constexpr uint32_t V = 16 / sizeof(IT);
     const uint32_t nv = tc / V;
     const uint4* src = (const uint4*)((const IT*)in + ts);
+    if (tc == (uint32_t)T) {
+        // a whole tile: every load of the thread in flight at once
+        constexpr uint32_t NV = T / V / NT;
+        uint4 qs[NV];
+        for (uint32_t u = 0; u < NV; u++) qs[u] = src[threadIdx.x + u * NT];
+        for (uint32_t u = 0; u < NV; u++) {
+            const uint32_t v = threadIdx.x + u * NT;
+            const uint32_t wd[4] = {qs[u].x, qs[u].y, qs[u].z, qs[u].w};
+            for (uint32_t k = 0; k < V; k++) {
+                const uint32_t x = (sizeof(IT) == 4) ? wd[k]
+                                 : (sizeof(IT) == 2) ? ((wd[k / 2] >> (16 * (k & 1))) & 0xFFFFu)
+                                                     : ((wd[k / 4] >> (8 * (k & 3))) & 0xFFu);
+                buf[v * V + k] = (KT_)(x & keymask);
+            }
+        }
+        return;
+    }
     for (uint32_t v = threadIdx.x; v < nv; v += NT) {
         const uint4 q = src[v];
         const uint32_t wd[4] = {q.x, q.y, q.z, q.w};

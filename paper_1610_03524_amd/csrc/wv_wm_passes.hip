@@ -67,12 +67,13 @@ struct Geometry {
     uint32_t K, C;
 };
 
-// K chunks of C keys (a multiple of the tile); by default one chunk per
-// resident workgroup of the first pass (whose keys are the widest)
-Geometry geometry(uint64_t n, uint32_t blocks, uint32_t L)
+// K chunks of C keys (a multiple of the tile): `blocks` chunks, else chunks
+// of `tile` tiles, else one chunk per resident workgroup of the first pass
+// (whose keys are the widest)
+Geometry geometry(uint64_t n, uint32_t blocks, uint32_t tile, uint32_t L)
 {
     const uint64_t tiles = wv_cdiv(n ? n : 1, T);
-    uint64_t K = blocks ? blocks : (L > 16 ? KRES32 : KRES16);
+    uint64_t K = blocks ? blocks : (tile ? wv_cdiv(tiles, tile) : (L > 16 ? KRES32 : KRES16));
     K = std::min<uint64_t>(K, tiles);
     const uint64_t C = wv_cdiv(wv_cdiv(n ? n : 1, K), T) * T;
     return Geometry{(uint32_t)wv_cdiv(n ? n : 1, C), (uint32_t)C};
@@ -112,7 +113,7 @@ int wv_wm_make_plan(uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt_tun
         tau = (L + passes - 1) / passes;
     }
     tau = std::min(tau, L);
-    const Geometry geo = geometry(n, tune ? tune->blocks : 0, L);
+    const Geometry geo = geometry(n, tune ? tune->blocks : 0, tune ? tune->tile : 0, L);
     p.enabled = true;
     p.tree_order = false;
     p.profile = tune && (tune->flags & WT_FLAG_PROFILE);

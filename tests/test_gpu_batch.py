@@ -88,3 +88,28 @@ def test_batch_every_input_and_payload_width():
     imgs = run_batch(seqs, taus=taus)
     for k, ((S, sigma), g) in enumerate(zip(seqs, imgs)):
         assert_same(g, oracle_image(B.KIND_WM, S, sigma), f"seq {k} {S.dtype} sigma={sigma} tau={taus[k]}")
+
+
+@pytest.mark.parametrize("tile", [1, 3, 16])
+def test_batch_tiles_per_chunk(tile):
+    """the tuning's tiles per chunk changes only the chunking: chunks of 1, 3
+    and 16 tiles with ragged last chunks and tiles give the oracle's images"""
+    rng = np.random.default_rng(46 + tile)
+    seqs = []
+    for k in range(12):
+        n = int(rng.integers(1, 9)) * 8192 + int(rng.integers(0, 8192)) if k % 4 else int(rng.integers(1, 300000))
+        sigma = int(2 ** rng.uniform(1, 18))
+        seqs.append((rng.integers(0, sigma, n).astype(np.uint32), sigma))
+    imgs = run_batch(seqs, tune=B.make_tuning(tile=tile))
+    for k, ((S, sigma), g) in enumerate(zip(seqs, imgs)):
+        assert_same(g, oracle_image(B.KIND_WM, S, sigma), f"tile {tile} seq {k} n={S.size} sigma={sigma}")
+
+
+@pytest.mark.parametrize("tile", [1, 5])
+def test_single_build_tiles_per_chunk(tile):
+    """wm_build with chunks of `tile` tiles equals the oracle"""
+    rng = np.random.default_rng(50 + tile)
+    n, sigma = 7 * 8192 + 777, 40000
+    S = rng.integers(0, sigma, n).astype(np.uint32)
+    img, _ = B.build(B.KIND_WM, to_device(S), sigma, tune=B.make_tuning(tile=tile))
+    assert_same(img.cpu().numpy(), oracle_image(B.KIND_WM, S, sigma), f"tile {tile}")
