@@ -228,7 +228,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3h", "c3m", "c4", "c5"])
     ap.add_argument("--horizon", type=float, default=2.0, help="c5: seconds of arrivals per rate")
-    ap.add_argument("--rates", default="100,200,500,1000,2000,5000", help="c5: build arrival rates /s")
+    ap.add_argument("--modes", default="continuous,plain", help="c5: serving modes, run in this order per rate")
+    ap.add_argument("--rates", default="100,300,1000,3000,10000,20000,50000", help="c5: build arrival rates /s")
     ap.add_argument("--limit", type=int, default=8192, help="c4: number of sequences")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -682,8 +683,9 @@ def bench_serve(args):
     for tag, rate, horizon in rates:
         bt, ids, qt = inputs.c5_requests(rate, horizon, seed=5, count=P)
         events = sorted([(t, "b", int(i)) for t, i in zip(bt, ids)] + [(t, "q", -1) for t in qt])
-        for mode in ("continuous", "plain"):
-            srv = serve.WaveletServer(dev, hbm_budget=64 << 30, ws_bytes=4 << 30, mode=mode, tau_of=T.choose_tau)
+        for mode in args.modes.split(","):
+            srv = serve.WaveletServer(dev, hbm_budget=64 << 30, ws_bytes=4 << 30, mode=mode, tau_of=T.choose_tau,
+                                      batch_tile=T.choose_batch_tile())
             srv.start()
             pick = np.random.default_rng(int(rate))
             t0 = time.perf_counter()

@@ -1,16 +1,27 @@
 """Serving loop: continuous batching of wavelet-matrix builds and queries.
 
 Requests arrive over time: builds (a sequence already resident in HBM) and
-query batches (access / rank / select on a built structure).  Two workers
-share the GPU:
+query batches (access / rank / select on a built structure).  One dispatcher
+thread serves both, on two streams:
 
-* the build worker takes every build that has arrived, admits them while
-  their images fit the HBM budget (evicting the least recently used built
-  structures when needed) and the batch workspace, and builds them with one
-  wt_batch_build on its own stream; requests arriving meanwhile form the
-  next batch, so batches grow with the load (continuous batching);
-* the query worker launches each query batch on a second stream as soon as
-  it arrives, so queries overlap with builds on the device.
+* builds: when no build batch is on the device, every build that has
+  arrived is admitted while the images fit the HBM budget (evicting the least
+  recently used built structures when needed) and the batch workspace, and
+  launched with one wt_batch_build (wm_build for a batch of one); requests
+  arriving meanwhile form the next batch, so batches grow with the load
+  (continuous batching);
+* queries: every query batch that has arrived is launched on the second
+  stream and one wait covers them all, also while a build batch is on the
+  device, so queries overlap with builds and group up under load.
+
+A lone request thus takes the same path as in the plain mode: one hand-off
+to one worker, its launches, one wait.  A few builds (SINGLES_MAX) are queued
+as single builds back to back; more go to one batched build.  The dispatcher
+blocks on builds of up to BLOCK_SYMBOLS symbols; while a larger batch runs it
+checks for finished work and new queries every POLL_S seconds.
+
+Plan figures (image and workspace sizes, pass width) of every sequence are
+taken when the server is created, so admission does no planning.
 
 The "plain" mode is the baseline: one worker serving every request alone, in
 arrival order (wm_build or one query launch, then wait).
@@ -41,6 +52,13 @@ from . import binding as B
 
 
 SWITCH_INTERVAL_S = 2e-4
+POLL_S = 2e-4
+# a batch of at most this many builds is queued as single builds one after
+# another (less set-up than a batched build for a few sequences)
+SINGLES_MAX = 4
+# a batch of at most this many symbols is waited for (blocking); a larger one
+# is polled so that queries arriving meanwhile are served
+BLOCK_SYMBOLS = 1 << 22
 
 
 @dataclass
@@ -65,8 +83,10 @@ class Structure:
 
 class WaveletServer:
     def __init__(self, seqs, hbm_budget: int, ws_bytes: int = 1 << 30, max_batch: int = 4096,
-                 mode: str = "continuous", tau_of=None):
-        """seqs: list of (device int tensor S, sigma) the builds refer to."""
+                 mode: str = "continuous", tau_of=None, batch_tile: int = 0):
+        """seqs: list of (device int tensor S, sigma) the builds refer to;
+        tau_of(n, sigma): pass width of a sequence (0 = automatic);
+        batch_tile: tiles per chunk of batched builds (0 = automatic)."""
         import torch
         self.torch = torch
         self.seqs = seqs
@@ -74,23 +94,34 @@ class WaveletServer:
         self.mode = mode
         self.max_batch = max_batch
         self.tau_of = tau_of or (lambda n, sigma: 0)
+        self.batch_tune = B.make_tuning(tile=batch_tile)
         self.build_stream = torch.cuda.Stream()
         self.query_stream = torch.cuda.Stream() if mode == "continuous" else self.build_stream
         self.ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+        # status words of a batch's images, copied here on the build stream
+        # and read after the one wait for the batch
+        self.status_host = torch.empty(max_batch, dtype=torch.int32, pin_memory=True)
         self.resident: dict[int, Structure] = {}
         self.used = 0
         self.lock = threading.Lock()
         # one condition per worker on the shared lock, so that a submitted
         # build wakes only the build worker and a query only the query worker
-        self.build_cv = threading.Condition(self.lock)
-        self.query_cv = threading.Condition(self.lock) if mode == "continuous" else self.build_cv
+        self.cv = threading.Condition(self.lock)   # new requests, closing
         self.builds = collections.deque()
         self.queries = collections.deque()
         self.all_reqs: list[Request] = []
         self.closing = False
         self.batches: list[int] = []
+        self.query_batches: list[int] = []
         self.threads = []
+        # plan figures of every sequence, taken before serving starts (a
+        # sequence the library refuses keeps its error code)
         self._cost_cache = {}
+        for k in range(len(seqs)):
+            try:
+                self._costs(k)
+            except B.WaveletError as e:
+                self._cost_cache[k] = e.code
 
     # ---- submission ------------------------------------------------------------
     def submit_build(self, seq: int) -> Request:
@@ -98,7 +129,7 @@ class WaveletServer:
             r = Request(len(self.all_reqs), "build", time.perf_counter(), seq=seq)
             self.all_reqs.append(r)
             (self.builds if self.mode == "continuous" else self.queries).append(r)
-            self.build_cv.notify()
+            self.cv.notify()
             return r
 
     def submit_query(self, target: int, args) -> Request:
@@ -108,7 +139,7 @@ class WaveletServer:
             r = Request(len(self.all_reqs), "query", time.perf_counter(), seq=target, qtype="mixed", args=args)
             self.all_reqs.append(r)
             self.queries.append(r)
-            self.query_cv.notify()
+            self.cv.notify()
             return r
 
     def is_resident(self, sid: int) -> bool:
@@ -127,8 +158,7 @@ class WaveletServer:
         self._switch = sys.getswitchinterval()
         sys.setswitchinterval(SWITCH_INTERVAL_S)
         if self.mode == "continuous":
-            self.threads = [threading.Thread(target=self._build_loop, daemon=True),
-                            threading.Thread(target=self._query_loop, daemon=True)]
+            self.threads = [threading.Thread(target=self._dispatch_loop, daemon=True)]
         else:
             self.threads = [threading.Thread(target=self._plain_loop, daemon=True)]
         for t in self.threads:
@@ -137,24 +167,28 @@ class WaveletServer:
     def close(self):
         with self.lock:
             self.closing = True
-            self.build_cv.notify_all()
-            self.query_cv.notify_all()
+            self.cv.notify_all()
         for t in self.threads:
             t.join()
         sys.setswitchinterval(self._switch)
 
     def _costs(self, seq):
-        """(image bytes, batch-workspace bytes) of one sequence, cached; the
-        workspace of a batch is at most the sum over its sequences"""
+        """(image bytes, batch-workspace bytes, single-build workspace bytes,
+        tau) of one sequence, cached; the workspace of a batch is at most the
+        sum over its sequences.  Raises WaveletError for a sequence the library
+        refuses."""
         c = self._cost_cache.get(seq)
+        if isinstance(c, int):
+            raise B.WaveletError(c, "wt_plan")
         if c is None:
             S, sigma = self.seqs[seq]
             tau = self.tau_of(S.numel(), sigma)
-            ob = B.plan(B.KIND_WM, S.numel(), sigma, S.element_size(), tune=B.make_tuning(tau=tau)).out_bytes
+            info = B.plan(B.KIND_WM, S.numel(), sigma, S.element_size(), tune=B.make_tuning(tau=tau))
+            ob = info.out_bytes
             # sizing only: any non-null, 16-byte aligned addresses pass the plan's checks
             d = B.wt_seq_desc()
             d.S, d.n, d.sigma, d.sym_bytes, d.out, d.out_bytes, d.tau = 256, S.numel(), sigma, S.element_size(), 256, ob, tau
-            c = (ob, B.batch_plan(B.KIND_WM, [d]))
+            c = (ob, B.batch_plan(B.KIND_WM, [d], self.batch_tune), info.workspace_bytes, tau)
             self._cost_cache[seq] = c
         return c
 
@@ -175,11 +209,12 @@ class WaveletServer:
         """builds that fit the budget and the batch workspace, in arrival order"""
         take, descs, imgs, nbytes = [], [], [], []
         ws_need = 0
+        taken, pending = set(), 0    # sequences and image bytes of this batch so far
         while self.builds and len(take) < self.max_batch:
             r = self.builds[0]
             S, sigma = self.seqs[r.seq]
             try:
-                ob, wsb = self._costs(r.seq)
+                ob, wsb, _, tau = self._costs(r.seq)
             except B.WaveletError as e:
                 self.builds.popleft()
                 r.error, r.done = e.code, time.perf_counter()
@@ -194,78 +229,90 @@ class WaveletServer:
                     r.error, r.done = B.WT_ENOSPC, time.perf_counter()
                     continue
                 break
-            if not self._evict_for(ob + sum(nbytes), keep={q.seq for q in take}):
+            if not self._evict_for(ob + pending, keep=taken):
                 break
             d = B.wt_seq_desc()
             d.S, d.n, d.sigma, d.sym_bytes = S.data_ptr(), S.numel(), sigma, S.element_size()
-            d.tau = self.tau_of(S.numel(), sigma)
-            with self.torch.cuda.stream(self.build_stream):
-                img = self.torch.empty(ob, dtype=self.torch.uint8, device="cuda")
+            d.tau = tau
+            # images are allocated on the build stream (their first use)
+            img = self.torch.empty(ob, dtype=self.torch.uint8, device="cuda")
             d.out, d.out_bytes = img.data_ptr(), ob
             ws_need += wsb
             self.builds.popleft()
             take.append(r)
+            taken.add(r.seq)
+            pending += ob
             descs.append(d)
             imgs.append(img)
             nbytes.append(ob)
         return take, descs, imgs, nbytes
 
-    def _statuses(self, imgs, rc):
-        """per-image status after a build call that returned rc: the call's
-        code if it failed, else WT_ERANGE for an image whose header status word
-        (what wt_check reads) reports a symbol >= sigma"""
-        if rc != B.WT_OK:
-            return [rc] * len(imgs)
-        if len(imgs) == 1:
-            return [B.check(imgs[0], stream=self.build_stream)]
+    def _status_copy(self, imgs):
+        """(on the build stream, after the build launches) copy every image's
+        header status word (what wt_check reads) to pinned host memory"""
         torch = self.torch
-        with torch.cuda.stream(self.build_stream):
-            words = torch.cat([img[36:40] for img in imgs]).view(torch.int32).cpu().numpy()
-        return [B.WT_OK if w == 0 else B.WT_ERANGE for w in words]
+        k = len(imgs)
+        words = imgs[0][36:40] if k == 1 else torch.cat([img[36:40] for img in imgs])
+        self.status_host[:k].copy_(words.view(torch.int32), non_blocking=True)
+
+    def _codes(self, k, rc, first=0):
+        """(after the build stream has passed the status copy) the codes of
+        images first..first+k-1: the call's code if it failed, else WT_ERANGE
+        for a status word that reports a symbol >= sigma"""
+        if rc != B.WT_OK:
+            return [rc] * k
+        return [B.WT_OK if w == 0 else B.WT_ERANGE for w in self.status_host[first:first + k].tolist()]
+
+    def _finish(self, imgs, rc):
+        """(plain mode) wait once for a build launched on the build stream;
+        image codes"""
+        if rc == B.WT_OK:
+            self._status_copy(imgs)
+        self.build_stream.synchronize()
+        return self._codes(len(imgs), rc)
 
     def _launch_builds(self, descs, imgs):
+        """queue the builds on the build stream, each segment of the batch
+        followed by the copy of its status words and an event; returns (rc,
+        [(first, end, event)]): rc is the code of the first launch that failed
+        (the segments before it stand)"""
         torch = self.torch
-        with torch.cuda.stream(self.build_stream):
-            if len(descs) == 1:
-                # a batch of one: the single-sequence build has less set-up
-                d = descs[0]
+        segs = []
+        if len(descs) <= SINGLES_MAX:
+            # a few sequences: single builds in stream order (one workspace),
+            # each finishing on its own
+            for i, d in enumerate(descs):
                 tn = B.make_tuning(tau=d.tau)
                 rc = B.lib().wm_build(d.S, d.n, d.sigma, d.sym_bytes, None, ctypes.byref(tn), d.out,
                                       d.out_bytes, self.ws.data_ptr(), self.ws.numel(),
                                       B._stream(self.build_stream))
-            else:
-                rc = B.batch_build(B.KIND_WM, descs, self.ws, stream=self.build_stream)
-            self.build_stream.synchronize()
-        return self._statuses(imgs, rc)
+                if rc != B.WT_OK:
+                    return rc, segs
+                self.status_host[i:i + 1].copy_(imgs[i][36:40].view(torch.int32), non_blocking=True)
+                ev = torch.cuda.Event()
+                ev.record(self.build_stream)
+                segs.append((i, i + 1, ev))
+            return B.WT_OK, segs
+        rc = B.batch_build(B.KIND_WM, descs, self.ws, self.batch_tune, stream=self.build_stream)
+        if rc != B.WT_OK:
+            return rc, segs
+        self._status_copy(imgs)
+        ev = torch.cuda.Event()
+        ev.record(self.build_stream)
+        return B.WT_OK, [(0, len(descs), ev)]
 
-    def _build_loop(self):
-        while True:
-            with self.lock:
-                while not self.builds and not self.closing:
-                    self.build_cv.wait()
-                if self.closing and not self.builds:
-                    return
-                take, descs, imgs, nbytes = self._admit()
-                self.used += sum(nbytes)
-            if not take:
-                time.sleep(0.0005)
-                continue
-            try:
-                codes = self._launch_builds(descs, imgs)
-            except Exception as e:   # fail this batch, keep serving
-                codes = [getattr(e, "code", B.WT_EHIP)] * len(take)
-            t = time.perf_counter()
-            with self.lock:
-                self.batches.append(len(take))
-                for r, img, nb, rc in zip(take, imgs, nbytes, codes):
-                    r.done, r.error = t, rc
-                    if rc == B.WT_OK:
-                        old = self.resident.pop(r.seq, None)
-                        if old is not None:
-                            self.used -= old.nbytes
-                        self.resident[r.seq] = Structure(img, nb, t)
-                    else:
-                        self.used -= nb
+    def _complete_builds(self, take, imgs, nbytes, codes):
+        t = time.perf_counter()
+        with self.lock:
+            for r, img, nb, rc in zip(take, imgs, nbytes, codes):
+                r.done, r.error = t, rc
+                if rc == B.WT_OK:
+                    old = self.resident.pop(r.seq, None)
+                    if old is not None:
+                        self.used -= old.nbytes
+                    self.resident[r.seq] = Structure(img, nb, t)
+                else:
+                    self.used -= nb
 
     def _take_structure(self, r, stream):
         """(under the lock) the structure a query reads, or None.  The
@@ -295,29 +342,108 @@ class WaveletServer:
         except Exception as e:   # fail this query, keep serving
             r.result, r.error = None, getattr(e, "code", B.WT_EHIP)
 
-    def _query_loop(self):
+    def _take_queries(self):
+        """(under the lock) every query that has arrived, with its structure"""
+        work = []
+        while self.queries and len(work) < self.max_batch:
+            r = self.queries.popleft()
+            work.append((r, self._take_structure(r, self.query_stream)))
+        return work
+
+    def _run_queries(self, work):
+        """launch every query of `work` on the query stream, wait once"""
+        launched = []
+        for r, st in work:
+            if st is None:
+                r.error = B.WT_EINVAL
+                continue
+            try:
+                self._run_query(r, st, self.query_stream)
+                launched.append(r)
+            except Exception as e:   # fail this query, keep serving
+                r.result, r.error = None, getattr(e, "code", B.WT_EHIP)
+        try:
+            self.query_stream.synchronize()
+        except Exception as e:
+            for r in launched:
+                r.result, r.error = None, getattr(e, "code", B.WT_EHIP)
+        t = time.perf_counter()
+        with self.lock:
+            self.query_batches.append(len(work))
+        for r, _ in work:
+            r.done = t
+
+    def _dispatch_loop(self):
+        torch = self.torch
+        # builds on the device: (take, imgs, nbytes, pending segments, short)
+        flight = None
         while True:
+            batch, qwork = None, []
             with self.lock:
-                while not self.queries and not self.closing:
-                    self.query_cv.wait()
-                if self.closing and not self.queries:
+                while (not self.builds and not self.queries and flight is None and not self.closing):
+                    self.cv.wait()
+                if self.closing and not self.builds and not self.queries and flight is None:
                     return
-                r = self.queries.popleft()
-                st = self._take_structure(r, self.query_stream)
-            self._serve_query(r, st, self.query_stream)
-            r.done = time.perf_counter()
+                if flight is None and self.builds:
+                    with torch.cuda.stream(self.build_stream):
+                        batch = self._admit()
+                    self.used += sum(batch[3])
+                qwork = self._take_queries()
+            if batch is not None and batch[0]:
+                take, descs, imgs, nbytes = batch
+                self.batches.append(len(take))
+                try:
+                    with torch.cuda.stream(self.build_stream):
+                        rc, segs = self._launch_builds(descs, imgs)
+                except Exception as e:   # fail the batch, keep serving
+                    rc, segs = getattr(e, "code", B.WT_EHIP), []
+                    try:   # whatever was queued finishes before the images are dropped
+                        self.build_stream.synchronize()
+                    except Exception:
+                        pass
+                queued = segs[-1][1] if segs else 0
+                if queued < len(take):
+                    self._complete_builds(take[queued:], imgs[queued:], nbytes[queued:],
+                                          [rc if rc != B.WT_OK else B.WT_EHIP] * (len(take) - queued))
+                if segs:
+                    flight = (take, imgs, nbytes, segs, sum(d.n for d in descs) <= BLOCK_SYMBOLS)
+            if qwork:
+                self._run_queries(qwork)
+            if flight is not None:
+                take, imgs, nbytes, segs, short = flight
+                # finish the segments the device is done with, in order; wait
+                # for short builds as the plain mode does, poll long ones
+                while segs:
+                    lo, hi, ev = segs[0]
+                    if short and not self.queries:
+                        ev.synchronize()
+                    elif not ev.query():
+                        break
+                    segs.pop(0)
+                    try:
+                        codes = self._codes(hi - lo, B.WT_OK, lo)
+                    except Exception as e:
+                        codes = [getattr(e, "code", B.WT_EHIP)] * (hi - lo)
+                    self._complete_builds(take[lo:hi], imgs[lo:hi], nbytes[lo:hi], codes)
+                if segs:
+                    with self.lock:
+                        if not self.queries and not self.closing:
+                            self.cv.wait(POLL_S)
+                    continue
+                flight = None
+            elif batch is not None and not batch[0] and not qwork:
+                time.sleep(0.0005)   # builds wait for room (budget or workspace)
 
     def _plain_build(self, r):
         torch = self.torch
         S, sigma = self.seqs[r.seq]
         try:
-            tn = B.make_tuning(tau=self.tau_of(S.numel(), sigma))
-            info = B.plan(B.KIND_WM, S.numel(), sigma, S.element_size(), tune=tn)
+            ob, _, wsb, tau = self._costs(r.seq)
         except B.WaveletError as e:
             r.error, r.done = e.code, time.perf_counter()
             return
-        ob = info.out_bytes
-        if ob > self.budget or self.ws.numel() < info.workspace_bytes:
+        tn = B.make_tuning(tau=tau)
+        if ob > self.budget or self.ws.numel() < wsb:
             r.error, r.done = B.WT_ENOSPC, time.perf_counter()
             return
         with self.lock:
@@ -326,11 +452,10 @@ class WaveletServer:
         try:
             with torch.cuda.stream(self.build_stream):
                 img = torch.empty(ob, dtype=torch.uint8, device="cuda")
-            rc = B.lib().wm_build(S.data_ptr(), S.numel(), sigma, S.element_size(), None,
-                                  ctypes.byref(tn), img.data_ptr(), ob, self.ws.data_ptr(),
-                                  self.ws.numel(), B._stream(self.build_stream))
-            self.build_stream.synchronize()
-            r.error = self._statuses([img], rc)[0]
+                rc = B.lib().wm_build(S.data_ptr(), S.numel(), sigma, S.element_size(), None,
+                                      ctypes.byref(tn), img.data_ptr(), ob, self.ws.data_ptr(),
+                                      self.ws.numel(), B._stream(self.build_stream))
+                r.error = self._finish([img], rc)[0]
         except Exception as e:   # fail this build, keep serving
             r.error = getattr(e, "code", B.WT_EHIP)
         r.done = time.perf_counter()
@@ -347,7 +472,7 @@ class WaveletServer:
         while True:
             with self.lock:
                 while not self.queries and not self.closing:
-                    self.build_cv.wait()
+                    self.cv.wait()
                 if self.closing and not self.queries:
                     return
                 r = self.queries.popleft()
