@@ -4,6 +4,9 @@
 // builds (node tables from symbol counts, canonical Huffman codewords) and
 // the dispatch to the device passes.
 #include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -14,6 +17,25 @@
 #include "wv_levelwise.h"
 #include "wv_treeperm.h"
 #include "wv_wm_passes.h"
+
+bool wv_trace_on()
+{
+    static const bool on = [] {
+        const char* v = std::getenv("WT_TRACE");
+        return v && *v && std::strcmp(v, "0") != 0;
+    }();
+    return on;
+}
+
+void wv_trace(const char* fmt, ...)
+{
+    char line[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(line, sizeof line, fmt, ap);
+    va_end(ap);
+    std::fprintf(stderr, "[wt] %s\n", line);
+}
 
 namespace {
 
@@ -100,8 +122,8 @@ inline uint64_t seg_bytes(uint64_t segs, uint64_t tiles)
     return wv_round256(WV_MAX_LEVELS * sizeof(wv_perm_level)) + wv_round256(segs * sizeof(wv_perm_seg)) + tiles * 4 + 256;
 }
 
-int make_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt_shape* shape,
-              const wt_tuning* tune, Plan& p)
+int make_plan_impl(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt_shape* shape,
+                   const wt_tuning* tune, Plan& p)
 {
     if (kind < WT_KIND_WT || kind > WT_KIND_MULTIARY) return WT_EINVAL;
     if (sigma == 0) return WT_EINVAL;
@@ -356,6 +378,52 @@ int make_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt
     p.ws_bytes = off;
     return WT_OK;
 }
+
+const char* kind_name(int kind)
+{
+    switch (kind) {
+    case WT_KIND_WT: return "tree";
+    case WT_KIND_WM: return "matrix";
+    case WT_KIND_SHAPED: return "shaped";
+    case WT_KIND_MULTIARY: return "multiary";
+    default: return "?";
+    }
+}
+
+// the plan, and with WT_TRACE set its figures on stderr: the path, the
+// passes (tau, chunks K of C keys in tiles of 8192), the workspace and every
+// level's array offsets in the image
+int make_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt_shape* shape,
+              const wt_tuning* tune, Plan& p)
+{
+    const int rc = make_plan_impl(kind, n, sigma, sym_bytes, shape, tune, p);
+    if (!wv_trace_on()) return rc;
+    if (rc) {
+        wv_trace("plan %s n=%llu sigma=%u sym_bytes=%u: %s", kind_name(kind), (unsigned long long)n, sigma,
+                 sym_bytes, wt_strerror(rc));
+        return rc;
+    }
+    const wv_wm_plan& m = p.wm.enabled ? p.wm : p.wmb;
+    const char* path = p.direct_tree ? "one-pass tree order"
+                       : (kind != WT_KIND_WM && p.dev_runs) ? "matrix passes + device runs + permutation"
+                       : m.enabled ? "matrix passes" : "level by level";
+    wv_trace("plan %s n=%llu sigma=%u sym_bytes=%u levels=%u key_bits=%u path=%s", kind_name(kind),
+             (unsigned long long)n, sigma, sym_bytes, p.nlevels, p.key_bits, path);
+    if (m.enabled)
+        wv_trace("  passes: tau=%u passes=%u chunks K=%u of C=%u keys (%u tiles) workspace=%llu", m.tau,
+                 (m.L + m.tau - 1) / m.tau, m.K, m.C, m.C / 8192u, (unsigned long long)p.ws_bytes);
+    else
+        wv_trace("  workspace=%llu", (unsigned long long)p.ws_bytes);
+    for (uint32_t l = 0; l < p.nlevels; l++) {
+        const wv_level& L = p.lay.lv[l];
+        wv_trace("  level %u: n=%llu bits@%llu rank@%llu sel0@%llu sel1@%llu nsel=%llu", l,
+                 (unsigned long long)L.n, (unsigned long long)L.bits_off, (unsigned long long)L.rank_off,
+                 (unsigned long long)L.sel0_off, (unsigned long long)L.sel1_off, (unsigned long long)L.nsel);
+    }
+    wv_trace("  image=%llu bytes", (unsigned long long)p.lay.image_bytes);
+    return rc;
+}
+
 
 // ---- host node tables ----------------------------------------------------------
 

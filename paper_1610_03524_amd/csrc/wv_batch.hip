@@ -489,7 +489,11 @@ int make_batch_plan(const wt_seq_desc* seqs, uint32_t count, const wt_tuning* tu
     bp.phase_off[bp.nphases] = bp.desc_total;
     bp.off_desc = bump(bp.desc_total);
     bp.ws_bytes = off;
-    (void)total_chunks;
+    if (wv_trace_on())
+        wv_trace("batch plan: %u sequences, %llu tiles, %llu tiles per chunk, %llu chunks, %u rounds, "
+                 "descriptors=%llu workspace=%llu", count, (unsigned long long)total_tiles,
+                 (unsigned long long)tiles_per_chunk, (unsigned long long)total_chunks, bp.max_passes,
+                 (unsigned long long)bp.desc_total, (unsigned long long)bp.ws_bytes);
     (void)total_dch;
     return WT_OK;
 }

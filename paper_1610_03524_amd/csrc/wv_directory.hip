@@ -245,14 +245,14 @@ __global__ void mfinish_k(uint8_t* __restrict__ image, MLevels a, const uint64_t
 
 // ---- header ------------------------------------------------------------------
 
+// The layout comes from the host (it holds 64-bit divisions that one device
+// thread would take microseconds over).
 __global__ void __launch_bounds__(DIR_THREADS)
-header_k(uint8_t* __restrict__ img, wv_layout_in in)
+header_k(uint8_t* __restrict__ img, wv_layout_in in, wv_layout_out lay)
 {
-    __shared__ wv_layout_out lay;
     __shared__ uint64_t span_lo[4 * WV_MAX_LEVELS + 4], span_hi[4 * WV_MAX_LEVELS + 4];
     __shared__ int nspan;
     if (threadIdx.x == 0) {
-        wv_layout(in, lay);
         const bool multi = in.kind == WT_KIND_MULTIARY;
         int s = 0;
         span_lo[s] = 0;
@@ -315,10 +315,15 @@ header_k(uint8_t* __restrict__ img, wv_layout_in in)
         e[6] = L.sel1_off;
         e[7] = L.nsel;
     }
-    // zero every gap between consecutive arrays
+    // zero every gap between consecutive arrays: bytes up to an 8-byte
+    // boundary, then 8-byte words, then the tail bytes
     for (int s = 0; s < nspan; s++) {
         const uint64_t lo = span_hi[s], hi = span_lo[s + 1];
-        for (uint64_t b = lo + threadIdx.x; b < hi; b += blockDim.x) img[b] = 0;
+        if (lo >= hi) continue;
+        const uint64_t wlo = min(hi, (lo + 7) & ~7ull), whi = max(wlo, hi & ~7ull);
+        for (uint64_t b = lo + threadIdx.x; b < wlo; b += blockDim.x) img[b] = 0;
+        for (uint64_t w = wlo / 8 + threadIdx.x; w < whi / 8; w += blockDim.x) ((uint64_t*)img)[w] = 0;
+        for (uint64_t b = whi + threadIdx.x; b < hi; b += blockDim.x) img[b] = 0;
     }
 }
 
@@ -475,7 +480,9 @@ hipError_t wv_multiary_ranges(uint8_t* image, const wv_level* lv, uint32_t M, ui
 
 hipError_t wv_write_header(uint8_t* image, const wv_layout_in& in, hipStream_t s)
 {
-    header_k<<<1, DIR_THREADS, 0, s>>>(image, in);
+    wv_layout_out lay;
+    wv_layout(in, lay);
+    header_k<<<1, DIR_THREADS, 0, s>>>(image, in, lay);
     return hipGetLastError();
 }
 

@@ -71,6 +71,11 @@ hipError_t wv_multiary_counters(uint8_t* image, const wv_level* lv, uint32_t M, 
 hipError_t wv_multiary_ranges(uint8_t* image, const wv_level* lv, uint32_t M, uint32_t D,
                               const wv_mdir_scratch& sc, hipStream_t s);
 
+// ---- tracing -----------------------------------------------------------------
+// WT_TRACE=1 in the environment: plans are logged to stderr ("[wt] " lines)
+bool wv_trace_on();
+void wv_trace(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+
 // ---- pinned host staging -------------------------------------------------------
 // Pinned host buffers for copies a build issues between launches (the tables
 // a shaped tree build uploads, the descriptors of a batch): a copy from

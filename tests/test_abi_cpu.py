@@ -255,3 +255,27 @@ def test_device_huffman_refuses_on_the_host():
     assert L.wt_huffman_codes_dev(p, 0, p, p, p, None) == B.WT_EINVAL
     assert L.wt_huffman_codes_dev(None, 10, p, p, p, None) == B.WT_EINVAL
     assert L.wt_huffman_codes_dev(p, 10, p, p, None, None) == B.WT_EINVAL
+
+
+def test_trace_logs_plans_only_when_asked():
+    """WT_TRACE=1 logs every plan (path, passes, chunks, level offsets) and
+    batch plan on stderr; without it the library prints nothing"""
+    import subprocess
+    import sys
+    code = ("from paper_1610_03524_amd import binding as B\n"
+            "B.plan(B.KIND_WM, 1000000, 300, 2)\n"
+            "d = B.wt_seq_desc(); d.S = 256; d.n = 100000; d.sigma = 1000; d.sym_bytes = 4\n"
+            "d.out = 256; d.out_bytes = 1 << 30\n"
+            "B.batch_plan(B.KIND_WM, [d])\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, WT_TRACE="1")
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    lines = [l for l in r.stderr.splitlines() if l.startswith("[wt] ")]
+    assert any("plan matrix n=1000000 sigma=300" in l for l in lines), r.stderr
+    assert any("passes: tau=" in l and "chunks K=" in l for l in lines), r.stderr
+    assert sum("  level " in l for l in lines) == 9, r.stderr
+    assert any(l.startswith("[wt] batch plan: 1 sequences") for l in lines), r.stderr
+    env.pop("WT_TRACE")
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and "[wt]" not in r.stderr

@@ -131,3 +131,34 @@ def test_multiary_select_through_digit_samples(D):
     ok = (k >= 1) & (k <= last - first)
     want = np.where(ok, order[np.minimum(first + k - 1, n - 1)], -1)
     assert np.array_equal(got, want.astype(np.int64)), f"D={D}: {np.count_nonzero(got != want)} wrong"
+
+
+@pytest.mark.parametrize("kind,D", [(B.KIND_WM, 0), (B.KIND_WT, 0), (B.KIND_MULTIARY, 2), (B.KIND_SHAPED, 0)])
+def test_image_is_position_independent(kind, D, tmp_path):
+    """An image holds offsets only: copied to the host, written to a file,
+    read back and placed at another device address (inside a larger buffer,
+    behind other data) it answers every query as the original does, and both
+    equal brute force on S."""
+    import torch
+    rng = np.random.default_rng(77 + kind + D)
+    n, sigma = 120001, 3000
+    S = np.minimum(rng.geometric(0.003, n) - 1, sigma - 1).astype(np.uint16)
+    if kind == B.KIND_SHAPED:
+        (gc, gl), _ = shaped_inputs(S, sigma)
+        counts = B.symbol_counts(to_device(S), sigma).cpu().numpy()
+        img, _ = B.build(kind, to_device(S), sigma, codes=gc, code_len=gl, counts=counts)
+    else:
+        img, _ = B.build(kind, to_device(S), sigma, arity_log2=D)
+    torch.cuda.synchronize()
+    host = img.cpu().numpy()
+    path = tmp_path / "image.bin"
+    host.tofile(path)
+    back = np.fromfile(path, dtype=np.uint8)
+    assert np.array_equal(back, host)
+    del img   # the original allocation is gone before the copy is used
+    torch.cuda.synchronize()
+    big = torch.full((back.size + 3 * 4096,), 0x5C, dtype=torch.uint8, device="cuda")
+    moved = big[2 * 4096:2 * 4096 + back.size]
+    moved.copy_(torch.from_numpy(back))
+    assert B.check(moved) == B.WT_OK
+    run_queries(moved, S, sigma, rng)
