@@ -245,44 +245,49 @@ __global__ void mfinish_k(uint8_t* __restrict__ image, MLevels a, const uint64_t
 
 // ---- header ------------------------------------------------------------------
 
-// The layout comes from the host (it holds 64-bit divisions that one device
-// thread would take microseconds over).
-__global__ void __launch_bounds__(DIR_THREADS)
+// 8-byte aligned middle in words, the ends in bytes
+__device__ inline void zero_bytes(uint8_t* img, uint64_t lo, uint64_t hi)
+{
+    if (lo >= hi) return;
+    const uint64_t wlo = min(hi, (lo + 7) & ~7ull), whi = max(wlo, hi & ~7ull);
+    for (uint64_t b = lo; b < wlo; b++) img[b] = 0;
+    for (uint64_t w = wlo / 8; w < whi / 8; w++) ((uint64_t*)img)[w] = 0;
+    for (uint64_t b = whi; b < hi; b++) img[b] = 0;
+}
+
+// The header, the level records and every gap between consecutive arrays
+// (arrays start on 256-byte boundaries, so each gap is under 256 bytes).
+// The layout comes from the host; thread l < nlevels writes level l's record
+// and the gaps after its arrays, thread nlevels the header and the gaps
+// around it and after the node and codeword tables: no thread waits for
+// another.
+__global__ void __launch_bounds__(64)
 header_k(uint8_t* __restrict__ img, wv_layout_in in, wv_layout_out lay)
 {
-    __shared__ uint64_t span_lo[4 * WV_MAX_LEVELS + 4], span_hi[4 * WV_MAX_LEVELS + 4];
-    __shared__ int nspan;
-    if (threadIdx.x == 0) {
-        const bool multi = in.kind == WT_KIND_MULTIARY;
-        int s = 0;
-        span_lo[s] = 0;
-        span_hi[s++] = WV_HEADER_BYTES + (uint64_t)WV_LEVEL_BYTES * in.nlevels;
-        for (uint32_t l = 0; l < in.nlevels; l++) {
-            const wv_level& L = lay.lv[l];
-            span_lo[s] = L.bits_off;
-            span_hi[s++] = L.bits_off + (multi ? wv_mbits_bytes(L.n, in.arity_log2) : wv_bits_bytes(L.n));
-            span_lo[s] = L.rank_off;
-            span_hi[s++] = L.rank_off + (multi ? wv_mrank_bytes(L.n, in.arity_log2) : wv_rank_bytes(L.n));
-            if (!multi) {
-                span_lo[s] = L.sel0_off;
-                span_hi[s++] = L.sel0_off + 8 * L.nsel;
-                span_lo[s] = L.sel1_off;
-                span_hi[s++] = L.sel1_off + 8 * L.nsel;
-            } else {
-                span_lo[s] = L.sel0_off;
-                span_hi[s++] = L.sel0_off + (8ull << in.arity_log2) * L.nsel;
-            }
+    const uint32_t t = threadIdx.x, nl = in.nlevels, D = in.arity_log2;
+    const bool multi = in.kind == WT_KIND_MULTIARY, shaped = in.kind == WT_KIND_SHAPED;
+    const uint64_t after_levels = shaped ? lay.nodes_off : lay.image_bytes;
+    if (t < nl) {
+        const wv_level& L = lay.lv[t];
+        const uint64_t next = t + 1 < nl ? lay.lv[t + 1].bits_off : after_levels;
+        zero_bytes(img, L.bits_off + (multi ? wv_mbits_bytes(L.n, D) : wv_bits_bytes(L.n)), L.rank_off);
+        zero_bytes(img, L.rank_off + (multi ? wv_mrank_bytes(L.n, D) : wv_rank_bytes(L.n)), L.sel0_off);
+        if (multi) {
+            zero_bytes(img, L.sel0_off + (8ull << D) * L.nsel, next);
+        } else {
+            zero_bytes(img, L.sel0_off + 8 * L.nsel, L.sel1_off);
+            zero_bytes(img, L.sel1_off + 8 * L.nsel, next);
         }
-        if (in.kind == WT_KIND_SHAPED) {
-            span_lo[s] = lay.nodes_off;
-            span_hi[s++] = lay.nodes_off + in.nnodes * WV_NODE_BYTES;
-            span_lo[s] = lay.codes_off;
-            span_hi[s++] = lay.codes_off + (uint64_t)in.sigma * WV_CODE_BYTES;
-        }
-        span_lo[s] = lay.image_bytes;   // sentinel
-        span_hi[s] = lay.image_bytes;
-        nspan = s;
-
+        uint64_t* e = (uint64_t*)(img + WV_HEADER_BYTES + (uint64_t)WV_LEVEL_BYTES * t);
+        e[0] = L.n;
+        e[1] = 0;
+        e[2] = 0;
+        e[3] = L.bits_off;
+        e[4] = L.rank_off;
+        e[5] = L.sel0_off;
+        e[6] = L.sel1_off;
+        e[7] = L.nsel;
+    } else if (t == nl) {
         uint32_t* h32 = (uint32_t*)img;
         uint64_t* h64 = (uint64_t*)img;
         h32[0] = WV_MAGIC;
@@ -300,30 +305,12 @@ header_k(uint8_t* __restrict__ img, wv_layout_in in, wv_layout_out lay)
         h64[8] = in.nnodes;
         h64[9] = lay.codes_off;
         h64[10] = in.ncoded;
-    }
-    __syncthreads();
-    for (uint32_t b = 88 + threadIdx.x; b < WV_HEADER_BYTES; b += blockDim.x) img[b] = 0;
-    if (threadIdx.x < in.nlevels) {
-        const wv_level& L = lay.lv[threadIdx.x];
-        uint64_t* e = (uint64_t*)(img + WV_HEADER_BYTES + (uint64_t)WV_LEVEL_BYTES * threadIdx.x);
-        e[0] = L.n;
-        e[1] = 0;
-        e[2] = 0;
-        e[3] = L.bits_off;
-        e[4] = L.rank_off;
-        e[5] = L.sel0_off;
-        e[6] = L.sel1_off;
-        e[7] = L.nsel;
-    }
-    // zero every gap between consecutive arrays: bytes up to an 8-byte
-    // boundary, then 8-byte words, then the tail bytes
-    for (int s = 0; s < nspan; s++) {
-        const uint64_t lo = span_hi[s], hi = span_lo[s + 1];
-        if (lo >= hi) continue;
-        const uint64_t wlo = min(hi, (lo + 7) & ~7ull), whi = max(wlo, hi & ~7ull);
-        for (uint64_t b = lo + threadIdx.x; b < wlo; b += blockDim.x) img[b] = 0;
-        for (uint64_t w = wlo / 8 + threadIdx.x; w < whi / 8; w += blockDim.x) ((uint64_t*)img)[w] = 0;
-        for (uint64_t b = whi + threadIdx.x; b < hi; b += blockDim.x) img[b] = 0;
+        zero_bytes(img, 88, WV_HEADER_BYTES);
+        zero_bytes(img, WV_HEADER_BYTES + (uint64_t)WV_LEVEL_BYTES * nl, nl ? lay.lv[0].bits_off : after_levels);
+        if (shaped) {
+            zero_bytes(img, lay.nodes_off + in.nnodes * WV_NODE_BYTES, lay.codes_off);
+            zero_bytes(img, lay.codes_off + (uint64_t)in.sigma * WV_CODE_BYTES, lay.image_bytes);
+        }
     }
 }
 
@@ -482,7 +469,7 @@ hipError_t wv_write_header(uint8_t* image, const wv_layout_in& in, hipStream_t s
 {
     wv_layout_out lay;
     wv_layout(in, lay);
-    header_k<<<1, DIR_THREADS, 0, s>>>(image, in, lay);
+    header_k<<<1, 64, 0, s>>>(image, in, lay);
     return hipGetLastError();
 }
 
