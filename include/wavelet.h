@@ -16,7 +16,9 @@
  *
  * Every binary level carries a rank-of-0 directory (Sec. 5.1, "Rank": 512-bit
  * ranges, 64-bit sub-ranges) and sampled select on ones and zeros (Sec. 5.1,
- * "Select", sampling every 4096th one/zero); multiary levels carry per-digit
+ * "Select": the two sampling levels of Clark's structure, every 4096th and
+ * every 512th one/zero, a select searching the rank ranges between two
+ * sub-samples); multiary levels carry per-digit
  * rank counters (Sec. 5.2, "Rank").
  *
  * Output: one flat, position-independent byte image per structure (layout
@@ -66,7 +68,7 @@ extern "C" {
 
 /* ---- image layout (little endian) ----------------------------------------
  * Header, 256 bytes at offset 0:
- *   u32 magic 0x54564157 ("WAVT"), u32 version 1, u32 kind, u32 arity_log2,
+ *   u32 magic 0x54564157 ("WAVT"), u32 version 2, u32 kind, u32 arity_log2,
  *   u64 n, u32 sigma, u32 nlevels, u32 key_bits, u32 status (0 ok; bit 0:
  *   a symbol >= sigma was seen; bit 1: the symbol counts differ from those
  *   the shape gave), u64 image_bytes, u64 levels_off (= 256),
@@ -83,7 +85,12 @@ extern "C" {
  *                 (zeros in [512k, min(512k+64j, n_l))) << 9(j-1), 0 when
  *                 512k >= n_l;
  *                 sel0 / sel1: nsel = ceil(n_l/4096)+1 u64: position of the
- *                 zero / one whose 0-based ordinal is 4096k, then n_l.
+ *                 zero / one whose 0-based ordinal is 4096k, then n_l;
+ *                 sub (at sel1_off + 8*nsel rounded up to 256 bytes, not in
+ *                 the descriptor): nsub = ceil(n_l/512)+2 u32: entry j = the
+ *                 position of the one of ordinal 512j, entry nsub-1-j = that
+ *                 of the zero of ordinal 512j, every other entry n_l (at
+ *                 least one such entry separates the two).
  *   multiary level (D-bit digits, P = floor(64/D) per word, digit t at bits
  *                 [tD, tD+D) of word t/P): ceil(n_l/P) words; then counters:
  *                 (ceil(n_l/64P)+1) x d u64 = count of each digit before

@@ -18,8 +18,9 @@
  *     (Sec. 4.3, paragraph "Multiary wavelet trees");
  *   - the rank-of-0 directory of every binary level (Sec. 5.1, "Rank":
  *     Jacobson's ranges and sub-ranges, here 512-bit ranges and 64-bit
- *     sub-ranges) and sampled select (Sec. 5.1, "Select": the sampling layer
- *     of Clark's structure, here every 4096th one and every 4096th zero);
+ *     sub-ranges) and sampled select (Sec. 5.1, "Select": the two sampling
+ *     levels of Clark's structure, here every 4096th and every 512th one and
+ *     zero, the search between two samples running over the rank ranges);
  *   - per-digit rank counters on multiary levels (Sec. 5.2, "Rank") and
  *     per-digit sampled select (Sec. 5.2, "Select": the range symbols, every
  *     4096th occurrence of each digit value);
@@ -52,7 +53,7 @@
 
 /* ---- image layout ------------------------------------------------------- */
 #define O_MAGIC        0x54564157u  /* bytes 'W','A','V','T' */
-#define O_VERSION      1u
+#define O_VERSION      2u
 #define O_HEADER_BYTES 256u
 #define O_LEVEL_BYTES  64u
 #define O_NODE_BYTES   32u
@@ -60,6 +61,7 @@
 #define O_RANGE_BITS   512u   /* rank directory range (superblock) */
 #define O_SUB_BITS     64u    /* rank directory sub-range (block) */
 #define O_SEL_STRIDE   4096u  /* select sampling stride */
+#define O_SUB_STRIDE   512u   /* select sub-sampling stride (second level) */
 #define O_LEAF_FLAG    0x80000000u
 #define O_NO_CHILD     0xFFFFFFFFu
 #define O_MAX_CODE_LEN 32u
@@ -73,6 +75,9 @@ typedef struct {
     uint64_t sel0_off;  /* sampled select on zeros */
     uint64_t sel1_off;  /* sampled select on ones */
     uint64_t nsel;      /* entries in each sampled-select array */
+    uint64_t sub_off;   /* binary: select sub-samples, ones from the front,
+                           zeros from the back (32-bit positions) */
+    uint64_t nsub;      /* entries of the sub-sample array */
 } olevel;
 
 static uint64_t round256(uint64_t x) { return (x + 255u) & ~(uint64_t)255u; }
@@ -100,6 +105,9 @@ static uint64_t bin_rank_bytes(uint64_t m)
     return ((m + O_RANGE_BITS - 1) / O_RANGE_BITS + 1) * 16;
 }
 static uint64_t bin_nsel(uint64_t m) { return (m + O_SEL_STRIDE - 1) / O_SEL_STRIDE + 1; }
+/* ceil(ones/512) + ceil(zeros/512) <= ceil(m/512) + 1 entries are used, so
+ * one more leaves at least one unused entry between the two halves */
+static uint64_t bin_nsub(uint64_t m) { return (m + O_SUB_STRIDE - 1) / O_SUB_STRIDE + 2; }
 
 /* Sizes for one multiary level of m digits of D bits. */
 static uint64_t multi_bits_bytes(uint64_t m, unsigned D)
@@ -115,9 +123,10 @@ static uint64_t multi_rank_bytes(uint64_t m, unsigned D)
     return (nsb + 1) * d * 8 + nb * d * 2;
 }
 
-/* Assign the offsets of every array.  Binary levels hold bits, rank, sel0 and
- * sel1; multiary levels hold digits and counters; shaped trees append the node
- * table and the code table.  Every array starts on a 256-byte boundary. */
+/* Assign the offsets of every array.  Binary levels hold bits, rank, sel0,
+ * sel1 and the select sub-samples; multiary levels hold digits, counters and
+ * per-digit samples; shaped trees append the node table and the code table.
+ * Every array starts on a 256-byte boundary. */
 static uint64_t lay_out(olevel* lv, unsigned nlev, int multiary, unsigned D,
                         uint64_t nnodes, uint32_t sigma, int shaped,
                         uint64_t* nodes_off, uint64_t* codes_off)
@@ -135,12 +144,16 @@ static uint64_t lay_out(olevel* lv, unsigned nlev, int multiary, unsigned D,
             off = round256(off + lv[l].nsel * 8);
             lv[l].sel1_off = off;
             off = round256(off + lv[l].nsel * 8);
+            lv[l].nsub = bin_nsub(m);
+            lv[l].sub_off = off;
+            off = round256(off + lv[l].nsub * 4);
         } else {
             /* generalized select: d arrays of nsel samples, digit-major */
             lv[l].nsel = bin_nsel(m);
             lv[l].sel0_off = off;
             off = round256(off + ((uint64_t)1 << D) * lv[l].nsel * 8);
             lv[l].sel1_off = 0;
+            lv[l].sub_off = lv[l].nsub = 0;
         }
     }
     *nodes_off = *codes_off = 0;
@@ -197,13 +210,24 @@ static int write_binary_level(uint8_t* img, olevel* lv, const uint8_t* b)
         put_u64(s0 + 8 * k, m);
         put_u64(s1 + 8 * k, m);
     }
+    /* Second sampling level of Clark's structure (Sec. 5.1, "Select"): the
+     * position of every one (zero) whose ordinal is a multiple of 512, so a
+     * select only searches the rank ranges between two such positions.  As
+     * n < 2^32 the positions themselves fit 32 bits (no offsets relative to
+     * the first level are needed).  Ones fill the array from the front, zeros
+     * from the back (entry nsub-1-j holds zero 512j); entries left between
+     * the two hold m. */
+    uint8_t* sub = img + lv->sub_off;
+    for (uint64_t k = 0; k < lv->nsub; k++) put_u32(sub + 4 * k, (uint32_t)m);
     uint64_t c0 = 0, c1 = 0;
     for (uint64_t i = 0; i < m; i++) {
         if (b[i]) {
             if (c1 % O_SEL_STRIDE == 0) put_u64(s1 + 8 * (c1 / O_SEL_STRIDE), i);
+            if (c1 % O_SUB_STRIDE == 0) put_u32(sub + 4 * (c1 / O_SUB_STRIDE), (uint32_t)i);
             c1++;
         } else {
             if (c0 % O_SEL_STRIDE == 0) put_u64(s0 + 8 * (c0 / O_SEL_STRIDE), i);
+            if (c0 % O_SUB_STRIDE == 0) put_u32(sub + 4 * (lv->nsub - 1 - c0 / O_SUB_STRIDE), (uint32_t)i);
             c0++;
         }
     }

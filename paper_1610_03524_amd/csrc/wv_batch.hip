@@ -38,7 +38,7 @@ struct SeqRound {
 
 struct SpanDesc {
     uint8_t* image;
-    uint64_t n, bits_off, rank_off, sel0_off, sel1_off, nsel;
+    uint64_t n, bits_off, rank_off, sel0_off, sel1_off, nsel, sub_off, nsub;
     uint32_t* cnt;          // ones per directory chunk
     uint64_t* pre;          // exclusive prefix of cnt
     uint32_t level, chunk0; // level index, first directory workgroup of the span
@@ -241,6 +241,9 @@ b_dir_scan_k(const SpanDesc* __restrict__ spans)
     }
     for (uint64_t k = wv_cdiv(ones, WV_SEL_STRIDE) + threadIdx.x; k < d.nsel; k += 256) sel1[k] = d.n;
     for (uint64_t k = wv_cdiv(zeros, WV_SEL_STRIDE) + threadIdx.x; k < d.nsel; k += 256) sel0[k] = d.n;
+    uint32_t* sub = (uint32_t*)(d.image + d.sub_off);
+    const uint64_t sub_hi = d.nsub - wv_cdiv(zeros, WV_SUB_STRIDE);
+    for (uint64_t k = wv_cdiv(ones, WV_SUB_STRIDE) + threadIdx.x; k < sub_hi; k += 256) sub[k] = (uint32_t)d.n;
 }
 
 __global__ void __launch_bounds__(256)
@@ -256,6 +259,7 @@ b_dir_write_k(const SpanDesc* __restrict__ spans, const uint32_t* __restrict__ c
     uint64_t* dir = (uint64_t*)(d.image + d.rank_off);
     uint64_t* sel0 = (uint64_t*)(d.image + d.sel0_off);
     uint64_t* sel1 = (uint64_t*)(d.image + d.sel1_off);
+    uint32_t* sub = (uint32_t*)(d.image + d.sub_off);
     const uint64_t c0 = (uint64_t)(blockIdx.x - d.chunk0) * SDG;
     for (uint64_t c = c0; c < min(nch, c0 + SDG); c++) {   // uniform
         const uint64_t cw = c * SDW, w0 = cw + 2 * threadIdx.x;
@@ -276,14 +280,23 @@ b_dir_write_k(const SpanDesc* __restrict__ spans, const uint32_t* __restrict__ c
         for (int qd = 0; qd < 2; qd++) {
             const uint64_t w = w0 + qd;
             if (w >= nw) break;
-            const uint64_t t1 = wv_cdiv(obs[qd], WV_SEL_STRIDE) * WV_SEL_STRIDE;
-            if (t1 < obs[qd] + os[qd]) sel1[t1 / WV_SEL_STRIDE] = 64 * w + wv_select_in_word(xs[qd], (uint32_t)(t1 - obs[qd]));
+            // ordinals 512k inside the word (at most one): sub-samples, and
+            // samples when 4096 divides them
+            const uint64_t t1 = wv_cdiv(obs[qd], WV_SUB_STRIDE) * WV_SUB_STRIDE;
+            if (t1 < obs[qd] + os[qd]) {
+                const uint64_t p = 64 * w + wv_select_in_word(xs[qd], (uint32_t)(t1 - obs[qd]));
+                sub[t1 / WV_SUB_STRIDE] = (uint32_t)p;
+                if (t1 % WV_SEL_STRIDE == 0) sel1[t1 / WV_SEL_STRIDE] = p;
+            }
             const uint64_t valid = min((uint64_t)64, n - 64 * w);
             const uint64_t vm = valid >= 64 ? ~0ull : ((1ull << valid) - 1ull);
             const uint32_t zc = (uint32_t)valid - os[qd];
-            const uint64_t t0 = wv_cdiv(zbs[qd], WV_SEL_STRIDE) * WV_SEL_STRIDE;
-            if (t0 < zbs[qd] + zc)
-                sel0[t0 / WV_SEL_STRIDE] = 64 * w + wv_select_in_word(~xs[qd] & vm, (uint32_t)(t0 - zbs[qd]));
+            const uint64_t t0 = wv_cdiv(zbs[qd], WV_SUB_STRIDE) * WV_SUB_STRIDE;
+            if (t0 < zbs[qd] + zc) {
+                const uint64_t p = 64 * w + wv_select_in_word(~xs[qd] & vm, (uint32_t)(t0 - zbs[qd]));
+                sub[d.nsub - 1 - t0 / WV_SUB_STRIDE] = (uint32_t)p;
+                if (t0 % WV_SEL_STRIDE == 0) sel0[t0 / WV_SEL_STRIDE] = p;
+            }
         }
         __syncthreads();
         if (threadIdx.x < SDW / 8) {
@@ -309,7 +322,7 @@ b_header_k(uint8_t* const* __restrict__ images, const wv_layout_in* __restrict__
     if (blockIdx.x >= count) return;   // whole workgroups; clearing only
     // same header writer as a single build, one workgroup per image
     __shared__ wv_layout_out lay;
-    __shared__ uint64_t span_lo[4 * WV_MAX_LEVELS + 4], span_hi[4 * WV_MAX_LEVELS + 4];
+    __shared__ uint64_t span_lo[5 * WV_MAX_LEVELS + 4], span_hi[5 * WV_MAX_LEVELS + 4];
     __shared__ int nspan;
     uint8_t* img = images[blockIdx.x];
     const wv_layout_in& in = lins[blockIdx.x];
@@ -324,6 +337,7 @@ b_header_k(uint8_t* const* __restrict__ images, const wv_layout_in* __restrict__
             span_lo[s] = L.rank_off;  span_hi[s++] = L.rank_off + wv_rank_bytes(L.n);
             span_lo[s] = L.sel0_off;  span_hi[s++] = L.sel0_off + 8 * L.nsel;
             span_lo[s] = L.sel1_off;  span_hi[s++] = L.sel1_off + 8 * L.nsel;
+            span_lo[s] = L.sub_off;   span_hi[s++] = L.sub_off + 4 * L.nsub;
         }
         span_lo[s] = lay.image_bytes;
         span_hi[s] = lay.image_bytes;
@@ -356,11 +370,11 @@ struct SeqPlan {
     uint64_t off_H, off_tot, off_G0, off_pay[2], off_dcnt, off_dpre;
     // image layout: every level of a matrix has n bits, so level l's arrays
     // sit at level 0's offsets + l * lstride
-    uint64_t bits0, rank0, sel00, sel10, lstride, nsel, image_bytes;
+    uint64_t bits0, rank0, sel00, sel10, sub0, lstride, nsel, nsub, image_bytes;
     wv_level lv(uint32_t l) const
     {
         const uint64_t d = (uint64_t)l * lstride;
-        return wv_level{n, bits0 + d, rank0 + d, sel00 + d, sel10 + d, nsel};
+        return wv_level{n, bits0 + d, rank0 + d, sel00 + d, sel10 + d, nsel, sub0 + d, nsub};
     }
 };
 
@@ -434,6 +448,7 @@ int make_batch_plan(const wt_seq_desc* seqs, uint32_t count, const wt_tuning* tu
             wv_layout(matrix_layout_in(d.n, d.sigma, wp.L), lay);
             s.bits0 = lay.lv[0].bits_off; s.rank0 = lay.lv[0].rank_off;
             s.sel00 = lay.lv[0].sel0_off; s.sel10 = lay.lv[0].sel1_off; s.nsel = lay.lv[0].nsel;
+            s.sub0 = lay.lv[0].sub_off; s.nsub = lay.lv[0].nsub;
             s.lstride = wp.L > 1 ? lay.lv[1].bits_off - lay.lv[0].bits_off : 0;
             s.image_bytes = lay.image_bytes;
         }
@@ -627,6 +642,8 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
                 d.sel0_off = lvl.sel0_off;
                 d.sel1_off = lvl.sel1_off;
                 d.nsel = lvl.nsel;
+                d.sub_off = lvl.sub_off;
+                d.nsub = lvl.nsub;
                 d.cnt = (uint32_t*)(ws + sp.off_dcnt) + l * std::max<uint64_t>(dch, 1);
                 d.pre = (uint64_t*)(ws + sp.off_dpre) + l * std::max<uint64_t>(dch, 1);
                 d.level = l;

@@ -11,13 +11,14 @@
 #include "wavelet.h"
 
 #define WV_MAGIC        0x54564157u
-#define WV_VERSION      1u
+#define WV_VERSION      2u
 #define WV_HEADER_BYTES 256u
 #define WV_LEVEL_BYTES  64u
 #define WV_NODE_BYTES   32u
 #define WV_CODE_BYTES   16u
 #define WV_SB_BITS      512u    // rank range (superblock), Sec. 5.1
 #define WV_SEL_STRIDE   4096u   // select sampling stride, Sec. 5.1
+#define WV_SUB_STRIDE   512u    // select sub-sampling stride (second level)
 #define WV_MAX_LEVELS   32u
 #define WV_LEAF         0x80000000u
 #define WV_NONE         0xFFFFFFFFu
@@ -43,6 +44,17 @@ __host__ __device__ inline uint32_t wv_key_bits(uint32_t sigma)
 __host__ __device__ inline uint64_t wv_bits_bytes(uint64_t m) { return wv_cdiv(m, 64) * 8; }
 __host__ __device__ inline uint64_t wv_rank_bytes(uint64_t m) { return (wv_cdiv(m, WV_SB_BITS) + 1) * 16; }
 __host__ __device__ inline uint64_t wv_nsel(uint64_t m) { return wv_cdiv(m, WV_SEL_STRIDE) + 1; }
+// Binary levels also keep the position of every one (zero) of ordinal 512j:
+// ones at entry j from the front, zeros at entry nsub-1-j from the back,
+// unused entries m.  ceil(ones/512) + ceil(zeros/512) <= ceil(m/512) + 1, so
+// with one entry more at least one unused entry separates the two halves
+// (the end marker of each).  The array follows sel1; the image's level
+// record does not hold its offset (it is sel1's end rounded to 256 bytes).
+__host__ __device__ inline uint64_t wv_nsub(uint64_t m) { return wv_cdiv(m, WV_SUB_STRIDE) + 2; }
+__host__ __device__ inline uint64_t wv_sub_off(uint64_t sel1_off, uint64_t nsel)
+{
+    return wv_round256(sel1_off + 8 * nsel);
+}
 __host__ __device__ inline uint32_t wv_digits_per_word(uint32_t D) { return D == 3 ? 21u : 64u >> (D >> 1); }
 // ceil(m / (words * digits per word)); a shift for D = 1, 2, 4 (no 64-bit
 // division on the device)
@@ -64,6 +76,7 @@ __host__ __device__ inline uint64_t wv_mrank_bytes(uint64_t m, uint32_t D)
 
 struct wv_level {
     uint64_t n, bits_off, rank_off, sel0_off, sel1_off, nsel;
+    uint64_t sub_off, nsub;   // binary levels: select sub-samples (else 0)
 };
 
 // Everything needed to place the arrays of an image.
@@ -98,12 +111,16 @@ __host__ __device__ inline void wv_layout(const wv_layout_in& in, wv_layout_out&
             off = wv_round256(off + L.nsel * 8);
             L.sel1_off = off;
             off = wv_round256(off + L.nsel * 8);
+            L.nsub = wv_nsub(m);
+            L.sub_off = off;
+            off = wv_round256(off + L.nsub * 4);
         } else {
             // generalized select: 2^D arrays of nsel samples, digit-major
             L.nsel = wv_nsel(m);
             L.sel0_off = off;
             off = wv_round256(off + (8ull << D) * L.nsel);
             L.sel1_off = 0;
+            L.sub_off = L.nsub = 0;
         }
     }
     out.nodes_off = out.codes_off = 0;

@@ -7,8 +7,11 @@
 // word), and each superblock then writes {zeros before it, seven 9-bit zero
 // counts relative to its start}.  Sampled select (Sec. 5.1, "Select"): the
 // superblock holding the one (zero) of ordinal 4096k finds it inside its
-// word and writes its position.  Multiary levels (Sec. 5.2, "Rank"): the same
-// with one counter per digit value.
+// word and writes its position; the same for ordinals 512k into the
+// sub-sample array (the second sampling level of Clark's structure, so that
+// a select searches the ranges between two positions 512 ones apart).
+// Multiary levels (Sec. 5.2, "Rank"): the same with one counter per digit
+// value.
 #include <algorithm>
 
 #include "wv_internal.h"
@@ -71,22 +74,31 @@ dir_write_k(uint8_t* __restrict__ image, wv_level L, const uint64_t* __restrict_
     dir[2 * k] = zeros_before;
     dir[2 * k + 1] = blk;
 
-    // the one of ordinal t (a multiple of 4096) inside this superblock
-    uint64_t t = wv_cdiv(ones_before, WV_SEL_STRIDE) * WV_SEL_STRIDE;
+    // the one of ordinal t (a multiple of 512) inside this superblock (a
+    // superblock holds at most one), a sample when t is a multiple of 4096
+    uint32_t* sub = (uint32_t*)(image + L.sub_off);
+    uint64_t t = wv_cdiv(ones_before, WV_SUB_STRIDE) * WV_SUB_STRIDE;
     if (t < ones_before + oacc) {
         uint32_t r = (uint32_t)(t - ones_before);
         for (int j = 0; j < 8; j++) {
-            if (r < o[j]) { sel1[t / WV_SEL_STRIDE] = base + 64u * j + wv_select_in_word(w[j], r); break; }
+            if (r < o[j]) {
+                const uint64_t p = base + 64u * j + wv_select_in_word(w[j], r);
+                sub[t / WV_SUB_STRIDE] = (uint32_t)p;
+                if (t % WV_SEL_STRIDE == 0) sel1[t / WV_SEL_STRIDE] = p;
+                break;
+            }
             r -= o[j];
         }
     }
-    t = wv_cdiv(zeros_before, WV_SEL_STRIDE) * WV_SEL_STRIDE;
+    t = wv_cdiv(zeros_before, WV_SUB_STRIDE) * WV_SUB_STRIDE;
     if (t < zeros_before + zacc) {
         uint32_t r = (uint32_t)(t - zeros_before);
         for (int j = 0; j < 8; j++) {
             if (r < z[j]) {
                 const int64_t vb = (int64_t)n - (int64_t)(base + 64u * j);
-                sel0[t / WV_SEL_STRIDE] = base + 64u * j + wv_select_in_word(~w[j] & valid_mask(vb), r);
+                const uint64_t p = base + 64u * j + wv_select_in_word(~w[j] & valid_mask(vb), r);
+                sub[L.nsub - 1 - t / WV_SUB_STRIDE] = (uint32_t)p;
+                if (t % WV_SEL_STRIDE == 0) sel0[t / WV_SEL_STRIDE] = p;
                 break;
             }
             r -= z[j];
@@ -116,6 +128,10 @@ dir_finish_k(uint8_t* __restrict__ image, uint32_t level, wv_level L,
     }
     for (uint64_t k = wv_cdiv(ones, WV_SEL_STRIDE) + tid; k < L.nsel; k += stride) sel1[k] = n;
     for (uint64_t k = wv_cdiv(zeros, WV_SEL_STRIDE) + tid; k < L.nsel; k += stride) sel0[k] = n;
+    // sub-samples between the ones' and the zeros' entries
+    uint32_t* sub = (uint32_t*)(image + L.sub_off);
+    const uint64_t sub_hi = L.nsub - wv_cdiv(zeros, WV_SUB_STRIDE);
+    for (uint64_t k = wv_cdiv(ones, WV_SUB_STRIDE) + tid; k < sub_hi; k += stride) sub[k] = (uint32_t)n;
 }
 
 // ---- multiary counters -------------------------------------------------------
@@ -276,7 +292,8 @@ header_k(uint8_t* __restrict__ img, wv_layout_in in, wv_layout_out lay)
             zero_bytes(img, L.sel0_off + (8ull << D) * L.nsel, next);
         } else {
             zero_bytes(img, L.sel0_off + 8 * L.nsel, L.sel1_off);
-            zero_bytes(img, L.sel1_off + 8 * L.nsel, next);
+            zero_bytes(img, L.sel1_off + 8 * L.nsel, L.sub_off);
+            zero_bytes(img, L.sub_off + 4 * L.nsub, next);
         }
         uint64_t* e = (uint64_t*)(img + WV_HEADER_BYTES + (uint64_t)WV_LEVEL_BYTES * t);
         e[0] = L.n;
@@ -547,6 +564,7 @@ constexpr uint32_t SD_W = 2 * SD_T;            // words per chunk (64 superblock
 
 struct SpanLevels {
     uint64_t bits_off[WV_MAX_LEVELS], rank_off[WV_MAX_LEVELS], sel0_off[WV_MAX_LEVELS], sel1_off[WV_MAX_LEVELS];
+    uint64_t sub_off[WV_MAX_LEVELS], nsub[WV_MAX_LEVELS];
     uint64_t n[WV_MAX_LEVELS], nsel[WV_MAX_LEVELS];   // per level (chunks past a level's end count 0)
     uint32_t l0, nl;
 };
@@ -587,7 +605,9 @@ span_write_k(uint8_t* __restrict__ image, SpanLevels a, const uint64_t* __restri
     uint64_t* dir = (uint64_t*)(image + a.rank_off[l]);
     uint64_t* sel0 = (uint64_t*)(image + a.sel0_off[l]);
     uint64_t* sel1 = (uint64_t*)(image + a.sel1_off[l]);
-    constexpr uint32_t SM = WV_SEL_STRIDE - 1;
+    uint32_t* sub = (uint32_t*)(image + a.sub_off[l]);
+    const uint64_t nsub = a.nsub[l];
+    constexpr uint32_t SM = WV_SUB_STRIDE - 1;
     // my two words of chunk c (16-byte aligned: the first is even)
     auto load2 = [&](uint32_t c, uint64_t& y0, uint64_t& y1) {
         const uint64_t w = (uint64_t)c * SD_W + 2 * threadIdx.x;
@@ -628,23 +648,30 @@ span_write_k(uint8_t* __restrict__ image, SpanLevels a, const uint64_t* __restri
         const uint32_t z0 = min(64u * wl, nloc) - ob0, z1 = min(64u * (wl + 1), nloc) - ob1;
         zex[wl] = z0;
         zex[wl + 1] = z1;
-        // sampled select: the one / zero of ordinal 4096k inside one of my
-        // words lies `dist` after the word's first one / zero
+        // sampled select: the one / zero of ordinal 512k inside one of my
+        // words (a word holds at most one) lies `dist` after the word's first
+        // one / zero; a sub-sample, and a sample when 4096 divides the ordinal
         const uint64_t xs[2] = {x0, x1};
         const uint32_t os[2] = {o0, o1}, obs[2] = {ob0, ob1}, zbs[2] = {z0, z1};
         const uint32_t obm = (uint32_t)(obase & SM), zbm = (uint32_t)(zbase & SM);
         for (int q = 0; q < 2; q++) {
             const uint64_t w = w0 + q;
             if (w >= nw) break;
-            const uint32_t d1 = (WV_SEL_STRIDE - ((obm + obs[q]) & SM)) & SM;
-            if (d1 < os[q])
-                sel1[(obase + obs[q] + d1) / WV_SEL_STRIDE] = 64 * w + wv_select_in_word(xs[q], d1);
+            const uint32_t d1 = (WV_SUB_STRIDE - ((obm + obs[q]) & SM)) & SM;
+            if (d1 < os[q]) {
+                const uint64_t ord = obase + obs[q] + d1, p = 64 * w + wv_select_in_word(xs[q], d1);
+                sub[ord / WV_SUB_STRIDE] = (uint32_t)p;
+                if (ord % WV_SEL_STRIDE == 0) sel1[ord / WV_SEL_STRIDE] = p;
+            }
             const uint32_t valid = min(64u, nloc - 64u * (wl + q));
             const uint64_t vm = valid >= 64 ? ~0ull : ((1ull << valid) - 1ull);
             const uint32_t zc = valid - os[q];
-            const uint32_t d0 = (WV_SEL_STRIDE - ((zbm + zbs[q]) & SM)) & SM;
-            if (d0 < zc)
-                sel0[(zbase + zbs[q] + d0) / WV_SEL_STRIDE] = 64 * w + wv_select_in_word(~xs[q] & vm, d0);
+            const uint32_t d0 = (WV_SUB_STRIDE - ((zbm + zbs[q]) & SM)) & SM;
+            if (d0 < zc) {
+                const uint64_t ord = zbase + zbs[q] + d0, p = 64 * w + wv_select_in_word(~xs[q] & vm, d0);
+                sub[nsub - 1 - ord / WV_SUB_STRIDE] = (uint32_t)p;
+                if (ord % WV_SEL_STRIDE == 0) sel0[ord / WV_SEL_STRIDE] = p;
+            }
         }
         __syncthreads();
         // one thread per superblock of the chunk: zeros before it, and the
@@ -680,6 +707,9 @@ span_finish_k(uint8_t* __restrict__ image, SpanLevels a, const uint64_t* __restr
     }
     for (uint64_t k = wv_cdiv(ones, WV_SEL_STRIDE) + threadIdx.x; k < a.nsel[l]; k += SD_T) sel1[k] = n;
     for (uint64_t k = wv_cdiv(zeros, WV_SEL_STRIDE) + threadIdx.x; k < a.nsel[l]; k += SD_T) sel0[k] = n;
+    uint32_t* sub = (uint32_t*)(image + a.sub_off[l]);
+    const uint64_t sub_hi = a.nsub[l] - wv_cdiv(zeros, WV_SUB_STRIDE);
+    for (uint64_t k = wv_cdiv(ones, WV_SUB_STRIDE) + threadIdx.x; k < sub_hi; k += SD_T) sub[k] = (uint32_t)n;
 }
 
 }  // namespace
@@ -717,6 +747,8 @@ hipError_t wv_span_directory(uint8_t* image, const wv_layout_out& lay, uint32_t 
         a.rank_off[l] = lay.lv[l0 + l].rank_off;
         a.sel0_off[l] = lay.lv[l0 + l].sel0_off;
         a.sel1_off[l] = lay.lv[l0 + l].sel1_off;
+        a.sub_off[l] = lay.lv[l0 + l].sub_off;
+        a.nsub[l] = lay.lv[l0 + l].nsub;
     }
     uint32_t* cnt = (uint32_t*)(scratch + sz.off_cnt);
     uint64_t* pre = (uint64_t*)(scratch + sz.off_pre);

@@ -10,8 +10,9 @@
 //   shaped trees: the node table gives every node's start and children;
 //   multiary trees: per-digit counters replace rank0.
 // select walks down to the symbol's range, then back up with select0/1,
-// which uses the sampled positions plus a binary search over the rank
-// superblocks (Sec. 5.1).  One thread answers one query.
+// which takes the sub-sampled positions of ordinals 512j and 512(j+1) (the
+// second sampling level of Clark's structure) and searches the rank
+// superblocks between them (Sec. 5.1).  One thread answers one query.
 #include "wv_internal.h"
 
 namespace {
@@ -20,7 +21,7 @@ constexpr int Q_THREADS = 256;
 constexpr uint64_t U64MAX = ~0ull;
 
 struct QLevel {
-    uint64_t n, zeros, bits_off, rank_off, sel0_off, sel1_off, nsel;
+    uint64_t n, zeros, bits_off, rank_off, sel0_off, sel1_off, nsel, sub_off, nsub;
 };
 
 struct QImg {
@@ -44,7 +45,11 @@ __device__ inline void load_image(const uint8_t* img, QImg& q)
     q.codes_off = h64[9];
     for (uint32_t l = 0; l < q.nlevels; l++) {
         const uint64_t* e = (const uint64_t*)(img + WV_HEADER_BYTES + (uint64_t)WV_LEVEL_BYTES * l);
-        q.lv[l] = QLevel{e[0], e[1], e[3], e[4], e[5], e[6], e[7]};
+        q.lv[l] = QLevel{e[0], e[1], e[3], e[4], e[5], e[6], e[7], 0, 0};
+        if (q.kind != WT_KIND_MULTIARY) {   // binary: the sub-samples follow sel1
+            q.lv[l].sub_off = wv_sub_off(e[6], e[7]);
+            q.lv[l].nsub = wv_nsub(e[0]);
+        }
     }
 }
 
@@ -67,12 +72,15 @@ __device__ inline uint64_t rankb(const QImg& q, uint32_t l, uint32_t b, uint64_t
 __device__ uint64_t selectb(const QImg& q, uint32_t l, uint32_t b, uint64_t j)
 {
     const QLevel& L = q.lv[l];
-    const uint64_t* sel = (const uint64_t*)(q.img + (b ? L.sel1_off : L.sel0_off));
+    const uint32_t* sub = (const uint32_t*)(q.img + L.sub_off);
     const uint64_t* dir = dir_of(q, l);
     const uint64_t* words = words_of(q, l);
     const uint64_t ns = wv_cdiv(L.n, WV_SB_BITS), nw = wv_cdiv(L.n, 64);
-    const uint64_t s = j / WV_SEL_STRIDE;
-    const uint64_t p0 = sel[s], p1 = sel[s + 1];
+    // ordinals 512s and 512(s+1): ones from the front of the array, zeros
+    // from its back; past the last one (zero) of the level the entry is n
+    const uint64_t s = j / WV_SUB_STRIDE;
+    const uint64_t p0 = b ? sub[s] : sub[L.nsub - 1 - s];
+    const uint64_t p1 = b ? sub[s + 1] : sub[L.nsub - 2 - s];
     uint64_t lo = p0 >> 9, hi = (p1 >> 9) < ns ? (p1 >> 9) : ns - 1;
     auto before = [&](uint64_t k) -> uint64_t { return b ? (k * WV_SB_BITS - dir[2 * k]) : dir[2 * k]; };
     while (lo < hi) {

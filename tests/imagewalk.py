@@ -41,9 +41,13 @@ class Image:
         self.levels = []
         for l in range(self.nlevels):
             e = _u64(b, self.levels_off + 64 * l, 8)
-            self.levels.append(dict(n=int(e[0]), zeros=int(e[1]), ones=int(e[2]),
-                                    bits_off=int(e[3]), rank_off=int(e[4]),
-                                    sel0_off=int(e[5]), sel1_off=int(e[6]), nsel=int(e[7])))
+            lv = dict(n=int(e[0]), zeros=int(e[1]), ones=int(e[2]), bits_off=int(e[3]), rank_off=int(e[4]),
+                      sel0_off=int(e[5]), sel1_off=int(e[6]), nsel=int(e[7]), sub_off=0, nsub=0)
+            if self.kind != 4:
+                # binary: the select sub-samples follow sel1 (not in the record)
+                lv["sub_off"] = (lv["sel1_off"] + 8 * lv["nsel"] + 255) // 256 * 256
+                lv["nsub"] = -(-lv["n"] // 512) + 2
+            self.levels.append(lv)
         self._bits = {}
         self._zpre = {}
 
@@ -76,6 +80,12 @@ class Image:
         lv = self.levels[l]
         off = lv["sel1_off"] if which else lv["sel0_off"]
         return _u64(self.buf, off, lv["nsel"])
+
+    def sub(self, l: int) -> np.ndarray:
+        """select sub-samples: ones' positions of ordinal 512j at j, zeros'
+        at nsub-1-j, unused entries n"""
+        lv = self.levels[l]
+        return np.frombuffer(self.buf[lv["sub_off"]:lv["sub_off"] + 4 * lv["nsub"]].tobytes(), dtype=np.uint32)
 
     def rank0_via_directory(self, l: int, i: int) -> int:
         """zeros in [0, i) using only the directory and one word."""
@@ -385,6 +395,8 @@ def array_digests(buf: np.ndarray) -> dict:
                  ("rank", lv["rank_off"], 16 * (-(-m // 512) + 1)),
                  ("sel0", lv["sel0_off"], 8 * lv["nsel"]),
                  ("sel1", lv["sel1_off"], 8 * lv["nsel"])]
+        if lv["sub_off"]:
+            spans.append(("sub", lv["sub_off"], 4 * lv["nsub"]))
         for name, off, size in spans:
             if off:
                 out[f"level{l}.{name}"] = hashlib.sha256(b[off:off + size].tobytes()).hexdigest()

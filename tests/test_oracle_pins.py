@@ -262,6 +262,16 @@ def test_rank_select_directory(n):
             want = np.full(nsel, n, dtype=np.uint64)
             want[:pos.size] = pos
             assert np.array_equal(s, want)
+        # second sampling level: every 512th one from the front, every 512th
+        # zero from the back, n in between (at least one such entry)
+        nsub = -(-n // 512) + 2
+        sub = img.sub(0)
+        ones, zeros = np.flatnonzero(bits == 1)[::512], np.flatnonzero(bits == 0)[::512]
+        want = np.full(nsub, n, dtype=np.uint32)
+        want[:ones.size] = ones
+        want[nsub - zeros.size:] = zeros[::-1]
+        assert ones.size + zeros.size < nsub
+        assert np.array_equal(sub, want)
         # padding bits past n are zero
         w = img.words(0)
         if n % 64:
@@ -506,6 +516,8 @@ def test_layout(kind, D):
             spans.append((lv["rank_off"], lv["rank_off"] + 16 * (-(-m // 512) + 1)))
             spans.append((lv["sel0_off"], lv["sel0_off"] + 8 * lv["nsel"]))
             spans.append((lv["sel1_off"], lv["sel1_off"] + 8 * lv["nsel"]))
+            assert lv["sub_off"] % 256 == 0 and lv["nsub"] == -(-m // 512) + 2
+            spans.append((lv["sub_off"], lv["sub_off"] + 4 * lv["nsub"]))
     if kind == KIND_SHAPED:
         spans.append((img.nodes_off, img.nodes_off + 32 * img.nnodes))
         spans.append((img.codes_off, img.codes_off + 16 * img.sigma))
