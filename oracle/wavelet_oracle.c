@@ -13,7 +13,9 @@
  *      the topology pointers are dropped, as Sec. 2 notes is possible);
  *   - the wavelet matrix (Sec. 4.3, paragraph "Wavelet matrix");
  *   - the arbitrary-shaped binary wavelet tree given codewords
- *     (Sec. 4.3, paragraph "Arbitrarily-shaped binary trees");
+ *     (Sec. 4.3, paragraph "Arbitrarily-shaped binary trees"), and the same
+ *     over codewords of D-bit digits, a shaped multiary tree (the paper notes
+ *     shapes carry over to multiary trees);
  *   - the balanced multiary wavelet tree of degree d = 2^D
  *     (Sec. 4.3, paragraph "Multiary wavelet trees");
  *   - the rank-of-0 directory of every binary level (Sec. 5.1, "Rank":
@@ -56,7 +58,11 @@
 #define O_VERSION      2u
 #define O_HEADER_BYTES 256u
 #define O_LEVEL_BYTES  64u
-#define O_NODE_BYTES   32u
+#define O_NODE_BYTES   32u    /* binary shaped trees */
+/* shaped trees of D-bit digits (D >= 2): u64 start, u64 count, u32 level,
+ * u32 prefix, u32 child[2^D] */
+static uint64_t mnode_bytes(unsigned D) { return 24u + 4u * ((uint64_t)1 << D); }
+static uint64_t node_bytes(unsigned D) { return D >= 2 ? mnode_bytes(D) : O_NODE_BYTES; }
 #define O_CODE_BYTES   16u
 #define O_RANGE_BITS   512u   /* rank directory range (superblock) */
 #define O_SUB_BITS     64u    /* rank directory sub-range (block) */
@@ -159,7 +165,7 @@ static uint64_t lay_out(olevel* lv, unsigned nlev, int multiary, unsigned D,
     *nodes_off = *codes_off = 0;
     if (shaped) {
         *nodes_off = off;
-        off = round256(off + nnodes * O_NODE_BYTES);
+        off = round256(off + nnodes * node_bytes(D));
         *codes_off = off;
         off = round256(off + (uint64_t)sigma * O_CODE_BYTES);
     }
@@ -466,11 +472,23 @@ static int64_t find_node(const onode_key* nodes, uint64_t nn, uint32_t level, ui
  * prefixes of length l of the codewords; level l holds, for every symbol
  * whose codeword is longer than l, bit l of its codeword, in the order of a
  * stable sort by the first l codeword bits (node order, left to right). */
-static int build_shaped(uint8_t* img_or_null, olevel* lv, unsigned h,
+/* The shaped tree of D-bit digits (D = 1: binary; Sec. 4.3, the shape
+ * carried over to multiary trees): a codeword has lens[s] digits, digit l at
+ * bits [D(lens-1-l), D(lens-l)) of codes[s].  Level l holds digit l of every
+ * symbol whose codeword is longer than l, node by node in prefix order, in
+ * input order inside a node. */
+static uint64_t code_prefix(const uint64_t* codes, const uint32_t* lens, uint32_t s, unsigned l, unsigned D)
+{
+    return l ? (codes[s] >> (D * (lens[s] - l))) : 0;
+}
+
+static int build_shaped(uint8_t* img_or_null, olevel* lv, unsigned h, unsigned D,
                         const uint32_t* x, uint64_t n, uint32_t sigma,
                         const uint64_t* codes, const uint32_t* lens,
                         onode_key* nodes, uint64_t nnodes, uint8_t* node_rec)
 {
+    const uint64_t nb = node_bytes(D);
+    const uint32_t d = 1u << D;
     /* cur: indices into x of the symbols on the current level */
     uint64_t* cur = (uint64_t*)malloc((n ? n : 1) * sizeof(uint64_t));
     uint64_t* nxt = (uint64_t*)malloc((n ? n : 1) * sizeof(uint64_t));
@@ -482,28 +500,32 @@ static int build_shaped(uint8_t* img_or_null, olevel* lv, unsigned h,
         if (m != lv[l].n) { free(cur); free(nxt); free(b); return O_EINVAL; }
         for (uint64_t k = 0; k < m; k++) {
             uint32_t s = x[cur[k]];
-            b[k] = (uint8_t)((codes[s] >> (lens[s] - 1 - l)) & 1);
+            b[k] = (uint8_t)((codes[s] >> (D * (lens[s] - 1 - l))) & (d - 1));
         }
         if (img_or_null) {
-            int rc = write_binary_level(img_or_null, &lv[l], b);
-            if (rc) { free(cur); free(nxt); free(b); return rc; }
+            if (D == 1) {
+                int rc = write_binary_level(img_or_null, &lv[l], b);
+                if (rc) { free(cur); free(nxt); free(b); return rc; }
+            } else {
+                write_multi_level(img_or_null, &lv[l], b, D);
+            }
         }
         /* node records of depth l: start and count of every node segment */
         uint64_t s0 = 0;
         while (s0 < m) {
             uint32_t sy = x[cur[s0]];
-            uint64_t p = l ? (codes[sy] >> (lens[sy] - l)) : 0;
+            uint64_t p = code_prefix(codes, lens, sy, l, D);
             uint64_t e = s0 + 1;
             while (e < m) {
                 uint32_t t = x[cur[e]];
-                uint64_t q = l ? (codes[t] >> (lens[t] - l)) : 0;
+                uint64_t q = code_prefix(codes, lens, t, l, D);
                 if (q != p) break;
                 e++;
             }
             int64_t id = find_node(nodes, nnodes, l, p);
             if (id < 0) { free(cur); free(nxt); free(b); return O_EINVAL; }
-            put_u64(node_rec + (uint64_t)id * O_NODE_BYTES + 0, s0);
-            put_u64(node_rec + (uint64_t)id * O_NODE_BYTES + 8, e - s0);
+            put_u64(node_rec + (uint64_t)id * nb + 0, s0);
+            put_u64(node_rec + (uint64_t)id * nb + 8, e - s0);
             s0 = e;
         }
         /* go down: stable partition inside each node, then drop the symbols
@@ -512,17 +534,17 @@ static int build_shaped(uint8_t* img_or_null, olevel* lv, unsigned h,
         s0 = 0;
         while (s0 < m) {
             uint32_t sy = x[cur[s0]];
-            uint64_t p = l ? (codes[sy] >> (lens[sy] - l)) : 0;
+            uint64_t p = code_prefix(codes, lens, sy, l, D);
             uint64_t e = s0 + 1;
             while (e < m) {
                 uint32_t t = x[cur[e]];
-                uint64_t q = l ? (codes[t] >> (lens[t] - l)) : 0;
+                uint64_t q = code_prefix(codes, lens, t, l, D);
                 if (q != p) break;
                 e++;
             }
-            for (int bit = 0; bit < 2; bit++)
+            for (uint32_t digit = 0; digit < d; digit++)
                 for (uint64_t k = s0; k < e; k++)
-                    if (b[k] == bit && lens[x[cur[k]]] > l + 1) nxt[o++] = cur[k];
+                    if (b[k] == digit && lens[x[cur[k]]] > l + 1) nxt[o++] = cur[k];
             s0 = e;
         }
         uint64_t* t = cur; cur = nxt; nxt = t;
@@ -632,8 +654,9 @@ int oracle_build(int kind, const void* S, int sym_bytes, uint64_t n, uint32_t si
     *image_bytes = 0;
     if (sigma == 0) return O_EINVAL;
     if (kind < O_KIND_WT || kind > O_KIND_MULTI) return O_EINVAL;
-    if (kind == O_KIND_MULTI && (arity_log2 < 1 || arity_log2 > 4)) return O_EINVAL;
-    if (kind != O_KIND_MULTI) arity_log2 = 1;
+    if (kind == O_KIND_SHAPED && arity_log2 == 0) arity_log2 = 1;   /* binary */
+    if ((kind == O_KIND_MULTI || kind == O_KIND_SHAPED) && (arity_log2 < 1 || arity_log2 > 4)) return O_EINVAL;
+    if (kind != O_KIND_MULTI && kind != O_KIND_SHAPED) arity_log2 = 1;
     if (kind == O_KIND_SHAPED && (!codes || !lens)) return O_EINVAL;
 
     uint32_t* x = NULL;
@@ -657,16 +680,17 @@ int oracle_build(int kind, const void* S, int sym_bytes, uint64_t n, uint32_t si
         key_bits = D * nlev;
         for (unsigned l = 0; l < nlev; l++) lv[l].n = n;
     } else {
+        /* code lengths count D-bit digits; at most 32 bits per codeword */
         unsigned h = 0;
         for (uint32_t s = 0; s < sigma; s++) {
-            if (lens[s] > O_MAX_CODE_LEN) { free(x); return O_EUNSUP; }
+            if ((uint64_t)lens[s] * D > O_MAX_CODE_LEN) { free(x); return O_EUNSUP; }
             if (lens[s]) { ncoded++; if (lens[s] > h) h = lens[s]; }
         }
         for (uint64_t i = 0; i < n; i++)
             if (lens[x[i]] == 0) { free(x); return O_ERANGE; }
         if (h == 0) { free(x); return O_EINVAL; }
         nlev = h;
-        key_bits = h;
+        key_bits = h * D;
         for (uint64_t i = 0; i < n; i++)
             for (unsigned l = 0; l < lens[x[i]]; l++) lv[l].n++;
         /* internal nodes: proper prefixes of the codewords */
@@ -677,7 +701,7 @@ int oracle_build(int kind, const void* S, int sym_bytes, uint64_t n, uint32_t si
         for (uint32_t s = 0; s < sigma; s++)
             for (unsigned l = 0; l < lens[s]; l++) {
                 nodes[nnodes].level = l;
-                nodes[nnodes].prefix = l ? (codes[s] >> (lens[s] - l)) : 0;
+                nodes[nnodes].prefix = code_prefix(codes, lens, s, l, D);
                 nnodes++;
             }
         qsort(nodes, nnodes, sizeof(onode_key), cmp_node_key);
@@ -688,7 +712,8 @@ int oracle_build(int kind, const void* S, int sym_bytes, uint64_t n, uint32_t si
     }
 
     uint64_t nodes_off = 0, codes_off = 0;
-    uint64_t total = lay_out(lv, nlev, kind == O_KIND_MULTI, D, nnodes, sigma,
+    const int multi_levels = kind == O_KIND_MULTI || (kind == O_KIND_SHAPED && D >= 2);
+    uint64_t total = lay_out(lv, nlev, multi_levels, D, nnodes, sigma,
                              kind == O_KIND_SHAPED, &nodes_off, &codes_off);
     uint8_t* img = (uint8_t*)calloc(1, total);
     if (!img) { free(x); free(nodes); return O_ENOMEM; }
@@ -698,31 +723,32 @@ int oracle_build(int kind, const void* S, int sym_bytes, uint64_t n, uint32_t si
     else if (kind == O_KIND_MULTI) rc = build_multi(img, lv, L, D, x, n);
     else {
         uint8_t* rec = img + nodes_off;
+        const uint64_t nb = node_bytes(D);
+        const uint32_t d = 1u << D;
         /* every node starts empty at the position its symbols would take */
-        rc = build_shaped(img, lv, nlev, x, n, sigma, codes, lens, nodes, nnodes, rec);
+        rc = build_shaped(img, lv, nlev, D, x, n, sigma, codes, lens, nodes, nnodes, rec);
         if (rc == O_OK) {
             /* empty nodes (codewords of absent symbols): start = number of
-             * level-l symbols whose l-bit prefix is smaller */
+             * level-l symbols whose l-digit prefix is smaller */
             for (uint64_t t = 0; t < nnodes; t++) {
                 uint64_t cnt;
-                memcpy(&cnt, rec + t * O_NODE_BYTES + 8, 8);
+                memcpy(&cnt, rec + t * nb + 8, 8);
                 if (cnt) continue;
                 uint64_t before = 0;
                 for (uint64_t i = 0; i < n; i++) {
                     uint32_t s = x[i];
                     unsigned l = nodes[t].level;
-                    if (lens[s] > l) {
-                        uint64_t p = l ? (codes[s] >> (lens[s] - l)) : 0;
-                        if (p < nodes[t].prefix) before++;
-                    }
+                    if (lens[s] > l && code_prefix(codes, lens, s, l, D) < nodes[t].prefix) before++;
                 }
-                put_u64(rec + t * O_NODE_BYTES + 0, before);
+                put_u64(rec + t * nb + 0, before);
             }
+            /* children: an internal node, a leaf (a symbol whose codeword is
+             * this prefix), or none */
             for (uint64_t t = 0; t < nnodes; t++) {
-                uint8_t* e = rec + t * O_NODE_BYTES;
-                for (int c = 0; c < 2; c++) {
+                uint8_t* e = rec + t * nb;
+                for (uint32_t c = 0; c < d; c++) {
                     uint32_t l1 = nodes[t].level + 1;
-                    uint64_t q = nodes[t].prefix * 2 + (uint64_t)c;
+                    uint64_t q = nodes[t].prefix * d + (uint64_t)c;
                     uint32_t child = O_NO_CHILD;
                     int64_t id = find_node(nodes, nnodes, l1, q);
                     if (id >= 0) {
@@ -731,10 +757,10 @@ int oracle_build(int kind, const void* S, int sym_bytes, uint64_t n, uint32_t si
                         for (uint32_t s = 0; s < sigma; s++)
                             if (lens[s] == l1 && codes[s] == q) { child = O_LEAF_FLAG | s; break; }
                     }
-                    put_u32(e + 16 + 4 * c, child);
+                    put_u32(e + (D == 1 ? 16 : 24) + 4 * c, child);
                 }
-                put_u32(e + 24, nodes[t].level);
-                put_u32(e + 28, (uint32_t)nodes[t].prefix);
+                put_u32(e + (D == 1 ? 24 : 16), nodes[t].level);
+                put_u32(e + (D == 1 ? 28 : 20), (uint32_t)nodes[t].prefix);
             }
             for (uint32_t s = 0; s < sigma; s++) {
                 put_u64(img + codes_off + (uint64_t)s * O_CODE_BYTES, lens[s] ? codes[s] : 0);

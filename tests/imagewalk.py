@@ -38,12 +38,14 @@ class Image:
         self.nnodes = int(_u64(b, 64)[0])
         self.codes_off = int(_u64(b, 72)[0])
         self.ncoded = int(_u64(b, 80)[0])
+        # digit levels: multiary trees, and shaped trees of D-bit digits
+        self.multi_levels = self.kind == 4 or (self.kind == 3 and self.arity_log2 >= 2)
         self.levels = []
         for l in range(self.nlevels):
             e = _u64(b, self.levels_off + 64 * l, 8)
             lv = dict(n=int(e[0]), zeros=int(e[1]), ones=int(e[2]), bits_off=int(e[3]), rank_off=int(e[4]),
                       sel0_off=int(e[5]), sel1_off=int(e[6]), nsel=int(e[7]), sub_off=0, nsub=0)
-            if self.kind != 4:
+            if not self.multi_levels:
                 # binary: the select sub-samples follow sel1 (not in the record)
                 lv["sub_off"] = (lv["sel1_off"] + 8 * lv["nsel"] + 255) // 256 * 256
                 lv["nsub"] = -(-lv["n"] // 512) + 2
@@ -137,16 +139,44 @@ class Image:
 
     # ---- shaped trees ------------------------------------------------------
     def nodes(self):
+        """node records: binary {u64 start, u64 count, u32 child[2], u32 level,
+        u32 prefix}; D-bit digits {u64 start, u64 count, u32 level, u32 prefix,
+        u32 child[2^D]}"""
         if getattr(self, "_nodes", None) is not None:
             return self._nodes
         out = []
+        D = self.arity_log2 if self.multi_levels else 1
+        d = 1 << D
+        rb = 32 if D == 1 else 24 + 4 * d
         for t in range(self.nnodes):
-            o = self.nodes_off + 32 * t
+            o = self.nodes_off + rb * t
             st, cnt = (int(v) for v in _u64(self.buf, o, 2))
-            c0, c1, lev, pre = (int(v) for v in np.frombuffer(self.buf[o + 16:o + 32].tobytes(), dtype=np.uint32))
-            out.append(dict(start=st, count=cnt, child=(c0, c1), level=lev, prefix=pre))
+            w = [int(v) for v in np.frombuffer(self.buf[o + 16:o + rb].tobytes(), dtype=np.uint32)]
+            if D == 1:
+                out.append(dict(start=st, count=cnt, child=(w[0], w[1]), level=w[2], prefix=w[3]))
+            else:
+                out.append(dict(start=st, count=cnt, child=tuple(w[2:2 + d]), level=w[0], prefix=w[1]))
         self._nodes = out
         return out
+
+    # ---- levels of either form (bits, or D-bit digits) ---------------------
+    def sym_at(self, l: int, p: int) -> int:
+        return int(self.digits(l)[p]) if self.multi_levels else int(self.bits(l)[p])
+
+    def rank_any(self, l: int, g: int, i: int) -> int:
+        """occurrences of bit / digit g in [0, i) of level l"""
+        return self.mrank(l, g, i) if self.multi_levels else self.rank(l, g, i)
+
+    def select_any(self, l: int, g: int, j: int) -> int:
+        if self.multi_levels:
+            return int(np.flatnonzero(self.digits(l) == g)[j])
+        return self.select(l, g, j)
+
+    def code_digit(self, c: int, t: int) -> int:
+        """digit t (from the top) of c's codeword"""
+        codes, lens = self.codes()
+        D = self.arity_log2 if self.multi_levels else 1
+        return int((int(codes[c]) >> (D * (int(lens[c]) - 1 - t))) & ((1 << D) - 1))
 
     def codes(self):
         if getattr(self, "_codes", None) is not None:
@@ -199,8 +229,8 @@ class Image:
             while True:
                 nd = nodes[v]
                 l, st = nd["level"], nd["start"]
-                b = int(self.bits(l)[st + rel])
-                rel = self.rank(l, b, st + rel) - self.rank(l, b, st)
+                b = self.sym_at(l, st + rel)
+                rel = self.rank_any(l, b, st + rel) - self.rank_any(l, b, st)
                 ch = nd["child"][b]
                 if ch & LEAF:
                     return ch & ~LEAF
@@ -250,8 +280,8 @@ class Image:
             for t in range(int(lens[c])):
                 nd = nodes[v]
                 l, st = nd["level"], nd["start"]
-                b = int((int(codes[c]) >> (int(lens[c]) - 1 - t)) & 1)
-                rel = self.rank(l, b, st + rel) - self.rank(l, b, st)
+                b = self.code_digit(c, t)
+                rel = self.rank_any(l, b, st + rel) - self.rank_any(l, b, st)
                 v = nd["child"][b]
             return rel
         raise ValueError("kind")
@@ -301,14 +331,13 @@ class Image:
             v = 0
             for t in range(int(lens[c])):
                 path.append(v)
-                b = int((int(codes[c]) >> (int(lens[c]) - 1 - t)) & 1)
-                v = nodes[v]["child"][b]
+                v = nodes[v]["child"][self.code_digit(c, t)]
             rel = k - 1
             for t in range(int(lens[c]) - 1, -1, -1):
                 nd = nodes[path[t]]
                 l, st = nd["level"], nd["start"]
-                b = int((int(codes[c]) >> (int(lens[c]) - 1 - t)) & 1)
-                rel = self.select(l, b, self.rank(l, b, st) + rel) - st
+                b = self.code_digit(c, t)
+                rel = self.select_any(l, b, self.rank_any(l, b, st) + rel) - st
             return rel
         if self.kind == KIND_MULTI:
             lo, hi = 0, self.n - 1

@@ -17,6 +17,7 @@ import os
 import numpy as np
 import pytest
 
+import dary
 import oracle
 from imagewalk import Image, KIND_MULTI, KIND_SHAPED, KIND_WM, KIND_WT, LEAF
 
@@ -81,6 +82,9 @@ def brute_select(S, c, k):
 
 
 def build(kind, S, sigma, D=1):
+    if kind == KIND_SHAPED and D >= 2:
+        lens = dary.huffman_lengths(oracle.symbol_counts(S, sigma), D)
+        return oracle.build_image(kind, S, sigma, D, codes=dary.canonical(lens, D), lens=lens)
     if kind == KIND_SHAPED:
         codes, lens = oracle.huffman(oracle.symbol_counts(S, sigma))
         return oracle.build_image(kind, S, sigma, codes=codes, lens=lens)
@@ -491,7 +495,8 @@ def test_errors():
     assert e.value.code == oracle.ERANGE
 
 
-@pytest.mark.parametrize("kind,D", [(KIND_WT, 1), (KIND_WM, 1), (KIND_MULTI, 2), (KIND_SHAPED, 1)])
+@pytest.mark.parametrize("kind,D", [(KIND_WT, 1), (KIND_WM, 1), (KIND_MULTI, 2), (KIND_SHAPED, 1),
+                                    (KIND_SHAPED, 2), (KIND_SHAPED, 4)])
 def test_layout(kind, D):
     rng = np.random.default_rng(kind)
     S = rng.integers(0, 37, 1000).astype(np.uint8)
@@ -504,7 +509,7 @@ def test_layout(kind, D):
             if lv[key]:
                 assert lv[key] % 256 == 0
         m = lv["n"]
-        if kind == KIND_MULTI:
+        if img.multi_levels:
             p = 64 // D
             d = 1 << D
             spans.append((lv["bits_off"], lv["bits_off"] + 8 * (-(-m // p))))
@@ -519,7 +524,8 @@ def test_layout(kind, D):
             assert lv["sub_off"] % 256 == 0 and lv["nsub"] == -(-m // 512) + 2
             spans.append((lv["sub_off"], lv["sub_off"] + 4 * lv["nsub"]))
     if kind == KIND_SHAPED:
-        spans.append((img.nodes_off, img.nodes_off + 32 * img.nnodes))
+        rb = 32 if D == 1 else 24 + 4 * (1 << D)
+        spans.append((img.nodes_off, img.nodes_off + rb * img.nnodes))
         spans.append((img.codes_off, img.codes_off + 16 * img.sigma))
     spans.sort()
     for (a0, a1), (b0, b1) in zip(spans, spans[1:]):
@@ -571,3 +577,98 @@ def test_multiary_select_samples(D):
                 want = np.full(nsel, m, dtype=np.uint64)
                 want[:pos.size] = pos
                 assert np.array_equal(tab[c], want), (sigma, n, D, l, c)
+
+
+# ---------------------------------------------------------------------------
+# shaped trees over D-bit digits (Sec. 4.3: shapes carry over to multiary
+# trees); pinned against closed forms and brute force, never against the
+# binary shaped code path
+# ---------------------------------------------------------------------------
+
+def dary_prefix(codes, lens, syms, l, D):
+    c = codes[syms].astype(np.uint64)
+    sh = (D * (lens[syms].astype(np.int64) - l)).astype(np.uint64)
+    return np.where(l > 0, c >> sh, np.uint64(0))
+
+
+@pytest.mark.parametrize("D", [2, 3, 4])
+@pytest.mark.parametrize("seed", range(6))
+def test_shaped_multiary_closed_form(D, seed):
+    """level l holds digit l of every symbol whose codeword is longer than l,
+    stably sorted by its l-digit prefix; each node record's start and count
+    are the symbols of its level under smaller prefixes and under its own; a
+    child is the node of the extended prefix, else the leaf of the symbol
+    whose codeword it is, else absent"""
+    rng = np.random.default_rng(100 * D + seed)
+    d = 1 << D
+    sigma = int(rng.integers(2, 400))
+    n = int(rng.integers(1, 4000))
+    S = np.minimum(rng.geometric(0.02, n) - 1, sigma - 1).astype(np.uint16)
+    lens = dary.random_lengths(sigma, D, rng)   # codewords for absent symbols too
+    codes = dary.canonical(lens, D)
+    img = Image(oracle.build_image(KIND_SHAPED, S, sigma, D, codes=codes, lens=lens))
+    h = int(lens.max())
+    assert img.nlevels == h and img.arity_log2 == D and img.multi_levels
+    for l in range(h):
+        idx = np.flatnonzero(lens[S] > l)
+        pre = dary_prefix(codes, lens, S[idx], l, D)
+        order = idx[np.argsort(pre, kind="stable")]
+        want = (codes[S[order]] >> (np.uint64(D) * (lens[S[order]].astype(np.uint64) - np.uint64(1 + l)))) & np.uint64(d - 1)
+        assert np.array_equal(img.digits(l), want.astype(np.int64)), f"level {l}"
+        assert img.levels[l]["n"] == idx.size
+    nodes = img.nodes()
+    keys = {(nd["level"], nd["prefix"]): t for t, nd in enumerate(nodes)}
+    want_keys = {(l, int(p)) for s_ in range(sigma) for l in range(int(lens[s_]))
+                 for p in [int(codes[s_]) >> (D * (int(lens[s_]) - l)) if l else 0]}
+    assert set(keys) == want_keys
+    assert [k for k in sorted(keys)] == [(nd["level"], nd["prefix"]) for nd in nodes]
+    leaf = {(int(lens[s_]), int(codes[s_])): s_ for s_ in range(sigma) if lens[s_]}
+    for nd in nodes:
+        l, p = nd["level"], nd["prefix"]
+        idx = np.flatnonzero(lens[S] > l)
+        pre = dary_prefix(codes, lens, S[idx], l, D)
+        assert nd["count"] == int(np.count_nonzero(pre == p))
+        assert nd["start"] == int(np.count_nonzero(pre < p))
+        for c in range(d):
+            q = p * d + c
+            if (l + 1, q) in keys:
+                assert nd["child"][c] == keys[(l + 1, q)]
+            elif (l + 1, q) in leaf:
+                assert nd["child"][c] == LEAF | leaf[(l + 1, q)]
+            else:
+                assert nd["child"][c] == 0xFFFFFFFF
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_shaped_multiary_tiny_exhaustive_queries(D):
+    """every sequence of length <= 4 over 4 symbols, with a d-ary Huffman code
+    and with a random code that also covers absent symbols: access, rank and
+    select walked through the image equal brute force"""
+    rng = np.random.default_rng(D)
+    sigma = 4
+    for n in range(1, 5):
+        for S in itertools.product(range(sigma), repeat=n):
+            S = np.array(S, dtype=np.uint8)
+            for variant in range(2):
+                if variant == 0:
+                    lens = dary.huffman_lengths(oracle.symbol_counts(S, sigma), D)
+                else:
+                    lens = dary.random_lengths(sigma, D, rng)
+                codes = dary.canonical(lens, D)
+                img = Image(oracle.build_image(KIND_SHAPED, S, sigma, D, codes=codes, lens=lens))
+                check_queries(img, S, sigma, all_symbols=variant == 1)
+
+
+def test_shaped_multiary_refusals():
+    """a codeword of more than 32 bits is refused, and so is a symbol of S
+    without a codeword"""
+    S = np.array([0, 1, 2], dtype=np.uint8)
+    lens = np.array([9, 1, 1], dtype=np.uint32)   # 9 digits of 4 bits
+    codes = dary.canonical(lens, 4)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.build_image(KIND_SHAPED, S, 3, 4, codes=codes, lens=lens)
+    assert e.value.code == oracle.EUNSUP
+    lens = np.array([1, 1, 0], dtype=np.uint32)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.build_image(KIND_SHAPED, S, 3, 2, codes=dary.canonical(lens, 2), lens=lens)
+    assert e.value.code == oracle.ERANGE
