@@ -100,11 +100,17 @@ extern "C" {
  *                 then the generalized select samples (Sec. 5.2, "Select"):
  *                 for every digit value c (c-major) nsel = ceil(n_l/4096)+1
  *                 u64: position of the c of 0-based ordinal 4096k, then n_l.
- *   shaped trees  node table (32 B per internal node, ordered by (level,
- *                 prefix)): u64 start in its level, u64 count, u32 child[2]
- *                 (node index, or 0x80000000|symbol for a leaf, 0xFFFFFFFF
- *                 if absent), u32 level, u32 prefix; then the code table
- *                 (16 B per symbol): u64 codeword, u32 length (0 = none), u32 0.
+ *   shaped trees  node table (one record per internal node, ordered by
+ *                 (level, prefix)): binary codes, 32 B: u64 start in its
+ *                 level, u64 count, u32 child[2] (node index, or
+ *                 0x80000000|symbol for a leaf, 0xFFFFFFFF if absent),
+ *                 u32 level, u32 prefix; codes of D-bit digits (D >= 2),
+ *                 24 + 4*2^D B: u64 start, u64 count, u32 level, u32 prefix,
+ *                 u32 child[2^D]; then the code table (16 B per symbol): u64
+ *                 codeword, u32 length in digits (0 = none), u32 0.  A shaped
+ *                 tree over D-bit digits has multiary levels (as above, with
+ *                 the level sizes of its codewords) and arity_log2 = D in
+ *                 its header.
  * Bytes outside every array are zero.  Balanced trees (Sec. 2): level l is
  * the concatenation of the node bitstrings of depth l, left to right, every
  * level has n bits.  Wavelet matrix: level l is bit l from the top of the
@@ -112,13 +118,19 @@ extern "C" {
  * ------------------------------------------------------------------------ */
 
 typedef struct wt_shape {
-    uint32_t arity_log2;       /* multiary: D in 1..4; binary kinds: 0 or 1 */
+    uint32_t arity_log2;       /* multiary: D in 1..4; shaped: 0 or 1 for
+                                  binary codewords, 2..4 for codewords of
+                                  D-bit digits (a shaped multiary tree, the
+                                  shape carried over to multiary trees,
+                                  Sec. 4.3); WT/WM: 0 or 1                  */
     uint32_t reserved;
     const uint64_t* codes;     /* shaped: host [sigma], codeword value, its
-                                  i-th most significant of code_len bits is 0
-                                  when the root-to-leaf path turns left
+                                  i-th most significant digit (of code_len
+                                  digits of D bits; D = 1 binary) is the
+                                  child taken at depth i (binary: 0 = left)
                                   (Sec. 4.3, "Arbitrarily-shaped")          */
-    const uint32_t* code_len;  /* shaped: host [sigma], 0 = no codeword    */
+    const uint32_t* code_len;  /* shaped: host [sigma], length in digits, 0 =
+                                  no codeword; code_len * D <= 32           */
     const uint64_t* counts;    /* shaped: host [sigma], occurrences of every
                                   symbol in S (fixes the level sizes)       */
 } wt_shape;
@@ -159,7 +171,8 @@ typedef struct wt_plan_info {
 
 /* Size a build (Sec. 2 problem statement; host only, no device work).
  * shape: NULL for WT/WM; codes+code_len+counts for SHAPED (the codewords
- * must be prefix-free, else WT_EINVAL); arity for MULTIARY.  tune may be
+ * must be prefix-free, else WT_EINVAL; a code over D-bit digits when
+ * arity_log2 >= 2, built level by level); arity for MULTIARY.  tune may be
  * NULL.  Fills *info. */
 int wt_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes,
             const wt_shape* shape, const wt_tuning* tune, wt_plan_info* info);

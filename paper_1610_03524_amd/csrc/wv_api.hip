@@ -85,27 +85,29 @@ uint64_t bump(uint64_t& off, uint64_t bytes)
 }
 
 // The coded symbols of a shape, ordered by codeword padded at the bottom to
-// the longest code length h.  In that order a codeword shares its top lcp
-// bits with its predecessor and adds len - 1 - lcp new proper prefixes (tree
-// nodes), and the code is prefix-free iff no codeword's top len bits equal
-// its successor's.
+// the longest code length h (D-bit digits; D = 1 for binary codes).  In that
+// order a codeword shares its top lcp digits with its predecessor and adds
+// len - 1 - lcp new proper prefixes (tree nodes), and the code is
+// prefix-free iff no codeword's top len digits equal its successor's.
 struct Coded {
     uint64_t key;
     uint32_t len, sym;
 };
 
-int sorted_codes(const wt_shape& sh, uint32_t sigma, uint32_t h, std::vector<Coded>& cs, uint64_t* nnodes)
+int sorted_codes(const wt_shape& sh, uint32_t sigma, uint32_t h, std::vector<Coded>& cs, uint64_t* nnodes,
+                 uint32_t D = 1)
 {
     cs.clear();
     for (uint32_t x = 0; x < sigma; x++)
-        if (sh.code_len[x]) cs.push_back(Coded{(uint64_t)sh.codes[x] << (h - sh.code_len[x]), sh.code_len[x], x});
+        if (sh.code_len[x])
+            cs.push_back(Coded{(uint64_t)sh.codes[x] << (D * (h - sh.code_len[x])), sh.code_len[x], x});
     std::sort(cs.begin(), cs.end(), [](const Coded& a, const Coded& b) { return a.key < b.key; });
     uint64_t nodes = 0;
     for (size_t i = 0; i < cs.size(); i++) {
         uint32_t lcp = 0;
         if (i) {
             const uint64_t x = cs[i - 1].key ^ cs[i].key;
-            lcp = x ? (uint32_t)__builtin_clzll(x) - (64 - h) : h;
+            lcp = x ? ((uint32_t)__builtin_clzll(x) - (64 - D * h)) / D : h;
             if (lcp >= std::min(cs[i - 1].len, cs[i].len)) return WT_EINVAL;   // one code is a prefix of the other
             nodes += cs[i].len - 1 - lcp;
         } else {
@@ -151,21 +153,26 @@ int make_plan_impl(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, con
         level_n.assign(p.nlevels, n);
     } else {
         if (!shape || !shape->codes || !shape->code_len || !shape->counts) return WT_EINVAL;
+        // codewords of D-bit digits (arity_log2 0 or 1: binary), lengths in
+        // digits, at most 32 bits per codeword
+        if (shape->arity_log2 > 4) return WT_EINVAL;
+        p.D = std::max(shape->arity_log2, 1u);
         uint32_t h = 0;
         uint64_t total = 0;
         for (uint32_t s = 0; s < sigma; s++) {
             const uint32_t len = shape->code_len[s];
-            if (len > 32) return WT_EUNSUP;
-            if (len && len < 64 && (shape->codes[s] >> len)) return WT_EINVAL;
+            if ((uint64_t)len * p.D > 32) return WT_EUNSUP;
+            if (len && (shape->codes[s] >> (len * p.D))) return WT_EINVAL;
             if (len) p.ncoded++;
             h = std::max(h, len);
             total += shape->counts[s];
             if (shape->counts[s] && !len) return WT_ERANGE;
         }
         if (h == 0 || total != n) return WT_EINVAL;
-        p.D = 1;
-        p.key_bits = h;
+        p.key_bits = h * p.D;
         p.nlevels = h;
+        // shaped multiary trees are built level by level
+        if (p.D >= 2) p.levelwise = true;
         level_n.assign(h, 0);
         for (uint32_t s = 0; s < sigma; s++)
             for (uint32_t l = 0; l < shape->code_len[s]; l++) level_n[l] += shape->counts[s];
@@ -175,7 +182,7 @@ int make_plan_impl(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, con
     // image layout
     p.lin = wv_layout_in{};
     p.lin.kind = (uint32_t)kind;
-    p.lin.arity_log2 = kind == WT_KIND_MULTIARY ? p.D : 1u;
+    p.lin.arity_log2 = wv_multi_levels(kind, p.D) ? p.D : 1u;
     p.lin.nlevels = p.nlevels;
     p.lin.key_bits = p.key_bits;
     p.lin.sigma = sigma;
@@ -185,7 +192,7 @@ int make_plan_impl(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, con
     if (kind == WT_KIND_SHAPED) {
         // internal nodes: distinct proper prefixes of the codewords
         std::vector<Coded> cs;
-        const int rc = sorted_codes(*shape, sigma, p.key_bits, cs, &p.nnodes_image);
+        const int rc = sorted_codes(*shape, sigma, p.nlevels, cs, &p.nnodes_image, p.D);
         if (rc) return rc;
         p.lin.nnodes = p.nnodes_image;
     }
@@ -208,9 +215,10 @@ int make_plan_impl(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, con
     // workspace
     const uint32_t d = 1u << p.D;
     const uint64_t ns = wv_cdiv(n, WV_SB_BITS);
-    const uint64_t nr = kind == WT_KIND_MULTIARY ? wv_mranges(n, p.D) : 0;
+    const bool multi = wv_multi_levels(kind, p.D);
+    const uint64_t nr = multi ? wv_mranges(n, p.D) : 0;
     // multiary counters are built for all levels at once: M * d columns
-    const uint64_t mcols = kind == WT_KIND_MULTIARY ? (uint64_t)d * p.nlevels : 0;
+    const uint64_t mcols = multi ? (uint64_t)d * p.nlevels : 0;
     const uint64_t dir_items = std::max<uint64_t>(std::max(ns, nr * mcols), 1);
     uint64_t off = 0;
     p.ws_scalars = bump(off, 256);
@@ -489,67 +497,83 @@ int balanced_nodes(const std::vector<uint64_t>& counts, uint32_t sigma, uint32_t
 // order, in which the prefixes of one length come out sorted.
 int shaped_nodes(const wt_shape& sh, uint32_t sigma, HostNodes& H, std::vector<uint8_t>& rec)
 {
+    const uint32_t D = std::max(sh.arity_log2, 1u), d = 1u << D;
+    const uint64_t RB = wv_node_bytes(D >= 2 ? D : 1);
     uint32_t h = 0;
     for (uint32_t x = 0; x < sigma; x++) h = std::max(h, sh.code_len[x]);
     std::vector<Coded> cs;
     uint64_t N = 0;
-    int rc = sorted_codes(sh, sigma, h, cs, &N);
+    int rc = sorted_codes(sh, sigma, h, cs, &N, D);
     if (rc) return rc;
     // symbols before every position of the key order
     std::vector<uint64_t> pc(cs.size() + 1, 0);
     for (size_t i = 0; i < cs.size(); i++) pc[i + 1] = pc[i] + sh.counts[cs[i].sym];
     H.start.assign(N, 0);
-    H.child_start.assign(2 * N, 0);
-    H.child.assign(2 * N, WV_NONE);
-    rec.assign(N * WV_NODE_BYTES, 0);
+    H.child_start.assign(d * N, 0);
+    H.child.assign(d * N, WV_NONE);
+    rec.assign(N * RB, 0);
     // level by level, nodes in key order: a node is the range of codewords
-    // sharing its prefix; its children split the range by the next key bit,
-    // a child holding one codeword that ends there is that symbol's leaf
+    // sharing its prefix; its children split the range by the next digit
+    // (the keys of one node are sorted by it), a child holding one codeword
+    // that ends there is that symbol's leaf
     struct Node { uint32_t a, b; uint64_t start; };
     std::vector<Node> cur, nxt;
     if (!cs.empty()) cur.push_back(Node{0, (uint32_t)cs.size(), 0});
     uint64_t base = 0;
+    std::vector<uint32_t> lo(d), hi(d), ch(d);
     for (uint32_t l = 0; l < h && !cur.empty(); l++) {
         const uint64_t nbase = base + cur.size();
         if (nbase > N) return WT_EINVAL;
-        const uint32_t bit = h - 1 - l;
+        const uint32_t shift = D * (h - 1 - l);   // digit l of a padded key
         nxt.clear();
         uint64_t nrun = 0;
         for (uint64_t k = 0; k < cur.size(); k++) {
             const Node nd = cur[k];
             const uint64_t t = base + k;
             const uint64_t cnt = pc[nd.b] - pc[nd.a];
-            const uint32_t m = (uint32_t)(std::partition_point(cs.begin() + nd.a, cs.begin() + nd.b,
-                                                               [&](const Coded& c) { return !((c.key >> bit) & 1u); }) -
-                                          cs.begin());
-            const uint32_t lo[2] = {nd.a, m}, hi[2] = {m, nd.b};
-            uint32_t ch[2];
-            for (uint32_t e = 0; e < 2; e++) {
+            uint32_t a = nd.a;
+            for (uint32_t g = 0; g < d; g++) {
+                const uint32_t m = g + 1 < d
+                    ? (uint32_t)(std::partition_point(cs.begin() + a, cs.begin() + nd.b,
+                                                      [&](const Coded& c) { return ((c.key >> shift) & (d - 1)) <= g; }) -
+                                 cs.begin())
+                    : nd.b;
+                lo[g] = a;
+                hi[g] = m;
+                a = m;
+            }
+            for (uint32_t g = 0; g < d; g++) {
                 uint32_t c = WV_NONE;
                 uint64_t cst = 0;
-                if (hi[e] - lo[e] == 1 && cs[lo[e]].len == l + 1) {
-                    c = WV_LEAF | cs[lo[e]].sym;
-                } else if (hi[e] > lo[e]) {
+                if (hi[g] - lo[g] == 1 && cs[lo[g]].len == l + 1) {
+                    c = WV_LEAF | cs[lo[g]].sym;
+                } else if (hi[g] > lo[g]) {
                     const uint64_t id = nbase + nxt.size();
                     if (id >= N) return WT_EINVAL;
                     c = (uint32_t)id;
                     cst = nrun;
-                    nxt.push_back(Node{lo[e], hi[e], nrun});
-                    nrun += pc[hi[e]] - pc[lo[e]];
+                    nxt.push_back(Node{lo[g], hi[g], nrun});
+                    nrun += pc[hi[g]] - pc[lo[g]];
                 }
-                ch[e] = c;
-                H.child[2 * t + e] = c;
-                H.child_start[2 * t + e] = (uint32_t)cst;
+                ch[g] = c;
+                H.child[(uint64_t)d * t + g] = c;
+                H.child_start[(uint64_t)d * t + g] = (uint32_t)cst;
             }
             H.start[t] = (uint32_t)nd.start;
-            uint8_t* e = rec.data() + t * WV_NODE_BYTES;
-            const uint32_t lev = l, pr = l ? (uint32_t)(cs[nd.a].key >> (h - l)) : 0u;
+            uint8_t* e = rec.data() + t * RB;
+            const uint32_t lev = l, pr = l ? (uint32_t)(cs[nd.a].key >> (D * (h - l))) : 0u;
             std::memcpy(e + 0, &nd.start, 8);
             std::memcpy(e + 8, &cnt, 8);
-            std::memcpy(e + 16, &ch[0], 4);
-            std::memcpy(e + 20, &ch[1], 4);
-            std::memcpy(e + 24, &lev, 4);
-            std::memcpy(e + 28, &pr, 4);
+            if (D == 1) {
+                std::memcpy(e + 16, &ch[0], 4);
+                std::memcpy(e + 20, &ch[1], 4);
+                std::memcpy(e + 24, &lev, 4);
+                std::memcpy(e + 28, &pr, 4);
+            } else {
+                std::memcpy(e + 16, &lev, 4);
+                std::memcpy(e + 20, &pr, 4);
+                std::memcpy(e + 24, ch.data(), 4ull * d);
+            }
         }
         base = nbase;
         cur.swap(nxt);

@@ -14,7 +14,7 @@
 #define WV_VERSION      2u
 #define WV_HEADER_BYTES 256u
 #define WV_LEVEL_BYTES  64u
-#define WV_NODE_BYTES   32u
+#define WV_NODE_BYTES   32u     // node record of a binary shaped tree
 #define WV_CODE_BYTES   16u
 #define WV_SB_BITS      512u    // rank range (superblock), Sec. 5.1
 #define WV_SEL_STRIDE   4096u   // select sampling stride, Sec. 5.1
@@ -50,6 +50,19 @@ __host__ __device__ inline uint64_t wv_nsel(uint64_t m) { return wv_cdiv(m, WV_S
 // with one entry more at least one unused entry separates the two halves
 // (the end marker of each).  The array follows sel1; the image's level
 // record does not hold its offset (it is sel1's end rounded to 256 bytes).
+// Levels of D-bit digits: multiary trees, and shaped trees whose codewords
+// are D-bit digits (D >= 2; Sec. 4.3 carries shapes over to multiary trees).
+__host__ __device__ inline bool wv_multi_levels(uint32_t kind, uint32_t arity_log2)
+{
+    return kind == WT_KIND_MULTIARY || (kind == WT_KIND_SHAPED && arity_log2 >= 2);
+}
+// node record of a shaped tree: binary {u64 start, u64 count, u32 child[2],
+// u32 level, u32 prefix}; D-bit digits {u64 start, u64 count, u32 level,
+// u32 prefix, u32 child[2^D]}
+__host__ __device__ inline uint64_t wv_node_bytes(uint32_t arity_log2)
+{
+    return arity_log2 >= 2 ? 24u + (4ull << arity_log2) : (uint64_t)WV_NODE_BYTES;
+}
 __host__ __device__ inline uint64_t wv_nsub(uint64_t m) { return wv_cdiv(m, WV_SUB_STRIDE) + 2; }
 __host__ __device__ inline uint64_t wv_sub_off(uint64_t sel1_off, uint64_t nsel)
 {
@@ -94,7 +107,7 @@ struct wv_layout_out {
 
 __host__ __device__ inline void wv_layout(const wv_layout_in& in, wv_layout_out& out)
 {
-    const bool multi = in.kind == WT_KIND_MULTIARY;
+    const bool multi = wv_multi_levels(in.kind, in.arity_log2);
     const uint32_t D = in.arity_log2;
     uint64_t off = WV_HEADER_BYTES + wv_round256((uint64_t)WV_LEVEL_BYTES * in.nlevels);
     for (uint32_t l = 0; l < in.nlevels; l++) {
@@ -126,7 +139,7 @@ __host__ __device__ inline void wv_layout(const wv_layout_in& in, wv_layout_out&
     out.nodes_off = out.codes_off = 0;
     if (in.kind == WT_KIND_SHAPED) {
         out.nodes_off = off;
-        off = wv_round256(off + in.nnodes * WV_NODE_BYTES);
+        off = wv_round256(off + in.nnodes * wv_node_bytes(in.arity_log2));
         out.codes_off = off;
         off = wv_round256(off + (uint64_t)in.sigma * WV_CODE_BYTES);
     }

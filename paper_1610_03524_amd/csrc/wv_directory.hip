@@ -281,7 +281,7 @@ __global__ void __launch_bounds__(64)
 header_k(uint8_t* __restrict__ img, wv_layout_in in, wv_layout_out lay)
 {
     const uint32_t t = threadIdx.x, nl = in.nlevels, D = in.arity_log2;
-    const bool multi = in.kind == WT_KIND_MULTIARY, shaped = in.kind == WT_KIND_SHAPED;
+    const bool multi = wv_multi_levels(in.kind, in.arity_log2), shaped = in.kind == WT_KIND_SHAPED;
     const uint64_t after_levels = shaped ? lay.nodes_off : lay.image_bytes;
     if (t < nl) {
         const wv_level& L = lay.lv[t];
@@ -325,7 +325,7 @@ header_k(uint8_t* __restrict__ img, wv_layout_in in, wv_layout_out lay)
         zero_bytes(img, 88, WV_HEADER_BYTES);
         zero_bytes(img, WV_HEADER_BYTES + (uint64_t)WV_LEVEL_BYTES * nl, nl ? lay.lv[0].bits_off : after_levels);
         if (shaped) {
-            zero_bytes(img, lay.nodes_off + in.nnodes * WV_NODE_BYTES, lay.codes_off);
+            zero_bytes(img, lay.nodes_off + in.nnodes * wv_node_bytes(in.arity_log2), lay.codes_off);
             zero_bytes(img, lay.codes_off + (uint64_t)in.sigma * WV_CODE_BYTES, lay.image_bytes);
         }
     }

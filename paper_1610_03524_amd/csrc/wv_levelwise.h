@@ -4,7 +4,7 @@
 #include "wv_internal.h"
 
 #define WV_KEY_SYMBOL      0u   // bit l from the top of the symbol
-#define WV_KEY_CODE        1u   // bit l of the symbol's codeword
+#define WV_KEY_CODE        1u   // digit l (D bits) of the symbol's codeword
 #define WV_KEY_DIGIT_MULTI 2u   // D-bit digit l from the top of the symbol
 
 // How a symbol maps to its bit / digit on one level.
@@ -17,8 +17,8 @@ struct wv_keyfn {
 __device__ inline uint32_t wv_digit(const wv_keyfn& f, uint32_t key)
 {
     if (f.mode == WV_KEY_CODE) {
-        const uint32_t len = f.lens[key];
-        return (f.codes[key] >> (len - 1 - f.level)) & 1u;
+        const uint32_t len = f.lens[key];   // digits
+        return (f.codes[key] >> (f.D * (len - 1 - f.level))) & ((1u << f.D) - 1u);
     }
     return (key >> f.shift) & ((1u << f.D) - 1u);
 }

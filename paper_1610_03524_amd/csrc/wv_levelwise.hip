@@ -138,7 +138,10 @@ hipError_t scatter_level(const void* keys, const uint32_t* nodes_in, uint64_t m,
     if (!m) return hipSuccess;
     const uint64_t* words = (const uint64_t*)(image + L.bits_off);
     const uint32_t g = blocks_for(m, LW_THREADS);
-    if (kind == WT_KIND_WM)
+    if (kind != WT_KIND_WM && f.D >= 2)   // digit levels: multiary and shaped multiary trees
+        scatter_multi_k<T><<<g, LW_THREADS, 0, s>>>(keys, nodes_in, m, f, words, image + L.rank_off, nt,
+                                                     keys_out, nodes_out);
+    else if (kind == WT_KIND_WM)
         scatter_wm_k<T><<<g, LW_THREADS, 0, s>>>(keys, m, f, words, (const uint64_t*)(image + L.rank_off), zl, keys_out);
     else if (kind == WT_KIND_MULTIARY)
         scatter_multi_k<T><<<g, LW_THREADS, 0, s>>>(keys, nodes_in, m, f, words, image + L.rank_off, nt,
@@ -170,8 +173,8 @@ hipError_t run_levels(const wv_lw_args& a, hipStream_t s)
                            : emit_level<uint32_t>(keys, m, f, a.image, L, a.dir.sb_ones, s));
         if (e != hipSuccess) return e;
         WV_TIMED(a.profile, s, "lw_directory",
-                 e = kind == WT_KIND_MULTIARY ? wv_multiary_counters(a.image, &L, 1, f.D, a.mdir, s)
-                                              : wv_binary_directory(a.image, l, L, a.dir, a.zl, s));
+                 e = wv_multi_levels(kind, a.arity_log2) ? wv_multiary_counters(a.image, &L, 1, f.D, a.mdir, s)
+                                                         : wv_binary_directory(a.image, l, L, a.dir, a.zl, s));
         if (e != hipSuccess) return e;
         if (l + 1 == a.nlevels) break;
         WV_TIMED(a.profile, s, "lw_scatter",
@@ -196,6 +199,7 @@ wv_keyfn wv_lw_args::keyfn(uint32_t l) const
     f.D = kind == WT_KIND_MULTIARY ? arity_log2 : 1u;
     if (kind == WT_KIND_SHAPED) {
         f.mode = WV_KEY_CODE;
+        f.D = arity_log2 >= 2 ? arity_log2 : 1u;
         f.level = l;
         f.codes = codes;
         f.lens = lens;

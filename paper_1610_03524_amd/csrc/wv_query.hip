@@ -27,6 +27,7 @@ struct QLevel {
 struct QImg {
     const uint8_t* img;
     uint32_t kind, D, nlevels, sigma;
+    bool multi;   // levels of D-bit digits (multiary, or shaped over digits)
     uint64_t n, nodes_off, codes_off;
     QLevel lv[WV_MAX_LEVELS];
 };
@@ -43,10 +44,11 @@ __device__ inline void load_image(const uint8_t* img, QImg& q)
     q.nlevels = h32[7] > WV_MAX_LEVELS ? WV_MAX_LEVELS : h32[7];
     q.nodes_off = h64[7];
     q.codes_off = h64[9];
+    q.multi = wv_multi_levels(q.kind, q.D);
     for (uint32_t l = 0; l < q.nlevels; l++) {
         const uint64_t* e = (const uint64_t*)(img + WV_HEADER_BYTES + (uint64_t)WV_LEVEL_BYTES * l);
         q.lv[l] = QLevel{e[0], e[1], e[3], e[4], e[5], e[6], e[7], 0, 0};
-        if (q.kind != WT_KIND_MULTIARY) {   // binary: the sub-samples follow sel1
+        if (!q.multi) {   // binary: the sub-samples follow sel1
             q.lv[l].sub_off = wv_sub_off(e[6], e[7]);
             q.lv[l].nsub = wv_nsub(e[0]);
         }
@@ -116,19 +118,46 @@ __device__ inline uint64_t mrank(const QImg& q, uint32_t l, uint32_t g, uint64_t
 
 struct QNode {
     uint64_t start, count;
-    uint32_t child[2], level;
+    uint32_t level;
+    const uint32_t* child;   // child[g] of the node's record
 };
 
+// node record k: binary {start, count, child[2], level, prefix}; D-bit
+// digits {start, count, level, prefix, child[2^D]}
 __device__ inline QNode node_at(const QImg& q, uint32_t k)
 {
-    const uint8_t* e = q.img + q.nodes_off + (uint64_t)k * WV_NODE_BYTES;
+    const uint8_t* e = q.img + q.nodes_off + (uint64_t)k * wv_node_bytes(q.multi ? q.D : 1u);
     QNode nd;
     nd.start = ((const uint64_t*)e)[0];
     nd.count = ((const uint64_t*)e)[1];
-    nd.child[0] = ((const uint32_t*)e)[4];
-    nd.child[1] = ((const uint32_t*)e)[5];
-    nd.level = ((const uint32_t*)e)[6];
+    nd.level = ((const uint32_t*)e)[q.multi ? 4 : 6];
+    nd.child = (const uint32_t*)e + (q.multi ? 6 : 4);
     return nd;
+}
+
+// a level's bit or digit at a position, its rank (occurrences of g in
+// [0, i)) and its select (position of the g of 0-based ordinal j), for bit
+// levels and digit levels alike (shaped trees)
+__device__ inline uint32_t sym_at(const QImg& q, uint32_t l, uint64_t i)
+{
+    return q.multi ? digit_at(q, l, i) : bit_at(q, l, i);
+}
+__device__ inline uint64_t rank_sym_on(const QImg& q, uint32_t l, uint32_t g, uint64_t i)
+{
+    return q.multi ? mrank(q, l, g, i) : rankb(q, l, g, i);
+}
+__device__ inline uint64_t select_sym_on(const QImg& q, uint32_t l, uint32_t g, uint64_t j)
+{
+    if (!q.multi) return selectb(q, l, g, j);
+    const QLevel& lv = q.lv[l];
+    return wv_mselect(words_of(q, l), q.img + lv.rank_off, (const uint64_t*)(q.img + lv.sel0_off), lv.nsel, lv.n,
+                      q.D, g, j);
+}
+// digit t (from the top) of a codeword of len digits
+__device__ inline uint32_t code_digit(const QImg& q, uint64_t code, uint32_t len, uint32_t t)
+{
+    const uint32_t D = q.multi ? q.D : 1u;
+    return (uint32_t)((code >> (D * (len - 1 - t))) & ((1ull << D) - 1ull));
 }
 
 // ---- access ------------------------------------------------------------------
@@ -186,8 +215,8 @@ __device__ uint32_t q_access(const QImg& q, uint64_t i)
     for (uint32_t step = 0; step <= WV_MAX_LEVELS; step++) {
         const QNode nd = node_at(q, k);
         const uint64_t pos = nd.start + rel;
-        const uint32_t b = bit_at(q, nd.level, pos);
-        rel = rankb(q, nd.level, b, pos) - rankb(q, nd.level, b, nd.start);
+        const uint32_t b = sym_at(q, nd.level, pos);
+        rel = rank_sym_on(q, nd.level, b, pos) - rank_sym_on(q, nd.level, b, nd.start);
         const uint32_t c = nd.child[b];
         if (c & WV_LEAF) return c == WV_NONE ? 0xFFFFFFFFu : (c & ~WV_LEAF);
         k = c;
@@ -256,9 +285,9 @@ __device__ uint64_t q_count_prefix(const QImg& q, uint32_t c, uint64_t p)
     uint64_t rel = p;
     for (uint32_t t = 0; t < len; t++) {
         const QNode nd = node_at(q, k);
-        const uint32_t b = (uint32_t)((code >> (len - 1 - t)) & 1ull);
+        const uint32_t b = code_digit(q, code, len, t);
         const uint64_t pos = nd.start + rel;
-        rel = rankb(q, nd.level, b, pos) - rankb(q, nd.level, b, nd.start);
+        rel = rank_sym_on(q, nd.level, b, pos) - rank_sym_on(q, nd.level, b, nd.start);
         k = nd.child[b];
     }
     return rel;
@@ -322,13 +351,13 @@ __device__ uint64_t q_select(const QImg& q, uint32_t c, uint64_t k)
         uint32_t kk = 0;
         for (uint32_t t = 0; t < len; t++) {
             path[t] = kk;
-            kk = node_at(q, kk).child[(code >> (len - 1 - t)) & 1ull];
+            kk = node_at(q, kk).child[code_digit(q, code, len, t)];
         }
         uint64_t rel = k - 1;
         for (uint32_t t = len; t-- > 0;) {
             const QNode nd = node_at(q, path[t]);
-            const uint32_t b = (uint32_t)((code >> (len - 1 - t)) & 1ull);
-            rel = selectb(q, nd.level, b, rankb(q, nd.level, b, nd.start) + rel) - nd.start;
+            const uint32_t b = code_digit(q, code, len, t);
+            rel = select_sym_on(q, nd.level, b, rank_sym_on(q, nd.level, b, nd.start) + rel) - nd.start;
         }
         return rel;
     }

@@ -279,3 +279,46 @@ def test_trace_logs_plans_only_when_asked():
     env.pop("WT_TRACE")
     r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True, timeout=120)
     assert r.returncode == 0 and "[wt]" not in r.stderr
+
+
+@pytest.mark.parametrize("D", [2, 3, 4])
+def test_plan_of_shaped_multiary_trees(D):
+    """wt_plan over codewords of D-bit digits: level sizes from the counts,
+    the oracle's image size; refusals for a prefix, a codeword wider than its
+    length, more than 32 bits, and a symbol of S without a codeword"""
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import dary
+    rng = np.random.default_rng(D)
+    sigma = 300
+    S = np.minimum(rng.geometric(0.02, 20000) - 1, sigma - 1).astype(np.uint16)
+    counts = np.bincount(S, minlength=sigma).astype(np.uint64)
+    lens = dary.huffman_lengths(counts, D)
+    codes = dary.canonical(lens, D)
+    info = B.plan(B.KIND_SHAPED, S.size, sigma, 2, B.make_shape(D, codes, lens, counts))
+    assert info.nlevels == int(lens.max()) and info.arity_log2 == D and info.key_bits == D * int(lens.max())
+    for l in range(info.nlevels):
+        assert info.level_n[l] == int(counts[lens > l].sum())
+    assert info.out_bytes == oracle.build_image(oracle.KIND_SHAPED, S, sigma, D, codes=codes, lens=lens).size
+
+    def verdict(c, ln, cnt=counts):
+        try:
+            B.plan(B.KIND_SHAPED, int(cnt.sum()), sigma, 2, B.make_shape(D, c, ln, cnt))
+            return B.WT_OK
+        except B.WaveletError as e:
+            return e.code
+    a, b = [int(x) for x in np.flatnonzero(lens)[:2]]
+    bad = codes.copy()
+    bad[b] = codes[a] << np.uint64(D)   # a's codeword extended: a is a prefix of b
+    ln = lens.copy()
+    ln[b] = lens[a] + 1
+    assert verdict(bad, ln) == B.WT_EINVAL
+    wide = codes.copy()
+    wide[a] |= np.uint64(1) << np.uint64(D * int(lens[a]))
+    assert verdict(wide, lens) == B.WT_EINVAL
+    long_ = lens.copy()
+    long_[a] = 32 // D + 1
+    assert verdict(codes, long_) == B.WT_EUNSUP
+    none = lens.copy()
+    none[int(np.flatnonzero(counts)[0])] = 0
+    assert verdict(codes, none) == B.WT_ERANGE
