@@ -252,7 +252,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3h", "c3m", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3h", "c3m", "c3hm", "c4", "c5"])
     ap.add_argument("--horizon", type=float, default=2.0, help="c5: seconds of arrivals per rate")
     ap.add_argument("--modes", default="continuous,plain", help="c5: serving modes, run in this order per rate")
     ap.add_argument("--rates", default="100,300,1000,3000,10000,20000,50000", help="c5: build arrival rates /s")
@@ -265,7 +265,7 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.steps)
         return
-    if args.workload in ("c1", "c3h", "c3m"):
+    if args.workload in ("c1", "c3h", "c3m", "c3hm"):
         bench_tree(args)
         return
     if args.workload == "c4":
@@ -399,6 +399,43 @@ def info_passes(info):
     return -(-info.nlevels // info.tau)
 
 
+def dary_huffman_codes(counts, D):
+    """the shape of a Huffman-shaped d-ary tree (its input, prepared on the
+    host): d-ary Huffman code lengths in digits (zero-weight dummies bring the
+    leaf count to 1 mod d-1, the d lightest subtrees merge, ties by creation
+    order) and canonical codewords in (length, symbol) order"""
+    import heapq
+    d = 1 << D
+    present = [s for s in range(len(counts)) if counts[s]]
+    lens = np.zeros(len(counts), dtype=np.uint32)
+    if len(present) == 1:
+        lens[present[0]] = 1
+    else:
+        heap = [(int(counts[s]), t, [s]) for t, s in enumerate(present)]
+        t = len(heap)
+        while (len(heap) - 1) % (d - 1):
+            heap.append((0, t, []))
+            t += 1
+        heapq.heapify(heap)
+        while len(heap) > 1:
+            w, members = 0, []
+            for _ in range(min(d, len(heap))):
+                a, _, m = heapq.heappop(heap)
+                w += a
+                members += m
+            lens[members] += 1
+            heapq.heappush(heap, (w, t, members))
+            t += 1
+    codes = np.zeros(len(counts), dtype=np.uint64)
+    code, prev = 0, None
+    for l, s in sorted((int(l), s) for s, l in enumerate(lens) if l):
+        if prev is not None:
+            code = (code + 1) * d ** (l - prev)
+        codes[s] = code
+        prev = l
+    return codes, lens
+
+
 def tree_kernel_bytes(name, info, sym_bytes, kind):
     """compulsory bytes of all launches of one kernel in one tree build, or
     None for a kernel without a stated figure.  The tree is gathered from the
@@ -406,7 +443,7 @@ def tree_kernel_bytes(name, info, sym_bytes, kind):
     padded to the longest code for the shaped tree)."""
     n = int(info.n)
     K = int(info.key_bits)
-    D = int(info.arity_log2) if kind == 4 else 1
+    D = int(info.arity_log2) if (kind == 4 or (kind == 3 and int(info.arity_log2) >= 2)) else 1
     key_w = 4 if kind == 3 else sym_bytes
     tree_bits = sum(int(info.level_n[l]) * D for l in range(info.nlevels))
     # the matrix whose passes are timed as "wm_pass" / "wm_hist": (symbols,
@@ -435,6 +472,8 @@ def tree_kernel_bytes(name, info, sym_bytes, kind):
         return info.nlevels * (n * D // 8)
     if name == "tree_keys":          # read S once (the codes it writes are intermediate)
         return n * sym_bytes
+    if name == "lw_emit":            # level by level: level 0 reads S, every level's digits written once
+        return n * sym_bytes + sum((int(info.level_n[l]) * D + 63) // 64 * 8 for l in range(info.nlevels))
     return None
 
 
@@ -456,13 +495,16 @@ def bench_tree(args):
         St = torch.from_numpy(Sn.view(np.int16)).to(dev)
         if args.workload == "c3h":
             kind, D, name = B.KIND_SHAPED, 0, "C3 Huffman-shaped wavelet tree: n=2^26 uint16, sigma=4096, geometric(0.01)"
+        elif args.workload == "c3hm":
+            kind, D, name = (B.KIND_SHAPED, 2, "C3 Huffman-shaped 4-ary wavelet tree: n=2^26 uint16, sigma=4096, "
+                                               "geometric(0.01), 4-ary Huffman codewords")
         else:
             kind, D, name = B.KIND_MULTIARY, 2, "C3 4-ary wavelet tree: n=2^26 uint16, sigma=4096, geometric(0.01)"
     n, sym = Sn.size, Sn.itemsize
     codes = lens = counts = None
     if kind == B.KIND_SHAPED:
         counts = B.symbol_counts(St, sigma).cpu().numpy().astype(np.uint64)
-        codes, lens = B.huffman_codes(counts)
+        codes, lens = B.huffman_codes(counts) if D < 2 else dary_huffman_codes(counts, D)
     tune = B.make_tuning()
     prof_tune = B.make_tuning(flags=B.FLAG_PROFILE)
     shape = B.make_shape(D, codes, lens, counts) if (D or codes is not None) else None
@@ -495,7 +537,12 @@ def bench_tree(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u16" if sym == 2 else "u8", "data": "synthetic",
         "config": {"workload": name, "n": n, "sigma": sigma, "levels": info.nlevels,
-                   "path": "wavelet-matrix passes over the keys, runs moved to tree order"},
+                   "path": {"c1": "one pass of the matrix passes straight into tree order (domain decomposition)",
+                            "c3h": "wavelet-matrix passes over the padded codewords (split at 16 bits), runs moved "
+                                   "to tree order",
+                            "c3m": "wavelet-matrix passes over the keys, 2-bit digits assembled, runs moved to "
+                                   "tree order",
+                            "c3hm": "level by level over the 2-bit digits of the codewords"}[args.workload]},
         "symbol_levels_per_s": round(symbol_levels(info) / t, 1),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(dom_bytes / (dom_ms / 1e3) / 1e9, 2),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s",
