@@ -253,7 +253,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3h", "c3m", "c3hm", "c4", "c5"])
-    ap.add_argument("--horizon", type=float, default=2.0, help="c5: seconds of arrivals per rate")
+    ap.add_argument("--horizon", type=float, default=2.0,
+                    help="c5: seconds of arrivals per rate, at least enough for --min-builds builds")
+    ap.add_argument("--min-builds", type=int, default=3000,
+                    help="c5: arrivals per rate at least (so that a p99 rests on 30 samples or more)")
     ap.add_argument("--modes", default="continuous,plain", help="c5: serving modes, run in this order per rate")
     ap.add_argument("--rates", default="100,300,1000,3000,10000,20000,50000", help="c5: build arrival rates /s")
     ap.add_argument("--limit", type=int, default=8192, help="c4: number of sequences")
@@ -757,7 +760,8 @@ def bench_serve(args):
     torch.cuda.synchronize()
     rows = []
     # warm-up of both modes (first launches, allocator, streams), not recorded
-    rates = [("warmup", 1000.0, 0.5)] + [("run", float(r), args.horizon) for r in args.rates.split(",")]
+    rates = [("warmup", 1000.0, 0.5)] + [("run", float(r), max(args.horizon, args.min_builds / float(r)))
+                                         for r in args.rates.split(",")]
     for tag, rate, horizon in rates:
         bt, ids, qt = inputs.c5_requests(rate, horizon, seed=5, count=P)
         events = sorted([(t, "b", int(i)) for t, i in zip(bt, ids)] + [(t, "q", -1) for t in qt])
@@ -791,7 +795,8 @@ def bench_serve(args):
             if tag == "warmup":
                 del srv
                 continue
-            rows.append({"rate": rate, "mode": mode, "builds": int(len(bl)), "query_batches": int(len(ql)),
+            rows.append({"rate": rate, "mode": mode, "horizon_s": round(horizon, 2), "builds": int(len(bl)),
+                         "query_batches": int(len(ql)),
                          "build_p50_ms": serve.percentile_ms(bl, 50), "build_p99_ms": serve.percentile_ms(bl, 99),
                          "query_p50_ms": serve.percentile_ms(ql, 50), "query_p99_ms": serve.percentile_ms(ql, 99),
                          "builds_per_s": round(len(bl) / (t_end - t0), 1),
@@ -804,7 +809,8 @@ def bench_serve(args):
     print(json.dumps({
         "metric": "serving p50/p99 latency and throughput (continuous batching vs plain queue)",
         "workload": f"C5: Poisson builds from the C4 mix over a pool of {P} sequences, query batches of 2^16 "
-                    f"mixed access/rank/select at max(10, rate/10)/s, {args.horizon} s per rate, HBM budget 64 GiB",
+                    f"mixed access/rank/select at max(10, rate/10)/s, max({args.horizon} s, {args.min_builds} "
+                    f"arrivals) per rate, HBM budget 64 GiB",
         "n_gpus": 1, "data": "synthetic", "rows": rows}), flush=True)
 
 
