@@ -759,8 +759,9 @@ def bench_serve(args):
     qb = [serve.make_query_batch(S, 1 << 16, rng) for S, _ in host]
     torch.cuda.synchronize()
     rows = []
-    # warm-up of both modes (first launches, allocator, streams), not recorded
-    rates = [("warmup", 1000.0, 0.5)] + [("run", float(r), max(args.horizon, args.min_builds / float(r)))
+    # warm-up of both modes (first launches of the single and the batched
+    # build, allocator, streams), not recorded
+    rates = [("warmup", 20000.0, 0.25)] + [("run", float(r), max(args.horizon, args.min_builds / float(r)))
                                          for r in args.rates.split(",")]
     for tag, rate, horizon in rates:
         bt, ids, qt = inputs.c5_requests(rate, horizon, seed=5, count=P)

@@ -10,9 +10,10 @@ thread serves both, on two streams:
   launched with one wt_batch_build (wm_build for a batch of one); requests
   arriving meanwhile form the next batch, so batches grow with the load
   (continuous batching);
-* queries: every query batch that has arrived is launched on the second
-  stream and one wait covers them all, also while a build batch is on the
-  device, so queries overlap with builds and group up under load.
+* queries: every query batch that has arrived is launched (before the builds
+  that arrived with them) and one wait covers them all; while builds are on
+  the device they go on the second stream, so queries overlap with builds
+  and group up under load, otherwise on the build stream.
 
 A lone request thus takes the same path as in the plain mode: one hand-off
 to one worker, its launches, one wait.  A few builds (SINGLES_MAX) are queued
@@ -22,6 +23,10 @@ checks for finished work and new queries every POLL_S seconds.
 
 Plan figures (image and workspace sizes, pass width) of every sequence are
 taken when the server is created, so admission does no planning.
+
+From start() to close() the server shortens the interpreter's thread switch
+interval and turns Python's cyclic garbage collector off (a full collection
+would stall every thread for tens of milliseconds); close() restores both.
 
 The "plain" mode is the baseline: one worker serving every request alone, in
 arrival order (wm_build or one query launch, then wait).
@@ -41,6 +46,7 @@ from __future__ import annotations
 
 import collections
 import ctypes
+import gc
 import sys
 import threading
 import time
@@ -96,6 +102,8 @@ class WaveletServer:
         self.tau_of = tau_of or (lambda n, sigma: 0)
         self.batch_tune = B.make_tuning(tile=batch_tile)
         self.build_stream = torch.cuda.Stream()
+        self._build_handle = B._stream(self.build_stream)
+        self._tunings = {}
         self.query_stream = torch.cuda.Stream() if mode == "continuous" else self.build_stream
         self.ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
         # status words of a batch's images, copied here on the build stream
@@ -157,6 +165,15 @@ class WaveletServer:
         # code would wait that long, so the server shortens it while running
         self._switch = sys.getswitchinterval()
         sys.setswitchinterval(SWITCH_INTERVAL_S)
+        # a full collection of the cyclic garbage collector walks every
+        # object of the process (hundreds of thousands once torch is
+        # imported) with the interpreter held: tens of milliseconds during
+        # which no request is dispatched.  Requests make no reference cycles,
+        # so collection is off while serving; the objects made before are
+        # moved out of the collector's generations for good measure.
+        self._gc = gc.isenabled()
+        gc.freeze()
+        gc.disable()
         if self.mode == "continuous":
             self.threads = [threading.Thread(target=self._dispatch_loop, daemon=True)]
         else:
@@ -171,6 +188,9 @@ class WaveletServer:
         for t in self.threads:
             t.join()
         sys.setswitchinterval(self._switch)
+        gc.unfreeze()
+        if self._gc:
+            gc.enable()
 
     def _costs(self, seq):
         """(image bytes, batch-workspace bytes, single-build workspace bytes,
@@ -275,31 +295,35 @@ class WaveletServer:
         """queue the builds on the build stream, each segment of the batch
         followed by the copy of its status words and an event; returns (rc,
         [(first, end, event)]): rc is the code of the first launch that failed
-        (the segments before it stand)"""
+        (the segments before it stand).  The last segment's event is the
+        build stream itself (nothing else is queued on it while a batch is on
+        the device)."""
         torch = self.torch
         segs = []
         if len(descs) <= SINGLES_MAX:
             # a few sequences: single builds in stream order (one workspace),
             # each finishing on its own
             for i, d in enumerate(descs):
-                tn = B.make_tuning(tau=d.tau)
+                tn = self._tunings.get(d.tau)
+                if tn is None:
+                    tn = self._tunings[d.tau] = B.make_tuning(tau=d.tau)
                 rc = B.lib().wm_build(d.S, d.n, d.sigma, d.sym_bytes, None, ctypes.byref(tn), d.out,
-                                      d.out_bytes, self.ws.data_ptr(), self.ws.numel(),
-                                      B._stream(self.build_stream))
+                                      d.out_bytes, self.ws.data_ptr(), self.ws.numel(), self._build_handle)
                 if rc != B.WT_OK:
                     return rc, segs
                 self.status_host[i:i + 1].copy_(imgs[i][36:40].view(torch.int32), non_blocking=True)
-                ev = torch.cuda.Event()
-                ev.record(self.build_stream)
+                if i + 1 < len(descs):
+                    ev = torch.cuda.Event()
+                    ev.record(self.build_stream)
+                else:
+                    ev = self.build_stream
                 segs.append((i, i + 1, ev))
             return B.WT_OK, segs
         rc = B.batch_build(B.KIND_WM, descs, self.ws, self.batch_tune, stream=self.build_stream)
         if rc != B.WT_OK:
             return rc, segs
         self._status_copy(imgs)
-        ev = torch.cuda.Event()
-        ev.record(self.build_stream)
-        return B.WT_OK, [(0, len(descs), ev)]
+        return B.WT_OK, [(0, len(descs), self.build_stream)]
 
     def _complete_builds(self, take, imgs, nbytes, codes):
         t = time.perf_counter()
@@ -342,28 +366,33 @@ class WaveletServer:
         except Exception as e:   # fail this query, keep serving
             r.result, r.error = None, getattr(e, "code", B.WT_EHIP)
 
-    def _take_queries(self):
-        """(under the lock) every query that has arrived, with its structure"""
+    def _take_queries(self, stream):
+        """(under the lock) every query that has arrived, with its structure,
+        to be run on `stream`"""
         work = []
         while self.queries and len(work) < self.max_batch:
             r = self.queries.popleft()
-            work.append((r, self._take_structure(r, self.query_stream)))
+            work.append((r, self._take_structure(r, stream)))
         return work
 
-    def _run_queries(self, work):
-        """launch every query of `work` on the query stream, wait once"""
+    def _launch_queries(self, work, stream):
+        """launch every query of `work` on `stream`; the launched ones"""
         launched = []
         for r, st in work:
             if st is None:
                 r.error = B.WT_EINVAL
                 continue
             try:
-                self._run_query(r, st, self.query_stream)
+                self._run_query(r, st, stream)
                 launched.append(r)
             except Exception as e:   # fail this query, keep serving
                 r.result, r.error = None, getattr(e, "code", B.WT_EHIP)
+        return launched
+
+    def _wait_queries(self, work, launched, stream):
+        """one wait for the queries of `work` launched on `stream`"""
         try:
-            self.query_stream.synchronize()
+            stream.synchronize()
         except Exception as e:
             for r in launched:
                 r.result, r.error = None, getattr(e, "code", B.WT_EHIP)
@@ -388,7 +417,15 @@ class WaveletServer:
                     with torch.cuda.stream(self.build_stream):
                         batch = self._admit()
                     self.used += sum(batch[3])
-                qwork = self._take_queries()
+                # queries overlap builds on their own stream; with no build on
+                # the device they take the build stream, the one in recent use
+                # (measured at low load: a query batch on the second stream,
+                # idle between queries, finished 0.02-0.03 ms later)
+                qstream = (self.build_stream if flight is None and not (batch and batch[0])
+                           else self.query_stream)
+                qwork = self._take_queries(qstream)
+            # queries are launched before the builds that arrived with them
+            launched = self._launch_queries(qwork, qstream) if qwork else None
             if batch is not None and batch[0]:
                 take, descs, imgs, nbytes = batch
                 self.batches.append(len(take))
@@ -408,7 +445,7 @@ class WaveletServer:
                 if segs:
                     flight = (take, imgs, nbytes, segs, sum(d.n for d in descs) <= BLOCK_SYMBOLS)
             if qwork:
-                self._run_queries(qwork)
+                self._wait_queries(qwork, launched, qstream)
             if flight is not None:
                 take, imgs, nbytes, segs, short = flight
                 # finish the segments the device is done with, in order; wait
