@@ -22,7 +22,8 @@
  *     Jacobson's ranges and sub-ranges, here 512-bit ranges and 64-bit
  *     sub-ranges) and sampled select (Sec. 5.1, "Select": the two sampling
  *     levels of Clark's structure, here every 4096th and every 512th one and
- *     zero, the search between two samples running over the rank ranges);
+ *     zero, plus Clark's rule of storing every answer of a long range, here
+ *     for the 512-one sub-ranges spanning 2^20 bits or more);
  *   - per-digit rank counters on multiary levels (Sec. 5.2, "Rank") and
  *     per-digit sampled select (Sec. 5.2, "Select": the range symbols, every
  *     4096th occurrence of each digit value);
@@ -55,7 +56,7 @@
 
 /* ---- image layout ------------------------------------------------------- */
 #define O_MAGIC        0x54564157u  /* bytes 'W','A','V','T' */
-#define O_VERSION      2u
+#define O_VERSION      3u
 #define O_HEADER_BYTES 256u
 #define O_LEVEL_BYTES  64u
 #define O_NODE_BYTES   32u    /* binary shaped trees */
@@ -68,6 +69,7 @@ static uint64_t node_bytes(unsigned D) { return D >= 2 ? mnode_bytes(D) : O_NODE
 #define O_SUB_BITS     64u    /* rank directory sub-range (block) */
 #define O_SEL_STRIDE   4096u  /* select sampling stride */
 #define O_SUB_STRIDE   512u   /* select sub-sampling stride (second level) */
+#define O_LONG_SPAN    (1ull << 20)  /* a sub-range this long keeps every answer */
 #define O_LEAF_FLAG    0x80000000u
 #define O_NO_CHILD     0xFFFFFFFFu
 #define O_MAX_CODE_LEN 32u
@@ -84,6 +86,8 @@ typedef struct {
     uint64_t sub_off;   /* binary: select sub-samples, ones from the front,
                            zeros from the back (32-bit positions) */
     uint64_t nsub;      /* entries of the sub-sample array */
+    uint64_t pool_off;  /* binary: stored answers of long sub-ranges */
+    uint64_t nslot;     /* slots of 512 answers per kind (ones, then zeros) */
 } olevel;
 
 static uint64_t round256(uint64_t x) { return (x + 255u) & ~(uint64_t)255u; }
@@ -153,6 +157,11 @@ static uint64_t lay_out(olevel* lv, unsigned nlev, int multiary, unsigned D,
             lv[l].nsub = bin_nsub(m);
             lv[l].sub_off = off;
             off = round256(off + lv[l].nsub * 4);
+            /* long sub-ranges are disjoint and at least 2^20 bits each, so
+             * a level of m bits has at most floor(m / 2^20) of each kind */
+            lv[l].nslot = m / O_LONG_SPAN;
+            lv[l].pool_off = off;
+            off = round256(off + lv[l].nslot * 2 * O_SUB_STRIDE * 4);
         } else {
             /* generalized select: d arrays of nsel samples, digit-major */
             lv[l].nsel = bin_nsel(m);
@@ -160,6 +169,7 @@ static uint64_t lay_out(olevel* lv, unsigned nlev, int multiary, unsigned D,
             off = round256(off + ((uint64_t)1 << D) * lv[l].nsel * 8);
             lv[l].sel1_off = 0;
             lv[l].sub_off = lv[l].nsub = 0;
+            lv[l].pool_off = lv[l].nslot = 0;
         }
     }
     *nodes_off = *codes_off = 0;
@@ -236,6 +246,32 @@ static int write_binary_level(uint8_t* img, olevel* lv, const uint8_t* b)
             if (c0 % O_SUB_STRIDE == 0) put_u32(sub + 4 * (lv->nsub - 1 - c0 / O_SUB_STRIDE), (uint32_t)i);
             c0++;
         }
+    }
+    /* Clark's rule for long ranges (Sec. 5.1, "Select"): when the stretch
+     * from the one (zero) of ordinal 512j to that of ordinal 512(j+1) (to m
+     * if there is none) is at least 2^20 bits, every answer in it is stored:
+     * the positions of ordinals 512j, 512j+1, ... (at most 512 of them) in
+     * slot floor(p / 2^20) of the kind's pool, p being the stretch's start.
+     * The pool holds the ones' slots, then the zeros'; unused entries m. */
+    if (lv->nslot) {
+        uint8_t* pool = img + lv->pool_off;
+        for (uint64_t k = 0; k < 2 * lv->nslot * O_SUB_STRIDE; k++) put_u32(pool + 4 * k, (uint32_t)m);
+        uint64_t* pos = (uint64_t*)malloc((m + 1) * sizeof(uint64_t));
+        if (!pos) { free(zp); return O_ENOMEM; }
+        for (int kind = 1; kind >= 0; kind--) {
+            uint64_t cnt = 0;   /* positions of this kind's bits, in order */
+            for (uint64_t i = 0; i < m; i++)
+                if ((b[i] != 0) == (kind == 1)) pos[cnt++] = i;
+            for (uint64_t j0 = 0; j0 < cnt; j0 += O_SUB_STRIDE) {
+                uint64_t start = pos[j0];
+                uint64_t end = j0 + O_SUB_STRIDE < cnt ? pos[j0 + O_SUB_STRIDE] : m;
+                if (end - start < O_LONG_SPAN) continue;
+                uint64_t slot = (kind == 1 ? 0 : lv->nslot) + start / O_LONG_SPAN;
+                for (uint64_t t = 0; t < O_SUB_STRIDE && j0 + t < cnt; t++)
+                    put_u32(pool + 4 * (slot * O_SUB_STRIDE + t), (uint32_t)pos[j0 + t]);
+            }
+        }
+        free(pos);
     }
     free(zp);
     return O_OK;

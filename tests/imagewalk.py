@@ -44,11 +44,15 @@ class Image:
         for l in range(self.nlevels):
             e = _u64(b, self.levels_off + 64 * l, 8)
             lv = dict(n=int(e[0]), zeros=int(e[1]), ones=int(e[2]), bits_off=int(e[3]), rank_off=int(e[4]),
-                      sel0_off=int(e[5]), sel1_off=int(e[6]), nsel=int(e[7]), sub_off=0, nsub=0)
+                      sel0_off=int(e[5]), sel1_off=int(e[6]), nsel=int(e[7]), sub_off=0, nsub=0,
+                      pool_off=0, nslot=0)
             if not self.multi_levels:
-                # binary: the select sub-samples follow sel1 (not in the record)
+                # binary: the select sub-samples follow sel1, the pool of
+                # stored answers follows them (neither is in the record)
                 lv["sub_off"] = (lv["sel1_off"] + 8 * lv["nsel"] + 255) // 256 * 256
                 lv["nsub"] = -(-lv["n"] // 512) + 2
+                lv["pool_off"] = (lv["sub_off"] + 4 * lv["nsub"] + 255) // 256 * 256
+                lv["nslot"] = lv["n"] >> 20
             self.levels.append(lv)
         self._bits = {}
         self._zpre = {}
@@ -88,6 +92,13 @@ class Image:
         at nsub-1-j, unused entries n"""
         lv = self.levels[l]
         return np.frombuffer(self.buf[lv["sub_off"]:lv["sub_off"] + 4 * lv["nsub"]].tobytes(), dtype=np.uint32)
+
+    def pool(self, l: int) -> np.ndarray:
+        """stored answers of the long sub-ranges: 2 * nslot slots of 512
+        positions, the ones' slots first"""
+        lv = self.levels[l]
+        size = 4 * 2 * lv["nslot"] * 512
+        return np.frombuffer(self.buf[lv["pool_off"]:lv["pool_off"] + size].tobytes(), dtype=np.uint32)
 
     def rank0_via_directory(self, l: int, i: int) -> int:
         """zeros in [0, i) using only the directory and one word."""
@@ -426,6 +437,8 @@ def array_digests(buf: np.ndarray) -> dict:
                  ("sel1", lv["sel1_off"], 8 * lv["nsel"])]
         if lv["sub_off"]:
             spans.append(("sub", lv["sub_off"], 4 * lv["nsub"]))
+        if lv["nslot"]:
+            spans.append(("pool", lv["pool_off"], 4 * 2 * lv["nslot"] * 512))
         for name, off, size in spans:
             if off:
                 out[f"level{l}.{name}"] = hashlib.sha256(b[off:off + size].tobytes()).hexdigest()

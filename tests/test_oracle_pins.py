@@ -500,7 +500,12 @@ def test_errors():
 def test_layout(kind, D):
     rng = np.random.default_rng(kind)
     S = rng.integers(0, 37, 1000).astype(np.uint8)
-    buf = build(kind, S, 37, D)
+    check_layout(build(kind, S, 37, D), kind, D)
+
+
+def check_layout(buf, kind, D=1):
+    """every array on a 256-byte boundary, no two overlap, every byte outside
+    them zero"""
     img = Image(buf)
     assert img.image_bytes == buf.size and buf.size % 256 == 0
     spans = [(0, 256 + 64 * img.nlevels)]
@@ -523,6 +528,8 @@ def test_layout(kind, D):
             spans.append((lv["sel1_off"], lv["sel1_off"] + 8 * lv["nsel"]))
             assert lv["sub_off"] % 256 == 0 and lv["nsub"] == -(-m // 512) + 2
             spans.append((lv["sub_off"], lv["sub_off"] + 4 * lv["nsub"]))
+            assert lv["pool_off"] % 256 == 0 and lv["nslot"] == m >> 20
+            spans.append((lv["pool_off"], lv["pool_off"] + 4 * 2 * lv["nslot"] * 512))
     if kind == KIND_SHAPED:
         rb = 32 if D == 1 else 24 + 4 * (1 << D)
         spans.append((img.nodes_off, img.nodes_off + rb * img.nnodes))
@@ -534,6 +541,90 @@ def test_layout(kind, D):
     for a, b in spans:
         covered[a:b] = True
     assert not buf[~covered].any(), "bytes outside every array must be zero"
+
+
+LONG = 1 << 20
+
+
+def select_through_structure(img, l, b, j):
+    """the select of the query path: the sub-samples of ordinals 512s and
+    512(s+1) bound a stretch; a stretch of 2^20 bits or more answers from its
+    pool slot, any other by a search of the stretch (brute force here)"""
+    lv = img.levels[l]
+    sub, nsub = img.sub(l), lv["nsub"]
+    s = j // 512
+    p0 = int(sub[s] if b else sub[nsub - 1 - s])
+    p1 = int(sub[s + 1] if b else sub[nsub - 2 - s])
+    if p1 - p0 >= LONG:
+        slot = (0 if b else lv["nslot"]) + (p0 >> 20)
+        return int(img.pool(l)[slot * 512 + j % 512]), True
+    inside = np.flatnonzero(img.bits(l)[p0:p1] == b)
+    return p0 + int(inside[j - 512 * s]), False
+
+
+def long_stretch_bits(case, n, rng):
+    """bit strings whose 512-one (or zero) stretches include long ones: a
+    dense block, a block of 512 spread over about a million bits, and a short
+    tail spread to the end; complemented for zeros; or sparse at random"""
+    if case == "random":
+        return (rng.random(n) < 1 / 2500).astype(np.uint8)
+    b = np.zeros(n, dtype=np.uint8)
+    if case == "edge":
+        # a stretch of exactly 2^20 bits (long), then a tail of 2^20 - 1 (not)
+        b[:512] = 1
+        b[np.linspace(1000, 1000 + LONG, 512, endpoint=False).astype(np.int64)] = 1
+        b[1000 + LONG] = 1
+        assert n == 1000 + 2 * LONG - 1
+        return b
+    b[:512] = 1
+    b[np.linspace(1000, 1000 + 1_100_000, 512, endpoint=False).astype(np.int64)] = 1
+    b[np.linspace(1_200_000, n - 1, 37).astype(np.int64)] = 1
+    return b if case == "ones" else 1 - b
+
+
+@pytest.mark.parametrize("case", ["ones", "zeros", "random", "edge"])
+def test_long_stretches_store_every_answer(case):
+    """Clark's rule for long ranges (Sec. 5.1, "Select"): selects through the
+    sub-samples and the pool of stored answers equal brute force for every
+    ordinal of every long stretch and for sampled others; a slot is in use
+    exactly for each long stretch, its positions hold the right bit and
+    increase; unused entries are n; the layout stays valid at n >= 2^20"""
+    rng = np.random.default_rng({"ones": 1, "zeros": 2, "random": 3, "edge": 4}[case])
+    n = 1000 + 2 * LONG - 1 if case == "edge" else (1 << 21) + 300000
+    bits = long_stretch_bits(case, n, rng)
+    buf = oracle.build_image(KIND_WM, bits, 2)
+    check_layout(buf, KIND_WM)
+    img = Image(buf)
+    nslot = img.levels[0]["nslot"]
+    assert nslot == n >> 20
+    pool = img.pool(0).reshape(2 * nslot, 512)
+    for b in (0, 1):
+        pos = np.flatnonzero(bits == b)
+        long_ordinals, nlong = [], 0
+        for j0 in range(0, pos.size, 512):
+            end = pos[j0 + 512] if j0 + 512 < pos.size else n
+            if end - pos[j0] >= LONG:
+                nlong += 1
+                long_ordinals.extend(range(j0, min(j0 + 512, pos.size)))
+        if case == ("ones" if b else "zeros"):
+            assert nlong == 2   # the spread block and the tail
+        if case == "random" and b == 1:
+            assert nlong >= 1
+        if case == "edge":
+            assert nlong == b
+        from_pool = 0
+        for j in long_ordinals + [int(x) for x in rng.integers(0, pos.size, 300)]:
+            got, stored = select_through_structure(img, 0, b, j)
+            assert got == pos[j], (b, j)
+            from_pool += stored
+        assert from_pool >= len(long_ordinals)
+        slots = pool[:nslot] if b else pool[nslot:]
+        in_use = 0
+        for row in slots:
+            live = row[row != n].astype(np.int64)
+            in_use += live.size > 0
+            assert np.all(bits[live] == b) and np.all(np.diff(live) > 0)
+        assert in_use == nlong
 
 
 def test_matrix_walk_on_oracle_images():
