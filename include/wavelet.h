@@ -17,8 +17,10 @@
  * Every binary level carries a rank-of-0 directory (Sec. 5.1, "Rank": 512-bit
  * ranges, 64-bit sub-ranges) and sampled select on ones and zeros (Sec. 5.1,
  * "Select": the two sampling levels of Clark's structure, every 4096th and
- * every 512th one/zero, a select searching the rank ranges between two
- * sub-samples); multiary levels carry per-digit
+ * every 512th one/zero, and Clark's rule for long ranges: the 512 answers of
+ * a stretch between two sub-samples spanning 2^20 bits or more are stored,
+ * any other stretch is searched in the rank ranges); multiary levels carry
+ * per-digit
  * rank counters (Sec. 5.2, "Rank").
  *
  * Output: one flat, position-independent byte image per structure (layout
@@ -68,7 +70,7 @@ extern "C" {
 
 /* ---- image layout (little endian) ----------------------------------------
  * Header, 256 bytes at offset 0:
- *   u32 magic 0x54564157 ("WAVT"), u32 version 2, u32 kind, u32 arity_log2,
+ *   u32 magic 0x54564157 ("WAVT"), u32 version 3, u32 kind, u32 arity_log2,
  *   u64 n, u32 sigma, u32 nlevels, u32 key_bits, u32 status (0 ok; bit 0:
  *   a symbol >= sigma was seen; bit 1: the symbol counts differ from those
  *   the shape gave), u64 image_bytes, u64 levels_off (= 256),
@@ -90,7 +92,15 @@ extern "C" {
  *                 the descriptor): nsub = ceil(n_l/512)+2 u32: entry j = the
  *                 position of the one of ordinal 512j, entry nsub-1-j = that
  *                 of the zero of ordinal 512j, every other entry n_l (at
- *                 least one such entry separates the two).
+ *                 least one such entry separates the two);
+ *                 pool (at the end of sub rounded up to 256 bytes): 2 x
+ *                 nslot slots of 512 u32, nslot = floor(n_l / 2^20), the
+ *                 ones' slots then the zeros'.  When the one of ordinal 512j
+ *                 sits at p and the one of ordinal 512(j+1) (n_l if none) at
+ *                 least 2^20 bits later, slot floor(p / 2^20) holds the
+ *                 positions of the ones of ordinals 512j, 512j+1, ... (no
+ *                 two such stretches share a slot); the same for zeros;
+ *                 every other entry n_l.
  *   multiary level (D-bit digits, P = floor(64/D) per word, digit t at bits
  *                 [tD, tD+D) of word t/P): ceil(n_l/P) words; then counters:
  *                 (ceil(n_l/64P)+1) x d u64 = count of each digit before

@@ -322,7 +322,7 @@ b_header_k(uint8_t* const* __restrict__ images, const wv_layout_in* __restrict__
     if (blockIdx.x >= count) return;   // whole workgroups; clearing only
     // same header writer as a single build, one workgroup per image
     __shared__ wv_layout_out lay;
-    __shared__ uint64_t span_lo[5 * WV_MAX_LEVELS + 4], span_hi[5 * WV_MAX_LEVELS + 4];
+    __shared__ uint64_t span_lo[6 * WV_MAX_LEVELS + 4], span_hi[6 * WV_MAX_LEVELS + 4];
     __shared__ int nspan;
     uint8_t* img = images[blockIdx.x];
     const wv_layout_in& in = lins[blockIdx.x];
@@ -338,6 +338,7 @@ b_header_k(uint8_t* const* __restrict__ images, const wv_layout_in* __restrict__
             span_lo[s] = L.sel0_off;  span_hi[s++] = L.sel0_off + 8 * L.nsel;
             span_lo[s] = L.sel1_off;  span_hi[s++] = L.sel1_off + 8 * L.nsel;
             span_lo[s] = L.sub_off;   span_hi[s++] = L.sub_off + 4 * L.nsub;
+            span_lo[s] = L.pool_off;  span_hi[s++] = L.pool_off + wv_pool_bytes(L.n);
         }
         span_lo[s] = lay.image_bytes;
         span_hi[s] = lay.image_bytes;
@@ -360,6 +361,19 @@ b_header_k(uint8_t* const* __restrict__ images, const wv_layout_in* __restrict__
         for (uint64_t b = span_hi[s] + threadIdx.x; b < span_lo[s + 1]; b += blockDim.x) img[b] = 0;
 }
 
+// explicit select answers of the long sub-ranges (wv_xsel_block), one
+// workgroup per pool slot of every listed level
+__global__ void __launch_bounds__(WV_SUB_STRIDE)
+b_xsel_k(const wv_xlevel* __restrict__ xs, uint32_t nx)
+{
+    uint32_t lo = 0, hi = nx - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (xs[mid].blk0 <= blockIdx.x) lo = mid; else hi = mid - 1;
+    }
+    wv_xsel_block(xs[lo], blockIdx.x - xs[lo].blk0);
+}
+
 inline uint32_t width_of(uint32_t bits) { return bits <= 8 ? 1u : (bits <= 16 ? 2u : 4u); }
 
 // ---- host planning -----------------------------------------------------------------
@@ -370,11 +384,11 @@ struct SeqPlan {
     uint64_t off_H, off_tot, off_G0, off_pay[2], off_dcnt, off_dpre;
     // image layout: every level of a matrix has n bits, so level l's arrays
     // sit at level 0's offsets + l * lstride
-    uint64_t bits0, rank0, sel00, sel10, sub0, lstride, nsel, nsub, image_bytes;
+    uint64_t bits0, rank0, sel00, sel10, sub0, pool0, lstride, nsel, nsub, image_bytes;
     wv_level lv(uint32_t l) const
     {
         const uint64_t d = (uint64_t)l * lstride;
-        return wv_level{n, bits0 + d, rank0 + d, sel00 + d, sel10 + d, nsel, sub0 + d, nsub};
+        return wv_level{n, bits0 + d, rank0 + d, sel00 + d, sel10 + d, nsel, sub0 + d, nsub, pool0 + d, wv_nslot(n)};
     }
 };
 
@@ -415,7 +429,7 @@ int make_batch_plan(const wt_seq_desc* seqs, uint32_t count, const wt_tuning* tu
     // one work-queue counter per phase (at most 2 + 2 * 32 phases), then the
     // histogram areas: the header launch clears both at once
     bp.off_queue = bump(4 * (2 + 2 * 32));
-    uint64_t total_chunks = 0, total_spans = 0, total_dch = 0;
+    uint64_t total_chunks = 0, total_spans = 0, total_dch = 0, total_x = 0;
     // One persistent launch serves every sequence, so a chunk can span many
     // tiles: fewer chunks mean fewer histogram workgroups, offset tables and
     // shared boundary words.  Chunks grow only while every pass workgroup
@@ -448,7 +462,7 @@ int make_batch_plan(const wt_seq_desc* seqs, uint32_t count, const wt_tuning* tu
             wv_layout(matrix_layout_in(d.n, d.sigma, wp.L), lay);
             s.bits0 = lay.lv[0].bits_off; s.rank0 = lay.lv[0].rank_off;
             s.sel00 = lay.lv[0].sel0_off; s.sel10 = lay.lv[0].sel1_off; s.nsel = lay.lv[0].nsel;
-            s.sub0 = lay.lv[0].sub_off; s.nsub = lay.lv[0].nsub;
+            s.sub0 = lay.lv[0].sub_off; s.nsub = lay.lv[0].nsub; s.pool0 = lay.lv[0].pool_off;
             s.lstride = wp.L > 1 ? lay.lv[1].bits_off - lay.lv[0].bits_off : 0;
             s.image_bytes = lay.image_bytes;
         }
@@ -474,6 +488,7 @@ int make_batch_plan(const wt_seq_desc* seqs, uint32_t count, const wt_tuning* tu
         s.off_dpre = bump(std::max<uint64_t>(dch, 1) * s.L * 8);
         total_spans += s.L;
         total_dch += dch * s.L;
+        if (wv_nslot(s.n)) total_x += s.L;
     }
     bp.order.resize(count);
     std::iota(bp.order.begin(), bp.order.end(), 0u);
@@ -500,7 +515,8 @@ int make_batch_plan(const wt_seq_desc* seqs, uint32_t count, const wt_tuning* tu
             area(ph, wv_round256((uint64_t)m * sizeof(SeqRound)) + wv_round256((uint64_t)m * 4) + (uint64_t)m * 4);
         }
     }
-    area(bp.nphases - 1, wv_round256(total_spans * sizeof(SpanDesc)) + total_spans * 4);
+    area(bp.nphases - 1, wv_round256(total_spans * sizeof(SpanDesc)) + wv_round256(total_spans * 4) +
+                             total_x * sizeof(wv_xlevel));
     bp.phase_off[bp.nphases] = bp.desc_total;
     bp.off_desc = bump(bp.desc_total);
     bp.ws_bytes = off;
@@ -624,10 +640,12 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
     // last phase: the directories of every level of every sequence
     const uint32_t dphase = bp.nphases - 1;
     uint32_t nspan = 0, dchunks = 0;   // dchunks: directory workgroups (SDG chunks each)
+    uint32_t nx = 0, xblocks = 0;      // levels with pool slots, their workgroups
     {
         for (uint32_t i = 0; i < count; i++) nspan += bp.seq[i].L;
         SpanDesc* sd = (SpanDesc*)host_area(dphase);
         uint32_t* first = (uint32_t*)(host_area(dphase) + wv_round256((uint64_t)nspan * sizeof(SpanDesc)));
+        wv_xlevel* xl = (wv_xlevel*)((uint8_t*)first + wv_round256((uint64_t)nspan * 4));
         uint32_t k = 0;
         for (uint32_t i = 0; i < count; i++) {
             const SeqPlan& sp = bp.seq[i];
@@ -650,6 +668,17 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
                 d.chunk0 = dchunks;
                 first[k] = dchunks;
                 dchunks += (uint32_t)wv_cdiv(dch, SDG);
+                if (lvl.nslot) {
+                    wv_xlevel& x = xl[nx++];
+                    x.image = d.image;
+                    x.m = sp.n;
+                    x.bits_off = lvl.bits_off;
+                    x.rank_off = lvl.rank_off;
+                    x.sub_off = lvl.sub_off;
+                    x.nsub = lvl.nsub;
+                    x.blk0 = xblocks;
+                    xblocks += (uint32_t)(2 * lvl.nslot);
+                }
             }
         }
     }
@@ -695,6 +724,8 @@ int wt_batch_build(int kind, const wt_seq_desc* seqs, uint32_t count, void* ws_,
         if (dchunks) WV_TIMED(prof, s, "b_dir_count", (b_dir_count_k<<<dchunks, 256, 0, s>>>(dsd, dfirst, nspan)));
         WV_TIMED(prof, s, "b_dir_scan", (b_dir_scan_k<<<nspan, 256, 0, s>>>(dsd)));
         if (dchunks) WV_TIMED(prof, s, "b_dir_write", (b_dir_write_k<<<dchunks, 256, 0, s>>>(dsd, dfirst, nspan)));
+        const wv_xlevel* dxl = (const wv_xlevel*)((const uint8_t*)dfirst + wv_round256((uint64_t)nspan * 4));
+        if (xblocks) WV_TIMED(prof, s, "b_dir_explicit", (b_xsel_k<<<xblocks, WV_SUB_STRIDE, 0, s>>>(dxl, nx)));
         WV_CHECK(hipGetLastError());
     }
     // the upload reads the host descriptors: the pinned buffer returns to the

@@ -11,7 +11,7 @@
 #include "wavelet.h"
 
 #define WV_MAGIC        0x54564157u
-#define WV_VERSION      2u
+#define WV_VERSION      3u
 #define WV_HEADER_BYTES 256u
 #define WV_LEVEL_BYTES  64u
 #define WV_NODE_BYTES   32u     // node record of a binary shaped tree
@@ -19,6 +19,7 @@
 #define WV_SB_BITS      512u    // rank range (superblock), Sec. 5.1
 #define WV_SEL_STRIDE   4096u   // select sampling stride, Sec. 5.1
 #define WV_SUB_STRIDE   512u    // select sub-sampling stride (second level)
+#define WV_XSPAN_LOG2   20u     // sub-ranges spanning 2^20 bits or more keep every answer
 #define WV_MAX_LEVELS   32u
 #define WV_LEAF         0x80000000u
 #define WV_NONE         0xFFFFFFFFu
@@ -68,6 +69,18 @@ __host__ __device__ inline uint64_t wv_sub_off(uint64_t sel1_off, uint64_t nsel)
 {
     return wv_round256(sel1_off + 8 * nsel);
 }
+// Clark's rule for long ranges (Sec. 5.1, "Select": a range whose length
+// passes a threshold stores the answer of every select in it), applied to
+// the sub-ranges between two sub-samples: the ones (zeros) of ordinals
+// 512j .. 512j+511 span [p_j, p_{j+1}) with p_{j+1} = m past the last one.
+// A sub-range spanning at least 2^20 bits keeps the 512 positions (u32) in
+// slot floor(p_j / 2^20) of its kind's pool.  Such sub-ranges are disjoint
+// and at least 2^20 long, so two of them never share a slot and a level of m
+// bits needs floor(m / 2^20) slots per kind (2 KB each: at most 1/64 of the
+// level's bit array per kind).  Pool: the ones' slots, then the zeros'; unused entries m.
+__host__ __device__ inline uint64_t wv_nslot(uint64_t m) { return m >> WV_XSPAN_LOG2; }
+__host__ __device__ inline uint64_t wv_pool_bytes(uint64_t m) { return wv_nslot(m) * 2 * WV_SUB_STRIDE * 4; }
+__host__ __device__ inline uint64_t wv_pool_off(uint64_t sub_off, uint64_t nsub) { return wv_round256(sub_off + 4 * nsub); }
 __host__ __device__ inline uint32_t wv_digits_per_word(uint32_t D) { return D == 3 ? 21u : 64u >> (D >> 1); }
 // ceil(m / (words * digits per word)); a shift for D = 1, 2, 4 (no 64-bit
 // division on the device)
@@ -90,6 +103,7 @@ __host__ __device__ inline uint64_t wv_mrank_bytes(uint64_t m, uint32_t D)
 struct wv_level {
     uint64_t n, bits_off, rank_off, sel0_off, sel1_off, nsel;
     uint64_t sub_off, nsub;   // binary levels: select sub-samples (else 0)
+    uint64_t pool_off, nslot; // binary levels: explicit answers of long sub-ranges
 };
 
 // Everything needed to place the arrays of an image.
@@ -127,6 +141,9 @@ __host__ __device__ inline void wv_layout(const wv_layout_in& in, wv_layout_out&
             L.nsub = wv_nsub(m);
             L.sub_off = off;
             off = wv_round256(off + L.nsub * 4);
+            L.nslot = wv_nslot(m);
+            L.pool_off = off;
+            off = wv_round256(off + wv_pool_bytes(m));
         } else {
             // generalized select: 2^D arrays of nsel samples, digit-major
             L.nsel = wv_nsel(m);
@@ -134,6 +151,7 @@ __host__ __device__ inline void wv_layout(const wv_layout_in& in, wv_layout_out&
             off = wv_round256(off + (8ull << D) * L.nsel);
             L.sel1_off = 0;
             L.sub_off = L.nsub = 0;
+            L.pool_off = L.nslot = 0;
         }
     }
     out.nodes_off = out.codes_off = 0;
@@ -217,6 +235,82 @@ __device__ inline uint64_t wv_rank0(const uint64_t* __restrict__ words,
         r += t - __popcll(w & ((1ull << t) - 1ull));
     }
     return r;
+}
+
+// Position of the b-bit of 0-based ordinal j on a binary level of n bits,
+// given the positions p0 of its ordinal 512*floor(j/512) and p1 of the next
+// sub-sample (n if none): the rank superblocks between the two are searched
+// for the last one with at most j b-bits before it, then its seven relative
+// counts give the word.
+__device__ inline uint64_t wv_select_dir(const uint64_t* __restrict__ words, const uint64_t* __restrict__ dir,
+                                         uint64_t n, uint32_t b, uint64_t j, uint64_t p0, uint64_t p1)
+{
+    const uint64_t ns = wv_cdiv(n, WV_SB_BITS), nw = wv_cdiv(n, 64);
+    uint64_t lo = p0 >> 9, hi = (p1 >> 9) < ns ? (p1 >> 9) : ns - 1;
+    auto before = [&](uint64_t k) -> uint64_t { return b ? (k * WV_SB_BITS - dir[2 * k]) : dir[2 * k]; };
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi + 1) / 2;
+        if (before(mid) <= j) lo = mid; else hi = mid - 1;
+    }
+    const uint64_t k = lo;
+    const uint64_t r = j - before(k);
+    const uint64_t blk = dir[2 * k + 1];
+    uint32_t qw = 0;
+    uint64_t cq = 0;
+    for (uint32_t t = 1; t < 8; t++) {
+        if (8 * k + t >= nw) break;
+        const uint64_t f = (blk >> (9 * (t - 1))) & 511u;
+        const uint64_t c = b ? (64u * t - f) : f;
+        if (c <= r) { qw = t; cq = c; } else break;
+    }
+    uint64_t w = words[8 * k + qw];
+    if (!b) w = ~w;
+    return k * WV_SB_BITS + 64u * qw + wv_select_in_word(w, (uint32_t)(r - cq));
+}
+
+// A binary level whose explicit answers are written by wv_xsel_block: the
+// image, the level's length and array offsets, and the first workgroup of
+// the level in the launch (2 * nslot workgroups per level).
+struct wv_xlevel {
+    uint8_t* image;
+    uint64_t m, bits_off, rank_off, sub_off, nsub;
+    uint32_t blk0, pad;
+};
+
+// One slot of a level's pool, by a workgroup of WV_SUB_STRIDE threads:
+// local = kind * nslot + slot, ones (kind 0 here) first.  The only sub-range
+// that can own slot s is the last one starting before (s+1)*2^20; it owns it
+// if it starts at s*2^20 or later and spans 2^20 bits or more.  Thread t
+// then writes the position of ordinal 512j+t (found by the directory
+// search), or m past the kind's count and in an unowned slot.
+__device__ inline void wv_xsel_block(const wv_xlevel& X, uint32_t local)
+{
+    const uint64_t m = X.m, nslot = wv_nslot(m), ns = wv_cdiv(m, WV_SB_BITS);
+    const uint32_t b = local < nslot ? 1u : 0u;
+    const uint64_t slot = b ? local : local - nslot;
+    const uint64_t* dir = (const uint64_t*)(X.image + X.rank_off);
+    const uint64_t* words = (const uint64_t*)(X.image + X.bits_off);
+    const uint32_t* sub = (const uint32_t*)(X.image + X.sub_off);
+    uint32_t* pool = (uint32_t*)(X.image + wv_pool_off(X.sub_off, X.nsub)) +
+                     ((b ? 0 : nslot) + slot) * WV_SUB_STRIDE;
+    const uint64_t zeros = dir[2 * ns], count = b ? m - zeros : zeros;
+    const uint64_t J = wv_cdiv(count, WV_SUB_STRIDE);   // sub-ranges of the kind
+    auto entry = [&](uint64_t j) -> uint64_t { return b ? sub[j] : sub[X.nsub - 1 - j]; };
+    const uint64_t lim = (slot + 1) << WV_XSPAN_LOG2;
+    uint64_t out = m;
+    if (J && entry(0) < lim) {
+        uint64_t lo = 0, hi = J - 1;   // the last sub-range starting before lim
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi + 1) >> 1;
+            if (entry(mid) < lim) lo = mid; else hi = mid - 1;
+        }
+        const uint64_t p0 = entry(lo);
+        const uint64_t p1 = lo + 1 < J ? entry(lo + 1) : m;
+        const uint64_t o = lo * WV_SUB_STRIDE + threadIdx.x;
+        if (p0 >= (slot << WV_XSPAN_LOG2) && p1 - p0 >= (1ull << WV_XSPAN_LOG2) && o < count)
+            out = wv_select_dir(words, dir, m, b, o, p0, p1);
+    }
+    pool[threadIdx.x] = (uint32_t)out;
 }
 
 // the low bit of every digit equal to g among the first t (< P) digits of

@@ -9,7 +9,9 @@
 // superblock holding the one (zero) of ordinal 4096k finds it inside its
 // word and writes its position; the same for ordinals 512k into the
 // sub-sample array (the second sampling level of Clark's structure, so that
-// a select searches the ranges between two positions 512 ones apart).
+// a select searches the ranges between two positions 512 ones apart); a
+// sub-range spanning 2^20 bits or more then gets all its answers stored in
+// the level's pool (Clark's rule for long ranges).
 // Multiary levels (Sec. 5.2, "Rank"): the same with one counter per digit
 // value.
 #include <algorithm>
@@ -293,7 +295,8 @@ header_k(uint8_t* __restrict__ img, wv_layout_in in, wv_layout_out lay)
         } else {
             zero_bytes(img, L.sel0_off + 8 * L.nsel, L.sel1_off);
             zero_bytes(img, L.sel1_off + 8 * L.nsel, L.sub_off);
-            zero_bytes(img, L.sub_off + 4 * L.nsub, next);
+            zero_bytes(img, L.sub_off + 4 * L.nsub, L.pool_off);
+            zero_bytes(img, L.pool_off + wv_pool_bytes(L.n), next);
         }
         uint64_t* e = (uint64_t*)(img + WV_HEADER_BYTES + (uint64_t)WV_LEVEL_BYTES * t);
         e[0] = L.n;
@@ -393,6 +396,43 @@ validate_k(const void* __restrict__ S, uint64_t n, uint32_t sigma, uint32_t* __r
     }
 }
 
+// explicit select answers of the long sub-ranges of up to WV_MAX_LEVELS
+// binary levels of one image (after their directories and sub-samples)
+struct XList {
+    wv_xlevel lv[WV_MAX_LEVELS];
+    uint32_t n;
+};
+
+__global__ void __launch_bounds__(WV_SUB_STRIDE)
+xsel_k(XList a)
+{
+    uint32_t i = 0;
+    while (i + 1 < a.n && a.lv[i + 1].blk0 <= blockIdx.x) i++;
+    wv_xsel_block(a.lv[i], blockIdx.x - a.lv[i].blk0);
+}
+
+hipError_t launch_xsel(uint8_t* image, const wv_level* lv, uint32_t nl, hipStream_t s)
+{
+    XList a{};
+    uint32_t blocks = 0;
+    for (uint32_t l = 0; l < nl; l++) {
+        const uint64_t nslot = wv_nslot(lv[l].n);
+        if (!nslot) continue;
+        wv_xlevel& x = a.lv[a.n++];
+        x.image = image;
+        x.m = lv[l].n;
+        x.bits_off = lv[l].bits_off;
+        x.rank_off = lv[l].rank_off;
+        x.sub_off = lv[l].sub_off;
+        x.nsub = lv[l].nsub;
+        x.blk0 = blocks;
+        blocks += (uint32_t)(2 * nslot);
+    }
+    if (!blocks) return hipSuccess;
+    xsel_k<<<blocks, WV_SUB_STRIDE, 0, s>>>(a);
+    return hipGetLastError();
+}
+
 __global__ void fill_u64_k(uint64_t* p, uint64_t count, uint64_t value)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -431,7 +471,9 @@ hipError_t wv_binary_directory(uint8_t* image, uint32_t level, const wv_level& L
     if (e != hipSuccess) return e;
     if (ns) dir_write_k<<<(uint32_t)wv_cdiv(ns, DIR_THREADS), DIR_THREADS, 0, s>>>(image, L, sc.sb_pre);
     dir_finish_k<<<grid_for(L.nsel, DIR_THREADS, 64), DIR_THREADS, 0, s>>>(image, level, L, sc.total, zl_dev);
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_xsel(image, &L, 1, s);
 }
 
 hipError_t wv_multiary_counters(uint8_t* image, const wv_level* lv, uint32_t M, uint32_t D,
@@ -761,5 +803,8 @@ hipError_t wv_span_directory(uint8_t* image, const wv_layout_out& lay, uint32_t 
     if (e != hipSuccess) return e;
     if (sz.nchunks) WV_TIMED(prof, s, "dir_write", (span_write_k<<<dim3((uint32_t)wv_cdiv(sz.nchunks, 4), nl), SD_T, 0, s>>>(image, a, pre, (uint32_t)sz.nchunks)));
     WV_TIMED(prof, s, "dir_finish", (span_finish_k<<<nl, SD_T, 0, s>>>(image, a, tot)));
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    WV_TIMED(prof, s, "dir_explicit", e = launch_xsel(image, lay.lv + l0, nl, s));
+    return e;
 }

@@ -11,8 +11,9 @@
 //   multiary trees: per-digit counters replace rank0.
 // select walks down to the symbol's range, then back up with select0/1,
 // which takes the sub-sampled positions of ordinals 512j and 512(j+1) (the
-// second sampling level of Clark's structure) and searches the rank
-// superblocks between them (Sec. 5.1).  One thread answers one query.
+// second sampling level of Clark's structure): a sub-range spanning 2^20 bits
+// or more has every answer stored, any other is searched in the rank
+// superblocks between the two (Sec. 5.1).  One thread answers one query.
 #include "wv_internal.h"
 
 namespace {
@@ -21,7 +22,7 @@ constexpr int Q_THREADS = 256;
 constexpr uint64_t U64MAX = ~0ull;
 
 struct QLevel {
-    uint64_t n, zeros, bits_off, rank_off, sel0_off, sel1_off, nsel, sub_off, nsub;
+    uint64_t n, zeros, bits_off, rank_off, sel0_off, sel1_off, nsel, sub_off, nsub, pool_off;
 };
 
 struct QImg {
@@ -47,10 +48,11 @@ __device__ inline void load_image(const uint8_t* img, QImg& q)
     q.multi = wv_multi_levels(q.kind, q.D);
     for (uint32_t l = 0; l < q.nlevels; l++) {
         const uint64_t* e = (const uint64_t*)(img + WV_HEADER_BYTES + (uint64_t)WV_LEVEL_BYTES * l);
-        q.lv[l] = QLevel{e[0], e[1], e[3], e[4], e[5], e[6], e[7], 0, 0};
-        if (!q.multi) {   // binary: the sub-samples follow sel1
+        q.lv[l] = QLevel{e[0], e[1], e[3], e[4], e[5], e[6], e[7], 0, 0, 0};
+        if (!q.multi) {   // binary: the sub-samples follow sel1, the pool them
             q.lv[l].sub_off = wv_sub_off(e[6], e[7]);
             q.lv[l].nsub = wv_nsub(e[0]);
+            q.lv[l].pool_off = wv_pool_off(q.lv[l].sub_off, q.lv[l].nsub);
         }
     }
 }
@@ -75,34 +77,17 @@ __device__ uint64_t selectb(const QImg& q, uint32_t l, uint32_t b, uint64_t j)
 {
     const QLevel& L = q.lv[l];
     const uint32_t* sub = (const uint32_t*)(q.img + L.sub_off);
-    const uint64_t* dir = dir_of(q, l);
-    const uint64_t* words = words_of(q, l);
-    const uint64_t ns = wv_cdiv(L.n, WV_SB_BITS), nw = wv_cdiv(L.n, 64);
     // ordinals 512s and 512(s+1): ones from the front of the array, zeros
     // from its back; past the last one (zero) of the level the entry is n
     const uint64_t s = j / WV_SUB_STRIDE;
     const uint64_t p0 = b ? sub[s] : sub[L.nsub - 1 - s];
     const uint64_t p1 = b ? sub[s + 1] : sub[L.nsub - 2 - s];
-    uint64_t lo = p0 >> 9, hi = (p1 >> 9) < ns ? (p1 >> 9) : ns - 1;
-    auto before = [&](uint64_t k) -> uint64_t { return b ? (k * WV_SB_BITS - dir[2 * k]) : dir[2 * k]; };
-    while (lo < hi) {
-        const uint64_t mid = (lo + hi + 1) / 2;
-        if (before(mid) <= j) lo = mid; else hi = mid - 1;
+    if (p1 - p0 >= (1ull << WV_XSPAN_LOG2)) {   // a long sub-range: the answer is stored
+        const uint64_t nslot = wv_nslot(L.n);
+        const uint32_t* pool = (const uint32_t*)(q.img + L.pool_off);
+        return pool[((b ? 0 : nslot) + (p0 >> WV_XSPAN_LOG2)) * WV_SUB_STRIDE + (j % WV_SUB_STRIDE)];
     }
-    const uint64_t k = lo;
-    const uint64_t r = j - before(k);
-    const uint64_t blk = dir[2 * k + 1];
-    uint32_t qw = 0;
-    uint64_t cq = 0;
-    for (uint32_t t = 1; t < 8; t++) {
-        if (8 * k + t >= nw) break;
-        const uint64_t f = (blk >> (9 * (t - 1))) & 511u;
-        const uint64_t c = b ? (64u * t - f) : f;
-        if (c <= r) { qw = t; cq = c; } else break;
-    }
-    uint64_t w = words[8 * k + qw];
-    if (!b) w = ~w;
-    return k * WV_SB_BITS + 64u * qw + wv_select_in_word(w, (uint32_t)(r - cq));
+    return wv_select_dir(words_of(q, l), dir_of(q, l), L.n, b, j, p0, p1);
 }
 
 __device__ inline uint32_t digit_at(const QImg& q, uint32_t l, uint64_t i)

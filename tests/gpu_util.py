@@ -49,7 +49,7 @@ def describe_diff(a: np.ndarray, b: np.ndarray) -> str:
     img = Image(b)
     where = "header"
     for l, lv in enumerate(img.levels):
-        for key in ("bits_off", "rank_off", "sel0_off", "sel1_off", "sub_off"):
+        for key in ("bits_off", "rank_off", "sel0_off", "sel1_off", "sub_off", "pool_off"):
             if lv[key] and lv[key] <= off:
                 where = f"level {l} {key[:-4]} (+{off - lv[key]})"
     if img.nodes_off and off >= img.nodes_off:
