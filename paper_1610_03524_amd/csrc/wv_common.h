@@ -279,10 +279,12 @@ struct wv_xlevel {
 
 // One slot of a level's pool, by a workgroup of WV_SUB_STRIDE threads:
 // local = kind * nslot + slot, ones (kind 0 here) first.  The only sub-range
-// that can own slot s is the last one starting before (s+1)*2^20; it owns it
-// if it starts at s*2^20 or later and spans 2^20 bits or more.  Thread t
-// then writes the position of ordinal 512j+t (found by the directory
-// search), or m past the kind's count and in an unowned slot.
+// that can own slot s is the last one starting before lim = (s+1)*2^20: with
+// c b-bits before lim (one rank directory entry, lim being a multiple of
+// 512 and at most m), it is j = (c-1)/512.  It owns the slot if it starts
+// at s*2^20 or later and spans 2^20 bits or more.  Thread t then writes the
+// position of ordinal 512j+t (found by the directory search), or m past the
+// kind's count and in an unowned slot.
 __device__ inline void wv_xsel_block(const wv_xlevel& X, uint32_t local)
 {
     const uint64_t m = X.m, nslot = wv_nslot(m), ns = wv_cdiv(m, WV_SB_BITS);
@@ -297,16 +299,14 @@ __device__ inline void wv_xsel_block(const wv_xlevel& X, uint32_t local)
     const uint64_t J = wv_cdiv(count, WV_SUB_STRIDE);   // sub-ranges of the kind
     auto entry = [&](uint64_t j) -> uint64_t { return b ? sub[j] : sub[X.nsub - 1 - j]; };
     const uint64_t lim = (slot + 1) << WV_XSPAN_LOG2;
+    const uint64_t zb = dir[2 * (lim >> 9)];
+    const uint64_t c = b ? lim - zb : zb;
     uint64_t out = m;
-    if (J && entry(0) < lim) {
-        uint64_t lo = 0, hi = J - 1;   // the last sub-range starting before lim
-        while (lo < hi) {
-            const uint64_t mid = (lo + hi + 1) >> 1;
-            if (entry(mid) < lim) lo = mid; else hi = mid - 1;
-        }
-        const uint64_t p0 = entry(lo);
-        const uint64_t p1 = lo + 1 < J ? entry(lo + 1) : m;
-        const uint64_t o = lo * WV_SUB_STRIDE + threadIdx.x;
+    if (c) {
+        const uint64_t j = (c - 1) / WV_SUB_STRIDE;   // j < J
+        const uint64_t p0 = entry(j);
+        const uint64_t p1 = j + 1 < J ? entry(j + 1) : m;
+        const uint64_t o = j * WV_SUB_STRIDE + threadIdx.x;
         if (p0 >= (slot << WV_XSPAN_LOG2) && p1 - p0 >= (1ull << WV_XSPAN_LOG2) && o < count)
             out = wv_select_dir(words, dir, m, b, o, p0, p1);
     }
