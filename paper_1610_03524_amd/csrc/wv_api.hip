@@ -171,8 +171,8 @@ int make_plan_impl(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, con
         if (h == 0 || total != n) return WT_EINVAL;
         p.key_bits = h * p.D;
         p.nlevels = h;
-        // shaped multiary trees are built level by level
-        if (p.D >= 2) p.levelwise = true;
+        // 3-bit digits do not pack words exactly: level by level
+        if (p.D == 3) p.levelwise = true;
         level_n.assign(h, 0);
         for (uint32_t s = 0; s < sigma; s++)
             for (uint32_t l = 0; l < shape->code_len[s]; l++) level_n[l] += shape->counts[s];
@@ -249,17 +249,20 @@ int make_plan_impl(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, con
             return WT_OK;
         }
     }
-    // balanced and shaped binary trees: matrix passes over the (padded) keys,
-    // then the runs of every level moved to tree order
-    // (multiary trees: digits of 1, 2 or 4 bits, which pack words exactly)
-    if ((kind == WT_KIND_WT || kind == WT_KIND_SHAPED || (kind == WT_KIND_MULTIARY && p.D != 3)) &&
+    // balanced and shaped trees: matrix passes over the (padded) keys, then
+    // the runs of every level moved to tree order (levels of digits of 1, 2
+    // or 4 bits, which pack words exactly, assembled from the matrix levels
+    // first)
+    if ((kind == WT_KIND_WT || ((kind == WT_KIND_SHAPED || kind == WT_KIND_MULTIARY) && p.D != 3)) &&
         !p.levelwise && n && p.key_bits <= 31) {
         const uint32_t sig_k = kind == WT_KIND_WT ? sigma : (1u << p.key_bits);
         const uint32_t sb_k = kind == WT_KIND_SHAPED ? 4u : sym_bytes;
         p.from_matrix = wv_wm_make_plan(n, sig_k, sb_k, tune, p.wm) == WT_OK && p.wm.enabled &&
                         p.wm.L == p.key_bits;
     }
-    if (p.from_matrix && kind == WT_KIND_MULTIARY) {
+    if (p.from_matrix && multi) {
+        // digit levels (multiary trees, shaped trees over D-bit digits): the
+        // matrix levels in a workspace image, then the digit strings
         p.tau = p.wm.tau;
         p.ws_wm = bump(off, p.wm.ws_bytes);
         wv_layout_in tl{};
@@ -274,6 +277,22 @@ int make_plan_impl(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, con
         p.ws_tmpimg = bump(off, p.tlay.image_bytes);
         p.dstride = wv_round256((wv_cdiv(n * p.D, 64) + 1) * 8);   // one readable word past each string
         p.ws_digits = bump(off, p.dstride * p.nlevels);
+        if (kind == WT_KIND_SHAPED) {
+            // padded codeword keys; runs from the shape's counts on the host
+            p.ws_tkeys = bump(off, n * 4);
+            p.seg_bound = p.nnodes_image;
+            p.tile_bound = wv_tree_tile_bound(n, p.D, p.nlevels);
+            p.ws_segs = bump(off, seg_bytes(p.seg_bound, p.tile_bound));
+            p.ws_counts = bump(off, (uint64_t)sigma * 8);
+            // codes, lengths, padded-key table and the shape's counts next
+            // to each other: one upload
+            p.ws_codes = bump(off, (uint64_t)sigma * 4);
+            p.ws_lens = bump(off, (uint64_t)sigma * 4);
+            p.ws_ktab = bump(off, (uint64_t)sigma * 4);
+            p.ws_scounts = bump(off, (uint64_t)sigma * 8);
+            p.ws_bytes = off;
+            return WT_OK;
+        }
         if (p.key_bits <= WV_GROUP_MAX_BITS) {
             p.dev_runs = true;
             p.gz = wv_group_ws_sizes(p.key_bits);
@@ -288,7 +307,7 @@ int make_plan_impl(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, con
         p.ws_bytes = off;
         return WT_OK;
     }
-    if (p.from_matrix && kind == WT_KIND_SHAPED && p.key_bits > WV_SPLIT_BITS) {
+    if (p.from_matrix && kind == WT_KIND_SHAPED && p.D == 1 && p.key_bits > WV_SPLIT_BITS) {
         // codes longer than WV_SPLIT_BITS are rare in a skewed alphabet: the
         // first matrix then needs 16-bit keys and fewer passes, and the deep
         // levels come from a small second matrix over those symbols alone
@@ -355,9 +374,11 @@ int make_plan_impl(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, con
         }
         p.ws_counts = bump(off, (uint64_t)sigma * 8);
         if (kind == WT_KIND_SHAPED) {
-            // codes, lengths and the shape's counts next to each other: one upload
+            // codes, lengths, padded-key table and the shape's counts next to
+            // each other: one upload
             p.ws_codes = bump(off, (uint64_t)sigma * 4);
             p.ws_lens = bump(off, (uint64_t)sigma * 4);
+            p.ws_ktab = bump(off, (uint64_t)sigma * 4);
             p.ws_scounts = bump(off, (uint64_t)sigma * 8);
         }
         p.ws_bytes = off;
@@ -737,7 +758,11 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
     const uint64_t n = p.n;
     const uint32_t sigma = p.sigma, K = p.key_bits;
     const bool shaped = p.kind == WT_KIND_SHAPED, multi = p.kind == WT_KIND_MULTIARY;
-    const uint32_t D = multi ? p.D : 1u, T = multi ? p.nlevels : K;
+    // levels of D-bit digits: multiary trees, and shaped trees over digits
+    // (whose counters are taken after the gather, their levels being of
+    // different lengths)
+    const bool digits = multi || (shaped && p.D >= 2);
+    const uint32_t D = digits ? p.D : 1u, T = digits ? p.nlevels : K;
     // 1. symbol counts (and status).  A shaped tree takes its counts from the
     // shape, which fixes the level sizes, and the device only checks them
     // (image status); a balanced tree over more than WV_GROUP_MAX_BITS key
@@ -791,13 +816,15 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
     std::vector<uint8_t> up_codes_v, up_late_v;
     const void* keys = S;
     if (shaped) {
+        // codeword lengths in bits (digits of D bits)
         c32.resize(sigma);
         l32.resize(sigma);
         for (uint32_t x = 0; x < sigma; x++) {
-            l32[x] = shape->code_len[x];
+            l32[x] = shape->code_len[x] * p.D;
             c32[x] = l32[x] ? (uint32_t)shape->codes[x] : 0u;
         }
         if (p.h1) wv_split_table(c32.data(), l32.data(), sigma, K, p.h1, ktab);   // top h1 bits of every codeword
+        else wv_key_table(c32.data(), l32.data(), sigma, K, ktab);                // every codeword padded to K bits
         // codes, lengths (and key table) and the shape's counts in the
         // workspace layout, one copy; the device checks its counts against
         // the shape's (image status)
@@ -806,7 +833,7 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
         uint8_t* hb = up_codes.get() ? (uint8_t*)up_codes.get() : up_codes_v.data();
         std::memcpy(hb, c32.data(), (uint64_t)sigma * 4);
         std::memcpy(hb + (p.ws_lens - p.ws_codes), l32.data(), (uint64_t)sigma * 4);
-        if (p.h1) std::memcpy(hb + (p.ws_ktab - p.ws_codes), ktab.data(), (uint64_t)sigma * 4);
+        std::memcpy(hb + (p.ws_ktab - p.ws_codes), ktab.data(), (uint64_t)sigma * 4);
         std::memcpy(hb + (p.ws_scounts - p.ws_codes), shape->counts, (uint64_t)sigma * 8);
         if (up_codes.get()) WV_CHECK(wv_upload(at<void>(ws, p.ws_codes), hb, span, s));
         else WV_CHECK(hipMemcpyAsync(at<void>(ws, p.ws_codes), hb, span, hipMemcpyHostToDevice, s));
@@ -828,11 +855,12 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
                                                 at<uint32_t>(ws, p.ws_lkeys), p.nlong, s)));
         } else {
             WV_TIMED(prof, s, "tree_keys",
-                     WV_CHECK(wv_tree_keys(S, n, p.sym_bytes, sigma, dc, dl, K, at<uint32_t>(ws, p.ws_tkeys), s)));
+                     WV_CHECK(wv_tree_keys(S, n, p.sym_bytes, sigma, at<uint32_t>(ws, p.ws_ktab),
+                                           at<uint32_t>(ws, p.ws_tkeys), s)));
         }
         keys = at<void>(ws, p.ws_tkeys);
     }
-    if (multi) {
+    if (digits) {
         // the matrix levels in the workspace, then the digits: 2-bit digits
         // need only the zeros before every 256-word block of the levels 2t,
         // 16-ary digits query the matrix's rank directories
@@ -840,11 +868,11 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
         const uint64_t *zpre = nullptr, *ztot = nullptr;
         if (D == 4) {
             wv_dir_scratch unused{};
-            WV_CHECK(wv_wm_run(p.wm, S, timg, p.tlay, at<uint8_t>(ws, p.ws_wm), unused, s));
+            WV_CHECK(wv_wm_run(p.wm, keys, timg, p.tlay, at<uint8_t>(ws, p.ws_wm), unused, s));
         } else {
             uint64_t* lw[WV_MAX_LEVELS];
             for (uint32_t l = 0; l < K; l++) lw[l] = (uint64_t*)(timg + p.tlay.lv[l].bits_off);
-            WV_CHECK(wv_wm_levels(p.wm, S, lw, nullptr, at<uint8_t>(ws, p.ws_wm), s));
+            WV_CHECK(wv_wm_levels(p.wm, keys, lw, nullptr, at<uint8_t>(ws, p.ws_wm), s));
             if (D == 2) {
                 // scratch of the digit counters, not used before the gather
                 wv_digit_words dw{};
@@ -933,8 +961,9 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
         code_rec.assign((uint64_t)sigma * WV_CODE_BYTES, 0);
         for (uint32_t x = 0; x < sigma; x++) {
             const uint64_t c = c32[x];
+            const uint32_t len = shape->code_len[x];   // in digits
             std::memcpy(code_rec.data() + (uint64_t)x * WV_CODE_BYTES, &c, 8);
-            std::memcpy(code_rec.data() + (uint64_t)x * WV_CODE_BYTES + 8, &l32[x], 4);
+            std::memcpy(code_rec.data() + (uint64_t)x * WV_CODE_BYTES + 8, &len, 4);
         }
     }
     // 4. every level's runs, from the counts
@@ -958,8 +987,8 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
             seg0[K] = segs.size();
         }
         // tree level t: matrix level t (binary), or digit level t from matrix
-        // level t*D with every run D bits per symbol (multiary)
-        if (multi) {
+        // level t*D with every run D bits per symbol (digit levels)
+        if (digits) {
             std::vector<wv_perm_seg> ms;
             std::vector<uint64_t> m0(T + 1, 0);
             for (uint32_t t = 0; t < T; t++) {
@@ -977,7 +1006,7 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
     std::vector<wv_perm_level> lv(T);
     for (uint32_t l = 0; l < T; l++) {
         lv[l].dst = (uint64_t*)(img + p.lay.lv[l].bits_off);
-        lv[l].src = multi ? at<uint64_t>(ws, p.ws_digits + l * p.dstride)
+        lv[l].src = digits ? at<uint64_t>(ws, p.ws_digits + l * p.dstride)
                   : (p.h1 && l >= p.h1) ? at<uint64_t>(ws, p.ws_btmp + l * p.btmp_stride)
                                         : at<uint64_t>(ws, p.ws_tmp + l * p.tmp_stride);
         lv[l].nbits = p.lay.lv[l].n * D;
@@ -1029,6 +1058,8 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
     uint8_t* dscr = p.h1 ? at<uint8_t>(ws, p.ws_sdir) : at<uint8_t>(ws, p.ws_wm + p.wm.off_dir);
     if (multi) {
         WV_TIMED(prof, s, "mcounters", WV_CHECK(wv_multiary_ranges(img, p.lay.lv, T, D, md, s)));
+    } else if (digits) {
+        WV_TIMED(prof, s, "mcounters", WV_CHECK(wv_multiary_counters(img, p.lay.lv, T, D, md, s)));
     } else if (shaped) {
         // level 0 is the longest
         WV_CHECK(wv_span_directory(img, p.lay, 0, K, dscr, wv_span_dir_sizes(p.lay.lv[0].n, K), s, prof));

@@ -138,12 +138,14 @@ dir_finish_k(uint8_t* __restrict__ image, uint32_t level, wv_level L,
 
 // ---- multiary counters -------------------------------------------------------
 
-// Multiary counters of M levels of m digits at once (level t = blockIdx.y),
+// Multiary counters of M levels at once (level t = blockIdx.y, m[t] digits),
 // one wave per range of 64 words (lane = word).  Range counts and prefixes
-// are laid out [range][level][digit].
+// are laid out [range][level][digit] with nr0 rows, the ranges of the
+// longest level (a shorter level counts zero in the rows past its end).
 struct MLevels {
     uint64_t bits_off[WV_MAX_LEVELS], rank_off[WV_MAX_LEVELS], sel_off[WV_MAX_LEVELS];
-    uint64_t m, nsel;
+    uint64_t m[WV_MAX_LEVELS], nsel[WV_MAX_LEVELS];
+    uint64_t nr0, nsel0;   // most ranges, most samples per digit of any level
     uint32_t M, D;
 };
 
@@ -157,7 +159,7 @@ msel_k(uint8_t* __restrict__ image, MLevels a)
     const uint32_t lane = threadIdx.x & 63, t = blockIdx.y;
     const uint64_t r = ((uint64_t)blockIdx.x * DIR_THREADS + threadIdx.x) >> 6;
     const uint32_t D = a.D, P = wv_digits_per_word(D), d = 1u << D;
-    const uint64_t m = a.m, nr = wv_mranges(m, D), nw = wv_cdiv(m, P);
+    const uint64_t m = a.m[t], nr = wv_mranges(m, D), nw = wv_cdiv(m, P);
     if (r >= nr) return;   // whole waves: the scans below need every lane
     const uint64_t* words = (const uint64_t*)(image + a.bits_off[t]);
     const uint64_t* rng = (const uint64_t*)(image + a.rank_off[t]);
@@ -171,7 +173,7 @@ msel_k(uint8_t* __restrict__ image, MLevels a)
         const uint64_t base = rng[r * d + g];                          // digits g before the range
         const uint64_t o = wv_cdiv(base, WV_SEL_STRIDE) * WV_SEL_STRIDE;   // the next sampled ordinal
         if (o >= base + inc - v && o < base + inc)
-            sel[g * a.nsel + o / WV_SEL_STRIDE] = wi * P + wv_digit_select(w, D, g, c, (uint32_t)(o - (base + inc - v)));
+            sel[g * a.nsel[t] + o / WV_SEL_STRIDE] = wi * P + wv_digit_select(w, D, g, c, (uint32_t)(o - (base + inc - v)));
     }
 }
 
@@ -180,21 +182,21 @@ __global__ void __launch_bounds__(DIR_THREADS)
 msel_fill_k(uint8_t* __restrict__ image, MLevels a)
 {
     const uint32_t t = blockIdx.y, d = 1u << a.D;
-    const uint64_t nr = wv_mranges(a.m, a.D);
+    const uint64_t m = a.m[t], nsel = a.nsel[t], nr = wv_mranges(m, a.D);
     const uint64_t* rng = (const uint64_t*)(image + a.rank_off[t]);
     uint64_t* sel = (uint64_t*)(image + a.sel_off[t]);
-    for (uint64_t i = (uint64_t)blockIdx.x * DIR_THREADS + threadIdx.x; i < d * a.nsel; i += (uint64_t)gridDim.x * DIR_THREADS) {
-        const uint64_t g = i / a.nsel, k = i % a.nsel;
-        if (k >= wv_cdiv(rng[nr * d + g], WV_SEL_STRIDE)) sel[i] = a.m;
+    for (uint64_t i = (uint64_t)blockIdx.x * DIR_THREADS + threadIdx.x; i < d * nsel; i += (uint64_t)gridDim.x * DIR_THREADS) {
+        const uint64_t g = i / nsel, k = i % nsel;
+        if (k >= wv_cdiv(rng[nr * d + g], WV_SEL_STRIDE)) sel[i] = m;
     }
 }
 
 hipError_t launch_msel(uint8_t* image, const MLevels& a, hipStream_t s)
 {
-    const uint64_t nr = wv_mranges(a.m, a.D);
+    const uint64_t nr = a.nr0;
     const uint64_t d = 1ull << a.D;
     if (nr) msel_k<<<dim3((uint32_t)wv_cdiv(nr, DIR_THREADS / 64), a.M), DIR_THREADS, 0, s>>>(image, a);
-    msel_fill_k<<<dim3((uint32_t)std::min<uint64_t>(wv_cdiv(d * a.nsel, DIR_THREADS), 1024), a.M), DIR_THREADS, 0, s>>>(
+    msel_fill_k<<<dim3((uint32_t)std::min<uint64_t>(wv_cdiv(d * a.nsel0, DIR_THREADS), 1024), a.M), DIR_THREADS, 0, s>>>(
         image, a);
     return hipGetLastError();
 }
@@ -205,8 +207,9 @@ mcount_k(const uint8_t* __restrict__ image, MLevels a, uint32_t* __restrict__ rn
     const uint32_t lane = threadIdx.x & 63, t = blockIdx.y;
     const uint64_t r = ((uint64_t)blockIdx.x * DIR_THREADS + threadIdx.x) >> 6;
     const uint32_t D = a.D, P = wv_digits_per_word(D), d = 1u << D;
-    const uint64_t m = a.m, nr = wv_mranges(m, D), nw = wv_cdiv(m, P);
-    if (r >= nr) return;   // whole waves: the scans below need every lane
+    const uint64_t m = a.m[t], nw = wv_cdiv(m, P);
+    // every row of the counts: rows past the level's end count zero
+    if (r >= a.nr0) return;   // whole waves: the scans below need every lane
     const uint64_t* words = (const uint64_t*)(image + a.bits_off[t]);
     const uint64_t wi = 64 * r + lane;
     const uint64_t w = wi < nw ? words[wi] : 0ull;
@@ -223,7 +226,7 @@ mwrite_k(uint8_t* __restrict__ image, MLevels a, const uint64_t* __restrict__ rn
     const uint32_t lane = threadIdx.x & 63, t = blockIdx.y;
     const uint64_t r = ((uint64_t)blockIdx.x * DIR_THREADS + threadIdx.x) >> 6;
     const uint32_t D = a.D, P = wv_digits_per_word(D), d = 1u << D;
-    const uint64_t m = a.m, nr = wv_mranges(m, D), nsub = wv_msubs(m, D), nw = wv_cdiv(m, P);
+    const uint64_t m = a.m[t], nr = wv_mranges(m, D), nsub = wv_msubs(m, D), nw = wv_cdiv(m, P);
     if (r >= nr) return;   // whole waves
     const uint64_t* words = (const uint64_t*)(image + a.bits_off[t]);
     uint64_t* rng = (uint64_t*)(image + a.rank_off[t]);
@@ -247,7 +250,7 @@ mrange_k(uint8_t* __restrict__ image, MLevels a, const uint64_t* __restrict__ rn
 {
     const uint32_t t = blockIdx.y, d = 1u << a.D;
     const uint64_t i = (uint64_t)blockIdx.x * DIR_THREADS + threadIdx.x;
-    const uint64_t nr = wv_mranges(a.m, a.D);
+    const uint64_t nr = wv_mranges(a.m[t], a.D);
     if (i >= nr * d) return;
     uint64_t* rng = (uint64_t*)(image + a.rank_off[t]);
     rng[i] = rng_pre[((i / d) * a.M + t) * d + i % d];
@@ -256,7 +259,7 @@ mrange_k(uint8_t* __restrict__ image, MLevels a, const uint64_t* __restrict__ rn
 __global__ void mfinish_k(uint8_t* __restrict__ image, MLevels a, const uint64_t* __restrict__ totals)
 {
     const uint32_t t = blockIdx.x, d = 1u << a.D;
-    const uint64_t nr = wv_mranges(a.m, a.D);
+    const uint64_t nr = wv_mranges(a.m[t], a.D);
     uint64_t* rng = (uint64_t*)(image + a.rank_off[t]);
     if (threadIdx.x < d) rng[nr * d + threadIdx.x] = totals[t * d + threadIdx.x];
 }
@@ -476,21 +479,29 @@ hipError_t wv_binary_directory(uint8_t* image, uint32_t level, const wv_level& L
     return launch_xsel(image, &L, 1, s);
 }
 
-hipError_t wv_multiary_counters(uint8_t* image, const wv_level* lv, uint32_t M, uint32_t D,
-                                const wv_mdir_scratch& sc, hipStream_t s)
+static MLevels mlevels(const wv_level* lv, uint32_t M, uint32_t D)
 {
-    if (!M) return hipSuccess;
     MLevels a{};
-    a.m = lv[0].n;
     a.M = M;
     a.D = D;
-    a.nsel = lv[0].nsel;
     for (uint32_t t = 0; t < M; t++) {
         a.bits_off[t] = lv[t].bits_off;
         a.rank_off[t] = lv[t].rank_off;
         a.sel_off[t] = lv[t].sel0_off;
+        a.m[t] = lv[t].n;
+        a.nsel[t] = lv[t].nsel;
+        a.nr0 = std::max<uint64_t>(a.nr0, wv_mranges(lv[t].n, D));
+        a.nsel0 = std::max<uint64_t>(a.nsel0, lv[t].nsel);
     }
-    const uint64_t nr = wv_mranges(a.m, D);
+    return a;
+}
+
+hipError_t wv_multiary_counters(uint8_t* image, const wv_level* lv, uint32_t M, uint32_t D,
+                                const wv_mdir_scratch& sc, hipStream_t s)
+{
+    if (!M) return hipSuccess;
+    const MLevels a = mlevels(lv, M, D);
+    const uint64_t nr = a.nr0;
     const uint32_t d = 1u << D;
     const dim3 grid((uint32_t)wv_cdiv(nr, DIR_THREADS / 64), M);
     if (nr) mcount_k<<<grid, DIR_THREADS, 0, s>>>(image, a, sc.rng_cnt);
@@ -505,17 +516,8 @@ hipError_t wv_multiary_ranges(uint8_t* image, const wv_level* lv, uint32_t M, ui
                               const wv_mdir_scratch& sc, hipStream_t s)
 {
     if (!M) return hipSuccess;
-    MLevels a{};
-    a.m = lv[0].n;
-    a.M = M;
-    a.D = D;
-    a.nsel = lv[0].nsel;
-    for (uint32_t t = 0; t < M; t++) {
-        a.bits_off[t] = lv[t].bits_off;
-        a.rank_off[t] = lv[t].rank_off;
-        a.sel_off[t] = lv[t].sel0_off;
-    }
-    const uint64_t nr = wv_mranges(a.m, D);
+    const MLevels a = mlevels(lv, M, D);
+    const uint64_t nr = a.nr0;
     const uint32_t d = 1u << D;
     hipError_t e = wv_scan_u32(sc.rng_cnt, sc.rng_pre, nr, M * d, sc.partial, sc.totals, s);
     if (e != hipSuccess) return e;

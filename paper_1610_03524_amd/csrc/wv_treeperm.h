@@ -56,9 +56,11 @@ inline uint64_t wv_tree_tile_bound(uint64_t n, uint32_t D, uint32_t nlev)
 void wv_tree_segments(const std::vector<uint64_t>& counts, uint32_t key_bits, const uint32_t* codes,
                       const uint32_t* lens, std::vector<wv_perm_seg>& segs, std::vector<uint64_t>& seg0);
 
-// keys[i] = codes[S[i]] << (h - lens[S[i]]) (device arrays; 0 for S[i] >= sigma)
-hipError_t wv_tree_keys(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma, const uint32_t* codes,
-                        const uint32_t* lens, uint32_t h, uint32_t* keys, hipStream_t s);
+// keys[i] = ktab[S[i]] (device table; 0 for S[i] >= sigma)
+hipError_t wv_tree_keys(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma, const uint32_t* ktab,
+                        uint32_t* keys, hipStream_t s);
+// the padded-key table: codes[x] << (h - lens[x]) for every coded symbol, else 0
+void wv_key_table(const uint32_t* codes, const uint32_t* lens, uint32_t sigma, uint32_t h, std::vector<uint32_t>& tab);
 
 // Shaped trees with codes longer than WV_SPLIT_BITS whose symbols make at most
 // 1/WV_SPLIT_SHARE of the sequence are built from two matrices: one over the

@@ -36,18 +36,6 @@
 
 namespace {
 
-template <typename T>
-__global__ void __launch_bounds__(256)
-tree_keys_k(const T* __restrict__ S, uint64_t n, uint32_t sigma, const uint32_t* __restrict__ codes,
-            const uint32_t* __restrict__ lens, uint32_t h, uint32_t* __restrict__ keys)
-{
-    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t x = (uint32_t)S[i];
-    // a symbol >= sigma has been flagged by the validation; its key is 0
-    keys[i] = x < sigma ? codes[x] << (h - lens[x]) : 0u;
-}
-
 // Split shaped build.  A block takes KB symbols; with 16-byte aligned input
 // every thread reads V = 16 / sizeof(T) consecutive symbols per row with one
 // load (rows of KB_T * V symbols), else (and in a ragged last block) one
@@ -86,6 +74,44 @@ __device__ inline const uint32_t* stage_table(const uint32_t* __restrict__ ktab,
     for (uint32_t x = threadIdx.x; x < sigma; x += KB_T) lds[x] = ktab[x];
     __syncthreads();
     return lds;
+}
+
+// Padded codeword keys, keys[i] = ktab[S[i]] (0 for a symbol >= sigma, which
+// the validation has flagged): the table in LDS when sigma is small, blocks
+// of KB symbols read and written in 16-byte pieces.
+template <typename T>
+__global__ void __launch_bounds__(KB_T)
+tree_keys_k(const T* __restrict__ S, uint64_t n, uint32_t sigma, const uint32_t* __restrict__ ktab,
+            uint32_t* __restrict__ keys, uint64_t nblocks)
+{
+    constexpr uint32_t V = SymVec<T>::V, ROWS = KB / (KB_T * V);
+    __shared__ uint32_t tab_s[KTAB_LDS];
+    const uint32_t* tab = stage_table(ktab, sigma, tab_s);
+    for (uint64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+        const uint64_t b0 = blk * KB;
+        const bool vec = (((uintptr_t)S & 15u) == 0) && (((uintptr_t)keys & 15u) == 0) && b0 + KB <= n;
+        SymVec<T> sv[ROWS];
+#pragma unroll
+        for (uint32_t r = 0; r < ROWS; r++) load_syms(S, b0 + (r * KB_T + threadIdx.x) * V, n, vec, sv[r]);
+#pragma unroll
+        for (uint32_t r = 0; r < ROWS; r++) {
+            const uint64_t i0 = b0 + (r * KB_T + threadIdx.x) * V;
+            uint32_t kk[V];
+#pragma unroll
+            for (uint32_t k = 0; k < V; k++) {
+                const uint32_t x = (uint32_t)sv[r].v[k];
+                kk[k] = i0 + k < n && x < sigma ? tab[x] : 0u;
+            }
+            if (vec) {
+#pragma unroll
+                for (uint32_t k = 0; k < V; k += 4) *(uint4*)(keys + i0 + k) = make_uint4(kk[k], kk[k + 1], kk[k + 2], kk[k + 3]);
+            } else {
+#pragma unroll
+                for (uint32_t k = 0; k < V; k++)
+                    if (i0 + k < n) keys[i0 + k] = kk[k];
+            }
+        }
+    }
 }
 
 template <typename T>
@@ -640,15 +666,23 @@ void wv_tree_segments(const std::vector<uint64_t>& counts, uint32_t key_bits, co
     seg0[key_bits] = segs.size();
 }
 
-hipError_t wv_tree_keys(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma, const uint32_t* codes,
-                        const uint32_t* lens, uint32_t h, uint32_t* keys, hipStream_t s)
+hipError_t wv_tree_keys(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma, const uint32_t* ktab,
+                        uint32_t* keys, hipStream_t s)
 {
     if (!n) return hipSuccess;
-    const uint32_t g = (uint32_t)wv_cdiv(n, 256);
-    if (sym_bytes == 1) tree_keys_k<uint8_t><<<g, 256, 0, s>>>((const uint8_t*)S, n, sigma, codes, lens, h, keys);
-    else if (sym_bytes == 2) tree_keys_k<uint16_t><<<g, 256, 0, s>>>((const uint16_t*)S, n, sigma, codes, lens, h, keys);
-    else tree_keys_k<uint32_t><<<g, 256, 0, s>>>((const uint32_t*)S, n, sigma, codes, lens, h, keys);
+    const uint64_t nb = wv_tree_key_blocks(n);
+    const uint32_t g = (uint32_t)std::min<uint64_t>(nb, KB_GRID);
+    if (sym_bytes == 1) tree_keys_k<uint8_t><<<g, KB_T, 0, s>>>((const uint8_t*)S, n, sigma, ktab, keys, nb);
+    else if (sym_bytes == 2) tree_keys_k<uint16_t><<<g, KB_T, 0, s>>>((const uint16_t*)S, n, sigma, ktab, keys, nb);
+    else tree_keys_k<uint32_t><<<g, KB_T, 0, s>>>((const uint32_t*)S, n, sigma, ktab, keys, nb);
     return hipGetLastError();
+}
+
+void wv_key_table(const uint32_t* codes, const uint32_t* lens, uint32_t sigma, uint32_t h, std::vector<uint32_t>& tab)
+{
+    tab.assign(sigma, 0u);
+    for (uint32_t x = 0; x < sigma; x++)
+        if (lens[x]) tab[x] = codes[x] << (h - lens[x]);
 }
 
 namespace {
