@@ -716,15 +716,15 @@ int build_balanced_dev(const Plan& p, const void* S, uint8_t* img, uint8_t* ws, 
                 ztot = tot;
             }
         }
+        wv_digit_set ds{};
         for (uint32_t t = 0; t < T; t++) {
-            wv_digit_levels dl{};
             for (uint32_t k = 0; k < D; k++) {
-                dl.words[k] = (const uint64_t*)(timg + p.tlay.lv[t * D + k].bits_off);
-                dl.dir[k] = (const uint64_t*)(timg + p.tlay.lv[t * D + k].rank_off);
+                ds.lv[t].words[k] = (const uint64_t*)(timg + p.tlay.lv[t * D + k].bits_off);
+                ds.lv[t].dir[k] = (const uint64_t*)(timg + p.tlay.lv[t * D + k].rank_off);
             }
-            WV_TIMED(prof, s, "tree_digits",
-                     WV_CHECK(wv_tree_digits(dl, n, D, at<uint64_t>(ws, p.ws_digits + t * p.dstride), zpre, ztot, t, T, s)));
+            ds.out[t] = at<uint64_t>(ws, p.ws_digits + t * p.dstride);
         }
+        WV_TIMED(prof, s, "tree_digits", WV_CHECK(wv_tree_digits(ds, T, n, D, zpre, ztot, s)));
     } else {
         uint64_t* lw[WV_MAX_LEVELS];
         for (uint32_t l = 0; l < K; l++) lw[l] = at<uint64_t>(ws, p.ws_tmp + l * p.tmp_stride);
@@ -887,15 +887,15 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
                 ztot = tot;
             }
         }
+        wv_digit_set ds{};
         for (uint32_t t = 0; t < T; t++) {
-            wv_digit_levels dl{};
             for (uint32_t k = 0; k < D; k++) {
-                dl.words[k] = (const uint64_t*)(timg + p.tlay.lv[t * D + k].bits_off);
-                dl.dir[k] = (const uint64_t*)(timg + p.tlay.lv[t * D + k].rank_off);
+                ds.lv[t].words[k] = (const uint64_t*)(timg + p.tlay.lv[t * D + k].bits_off);
+                ds.lv[t].dir[k] = (const uint64_t*)(timg + p.tlay.lv[t * D + k].rank_off);
             }
-            WV_TIMED(prof, s, "tree_digits",
-                     WV_CHECK(wv_tree_digits(dl, n, D, at<uint64_t>(ws, p.ws_digits + t * p.dstride), zpre, ztot, t, T, s)));
+            ds.out[t] = at<uint64_t>(ws, p.ws_digits + t * p.dstride);
         }
+        WV_TIMED(prof, s, "tree_digits", WV_CHECK(wv_tree_digits(ds, T, n, D, zpre, ztot, s)));
     } else if (p.h1) {
         // S itself was validated above; the keys need no check
         // the big matrix first, then the small matrix of the long codes on a
@@ -1013,11 +1013,11 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
         lv[l].seg0 = seg0[l];
         lv[l].nseg = seg0[l + 1] - seg0[l];
         lv[l].sub = nullptr;
-        // multiary: the sub-range counters follow the range counters
-        if (multi) lv[l].sub = (uint16_t*)(img + p.lay.lv[l].rank_off + (wv_mranges(p.lay.lv[l].n, D) + 1) * (8ull << D));
+        // digit levels: the sub-range counters follow the range counters
+        if (digits) lv[l].sub = (uint16_t*)(img + p.lay.lv[l].rank_off + (wv_mranges(p.lay.lv[l].n, D) + 1) * (8ull << D));
     }
     std::vector<uint32_t> tile0, tile_seg;
-    wv_tree_tiles(lv, segs, multi, tile0, tile_seg);
+    wv_tree_tiles(lv, segs, digits, tile0, tile_seg);
     if (tile_seg.size() > p.tile_bound) return fail(WT_EUNSUP);
     // descriptors, runs and tiles in one copy; the node and code tables of a
     // shaped tree behind them in the same host buffer
@@ -1049,17 +1049,21 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
     }
 
     // 5. runs to tree order, then the directories
-    // multiary: the gather also counts digits per range and sub-range
+    // digit levels: the gather also counts digits per range and sub-range
+    // (levels shorter than the first leave rows of the range counts that
+    // the scan must read as zero)
     const wv_mdir_scratch md{at<uint32_t>(ws, p.ws_sb_ones), at<uint64_t>(ws, p.ws_sb_pre),
                              at<uint64_t>(ws, p.ws_partial), at<uint64_t>(ws, p.ws_mtot)};
     const wv_perm_counts pc{md.rng_cnt, n, D, T};
+    if (digits && !multi) {
+        const uint64_t cells = wv_mranges(n, D) * T * (1ull << D);
+        WV_TIMED(prof, s, "mcounters", WV_CHECK(wv_fill_u64((uint64_t*)md.rng_cnt, wv_cdiv(cells, 2), 0, s)));
+    }
     WV_TIMED(prof, s, "tree_perm",
-             WV_CHECK(wv_tree_permute(dlv, T, dseg, dtile, tile0.data(), multi ? &pc : nullptr, s)));
+             WV_CHECK(wv_tree_permute(dlv, T, dseg, dtile, tile0.data(), digits ? &pc : nullptr, s)));
     uint8_t* dscr = p.h1 ? at<uint8_t>(ws, p.ws_sdir) : at<uint8_t>(ws, p.ws_wm + p.wm.off_dir);
-    if (multi) {
+    if (digits) {
         WV_TIMED(prof, s, "mcounters", WV_CHECK(wv_multiary_ranges(img, p.lay.lv, T, D, md, s)));
-    } else if (digits) {
-        WV_TIMED(prof, s, "mcounters", WV_CHECK(wv_multiary_counters(img, p.lay.lv, T, D, md, s)));
     } else if (shaped) {
         // level 0 is the longest
         WV_CHECK(wv_span_directory(img, p.lay, 0, K, dscr, wv_span_dir_sizes(p.lay.lv[0].n, K), s, prof));

@@ -20,10 +20,12 @@ struct wv_perm_level {
     uint16_t* sub;          // multiary: the level's sub-range counters (counting launch only)
 };
 
-// Counters of multiary levels taken while gathering them: every level holds
-// m digits of D bits.  rng_cnt[(r * M + l) * 2^D + g] receives the number of
-// digits g in 64-word range r of level l, and each level's sub-range counters
-// are written.
+// Counters of multiary levels taken while gathering them (levels of D-bit
+// digits; m = the digits of every level in the gather of balanced trees from
+// symbol groups, the gather of runs takes each level's own length).
+// rng_cnt[(r * M + l) * 2^D + g] receives the number of digits g in 64-word
+// range r of level l (rows past a shorter level's ranges are not written),
+// and each level's sub-range counters are written.
 struct wv_perm_counts {
     uint32_t* rng_cnt;
     uint64_t m;
@@ -99,6 +101,12 @@ struct wv_digit_levels {
     const uint64_t* dir[4];
 };
 
+// the digit levels t < T of one launch: their matrix levels and outputs
+struct wv_digit_set {
+    wv_digit_levels lv[WV_MAX_LEVELS];
+    uint64_t* out[WV_MAX_LEVELS];
+};
+
 // words of the matrix levels 2t of a 4-ary tree (t < T)
 struct wv_digit_words {
     const uint64_t* w[WV_MAX_LEVELS / 2];
@@ -110,13 +118,13 @@ uint64_t wv_digit_blocks(uint64_t n);
 // cnt[b * T + t] = zeros in block b of matrix level 2t (blocks of 256 words)
 hipError_t wv_digit_zero_counts(const wv_digit_words& a, uint64_t n, uint32_t T, uint32_t* cnt, hipStream_t s);
 
-// the digit string of one multiary level in the order of matrix level bD
-// (ceil(n*D/64) words; D = 1, 2 or 4).  D = 2 takes the zeros before every
+// the digit strings of digit levels t < T, each in the order of matrix level
+// tD (ceil(n*D/64) words; D = 1, 2 or 4), in one launch.  D = 2 takes the zeros before every
 // block of level 2t from zpre[b * T + t] (the exclusive scan of the zero
 // counts above) and the level's zeros from ztot[t] instead of rank queries;
 // D = 4 queries the rank directories in `a`.
-hipError_t wv_tree_digits(const wv_digit_levels& a, uint64_t n, uint32_t D, uint64_t* out, const uint64_t* zpre,
-                          const uint64_t* ztot, uint32_t t, uint32_t T, hipStream_t s);
+hipError_t wv_tree_digits(const wv_digit_set& a, uint32_t T, uint64_t n, uint32_t D, const uint64_t* zpre,
+                          const uint64_t* ztot, hipStream_t s);
 
 // ---- runs of balanced trees, derived on the device --------------------------
 //

@@ -286,10 +286,11 @@ perm_runs_k(PermArgs a)
     if (COUNT) {
         const wv_perm_counts& cnt = a.cnt;
         const uint32_t lane = threadIdx.x & 63, D = cnt.D, P = wv_digits_per_word(D), d = 1u << D;
+        const uint64_t m = L.nbits >> (D >> 1);   // the level's digits (D = 1, 2, 4)
         const uint64_t r = w >> 6, sk = w >> 3;
-        if (r >= wv_mranges(cnt.m, D)) return;   // whole waves
-        const uint32_t c = w < nw ? (uint32_t)min<uint64_t>(P, cnt.m - w * P) : 0u;
-        const bool subw = (lane & 7) == 0 && sk < wv_msubs(cnt.m, D);
+        if (r >= wv_mranges(m, D)) return;   // whole waves
+        const uint32_t c = w < nw ? (uint32_t)min<uint64_t>(P, m - w * P) : 0u;
+        const bool subw = (lane & 7) == 0 && sk < wv_msubs(m, D);
         for (uint32_t g0 = 0; g0 < d; g0 += 4) {
             uint64_t pack = 0;   // up to four 16-bit sub-range counters
             for (uint32_t gg = 0; gg < 4 && g0 + gg < d; gg++) {
@@ -431,8 +432,10 @@ constexpr uint32_t DW = 8;
 
 template <uint32_t D>
 __global__ void __launch_bounds__(256)
-digits_k(wv_digit_levels a, uint64_t n, uint64_t nwords, uint64_t* __restrict__ out)
+digits_k(wv_digit_set set, uint64_t n, uint64_t nwords)
 {
+    const wv_digit_levels& a = set.lv[blockIdx.y];   // digit level t = blockIdx.y
+    uint64_t* __restrict__ out = set.out[blockIdx.y];
     const uint32_t lane = threadIdx.x & 63;
     const uint64_t wave = ((uint64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
     const uint64_t nw0 = wv_cdiv(n, 64);
@@ -541,9 +544,12 @@ __device__ inline uint64_t bits64(const uint64_t* __restrict__ w, uint64_t pos, 
 constexpr uint32_t DG = 256;
 
 __global__ void __launch_bounds__(DG)
-digits2_k(wv_digit_levels a, uint64_t n, uint64_t nwords, uint64_t* __restrict__ out, const uint64_t* __restrict__ zpre,
-          const uint64_t* __restrict__ ztot, uint32_t t, uint32_t T)
+digits2_k(wv_digit_set set, uint64_t n, uint64_t nwords, const uint64_t* __restrict__ zpre,
+          const uint64_t* __restrict__ ztot, uint32_t T)
 {
+    const uint32_t t = blockIdx.y;   // digit level
+    const wv_digit_levels& a = set.lv[t];
+    uint64_t* __restrict__ out = set.out[t];
     __shared__ uint32_t wsum[DG / 64];
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t nw0 = wv_cdiv(n, 64);
@@ -759,15 +765,16 @@ hipError_t wv_tree_long_keys(const void* S, uint64_t n, uint32_t sym_bytes, uint
     return hipGetLastError();
 }
 
-hipError_t wv_tree_digits(const wv_digit_levels& a, uint64_t n, uint32_t D, uint64_t* out, const uint64_t* zpre,
-                          const uint64_t* ztot, uint32_t t, uint32_t T, hipStream_t s)
+hipError_t wv_tree_digits(const wv_digit_set& a, uint32_t T, uint64_t n, uint32_t D, const uint64_t* zpre,
+                          const uint64_t* ztot, hipStream_t s)
 {
-    if (!n) return hipSuccess;
+    if (!n || !T) return hipSuccess;
+    if (T > WV_MAX_LEVELS) return hipErrorInvalidValue;
     const uint32_t g = (uint32_t)wv_cdiv(wv_cdiv(wv_cdiv(n, 64), DW), 4);   // 4 waves per block
     const uint64_t nw = wv_cdiv(n * D, 64);
-    if (D == 1) digits_k<1><<<g, 256, 0, s>>>(a, n, nw, out);
-    else if (D == 2) digits2_k<<<(uint32_t)wv_digit_blocks(n), DG, 0, s>>>(a, n, nw, out, zpre, ztot, t, T);
-    else if (D == 4) digits_k<4><<<g, 256, 0, s>>>(a, n, nw, out);
+    if (D == 1) digits_k<1><<<dim3(g, T), 256, 0, s>>>(a, n, nw);
+    else if (D == 2) digits2_k<<<dim3((uint32_t)wv_digit_blocks(n), T), DG, 0, s>>>(a, n, nw, zpre, ztot, T);
+    else if (D == 4) digits_k<4><<<dim3(g, T), 256, 0, s>>>(a, n, nw);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
