@@ -637,24 +637,28 @@ span_count_k(const uint8_t* __restrict__ image, SpanLevels a, uint32_t* __restri
     }
 }
 
+// Positions, counts and word indices of a level fit 32 bits (n < 2^32): the
+// per-word work is done in 32-bit arithmetic, widened only where a u64 entry
+// is stored.
 __global__ void __launch_bounds__(SD_T)
 span_write_k(uint8_t* __restrict__ image, SpanLevels a, const uint64_t* __restrict__ pre, uint32_t nchunks)
 {
     __shared__ uint32_t wpart[SD_T / 64];
-    __shared__ uint32_t zex[SD_W];   // zeros of the chunk before each of its words (up to the level's end)
+    __shared__ alignas(16) uint32_t zex[SD_W];   // zeros of the chunk before each of its words (up to the level's end)
     const uint32_t l = blockIdx.y;
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint64_t n = a.n[l], nw = wv_cdiv(n, 64), ns = wv_cdiv(n, WV_SB_BITS);
+    const uint32_t n = (uint32_t)a.n[l];
+    const uint32_t nw = (uint32_t)wv_cdiv(n, 64), ns = (uint32_t)wv_cdiv(n, WV_SB_BITS);
     const uint64_t* words = (const uint64_t*)(image + a.bits_off[l]);
     uint64_t* dir = (uint64_t*)(image + a.rank_off[l]);
     uint64_t* sel0 = (uint64_t*)(image + a.sel0_off[l]);
     uint64_t* sel1 = (uint64_t*)(image + a.sel1_off[l]);
     uint32_t* sub = (uint32_t*)(image + a.sub_off[l]);
-    const uint64_t nsub = a.nsub[l];
+    const uint32_t nsub = (uint32_t)a.nsub[l];
     constexpr uint32_t SM = WV_SUB_STRIDE - 1;
     // my two words of chunk c (16-byte aligned: the first is even)
     auto load2 = [&](uint32_t c, uint64_t& y0, uint64_t& y1) {
-        const uint64_t w = (uint64_t)c * SD_W + 2 * threadIdx.x;
+        const uint32_t w = c * SD_W + 2 * threadIdx.x;
         y0 = y1 = 0;
         if (w + 1 < nw) {
             const ulonglong2 v = *(const ulonglong2*)(words + w);
@@ -672,15 +676,13 @@ span_write_k(uint8_t* __restrict__ image, SpanLevels a, const uint64_t* __restri
         // this chunk's words were loaded one chunk ahead; load the next now
         const uint64_t x0 = nx0, x1 = nx1;
         if (gi + 1 < 4 && c + 1 < nchunks) load2(c + 1, nx0, nx1);
-        const uint64_t cw = (uint64_t)c * SD_W;
-        // counts inside the chunk fit 32 bits; the chunk's base counts are
-        // added where a global position is written
-        const uint64_t cbits = min(64 * cw, n);
-        const uint32_t nloc = (uint32_t)min<uint64_t>(n - cbits, 64ull * SD_W);   // level bits in the chunk
-        const uint64_t obase = pre[(uint64_t)c * a.nl + l];                       // ones before the chunk
-        const uint64_t zbase = cbits - obase;                                     // zeros before the chunk
-        const uint32_t wl = 2 * threadIdx.x;                                      // my first word, chunk-local
-        const uint64_t w0 = cw + wl;
+        const uint32_t cw = c * SD_W;
+        const uint32_t cbits = (uint32_t)min<uint64_t>(64ull * cw, n);
+        const uint32_t nloc = min(n - cbits, 64u * SD_W);                 // level bits in the chunk
+        const uint32_t obase = (uint32_t)pre[(uint64_t)c * a.nl + l];     // ones before the chunk
+        const uint32_t zbase = cbits - obase;                             // zeros before the chunk
+        const uint32_t wl = 2 * threadIdx.x;                              // my first word, chunk-local
+        const uint32_t w0 = cw + wl;
         const uint32_t o0 = __popcll(x0), o1 = __popcll(x1);
         // exclusive prefix of ones over the words of the chunk
         const uint32_t inc = wv_wave_incl_scan(o0 + o1);
@@ -697,23 +699,23 @@ span_write_k(uint8_t* __restrict__ image, SpanLevels a, const uint64_t* __restri
         // one / zero; a sub-sample, and a sample when 4096 divides the ordinal
         const uint64_t xs[2] = {x0, x1};
         const uint32_t os[2] = {o0, o1}, obs[2] = {ob0, ob1}, zbs[2] = {z0, z1};
-        const uint32_t obm = (uint32_t)(obase & SM), zbm = (uint32_t)(zbase & SM);
+        const uint32_t obm = obase & SM, zbm = zbase & SM;
         for (int q = 0; q < 2; q++) {
-            const uint64_t w = w0 + q;
+            const uint32_t w = w0 + q;
             if (w >= nw) break;
             const uint32_t d1 = (WV_SUB_STRIDE - ((obm + obs[q]) & SM)) & SM;
             if (d1 < os[q]) {
-                const uint64_t ord = obase + obs[q] + d1, p = 64 * w + wv_select_in_word(xs[q], d1);
-                sub[ord / WV_SUB_STRIDE] = (uint32_t)p;
+                const uint32_t ord = obase + obs[q] + d1, p = 64 * w + wv_select_in_word(xs[q], d1);
+                sub[ord / WV_SUB_STRIDE] = p;
                 if (ord % WV_SEL_STRIDE == 0) sel1[ord / WV_SEL_STRIDE] = p;
             }
             const uint32_t valid = min(64u, nloc - 64u * (wl + q));
-            const uint64_t vm = valid >= 64 ? ~0ull : ((1ull << valid) - 1ull);
             const uint32_t zc = valid - os[q];
             const uint32_t d0 = (WV_SUB_STRIDE - ((zbm + zbs[q]) & SM)) & SM;
             if (d0 < zc) {
-                const uint64_t ord = zbase + zbs[q] + d0, p = 64 * w + wv_select_in_word(~xs[q] & vm, d0);
-                sub[nsub - 1 - ord / WV_SUB_STRIDE] = (uint32_t)p;
+                const uint64_t vm = valid >= 64 ? ~0ull : ((1ull << valid) - 1ull);
+                const uint32_t ord = zbase + zbs[q] + d0, p = 64 * w + wv_select_in_word(~xs[q] & vm, d0);
+                sub[nsub - 1 - ord / WV_SUB_STRIDE] = p;
                 if (ord % WV_SEL_STRIDE == 0) sel0[ord / WV_SEL_STRIDE] = p;
             }
         }
@@ -721,12 +723,14 @@ span_write_k(uint8_t* __restrict__ image, SpanLevels a, const uint64_t* __restri
         // one thread per superblock of the chunk: zeros before it, and the
         // zeros before each of its words 1..7 relative to that (9 bits each)
         if (threadIdx.x < SD_W / 8) {
-            const uint64_t k = cw / 8 + threadIdx.x;
+            const uint32_t k = cw / 8 + threadIdx.x;
             if (k < ns) {
-                const uint32_t zb = zex[8 * threadIdx.x];
-                uint64_t blk = 0;
-                for (uint32_t q = 1; q < 8; q++) blk |= (uint64_t)(zex[8 * threadIdx.x + q] - zb) << (9 * (q - 1));
-                *(ulonglong2*)(dir + 2 * k) = make_ulonglong2(zbase + zb, blk);   // 16-byte aligned
+                const uint4 za = *(const uint4*)(zex + 8 * threadIdx.x), zb4 = *(const uint4*)(zex + 8 * threadIdx.x + 4);
+                const uint32_t zb = za.x;
+                const uint32_t lo = (za.y - zb) | ((za.z - zb) << 9) | ((za.w - zb) << 18);
+                const uint32_t hi = (zb4.x - zb) | ((zb4.y - zb) << 9) | ((zb4.z - zb) << 18);
+                const uint64_t blk = (uint64_t)lo | ((uint64_t)hi << 27) | ((uint64_t)(zb4.w - zb) << 54);
+                *(ulonglong2*)(dir + 2 * (uint64_t)k) = make_ulonglong2((uint64_t)(zbase + zb), blk);   // 16-byte aligned
             }
         }
         __syncthreads();   // wpart and zex are rewritten by the next chunk

@@ -7,6 +7,7 @@ eager work has overwritten the images and the workspace in between."""
 import numpy as np
 import pytest
 
+import dary
 from gpu_util import assert_same, oracle_image, to_device
 from paper_1610_03524_amd import binding as B
 
@@ -68,6 +69,9 @@ TREE_CASES = [
     ("4-ary", B.KIND_MULTIARY, 2, (1 << 19) + 5, 4096, np.uint16),
     ("16-ary", B.KIND_MULTIARY, 4, 100001, 70000, np.uint32),
     ("huffman", B.KIND_SHAPED, 0, 400009, 4096, np.uint16),
+    ("huffman, levels of 2^20 bits", B.KIND_SHAPED, 0, (1 << 21) + 9, 4096, np.uint16),
+    ("4-ary huffman", B.KIND_SHAPED, 2, 400009, 4096, np.uint16),
+    ("16-ary huffman", B.KIND_SHAPED, 4, 300007, 70000, np.uint32),
 ]
 
 
@@ -87,8 +91,12 @@ def test_tree_build_replayed_from_a_graph(name, kind, D, n, sigma, dt):
     codes = lens = counts = None
     if kind == B.KIND_SHAPED:
         counts = oracle.symbol_counts(S, sigma)
-        codes, lens = B.huffman_codes(counts)
-        want = oracle.build_image(oracle.KIND_SHAPED, S, sigma, codes=codes, lens=lens)
+        if D >= 2:   # d-ary Huffman codewords over D-bit digits
+            lens = dary.huffman_lengths(counts, D)
+            codes = dary.canonical(lens, D)
+        else:
+            codes, lens = B.huffman_codes(counts)
+        want = oracle.build_image(oracle.KIND_SHAPED, S, sigma, max(D, 1), codes=codes, lens=lens)
     else:
         want = oracle_image(kind, S, sigma, D)
     shape = B.make_shape(D, codes, lens, counts) if (D or codes is not None) else None
