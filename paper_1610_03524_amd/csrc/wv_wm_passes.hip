@@ -36,8 +36,16 @@
 
 namespace {
 
-// 16-bit keys in LDS: four workgroups per CU (8 waves per SIMD, 64 VGPRs);
-// 32-bit keys: LDS holds three workgroups per CU, so 6 waves per SIMD
+// 8- and 16-bit keys in LDS: four workgroups per CU (8 waves per SIMD, 64
+// VGPRs; byte keys need no scaling of their LDS index); 32-bit keys: LDS
+// holds three workgroups per CU, so 6 waves per SIMD
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8)))
+wm_pass8_k(PassArgs a)
+{
+    __shared__ PassShared<uint8_t> sh;
+    wm_pass_chunk<uint8_t>(a, blockIdx.x, sh);
+}
+
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8)))
 wm_pass16_k(PassArgs a)
 {
@@ -81,7 +89,8 @@ Geometry geometry(uint64_t n, uint32_t blocks, uint32_t tile, uint32_t L)
 
 void launch_pass(const PassArgs& a, hipStream_t s)
 {
-    if (a.R <= 16) wm_pass16_k<<<a.K, NT, 0, s>>>(a);
+    if (a.R <= 8) wm_pass8_k<<<a.K, NT, 0, s>>>(a);
+    else if (a.R <= 16) wm_pass16_k<<<a.K, NT, 0, s>>>(a);
     else wm_pass32_k<<<a.K, NT, 0, s>>>(a);
 }
 
