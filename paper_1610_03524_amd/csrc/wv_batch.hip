@@ -249,67 +249,59 @@ b_dir_scan_k(const SpanDesc* __restrict__ spans)
 __global__ void __launch_bounds__(256)
 b_dir_write_k(const SpanDesc* __restrict__ spans, const uint32_t* __restrict__ chunk0, uint32_t nspan)
 {
+    // counts and positions of a level fit 32 bits (n < 2^32)
     __shared__ uint32_t wpart[4];
-    __shared__ uint64_t zex[SDW];
+    __shared__ alignas(16) uint32_t zex[SDW];   // zeros of the chunk before each of its words
+    __shared__ uint64_t wds[SDW];               // the chunk's words
     const uint32_t s = owner_of(chunk0, nspan, blockIdx.x);
     const SpanDesc& d = spans[s];
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint64_t n = d.n, nw = wv_cdiv(n, 64), ns = wv_cdiv(n, WV_SB_BITS), nch = wv_cdiv(nw, SDW);
+    const uint32_t n = (uint32_t)d.n, nw = (uint32_t)wv_cdiv(n, 64), ns = (uint32_t)wv_cdiv(n, WV_SB_BITS);
+    const uint32_t nch = (uint32_t)wv_cdiv(nw, SDW);
     const uint64_t* words = (const uint64_t*)(d.image + d.bits_off);
     uint64_t* dir = (uint64_t*)(d.image + d.rank_off);
     uint64_t* sel0 = (uint64_t*)(d.image + d.sel0_off);
     uint64_t* sel1 = (uint64_t*)(d.image + d.sel1_off);
     uint32_t* sub = (uint32_t*)(d.image + d.sub_off);
-    const uint64_t c0 = (uint64_t)(blockIdx.x - d.chunk0) * SDG;
-    for (uint64_t c = c0; c < min(nch, c0 + SDG); c++) {   // uniform
-        const uint64_t cw = c * SDW, w0 = cw + 2 * threadIdx.x;
+    const uint32_t c0 = (blockIdx.x - d.chunk0) * SDG;
+    for (uint32_t c = c0; c < min(nch, c0 + SDG); c++) {   // uniform
+        const uint32_t cw = c * SDW, wl = 2 * threadIdx.x, w0 = cw + wl;
         const uint64_t x0 = w0 < nw ? words[w0] : 0ull, x1 = w0 + 1 < nw ? words[w0 + 1] : 0ull;
+        const uint32_t cbits = (uint32_t)min<uint64_t>(64ull * cw, n);
+        const uint32_t nloc = min(n - cbits, 64u * SDW);    // level bits in the chunk
+        const uint32_t obase = (uint32_t)d.pre[c];           // ones before the chunk
+        const uint32_t zbase = cbits - obase;
         const uint32_t o0 = __popcll(x0), o1 = __popcll(x1);
         uint32_t tot;
         const uint32_t ex = wave_excl_scan(o0 + o1, &tot);
         if (lane == 0) wpart[wave] = tot;
         __syncthreads();
-        uint32_t off = 0;
-        for (uint32_t k = 0; k < wave; k++) off += wpart[k];
-        const uint64_t ob0 = d.pre[c] + off + ex, ob1 = ob0 + o0;
-        const uint64_t z0 = min(64 * w0, n) - ob0, z1 = min(64 * (w0 + 1), n) - ob1;
-        zex[2 * threadIdx.x] = z0;
-        zex[2 * threadIdx.x + 1] = z1;
-        const uint64_t xs[2] = {x0, x1}, obs[2] = {ob0, ob1}, zbs[2] = {z0, z1};
-        const uint32_t os[2] = {o0, o1};
-        for (int qd = 0; qd < 2; qd++) {
-            const uint64_t w = w0 + qd;
-            if (w >= nw) break;
-            // ordinals 512k inside the word (at most one): sub-samples, and
-            // samples when 4096 divides them
-            const uint64_t t1 = wv_cdiv(obs[qd], WV_SUB_STRIDE) * WV_SUB_STRIDE;
-            if (t1 < obs[qd] + os[qd]) {
-                const uint64_t p = 64 * w + wv_select_in_word(xs[qd], (uint32_t)(t1 - obs[qd]));
-                sub[t1 / WV_SUB_STRIDE] = (uint32_t)p;
-                if (t1 % WV_SEL_STRIDE == 0) sel1[t1 / WV_SEL_STRIDE] = p;
-            }
-            const uint64_t valid = min((uint64_t)64, n - 64 * w);
-            const uint64_t vm = valid >= 64 ? ~0ull : ((1ull << valid) - 1ull);
-            const uint32_t zc = (uint32_t)valid - os[qd];
-            const uint64_t t0 = wv_cdiv(zbs[qd], WV_SUB_STRIDE) * WV_SUB_STRIDE;
-            if (t0 < zbs[qd] + zc) {
-                const uint64_t p = 64 * w + wv_select_in_word(~xs[qd] & vm, (uint32_t)(t0 - zbs[qd]));
-                sub[d.nsub - 1 - t0 / WV_SUB_STRIDE] = (uint32_t)p;
-                if (t0 % WV_SEL_STRIDE == 0) sel0[t0 / WV_SEL_STRIDE] = p;
-            }
+        uint32_t off = 0, ones = 0;
+        for (uint32_t k = 0; k < 4; k++) {
+            if (k < wave) off += wpart[k];
+            ones += wpart[k];
         }
+        const uint32_t ob0 = off + ex, ob1 = ob0 + o0;     // ones of the chunk before my words
+        zex[wl] = min(64u * wl, nloc) - ob0;
+        zex[wl + 1] = min(64u * (wl + 1), nloc) - ob1;
+        wds[wl] = x0;
+        wds[wl + 1] = x1;
         __syncthreads();
+        // the ones / zeros of ordinal 512k in the chunk: sub-samples, and
+        // samples when 4096 divides them
+        wv_chunk_samples(wds, zex, min(SDW, nw - cw), nloc, cw, obase, zbase, ones, sub, (uint32_t)d.nsub, sel0, sel1);
         if (threadIdx.x < SDW / 8) {
-            const uint64_t k = cw / 8 + threadIdx.x;
+            const uint32_t k = cw / 8 + threadIdx.x;
             if (k < ns) {
-                const uint64_t zb = zex[8 * threadIdx.x];
-                uint64_t blk = 0;
-                for (uint32_t qd = 1; qd < 8; qd++) blk |= (zex[8 * threadIdx.x + qd] - zb) << (9 * (qd - 1));
-                dir[2 * k] = zb;
-                dir[2 * k + 1] = blk;
+                const uint4 za = *(const uint4*)(zex + 8 * threadIdx.x), zb4 = *(const uint4*)(zex + 8 * threadIdx.x + 4);
+                const uint32_t zb = za.x;
+                const uint32_t lo = (za.y - zb) | ((za.z - zb) << 9) | ((za.w - zb) << 18);
+                const uint32_t hi = (zb4.x - zb) | ((zb4.y - zb) << 9) | ((zb4.z - zb) << 18);
+                dir[2 * (uint64_t)k] = zbase + zb;
+                dir[2 * (uint64_t)k + 1] = (uint64_t)lo | ((uint64_t)hi << 27) | ((uint64_t)(zb4.w - zb) << 54);
             }
         }
-        __syncthreads();   // zex and wpart are rewritten by the next chunk
+        __syncthreads();   // zex, wds and wpart are rewritten by the next chunk
     }
 }
 

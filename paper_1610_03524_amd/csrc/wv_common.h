@@ -268,6 +268,42 @@ __device__ inline uint64_t wv_select_dir(const uint64_t* __restrict__ words, con
     return k * WV_SB_BITS + 64u * qw + wv_select_in_word(w, (uint32_t)(r - cq));
 }
 
+// The select samples inside one chunk of nwl words (at most 64 ones and 64
+// zeros of ordinal 512k, as a chunk holds 32768 bits), after zex (zeros
+// before each word of the chunk) and wds (its words) are in LDS: thread k <
+// 128 takes the k-th one of ordinal 512k' in the chunk, thread 128 + k the
+// k-th zero; a binary search of zex gives its word, a select inside the word
+// its position.  One select per sample instead of a test in every word.
+__device__ inline void wv_chunk_samples(const uint64_t* wds, const uint32_t* zex, uint32_t nwl, uint32_t nloc,
+                                     uint32_t cw, uint32_t obase, uint32_t zbase, uint32_t ones, uint32_t* sub,
+                                     uint32_t nsub, uint64_t* sel0, uint64_t* sel1)
+{
+    const uint32_t t = threadIdx.x, b = t < 128 ? 1u : 0u, k = t & 127;
+    const uint32_t base = b ? obase : zbase, cnt = b ? ones : nloc - ones;
+    const uint32_t first = (uint32_t)(wv_cdiv((uint64_t)base, WV_SUB_STRIDE) * WV_SUB_STRIDE - base);   // chunk-local ordinal
+    const uint32_t r = first + k * WV_SUB_STRIDE;
+    if (r >= cnt || k >= 64) return;
+    // b-bits before word w of the chunk
+    auto before = [&](uint32_t w) -> uint32_t { return b ? min(64u * w, nloc) - zex[w] : zex[w]; };
+    uint32_t lo = 0, hi = nwl - 1;   // the last word with at most r b-bits before it
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (before(mid) <= r) lo = mid; else hi = mid - 1;
+    }
+    const uint32_t valid = min(64u, nloc - 64u * lo);
+    const uint64_t vm = valid >= 64 ? ~0ull : ((1ull << valid) - 1ull);
+    const uint64_t x = b ? wds[lo] : (~wds[lo] & vm);
+    const uint32_t p = 64 * (cw + lo) + wv_select_in_word(x, r - before(lo));
+    const uint32_t ord = base + r;
+    if (b) {
+        sub[ord / WV_SUB_STRIDE] = p;
+        if (ord % WV_SEL_STRIDE == 0) sel1[ord / WV_SEL_STRIDE] = p;
+    } else {
+        sub[nsub - 1 - ord / WV_SUB_STRIDE] = p;
+        if (ord % WV_SEL_STRIDE == 0) sel0[ord / WV_SEL_STRIDE] = p;
+    }
+}
+
 // A binary level whose explicit answers are written by wv_xsel_block: the
 // image, the level's length and array offsets, and the first workgroup of
 // the level in the launch (2 * nslot workgroups per level).

@@ -645,6 +645,7 @@ span_write_k(uint8_t* __restrict__ image, SpanLevels a, const uint64_t* __restri
 {
     __shared__ uint32_t wpart[SD_T / 64];
     __shared__ alignas(16) uint32_t zex[SD_W];   // zeros of the chunk before each of its words (up to the level's end)
+    __shared__ uint64_t wds[SD_W];               // the chunk's words
     const uint32_t l = blockIdx.y;
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t n = (uint32_t)a.n[l];
@@ -655,7 +656,6 @@ span_write_k(uint8_t* __restrict__ image, SpanLevels a, const uint64_t* __restri
     uint64_t* sel1 = (uint64_t*)(image + a.sel1_off[l]);
     uint32_t* sub = (uint32_t*)(image + a.sub_off[l]);
     const uint32_t nsub = (uint32_t)a.nsub[l];
-    constexpr uint32_t SM = WV_SUB_STRIDE - 1;
     // my two words of chunk c (16-byte aligned: the first is even)
     auto load2 = [&](uint32_t c, uint64_t& y0, uint64_t& y1) {
         const uint32_t w = c * SD_W + 2 * threadIdx.x;
@@ -682,44 +682,27 @@ span_write_k(uint8_t* __restrict__ image, SpanLevels a, const uint64_t* __restri
         const uint32_t obase = (uint32_t)pre[(uint64_t)c * a.nl + l];     // ones before the chunk
         const uint32_t zbase = cbits - obase;                             // zeros before the chunk
         const uint32_t wl = 2 * threadIdx.x;                              // my first word, chunk-local
-        const uint32_t w0 = cw + wl;
         const uint32_t o0 = __popcll(x0), o1 = __popcll(x1);
         // exclusive prefix of ones over the words of the chunk
         const uint32_t inc = wv_wave_incl_scan(o0 + o1);
         if (lane == 63) wpart[wave] = inc;
         __syncthreads();
-        uint32_t off = 0;
-        for (uint32_t k = 0; k < wave; k++) off += wpart[k];
+        uint32_t off = 0, ones = 0;
+        for (uint32_t k = 0; k < SD_T / 64; k++) {
+            if (k < wave) off += wpart[k];
+            ones += wpart[k];
+        }
         const uint32_t ob0 = off + inc - (o0 + o1), ob1 = ob0 + o0;   // ones before my words
         const uint32_t z0 = min(64u * wl, nloc) - ob0, z1 = min(64u * (wl + 1), nloc) - ob1;
         zex[wl] = z0;
         zex[wl + 1] = z1;
-        // sampled select: the one / zero of ordinal 512k inside one of my
-        // words (a word holds at most one) lies `dist` after the word's first
-        // one / zero; a sub-sample, and a sample when 4096 divides the ordinal
-        const uint64_t xs[2] = {x0, x1};
-        const uint32_t os[2] = {o0, o1}, obs[2] = {ob0, ob1}, zbs[2] = {z0, z1};
-        const uint32_t obm = obase & SM, zbm = zbase & SM;
-        for (int q = 0; q < 2; q++) {
-            const uint32_t w = w0 + q;
-            if (w >= nw) break;
-            const uint32_t d1 = (WV_SUB_STRIDE - ((obm + obs[q]) & SM)) & SM;
-            if (d1 < os[q]) {
-                const uint32_t ord = obase + obs[q] + d1, p = 64 * w + wv_select_in_word(xs[q], d1);
-                sub[ord / WV_SUB_STRIDE] = p;
-                if (ord % WV_SEL_STRIDE == 0) sel1[ord / WV_SEL_STRIDE] = p;
-            }
-            const uint32_t valid = min(64u, nloc - 64u * (wl + q));
-            const uint32_t zc = valid - os[q];
-            const uint32_t d0 = (WV_SUB_STRIDE - ((zbm + zbs[q]) & SM)) & SM;
-            if (d0 < zc) {
-                const uint64_t vm = valid >= 64 ? ~0ull : ((1ull << valid) - 1ull);
-                const uint32_t ord = zbase + zbs[q] + d0, p = 64 * w + wv_select_in_word(~xs[q] & vm, d0);
-                sub[nsub - 1 - ord / WV_SUB_STRIDE] = p;
-                if (ord % WV_SEL_STRIDE == 0) sel0[ord / WV_SEL_STRIDE] = p;
-            }
-        }
+        wds[wl] = x0;
+        wds[wl + 1] = x1;
         __syncthreads();
+        // sampled select: the ones / zeros of ordinal 512k in the chunk (a
+        // sub-sample each, a sample when 4096 divides the ordinal)
+        wv_chunk_samples(wds, zex, (uint32_t)min<uint64_t>(SD_W, nw - cw), nloc, cw, obase, zbase, ones, sub, nsub,
+                      sel0, sel1);
         // one thread per superblock of the chunk: zeros before it, and the
         // zeros before each of its words 1..7 relative to that (9 bits each)
         if (threadIdx.x < SD_W / 8) {
