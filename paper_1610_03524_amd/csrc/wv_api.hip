@@ -56,6 +56,8 @@ struct Plan {
     uint64_t ws_tkeys = 0, ws_tmp = 0, tmp_stride = 0, ws_segs = 0, seg_bound = 0, tile_bound = 0;
     uint64_t ws_tmpimg = 0, ws_digits = 0, dstride = 0;   // multiary: matrix image, digit strings
     wv_layout_out tlay{};
+    uint64_t ws_timgb = 0;     // split shaped trees over digits: the image of matrix B
+    wv_layout_out tlayb{};
     // shaped trees split at level h1: matrix A over the top h1 bits of every
     // codeword (p.wm), matrix B over the whole codewords of the nlong symbols
     // whose codes are longer than h1 (wmb)
@@ -260,26 +262,61 @@ int make_plan_impl(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, con
         p.from_matrix = wv_wm_make_plan(n, sig_k, sb_k, tune, p.wm) == WT_OK && p.wm.enabled &&
                         p.wm.L == p.key_bits;
     }
+    if (p.from_matrix && multi && kind == WT_KIND_SHAPED && p.key_bits > WV_SPLIT_BITS) {
+        // as for binary codewords: when codewords longer than WV_SPLIT_BITS
+        // bits are rare, matrix A takes the top WV_SPLIT_BITS bits of every
+        // padded codeword (16-bit keys, fewer passes) and matrix B the whole
+        // codewords of the long-code symbols alone (WV_SPLIT_BITS is a
+        // multiple of D = 2, 4: the split falls between digit levels)
+        uint64_t nlong = 0;
+        for (uint32_t x = 0; x < sigma; x++)
+            if (shape->code_len[x] * p.D > WV_SPLIT_BITS) nlong += shape->counts[x];
+        wv_wm_plan a{}, b{};
+        if (nlong * WV_SPLIT_SHARE <= n && wv_wm_make_plan(n, 1u << WV_SPLIT_BITS, 2, tune, a) == WT_OK && a.enabled &&
+            (!nlong || (wv_wm_make_plan(nlong, 1u << p.key_bits, 4, tune, b) == WT_OK && b.enabled))) {
+            p.h1 = WV_SPLIT_BITS;
+            p.nlong = nlong;
+            p.wm = a;
+            p.wmb = b;
+        }
+    }
     if (p.from_matrix && multi) {
         // digit levels (multiary trees, shaped trees over D-bit digits): the
         // matrix levels in a workspace image, then the digit strings
         p.tau = p.wm.tau;
         p.ws_wm = bump(off, p.wm.ws_bytes);
-        wv_layout_in tl{};
-        tl.kind = WT_KIND_WM;
-        tl.arity_log2 = 1;
-        tl.nlevels = p.key_bits;
-        tl.key_bits = p.key_bits;
-        tl.sigma = sigma;
-        tl.n = n;
-        for (uint32_t l = 0; l < p.key_bits; l++) tl.level_n[l] = n;
-        wv_layout(tl, p.tlay);
+        auto matrix_layout = [&](uint64_t m, uint32_t levels, wv_layout_out& out) {
+            wv_layout_in tl{};
+            tl.kind = WT_KIND_WM;
+            tl.arity_log2 = 1;
+            tl.nlevels = levels;
+            tl.key_bits = levels;
+            tl.sigma = sigma;
+            tl.n = m;
+            for (uint32_t l = 0; l < levels; l++) tl.level_n[l] = m;
+            wv_layout(tl, out);
+        };
+        matrix_layout(n, p.h1 ? p.h1 : p.key_bits, p.tlay);
         p.ws_tmpimg = bump(off, p.tlay.image_bytes);
         p.dstride = wv_round256((wv_cdiv(n * p.D, 64) + 1) * 8);   // one readable word past each string
         p.ws_digits = bump(off, p.dstride * p.nlevels);
+        if (p.h1) {
+            // 16-bit keys of every symbol, whole codewords of the long ones
+            p.ws_tkeys = bump(off, n * 2);
+            p.nkblocks = wv_tree_key_blocks(n);
+            p.ws_bcnt = bump(off, p.nkblocks * 4);
+            p.ws_boff = bump(off, p.nkblocks * 8 + 8);
+            p.ws_bpart = bump(off, 8 * wv_scan_partials(p.nkblocks, 1) + 8);
+            if (p.nlong) {
+                p.ws_wmb = bump(off, p.wmb.ws_bytes);
+                matrix_layout(p.nlong, p.key_bits, p.tlayb);
+                p.ws_timgb = bump(off, p.tlayb.image_bytes);
+                p.ws_lkeys = bump(off, p.nlong * 4);
+            }
+        }
         if (kind == WT_KIND_SHAPED) {
             // padded codeword keys; runs from the shape's counts on the host
-            p.ws_tkeys = bump(off, n * 4);
+            if (!p.h1) p.ws_tkeys = bump(off, n * 4);
             p.seg_bound = p.nnodes_image;
             p.tile_bound = wv_tree_tile_bound(n, p.D, p.nlevels);
             p.ws_segs = bump(off, seg_bytes(p.seg_bound, p.tile_bound));
@@ -441,6 +478,9 @@ int make_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, const wt
     if (m.enabled)
         wv_trace("  passes: tau=%u passes=%u chunks K=%u of C=%u keys (%u tiles) workspace=%llu", m.tau,
                  (m.L + m.tau - 1) / m.tau, m.K, m.C, m.C / 8192u, (unsigned long long)p.ws_bytes);
+    if (p.h1)
+        wv_trace("  split at %u key bits: matrix A over every symbol's top bits, matrix B over the %llu "
+                 "symbols with longer codes (tau=%u)", p.h1, (unsigned long long)p.nlong, p.wmb.tau);
     else
         wv_trace("  workspace=%llu", (unsigned long long)p.ws_bytes);
     for (uint32_t l = 0; l < p.nlevels; l++) {
@@ -863,39 +903,69 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
     if (digits) {
         // the matrix levels in the workspace, then the digits: 2-bit digits
         // need only the zeros before every 256-word block of the levels 2t,
-        // 16-ary digits query the matrix's rank directories
-        uint8_t* timg = at<uint8_t>(ws, p.ws_tmpimg);
-        const uint64_t *zpre = nullptr, *ztot = nullptr;
-        if (D == 4) {
-            wv_dir_scratch unused{};
-            WV_CHECK(wv_wm_run(p.wm, keys, timg, p.tlay, at<uint8_t>(ws, p.ws_wm), unused, s));
-        } else {
+        // 16-ary digits query the matrix's rank directories.  A split shaped
+        // tree takes digit levels t < TA from matrix A (n symbols) and the
+        // others from matrix B (the long-code symbols), built on the side
+        // stream meanwhile.
+        const uint32_t TA = p.h1 ? p.h1 / D : T;
+        auto run_matrix = [&](const wv_wm_plan& wp, const void* in, uint8_t* mimg, const wv_layout_out& lay,
+                              uint32_t levels, uint8_t* mws, hipStream_t st) -> hipError_t {
+            if (D == 4) {
+                wv_dir_scratch unused{};
+                return wv_wm_run(wp, in, mimg, lay, mws, unused, st);
+            }
             uint64_t* lw[WV_MAX_LEVELS];
-            for (uint32_t l = 0; l < K; l++) lw[l] = (uint64_t*)(timg + p.tlay.lv[l].bits_off);
-            WV_CHECK(wv_wm_levels(p.wm, keys, lw, nullptr, at<uint8_t>(ws, p.ws_wm), s));
+            for (uint32_t l = 0; l < levels; l++) lw[l] = (uint64_t*)(mimg + lay.lv[l].bits_off);
+            return wv_wm_levels(wp, in, lw, nullptr, mws, st);
+        };
+        auto digit_strings = [&](const uint8_t* mimg, const wv_layout_out& lay, uint64_t m, uint32_t t0,
+                                 uint32_t nt) -> hipError_t {
+            const uint64_t *zpre = nullptr, *ztot = nullptr;
             if (D == 2) {
                 // scratch of the digit counters, not used before the gather
                 wv_digit_words dw{};
-                for (uint32_t t = 0; t < T; t++) dw.w[t] = lw[2 * t];
+                for (uint32_t t = 0; t < nt; t++) dw.w[t] = (const uint64_t*)(mimg + lay.lv[2 * (t0 + t)].bits_off);
                 uint32_t* cnt = at<uint32_t>(ws, p.ws_sb_ones);
                 uint64_t* pre = at<uint64_t>(ws, p.ws_sb_pre);
                 uint64_t* tot = at<uint64_t>(ws, p.ws_mtot);
-                WV_TIMED(prof, s, "tree_digits", WV_CHECK(wv_digit_zero_counts(dw, n, T, cnt, s)));
-                WV_TIMED(prof, s, "tree_digits",
-                         WV_CHECK(wv_scan_u32(cnt, pre, wv_digit_blocks(n), T, at<uint64_t>(ws, p.ws_partial), tot, s)));
+                hipError_t e = wv_digit_zero_counts(dw, m, nt, cnt, s);
+                if (e == hipSuccess) e = wv_scan_u32(cnt, pre, wv_digit_blocks(m), nt, at<uint64_t>(ws, p.ws_partial), tot, s);
+                if (e != hipSuccess) return e;
                 zpre = pre;
                 ztot = tot;
             }
-        }
-        wv_digit_set ds{};
-        for (uint32_t t = 0; t < T; t++) {
-            for (uint32_t k = 0; k < D; k++) {
-                ds.lv[t].words[k] = (const uint64_t*)(timg + p.tlay.lv[t * D + k].bits_off);
-                ds.lv[t].dir[k] = (const uint64_t*)(timg + p.tlay.lv[t * D + k].rank_off);
+            wv_digit_set ds{};
+            for (uint32_t t = 0; t < nt; t++) {
+                for (uint32_t k = 0; k < D; k++) {
+                    ds.lv[t].words[k] = (const uint64_t*)(mimg + lay.lv[(t0 + t) * D + k].bits_off);
+                    ds.lv[t].dir[k] = (const uint64_t*)(mimg + lay.lv[(t0 + t) * D + k].rank_off);
+                }
+                ds.out[t] = at<uint64_t>(ws, p.ws_digits + (t0 + t) * p.dstride);
             }
-            ds.out[t] = at<uint64_t>(ws, p.ws_digits + t * p.dstride);
+            return wv_tree_digits(ds, nt, m, D, zpre, ztot, s);
+        };
+        uint8_t* timg = at<uint8_t>(ws, p.ws_tmpimg);
+        hipStream_t s2 = nullptr;
+        if (p.h1 && p.nlong) {
+            // matrix B on the side stream, forked after the keys
+            s2 = wv_side_stream();
+            if (!s2) return WT_EHIP;
+            wv_wm_plan pb = p.wmb;
+            pb.profile = false;
+            WV_CHECK(hipEventRecord(fork.e[0], s));
+            WV_CHECK(hipStreamWaitEvent(s2, fork.e[0], 0));
+            WV_TIMED(prof, s2, "side_matrix",
+                     WV_CHECK(run_matrix(pb, at<void>(ws, p.ws_lkeys), at<uint8_t>(ws, p.ws_timgb), p.tlayb, K,
+                                         at<uint8_t>(ws, p.ws_wmb), s2)));
+            WV_CHECK(hipEventRecord(fork.e[1], s2));
         }
-        WV_TIMED(prof, s, "tree_digits", WV_CHECK(wv_tree_digits(ds, T, n, D, zpre, ztot, s)));
+        WV_CHECK(run_matrix(p.wm, keys, timg, p.tlay, p.h1 ? p.h1 : K, at<uint8_t>(ws, p.ws_wm), s));
+        WV_TIMED(prof, s, "tree_digits", WV_CHECK(digit_strings(timg, p.tlay, n, 0, TA)));
+        if (s2) {
+            WV_CHECK(hipStreamWaitEvent(s, fork.e[1], 0));
+            WV_TIMED(prof, s, "tree_digits",
+                     WV_CHECK(digit_strings(at<uint8_t>(ws, p.ws_timgb), p.tlayb, p.nlong, TA, T - TA)));
+        }
     } else if (p.h1) {
         // S itself was validated above; the keys need no check
         // the big matrix first, then the small matrix of the long codes on a

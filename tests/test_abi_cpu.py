@@ -322,3 +322,30 @@ def test_plan_of_shaped_multiary_trees(D):
     none = lens.copy()
     none[int(np.flatnonzero(counts)[0])] = 0
     assert verdict(codes, none) == B.WT_ERANGE
+
+
+def test_shaped_digit_trees_plan_their_path():
+    """shaped trees over 2- and 4-bit digits are planned as matrix passes over
+    padded codewords, split at 16 key bits when longer codewords are rare;
+    3-bit digits level by level (WT_TRACE shows the plan)"""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, 'tests')\n"
+            "import numpy as np, dary\n"
+            "from paper_1610_03524_amd import binding as B\n"
+            "for D, sigma in [(2, 4096), (4, 300), (3, 300)]:\n"
+            "    rng = np.random.default_rng(7 * D + sigma)\n"
+            "    S = np.minimum(rng.geometric(0.01, 200003) - 1, sigma - 1)\n"
+            "    counts = np.bincount(S, minlength=sigma).astype(np.uint64)\n"
+            "    lens = dary.huffman_lengths(counts, D)\n"
+            "    B.plan(B.KIND_SHAPED, S.size, sigma, 2, B.make_shape(D, dary.canonical(lens, D), lens, counts))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, WT_TRACE="1")
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    plans = [l for l in r.stderr.splitlines() if l.startswith("[wt] plan shaped")]
+    assert len(plans) == 3, r.stderr
+    assert "path=matrix passes" in plans[0] and "path=matrix passes" in plans[1], plans
+    assert "path=level by level" in plans[2], plans
+    split = [l for l in r.stderr.splitlines() if "split at 16 key bits" in l]
+    assert len(split) == 1, r.stderr   # the 4-ary code of sigma 4096 is longer than 16 bits, rarely
