@@ -171,10 +171,12 @@ typedef struct wt_plan_info {
     uint64_t out_bytes;        /* size of the canonical image              */
     uint64_t workspace_bytes;  /* device scratch the build needs           */
     uint64_t level_n[32];      /* bits / digits per level                  */
-    /* shaped trees built from two matrices: the levels above split_bits from
-     * a matrix over the top split_bits bits of every codeword, the deeper
-     * levels from a matrix over the split_long symbols with longer codes
-     * (chosen when those are at most 1/8 of S); 0, 0: one matrix or none  */
+    /* shaped trees built from two matrices: the levels above split_bits
+     * (key bits; for codewords of D-bit digits the digit levels above
+     * split_bits / D) from a matrix over the top split_bits bits of every
+     * padded codeword, the deeper levels from a matrix over the split_long
+     * symbols with longer codes (chosen when those are at most 1/8 of S);
+     * 0, 0: one matrix or none                                            */
     uint32_t split_bits, reserved0;
     uint64_t split_long;
 } wt_plan_info;

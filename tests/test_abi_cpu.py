@@ -349,3 +349,20 @@ def test_shaped_digit_trees_plan_their_path():
     assert "path=level by level" in plans[2], plans
     split = [l for l in r.stderr.splitlines() if "split at 16 key bits" in l]
     assert len(split) == 1, r.stderr   # the 4-ary code of sigma 4096 is longer than 16 bits, rarely
+
+
+def test_plan_reports_the_split_of_shaped_digit_trees():
+    """wt_plan_info.split_bits / split_long: 16 key bits and the long-code
+    symbols for a 4-ary Huffman shape whose long codewords are rare"""
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import dary
+    rng = np.random.default_rng(11)
+    sigma = 4096
+    S = np.minimum(rng.geometric(0.01, 200003) - 1, sigma - 1)
+    counts = np.bincount(S, minlength=sigma).astype(np.uint64)
+    lens = dary.huffman_lengths(counts, 2)
+    info = B.plan(B.KIND_SHAPED, S.size, sigma, 2, B.make_shape(2, dary.canonical(lens, 2), lens, counts))
+    assert info.key_bits == 2 * int(lens.max()) > 16
+    assert info.split_bits == 16
+    assert info.split_long == int(counts[lens > 8].sum()) > 0
