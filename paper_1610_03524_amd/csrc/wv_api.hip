@@ -64,6 +64,7 @@ struct Plan {
     uint32_t h1 = 0;
     uint64_t nlong = 0, ws_lkeys = 0, ws_btmp = 0, btmp_stride = 0, ws_wmb = 0;
     uint64_t ws_bcnt = 0, ws_boff = 0, ws_bpart = 0, nkblocks = 0, ws_sdir = 0, ws_ktab = 0;   // ws_sdir: directory scratch, all levels
+    uint64_t ws_lmask = 0;     // long-code marks of the split key kernel
     wv_wm_plan wmb{};
     // balanced trees of at most 8 key bits built in one pass straight into
     // tree order (domain decomposition), no matrix levels in between
@@ -307,6 +308,7 @@ int make_plan_impl(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, con
             p.ws_bcnt = bump(off, p.nkblocks * 4);
             p.ws_boff = bump(off, p.nkblocks * 8 + 8);
             p.ws_bpart = bump(off, 8 * wv_scan_partials(p.nkblocks, 1) + 8);
+            p.ws_lmask = bump(off, wv_tree_lmask_bytes(n, sym_bytes));
             if (p.nlong) {
                 p.ws_wmb = bump(off, p.wmb.ws_bytes);
                 matrix_layout(p.nlong, p.key_bits, p.tlayb);
@@ -370,6 +372,7 @@ int make_plan_impl(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes, con
         p.ws_bcnt = bump(off, p.nkblocks * 4);
         p.ws_boff = bump(off, p.nkblocks * 8 + 8);
         p.ws_bpart = bump(off, 8 * wv_scan_partials(p.nkblocks, 1) + 8);
+        p.ws_lmask = bump(off, wv_tree_lmask_bytes(n, sym_bytes));
         if (p.nlong) {
             p.ws_wmb = bump(off, p.wmb.ws_bytes);
             p.btmp_stride = wv_round256(wv_bits_bytes(p.nlong) + 8);
@@ -886,12 +889,12 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
             uint64_t* boff = at<uint64_t>(ws, p.ws_boff);
             WV_TIMED(prof, s, "tree_keys",
                      WV_CHECK(wv_tree_keys_split(S, n, p.sym_bytes, sigma, dk, at<uint16_t>(ws, p.ws_tkeys),
-                                                 at<uint32_t>(ws, p.ws_bcnt), s)));
+                                                 at<uint32_t>(ws, p.ws_bcnt), at<uint16_t>(ws, p.ws_lmask), s)));
             WV_TIMED(prof, s, "tree_keys",
                      WV_CHECK(wv_scan_u32(at<uint32_t>(ws, p.ws_bcnt), boff, p.nkblocks, 1, at<uint64_t>(ws, p.ws_bpart),
                                           boff + p.nkblocks, s)));
             WV_TIMED(prof, s, "tree_keys",
-                     WV_CHECK(wv_tree_long_keys(S, n, p.sym_bytes, sigma, dk, dc, dl, K, boff,
+                     WV_CHECK(wv_tree_long_keys(S, n, p.sym_bytes, dc, dl, K, boff, at<uint16_t>(ws, p.ws_lmask),
                                                 at<uint32_t>(ws, p.ws_lkeys), p.nlong, s)));
         } else {
             WV_TIMED(prof, s, "tree_keys",

@@ -85,15 +85,18 @@ void wv_split_table(const uint32_t* codes, const uint32_t* lens, uint32_t sigma,
 // keys[i] = the low 16 bits of ktab[S[i]] (0 for S[i] >= sigma); bcnt[b] =
 // symbols of block b whose code is longer than h1
 hipError_t wv_tree_keys_split(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma, const uint32_t* ktab,
-                              uint16_t* keys, uint32_t* bcnt, hipStream_t s);
+                              uint16_t* keys, uint32_t* bcnt, uint16_t* lmask, hipStream_t s);
+// bytes of the long-code marks the split key kernel leaves for the long keys
+uint64_t wv_tree_lmask_bytes(uint64_t n, uint32_t sym_bytes);
 
 // lkeys[r] = padded codeword (codes[x] << (h - lens[x])) of the r-th symbol,
-// in input order, whose code is longer than h1; boff = exclusive prefix of
-// bcnt.  Ranks >= nlong are not written (a sequence whose counts differ from
-// the shape is rejected later).
-hipError_t wv_tree_long_keys(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma, const uint32_t* ktab,
-                             const uint32_t* codes, const uint32_t* lens, uint32_t h, const uint64_t* boff,
-                             uint32_t* lkeys, uint64_t nlong, hipStream_t s);
+// in input order, whose code is longer than h1, found from the marks the
+// split key kernel left in lmask (S is read only at marked positions); boff
+// = exclusive prefix of bcnt.  Ranks >= nlong are not written (a sequence
+// whose counts differ from the shape is rejected later).
+hipError_t wv_tree_long_keys(const void* S, uint64_t n, uint32_t sym_bytes, const uint32_t* codes, const uint32_t* lens,
+                             uint32_t h, const uint64_t* boff, const uint16_t* lmask, uint32_t* lkeys, uint64_t nlong,
+                             hipStream_t s);
 
 // matrix levels bD .. bD+D-1 (words and rank directories) of one multiary level
 struct wv_digit_levels {

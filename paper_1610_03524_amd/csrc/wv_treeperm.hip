@@ -117,7 +117,8 @@ tree_keys_k(const T* __restrict__ S, uint64_t n, uint32_t sigma, const uint32_t*
 template <typename T>
 __global__ void __launch_bounds__(KB_T)
 tree_keys_split_k(const T* __restrict__ S, uint64_t n, uint32_t sigma, const uint32_t* __restrict__ ktab,
-                  uint16_t* __restrict__ keys, uint32_t* __restrict__ bcnt, uint64_t nblocks)
+                  uint16_t* __restrict__ keys, uint32_t* __restrict__ bcnt, uint16_t* __restrict__ lmask,
+                  uint64_t nblocks)
 {
     constexpr uint32_t V = SymVec<T>::V, ROWS = KB / (KB_T * V);
     __shared__ uint32_t tab_s[KTAB_LDS];
@@ -134,13 +135,16 @@ tree_keys_split_k(const T* __restrict__ S, uint64_t n, uint32_t sigma, const uin
         for (uint32_t r = 0; r < ROWS; r++) {
             const uint64_t i0 = b0 + (r * KB_T + threadIdx.x) * V;
             uint16_t kk[V];
+            uint32_t m = 0;   // bit k: symbol k of the thread's row piece has a long code
 #pragma unroll
             for (uint32_t k = 0; k < V; k++) {
                 const uint32_t x = (uint32_t)sv[r].v[k];
                 const uint32_t t = i0 + k < n && x < sigma ? tab[x] : 0u;
                 kk[k] = (uint16_t)t;
                 c += t >> 16;
+                m |= (t >> 16) << k;
             }
+            lmask[(blk * ROWS + r) * KB_T + threadIdx.x] = (uint16_t)m;
             if (vec) {
                 // V 16-bit keys: 32 bytes (8-bit symbols), 16 (16-bit) or 8 (32-bit)
                 if constexpr (V >= 8) {
@@ -175,35 +179,23 @@ tree_keys_split_k(const T* __restrict__ S, uint64_t n, uint32_t sigma, const uin
 
 template <typename T>
 __global__ void __launch_bounds__(KB_T)
-tree_long_keys_k(const T* __restrict__ S, uint64_t n, uint32_t sigma, const uint32_t* __restrict__ ktab,
-                 const uint32_t* __restrict__ codes, const uint32_t* __restrict__ lens, uint32_t h,
-                 const uint64_t* __restrict__ boff, uint32_t* __restrict__ lkeys, uint64_t nlong, uint64_t nblocks)
+tree_long_keys_k(const T* __restrict__ S, uint64_t n, const uint32_t* __restrict__ codes,
+                 const uint32_t* __restrict__ lens, uint32_t h, const uint64_t* __restrict__ boff,
+                 const uint16_t* __restrict__ lmask, uint32_t* __restrict__ lkeys, uint64_t nlong, uint64_t nblocks)
 {
     constexpr uint32_t V = SymVec<T>::V, ROWS = KB / (KB_T * V);
-    __shared__ uint32_t tab_s[KTAB_LDS];
     __shared__ uint32_t wsum[ROWS][KB_T / 64];
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint32_t* tab = stage_table(ktab, sigma, tab_s);
     for (uint64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
         const uint64_t b0 = blk * KB;
-        const bool vec = (((uintptr_t)S & 15u) == 0) && b0 + KB <= n;
-        SymVec<T> sv[ROWS];
-#pragma unroll
-        for (uint32_t r = 0; r < ROWS; r++) load_syms(S, b0 + (r * KB_T + threadIdx.x) * V, n, vec, sv[r]);
-        // long symbols per thread and row; symbols are in input order row by
-        // row, thread by thread inside a row
+        // long symbols per thread and row, as the key kernel marked them
+        // (S is read again only at those positions); symbols are in input
+        // order row by row, thread by thread inside a row
         uint32_t lm[ROWS], inc[ROWS];   // lm: bit k = symbol k of the thread's row piece is long
 #pragma unroll
         for (uint32_t r = 0; r < ROWS; r++) {
-            const uint64_t i0 = b0 + (r * KB_T + threadIdx.x) * V;
-            uint32_t m = 0;
-#pragma unroll
-            for (uint32_t k = 0; k < V; k++) {
-                const uint32_t x = (uint32_t)sv[r].v[k];
-                if (i0 + k < n && x < sigma && (tab[x] & WV_SPLIT_LONG)) m |= 1u << k;
-            }
-            lm[r] = m;
-            inc[r] = wv_wave_incl_scan((uint32_t)__popc(m));
+            lm[r] = lmask[(blk * ROWS + r) * KB_T + threadIdx.x];
+            inc[r] = wv_wave_incl_scan((uint32_t)__popc(lm[r]));
             if (lane == 63) wsum[r][wave] = inc[r];
         }
         __syncthreads();
@@ -213,10 +205,11 @@ tree_long_keys_k(const T* __restrict__ S, uint64_t n, uint32_t sigma, const uint
             uint64_t rank = base + inc[r] - (uint32_t)__popc(lm[r]);
             for (uint32_t w = 0; w < wave; w++) rank += wsum[r][w];
             if (lm[r]) {
+                const uint64_t i0 = b0 + (r * KB_T + threadIdx.x) * V;
 #pragma unroll
                 for (uint32_t k = 0; k < V; k++) {
                     if (!((lm[r] >> k) & 1u)) continue;
-                    const uint32_t x = (uint32_t)sv[r].v[k];
+                    const uint32_t x = (uint32_t)S[i0 + k];   // marked only below n and sigma
                     if (rank < nlong) lkeys[rank] = codes[x] << (h - lens[x]);
                     rank++;
                 }
@@ -735,33 +728,39 @@ void wv_split_table(const uint32_t* codes, const uint32_t* lens, uint32_t sigma,
 }
 
 hipError_t wv_tree_keys_split(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma, const uint32_t* ktab,
-                              uint16_t* keys, uint32_t* bcnt, hipStream_t s)
+                              uint16_t* keys, uint32_t* bcnt, uint16_t* lmask, hipStream_t s)
 {
     if (!n) return hipSuccess;
     const uint64_t nb = wv_tree_key_blocks(n);
     const uint32_t g = (uint32_t)std::min<uint64_t>(nb, KB_GRID);
     if (sym_bytes == 1)
-        tree_keys_split_k<uint8_t><<<g, KB_T, 0, s>>>((const uint8_t*)S, n, sigma, ktab, keys, bcnt, nb);
+        tree_keys_split_k<uint8_t><<<g, KB_T, 0, s>>>((const uint8_t*)S, n, sigma, ktab, keys, bcnt, lmask, nb);
     else if (sym_bytes == 2)
-        tree_keys_split_k<uint16_t><<<g, KB_T, 0, s>>>((const uint16_t*)S, n, sigma, ktab, keys, bcnt, nb);
+        tree_keys_split_k<uint16_t><<<g, KB_T, 0, s>>>((const uint16_t*)S, n, sigma, ktab, keys, bcnt, lmask, nb);
     else
-        tree_keys_split_k<uint32_t><<<g, KB_T, 0, s>>>((const uint32_t*)S, n, sigma, ktab, keys, bcnt, nb);
+        tree_keys_split_k<uint32_t><<<g, KB_T, 0, s>>>((const uint32_t*)S, n, sigma, ktab, keys, bcnt, lmask, nb);
     return hipGetLastError();
 }
 
-hipError_t wv_tree_long_keys(const void* S, uint64_t n, uint32_t sym_bytes, uint32_t sigma, const uint32_t* ktab,
-                             const uint32_t* codes, const uint32_t* lens, uint32_t h, const uint64_t* boff,
-                             uint32_t* lkeys, uint64_t nlong, hipStream_t s)
+uint64_t wv_tree_lmask_bytes(uint64_t n, uint32_t sym_bytes)
+{
+    // ROWS = sym_bytes rows of KB_T threads per block, a 16-bit mask each
+    return wv_tree_key_blocks(n) * sym_bytes * KB_T * 2;
+}
+
+hipError_t wv_tree_long_keys(const void* S, uint64_t n, uint32_t sym_bytes, const uint32_t* codes, const uint32_t* lens,
+                             uint32_t h, const uint64_t* boff, const uint16_t* lmask, uint32_t* lkeys, uint64_t nlong,
+                             hipStream_t s)
 {
     if (!n || !nlong) return hipSuccess;
     const uint64_t nb = wv_tree_key_blocks(n);
     const uint32_t g = (uint32_t)std::min<uint64_t>(nb, KB_GRID);
     if (sym_bytes == 1)
-        tree_long_keys_k<uint8_t><<<g, KB_T, 0, s>>>((const uint8_t*)S, n, sigma, ktab, codes, lens, h, boff, lkeys, nlong, nb);
+        tree_long_keys_k<uint8_t><<<g, KB_T, 0, s>>>((const uint8_t*)S, n, codes, lens, h, boff, lmask, lkeys, nlong, nb);
     else if (sym_bytes == 2)
-        tree_long_keys_k<uint16_t><<<g, KB_T, 0, s>>>((const uint16_t*)S, n, sigma, ktab, codes, lens, h, boff, lkeys, nlong, nb);
+        tree_long_keys_k<uint16_t><<<g, KB_T, 0, s>>>((const uint16_t*)S, n, codes, lens, h, boff, lmask, lkeys, nlong, nb);
     else
-        tree_long_keys_k<uint32_t><<<g, KB_T, 0, s>>>((const uint32_t*)S, n, sigma, ktab, codes, lens, h, boff, lkeys, nlong, nb);
+        tree_long_keys_k<uint32_t><<<g, KB_T, 0, s>>>((const uint32_t*)S, n, codes, lens, h, boff, lmask, lkeys, nlong, nb);
     return hipGetLastError();
 }
 
