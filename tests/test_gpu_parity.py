@@ -143,6 +143,11 @@ def test_wm_passes_widths(sigma, dt):
     for blocks in (0, 2):
         g = gpu_image(B.KIND_WM, S, sigma, tune=B.make_tuning(blocks=blocks))
         assert_same(g, o, f"sigma={sigma} blocks={blocks}")
+    # narrow passes: byte keys in LDS with remaining bits written for the
+    # next pass, from symbols of every width
+    for tau in (2, 3):
+        g = gpu_image(B.KIND_WM, S, sigma, tune=B.make_tuning(tau=tau))
+        assert_same(g, o, f"sigma={sigma} tau={tau}")
 
 
 def fibonacci_sequence(nsym, rng):
