@@ -802,8 +802,8 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
     const uint32_t sigma = p.sigma, K = p.key_bits;
     const bool shaped = p.kind == WT_KIND_SHAPED, multi = p.kind == WT_KIND_MULTIARY;
     // levels of D-bit digits: multiary trees, and shaped trees over digits
-    // (whose counters are taken after the gather, their levels being of
-    // different lengths)
+    // (levels of different lengths; their counters are taken during the
+    // gather all the same)
     const bool digits = multi || (shaped && p.D >= 2);
     const uint32_t D = digits ? p.D : 1u, T = digits ? p.nlevels : K;
     // 1. symbol counts (and status).  A shaped tree takes its counts from the
@@ -948,24 +948,27 @@ int build_from_matrix(const Plan& p, const void* S, const wt_shape* shape, uint8
             return wv_tree_digits(ds, nt, m, D, zpre, ztot, s);
         };
         uint8_t* timg = at<uint8_t>(ws, p.ws_tmpimg);
-        hipStream_t s2 = nullptr;
-        if (p.h1 && p.nlong) {
-            // matrix B on the side stream, forked after the keys
-            s2 = wv_side_stream();
-            if (!s2) return WT_EHIP;
+        const bool two = p.h1 && p.nlong;
+        // matrix B on the side stream (on `s` when there is none), forked
+        // after the keys, joined before its digits are read
+        hipStream_t s2 = two ? wv_side_stream() : nullptr;
+        if (two) {
+            hipStream_t sb = s2 ? s2 : s;
             wv_wm_plan pb = p.wmb;
             pb.profile = false;
-            WV_CHECK(hipEventRecord(fork.e[0], s));
-            WV_CHECK(hipStreamWaitEvent(s2, fork.e[0], 0));
-            WV_TIMED(prof, s2, "side_matrix",
+            if (s2) {
+                WV_CHECK(hipEventRecord(fork.e[0], s));
+                WV_CHECK(hipStreamWaitEvent(s2, fork.e[0], 0));
+            }
+            WV_TIMED(prof, sb, "side_matrix",
                      WV_CHECK(run_matrix(pb, at<void>(ws, p.ws_lkeys), at<uint8_t>(ws, p.ws_timgb), p.tlayb, K,
-                                         at<uint8_t>(ws, p.ws_wmb), s2)));
-            WV_CHECK(hipEventRecord(fork.e[1], s2));
+                                         at<uint8_t>(ws, p.ws_wmb), sb)));
+            if (s2) WV_CHECK(hipEventRecord(fork.e[1], s2));
         }
         WV_CHECK(run_matrix(p.wm, keys, timg, p.tlay, p.h1 ? p.h1 : K, at<uint8_t>(ws, p.ws_wm), s));
         WV_TIMED(prof, s, "tree_digits", WV_CHECK(digit_strings(timg, p.tlay, n, 0, TA)));
-        if (s2) {
-            WV_CHECK(hipStreamWaitEvent(s, fork.e[1], 0));
+        if (two) {
+            if (s2) WV_CHECK(hipStreamWaitEvent(s, fork.e[1], 0));
             WV_TIMED(prof, s, "tree_digits",
                      WV_CHECK(digit_strings(at<uint8_t>(ws, p.ws_timgb), p.tlayb, p.nlong, TA, T - TA)));
         }
