@@ -39,8 +39,10 @@
  *     returns WT_ERANGE (the rest of the image is unspecified); a shaped
  *     tree whose sequence has other counts than shape->counts is marked the
  *     same way and wt_check() returns WT_EINVAL.
- *   - Builds do not wait on the host (except the level-by-level tree path,
- *     below), so a caller may capture any build into a HIP graph.
+ *   - Builds do not wait on the host (except balanced and multiary trees
+ *     over more than 20 key bits, which read the symbol counts back, and the
+ *     level-by-level tree path, below), so a caller may capture any other
+ *     build into a HIP graph.
  *   - Limits: n < 2^32, sigma >= 1, sym_bytes in {1, 2, 4}, at most 32
  *     levels, codeword length <= 32.
  */
