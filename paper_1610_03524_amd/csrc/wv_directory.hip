@@ -558,7 +558,8 @@ __global__ void counts_match_k(const uint64_t* __restrict__ got, const uint64_t*
                                uint32_t* __restrict__ status)
 {
     bool bad = false;
-    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < sigma; x += gridDim.x * blockDim.x)
+    // 64-bit index: sigma may lie within one stride of 2^32
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < sigma; x += (uint64_t)gridDim.x * blockDim.x)
         bad |= got[x] != want[x];
     if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(status, WV_STATUS_COUNTS);
 }

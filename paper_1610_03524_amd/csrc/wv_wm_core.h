@@ -179,8 +179,11 @@ __device__ void wm_pass_chunk(const PassArgs& a, uint32_t b, PassShared<KT_>& S)
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t tau = a.tau, R = a.R;
     const uint32_t ngroups = (2u << tau) - 1u;         // j = 0..tau
+    // chunk b starts below n (< 2^32); its end is taken in 64 bits, as the
+    // chunks together may cover 2^32 keys or more
     const uint32_t cstart = b * a.C;
-    const uint32_t cend = min(a.n, cstart + a.C);
+    const uint32_t cend = (uint32_t)min<uint64_t>(a.n, (uint64_t)cstart + a.C);
+    const uint32_t ntiles = (cend - cstart + (uint32_t)T - 1) / (uint32_t)T;
     const uint32_t dshift = R - tau;
     const uint32_t dmask = (1u << tau) - 1u;
     const uint32_t pmask = dshift >= 32 ? ~0u : ((1u << dshift) - 1u);
@@ -194,7 +197,8 @@ __device__ void wm_pass_chunk(const PassArgs& a, uint32_t b, PassShared<KT_>& S)
     if (tid == 0) lb[TW] = 0;
     uint32_t cpar = 0;   // carry buffer read this tile
 
-    for (uint32_t ts = cstart; ts < cend; ts += T) {
+    for (uint32_t tile = 0; tile < ntiles; tile++) {   // no tile start wraps past 2^32
+        const uint32_t ts = cstart + tile * (uint32_t)T;
         const uint32_t tc = min((uint32_t)T, cend - ts);
         load_tile_any<KT_>(a.in, a.in_bytes, ts, tc, a.keymask, buf);
         if (tid == 0) { cnt[0] = tc; ls[0] = 0; }
@@ -398,7 +402,7 @@ __device__ void wm_hist_part(const void* __restrict__ in, uint32_t n, uint32_t C
                              uint32_t* h)
 {
     const uint32_t wave = threadIdx.x >> 6;
-    const uint32_t cs = b * C, ce = min(n, cs + C);
+    const uint32_t cs = b * C, ce = (uint32_t)min<uint64_t>(n, (uint64_t)cs + C);
     const uint32_t dshift = R - tau, dmask = (1u << tau) - 1u;
     for (uint32_t i = threadIdx.x; i < HWORDS; i += HT) h[i] = 0;
     uint32_t* hw = h + (wave * HCOPY + (threadIdx.x & (HCOPY - 1))) * HSTRIDE;
@@ -439,7 +443,8 @@ __device__ void wm_hist_part(const void* __restrict__ in, uint32_t n, uint32_t C
         }
     }
     if (part == HSPLIT - 1) {
-        for (uint32_t i = cs + nvec * V + threadIdx.x; i < ce; i += HT) {
+        // 64-bit index: ce may lie within HT of 2^32
+        for (uint64_t i = (uint64_t)cs + nvec * V + threadIdx.x; i < ce; i += HT) {
             const uint32_t x = ld<IT>(in, i);
             bad |= x >= sigma;
             atomicAdd(&hw[((x & keymask) >> dshift) & dmask], 1u);

@@ -83,6 +83,8 @@ Geometry geometry(uint64_t n, uint32_t blocks, uint32_t tile, uint32_t L)
     const uint64_t tiles = wv_cdiv(n ? n : 1, T);
     uint64_t K = blocks ? blocks : (tile ? wv_cdiv(tiles, tile) : (L > 16 ? KRES32 : KRES16));
     K = std::min<uint64_t>(K, tiles);
+    // a chunk length must fit 32 bits: at least two chunks near n = 2^32
+    K = std::max<uint64_t>(K, wv_cdiv(n ? n : 1, 0x100000000ull - T));
     const uint64_t C = wv_cdiv(wv_cdiv(n ? n : 1, K), T) * T;
     return Geometry{(uint32_t)wv_cdiv(n ? n : 1, C), (uint32_t)C};
 }
