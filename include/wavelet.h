@@ -255,7 +255,9 @@ int wt_check(const void* image, void* stream);
  *                  0 if c[q] >= sigma or has no codeword; UINT64_MAX if
  *                  i[q] >= n.
  * select (Sec. 2): res[q] = position of the k[q]-th occurrence of c[q]
- *                  (k 1-based); UINT64_MAX if k = 0, k > count or c invalid. */
+ *                  (k 1-based); UINT64_MAX if k = 0, k > count or c invalid.
+ * One launch per call: m > 2^39 - 256 queries returns WT_EUNSUP before any
+ * device work. */
 int wt_access(const void* image, const uint64_t* pos, uint32_t* res, uint64_t m, void* stream);
 int wt_rank(const void* image, const uint32_t* c, const uint64_t* i, uint64_t* res,
             uint64_t m, void* stream);

@@ -412,6 +412,7 @@ int wt_access(const void* image, const uint64_t* pos, uint32_t* res, uint64_t m,
 {
     if (!image || (m && (!pos || !res))) return WT_EINVAL;
     if (!m) return WT_OK;
+    if (wv_cdiv(m, Q_THREADS) > 0x7FFFFFFFull) return WT_EUNSUP;   // one thread a query, grid.x < 2^31
     access_k<<<(uint32_t)wv_cdiv(m, Q_THREADS), Q_THREADS, 0, (hipStream_t)stream>>>(
         (const uint8_t*)image, pos, res, m);
     return hipGetLastError() == hipSuccess ? WT_OK : WT_EHIP;
@@ -421,6 +422,7 @@ int wt_rank(const void* image, const uint32_t* c, const uint64_t* i, uint64_t* r
 {
     if (!image || (m && (!c || !i || !res))) return WT_EINVAL;
     if (!m) return WT_OK;
+    if (wv_cdiv(m, Q_THREADS) > 0x7FFFFFFFull) return WT_EUNSUP;   // one thread a query, grid.x < 2^31
     rank_k<<<(uint32_t)wv_cdiv(m, Q_THREADS), Q_THREADS, 0, (hipStream_t)stream>>>(
         (const uint8_t*)image, c, i, res, m);
     return hipGetLastError() == hipSuccess ? WT_OK : WT_EHIP;
@@ -430,6 +432,7 @@ int wt_select(const void* image, const uint32_t* c, const uint64_t* k, uint64_t*
 {
     if (!image || (m && (!c || !k || !res))) return WT_EINVAL;
     if (!m) return WT_OK;
+    if (wv_cdiv(m, Q_THREADS) > 0x7FFFFFFFull) return WT_EUNSUP;   // one thread a query, grid.x < 2^31
     select_k<<<(uint32_t)wv_cdiv(m, Q_THREADS), Q_THREADS, 0, (hipStream_t)stream>>>(
         (const uint8_t*)image, c, k, res, m);
     return hipGetLastError() == hipSuccess ? WT_OK : WT_EHIP;

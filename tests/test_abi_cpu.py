@@ -257,6 +257,20 @@ def test_device_huffman_refuses_on_the_host():
     assert L.wt_huffman_codes_dev(p, 10, p, p, None, None) == B.WT_EINVAL
 
 
+def test_queries_refuse_batches_beyond_one_launch():
+    """access / rank / select run one thread a query in one launch: a batch
+    needing 2^31 workgroups or more is refused before any device call (no GPU
+    needed), an empty one is a no-op, null arrays are argument errors"""
+    L = B.lib()
+    p, big = 0x10000, (1 << 31) * 256
+    assert L.wt_access(p, p, p, big, None) == B.WT_EUNSUP
+    assert L.wt_rank(p, p, p, p, big, None) == B.WT_EUNSUP
+    assert L.wt_select(p, p, p, p, big, None) == B.WT_EUNSUP
+    assert L.wt_access(p, None, None, 0, None) == B.WT_OK
+    assert L.wt_rank(p, None, p, p, 5, None) == B.WT_EINVAL
+    assert L.wt_select(None, p, p, p, 5, None) == B.WT_EINVAL
+
+
 def test_trace_logs_plans_only_when_asked():
     """WT_TRACE=1 logs every plan (path, passes, chunks, level offsets) and
     batch plan on stderr; without it the library prints nothing"""
