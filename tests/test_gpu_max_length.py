@@ -4,10 +4,11 @@ Cut into chunks one per resident workgroup, such a sequence gives chunks
 that together cover 2^32 keys or more, so chunk ends, tile starts and chunk
 lengths must not wrap in 32 bits (one chunk of it would not fit 32 bits at
 all).  The oracle cannot build 4 G symbols in a test's time; the checks are
-properties that hold at any size: level 0 of either kind is the top key bit
-of S in input order, word for word; every level's zero count; access at
-sampled positions (every chunk boundary and the tail included) equals S;
-rank and select agree with counts over S."""
+properties that hold at any size: level 0 of a matrix or binary tree is the
+top key bit of S in input order, and the one level of a 4-ary tree over four
+symbols is S itself as 2-bit digits, word for word; every binary level's
+zero count; access at sampled positions (every chunk boundary and the tail
+included) equals S; rank and select agree with counts over S."""
 import numpy as np
 import pytest
 
@@ -40,32 +41,46 @@ def count_upto(S, pieces, c, i):
     return int(pieces[:p, c].sum()) + rest
 
 
-@pytest.mark.parametrize("kind", [B.KIND_WM, B.KIND_WT])
-def test_longest_sequence(seq, kind):
+def packed_words(S, a, m, D, digit):
+    """the words of a level holding `digit`(S[a:a+m]) in input order, D bits a
+    symbol, 64 / D symbols a word, LSB first (m a multiple of 64 / D or the
+    end of S)"""
+    import torch
+    P = 64 // D
+    v = digit(S[a:a + m]).to(torch.int64)
+    if m % P:
+        v = torch.nn.functional.pad(v, (0, P - m % P))
+    shifts = torch.arange(0, 64, D, device="cuda", dtype=torch.int64)
+    return (v.view(-1, P) << shifts).sum(dim=1)
+
+
+@pytest.mark.parametrize("kind,D", [(B.KIND_WM, 0), (B.KIND_WT, 0), (B.KIND_MULTIARY, 2)])
+def test_longest_sequence(seq, kind, D):
     import torch
     S, pieces = seq
-    img, info = B.build(kind, S, SIGMA)
+    img, info = B.build(kind, S, SIGMA, arity_log2=D)
     torch.cuda.synchronize()
     assert B.check(img) == B.WT_OK
-    lv = img[256:256 + 64 * 2].cpu().numpy().view(np.uint64).reshape(2, 8)   # n_l, zeros, ones, bits_off, ...
-    assert int(lv[0, 0]) == N and int(lv[1, 0]) == N
-    # level 0: bit 1 of every symbol in input order, 64 symbols a word, LSB first
+    nl = int(img[28:32].cpu().numpy().view(np.uint32)[0])
+    lv = img[256:256 + 64 * nl].cpu().numpy().view(np.uint64).reshape(nl, 8)   # n_l, zeros, ones, bits_off, ...
+    assert nl == (1 if D == 2 else 2) and all(int(x) == N for x in lv[:, 0])
+    # level 0 in input order: the top key bit of every symbol (binary), or
+    # every symbol as one 2-bit digit (4-ary)
+    bits = 2 if D == 2 else 1
+    digit = (lambda x: x) if D == 2 else (lambda x: (x >> 1) & 1)
     off = int(lv[0, 3])
-    words = img[off:off + 8 * ((N + 63) // 64)].view(torch.int64)
-    shifts = torch.arange(64, device="cuda", dtype=torch.int64)
+    words = img[off:off + 8 * ((N * bits + 63) // 64)].view(torch.int64)
+    per = STEP * bits // 64
     for a in range(0, N, STEP):
-        m = min(N, a + STEP) - a
-        bits = ((S[a:a + m] >> 1) & 1).to(torch.int64)
-        if m % 64:
-            bits = torch.nn.functional.pad(bits, (0, 64 - m % 64))
-        packed = (bits.view(-1, 64) << shifts).sum(dim=1)
-        assert torch.equal(packed, words[a // 64:a // 64 + packed.numel()]), f"level 0 from symbol {a}"
-    total = pieces.sum(axis=0)
-    assert int(lv[0, 1]) == int(total[0] + total[1]), "zeros of level 0"
-    assert int(lv[1, 1]) == int(total[0] + total[2]), "zeros of level 1"
+        got = packed_words(S, a, min(N, a + STEP) - a, bits, digit)
+        assert torch.equal(got, words[a // STEP * per:a // STEP * per + got.numel()]), f"level 0 from symbol {a}"
+    if D != 2:
+        total = pieces.sum(axis=0)
+        assert int(lv[0, 1]) == int(total[0] + total[1]), "zeros of level 0"
+        assert int(lv[1, 1]) == int(total[0] + total[2]), "zeros of level 1"
     # access: every boundary of the chunks of the library's geometry, the
     # tail, and random positions
-    rng = np.random.default_rng(kind)
+    rng = np.random.default_rng(kind + D)
     C = 1 << 22          # chunk length of 1024 chunks over 2^32 - 1 keys
     edges = np.concatenate([np.arange(C, N, C) + d for d in (-2, -1, 0, 1)])
     pos = np.unique(np.concatenate([edges, np.arange(N - 300, N), rng.integers(0, N, 4096)])).astype(np.int64)
