@@ -291,16 +291,18 @@ class WaveletServer:
         self.build_stream.synchronize()
         return self._codes(len(imgs), rc)
 
-    def _launch_builds(self, descs, imgs):
+    def _launch_builds(self, take, descs, imgs):
         """queue the builds on the build stream, each segment of the batch
         followed by the copy of its status words and an event; returns (rc,
         [(first, end, event)]): rc is the code of the first launch that failed
         (the segments before it stand).  The last segment's event is the
         build stream itself (nothing else is queued on it while a batch is on
-        the device)."""
+        the device).  A few sequences are built one by one when each one's
+        own workspace fits (admission counted their batched workspace, which
+        can be smaller), else as one batch."""
         torch = self.torch
         segs = []
-        if len(descs) <= SINGLES_MAX:
+        if len(descs) <= SINGLES_MAX and all(self._costs(r.seq)[2] <= self.ws.numel() for r in take):
             # a few sequences: single builds in stream order (one workspace),
             # each finishing on its own
             for i, d in enumerate(descs):
@@ -431,7 +433,7 @@ class WaveletServer:
                 self.batches.append(len(take))
                 try:
                     with torch.cuda.stream(self.build_stream):
-                        rc, segs = self._launch_builds(descs, imgs)
+                        rc, segs = self._launch_builds(take, descs, imgs)
                 except Exception as e:   # fail the batch, keep serving
                     rc, segs = getattr(e, "code", B.WT_EHIP), []
                     try:   # whatever was queued finishes before the images are dropped

@@ -81,6 +81,34 @@ def test_results_same_alone_and_in_the_mix(mode):
         assert max(srv.batches) > 1   # builds were batched
 
 
+def test_workspace_that_fits_the_batch_but_not_a_single_build():
+    """Admission counts a sequence's batched workspace; its single build can
+    need a little more.  With a workspace of exactly the batched figure a
+    lone request is built as a batch of one (continuous mode) and equals the
+    oracle's image; the plain queue, which builds one by one, refuses it."""
+    import torch
+    rng = np.random.default_rng(77)
+    S, sigma = rng.integers(0, 5209, 2611909).astype(np.uint32), 5209
+    dev = [(to_device(S), sigma)]
+    probe = serve.WaveletServer(dev, hbm_budget=1 << 34, ws_bytes=1 << 20)
+    _, batch_ws, single_ws, _ = probe._costs(0)
+    del probe
+    assert single_ws > batch_ws   # the case this test is about
+    want = oracle.build_image(oracle.KIND_WM, S, sigma)
+    for mode, code in (("continuous", 0), ("plain", B.WT_ENOSPC)):
+        srv = serve.WaveletServer(dev, hbm_budget=1 << 34, ws_bytes=batch_ws, mode=mode)
+        srv.start()
+        r = srv.submit_build(0)
+        deadline = time.time() + 60
+        while not r.done and time.time() < deadline:
+            time.sleep(0.002)
+        srv.close()
+        torch.cuda.synchronize()
+        assert r.done and r.error == code, (mode, r.error)
+        if code == 0:
+            assert np.array_equal(srv.resident[0].image.cpu().numpy(), want)
+
+
 def test_budget_admission_and_eviction():
     import torch
     host = pool(12, seed=3)
