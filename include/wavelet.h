@@ -206,7 +206,8 @@ int wt_plan(int kind, uint64_t n, uint32_t sigma, uint32_t sym_bytes,
  * device checks the counts (wt_check: WT_EINVAL if they differ).  A shaped
  * tree split into two matrices builds the smaller one on a second stream
  * the library keeps per device, forked from and joined back into `stream`
- * with events. */
+ * with events; split builds of different callers share that stream, so one
+ * of them must not be captured into a graph while another is being built. */
 int wt_build(const void* S, uint64_t n, uint32_t sigma, uint32_t sym_bytes,
              const wt_shape* shape, const wt_tuning* tune,
              void* out, size_t out_bytes, void* ws, size_t ws_bytes, void* stream);
