@@ -271,6 +271,30 @@ def test_queries_refuse_batches_beyond_one_launch():
     assert L.wt_select(None, p, p, p, 5, None) == B.WT_EINVAL
 
 
+def test_chunk_geometry_near_2_to_the_32():
+    """Every pass's chunks (read from the plan trace): C a multiple of the
+    8192-key tile that fits 32 bits, K chunks covering n without an empty one
+    -- also for one requested chunk or one huge tile count over a sequence
+    within a tile of 2^32, where a single chunk would not fit 32 bits"""
+    import re
+    import subprocess
+    import sys
+    cases = [((1 << 32) - 1, "blocks=1"), ((1 << 32) - 1, "tile=1 << 20"), ((1 << 32) - 8192, "blocks=1"),
+             ((1 << 32) - 8193, "blocks=1"), ((1 << 32) - 1, ""), ((1 << 32) - 1, "blocks=3"),
+             ((1 << 31) + 1, "blocks=1"), (8193, "blocks=1")]
+    code = "from paper_1610_03524_amd import binding as B\n" + "".join(
+        f"B.plan(B.KIND_WM, {n}, 4, 1, tune=B.make_tuning({t}))\n" for n, t in cases)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                       env={**os.environ, "WT_TRACE": "1"}, timeout=120)
+    assert r.returncode == 0, r.stderr
+    got = [(int(k), int(c)) for k, c in re.findall(r"chunks K=(\d+) of C=(\d+) keys", r.stderr)]
+    assert len(got) == len(cases)
+    for (n, t), (K, C) in zip(cases, got):
+        assert C % 8192 == 0 and 0 < C <= (1 << 32) - 8192, (n, t, K, C)
+        assert K * C >= n and (K - 1) * C < n, (n, t, K, C)
+
+
 def test_trace_logs_plans_only_when_asked():
     """WT_TRACE=1 logs every plan (path, passes, chunks, level offsets) and
     batch plan on stderr; without it the library prints nothing"""
