@@ -97,3 +97,32 @@ def test_longest_sequence(seq, kind, D):
     assert np.array_equal(gs, ip), "select of the occurrence at each sampled position"
     del img
     torch.cuda.empty_cache()
+
+
+def test_longest_sequence_in_a_batch(seq):
+    """The batched build over the longest sequence and a short one: the long
+    image equals the single build's byte for byte (its properties are checked
+    above), the short one the oracle's"""
+    import torch
+    import oracle
+    S, _ = seq
+    small = np.random.default_rng(5).integers(0, 300, 100003).astype(np.uint32)
+    Ss = torch.from_numpy(small.view(np.int32)).cuda()
+    single, _ = B.build(B.KIND_WM, S, SIGMA)
+    descs, imgs = [], []
+    for t, sigma, width in ((S, SIGMA, 1), (Ss, 300, 4)):
+        info = B.plan(B.KIND_WM, t.numel(), sigma, width)
+        img = torch.empty(info.out_bytes, dtype=torch.uint8, device="cuda")
+        d = B.wt_seq_desc()
+        d.S, d.n, d.sigma, d.sym_bytes = t.data_ptr(), t.numel(), sigma, width
+        d.out, d.out_bytes = img.data_ptr(), info.out_bytes
+        descs.append(d)
+        imgs.append(img)
+    ws = torch.empty(max(B.batch_plan(B.KIND_WM, descs), 1), dtype=torch.uint8, device="cuda")
+    assert B.batch_build(B.KIND_WM, descs, ws) == B.WT_OK
+    torch.cuda.synchronize()
+    assert all(B.check(img) == B.WT_OK for img in imgs)
+    assert torch.equal(imgs[0], single), "long sequence: batched image differs from the single build"
+    assert np.array_equal(imgs[1].cpu().numpy(), oracle.build_image(oracle.KIND_WM, small, 300)), "short sequence"
+    del single, imgs, ws
+    torch.cuda.empty_cache()
