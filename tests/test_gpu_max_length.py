@@ -126,3 +126,40 @@ def test_longest_sequence_in_a_batch(seq):
     assert np.array_equal(imgs[1].cpu().numpy(), oracle.build_image(oracle.KIND_WM, small, 300)), "short sequence"
     del single, imgs, ws
     torch.cuda.empty_cache()
+
+
+def test_longest_sequence_huffman_shaped(seq):
+    """A Huffman-shaped tree over the longest sequence (a 32-bit key per
+    symbol in the workspace, 16 GiB): level 0 holds the first codeword bit of
+    every symbol in input order, word for word; access, rank and select
+    agree with S"""
+    import torch
+    S, pieces = seq
+    counts = pieces.sum(axis=0).astype(np.uint64)
+    codes, lens = B.huffman_codes(counts)
+    img, _ = B.build(B.KIND_SHAPED, S, SIGMA, codes=codes, code_len=lens, counts=counts)
+    torch.cuda.synchronize()
+    assert B.check(img) == B.WT_OK
+    lv = img[256:256 + 64].cpu().numpy().view(np.uint64)
+    assert int(lv[0]) == N
+    first = torch.tensor([(int(c) >> (int(ln) - 1)) & 1 for c, ln in zip(codes, lens)], dtype=torch.uint8,
+                         device="cuda")
+    off = int(lv[3])
+    words = img[off:off + 8 * ((N + 63) // 64)].view(torch.int64)
+    per = STEP // 64
+    for a in range(0, N, STEP):
+        got = packed_words(S, a, min(N, a + STEP) - a, 1, lambda x: first[x.long()])
+        assert torch.equal(got, words[a // STEP * per:a // STEP * per + got.numel()]), f"level 0 from symbol {a}"
+    rng = np.random.default_rng(99)
+    pos = np.unique(np.concatenate([np.arange(N - 300, N), rng.integers(0, N, 4096)])).astype(np.int64)
+    got = B.access(img, torch.from_numpy(pos).cuda()).cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, S[torch.from_numpy(pos).cuda()].cpu().numpy()), "access"
+    ip = np.concatenate([[0, N - 1, N - 2], rng.integers(0, N, 12)]).astype(np.int64)
+    cs = S[torch.from_numpy(ip).cuda()].cpu().numpy().astype(np.int64)
+    ranks = np.array([count_upto(S, pieces, int(c), int(i)) for c, i in zip(cs, ip)], dtype=np.int64)
+    gr = B.rank(img, torch.from_numpy(cs.astype(np.int32)).cuda(), torch.from_numpy(ip).cuda()).cpu().numpy()
+    assert np.array_equal(gr, ranks), "rank"
+    gs = B.select(img, torch.from_numpy(cs.astype(np.int32)).cuda(), torch.from_numpy(ranks).cuda()).cpu().numpy()
+    assert np.array_equal(gs, ip), "select"
+    del img
+    torch.cuda.empty_cache()
