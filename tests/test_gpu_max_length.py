@@ -163,3 +163,40 @@ def test_longest_sequence_huffman_shaped(seq):
     assert np.array_equal(gs, ip), "select"
     del img
     torch.cuda.empty_cache()
+
+
+def test_longest_sequence_level_by_level(seq):
+    """The level-by-level builder (an 8-ary tree: one level of 3-bit digits,
+    21 to a word; 64 GiB of workspace) over the longest sequence: the level
+    is S itself in input order, word for word; access, rank and select agree
+    with S"""
+    import torch
+    S, pieces = seq
+    img, _ = B.build(B.KIND_MULTIARY, S, SIGMA, arity_log2=3)
+    torch.cuda.synchronize()
+    assert B.check(img) == B.WT_OK
+    lv = img[256:256 + 64].cpu().numpy().view(np.uint64)
+    assert int(img[28:32].cpu().numpy().view(np.uint32)[0]) == 1 and int(lv[0]) == N
+    P, step = 21, 21 << 21           # digits a word; symbols a piece (whole words)
+    words = img[int(lv[3]):int(lv[3]) + 8 * ((N + P - 1) // P)].view(torch.int64)
+    shifts = torch.arange(0, 3 * P, 3, device="cuda", dtype=torch.int64)
+    for a in range(0, N, step):
+        m = min(N, a + step) - a
+        v = S[a:a + m].to(torch.int64)
+        if m % P:
+            v = torch.nn.functional.pad(v, (0, P - m % P))
+        got = (v.view(-1, P) << shifts).sum(dim=1)
+        assert torch.equal(got, words[a // P:a // P + got.numel()]), f"level from symbol {a}"
+    rng = np.random.default_rng(3)
+    pos = np.unique(np.concatenate([np.arange(N - 300, N), rng.integers(0, N, 4096)])).astype(np.int64)
+    got = B.access(img, torch.from_numpy(pos).cuda()).cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, S[torch.from_numpy(pos).cuda()].cpu().numpy()), "access"
+    ip = np.concatenate([[0, N - 1, N - 2], rng.integers(0, N, 12)]).astype(np.int64)
+    cs = S[torch.from_numpy(ip).cuda()].cpu().numpy().astype(np.int64)
+    ranks = np.array([count_upto(S, pieces, int(c), int(i)) for c, i in zip(cs, ip)], dtype=np.int64)
+    gr = B.rank(img, torch.from_numpy(cs.astype(np.int32)).cuda(), torch.from_numpy(ip).cuda()).cpu().numpy()
+    assert np.array_equal(gr, ranks), "rank"
+    gs = B.select(img, torch.from_numpy(cs.astype(np.int32)).cuda(), torch.from_numpy(ranks).cuda()).cpu().numpy()
+    assert np.array_equal(gs, ip), "select"
+    del img
+    torch.cuda.empty_cache()
