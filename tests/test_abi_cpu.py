@@ -404,3 +404,15 @@ def test_plan_reports_the_split_of_shaped_digit_trees():
     assert info.key_bits == 2 * int(lens.max()) > 16
     assert info.split_bits == 16
     assert info.split_long == int(counts[lens > 8].sum()) > 0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: asked for more, it says so and exits with
+    status 2 before touching a device"""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    for n in (2, 8):
+        r = subprocess.run([sys.executable, "bench.py", "--gpus", str(n)], cwd=root, capture_output=True,
+                           text=True, timeout=120)
+        assert r.returncode == 2 and "one GPU only" in (r.stdout + r.stderr), (n, r.returncode, r.stdout, r.stderr)
